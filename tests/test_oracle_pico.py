@@ -1,0 +1,148 @@
+"""Pins of the oracle's PICO estimator, Tikhonov composition and PMR.
+
+  * Exact enumeration over every QPSK / Rademacher probe on tiny grids makes
+    the estimator exactly diag(Sigma) (unbiasedness, Sec. 2.2, Eq. (16)),
+    with Sigma from a dense LAPACK inverse.
+  * The enumerated per-voxel variance equals the Re-part of App. B, Eq. (A1):
+    1/2 sum_{l!=k} |Sigma_kl|^2 (random phase / QPSK, kappa = 1) and
+    sum_{l!=k} (Re Sigma_kl)^2 (real Rademacher).
+  * Full sampling (Sigma diagonal): a single random-phase probe is exact.
+  * Tikhonov: the two-solve composition equals (M+l)^-1 M (M+l)^-1 and its
+    diagonal lies below diag(M^-1) (App. D, Proposition).
+  * PMR converges to diag(Sigma) at the 1/sqrt(N) rate (App. C).
+  * Continuous random phase: z-scores of the estimate are standard (CLT).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pico, sense
+
+
+def _op(ny, nx, nc=2, R=2, acs=0, seed=1, full=False):
+    rng = np.random.default_rng(seed)
+    maps = workloads.coil_maps(ny, nx, nc, rng)
+    psi = workloads.noise_cov(nc, rng)
+    mask = np.ones(ny, np.uint8) if full else workloads.cart_mask_1d(ny, R, acs)
+    return pico.cartesian(maps, psi, mask)
+
+
+def _enum(values, n, shape):
+    for combo in itertools.product(values, repeat=n):
+        yield np.array(combo, np.complex128).reshape(shape)
+
+
+def test_qpsk_enumeration_is_exact_and_matches_A1():
+    op = _op(4, 1, nc=2)
+    cov = pico.Covariance(op, 0.0, cg_iters=12)
+    Sigma = np.linalg.inv(op.dense_normal())
+    acc = pico.noise_map(cov, 0, 0, 0, probes=_enum([1, 1j, -1, -1j], 4, (4, 1)))
+    assert acc["count"] == 256
+    est = pico.finalize(acc).ravel()
+    assert np.allclose(est, np.real(np.diag(Sigma)), rtol=1e-10, atol=0)
+    assert np.abs(acc["sum_im"] / acc["count"]).max() < 1e-9 * est.max()
+    var = acc["sumsq"].ravel() / acc["count"] - est ** 2
+    off = np.abs(Sigma) ** 2
+    np.fill_diagonal(off, 0)
+    assert np.allclose(var, 0.5 * off.sum(1), rtol=1e-8)
+
+
+def test_rademacher_enumeration_is_exact_and_matches_re_part_variance():
+    op = _op(4, 2, nc=2)
+    cov = pico.Covariance(op, 0.0, cg_iters=16)
+    Sigma = np.linalg.inv(op.dense_normal())
+    acc = pico.noise_map(cov, 0, 0, 0, probes=_enum([1, -1], 8, (4, 2)))
+    est = pico.finalize(acc).ravel()
+    assert np.allclose(est, np.real(np.diag(Sigma)), rtol=1e-9, atol=0)
+    var = acc["sumsq"].ravel() / acc["count"] - est ** 2
+    off = np.real(Sigma) ** 2
+    np.fill_diagonal(off, 0)
+    assert np.allclose(var, off.sum(1), rtol=1e-7)
+
+
+def test_tikhonov_composition_enumeration_and_shrinkage():
+    op = _op(4, 1, nc=2)
+    cov = pico.Covariance(op, 0.3, cg_iters=12)
+    assert cov.lam > 0
+    Md = op.dense_normal()
+    Ri = np.linalg.inv(Md + cov.lam * np.eye(4))
+    Sig_l = Ri @ Md @ Ri
+    acc = pico.noise_map(cov, 0, 0, 0, probes=_enum([1, 1j, -1, -1j], 4, (4, 1)))
+    assert np.allclose(pico.finalize(acc).ravel(), np.real(np.diag(Sig_l)), rtol=1e-9)
+    # App. D: Sigma_lam < Sigma_LS in the Loewner order, so the diagonal shrinks
+    Sig_ls = np.linalg.inv(Md)
+    assert np.linalg.eigvalsh(Sig_ls - Sig_l).min() > 0
+    big = _op(16, 8, nc=3, acs=2)
+    d_ls = sense.exact_diag_1d(big, big.P[:, 0])
+    d_l = sense.exact_diag_1d(big, big.P[:, 0], lam=0.05)
+    assert np.all(d_l < d_ls)
+
+
+def test_full_sampling_single_probe_exact():
+    op = _op(4, 2, nc=2, full=True)
+    cov = pico.Covariance(op, 0.0, cg_iters=16)
+    acc = pico.noise_map(cov, 9, 0, 1)
+    Sw = sense.whiten_maps(*_maps_psi(4, 2, 2, 1))
+    exact = 1.0 / np.sum(np.abs(Sw) ** 2, axis=0)
+    assert np.allclose(pico.finalize(acc), exact, rtol=1e-10)
+    # a complex Gaussian probe (kappa = 2) is not exact with one sample
+    acc_g = pico.noise_map(cov, 9, 0, 1, dist="gaussian")
+    assert np.abs(pico.finalize(acc_g) / exact - 1).max() > 0.05
+
+
+def _maps_psi(ny, nx, nc, seed):
+    rng = np.random.default_rng(seed)
+    return workloads.coil_maps(ny, nx, nc, rng), workloads.noise_cov(nc, rng)
+
+
+def test_random_phase_z_scores_are_standard():
+    op = _op(16, 8, nc=3, R=2)
+    Sigma = np.linalg.inv(op.dense_normal())
+    N = 300
+    cov = pico.Covariance(op, 0.0, cg_iters=60)
+    acc = pico.noise_map(cov, 21, 0, N)
+    est = pico.finalize(acc).ravel()
+    off = np.abs(Sigma) ** 2
+    np.fill_diagonal(off, 0)
+    z = (est - np.real(np.diag(Sigma))) / np.sqrt(0.5 * off.sum(1) / N)
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert 0.7 < z.var() < 1.3
+
+
+def test_resume_split_equals_single_call():
+    op = _op(8, 4, nc=2)
+    cov = pico.Covariance(op, 0.0, cg_iters=10)
+    a = pico.noise_map(cov, 4, 0, 6)
+    b = pico.noise_map(cov, 4, 0, 2)
+    b = pico.noise_map(cov, 4, 2, 4, acc=b)
+    assert np.array_equal(a["sum"], b["sum"]) and a["count"] == b["count"]
+
+
+def test_pmr_converges_to_exact_diagonal():
+    op = _op(8, 4, nc=2, R=2, acs=2)
+    exact = sense.exact_diag_1d(op, op.P[:, 0])
+    cov = pico.Covariance(op, 0.0, cg_iters=40)
+    N = 1500
+    acc = pico.pmr(cov, 17, 0, N)
+    var = pico.pmr_finalize(acc)
+    rel = var / exact
+    assert abs(rel.mean() - 1) < 4 / np.sqrt(N * rel.size)
+    assert pico.nrmse_var(var, exact) < 2.5 / np.sqrt(N)
+
+
+def test_pmr_hybrid_noise_is_white_on_the_mask():
+    op = _op(16, 8, nc=2, R=2, acs=2)
+    n = np.stack([pico.pmr_noise(op, 3, r) for r in range(200)])
+    on = op.P[None, None] > 0
+    p = np.mean(np.abs(n) ** 2, axis=0)
+    assert np.all(n[:, :, op.P == 0] == 0)
+    assert abs(p[np.broadcast_to(on[0], p.shape)].mean() - 1) < 0.03
+
+
+def test_nrmse_and_certify():
+    ref = np.full((4, 4), 4.0)
+    assert pico.nrmse_std(ref * 1.0201, ref) == pytest.approx(0.01, rel=1e-6)
+    maps = {100: ref * 1.05, 200: ref * 1.04, 400: ref * 1.001, 800: ref * 1.0005}
+    assert pico.certify(maps, ref) == 400
