@@ -1,0 +1,177 @@
+/*
+ * pico.h - C ABI of libpico: voxelwise noise-variance maps of iterative MRI
+ * reconstructions by image-space covariance probing (PICO), on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method (Dalmaz et al., "Fast Voxelwise SNR Estimation for Iterative MRI
+ * Reconstructions"):
+ *   - pre-whitened encoding A = L^-1 A~ with L L^H = Sigma_n (Sec. 2.1, Eq. (3));
+ *   - CG-SENSE reconstruction x = (A^H A + lam I)^-1 A^H b_w (Sec. 2.1, Eqs. (5)-(6));
+ *   - image covariance Sigma = (M + lam)^-1 M (M + lam)^-1, M = A^H A
+ *     (Sec. 2.1, Eqs. (7)-(9)), applied implicitly with CG solves
+ *     (Sec. 2.2, "Implicit matrix-vector product via CG");
+ *   - diagonal estimate var = Re((1/N) sum_i conj(v_i) . Sigma v_i) over
+ *     random-phase probes v_i (Sec. 2.2, Eqs. (13)-(14), (20); App. A,
+ *     Algorithm 1);
+ *   - the pseudo-multiple-replica baseline (Sec. 1; App. C).
+ *
+ * Conventions shared by every entry point:
+ *   - complex data are interleaved float32 pairs (complex64); images are
+ *     row-major [ny][nx]; multi-coil arrays are [ncoils][ny][nx];
+ *   - k-space masks are given in centred order (DC at index n/2), and the
+ *     Fourier transform is the centred orthonormal DFT;
+ *   - "device" pointers are HIP device memory (e.g. torch.Tensor.data_ptr()
+ *     of a CUDA/ROCm tensor); "host" pointers are ordinary memory;
+ *   - ``stream`` is a hipStream_t passed as void* (NULL = default stream);
+ *     every call enqueues its work on that stream and returns without
+ *     waiting, except pico_init (synchronous) and calls given a non-NULL
+ *     stats pointer (which wait for the stream);
+ *   - the library never frees caller memory; caller buffers must stay alive
+ *     until the enqueued work has finished;
+ *   - every function returns a status; on anything but PICO_OK,
+ *     pico_last_error() returns a message (thread-local).  Argument errors
+ *     are detected before anything is enqueued.
+ *   - one host thread per pico_op_t at a time; distinct handles are
+ *     independent.
+ */
+#ifndef PICO_H_
+#define PICO_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pico_op_s* pico_op_t;
+
+typedef enum {
+  PICO_OK = 0,
+  PICO_EINVAL = 1,         /* invalid argument or unsupported shape            */
+  PICO_ENOMEM = 2,         /* device allocation failed (nothing leaked)        */
+  PICO_EDEVICE = 3,        /* HIP runtime error                                */
+  PICO_EUNSUPPORTED = 4,   /* valid request this build does not implement      */
+  PICO_ENOTCONV = 5        /* some CG right-hand side broke down (map written) */
+} pico_status_t;
+
+typedef enum {
+  PICO_CART_1D = 0,        /* Cartesian, phase-encode mask [ny], all kx sampled */
+  PICO_CART_2D = 1,        /* Cartesian, 2-D mask [ny][nx]                     */
+  PICO_NONCART = 2         /* non-Cartesian trajectory                         */
+} pico_sampling_t;
+
+typedef enum {
+  PICO_CGSENSE = 0,        /* linear Tikhonov / least-squares CG-SENSE          */
+  PICO_CS_FISTA_L1WAV = 1  /* nonlinear compressed sensing (Jacobian probing)   */
+} pico_recon_t;
+
+typedef enum {
+  PICO_RANDOM_PHASE = 0,   /* v = exp(j 2 pi f), Sec. 2.2 Eq. (20) (default)    */
+  PICO_QPSK = 1,           /* v in {1, j, -1, -j}                               */
+  PICO_RADEMACHER = 2,     /* v in {+1, -1}, Sec. 2.2 Eq. (19)                  */
+  PICO_GAUSSIAN = 3        /* v ~ CN(0, 1), Sec. 2.2 Eq. (18)                   */
+} pico_probe_t;
+
+/* Operator description.  Pointers are read during pico_init only. */
+typedef struct {
+  int32_t ny, nx, ncoils;       /* image size and coil count (1..64)              */
+  const void* maps;             /* device complex64 [ncoils][ny][nx], un-whitened */
+  const double* psi;            /* host complex128 [ncoils][ncoils] (re, im
+                                   interleaved), channel noise covariance Sigma_n
+                                   (Sec. 2.1, Eq. (2)); NULL = identity            */
+  int32_t sampling;             /* pico_sampling_t                                 */
+  const uint8_t* mask;          /* device uint8, [ny] for PICO_CART_1D or [ny][nx]
+                                   for PICO_CART_2D, centred order, 0 / 1          */
+  const float* traj;            /* device float32 [nsamples][2] (w_y, w_x) rad in
+                                   [-pi, pi), PICO_NONCART only                    */
+  int64_t nsamples;
+  double lambda;                /* Tikhonov weight relative to the normalised
+                                   operator (Sec. 3.2.2); >= 0                     */
+  int32_t cg_iters;             /* CG iterations per solve (>= 1)                  */
+  double cg_tol;                /* 0: exactly cg_iters; > 0: stop a right-hand side
+                                   once ||r|| / ||r0|| <= cg_tol                   */
+  int32_t power_iters;          /* power-method steps for lambda_max (paper: 15)   */
+  double power_margin;          /* safety factor on lambda_max (paper: 1.01)       */
+  int32_t probe_tile;           /* probes solved together (K); sizes the workspace */
+  int32_t recon;                /* pico_recon_t                                    */
+} pico_op_desc_t;
+
+/* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a
+ * host probe count that the library advances.  Zero them before the first
+ * call.  sum_im and sumsq may be NULL. */
+typedef struct {
+  double* sum;                  /* PICO: sum Re(conj v . u); PMR: sum Re x         */
+  double* sum_im;               /* PICO: sum Im(conj v . u); PMR: sum Im x         */
+  double* sumsq;                /* PICO: sum (Re(conj v . u))^2; PMR: sum |x|^2    */
+  int64_t count;                /* probes / replicas accumulated                   */
+} pico_accum_t;
+
+typedef struct {
+  int64_t probes;               /* right-hand sides solved by the call             */
+  double max_relres;            /* max over them of ||r|| / ||r0|| at exit         */
+  double mean_relres;
+  int32_t frozen;               /* right-hand sides stopped by a CG breakdown       */
+  double lambda_abs;            /* lambda * power_margin * lambda_max              */
+} pico_stats_t;
+
+/* Build the operator: whitens the maps (Cholesky of psi on the host in
+ * float64; Sec. 2.1 Eq. (3)), prepares the sampling structures, runs the
+ * power method when lambda > 0 (Sec. 3.2.1, 3.3) and allocates the CG
+ * workspace for probe_tile right-hand sides.  Synchronous on ``stream``.
+ * Errors: PICO_EINVAL for a NULL or malformed descriptor (ny, nx even and
+ * supported by a built FFT size, 1 <= ncoils <= 64, cg_iters >= 1,
+ * probe_tile >= 1, psi Hermitian positive definite), PICO_EUNSUPPORTED for a
+ * sampling / reconstruction kind not built, PICO_ENOMEM, PICO_EDEVICE. */
+pico_status_t pico_init(const pico_op_desc_t* desc, void* stream, pico_op_t* out);
+
+/* u = Sigma v for k probe images (Sec. 2.2, Eq. (12)): v, u device
+ * complex64 [k][ny][nx], 1 <= k <= probe_tile, v and u may not overlap.
+ * Errors: PICO_EINVAL (NULL, k out of range), PICO_ENOTCONV (a right-hand
+ * side broke down; u still written), PICO_EDEVICE. */
+pico_status_t pico_apply_cov(pico_op_t op, const void* v, void* u, int32_t k, void* stream);
+
+/* Add probes [first_probe, first_probe + nprobes) of the counter-based
+ * probe sequence ``seed`` into ``acc`` (App. A, Algorithm 1).  Probe i,
+ * voxel j (row-major) is Philox4x32-10(counter = (j, i mod 2^32, i >> 32, 0),
+ * key = (seed mod 2^32, seed >> 32)) mapped to the family ``dist``; random
+ * phase uses f = (word0 >> 8) / 2^24, v = exp(j 2 pi f).  Splitting a probe
+ * range across calls gives the same map (bitwise when the split points are
+ * multiples of probe_tile).  stats may be NULL (no wait).
+ * Errors: PICO_EINVAL (NULL op / acc / acc->sum, nprobes < 0, bad dist),
+ * PICO_ENOTCONV, PICO_EDEVICE. */
+pico_status_t pico_noise_map(pico_op_t op, uint64_t seed, int64_t first_probe, int64_t nprobes,
+                             int32_t dist, pico_accum_t* acc, pico_stats_t* stats, void* stream);
+
+/* var = sum / count (device float64 [ny*nx]); Algorithm 1, last step.
+ * Errors: PICO_EINVAL (count < 1). */
+pico_status_t pico_finalize(pico_op_t op, const pico_accum_t* acc, double* var, void* stream);
+
+/* Pseudo multiple replica baseline: replicas [first, first + nrep) of white
+ * k-space noise n ~ CN(0, I) (Philox stream 1, Box-Muller), reconstructed by
+ * the same CG-SENSE solve, accumulated as sum x (sum / sum_im) and sum |x|^2
+ * (sumsq, required).  For a phase-encode (1-D) mask the noise is drawn in the
+ * hybrid (ky, x) domain, which the unitary DFT along x leaves white.
+ * Errors: as pico_noise_map; sum_im and sumsq must be non-NULL. */
+pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int64_t nrep,
+                                pico_accum_t* acc, pico_stats_t* stats, void* stream);
+
+/* Unbiased replica variance (sumsq - |sum|^2 / N) / (N - 1) into var
+ * (device float64 [ny*nx]).  Errors: PICO_EINVAL (count < 2, NULL fields). */
+pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* var, void* stream);
+
+/* lambda actually used in the normal equations (lambda * margin * lambda_max),
+ * or 0 for lambda == 0.  Returns NAN for a NULL handle. */
+double pico_lambda_abs(pico_op_t op);
+
+/* Release the operator and its device memory (waits for its last stream). */
+void pico_destroy(pico_op_t op);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* pico_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PICO_H_ */

@@ -101,6 +101,33 @@ def noise_map(cov: Covariance, seed: int, first: int, nprobes: int, dist: str = 
     return acc
 
 
+def noise_map_exact_columns(op, mask1d, seed: int, first: int, nprobes: int, cols,
+                            lam: float = 0.0, dist: str = "phase"):
+    """Estimator sums with Sigma applied exactly, on selected image columns.
+
+    For a phase-encode mask M is block diagonal over image columns, so
+    (Sigma v)[:, x] = Sigma_x v[:, x] with the dense ny x ny block
+    Sigma_x = (B_x + lam)^-1 B_x (B_x + lam)^-1 (Sec. 2.1, Eqs. (8)-(9)).
+    This is the estimator of Eq. (14) with converged solves; it lets
+    full-size problems be checked column by column.  ``lam`` is absolute.
+    Returns float64 [ny][len(cols)] of sum_i Re(conj v_i . Sigma v_i).
+    """
+    ny, nx = op.ny, op.nx
+    out = np.zeros((ny, len(cols)))
+    V = np.stack([probe_image(seed, i, (ny, nx), dist) for i in range(first, first + nprobes)])
+    for j, x in enumerate(cols):
+        B = op.column_normal(x, mask1d)
+        if lam == 0.0:
+            S = np.linalg.inv(B)
+        else:
+            Ri = np.linalg.inv(B + lam * np.eye(ny))
+            S = Ri @ B @ Ri
+        vc = V[:, :, x]                       # [N][ny]
+        u = vc @ S.T                          # rows: Sigma_x v
+        out[:, j] = np.sum((np.conj(vc) * u).real, axis=0)
+    return out
+
+
 def finalize(acc):
     """var = Re(s / N) (App. A, Algorithm 1, last step)."""
     return acc["sum"] / acc["count"]
@@ -194,5 +221,5 @@ def certify(maps_by_n: dict, gold, roi=None, d_nrmse=0.005, d_roi=0.002):
     return None
 
 
-__all__ = ["Covariance", "noise_map", "finalize", "pmr", "pmr_finalize", "pmr_noise",
+__all__ = ["Covariance", "noise_map", "noise_map_exact_columns", "finalize", "pmr", "pmr_finalize", "pmr_noise",
            "probe_image", "cartesian", "nrmse_std", "nrmse_var", "certify", "fft2c"]

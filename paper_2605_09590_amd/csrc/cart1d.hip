@@ -1,0 +1,336 @@
+// Separable Cartesian SENSE normal operator and the CG building blocks.
+//
+// With a phase-encode mask that is constant along kx, the whitened normal
+// operator M = sum_c S_c^H F^H P F S_c (Sec. 2.1, Eqs. (3), (6)) is block
+// diagonal over image columns: F_x^H F_x = I cancels, leaving one 1-D
+// transform along y per column and coil.  For even ny the centred
+// orthonormal DFT (fftshift o fft o ifftshift) equals (-1)^(ny/2) D F D / sqrt(ny)
+// with D = diag((-1)^y) and F the plain DFT, so F_c^H P F_c = D F^H P F D / ny:
+// D is folded into the whitened maps once, the centred-order mask applies
+// unchanged, and each coil costs one forward and one inverse unnormalised
+// FFT with the weight mask[k] / ny in between.
+//
+// Layout: every per-probe field is stored column-major, [K][nx][ny], so a
+// column is one contiguous line; maps are [nx][nc][ny].  One workgroup is one
+// wavefront holding G = 64/T probe columns of the same image column; each
+// column FFT lives in the registers of T lanes and exchanges through LDS.
+#include "fft.h"
+#include "runtime.h"
+
+namespace pico {
+
+template <class PL>
+__device__ __forceinline__ void normal_col(const float2 (&pv)[PL::P], float2 (&qa)[PL::P], float lam,
+                                           const float2* __restrict__ mcol, int nc,
+                                           uint32_t mbits, float2* lds, int t,
+                                           const float2 (&tw)[PL::NTW]) {
+  constexpr int P = PL::P, T = PL::T, N = PL::N;
+  constexpr float minv = 1.0f / N;
+#pragma unroll
+  for (int m = 0; m < P; ++m) qa[m] = cscale(pv[m], lam);
+  for (int c = 0; c < nc; ++c) {
+    const float2* __restrict__ s = mcol + (size_t)c * N;
+    float2 v[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[m] = cmul(s[t + T * m], pv[m]);
+    fft<PL, false>(v, lds, t, tw);
+#pragma unroll
+    for (int m = 0; m < P; ++m)
+      v[m] = ((mbits >> m) & 1u) ? cscale(v[m], minv) : make_float2(0.f, 0.f);
+    fft<PL, true>(v, lds, t, tw);
+#pragma unroll
+    for (int m = 0; m < P; ++m) qa[m] = cadd(qa[m], cmulc(s[t + T * m], v[m]));
+  }
+}
+
+template <class PL, int MODE>
+__global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
+  constexpr int P = PL::P, T = PL::T, N = PL::N, G = 64 / T;
+  constexpr int SPAN = lds_span<N>();
+  __shared__ float2 lds_all[G * SPAN];
+  const int g = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const int col = blockIdx.y;
+  const int k = blockIdx.x * G + g;
+  const bool active = k < a.K;
+  const int kk = active ? k : 0;  // idle groups work on probe 0 but never store
+  float2* lds = lds_all + g * SPAN;
+
+  float2 tw[PL::NTW];
+  load_twiddles<PL>(tw, a.twt, t);
+  uint32_t mbits = 0;
+#pragma unroll
+  for (int m = 0; m < P; ++m) mbits |= (a.maskw[t + T * m] != 0.f ? 1u : 0u) << m;
+
+  const size_t base = ((size_t)kk * a.nx + col) * N;
+  const float2* __restrict__ mcol = a.maps + (size_t)col * a.nc * N;
+  float2 pv[P];
+  double d0 = 0.0;
+
+  if constexpr (MODE == C1_PMR_RHS) {
+    // r = A^H n = sum_c conj(S_w,c) F_c^H P n_c with F_c^H = (-1)^(ny/2) D F^H D / sqrt(ny):
+    // per coil, w[k] = (-1)^(ny/2 + k) n[k] / sqrt(ny) on the sampled lines,
+    // unnormalised inverse FFT, times conj(S') (D already folded into S').
+    const float rs = rsqrtf((float)N);
+#pragma unroll
+    for (int m = 0; m < P; ++m) pv[m] = make_float2(0.f, 0.f);
+    for (int c = 0; c < a.nc; ++c) {
+      float2 v[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const int kc = t + T * m;
+        if ((mbits >> m) & 1u) {
+          const uint32_t elem = (uint32_t)(((size_t)c * N + kc) * a.nx + col);
+          const float2 n = draw_probe(a.seed, a.first + kk, elem, 1u, 3);
+          const float sg = ((kc + N / 2) & 1) ? -rs : rs;
+          v[m] = cscale(n, sg);
+        } else {
+          v[m] = make_float2(0.f, 0.f);
+        }
+      }
+      fft<PL, true>(v, lds, t, tw);
+      const float2* __restrict__ s = mcol + (size_t)c * N;
+#pragma unroll
+      for (int m = 0; m < P; ++m) pv[m] = cadd(pv[m], cmulc(s[t + T * m], v[m]));
+    }
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      if (active) a.r[base + t + T * m] = pv[m];
+      d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+    }
+    d0 = group_sum<T>(d0);
+    if (active && t == 0) a.part[((size_t)k * a.nx + col) * 2 + 1] = d0;
+    return;
+  } else {
+    if constexpr (MODE == C1_FIRST_PROBE) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const int y = t + T * m;
+        pv[m] = draw_probe(a.seed, a.first + kk, (uint32_t)(y * a.nx + col), 0u, a.dist);
+        if (active) { a.r[base + y] = pv[m]; a.p[base + y] = pv[m]; }
+        d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+      }
+    } else if constexpr (MODE == C1_FIRST_BUF) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        pv[m] = a.r[base + t + T * m];
+        if (active) a.p[base + t + T * m] = pv[m];
+        d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+      }
+    } else if constexpr (MODE == C1_ITER) {
+      const float beta = (float)a.beta[kk];
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const float2 rv = a.r[base + t + T * m];
+        const float2 po = a.p[base + t + T * m];
+        pv[m] = cfma(rv, beta, po);
+        if (active) a.p[base + t + T * m] = pv[m];
+      }
+    } else {  // C1_APPLY
+#pragma unroll
+      for (int m = 0; m < P; ++m) pv[m] = cscale(a.src[base + t + T * m], a.scale);
+    }
+
+    float2 qa[P];
+    normal_col<PL>(pv, qa, a.lam, mcol, a.nc, mbits, lds, t, tw);
+
+    double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      if (active) a.q[base + t + T * m] = qa[m];
+      d1 += (double)pv[m].x * qa[m].x + (double)pv[m].y * qa[m].y;
+      d2 += (double)qa[m].x * qa[m].x + (double)qa[m].y * qa[m].y;
+    }
+    d1 = group_sum<T>(d1);
+    if constexpr (MODE == C1_APPLY) d0 = group_sum<T>(d2);
+    else d0 = group_sum<T>(d0);
+    if (active && t == 0) {
+      double* pp = a.part + ((size_t)k * a.nx + col) * 2;
+      pp[0] = d1;
+      if constexpr (MODE != C1_ITER) pp[1] = d0;
+    }
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+template <class PL>
+static hipError_t launch_plan(int mode, const Cart1dArgs& a, hipStream_t s) {
+  constexpr int G = 64 / PL::T;
+  dim3 grid((a.K + G - 1) / G, a.nx), block(64);
+  switch (mode) {
+    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_cart1d<PL, C1_FIRST_PROBE>), grid, block, 0, s, a); break;
+    case C1_FIRST_BUF: hipLaunchKernelGGL((k_cart1d<PL, C1_FIRST_BUF>), grid, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL((k_cart1d<PL, C1_ITER>), grid, block, 0, s, a); break;
+    case C1_APPLY: hipLaunchKernelGGL((k_cart1d<PL, C1_APPLY>), grid, block, 0, s, a); break;
+    case C1_PMR_RHS: hipLaunchKernelGGL((k_cart1d<PL, C1_PMR_RHS>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Radix plans per line length (T lanes per line, radices dividing N/T)
+using Plan64 = FFTPlan<64, 8, 8, 8>;
+using Plan96 = FFTPlan<96, 8, 12, 4, 2>;
+using Plan128 = FFTPlan<128, 16, 8, 4, 4>;
+using Plan160 = FFTPlan<160, 8, 20, 4, 2>;
+using Plan192 = FFTPlan<192, 16, 12, 4, 4>;
+using Plan256 = FFTPlan<256, 16, 16, 16>;
+using Plan288 = FFTPlan<288, 16, 18, 2, 2, 2, 2>;
+using Plan320 = FFTPlan<320, 16, 20, 4, 4>;
+using Plan384 = FFTPlan<384, 16, 24, 4, 4>;
+using Plan512 = FFTPlan<512, 32, 16, 16, 2>;
+
+bool cart1d_supported(int ny) {
+  switch (ny) {
+    case 64: case 96: case 128: case 160: case 192: case 256: case 288: case 320: case 384: case 512:
+      return true;
+    default:
+      return false;
+  }
+}
+
+hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s) {
+  switch (a.ny) {
+    case 64: return launch_plan<Plan64>(mode, a, s);
+    case 96: return launch_plan<Plan96>(mode, a, s);
+    case 128: return launch_plan<Plan128>(mode, a, s);
+    case 160: return launch_plan<Plan160>(mode, a, s);
+    case 192: return launch_plan<Plan192>(mode, a, s);
+    case 256: return launch_plan<Plan256>(mode, a, s);
+    case 288: return launch_plan<Plan288>(mode, a, s);
+    case 320: return launch_plan<Plan320>(mode, a, s);
+    case 384: return launch_plan<Plan384>(mode, a, s);
+    case 512: return launch_plan<Plan512>(mode, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------ map preparation
+// out[col][c][y] = (-1)^y sum_d Linv[c][d] maps[d][y][col]  (whitening, Sec. 2.1 Eq. (3))
+__global__ void k_prep_maps_cart1d(const float2* __restrict__ maps, const double* __restrict__ linv,
+                                   float2* __restrict__ out, int nc, int ny, int nx) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (y >= ny) return;
+  const double sg = (y & 1) ? -1.0 : 1.0;
+  for (int c = 0; c < nc; ++c) {
+    double re = 0.0, im = 0.0;
+    for (int d = 0; d <= c; ++d) {
+      const double lr = linv[2 * (c * nc + d)], li = linv[2 * (c * nc + d) + 1];
+      const float2 m = maps[((size_t)d * ny + y) * nx + col];
+      re += lr * m.x - li * m.y;
+      im += lr * m.y + li * m.x;
+    }
+    out[((size_t)col * nc + c) * ny + y] = make_float2((float)(sg * re), (float)(sg * im));
+  }
+}
+
+hipError_t launch_prep_maps_cart1d(const float2* maps, const double* linv, float2* out, int nc,
+                                   int ny, int nx, hipStream_t s) {
+  dim3 grid((ny + 63) / 64, nx), block(64);
+  hipLaunchKernelGGL(k_prep_maps_cart1d, grid, block, 0, s, maps, linv, out, nc, ny, nx);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ power-method start
+__global__ void k_power_start(float2* __restrict__ p, int ny, int nx) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (y >= ny) return;
+  const float s = rsqrtf((float)ny * (float)nx);
+  const float2 v = draw_probe(0, 0, (uint32_t)(y * nx + col), 3u, 0);
+  p[(size_t)col * ny + y] = cscale(v, s);
+}
+
+hipError_t launch_power_start(float2* p, int ny, int nx, hipStream_t s) {
+  dim3 grid((ny + 63) / 64, nx), block(64);
+  hipLaunchKernelGGL(k_power_start, grid, block, 0, s, p, ny, nx);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ accumulation
+// PICO: sum += Re(conj v x), sum_im += Im(conj v x), sumsq += Re(.)^2 over the
+// K probes of the tile, in probe order (App. A, Algorithm 1).  PMR: sum +=
+// x, sumsq += |x|^2.
+__global__ void k_accum_colmajor(AccumArgs a) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (y >= a.ny) return;
+  const uint32_t vox = (uint32_t)(y * a.nx + col);
+  double s = 0.0, si = 0.0, ss = 0.0;
+  for (int k = 0; k < a.K; ++k) {
+    const float2 u = a.x[((size_t)k * a.nx + col) * a.ny + y];
+    if (a.pmr) {
+      s += (double)u.x;
+      si += (double)u.y;
+      ss += (double)u.x * u.x + (double)u.y * u.y;
+    } else {
+      const float2 v = draw_probe(a.seed, a.first + k, vox, 0u, a.dist);
+      const double re = (double)v.x * u.x + (double)v.y * u.y;
+      const double im = (double)v.x * u.y - (double)v.y * u.x;
+      s += re;
+      si += im;
+      ss += re * re;
+    }
+  }
+  a.sum[vox] += s;
+  if (a.sum_im) a.sum_im[vox] += si;
+  if (a.sumsq) a.sumsq[vox] += ss;
+}
+
+hipError_t launch_accum_colmajor(const AccumArgs& a, hipStream_t s) {
+  dim3 grid((a.ny + 63) / 64, a.nx), block(64);
+  hipLaunchKernelGGL(k_accum_colmajor, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ layout changes
+// v [K][ny][nx] (row-major images) -> out [K][nx][ny]
+__global__ void k_transpose_in(const float2* __restrict__ v, float2* __restrict__ out, int ny, int nx) {
+  __shared__ float2 tile[32][33];
+  const int k = blockIdx.z;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const float2* vk = v + (size_t)k * ny * nx;
+  float2* ok = out + (size_t)k * ny * nx;
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int y = y0 + i, x = x0 + threadIdx.x;
+    if (y < ny && x < nx) tile[i][threadIdx.x] = vk[(size_t)y * nx + x];
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int x = x0 + i, y = y0 + threadIdx.x;
+    if (y < ny && x < nx) ok[(size_t)x * ny + y] = tile[threadIdx.x][i];
+  }
+}
+
+// x [K][nx][ny] -> u [K][ny][nx]
+__global__ void k_transpose_out(const float2* __restrict__ x, float2* __restrict__ u, int ny, int nx) {
+  __shared__ float2 tile[32][33];
+  const int k = blockIdx.z;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const float2* xk = x + (size_t)k * ny * nx;
+  float2* uk = u + (size_t)k * ny * nx;
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int x = x0 + i, y = y0 + threadIdx.x;
+    if (y < ny && x < nx) tile[i][threadIdx.x] = xk[(size_t)x * ny + y];
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int y = y0 + i, xx = x0 + threadIdx.x;
+    if (y < ny && xx < nx) uk[(size_t)y * nx + xx] = tile[threadIdx.x][i];
+  }
+}
+
+hipError_t launch_transpose_in(const float2* v, float2* out, int K, int ny, int nx, hipStream_t s) {
+  dim3 grid((nx + 31) / 32, (ny + 31) / 32, K), block(32, 8);
+  hipLaunchKernelGGL(k_transpose_in, grid, block, 0, s, v, out, ny, nx);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_out(const float2* x, float2* u, int K, int ny, int nx, hipStream_t s) {
+  dim3 grid((nx + 31) / 32, (ny + 31) / 32, K), block(32, 8);
+  hipLaunchKernelGGL(k_transpose_out, grid, block, 0, s, x, u, ny, nx);
+  return hipGetLastError();
+}
+
+}  // namespace pico

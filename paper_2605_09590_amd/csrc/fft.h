@@ -1,0 +1,226 @@
+// Register-resident Stockham FFT for one line of length N spread over a
+// group of T lanes of a wavefront (gfx950: 64-wide wavefronts).
+//
+// Lane t of the group holds v[m] = x[t + T*m], m < P = N/T, before and after
+// the transform (natural order, no bit reversal).  Pass p has radix R_p; each
+// lane performs B_p = P/R_p butterflies j = t + T*b.  A butterfly reads the
+// elements j + r*N/R (which are exactly the lane's own registers b + B*r),
+// applies the twiddles W_{NS*R}^{r*k}, k = j mod NS, computes an R-point DFT
+// in registers and scatters to (j - k)*R + k + r*NS; all passes but the last
+// exchange through LDS, the last one lands back in the lane's registers.
+// The first pass (NS = 1) needs no twiddles.
+//
+// Direction: INV = false computes sum_n x[n] e^{-2 pi i n k / N},
+// INV = true the unnormalised inverse (e^{+}).
+#pragma once
+
+#include "device_common.h"
+
+namespace pico {
+
+// ------------------------------------------------------ in-register DFTs
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+  const float2 t = a0;
+  a0 = cadd(t, a1);
+  a1 = csub(t, a1);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
+  constexpr float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+  const float2 t1 = cadd(a1, a2);
+  const float2 t2 = csub(a1, a2);
+  const float2 b = make_float2(a0.x - 0.5f * t1.x, a0.y - 0.5f * t1.y);
+  const float2 d = mul_mj<INV>(make_float2(h * t2.x, h * t2.y));   // -/+ j h t2
+  a0 = cadd(a0, t1);
+  a1 = cadd(b, d);
+  a2 = csub(b, d);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  const float2 s13 = cadd(a1, a3), d13 = mul_mj<INV>(csub(a1, a3));
+  a0 = cadd(s02, s13);
+  a2 = csub(s02, s13);
+  a1 = cadd(d02, d13);
+  a3 = csub(d02, d13);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft5(float2& a0, float2& a1, float2& a2, float2& a3, float2& a4) {
+  constexpr float c1 = (float)tw_cos(1, 5), c2 = (float)tw_cos(2, 5);
+  constexpr float s1 = (float)tw_sin(1, 5), s2 = (float)tw_sin(2, 5);
+  const float2 t1 = cadd(a1, a4), t2 = cadd(a2, a3);
+  const float2 t3 = csub(a1, a4), t4 = csub(a2, a3);
+  const float2 b1 = make_float2(a0.x + c1 * t1.x + c2 * t2.x, a0.y + c1 * t1.y + c2 * t2.y);
+  const float2 b2 = make_float2(a0.x + c2 * t1.x + c1 * t2.x, a0.y + c2 * t1.y + c1 * t2.y);
+  const float2 d1 = mul_mj<INV>(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+  const float2 d2 = mul_mj<INV>(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+  a0 = cadd(a0, cadd(t1, t2));
+  a1 = cadd(b1, d1);
+  a4 = csub(b1, d1);
+  a2 = cadd(b2, d2);
+  a3 = csub(b2, d2);
+}
+
+// multiply by the compile-time twiddle W_R^{m} (sign by direction)
+template <int M, int R, bool INV>
+__device__ __forceinline__ float2 ctwiddle(float2 a) {
+  constexpr int mm = ((M % R) + R) % R;
+  if constexpr (mm == 0) {
+    return a;
+  } else if constexpr ((4 * mm) % R == 0) {
+    constexpr int q = (4 * mm) / R;                 // quarter turns, 1..3
+    if constexpr (q == 2) return make_float2(-a.x, -a.y);
+    else if constexpr (q == 1) return mul_mj<INV>(a);
+    else return mul_mj<!INV>(a);
+  } else {
+    constexpr float c = (float)tw_cos(mm, R);
+    constexpr float s = INV ? (float)tw_sin(mm, R) : -(float)tw_sin(mm, R);
+    return cmul(a, make_float2(c, s));
+  }
+}
+
+// R-point DFT in registers; composite R by decimation in time, R = F * Q:
+// X[k1 + Q k2] = sum_{n1<F} W_F^{n1 k2} W_R^{n1 k1} Y_{n1}[k1],
+// Y_{n1} = DFT_Q(x[n1 + F n2]).
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&a)[R]) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2<INV>(a[0], a[1]);
+  } else if constexpr (R == 3) {
+    dft3<INV>(a[0], a[1], a[2]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 5) {
+    dft5<INV>(a[0], a[1], a[2], a[3], a[4]);
+  } else {
+    constexpr int F = (R % 4 == 0) ? 4 : (R % 2 == 0) ? 2 : (R % 3 == 0) ? 3 : 5;
+    constexpr int Q = R / F;
+    static_assert(F * Q == R, "radix must factor into 2, 3, 4, 5");
+    float2 y[F][Q];
+    static_for<0, F>([&](auto n1) {
+      static_for<0, Q>([&](auto n2) { y[n1][n2] = a[n1 + F * n2]; });
+      dft<Q, INV>(y[n1]);
+    });
+    static_for<0, Q>([&](auto k1) {
+      float2 z[F];
+      static_for<0, F>([&](auto n1) {
+        z[n1] = ctwiddle<n1 * k1, R, INV>(y[n1][k1]);
+      });
+      dft<F, INV>(z);
+      static_for<0, F>([&](auto k2) { a[k1 + Q * k2] = z[k2]; });
+    });
+  }
+}
+
+// ------------------------------------------------------------------ plans
+template <int N_, int T_, int... Rs>
+struct FFTPlan {
+  static constexpr int N = N_;
+  static constexpr int T = T_;
+  static constexpr int P = N / T;
+  static constexpr int NP = sizeof...(Rs);
+  static constexpr int R[NP] = {Rs...};
+  static constexpr int ns(int p) {
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= R[i];
+    return s;
+  }
+  // one base twiddle per butterfly of every pass after the first
+  static constexpr int tw_off(int p) {
+    int s = 0;
+    for (int i = 1; i < p; ++i) s += P / R[i];
+    return s;
+  }
+  static constexpr int NTW = tw_off(NP) > 0 ? tw_off(NP) : 1;
+  static constexpr bool valid() {
+    int prod = 1;
+    for (int i = 0; i < NP; ++i) {
+      if (P % R[i] != 0) return false;
+      prod *= R[i];
+    }
+    return prod == N && N % T == 0 && 64 % T == 0;
+  }
+  static_assert(valid(), "invalid FFT plan");
+};
+
+// LDS index padding: one float2 of padding every 16 entries
+__device__ __forceinline__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+template <int N>
+constexpr int lds_span() { return N + N / 16 + 1; }
+
+// Per-lane base twiddles W_{NS R}^{k} (forward sign) for every butterfly of
+// every pass after the first, read once from a table W_N^m, m < N.
+template <class PL>
+__device__ __forceinline__ void load_twiddles(float2 (&tw)[PL::NTW],
+                                              const float2* __restrict__ table, int t) {
+  static_for<1, PL::NP>([&](auto pc) {
+    constexpr int p = pc;
+    constexpr int R = PL::R[p];
+    constexpr int NS = PL::ns(p);
+    constexpr int B = PL::P / R;
+    constexpr int off = PL::tw_off(p);
+    constexpr int stride = PL::N / (NS * R);
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + PL::T * b;
+      const int k = j % NS;
+      tw[off + b] = table[k * stride];
+    }
+  });
+}
+
+template <class PL, int p, bool INV>
+__device__ __forceinline__ void fft_pass(float2 (&v)[PL::P], float2* lds, int t,
+                                         const float2 (&tw)[PL::NTW]) {
+  constexpr int R = PL::R[p];
+  constexpr int NS = PL::ns(p);
+  constexpr int B = PL::P / R;
+  constexpr int T = PL::T;
+  constexpr bool last = (p == PL::NP - 1);
+  constexpr int off = PL::tw_off(p);
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    float2 a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[b + B * r];
+    if constexpr (NS > 1) {
+      const float2 w1 = INV ? make_float2(tw[off + b].x, -tw[off + b].y) : tw[off + b];
+      float2 w = w1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        a[r] = cmul(a[r], w);
+        if (r + 1 < R) w = cmul(w, w1);
+      }
+    }
+    dft<R, INV>(a);
+    if constexpr (last) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + B * r] = a[r];
+    } else {
+      const int j = t + T * b;
+      const int k = j % NS;
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = a[r];
+    }
+  }
+  if constexpr (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PL::P; ++m) v[m] = lds[lds_pad(t + T * m)];
+    __syncthreads();
+  }
+}
+
+template <class PL, bool INV>
+__device__ __forceinline__ void fft(float2 (&v)[PL::P], float2* lds, int t,
+                                    const float2 (&tw)[PL::NTW]) {
+  static_for<0, PL::NP>([&](auto pc) { fft_pass<PL, pc, INV>(v, lds, t, tw); });
+}
+
+}  // namespace pico

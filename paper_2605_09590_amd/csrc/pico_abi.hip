@@ -1,0 +1,478 @@
+// Host runtime behind the C ABI in include/pico.h.
+//
+// Owns the operator (whitened maps, sampling weights, twiddle tables, the
+// batched-CG workspace) and sequences the kernels of one probe tile:
+//   probe tile -> K independent CG solves (App. A, Algorithm 1, covariance
+//   step) -> FP64 accumulation of conj(v) . u.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pico.h"
+#include "runtime.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+pico_status_t fail(pico_status_t st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_OR_RETURN(expr)                                                          \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(PICO_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct pico_op_s {
+  int ny = 0, nx = 0, nc = 0, sampling = 0, recon = 0;
+  int cg_iters = 0, K = 0;
+  double cg_tol = 0.0, lam_rel = 0.0, lam_abs = 0.0;
+  int nblkB = 0;
+  hipStream_t last_stream = nullptr;
+  // resident operator
+  float2* maps = nullptr;   // [nx][nc][ny]
+  float* maskw = nullptr;   // [ny]
+  float2* twt = nullptr;    // [ny]
+  // batched CG workspace, [K][nx][ny] each
+  float2 *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  double* partA = nullptr;  // [K][nx][2]
+  double* partB = nullptr;  // [K][nblkB]
+  double *alpha = nullptr, *beta = nullptr, *rr = nullptr, *rr0 = nullptr;
+  int* state = nullptr;
+  std::vector<void*> allocs;
+
+  ~pico_op_s() {
+    for (void* ptr : allocs) (void)hipFree(ptr);
+  }
+  template <class T>
+  hipError_t alloc(T** ptr, size_t count) {
+    void* raw = nullptr;
+    hipError_t e = hipMalloc(&raw, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) {
+      allocs.push_back(raw);
+      *ptr = static_cast<T*>(raw);
+    }
+    return e;
+  }
+};
+
+namespace {
+
+// Cholesky L L^H = psi (lower), then L^-1; float64 on the host.
+bool cholesky_inverse(const double* psi, int n, std::vector<double>& linv_out, std::string& why) {
+  std::vector<cd> A(n * n), L(n * n, cd(0, 0)), Li(n * n, cd(0, 0));
+  for (int i = 0; i < n * n; ++i) A[i] = cd(psi[2 * i], psi[2 * i + 1]);
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(A[i * n + i]));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (std::abs(A[i * n + j] - std::conj(A[j * n + i])) > 1e-10 * scale) {
+        why = "psi is not Hermitian";
+        return false;
+      }
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j].real();
+    for (int k = 0; k < j; ++k) d -= std::norm(L[j * n + k]);
+    if (!(d > 0.0)) {
+      why = "psi is not positive definite";
+      return false;
+    }
+    const double ljj = std::sqrt(d);
+    L[j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      cd s = A[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * std::conj(L[j * n + k]);
+      L[i * n + j] = s / ljj;
+    }
+  }
+  for (int j = 0; j < n; ++j) {  // forward substitution for each unit vector
+    Li[j * n + j] = 1.0 / L[j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      cd s = 0.0;
+      for (int k = j; k < i; ++k) s -= L[i * n + k] * Li[k * n + j];
+      Li[i * n + j] = s / L[i * n + i];
+    }
+  }
+  linv_out.resize(2 * n * n);
+  for (int i = 0; i < n * n; ++i) {
+    linv_out[2 * i] = Li[i].real();
+    linv_out[2 * i + 1] = Li[i].imag();
+  }
+  return true;
+}
+
+pico_status_t check_op(pico_op_t op) {
+  if (!op) return fail(PICO_EINVAL, "NULL operator handle");
+  return PICO_OK;
+}
+
+pico::Cart1dArgs base_args(pico_op_t op, int K) {
+  pico::Cart1dArgs a{};
+  a.ny = op->ny;
+  a.nx = op->nx;
+  a.nc = op->nc;
+  a.K = K;
+  a.maps = op->maps;
+  a.maskw = op->maskw;
+  a.twt = op->twt;
+  a.r = op->r;
+  a.p = op->p;
+  a.q = op->q;
+  a.beta = op->beta;
+  a.part = op->partA;
+  a.lam = (float)op->lam_abs;
+  a.scale = 1.0f;
+  return a;
+}
+
+hipError_t scalars(pico_op_t op, int K, int stage, hipStream_t s) {
+  pico::ScalarArgs sa{};
+  sa.K = K;
+  sa.part = stage == 2 ? op->partB : op->partA;
+  sa.nblk = stage == 2 ? op->nblkB : op->nx;
+  sa.alpha = op->alpha;
+  sa.beta = op->beta;
+  sa.rr = op->rr;
+  sa.rr0 = op->rr0;
+  sa.state = op->state;
+  sa.tol = op->cg_tol;
+  sa.stage = stage;
+  return pico::launch_scalars(sa, s);
+}
+
+// One batched CG solve of (M + lam) x = b for K right-hand sides.  The
+// first normal-operator application uses ``first_mode`` (probe draw or the
+// right-hand side already in r); the solution ends in op->x.
+hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t first, int dist,
+                    hipStream_t s) {
+  pico::Cart1dArgs a = base_args(op, K);
+  a.seed = seed;
+  a.first = first;
+  a.dist = dist;
+  hipError_t e = pico::launch_cart1d(first_mode, a, s);
+  if (e != hipSuccess) return e;
+  if ((e = scalars(op, K, 0, s)) != hipSuccess) return e;
+  pico::UpdateArgs u{};
+  u.n = op->ny * op->nx;
+  u.K = K;
+  u.x = op->x;
+  u.r = op->r;
+  u.p = op->p;
+  u.q = op->q;
+  u.alpha = op->alpha;
+  u.part = op->partB;
+  u.nblk = op->nblkB;
+  for (int it = 0; it < op->cg_iters; ++it) {
+    if (it > 0) {
+      if ((e = pico::launch_cart1d(pico::C1_ITER, a, s)) != hipSuccess) return e;
+      if ((e = scalars(op, K, 1, s)) != hipSuccess) return e;
+    }
+    u.first_iter = (it == 0);
+    if ((e = pico::launch_update(u, s)) != hipSuccess) return e;
+    if ((e = scalars(op, K, 2, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// u = Sigma v for the K right-hand sides (probes drawn in-kernel or already
+// in r): one solve for lam = 0, else solve, M, solve (Sec. 2.1, Eq. (8)).
+hipError_t apply_sigma(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t first, int dist,
+                       hipStream_t s) {
+  hipError_t e = cg_solve(op, K, first_mode, seed, first, dist, s);
+  if (e != hipSuccess || op->lam_abs == 0.0) return e;
+  pico::Cart1dArgs a = base_args(op, K);
+  a.src = op->x;
+  a.q = op->r;     // t = M w lands in r, the next right-hand side
+  a.lam = 0.0f;
+  if ((e = pico::launch_cart1d(pico::C1_APPLY, a, s)) != hipSuccess) return e;
+  return cg_solve(op, K, pico::C1_FIRST_BUF, 0, 0, 0, s);
+}
+
+struct StatAcc {
+  int64_t n = 0;
+  double maxr = 0.0, sumr = 0.0;
+  int frozen = 0;
+};
+
+hipError_t collect_stats(pico_op_t op, int K, hipStream_t s, StatAcc& sa) {
+  std::vector<double> rr(K), rr0(K);
+  std::vector<int> st(K);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(rr.data(), op->rr, K * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(rr0.data(), op->rr0, K * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(st.data(), op->state, K * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  for (int k = 0; k < K; ++k) {
+    const double rel = rr0[k] > 0 ? std::sqrt(std::max(rr[k], 0.0) / rr0[k]) : 0.0;
+    sa.maxr = std::max(sa.maxr, rel);
+    sa.sumr += rel;
+    sa.frozen += (st[k] == pico::CG_BREAKDOWN);
+  }
+  sa.n += K;
+  return hipSuccess;
+}
+
+pico_status_t write_stats(pico_op_t op, const StatAcc& sa, pico_stats_t* st) {
+  st->probes = sa.n;
+  st->max_relres = sa.maxr;
+  st->mean_relres = sa.n ? sa.sumr / sa.n : 0.0;
+  st->frozen = sa.frozen;
+  st->lambda_abs = op->lam_abs;
+  if (sa.frozen) return fail(PICO_ENOTCONV, "CG breakdown in " + std::to_string(sa.frozen) + " right-hand side(s)");
+  return PICO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pico_last_error(void) { return g_err.c_str(); }
+
+pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
+  if (!d || !out) return fail(PICO_EINVAL, "NULL descriptor or output handle");
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if (d->recon != PICO_CGSENSE) return fail(PICO_EUNSUPPORTED, "only CG-SENSE reconstructions are built");
+  if (d->sampling != PICO_CART_1D)
+    return fail(PICO_EUNSUPPORTED, "only phase-encode (1-D) Cartesian sampling is built");
+  if (d->ncoils < 1 || d->ncoils > 64) return fail(PICO_EINVAL, "ncoils must be in 1..64");
+  if (d->nx < 1 || d->ny < 2 || (d->ny & 1)) return fail(PICO_EINVAL, "ny must be even and nx >= 1");
+  if (!pico::cart1d_supported(d->ny))
+    return fail(PICO_EINVAL, "ny=" + std::to_string(d->ny) +
+                                 " has no built FFT plan (64 96 128 160 192 256 288 320 384 512)");
+  if ((int64_t)d->ny * d->nx >= (int64_t)1 << 31) return fail(PICO_EINVAL, "image too large");
+  if (d->cg_iters < 1) return fail(PICO_EINVAL, "cg_iters must be >= 1");
+  if (d->probe_tile < 1 || d->probe_tile > 65535) return fail(PICO_EINVAL, "probe_tile must be in 1..65535");
+  if (!(d->lambda >= 0.0) || !std::isfinite(d->lambda)) return fail(PICO_EINVAL, "lambda must be finite and >= 0");
+  if (!(d->cg_tol >= 0.0)) return fail(PICO_EINVAL, "cg_tol must be >= 0");
+  if (!d->maps || !d->mask) return fail(PICO_EINVAL, "maps and mask are required");
+  if (d->lambda > 0.0 && (d->power_iters < 1 || !(d->power_margin > 0.0)))
+    return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
+
+  const int nc = d->ncoils, ny = d->ny, nx = d->nx;
+  std::vector<double> linv;
+  if (d->psi) {
+    std::string why;
+    if (!cholesky_inverse(d->psi, nc, linv, why)) return fail(PICO_EINVAL, why);
+  } else {
+    linv.assign(2 * nc * nc, 0.0);
+    for (int c = 0; c < nc; ++c) linv[2 * (c * nc + c)] = 1.0;
+  }
+
+  auto* op = new pico_op_s();
+  op->ny = ny;
+  op->nx = nx;
+  op->nc = nc;
+  op->sampling = d->sampling;
+  op->recon = d->recon;
+  op->cg_iters = d->cg_iters;
+  op->cg_tol = d->cg_tol;
+  op->lam_rel = d->lambda;
+  op->K = d->probe_tile;
+  op->last_stream = s;
+  const size_t n = (size_t)ny * nx;
+  const int K = op->K;
+  op->nblkB = (int)std::min<size_t>(1024, (n + 1023) / 1024);
+
+  double* linv_d = nullptr;
+  hipError_t e = hipSuccess;
+  auto bad = [&](hipError_t err, const char* what) {
+    delete op;
+    if (err == hipErrorOutOfMemory || err == hipErrorMemoryAllocation)
+      return fail(PICO_ENOMEM, std::string(what) + ": out of device memory");
+    return fail(PICO_EDEVICE, std::string(what) + ": " + hipGetErrorString(err));
+  };
+  if ((e = op->alloc(&op->maps, n * nc)) != hipSuccess) return bad(e, "maps");
+  if ((e = op->alloc(&op->maskw, ny)) != hipSuccess) return bad(e, "mask");
+  if ((e = op->alloc(&op->twt, ny)) != hipSuccess) return bad(e, "twiddles");
+  if ((e = op->alloc(&op->x, n * K)) != hipSuccess) return bad(e, "workspace x");
+  if ((e = op->alloc(&op->r, n * K)) != hipSuccess) return bad(e, "workspace r");
+  if ((e = op->alloc(&op->p, n * K)) != hipSuccess) return bad(e, "workspace p");
+  if ((e = op->alloc(&op->q, n * K)) != hipSuccess) return bad(e, "workspace q");
+  if ((e = op->alloc(&op->partA, (size_t)K * nx * 2)) != hipSuccess) return bad(e, "partials");
+  if ((e = op->alloc(&op->partB, (size_t)K * op->nblkB)) != hipSuccess) return bad(e, "partials");
+  if ((e = op->alloc(&op->alpha, K)) != hipSuccess) return bad(e, "scalars");
+  if ((e = op->alloc(&op->beta, K)) != hipSuccess) return bad(e, "scalars");
+  if ((e = op->alloc(&op->rr, K)) != hipSuccess) return bad(e, "scalars");
+  if ((e = op->alloc(&op->rr0, K)) != hipSuccess) return bad(e, "scalars");
+  if ((e = op->alloc(&op->state, K)) != hipSuccess) return bad(e, "scalars");
+  if ((e = op->alloc(&linv_d, linv.size())) != hipSuccess) return bad(e, "whitening");
+
+  // sampling weights: the centred DFT is (-1)^(ny/2) D F D with D = (-1)^y,
+  // so the centred-order mask applies unchanged to the plain FFT output;
+  // w[k] = mask[k] / ny carries the orthonormal scaling of F^H P F.
+  std::vector<uint8_t> mask_h(ny);
+  if ((e = hipMemcpyAsync(mask_h.data(), d->mask, ny, hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "mask copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "mask copy");
+  std::vector<float> w(ny);
+  for (int k = 0; k < ny; ++k) w[k] = mask_h[k] ? (float)(1.0 / ny) : 0.0f;
+  std::vector<float2> tw(ny);
+  for (int m = 0; m < ny; ++m) {
+    const double ang = -2.0 * 3.14159265358979323846 * (double)m / (double)ny;
+    tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  if ((e = hipMemcpyAsync(op->maskw, w.data(), ny * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+  if ((e = hipMemcpyAsync(op->twt, tw.data(), ny * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+  if ((e = hipMemcpyAsync(linv_d, linv.data(), linv.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+  if ((e = pico::launch_prep_maps_cart1d((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, s)) != hipSuccess) return bad(e, "prep maps");
+  if ((e = hipMemsetAsync(op->state, 0, K * sizeof(int), s)) != hipSuccess) return bad(e, "memset");
+
+  // spectral normalisation (Sec. 3.2.1, 3.3): lambda_max of M by power steps
+  if (d->lambda > 0.0) {
+    if ((e = pico::launch_power_start(op->p, ny, nx, s)) != hipSuccess) return bad(e, "power");
+    double lam_hat = 0.0;
+    double scale = 1.0;
+    float2* src = op->p;
+    float2* dst = op->q;
+    for (int it = 0; it < d->power_iters; ++it) {
+      pico::Cart1dArgs a = base_args(op, 1);
+      a.src = src;
+      a.q = dst;
+      a.lam = 0.0f;
+      a.scale = (float)scale;
+      if ((e = pico::launch_cart1d(pico::C1_APPLY, a, s)) != hipSuccess) return bad(e, "power");
+      std::vector<double> part((size_t)nx * 2);
+      if ((e = hipMemcpyAsync(part.data(), op->partA, part.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "power");
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "power");
+      double vq = 0.0, qq = 0.0;
+      for (int c = 0; c < nx; ++c) {
+        vq += part[2 * c];
+        qq += part[2 * c + 1];
+      }
+      lam_hat = vq;              // Rayleigh quotient of the unit vector (scale * src)
+      scale = 1.0 / std::sqrt(qq);
+      std::swap(src, dst);
+    }
+    op->lam_abs = d->lambda * d->power_margin * lam_hat;
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "init");
+  (void)hipFree(linv_d);
+  op->allocs.erase(std::remove(op->allocs.begin(), op->allocs.end(), (void*)linv_d), op->allocs.end());
+  *out = op;
+  return PICO_OK;
+}
+
+double pico_lambda_abs(pico_op_t op) { return op ? op->lam_abs : NAN; }
+
+pico_status_t pico_apply_cov(pico_op_t op, const void* v, void* u, int32_t k, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!v || !u) return fail(PICO_EINVAL, "NULL v or u");
+  if (k < 1 || k > op->K) return fail(PICO_EINVAL, "k must be in 1..probe_tile");
+  hipStream_t s = (hipStream_t)stream;
+  op->last_stream = s;
+  HIP_OR_RETURN(pico::launch_transpose_in((const float2*)v, op->r, k, op->ny, op->nx, s));
+  HIP_OR_RETURN(apply_sigma(op, k, pico::C1_FIRST_BUF, 0, 0, 0, s));
+  HIP_OR_RETURN(pico::launch_transpose_out(op->x, (float2*)u, k, op->ny, op->nx, s));
+  return PICO_OK;
+}
+
+pico_status_t pico_noise_map(pico_op_t op, uint64_t seed, int64_t first_probe, int64_t nprobes,
+                             int32_t dist, pico_accum_t* acc, pico_stats_t* stats, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!acc || !acc->sum) return fail(PICO_EINVAL, "accumulator with a sum buffer is required");
+  if (nprobes < 0 || first_probe < 0) return fail(PICO_EINVAL, "negative probe range");
+  if (dist < 0 || dist > 3) return fail(PICO_EINVAL, "unknown probe family");
+  hipStream_t s = (hipStream_t)stream;
+  op->last_stream = s;
+  StatAcc sa;
+  for (int64_t done = 0; done < nprobes;) {
+    const int K = (int)std::min<int64_t>(op->K, nprobes - done);
+    const uint64_t first = (uint64_t)(first_probe + done);
+    HIP_OR_RETURN(apply_sigma(op, K, pico::C1_FIRST_PROBE, seed, first, dist, s));
+    pico::AccumArgs aa{};
+    aa.ny = op->ny;
+    aa.nx = op->nx;
+    aa.K = K;
+    aa.x = op->x;
+    aa.sum = acc->sum;
+    aa.sum_im = acc->sum_im;
+    aa.sumsq = acc->sumsq;
+    aa.seed = seed;
+    aa.first = first;
+    aa.dist = dist;
+    aa.pmr = 0;
+    HIP_OR_RETURN(pico::launch_accum_colmajor(aa, s));
+    if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));
+    done += K;
+  }
+  acc->count += nprobes;
+  if (stats) return write_stats(op, sa, stats);
+  return PICO_OK;
+}
+
+pico_status_t pico_finalize(pico_op_t op, const pico_accum_t* acc, double* var, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!acc || !acc->sum || !var) return fail(PICO_EINVAL, "NULL accumulator or output");
+  if (acc->count < 1) return fail(PICO_EINVAL, "no probes accumulated");
+  HIP_OR_RETURN(pico::launch_finalize(acc->sum, var, (int64_t)op->ny * op->nx, 1.0 / (double)acc->count,
+                                      (hipStream_t)stream));
+  return PICO_OK;
+}
+
+pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int64_t nrep,
+                                pico_accum_t* acc, pico_stats_t* stats, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq)
+    return fail(PICO_EINVAL, "PMR needs sum, sum_im and sumsq buffers");
+  if (nrep < 0 || first < 0) return fail(PICO_EINVAL, "negative replica range");
+  hipStream_t s = (hipStream_t)stream;
+  op->last_stream = s;
+  StatAcc sa;
+  for (int64_t done = 0; done < nrep;) {
+    const int K = (int)std::min<int64_t>(op->K, nrep - done);
+    const uint64_t f = (uint64_t)(first + done);
+    pico::Cart1dArgs a = base_args(op, K);
+    a.seed = seed;
+    a.first = f;
+    HIP_OR_RETURN(pico::launch_cart1d(pico::C1_PMR_RHS, a, s));
+    HIP_OR_RETURN(cg_solve(op, K, pico::C1_FIRST_BUF, 0, 0, 0, s));
+    pico::AccumArgs aa{};
+    aa.ny = op->ny;
+    aa.nx = op->nx;
+    aa.K = K;
+    aa.x = op->x;
+    aa.sum = acc->sum;
+    aa.sum_im = acc->sum_im;
+    aa.sumsq = acc->sumsq;
+    aa.pmr = 1;
+    HIP_OR_RETURN(pico::launch_accum_colmajor(aa, s));
+    if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));
+    done += K;
+  }
+  acc->count += nrep;
+  if (stats) return write_stats(op, sa, stats);
+  return PICO_OK;
+}
+
+pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* var, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq || !var)
+    return fail(PICO_EINVAL, "NULL accumulator field or output");
+  if (acc->count < 2) return fail(PICO_EINVAL, "need at least 2 replicas");
+  HIP_OR_RETURN(pico::launch_pmr_finalize(acc->sum, acc->sum_im, acc->sumsq, var,
+                                          (int64_t)op->ny * op->nx, (double)acc->count,
+                                          (hipStream_t)stream));
+  return PICO_OK;
+}
+
+void pico_destroy(pico_op_t op) {
+  if (!op) return;
+  (void)hipStreamSynchronize(op->last_stream);
+  delete op;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal interface between the host runtime (pico.cpp) and the kernel
+// launchers (*.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pico {
+
+// Per-probe CG state flags
+enum : int { CG_ACTIVE = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
+
+// Modes of the separable Cartesian column kernel.
+enum Cart1dMode : int {
+  C1_FIRST_PROBE = 0,  // r = p = v (Philox probe); q = (M + lam) p
+  C1_FIRST_BUF = 1,    // p = r (right-hand side already in r); q = (M + lam) p
+  C1_ITER = 2,         // p = r + beta p; q = (M + lam) p
+  C1_APPLY = 3,        // dst = (M + lam) (scale * src)
+  C1_PMR_RHS = 4,      // r = A^H n, n white k-space noise in the hybrid (ky, x) domain
+};
+
+struct Cart1dArgs {
+  int ny, nx, nc, K;           // K probes in this launch
+  const float2* maps;          // [nx][nc][ny] whitened, (-1)^y folded
+  const float* maskw;          // [ny] weight mask[k] / ny (0 off the mask)
+  const float2* twt;           // [ny] W_ny^m = exp(-2 pi i m / ny)
+  const float2* src;           // input field   (mode dependent)
+  float2* r;                   // [K][nx][ny]
+  float2* p;
+  float2* q;
+  const double* beta;          // [K]
+  double* part;                // [K][nx][2] partial dots
+  float lam;                   // added to M p
+  float scale;                 // C1_APPLY input scale
+  uint64_t seed, first;        // probe / noise draw
+  int dist;                    // probe family
+};
+
+// CG update x += alpha p, r -= alpha q; part[.][.][1] = |r|^2 partials
+struct UpdateArgs {
+  int n, K;                    // n = voxels per probe
+  float2* x;
+  float2* r;
+  const float2* p;
+  const float2* q;
+  const double* alpha;         // [K]
+  double* part;                // [K][nblk][2]
+  int nblk;                    // partial blocks per probe
+  int first_iter;              // x treated as 0
+};
+
+struct ScalarArgs {
+  int K, nblk;
+  const double* part;          // [K][nblk][2]
+  double* alpha;               // [K]
+  double* beta;                // [K]
+  double* rr;                  // [K]
+  double* rr0;                 // [K]
+  int* state;                  // [K]
+  double tol;
+  int stage;                   // 0: after first normal op (sets rr0, rr, alpha); 1: after A (alpha); 2: after B (beta)
+};
+
+struct AccumArgs {
+  int ny, nx, K;
+  const float2* x;             // [K][nx][ny] (col-major image per probe)
+  double* sum;                 // [ny*nx]
+  double* sum_im;              // may be null
+  double* sumsq;               // may be null
+  uint64_t seed, first;
+  int dist;
+  int pmr;                     // 1: accumulate x itself (PMR); 0: conj(v) x (PICO)
+};
+
+bool cart1d_supported(int ny);
+hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
+hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
+hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);
+hipError_t launch_accum_colmajor(const AccumArgs& a, hipStream_t s);
+hipError_t launch_prep_maps_cart1d(const float2* maps, const double* linv, float2* out,
+                                   int nc, int ny, int nx, hipStream_t s);
+hipError_t launch_transpose_in(const float2* v, float2* out, int K, int ny, int nx, hipStream_t s);
+hipError_t launch_transpose_out(const float2* x, float2* u, int K, int ny, int nx, hipStream_t s);
+hipError_t launch_finalize(const double* sum, double* var, int64_t n, double inv_count,
+                           hipStream_t s);
+hipError_t launch_pmr_finalize(const double* sum, const double* sum_im, const double* sumsq,
+                               double* var, int64_t n, double count, hipStream_t s);
+hipError_t launch_power_start(float2* p, int ny, int nx, hipStream_t s);
+
+}  // namespace pico

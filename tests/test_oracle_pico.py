@@ -146,3 +146,16 @@ def test_nrmse_and_certify():
     assert pico.nrmse_std(ref * 1.0201, ref) == pytest.approx(0.01, rel=1e-6)
     maps = {100: ref * 1.05, 200: ref * 1.04, 400: ref * 1.001, 800: ref * 1.0005}
     assert pico.certify(maps, ref) == 400
+
+
+def test_exact_columns_estimator_matches_converged_cg():
+    op = _op(16, 6, nc=3, R=2, acs=2)
+    cov = pico.Covariance(op, 0.0, cg_iters=80)
+    acc = pico.noise_map(cov, 5, 0, 3)
+    cols = [0, 3, 5]
+    ex = pico.noise_map_exact_columns(op, op.P[:, 0], 5, 0, 3, cols)
+    assert np.allclose(acc["sum"][:, cols], ex, rtol=1e-9, atol=1e-12)
+    cov_l = pico.Covariance(op, 0.2, cg_iters=80)
+    acc_l = pico.noise_map(cov_l, 5, 0, 3)
+    ex_l = pico.noise_map_exact_columns(op, op.P[:, 0], 5, 0, 3, cols, lam=cov_l.lam)
+    assert np.allclose(acc_l["sum"][:, cols], ex_l, rtol=1e-9, atol=1e-12)
