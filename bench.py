@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the PICO noise-map hot path on one MI355X.
+
+Workload: 2-D Cartesian SENSE, 320 x 320 complex64 image, 15 coils with
+synthetic Gaussian-profile sensitivities, random SPD channel covariance,
+R=2 uniform phase-encode undersampling plus 24 fully sampled centre lines,
+K=256 random-phase probes solved as one batched CG of 30 iterations with
+FP64 inner products and accumulators.
+
+One step = one pico_noise_map call over 256 probes: probe generation, the
+256 CG solves and the FP64 accumulation, with all inputs resident in HBM.
+Printed: one JSON line (throughput in probe-solves/s, time to a 1 % NRMSE
+standard-deviation map against the exact map, roofline of the dominant
+kernel measured with HIP events, the FP64 CPU oracle timed on a bounded
+sample).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1%-error noise map (s) + probe solves/s; p50/p99 request latency"
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("cart1d.hip", "fft.h", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2605_09590_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def normal_op_flops(ny, nx, nc):
+    """Algorithmic FLOPs of one application of M to one probe (separable path).
+
+    Per coil and image column: two length-ny FFTs at 5 n log2 n, the map
+    product (6 n), the mask weight (2 n) and the conjugate map product with
+    accumulation (8 n).
+    """
+    n = ny
+    per_line = 2 * 5 * n * math.log2(n) + 16 * n
+    return nc * nx * per_line
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-probes", type=int, default=4, help="oracle sample size (probes)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1%% leg")
+    ap.add_argument("--no-ref", action="store_true", help="skip the exact reference map (implies --no-ttt)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures a single GPU: the noise-map path shards by probe range "
+              "across GPUs, and only the one-GPU figure is produced here (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_09590_amd import pico as lib
+
+    lib.load()
+    dev = torch.device("cuda:0")
+    prob = workloads.config(2, seed=0)
+    ny, nx, nc = prob.ny, prob.nx, prob.nc
+    K = 256
+    n = ny * nx
+    maps = torch.from_numpy(prob.maps.astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    t0 = time.perf_counter()
+    h = lib.pico_init(ny, nx, maps, prob.psi, mask, cg_iters=prob.cg_iters, probe_tile=K)
+    init_s = time.perf_counter() - t0
+
+    # exact reference map (row-unit probing of the column-separable Sigma)
+    ref = torch.empty(n, dtype=torch.float64, device=dev)
+    ref_s = None
+    if not args.no_ref:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lib.pico_exact_diag(h, ref)
+        torch.cuda.synchronize()
+        ref_s = round(time.perf_counter() - t0, 4)
+
+    out = {}
+    # --- time to 1 % NRMSE (std map), probes in chunks of 32 with the monitor
+    if not (args.no_ttt or args.no_ref):
+        acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+        acc = lib.make_accum(acc_t[0], None, acc_t[1])
+        chunk = 32
+        curve = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_done, t_hit, n_hit = 0, None, None
+        while n_done < 4096:
+            lib.pico_noise_map(h, 7, n_done, chunk, 0, acc)
+            n_done += chunk
+            e = lib.pico_monitor_nrmse(h, acc, ref)
+            t = time.perf_counter() - t0
+            curve.append((n_done, round(t, 5), round(e, 5)))
+            if e <= 0.01:
+                t_hit, n_hit = t, n_done
+                break
+        out["time_to_1pct_s"] = t_hit
+        out["n_at_1pct"] = n_hit
+        out["nrmse_curve"] = curve[:12]
+
+    # --- steady-state throughput: K=256 probes per step
+    acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    acc = lib.make_accum(*acc_t)
+    first = 0
+    for _ in range(args.warmup):
+        lib.pico_noise_map(h, 11, first, K, 0, acc)
+        first += K
+    torch.cuda.synchronize()
+    lib.pico_profile_start(h)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        lib.pico_noise_map(h, 11, first, K, 0, acc)
+        first += K
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    prof = lib.pico_profile_stop(h)
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    value = K * args.steps / (gpu_ms / 1e3)
+    st = lib.pico_stats_t()
+    lib.pico_noise_map(h, 11, first, K, 0, acc, st)   # convergence check (outside timing)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+
+    # --- roofline of the dominant kernel (fused p-update + normal operator)
+    it_ms, it_n = prof["normal_iter"]
+    avg_s = it_ms / it_n / 1e3
+    flops = normal_op_flops(ny, nx, nc) * K
+    bytes_alg = K * 4 * 8 * n + nc * n * 8           # read r, p; write p, q; maps once
+    achieved_tf = flops / avg_s / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_normal_iter_cart1d_320x320x15_K256.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        if tj.get("kernel_src_sha") == kernel_source_digest():
+            traffic = tj.get("hbm_bytes_per_launch")
+    roofline = {
+        "bound": "alu", "achieved": round(achieved_tf, 2), "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+        "kernel": "k_cart1d<TwoStep<20,16>, C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
+        "flops_per_launch": flops, "alg_bytes_per_launch": bytes_alg,
+        "hbm_GBs_alg": round(bytes_alg / avg_s / 1e9, 1),
+    }
+
+    # --- CPU baseline: the FP64 oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import pico as opico
+        op = opico.cartesian(prob.maps, prob.psi, prob.mask)
+        cov = opico.Covariance(op, 0.0, prob.cg_iters)
+        t0 = time.perf_counter()
+        opico.noise_map(cov, 11, 0, args.cpu_probes)
+        cs = time.perf_counter() - t0
+        cpu = {"value": round(args.cpu_probes / cs, 4), "unit": "probe-solves/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{args.cpu_probes} probes of the same 320x320 15-coil workload, "
+                         f"CG 30, FP64 numpy, one process ({cs:.1f} s)"}
+
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "probe-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cart1d 320x320 complex64, 15 coils, R=2 + 24 ACS lines, "
+                               "K=256 random-phase probes per step, CG 30, FP64 dots/accumulators",
+                   "probes_per_step": K, "ny": ny, "nx": nx, "coils": nc, "cg_iters": prob.cg_iters},
+        **out,
+        "init_s": round(init_s, 4), "reference_s": ref_s,
+        "wall_s_timed": round(wall, 4),
+        "cg_max_relres": st.max_relres,
+        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "kernel_launches": {k: v[1] for k, v in prof.items()},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    if args.copy_calib:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_calib_bytes"] = a.numel() * 8
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,40 @@ pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* v
  * or 0 for lambda == 0.  Returns NAN for a NULL handle. */
 double pico_lambda_abs(pico_op_t op);
 
+/* Convergence monitor (Sec. 3.2.2 evaluation; Sec. 3.2.3 computes NRMSE on
+ * standard-deviation maps): *nrmse = ||s - s_ref|| / ||s_ref|| with
+ * s = sqrt(max(sum / count, 0)) from ``acc`` and s_ref = sqrt(max(ref_var, 0)),
+ * ref_var device float64 [ny*nx].  Waits for ``stream``.  Reuses the
+ * operator's scratch, so it must not overlap other calls on the same op.
+ * Errors: PICO_EINVAL (NULL arguments, count < 1). */
+pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const double* ref_var,
+                                 double* nrmse, void* stream);
+
+/* Exact variance map diag(Sigma) into var (device float64 [ny*nx]) for a
+ * phase-encode (PICO_CART_1D) operator: Sigma is block diagonal over image
+ * columns (the mask is constant along kx), so the probe equal to 1 on one
+ * image row of every column returns, on that row, the diagonal of every
+ * column block; ny such probes give the whole map, exact up to the CG
+ * tolerance (Sec. 2.1, Eqs. (8)-(10)).  Errors: PICO_EUNSUPPORTED for other
+ * samplings, PICO_EINVAL, PICO_EDEVICE. */
+pico_status_t pico_exact_diag(pico_op_t op, double* var, void* stream);
+
+/* Kernel-class timing with HIP events recorded on the caller's stream.
+ * pico_profile_start clears and enables recording; pico_profile_stop waits
+ * for the recorded events and writes, per class k < PICO_PROF_KINDS, the
+ * summed duration in ms and the launch count (either pointer may be NULL). */
+enum {
+  PICO_PROF_NORMAL_FIRST = 0,  /* first normal-operator application of a solve */
+  PICO_PROF_NORMAL_ITER = 1,   /* p = r + beta p fused with q = (M + lam) p     */
+  PICO_PROF_CG_UPDATE = 2,     /* x += alpha p, r -= alpha q, |r|^2 partials     */
+  PICO_PROF_CG_SCALARS = 3,    /* per-probe alpha / beta reductions             */
+  PICO_PROF_ACCUM = 4,         /* FP64 accumulation of conj(v) u                */
+  PICO_PROF_OTHER = 5,         /* Tikhonov middle product, PMR right-hand side  */
+  PICO_PROF_KINDS = 8
+};
+pico_status_t pico_profile_start(pico_op_t op);
+pico_status_t pico_profile_stop(pico_op_t op, double* ms, int64_t* launches);
+
 /* Release the operator and its device memory (waits for its last stream). */
 void pico_destroy(pico_op_t op);
 

@@ -12,59 +12,85 @@
 //
 // Layout: every per-probe field is stored column-major, [K][nx][ny], so a
 // column is one contiguous line; maps are [nx][nc][ny].  One workgroup is one
-// wavefront holding G = 64/T probe columns of the same image column; each
-// column FFT lives in the registers of T lanes and exchanges through LDS.
+// wavefront holding G = 64/L probe columns of the same image column; each
+// column FFT lives in the registers of a group of L lanes and exchanges
+// through LDS.
 #include "fft.h"
 #include "runtime.h"
 
 namespace pico {
 
-template <class PL>
-__device__ __forceinline__ void normal_col(const float2 (&pv)[PL::P], float2 (&qa)[PL::P], float lam,
-                                           const float2* __restrict__ mcol, int nc,
-                                           uint32_t mbits, float2* lds, int t,
-                                           const float2 (&tw)[PL::NTW]) {
-  constexpr int P = PL::P, T = PL::T, N = PL::N;
+// q = (M + lam) p for one probe column held in layout A by the lanes of one
+// group: per coil, S' p -> FFT (layout A -> B) -> weight mask[k]/ny -> inverse
+// FFT (B -> A) -> accumulate conj(S') times the result.
+template <class CF>
+__device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 (&qa)[CF::VMAX],
+                                           float lam, const float2* __restrict__ mcol, int nc,
+                                           uint32_t mbits, float2* lds, int lane,
+                                           const typename CF::Tw& tw) {
+  constexpr int N = CF::N;
   constexpr float minv = 1.0f / N;
+  const bool inA = CF::inA(lane);
 #pragma unroll
-  for (int m = 0; m < P; ++m) qa[m] = cscale(pv[m], lam);
+  for (int m = 0; m < CF::VA; ++m) qa[m] = cscale(pv[m], lam);
   for (int c = 0; c < nc; ++c) {
     const float2* __restrict__ s = mcol + (size_t)c * N;
-    float2 v[P];
+    float2 v[CF::VMAX];
 #pragma unroll
-    for (int m = 0; m < P; ++m) v[m] = cmul(s[t + T * m], pv[m]);
-    fft<PL, false>(v, lds, t, tw);
+    for (int m = 0; m < CF::VA; ++m) v[m] = inA ? cmul(s[CF::posA(lane, m)], pv[m]) : make_float2(0.f, 0.f);
+    CF::template forward<false>(v, lds, lane, tw);
 #pragma unroll
-    for (int m = 0; m < P; ++m)
-      v[m] = ((mbits >> m) & 1u) ? cscale(v[m], minv) : make_float2(0.f, 0.f);
-    fft<PL, true>(v, lds, t, tw);
+    for (int r = 0; r < CF::VB; ++r)
+      v[r] = ((mbits >> r) & 1u) ? cscale(v[r], minv) : make_float2(0.f, 0.f);
+    CF::template inverse<true>(v, lds, lane, tw);
+    if (inA) {
 #pragma unroll
-    for (int m = 0; m < P; ++m) qa[m] = cadd(qa[m], cmulc(s[t + T * m], v[m]));
+      for (int m = 0; m < CF::VA; ++m) qa[m] = cadd(qa[m], cmulc(s[CF::posA(lane, m)], v[m]));
+    }
   }
 }
 
-template <class PL, int MODE>
+// Sum of one double per lane over each lane group of L lanes, in lane order
+// (bitwise reproducible); the result is valid in the group's first lane.
+template <int L>
+__device__ __forceinline__ double group_reduce(double v, double* red, int lane) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (lane == 0) {
+    const int base = threadIdx.x;
+    for (int i = 0; i < L; ++i) s += red[base + i];
+  }
+  __syncthreads();
+  return s;
+}
+
+template <class CF, int MODE>
 __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
-  constexpr int P = PL::P, T = PL::T, N = PL::N, G = 64 / T;
-  constexpr int SPAN = lds_span<N>();
-  __shared__ float2 lds_all[G * SPAN];
-  const int g = threadIdx.x / T;
-  const int t = threadIdx.x % T;
+  constexpr int N = CF::N, L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
+  constexpr int VA = CF::VA, VB = CF::VB;
+  __shared__ float2 lds_all[NG * CF::SPAN];
+  __shared__ double red[64];
+  const int g = threadIdx.x / L;
+  const int lane = threadIdx.x % L;
   const int col = blockIdx.y;
   const int k = blockIdx.x * G + g;
-  const bool active = k < a.K;
-  const int kk = active ? k : 0;  // idle groups work on probe 0 but never store
-  float2* lds = lds_all + g * SPAN;
+  const bool active = g < G && k < a.K;
+  const int kk = active ? k : 0;  // idle lanes work on probe 0 but never store
+  const bool inA = CF::inA(lane), inB = CF::inB(lane);
+  float2* lds = lds_all + g * CF::SPAN;
 
-  float2 tw[PL::NTW];
-  load_twiddles<PL>(tw, a.twt, t);
+  typename CF::Tw tw;
+  CF::load_tw(tw, a.twt, lane);
   uint32_t mbits = 0;
+  if (inB) {
 #pragma unroll
-  for (int m = 0; m < P; ++m) mbits |= (a.maskw[t + T * m] != 0.f ? 1u : 0u) << m;
+    for (int r = 0; r < VB; ++r) mbits |= (a.maskw[CF::posB(lane, r)] != 0.f ? 1u : 0u) << r;
+  }
 
   const size_t base = ((size_t)kk * a.nx + col) * N;
   const float2* __restrict__ mcol = a.maps + (size_t)col * a.nc * N;
-  float2 pv[P];
+  float2 pv[CF::VMAX];
   double d0 = 0.0;
 
   if constexpr (MODE == C1_PMR_RHS) {
@@ -73,78 +99,88 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
     // unnormalised inverse FFT, times conj(S') (D already folded into S').
     const float rs = rsqrtf((float)N);
 #pragma unroll
-    for (int m = 0; m < P; ++m) pv[m] = make_float2(0.f, 0.f);
+    for (int m = 0; m < VA; ++m) pv[m] = make_float2(0.f, 0.f);
     for (int c = 0; c < a.nc; ++c) {
-      float2 v[P];
+      float2 v[CF::VMAX];
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const int kc = t + T * m;
-        if ((mbits >> m) & 1u) {
+      for (int r = 0; r < VB; ++r) {
+        const int kc = CF::posB(lane, r);
+        if ((mbits >> r) & 1u) {
           const uint32_t elem = (uint32_t)(((size_t)c * N + kc) * a.nx + col);
           const float2 n = draw_probe(a.seed, a.first + kk, elem, 1u, 3);
-          const float sg = ((kc + N / 2) & 1) ? -rs : rs;
-          v[m] = cscale(n, sg);
+          v[r] = cscale(n, ((kc + N / 2) & 1) ? -rs : rs);
         } else {
-          v[m] = make_float2(0.f, 0.f);
+          v[r] = make_float2(0.f, 0.f);
         }
       }
-      fft<PL, true>(v, lds, t, tw);
+      CF::template inverse<true>(v, lds, lane, tw);
       const float2* __restrict__ s = mcol + (size_t)c * N;
+      if (inA) {
 #pragma unroll
-      for (int m = 0; m < P; ++m) pv[m] = cadd(pv[m], cmulc(s[t + T * m], v[m]));
+        for (int m = 0; m < VA; ++m) pv[m] = cadd(pv[m], cmulc(s[CF::posA(lane, m)], v[m]));
+      }
     }
+    if (inA) {
 #pragma unroll
-    for (int m = 0; m < P; ++m) {
-      if (active) a.r[base + t + T * m] = pv[m];
-      d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+      for (int m = 0; m < VA; ++m) {
+        if (active) a.r[base + CF::posA(lane, m)] = pv[m];
+        d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+      }
     }
-    d0 = group_sum<T>(d0);
-    if (active && t == 0) a.part[((size_t)k * a.nx + col) * 2 + 1] = d0;
+    d0 = group_reduce<L>(d0, red, lane);
+    if (active && lane == 0) a.part[((size_t)k * a.nx + col) * 2 + 1] = d0;
     return;
   } else {
-    if constexpr (MODE == C1_FIRST_PROBE) {
+    if (inA) {
+      if constexpr (MODE == C1_FIRST_PROBE) {
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const int y = t + T * m;
-        pv[m] = draw_probe(a.seed, a.first + kk, (uint32_t)(y * a.nx + col), 0u, a.dist);
-        if (active) { a.r[base + y] = pv[m]; a.p[base + y] = pv[m]; }
-        d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+        for (int m = 0; m < VA; ++m) {
+          const int y = CF::posA(lane, m);
+          pv[m] = draw_probe(a.seed, a.first + kk, (uint32_t)(y * a.nx + col), 0u, a.dist);
+          if (active) { a.r[base + y] = pv[m]; a.p[base + y] = pv[m]; }
+          d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+        }
+      } else if constexpr (MODE == C1_FIRST_BUF) {
+#pragma unroll
+        for (int m = 0; m < VA; ++m) {
+          const int y = CF::posA(lane, m);
+          pv[m] = a.r[base + y];
+          if (active) a.p[base + y] = pv[m];
+          d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
+        }
+      } else if constexpr (MODE == C1_ITER) {
+        const float beta = (float)a.beta[kk];
+#pragma unroll
+        for (int m = 0; m < VA; ++m) {
+          const int y = CF::posA(lane, m);
+          pv[m] = cfma(a.r[base + y], beta, a.p[base + y]);
+          if (active) a.p[base + y] = pv[m];
+        }
+      } else {  // C1_APPLY
+#pragma unroll
+        for (int m = 0; m < VA; ++m) pv[m] = cscale(a.src[base + CF::posA(lane, m)], a.scale);
       }
-    } else if constexpr (MODE == C1_FIRST_BUF) {
+    } else {
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        pv[m] = a.r[base + t + T * m];
-        if (active) a.p[base + t + T * m] = pv[m];
-        d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
-      }
-    } else if constexpr (MODE == C1_ITER) {
-      const float beta = (float)a.beta[kk];
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const float2 rv = a.r[base + t + T * m];
-        const float2 po = a.p[base + t + T * m];
-        pv[m] = cfma(rv, beta, po);
-        if (active) a.p[base + t + T * m] = pv[m];
-      }
-    } else {  // C1_APPLY
-#pragma unroll
-      for (int m = 0; m < P; ++m) pv[m] = cscale(a.src[base + t + T * m], a.scale);
+      for (int m = 0; m < VA; ++m) pv[m] = make_float2(0.f, 0.f);
     }
 
-    float2 qa[P];
-    normal_col<PL>(pv, qa, a.lam, mcol, a.nc, mbits, lds, t, tw);
+    float2 qa[CF::VMAX];
+    normal_col<CF>(pv, qa, a.lam, mcol, a.nc, mbits, lds, lane, tw);
 
     double d1 = 0.0, d2 = 0.0;
+    if (inA) {
 #pragma unroll
-    for (int m = 0; m < P; ++m) {
-      if (active) a.q[base + t + T * m] = qa[m];
-      d1 += (double)pv[m].x * qa[m].x + (double)pv[m].y * qa[m].y;
-      d2 += (double)qa[m].x * qa[m].x + (double)qa[m].y * qa[m].y;
+      for (int m = 0; m < VA; ++m) {
+        if (active) a.q[base + CF::posA(lane, m)] = qa[m];
+        d1 += (double)pv[m].x * qa[m].x + (double)pv[m].y * qa[m].y;
+        d2 += (double)qa[m].x * qa[m].x + (double)qa[m].y * qa[m].y;
+      }
     }
-    d1 = group_sum<T>(d1);
-    if constexpr (MODE == C1_APPLY) d0 = group_sum<T>(d2);
-    else d0 = group_sum<T>(d0);
-    if (active && t == 0) {
+    d1 = group_reduce<L>(d1, red, lane);
+    if constexpr (MODE == C1_APPLY) d0 = group_reduce<L>(d2, red, lane);
+    else if constexpr (MODE != C1_ITER) d0 = group_reduce<L>(d0, red, lane);
+    if (active && lane == 0) {
       double* pp = a.part + ((size_t)k * a.nx + col) * 2;
       pp[0] = d1;
       if constexpr (MODE != C1_ITER) pp[1] = d0;
@@ -153,32 +189,34 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
 }
 
 // ------------------------------------------------------------ dispatch
-template <class PL>
+template <class CF>
 static hipError_t launch_plan(int mode, const Cart1dArgs& a, hipStream_t s) {
-  constexpr int G = 64 / PL::T;
+  constexpr int G = 64 / CF::L;
   dim3 grid((a.K + G - 1) / G, a.nx), block(64);
   switch (mode) {
-    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_cart1d<PL, C1_FIRST_PROBE>), grid, block, 0, s, a); break;
-    case C1_FIRST_BUF: hipLaunchKernelGGL((k_cart1d<PL, C1_FIRST_BUF>), grid, block, 0, s, a); break;
-    case C1_ITER: hipLaunchKernelGGL((k_cart1d<PL, C1_ITER>), grid, block, 0, s, a); break;
-    case C1_APPLY: hipLaunchKernelGGL((k_cart1d<PL, C1_APPLY>), grid, block, 0, s, a); break;
-    case C1_PMR_RHS: hipLaunchKernelGGL((k_cart1d<PL, C1_PMR_RHS>), grid, block, 0, s, a); break;
+    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_cart1d<CF, C1_FIRST_PROBE>), grid, block, 0, s, a); break;
+    case C1_FIRST_BUF: hipLaunchKernelGGL((k_cart1d<CF, C1_FIRST_BUF>), grid, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL((k_cart1d<CF, C1_ITER>), grid, block, 0, s, a); break;
+    case C1_APPLY: hipLaunchKernelGGL((k_cart1d<CF, C1_APPLY>), grid, block, 0, s, a); break;
+    case C1_PMR_RHS: hipLaunchKernelGGL((k_cart1d<CF, C1_PMR_RHS>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// Radix plans per line length (T lanes per line, radices dividing N/T)
-using Plan64 = FFTPlan<64, 8, 8, 8>;
-using Plan96 = FFTPlan<96, 8, 12, 4, 2>;
-using Plan128 = FFTPlan<128, 16, 8, 4, 4>;
-using Plan160 = FFTPlan<160, 8, 20, 4, 2>;
-using Plan192 = FFTPlan<192, 16, 12, 4, 4>;
-using Plan256 = FFTPlan<256, 16, 16, 16>;
-using Plan288 = FFTPlan<288, 16, 18, 2, 2, 2, 2>;
-using Plan320 = FFTPlan<320, 16, 20, 4, 4>;
-using Plan384 = FFTPlan<384, 16, 24, 4, 4>;
-using Plan512 = FFTPlan<512, 32, 16, 16, 2>;
+// Column-FFT layouts per line length.  Stockham plans keep N/T values on T
+// lanes through every pass; two-step plans split N = LA * VA over LA lanes
+// with a single LDS transpose per transform.
+using Col64 = TwoStep<8, 8>;
+using Col96 = StockhamCol<FFTPlan<96, 8, 12, 4, 2>>;
+using Col128 = StockhamCol<FFTPlan<128, 16, 8, 4, 4>>;
+using Col160 = StockhamCol<FFTPlan<160, 8, 20, 4, 2>>;
+using Col192 = StockhamCol<FFTPlan<192, 16, 12, 4, 4>>;
+using Col256 = TwoStep<16, 16>;
+using Col288 = StockhamCol<FFTPlan<288, 16, 18, 2, 2, 2, 2>>;
+using Col320 = TwoStep<20, 16>;
+using Col384 = StockhamCol<FFTPlan<384, 16, 24, 4, 4>>;
+using Col512 = StockhamCol<FFTPlan<512, 32, 16, 16, 2>>;
 
 bool cart1d_supported(int ny) {
   switch (ny) {
@@ -191,16 +229,16 @@ bool cart1d_supported(int ny) {
 
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s) {
   switch (a.ny) {
-    case 64: return launch_plan<Plan64>(mode, a, s);
-    case 96: return launch_plan<Plan96>(mode, a, s);
-    case 128: return launch_plan<Plan128>(mode, a, s);
-    case 160: return launch_plan<Plan160>(mode, a, s);
-    case 192: return launch_plan<Plan192>(mode, a, s);
-    case 256: return launch_plan<Plan256>(mode, a, s);
-    case 288: return launch_plan<Plan288>(mode, a, s);
-    case 320: return launch_plan<Plan320>(mode, a, s);
-    case 384: return launch_plan<Plan384>(mode, a, s);
-    case 512: return launch_plan<Plan512>(mode, a, s);
+    case 64: return launch_plan<Col64>(mode, a, s);
+    case 96: return launch_plan<Col96>(mode, a, s);
+    case 128: return launch_plan<Col128>(mode, a, s);
+    case 160: return launch_plan<Col160>(mode, a, s);
+    case 192: return launch_plan<Col192>(mode, a, s);
+    case 256: return launch_plan<Col256>(mode, a, s);
+    case 288: return launch_plan<Col288>(mode, a, s);
+    case 320: return launch_plan<Col320>(mode, a, s);
+    case 384: return launch_plan<Col384>(mode, a, s);
+    case 512: return launch_plan<Col512>(mode, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -245,6 +283,39 @@ __global__ void k_power_start(float2* __restrict__ p, int ny, int nx) {
 hipError_t launch_power_start(float2* p, int ny, int nx, hipStream_t s) {
   dim3 grid((ny + 63) / 64, nx), block(64);
   hipLaunchKernelGGL(k_power_start, grid, block, 0, s, p, ny, nx);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ exact diagonal by row probing
+// For a phase-encode mask Sigma is block diagonal over image columns, so the
+// probe that is 1 on image row y0 + k of every column returns column x's
+// Sigma_x e_(y0+k): its entry on that row is diag(Sigma) there.
+__global__ void k_unit_rows(float2* __restrict__ r, int y0, int ny, int nx) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y, k = blockIdx.z;
+  if (y >= ny) return;
+  r[((size_t)k * nx + col) * ny + y] = make_float2(y == y0 + k ? 1.f : 0.f, 0.f);
+}
+
+__global__ void k_extract_rows(const float2* __restrict__ x, double* __restrict__ var, int K, int y0,
+                               int ny, int nx) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (col >= nx || k >= K) return;
+  const int y = y0 + k;
+  var[(size_t)y * nx + col] = (double)x[((size_t)k * nx + col) * ny + y].x;
+}
+
+hipError_t launch_unit_rows(float2* r, int K, int y0, int ny, int nx, hipStream_t s) {
+  dim3 grid((ny + 63) / 64, nx, K), block(64);
+  hipLaunchKernelGGL(k_unit_rows, grid, block, 0, s, r, y0, ny, nx);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_rows(const float2* x, double* var, int K, int y0, int ny, int nx,
+                               hipStream_t s) {
+  dim3 grid((nx + 63) / 64, K), block(64);
+  hipLaunchKernelGGL(k_extract_rows, grid, block, 0, s, x, var, K, y0, ny, nx);
   return hipGetLastError();
 }
 

@@ -115,6 +115,40 @@ hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Convergence monitor: partial sums of (s - s_ref)^2 and s_ref^2 over
+// standard-deviation maps s = sqrt(max(sum / N, 0)), s_ref = sqrt(max(ref, 0));
+// NRMSE = sqrt(sum / sum) is finished on the host in block order.
+__global__ __launch_bounds__(256) void k_nrmse_partials(const double* __restrict__ sum, double inv,
+                                                        const double* __restrict__ ref, int64_t n,
+                                                        double* __restrict__ part) {
+  double num = 0.0, den = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double s = sqrt(fmax(sum[i] * inv, 0.0));
+    const double s0 = sqrt(fmax(ref[i], 0.0));
+    num += (s - s0) * (s - s0);
+    den += s0 * s0;
+  }
+  num = group_sum<64>(num);
+  den = group_sum<64>(den);
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = num;
+    red[1][w] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    part[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+hipError_t launch_nrmse_partials(const double* sum, double inv_count, const double* ref, int64_t n,
+                                 double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_nrmse_partials, dim3(nblk), dim3(256), 0, s, sum, inv_count, ref, n, part);
+  return hipGetLastError();
+}
+
 // var = sum / N  (App. A, Algorithm 1, last step)
 __global__ void k_finalize(const double* __restrict__ sum, double* __restrict__ var, int64_t n, double inv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

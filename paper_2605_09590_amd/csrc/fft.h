@@ -224,3 +224,119 @@ __device__ __forceinline__ void fft(float2 (&v)[PL::P], float2* lds, int t,
 }
 
 }  // namespace pico
+
+namespace pico {
+
+// --------------------------------------------------------------------------
+// Two-step (four-step) FFT of length N = LA * VA over a group of LA lanes.
+//
+// Layout A: lane a < LA holds x[a + LA*m], m < VA.
+// Layout B: lane b < VA holds X[b + VA*r], r < LA.
+// Forward A -> B:  Y[a][k] = DFT_VA over m of x[a + LA m]   (lane a, registers)
+//                  Y[a][k] *= W_N^{a k}                      (lane a)
+//                  transpose through LDS                     (one exchange)
+//                  X[k + VA r] = DFT_LA over a of Y[a][k]    (lane k, registers)
+// Inverse B -> A is the same chain reversed with conjugate twiddles, so one
+// LDS exchange per transform and both twiddle stages use lane a's own set
+// {W_N^{a k} : 0 < k < VA}.  Lanes that are idle in a step still reach every
+// barrier.
+template <int LA_, int VA_>
+struct TwoStep {
+  static constexpr int LA = LA_, VA = VA_, N = LA * VA;
+  static constexpr int L = (LA > VA ? LA : VA);   // lanes per group
+  static constexpr int VB = LA;                    // values per lane in layout B
+  static constexpr int VMAX = (VA > LA ? VA : LA);
+  static constexpr int STRIDE = LA + 1;            // padded LDS row
+  static constexpr int SPAN = VA * STRIDE;
+  static_assert(64 % L == 0 || L <= 64, "group must fit a wavefront");
+  struct Tw { float2 w[VA]; };
+
+  __device__ static __forceinline__ int posA(int lane, int m) { return lane + LA * m; }
+  __device__ static __forceinline__ int posB(int lane, int r) { return lane + VA * r; }
+  __device__ static __forceinline__ bool inA(int lane) { return lane < LA; }
+  __device__ static __forceinline__ bool inB(int lane) { return lane < VA; }
+
+  __device__ static __forceinline__ void load_tw(Tw& tw, const float2* __restrict__ table, int lane) {
+    const int a = lane < LA ? lane : 0;
+#pragma unroll
+    for (int k = 0; k < VA; ++k) tw.w[k] = table[(a * k) % N];
+  }
+
+  // v[0..VA) in layout A  ->  v[0..LA) in layout B
+  template <bool INV>
+  __device__ static __forceinline__ void forward(float2 (&v)[VMAX], float2* lds, int lane, const Tw& tw) {
+    if (inA(lane)) {
+      float2 a[VA];
+#pragma unroll
+      for (int m = 0; m < VA; ++m) a[m] = v[m];
+      dft<VA, INV>(a);
+#pragma unroll
+      for (int k = 0; k < VA; ++k) {
+        const float2 w = INV ? make_float2(tw.w[k].x, -tw.w[k].y) : tw.w[k];
+        lds[k * STRIDE + lane] = k ? cmul(a[k], w) : a[k];
+      }
+    }
+    __syncthreads();
+    if (inB(lane)) {
+      float2 b[LA];
+#pragma unroll
+      for (int a = 0; a < LA; ++a) b[a] = lds[lane * STRIDE + a];
+      dft<LA, INV>(b);
+#pragma unroll
+      for (int r = 0; r < LA; ++r) v[r] = b[r];
+    }
+    __syncthreads();
+  }
+
+  // v[0..LA) in layout B  ->  v[0..VA) in layout A
+  template <bool INV>
+  __device__ static __forceinline__ void inverse(float2 (&v)[VMAX], float2* lds, int lane, const Tw& tw) {
+    if (inB(lane)) {
+      float2 b[LA];
+#pragma unroll
+      for (int r = 0; r < LA; ++r) b[r] = v[r];
+      dft<LA, INV>(b);
+#pragma unroll
+      for (int a = 0; a < LA; ++a) lds[lane * STRIDE + a] = b[a];
+    }
+    __syncthreads();
+    if (inA(lane)) {
+      float2 a[VA];
+#pragma unroll
+      for (int k = 0; k < VA; ++k) {
+        const float2 z = lds[k * STRIDE + lane];
+        const float2 w = INV ? make_float2(tw.w[k].x, -tw.w[k].y) : tw.w[k];
+        a[k] = k ? cmul(z, w) : z;
+      }
+      dft<VA, INV>(a);
+#pragma unroll
+      for (int m = 0; m < VA; ++m) v[m] = a[m];
+    }
+    __syncthreads();
+  }
+};
+
+// Stockham plan wrapped in the same interface (layouts A and B coincide).
+template <class PL>
+struct StockhamCol {
+  static constexpr int N = PL::N, L = PL::T, VA = PL::P, VB = PL::P, VMAX = PL::P;
+  static constexpr int SPAN = lds_span<PL::N>();
+  struct Tw { float2 w[PL::NTW]; };
+  __device__ static __forceinline__ int posA(int lane, int m) { return lane + L * m; }
+  __device__ static __forceinline__ int posB(int lane, int r) { return lane + L * r; }
+  __device__ static __forceinline__ bool inA(int) { return true; }
+  __device__ static __forceinline__ bool inB(int) { return true; }
+  __device__ static __forceinline__ void load_tw(Tw& tw, const float2* __restrict__ table, int lane) {
+    load_twiddles<PL>(tw.w, table, lane);
+  }
+  template <bool INV>
+  __device__ static __forceinline__ void forward(float2 (&v)[VMAX], float2* lds, int lane, const Tw& tw) {
+    fft<PL, INV>(v, lds, lane, tw.w);
+  }
+  template <bool INV>
+  __device__ static __forceinline__ void inverse(float2 (&v)[VMAX], float2* lds, int lane, const Tw& tw) {
+    fft<PL, INV>(v, lds, lane, tw.w);
+  }
+};
+
+}  // namespace pico

@@ -51,12 +51,27 @@ struct pico_op_s {
   float2 *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
   double* partA = nullptr;  // [K][nx][2]
   double* partB = nullptr;  // [K][nblkB]
+  double* mon = nullptr;    // [512] convergence-monitor partials
   double *alpha = nullptr, *beta = nullptr, *rr = nullptr, *rr0 = nullptr;
   int* state = nullptr;
   std::vector<void*> allocs;
+  // optional per-kernel-class timing with HIP events on the caller's stream
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_recs;
 
   ~pico_op_s() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* ptr : allocs) (void)hipFree(ptr);
+  }
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
   }
   template <class T>
   hipError_t alloc(T** ptr, size_t count) {
@@ -120,6 +135,20 @@ pico_status_t check_op(pico_op_t op) {
   return PICO_OK;
 }
 
+// Run one launch, bracketed by HIP events when profiling is on.
+template <class F>
+hipError_t timed(pico_op_t op, int kind, hipStream_t s, F&& launch) {
+  if (!op->prof_on) return launch();
+  hipEvent_t a = op->next_event(), b = op->next_event();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
+  if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+  op->prof_recs.push_back({kind, {a, b}});
+  return hipSuccess;
+}
+
 pico::Cart1dArgs base_args(pico_op_t op, int K) {
   pico::Cart1dArgs a{};
   a.ny = op->ny;
@@ -151,7 +180,7 @@ hipError_t scalars(pico_op_t op, int K, int stage, hipStream_t s) {
   sa.state = op->state;
   sa.tol = op->cg_tol;
   sa.stage = stage;
-  return pico::launch_scalars(sa, s);
+  return timed(op, PICO_PROF_CG_SCALARS, s, [&] { return pico::launch_scalars(sa, s); });
 }
 
 // One batched CG solve of (M + lam) x = b for K right-hand sides.  The
@@ -163,7 +192,7 @@ hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t
   a.seed = seed;
   a.first = first;
   a.dist = dist;
-  hipError_t e = pico::launch_cart1d(first_mode, a, s);
+  hipError_t e = timed(op, PICO_PROF_NORMAL_FIRST, s, [&] { return pico::launch_cart1d(first_mode, a, s); });
   if (e != hipSuccess) return e;
   if ((e = scalars(op, K, 0, s)) != hipSuccess) return e;
   pico::UpdateArgs u{};
@@ -178,11 +207,11 @@ hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t
   u.nblk = op->nblkB;
   for (int it = 0; it < op->cg_iters; ++it) {
     if (it > 0) {
-      if ((e = pico::launch_cart1d(pico::C1_ITER, a, s)) != hipSuccess) return e;
+      if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return pico::launch_cart1d(pico::C1_ITER, a, s); })) != hipSuccess) return e;
       if ((e = scalars(op, K, 1, s)) != hipSuccess) return e;
     }
     u.first_iter = (it == 0);
-    if ((e = pico::launch_update(u, s)) != hipSuccess) return e;
+    if ((e = timed(op, PICO_PROF_CG_UPDATE, s, [&] { return pico::launch_update(u, s); })) != hipSuccess) return e;
     if ((e = scalars(op, K, 2, s)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -198,7 +227,7 @@ hipError_t apply_sigma(pico_op_t op, int K, int first_mode, uint64_t seed, uint6
   a.src = op->x;
   a.q = op->r;     // t = M w lands in r, the next right-hand side
   a.lam = 0.0f;
-  if ((e = pico::launch_cart1d(pico::C1_APPLY, a, s)) != hipSuccess) return e;
+  if ((e = timed(op, PICO_PROF_OTHER, s, [&] { return pico::launch_cart1d(pico::C1_APPLY, a, s); })) != hipSuccess) return e;
   return cg_solve(op, K, pico::C1_FIRST_BUF, 0, 0, 0, s);
 }
 
@@ -305,6 +334,7 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   if ((e = op->alloc(&op->q, n * K)) != hipSuccess) return bad(e, "workspace q");
   if ((e = op->alloc(&op->partA, (size_t)K * nx * 2)) != hipSuccess) return bad(e, "partials");
   if ((e = op->alloc(&op->partB, (size_t)K * op->nblkB)) != hipSuccess) return bad(e, "partials");
+  if ((e = op->alloc(&op->mon, 512)) != hipSuccess) return bad(e, "monitor");
   if ((e = op->alloc(&op->alpha, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&op->beta, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&op->rr, K)) != hipSuccess) return bad(e, "scalars");
@@ -405,7 +435,7 @@ pico_status_t pico_noise_map(pico_op_t op, uint64_t seed, int64_t first_probe, i
     aa.first = first;
     aa.dist = dist;
     aa.pmr = 0;
-    HIP_OR_RETURN(pico::launch_accum_colmajor(aa, s));
+    HIP_OR_RETURN(timed(op, PICO_PROF_ACCUM, s, [&] { return pico::launch_accum_colmajor(aa, s); }));
     if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));
     done += K;
   }
@@ -438,7 +468,7 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
     pico::Cart1dArgs a = base_args(op, K);
     a.seed = seed;
     a.first = f;
-    HIP_OR_RETURN(pico::launch_cart1d(pico::C1_PMR_RHS, a, s));
+    HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] { return pico::launch_cart1d(pico::C1_PMR_RHS, a, s); }));
     HIP_OR_RETURN(cg_solve(op, K, pico::C1_FIRST_BUF, 0, 0, 0, s));
     pico::AccumArgs aa{};
     aa.ny = op->ny;
@@ -449,7 +479,7 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
     aa.sum_im = acc->sum_im;
     aa.sumsq = acc->sumsq;
     aa.pmr = 1;
-    HIP_OR_RETURN(pico::launch_accum_colmajor(aa, s));
+    HIP_OR_RETURN(timed(op, PICO_PROF_ACCUM, s, [&] { return pico::launch_accum_colmajor(aa, s); }));
     if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));
     done += K;
   }
@@ -466,6 +496,69 @@ pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* v
   HIP_OR_RETURN(pico::launch_pmr_finalize(acc->sum, acc->sum_im, acc->sumsq, var,
                                           (int64_t)op->ny * op->nx, (double)acc->count,
                                           (hipStream_t)stream));
+  return PICO_OK;
+}
+
+pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const double* ref_var,
+                                double* nrmse, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!acc || !acc->sum || !ref_var || !nrmse) return fail(PICO_EINVAL, "NULL accumulator, reference or output");
+  if (acc->count < 1) return fail(PICO_EINVAL, "no probes accumulated");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = (int64_t)op->ny * op->nx;
+  const int nblk = (int)std::min<int64_t>(256, (n + 255) / 256);
+  std::vector<double> part(2 * nblk);
+  HIP_OR_RETURN(pico::launch_nrmse_partials(acc->sum, 1.0 / (double)acc->count, ref_var, n,
+                                            op->mon, nblk, s));
+  HIP_OR_RETURN(hipMemcpyAsync(part.data(), op->mon, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OR_RETURN(hipStreamSynchronize(s));
+  double num = 0.0, den = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    num += part[2 * b];
+    den += part[2 * b + 1];
+  }
+  *nrmse = den > 0.0 ? std::sqrt(num / den) : NAN;
+  return PICO_OK;
+}
+
+pico_status_t pico_exact_diag(pico_op_t op, double* var, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!var) return fail(PICO_EINVAL, "NULL output");
+  if (op->sampling != PICO_CART_1D) return fail(PICO_EUNSUPPORTED, "exact diagonal needs a phase-encode mask");
+  hipStream_t s = (hipStream_t)stream;
+  for (int y0 = 0; y0 < op->ny; y0 += op->K) {
+    const int k = std::min(op->K, op->ny - y0);
+    HIP_OR_RETURN(pico::launch_unit_rows(op->r, k, y0, op->ny, op->nx, s));
+    HIP_OR_RETURN(apply_sigma(op, k, pico::C1_FIRST_BUF, 0, 0, 0, s));
+    HIP_OR_RETURN(pico::launch_extract_rows(op->x, var, k, y0, op->ny, op->nx, s));
+  }
+  return PICO_OK;
+}
+
+pico_status_t pico_profile_start(pico_op_t op) {
+  if (pico_status_t st = check_op(op)) return st;
+  op->prof_recs.clear();
+  op->ev_used = 0;
+  op->prof_on = true;
+  return PICO_OK;
+}
+
+pico_status_t pico_profile_stop(pico_op_t op, double* ms, int64_t* launches) {
+  if (pico_status_t st = check_op(op)) return st;
+  op->prof_on = false;
+  for (int k = 0; k < PICO_PROF_KINDS; ++k) {
+    if (ms) ms[k] = 0.0;
+    if (launches) launches[k] = 0;
+  }
+  for (auto& rec : op->prof_recs) {
+    HIP_OR_RETURN(hipEventSynchronize(rec.second.second));
+    float t = 0.0f;
+    HIP_OR_RETURN(hipEventElapsedTime(&t, rec.second.first, rec.second.second));
+    if (ms) ms[rec.first] += t;
+    if (launches) launches[rec.first] += 1;
+  }
+  op->prof_recs.clear();
+  op->ev_used = 0;
   return PICO_OK;
 }
 

@@ -60,8 +60,11 @@ class PicoError(RuntimeError):
 _lib = None
 
 EXPORTS = ["pico_init", "pico_apply_cov", "pico_noise_map", "pico_finalize",
-           "pico_pmr_baseline", "pico_pmr_finalize", "pico_lambda_abs", "pico_destroy",
+           "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse", "pico_exact_diag",
+           "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error"]
+PROF_KINDS = 8
+PROF_NAMES = ["normal_first", "normal_iter", "cg_update", "cg_scalars", "accumulate", "other"]
 
 
 def load(path: str = LIB_PATH):
@@ -82,6 +85,12 @@ def load(path: str = LIB_PATH):
     lib.pico_pmr_baseline.argtypes = [vp, u64, i64, i64, ctypes.POINTER(pico_accum_t),
                                       ctypes.POINTER(pico_stats_t), vp]
     lib.pico_pmr_finalize.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp, vp]
+    lib.pico_monitor_nrmse.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp,
+                                       ctypes.POINTER(ctypes.c_double), vp]
+    lib.pico_exact_diag.argtypes = [vp, vp, vp]
+    lib.pico_profile_start.argtypes = [vp]
+    lib.pico_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
     lib.pico_lambda_abs.argtypes = [vp]
     lib.pico_lambda_abs.restype = ctypes.c_double
     lib.pico_destroy.argtypes = [vp]
@@ -89,7 +98,8 @@ def load(path: str = LIB_PATH):
     lib.pico_last_error.argtypes = []
     lib.pico_last_error.restype = ctypes.c_char_p
     for name in ("pico_init", "pico_apply_cov", "pico_noise_map", "pico_finalize",
-                 "pico_pmr_baseline", "pico_pmr_finalize"):
+                 "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse",
+                 "pico_exact_diag", "pico_profile_start", "pico_profile_stop"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -173,6 +183,29 @@ def pico_pmr_baseline(h, seed, first, nrep, acc, stats=None, stream=None):
 
 def pico_pmr_finalize(h, acc, var, stream=None):
     return _check(load().pico_pmr_finalize(h, ctypes.byref(acc), _ptr(var), _stream(stream)))
+
+
+def pico_monitor_nrmse(h, acc, ref_var, stream=None) -> float:
+    out = ctypes.c_double()
+    _check(load().pico_monitor_nrmse(h, ctypes.byref(acc), _ptr(ref_var), ctypes.byref(out),
+                                     _stream(stream)))
+    return out.value
+
+
+def pico_exact_diag(h, var, stream=None):
+    return _check(load().pico_exact_diag(h, _ptr(var), _stream(stream)))
+
+
+def pico_profile_start(h):
+    return _check(load().pico_profile_start(h))
+
+
+def pico_profile_stop(h):
+    """Returns {kind name: (total ms, launches)}."""
+    ms = (ctypes.c_double * PROF_KINDS)()
+    n = (ctypes.c_int64 * PROF_KINDS)()
+    _check(load().pico_profile_stop(h, ms, n))
+    return {PROF_NAMES[k]: (ms[k], n[k]) for k in range(len(PROF_NAMES))}
 
 
 def pico_lambda_abs(h) -> float:

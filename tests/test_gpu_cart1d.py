@@ -203,3 +203,26 @@ def test_degenerate_single_coil_full_sampling(lib):
     # one random-phase probe is exact when Sigma is diagonal (kappa = 1)
     assert np.abs(s / 2 - 2.0).max() < 1e-5
     assert np.abs(si).max() < 1e-5
+
+
+def test_exact_diag_and_monitor(lib):
+    say("case: exact diagonal by row probing + NRMSE monitor, 160x24 8 coils R=2 + 16 ACS")
+    from oracle import sense
+    prob = workloads.config(2, seed=1, ny=160, nx=24, nc=8, acs=16, cg_iters=40)
+    n = prob.ny * prob.nx
+    h = _init(lib, prob, 64)
+    ref = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    lib.pico_exact_diag(h, ref)
+    (s, _, _), acc = _gpu_map(lib, h, n, 4, 0, 24)
+    acc_t = [torch.from_numpy(s).to("cuda:0")]
+    acc2 = lib.make_accum(acc_t[0], count=24)
+    e_gpu = lib.pico_monitor_nrmse(h, acc2, ref)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    op = opico.cartesian(prob.maps, prob.psi, prob.mask)
+    ex = sense.exact_diag_1d(op, prob.mask).ravel()
+    err = _rel(ref.cpu().numpy(), ex)
+    e_ref = opico.nrmse_std(s / 24, ex)
+    say(f"  exact diag rel err {err:.2e}; monitor NRMSE gpu {e_gpu:.6f} oracle {e_ref:.6f}")
+    assert err < TOL
+    assert abs(e_gpu - e_ref) < 1e-6
