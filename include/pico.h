@@ -188,8 +188,9 @@ pico_status_t pico_exact_diag(pico_op_t op, double* var, void* stream);
  * summed duration in ms and the launch count (either pointer may be NULL). */
 enum {
   PICO_PROF_NORMAL_FIRST = 0,  /* first normal-operator application of a solve */
-  PICO_PROF_NORMAL_ITER = 1,   /* p = r + beta p fused with q = (M + lam) p     */
-  PICO_PROF_CG_UPDATE = 2,     /* x += alpha p, r -= alpha q, |r|^2 partials     */
+  PICO_PROF_NORMAL_ITER = 1,   /* x += alpha p, r -= alpha q, p = r + beta p
+                                  fused with q = (M + lam) p and its dots       */
+  PICO_PROF_CG_UPDATE = 2,     /* last x += alpha p of each solve               */
   PICO_PROF_CG_SCALARS = 3,    /* per-probe alpha / beta reductions             */
   PICO_PROF_ACCUM = 4,         /* FP64 accumulation of conj(v) u                */
   PICO_PROF_OTHER = 5,         /* Tikhonov middle product, PMR right-hand side  */

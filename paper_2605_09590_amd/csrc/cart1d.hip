@@ -128,62 +128,86 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
       }
     }
     d0 = group_reduce<L>(d0, red, lane);
-    if (active && lane == 0) a.part[((size_t)k * a.nx + col) * 2 + 1] = d0;
+    if (active && lane == 0) a.part[((size_t)k * a.nx + col) * 4] = d0;
     return;
   } else {
+    // rv keeps r_i for the d3 = Re(r^H q) partial; pv = p_i enters the normal operator
+    float2 rv[CF::VMAX];
     if (inA) {
       if constexpr (MODE == C1_FIRST_PROBE) {
 #pragma unroll
         for (int m = 0; m < VA; ++m) {
           const int y = CF::posA(lane, m);
           pv[m] = draw_probe(a.seed, a.first + kk, (uint32_t)(y * a.nx + col), 0u, a.dist);
+          rv[m] = pv[m];
           if (active) { a.r[base + y] = pv[m]; a.p[base + y] = pv[m]; }
-          d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
         }
       } else if constexpr (MODE == C1_FIRST_BUF) {
 #pragma unroll
         for (int m = 0; m < VA; ++m) {
           const int y = CF::posA(lane, m);
           pv[m] = a.r[base + y];
+          rv[m] = pv[m];
           if (active) a.p[base + y] = pv[m];
-          d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
         }
       } else if constexpr (MODE == C1_ITER) {
+        // finish iteration i-1 and start iteration i:
+        //   x += alpha p, r -= alpha q, p = r + beta p
+        const float alpha = (float)a.alpha[kk];
         const float beta = (float)a.beta[kk];
 #pragma unroll
         for (int m = 0; m < VA; ++m) {
           const int y = CF::posA(lane, m);
-          pv[m] = cfma(a.r[base + y], beta, a.p[base + y]);
-          if (active) a.p[base + y] = pv[m];
+          const float2 po = a.p[base + y];
+          const float2 qo = a.q[base + y];
+          const float2 xo = a.x_zero ? make_float2(0.f, 0.f) : a.x[base + y];
+          rv[m] = cfma(a.r[base + y], -alpha, qo);
+          pv[m] = cfma(rv[m], beta, po);
+          if (active) {
+            a.x[base + y] = cfma(xo, alpha, po);
+            a.r[base + y] = rv[m];
+            a.p[base + y] = pv[m];
+          }
         }
       } else {  // C1_APPLY
 #pragma unroll
-        for (int m = 0; m < VA; ++m) pv[m] = cscale(a.src[base + CF::posA(lane, m)], a.scale);
+        for (int m = 0; m < VA; ++m) {
+          pv[m] = cscale(a.src[base + CF::posA(lane, m)], a.scale);
+          rv[m] = make_float2(0.f, 0.f);
+        }
       }
     } else {
 #pragma unroll
-      for (int m = 0; m < VA; ++m) pv[m] = make_float2(0.f, 0.f);
+      for (int m = 0; m < VA; ++m) {
+        pv[m] = make_float2(0.f, 0.f);
+        rv[m] = make_float2(0.f, 0.f);
+      }
     }
 
     float2 qa[CF::VMAX];
     normal_col<CF>(pv, qa, a.lam, mcol, a.nc, mbits, lds, lane, tw);
 
-    double d1 = 0.0, d2 = 0.0;
+    double d1 = 0.0, d2 = 0.0, d3 = 0.0;
     if (inA) {
 #pragma unroll
       for (int m = 0; m < VA; ++m) {
         if (active) a.q[base + CF::posA(lane, m)] = qa[m];
+        d0 += (double)rv[m].x * rv[m].x + (double)rv[m].y * rv[m].y;
         d1 += (double)pv[m].x * qa[m].x + (double)pv[m].y * qa[m].y;
         d2 += (double)qa[m].x * qa[m].x + (double)qa[m].y * qa[m].y;
+        d3 += (double)rv[m].x * qa[m].x + (double)rv[m].y * qa[m].y;
       }
     }
+    d0 = group_reduce<L>(d0, red, lane);
     d1 = group_reduce<L>(d1, red, lane);
-    if constexpr (MODE == C1_APPLY) d0 = group_reduce<L>(d2, red, lane);
-    else if constexpr (MODE != C1_ITER) d0 = group_reduce<L>(d0, red, lane);
+    d2 = group_reduce<L>(d2, red, lane);
+    d3 = group_reduce<L>(d3, red, lane);
     if (active && lane == 0) {
-      double* pp = a.part + ((size_t)k * a.nx + col) * 2;
-      pp[0] = d1;
-      if constexpr (MODE != C1_ITER) pp[1] = d0;
+      double* pp = a.part + ((size_t)k * a.nx + col) * 4;
+      pp[0] = d0;
+      pp[1] = d1;
+      pp[2] = d2;
+      pp[3] = d3;
     }
   }
 }

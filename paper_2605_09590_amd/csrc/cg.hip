@@ -8,110 +8,79 @@
 
 namespace pico {
 
-// x += alpha p, r -= alpha q; per-block partial |r|^2.
-// grid (nblk, K), block 256, each thread EPT consecutive elements per round.
-__global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
+// Last update of a solve: x += alpha p (iteration I's step; earlier steps
+// are fused into the normal-operator kernel).
+__global__ __launch_bounds__(256) void k_final_x(FinalArgs a) {
   const int k = blockIdx.y;
   const float alpha = (float)a.alpha[k];
   const size_t off = (size_t)k * a.n;
-  float2* __restrict__ x = a.x + off;
-  float2* __restrict__ r = a.r + off;
-  const float2* __restrict__ p = a.p + off;
-  const float2* __restrict__ q = a.q + off;
-  double acc = 0.0;
-  const int stride = gridDim.x * blockDim.x;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-    const float2 pv = p[i], qv = q[i];
-    float2 xv = a.first_iter ? make_float2(0.f, 0.f) : x[i];
-    float2 rv = r[i];
-    xv = cfma(xv, alpha, pv);
-    rv = cfma(rv, -alpha, qv);
-    x[i] = xv;
-    r[i] = rv;
-    acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
+    const float2 xo = a.x_zero ? make_float2(0.f, 0.f) : a.x[off + i];
+    a.x[off + i] = cfma(xo, alpha, a.p[off + i]);
   }
-  acc = group_sum<64>(acc);
-  __shared__ double red[4];
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) a.part[(size_t)k * a.nblk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
-  dim3 grid(a.nblk, a.K), block(256);
-  hipLaunchKernelGGL(k_update, grid, block, 0, s, a);
+hipError_t launch_final_x(const FinalArgs& a, hipStream_t s) {
+  const int nblk = (a.n + 1023) / 1024;
+  dim3 grid(nblk < 1024 ? nblk : 1024, a.K), block(256);
+  hipLaunchKernelGGL(k_final_x, grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-// Step scalars per right-hand side; one wavefront per probe.
-//  stage 0: rr0 = rr = sum partA[.][1]; then as stage 1
-//  stage 1: alpha = rr / Re(p^H q)             (freeze on breakdown)
-//  stage 2: rr' = sum partB; beta = rr' / rr   (freeze at tolerance)
-struct ScalarKArgs {
-  ScalarArgs s;
-  const double* partA;
-  int nblkA;
-  const double* partB;
-  int nblkB;
-};
-
-__global__ __launch_bounds__(64) void k_scalars(ScalarKArgs ka) {
-  const ScalarArgs& a = ka.s;
+// Step scalars of iteration i per right-hand side (one wavefront each), from
+// the partial dots of the kernel that formed p_i and q_i = (M + lam) p_i:
+//   rr_i = |r_i|^2 (measured), alpha_i = rr_i / Re(p_i^H q_i),
+//   rr_{i+1} = |r_i - alpha_i q_i|^2 = rr_i - 2 alpha_i Re(r_i^H q_i) + alpha_i^2 |q_i|^2,
+//   beta_i = rr_{i+1} / rr_i.
+// A right-hand side freezes (alpha = beta = 0 from then on) on breakdown
+// (Re p^H q <= 0 or a non-finite scalar), when rr_i = 0, and, in tolerance
+// mode, once sqrt(rr_{i+1} / rr_0) <= tol (after its last step is applied).
+__global__ __launch_bounds__(64) void k_scalars(ScalarArgs a) {
   const int k = blockIdx.x;
   const int lane = threadIdx.x;
-  double s0 = 0.0, s1 = 0.0;
-  if (a.stage <= 1) {
-    for (int i = lane; i < ka.nblkA; i += 64) {
-      s0 += ka.partA[((size_t)k * ka.nblkA + i) * 2 + 0];
-      if (a.stage == 0) s1 += ka.partA[((size_t)k * ka.nblkA + i) * 2 + 1];
-    }
-  } else {
-    for (int i = lane; i < ka.nblkB; i += 64) s1 += ka.partB[(size_t)k * ka.nblkB + i];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = lane; i < a.nblk; i += 64) {
+    const double* pp = a.part + ((size_t)k * a.nblk + i) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] += pp[j];
   }
-  s0 = group_sum<64>(s0);
-  s1 = group_sum<64>(s1);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) s[j] = group_sum<64>(s[j]);
   if (lane != 0) return;
   int st = a.state[k];
-  if (a.stage == 0) {
-    a.rr0[k] = s1;
-    a.rr[k] = s1;
+  const double rr = s[0];
+  if (a.first) {
+    a.rr0[k] = rr;
     st = CG_ACTIVE;
   }
-  if (a.stage <= 1) {
-    const double rr = a.rr[k];
-    double alpha = 0.0;
-    if (st == CG_ACTIVE) {
-      if (rr == 0.0) {
-        st = CG_CONVERGED;
-      } else if (!(s0 > 0.0) || !isfinite(s0) || !isfinite(rr)) {
+  double alpha = 0.0, beta = 0.0;
+  if (st == CG_ACTIVE) {
+    if (rr == 0.0) {
+      st = CG_CONVERGED;
+      a.rr[k] = 0.0;
+    } else if (!(s[1] > 0.0) || !isfinite(s[1]) || !isfinite(rr)) {
+      st = CG_BREAKDOWN;
+    } else {
+      alpha = rr / s[1];
+      double rn = rr - 2.0 * alpha * s[3] + alpha * alpha * s[2];
+      if (!isfinite(rn)) {
         st = CG_BREAKDOWN;
+        alpha = 0.0;
       } else {
-        alpha = rr / s0;
+        if (rn < 0.0) rn = 0.0;
+        a.rr[k] = rn;
+        if (rn == 0.0 || (a.tol > 0.0 && sqrt(rn / a.rr0[k]) <= a.tol)) st = CG_CONVERGED;
+        else beta = rn / rr;
       }
     }
-    a.alpha[k] = alpha;
-  } else {
-    double beta = 0.0;
-    if (st == CG_ACTIVE) {
-      const double rr = a.rr[k];
-      if (!isfinite(s1)) {
-        st = CG_BREAKDOWN;
-      } else {
-        a.rr[k] = s1;
-        if (a.tol > 0.0 && sqrt(s1 / a.rr0[k]) <= a.tol) st = CG_CONVERGED;
-        else beta = s1 / rr;
-      }
-    }
-    a.beta[k] = beta;
   }
+  a.alpha[k] = alpha;
+  a.beta[k] = beta;
   a.state[k] = st;
 }
 
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s) {
-  // partA / partB carried through the same struct for a single launch signature
-  ScalarKArgs ka{a, a.part, a.nblk, a.part, a.nblk};
-  hipLaunchKernelGGL(k_scalars, dim3(a.K), dim3(64), 0, s, ka);
+  hipLaunchKernelGGL(k_scalars, dim3(a.K), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

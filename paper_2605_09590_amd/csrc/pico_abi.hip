@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pico.h"
+#include "pico.h"
 #include "runtime.h"
 
 using cd = std::complex<double>;
@@ -41,7 +41,6 @@ struct pico_op_s {
   int ny = 0, nx = 0, nc = 0, sampling = 0, recon = 0;
   int cg_iters = 0, K = 0;
   double cg_tol = 0.0, lam_rel = 0.0, lam_abs = 0.0;
-  int nblkB = 0;
   hipStream_t last_stream = nullptr;
   // resident operator
   float2* maps = nullptr;   // [nx][nc][ny]
@@ -49,8 +48,7 @@ struct pico_op_s {
   float2* twt = nullptr;    // [ny]
   // batched CG workspace, [K][nx][ny] each
   float2 *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
-  double* partA = nullptr;  // [K][nx][2]
-  double* partB = nullptr;  // [K][nblkB]
+  double* partA = nullptr;  // [K][nx][4] partial dots per image column
   double* mon = nullptr;    // [512] convergence-monitor partials
   double *alpha = nullptr, *beta = nullptr, *rr = nullptr, *rr0 = nullptr;
   int* state = nullptr;
@@ -158,9 +156,11 @@ pico::Cart1dArgs base_args(pico_op_t op, int K) {
   a.maps = op->maps;
   a.maskw = op->maskw;
   a.twt = op->twt;
+  a.x = op->x;
   a.r = op->r;
   a.p = op->p;
   a.q = op->q;
+  a.alpha = op->alpha;
   a.beta = op->beta;
   a.part = op->partA;
   a.lam = (float)op->lam_abs;
@@ -168,22 +168,24 @@ pico::Cart1dArgs base_args(pico_op_t op, int K) {
   return a;
 }
 
-hipError_t scalars(pico_op_t op, int K, int stage, hipStream_t s) {
+hipError_t scalars(pico_op_t op, int K, bool first, hipStream_t s) {
   pico::ScalarArgs sa{};
   sa.K = K;
-  sa.part = stage == 2 ? op->partB : op->partA;
-  sa.nblk = stage == 2 ? op->nblkB : op->nx;
+  sa.part = op->partA;
+  sa.nblk = op->nx;
   sa.alpha = op->alpha;
   sa.beta = op->beta;
   sa.rr = op->rr;
   sa.rr0 = op->rr0;
   sa.state = op->state;
   sa.tol = op->cg_tol;
-  sa.stage = stage;
+  sa.first = first ? 1 : 0;
   return timed(op, PICO_PROF_CG_SCALARS, s, [&] { return pico::launch_scalars(sa, s); });
 }
 
-// One batched CG solve of (M + lam) x = b for K right-hand sides.  The
+// One batched CG solve of (M + lam) x = b for K right-hand sides, x0 = 0.
+// Iteration i's vector update is fused into the kernel that applies the
+// normal operator for iteration i + 1; the last one runs on its own.  The
 // first normal-operator application uses ``first_mode`` (probe draw or the
 // right-hand side already in r); the solution ends in op->x.
 hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t first, int dist,
@@ -194,27 +196,20 @@ hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t
   a.dist = dist;
   hipError_t e = timed(op, PICO_PROF_NORMAL_FIRST, s, [&] { return pico::launch_cart1d(first_mode, a, s); });
   if (e != hipSuccess) return e;
-  if ((e = scalars(op, K, 0, s)) != hipSuccess) return e;
-  pico::UpdateArgs u{};
-  u.n = op->ny * op->nx;
-  u.K = K;
-  u.x = op->x;
-  u.r = op->r;
-  u.p = op->p;
-  u.q = op->q;
-  u.alpha = op->alpha;
-  u.part = op->partB;
-  u.nblk = op->nblkB;
-  for (int it = 0; it < op->cg_iters; ++it) {
-    if (it > 0) {
-      if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return pico::launch_cart1d(pico::C1_ITER, a, s); })) != hipSuccess) return e;
-      if ((e = scalars(op, K, 1, s)) != hipSuccess) return e;
-    }
-    u.first_iter = (it == 0);
-    if ((e = timed(op, PICO_PROF_CG_UPDATE, s, [&] { return pico::launch_update(u, s); })) != hipSuccess) return e;
-    if ((e = scalars(op, K, 2, s)) != hipSuccess) return e;
+  if ((e = scalars(op, K, true, s)) != hipSuccess) return e;
+  for (int it = 1; it < op->cg_iters; ++it) {
+    a.x_zero = (it == 1);
+    if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return pico::launch_cart1d(pico::C1_ITER, a, s); })) != hipSuccess) return e;
+    if ((e = scalars(op, K, false, s)) != hipSuccess) return e;
   }
-  return hipSuccess;
+  pico::FinalArgs f{};
+  f.n = op->ny * op->nx;
+  f.K = K;
+  f.x = op->x;
+  f.p = op->p;
+  f.alpha = op->alpha;
+  f.x_zero = (op->cg_iters == 1);   // a single step: x enters as 0
+  return timed(op, PICO_PROF_CG_UPDATE, s, [&] { return pico::launch_final_x(f, s); });
 }
 
 // u = Sigma v for the K right-hand sides (probes drawn in-kernel or already
@@ -315,7 +310,6 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   op->last_stream = s;
   const size_t n = (size_t)ny * nx;
   const int K = op->K;
-  op->nblkB = (int)std::min<size_t>(1024, (n + 1023) / 1024);
 
   double* linv_d = nullptr;
   hipError_t e = hipSuccess;
@@ -332,8 +326,7 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   if ((e = op->alloc(&op->r, n * K)) != hipSuccess) return bad(e, "workspace r");
   if ((e = op->alloc(&op->p, n * K)) != hipSuccess) return bad(e, "workspace p");
   if ((e = op->alloc(&op->q, n * K)) != hipSuccess) return bad(e, "workspace q");
-  if ((e = op->alloc(&op->partA, (size_t)K * nx * 2)) != hipSuccess) return bad(e, "partials");
-  if ((e = op->alloc(&op->partB, (size_t)K * op->nblkB)) != hipSuccess) return bad(e, "partials");
+  if ((e = op->alloc(&op->partA, (size_t)K * nx * 4)) != hipSuccess) return bad(e, "partials");
   if ((e = op->alloc(&op->mon, 512)) != hipSuccess) return bad(e, "monitor");
   if ((e = op->alloc(&op->alpha, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&op->beta, K)) != hipSuccess) return bad(e, "scalars");
@@ -375,13 +368,13 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
       a.lam = 0.0f;
       a.scale = (float)scale;
       if ((e = pico::launch_cart1d(pico::C1_APPLY, a, s)) != hipSuccess) return bad(e, "power");
-      std::vector<double> part((size_t)nx * 2);
+      std::vector<double> part((size_t)nx * 4);
       if ((e = hipMemcpyAsync(part.data(), op->partA, part.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "power");
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "power");
       double vq = 0.0, qq = 0.0;
       for (int c = 0; c < nx; ++c) {
-        vq += part[2 * c];
-        qq += part[2 * c + 1];
+        vq += part[4 * c + 1];
+        qq += part[4 * c + 2];
       }
       lam_hat = vq;              // Rayleigh quotient of the unit vector (scale * src)
       scale = 1.0 / std::sqrt(qq);

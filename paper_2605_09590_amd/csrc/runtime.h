@@ -14,7 +14,7 @@ enum : int { CG_ACTIVE = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
 enum Cart1dMode : int {
   C1_FIRST_PROBE = 0,  // r = p = v (Philox probe); q = (M + lam) p
   C1_FIRST_BUF = 1,    // p = r (right-hand side already in r); q = (M + lam) p
-  C1_ITER = 2,         // p = r + beta p; q = (M + lam) p
+  C1_ITER = 2,         // x += alpha p, r -= alpha q, p = r + beta p; q = (M + lam) p
   C1_APPLY = 3,        // dst = (M + lam) (scale * src)
   C1_PMR_RHS = 4,      // r = A^H n, n white k-space noise in the hybrid (ky, x) domain
 };
@@ -25,40 +25,39 @@ struct Cart1dArgs {
   const float* maskw;          // [ny] weight mask[k] / ny (0 off the mask)
   const float2* twt;           // [ny] W_ny^m = exp(-2 pi i m / ny)
   const float2* src;           // input field   (mode dependent)
-  float2* r;                   // [K][nx][ny]
+  float2* x;                   // [K][nx][ny]
+  float2* r;
   float2* p;
   float2* q;
+  const double* alpha;         // [K] step of the previous iteration
   const double* beta;          // [K]
-  double* part;                // [K][nx][2] partial dots
+  int x_zero;                  // C1_ITER: x enters as 0 (first update)
+  double* part;                // [K][nx][4]: |r|^2, Re p^H q, |q|^2, Re r^H q
   float lam;                   // added to M p
   float scale;                 // C1_APPLY input scale
   uint64_t seed, first;        // probe / noise draw
   int dist;                    // probe family
 };
 
-// CG update x += alpha p, r -= alpha q; part[.][.][1] = |r|^2 partials
-struct UpdateArgs {
+// Last CG update x += alpha p
+struct FinalArgs {
   int n, K;                    // n = voxels per probe
   float2* x;
-  float2* r;
   const float2* p;
-  const float2* q;
   const double* alpha;         // [K]
-  double* part;                // [K][nblk][2]
-  int nblk;                    // partial blocks per probe
-  int first_iter;              // x treated as 0
+  int x_zero;                  // x enters as 0 (single-iteration solves)
 };
 
 struct ScalarArgs {
   int K, nblk;
-  const double* part;          // [K][nblk][2]
+  const double* part;          // [K][nblk][4]: |r_i|^2, Re p_i^H q_i, |q_i|^2, Re r_i^H q_i
   double* alpha;               // [K]
   double* beta;                // [K]
-  double* rr;                  // [K]
+  double* rr;                  // [K] |r_{i+1}|^2
   double* rr0;                 // [K]
   int* state;                  // [K]
   double tol;
-  int stage;                   // 0: after first normal op (sets rr0, rr, alpha); 1: after A (alpha); 2: after B (beta)
+  int first;                   // 1 after the first normal-operator application
 };
 
 struct AccumArgs {
@@ -74,7 +73,7 @@ struct AccumArgs {
 
 bool cart1d_supported(int ny);
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
-hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
+hipError_t launch_final_x(const FinalArgs& a, hipStream_t s);
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);
 hipError_t launch_accum_colmajor(const AccumArgs& a, hipStream_t s);
 hipError_t launch_prep_maps_cart1d(const float2* maps, const double* linv, float2* out,
