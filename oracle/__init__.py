@@ -29,4 +29,4 @@ Pins (what each part is checked against, in tests/test_oracle_*.py):
   cs            tangent vs central finite differences; tau=0 reduces to the
                 linear unrolled map.
 """
-from . import philox, sense, solvers, pico  # noqa: F401
+from . import philox, sense, solvers, pico, nufft  # noqa: F401

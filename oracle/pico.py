@@ -136,12 +136,17 @@ def finalize(acc):
 def pmr_noise(op, seed: int, r: int):
     """White k-space noise replica n_r ~ CN(0, I) for ``op``, zero off the mask.
 
-    Philox element index (c * ny + ky) * nx + x.  For a 1-D phase-encode
+    Philox element index (c * ny + ky) * nx + x (Cartesian) or c * M + m
+    (non-Cartesian, M samples per coil).  For a 1-D phase-encode
     mask the draw is made in the hybrid (ky, x) domain and carried to k-space
     by the centred orthonormal DFT along x; F_x is unitary, so the result is
     still CN(0, I) and the separable GPU path can consume the hybrid draw
     directly.
     """
+    if hasattr(op, "traj"):
+        # non-Cartesian: element index c * M + m over the acquired samples
+        return philox.probe(seed, r, op.nc * op.M, "gaussian",
+                            stream=philox.STREAM_PMR).reshape(op.nc, op.M)
     nc, ny, nx = op.nc, op.ny, op.nx
     h = philox.probe(seed, r, nc * ny * nx, "gaussian", stream=philox.STREAM_PMR)
     h = h.reshape(nc, ny, nx)
