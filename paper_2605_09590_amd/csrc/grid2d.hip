@@ -1,0 +1,431 @@
+// Normal operator on a 2-D frequency grid, shared by Cartesian 2-D masks and
+// the non-Cartesian Toeplitz embedding:
+//
+//   q = lam p + sum_c conj(S_c) . crop( G2^-1( W . G2( pad(S_c . p) ) ) )
+//
+// where G2 is the unnormalised 2-D DFT on a Gy x Gx grid and W a real
+// weight, transposed [Gx][Gy] in memory:
+//  * Cartesian 2-D mask: Gy x Gx = ny x nx, W = mask / (ny nx), maps folded
+//    with (-1)^(y+x) (the centred DFT is (-1)^((ny+nx)/2) D F D, D = (-1)^(y+x),
+//    so the centred-order mask applies unchanged; Sec. 2.1 Eq. (6));
+//  * spiral, Toeplitz form (Sec. 3.2.2, 3.3): Gy x Gx = 2ny x 2nx,
+//    W = DFT(circulant embedding of the point-spread function) / (4 ny nx),
+//    real because the PSF is Hermitian; the product is the exact NUDFT
+//    normal operator A^H A.
+//
+// Three kernels per application, all per-probe fields row-major [K][ny][nx]:
+//  rows_fwd  per image row: CG update / probe draw, then per coil S_c p,
+//            zero-pad to Gx, row FFT -> T[k][c][y][Gx] (only the ny
+//            non-zero rows of the padded grid are stored);
+//  cols      per tile of adjacent grid columns of one (k, c) plane, staged
+//            through LDS for coalescing: zero-pad to Gy, column FFT,
+//            times W, inverse column FFT, keep rows < ny;
+//  rows_inv  per image row: per coil inverse row FFT, crop to nx,
+//            conj(S_c) times it, summed over coils; q written with the FP64
+//            partial dots of the CG step.
+#include "fft.h"
+#include "runtime.h"
+
+namespace pico {
+
+template <int L>
+__device__ __forceinline__ double group_reduce2(double v, double* red, int lane) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (lane == 0) {
+    for (int i = 0; i < L; ++i) s += red[threadIdx.x + i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------- row pass 1
+template <class CF, int MODE>
+__global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
+  constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
+  constexpr int VA = CF::VA, VB = CF::VB;
+  __shared__ float2 lds_all[NG * CF::SPAN];
+  __shared__ double red[64];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const long gid = (long)blockIdx.x * G + g;
+  const bool active = g < G && gid < (long)a.K * a.ny;
+  const long gg = active ? gid : 0;
+  const int k = (int)(gg / a.ny), y = (int)(gg % a.ny);
+  const bool inA = CF::inA(lane), inB = CF::inB(lane);
+  float2* lds = lds_all + g * CF::SPAN;
+  typename CF::Tw tw;
+  CF::load_tw(tw, a.twx, lane);
+
+  const size_t rowoff = ((size_t)k * a.ny + y) * a.nx;
+  float2 pv[CF::VMAX];
+  double d0 = 0.0;
+#pragma unroll
+  for (int m = 0; m < VA; ++m) {
+    const int xx = CF::posA(lane, m);
+    float2 val = make_float2(0.f, 0.f);
+    if (inA && xx < a.nx) {
+      const size_t i = rowoff + xx;
+      if constexpr (MODE == C1_FIRST_PROBE) {
+        val = draw_probe(a.seed, a.first + k, (uint32_t)(y * a.nx + xx), 0u, a.dist);
+        if (active) { a.r[i] = val; a.p[i] = val; }
+        d0 += (double)val.x * val.x + (double)val.y * val.y;
+      } else if constexpr (MODE == C1_FIRST_BUF) {
+        val = a.r[i];
+        if (active) a.p[i] = val;
+        d0 += (double)val.x * val.x + (double)val.y * val.y;
+      } else if constexpr (MODE == C1_ITER) {
+        const float alpha = (float)a.alpha[k], beta = (float)a.beta[k];
+        const float2 po = a.p[i], qo = a.q[i];
+        const float2 xo = a.x_zero ? make_float2(0.f, 0.f) : a.x[i];
+        const float2 rn = cfma(a.r[i], -alpha, qo);
+        val = cfma(rn, beta, po);
+        if (active) {
+          a.x[i] = cfma(xo, alpha, po);
+          a.r[i] = rn;
+          a.p[i] = val;
+        }
+        d0 += (double)rn.x * rn.x + (double)rn.y * rn.y;
+      } else {  // C1_APPLY
+        val = cscale(a.src[i], a.scale);
+      }
+    }
+    pv[m] = val;
+  }
+  if constexpr (MODE != C1_APPLY) {
+    d0 = group_reduce2<L>(d0, red, lane);
+    if (active && lane == 0) a.part[((size_t)k * a.ny + y) * 4] = d0;
+  }
+
+  for (int c = 0; c < a.nc; ++c) {
+    const float2* __restrict__ s = a.maps + ((size_t)c * a.ny + y) * a.nx;
+    float2 v[CF::VMAX];
+#pragma unroll
+    for (int m = 0; m < VA; ++m) {
+      const int xx = CF::posA(lane, m);
+      v[m] = (inA && xx < a.nx) ? cmul(s[xx], pv[m]) : make_float2(0.f, 0.f);
+    }
+    CF::template forward<false>(v, lds, lane, tw);
+    if (active && inB) {
+      float2* t = a.T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+#pragma unroll
+      for (int r = 0; r < VB; ++r) t[CF::posB(lane, r)] = v[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- column pass
+// One workgroup of 256 lanes: NGRP = 256 / L column groups, one grid column
+// each, adjacent columns of one (k, c) plane.
+template <class CF>
+__global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
+  constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
+  constexpr int VA = CF::VA, VB = CF::VB;
+  constexpr int TS = NGRP + 1;  // padded tile row
+  extern __shared__ float2 dyn[];
+  float2* tile = dyn;                                  // [ny][TS]
+  float2* xch = dyn + (size_t)a.ny * TS;               // NG exchange regions
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const int x0 = blockIdx.x * NGRP;
+  const size_t plane = (size_t)blockIdx.y * a.ny * a.Gx;
+  const int ncol = min(NGRP, a.Gx - x0);
+  for (int i = threadIdx.x; i < a.ny * NGRP; i += 256) {
+    const int yy = i / NGRP, j = i % NGRP;
+    tile[yy * TS + j] = j < ncol ? a.T[plane + (size_t)yy * a.Gx + x0 + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const bool grp = g < NGRP && g < ncol;
+  const bool inA = CF::inA(lane), inB = CF::inB(lane);
+  typename CF::Tw tw;
+  CF::load_tw(tw, a.twy, lane);
+  float2 v[CF::VMAX];
+#pragma unroll
+  for (int m = 0; m < VA; ++m) {
+    const int yy = CF::posA(lane, m);
+    v[m] = (grp && inA && yy < a.ny) ? tile[yy * TS + g] : make_float2(0.f, 0.f);
+  }
+  float2* lds = xch + g * CF::SPAN;
+  CF::template forward<false>(v, lds, lane, tw);
+  const float* __restrict__ wcol = a.w + (size_t)(grp ? x0 + g : 0) * a.Gy;
+  if (inB) {
+#pragma unroll
+    for (int r = 0; r < VB; ++r) v[r] = cscale(v[r], wcol[CF::posB(lane, r)]);
+  }
+  CF::template inverse<true>(v, lds, lane, tw);
+  if (grp && inA) {
+#pragma unroll
+    for (int m = 0; m < VA; ++m) {
+      const int yy = CF::posA(lane, m);
+      if (yy < a.ny) tile[yy * TS + g] = v[m];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.ny * NGRP; i += 256) {
+    const int yy = i / NGRP, j = i % NGRP;
+    if (j < ncol) a.T[plane + (size_t)yy * a.Gx + x0 + j] = tile[yy * TS + j];
+  }
+}
+
+// ---------------------------------------------------------------- row pass 2
+template <class CF, int MODE>
+__global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
+  constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
+  constexpr int VA = CF::VA, VB = CF::VB;
+  __shared__ float2 lds_all[NG * CF::SPAN];
+  __shared__ double red[64];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const long gid = (long)blockIdx.x * G + g;
+  const bool active = g < G && gid < (long)a.K * a.ny;
+  const long gg = active ? gid : 0;
+  const int k = (int)(gg / a.ny), y = (int)(gg % a.ny);
+  const bool inA = CF::inA(lane), inB = CF::inB(lane);
+  float2* lds = lds_all + g * CF::SPAN;
+  typename CF::Tw tw;
+  CF::load_tw(tw, a.twx, lane);
+  const size_t rowoff = ((size_t)k * a.ny + y) * a.nx;
+
+  float2 qa[CF::VMAX];
+#pragma unroll
+  for (int m = 0; m < VA; ++m) {
+    const int xx = CF::posA(lane, m);
+    float2 pval = make_float2(0.f, 0.f);
+    if (inA && xx < a.nx && a.lam != 0.f)
+      pval = MODE == C1_APPLY ? cscale(a.src[rowoff + xx], a.scale) : a.p[rowoff + xx];
+    qa[m] = cscale(pval, a.lam);
+  }
+  for (int c = 0; c < a.nc; ++c) {
+    float2 v[CF::VMAX];
+    const float2* t = a.T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+#pragma unroll
+    for (int r = 0; r < VB; ++r) v[r] = inB ? t[CF::posB(lane, r)] : make_float2(0.f, 0.f);
+    CF::template inverse<true>(v, lds, lane, tw);
+    const float2* __restrict__ s = a.maps + ((size_t)c * a.ny + y) * a.nx;
+#pragma unroll
+    for (int m = 0; m < VA; ++m) {
+      const int xx = CF::posA(lane, m);
+      if (inA && xx < a.nx) qa[m] = cadd(qa[m], cmulc(s[xx], v[m]));
+    }
+  }
+  double d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+  for (int m = 0; m < VA; ++m) {
+    const int xx = CF::posA(lane, m);
+    if (inA && xx < a.nx) {
+      const size_t i = rowoff + xx;
+      const float2 pval = MODE == C1_APPLY ? cscale(a.src[i], a.scale) : a.p[i];
+      const float2 rval = MODE == C1_ITER ? a.r[i] : pval;
+      if (active) a.q[i] = qa[m];
+      d1 += (double)pval.x * qa[m].x + (double)pval.y * qa[m].y;
+      d2 += (double)qa[m].x * qa[m].x + (double)qa[m].y * qa[m].y;
+      d3 += (double)rval.x * qa[m].x + (double)rval.y * qa[m].y;
+    }
+  }
+  d1 = group_reduce2<L>(d1, red, lane);
+  d2 = group_reduce2<L>(d2, red, lane);
+  d3 = group_reduce2<L>(d3, red, lane);
+  if (active && lane == 0) {
+    double* pp = a.part + ((size_t)k * a.ny + y) * 4;
+    pp[1] = d1;
+    pp[2] = d2;
+    pp[3] = d3;
+  }
+}
+
+// ---------------------------------------------------------------- plans
+using L64 = TwoStep<8, 8>;
+using L96 = StockhamCol<FFTPlan<96, 8, 12, 4, 2>>;
+using L128 = StockhamCol<FFTPlan<128, 16, 8, 4, 4>>;
+using L160 = StockhamCol<FFTPlan<160, 8, 20, 4, 2>>;
+using L192 = StockhamCol<FFTPlan<192, 16, 12, 4, 4>>;
+using L256 = TwoStep<16, 16>;
+using L288 = StockhamCol<FFTPlan<288, 16, 18, 2, 2, 2, 2>>;
+using L320 = TwoStep<20, 16>;
+using L384 = StockhamCol<FFTPlan<384, 16, 24, 4, 4>>;
+using L512 = StockhamCol<FFTPlan<512, 32, 16, 16, 2>>;
+using L576 = StockhamCol<FFTPlan<576, 16, 36, 4, 4>>;
+using L640 = StockhamCol<FFTPlan<640, 32, 20, 4, 4, 2>>;
+using L768 = StockhamCol<FFTPlan<768, 32, 24, 4, 4, 2>>;
+
+bool grid_line_supported(int n) {
+  switch (n) {
+    case 64: case 96: case 128: case 160: case 192: case 256: case 288: case 320: case 384:
+    case 512: case 576: case 640: case 768:
+      return true;
+    default:
+      return false;
+  }
+}
+
+template <class F>
+static hipError_t with_line(int n, F&& f) {
+  switch (n) {
+    case 64: return f(L64{});
+    case 96: return f(L96{});
+    case 128: return f(L128{});
+    case 160: return f(L160{});
+    case 192: return f(L192{});
+    case 256: return f(L256{});
+    case 288: return f(L288{});
+    case 320: return f(L320{});
+    case 384: return f(L384{});
+    case 512: return f(L512{});
+    case 576: return f(L576{});
+    case 640: return f(L640{});
+    case 768: return f(L768{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class CF>
+static hipError_t rows_fwd(int mode, const Grid2dArgs& a, hipStream_t s) {
+  constexpr int G = 64 / CF::L;
+  const long rows = (long)a.K * a.ny;
+  dim3 grid((unsigned)((rows + G - 1) / G)), block(64);
+  switch (mode) {
+    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_rows_fwd<CF, C1_FIRST_PROBE>), grid, block, 0, s, a); break;
+    case C1_FIRST_BUF: hipLaunchKernelGGL((k_rows_fwd<CF, C1_FIRST_BUF>), grid, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL((k_rows_fwd<CF, C1_ITER>), grid, block, 0, s, a); break;
+    case C1_APPLY: hipLaunchKernelGGL((k_rows_fwd<CF, C1_APPLY>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class CF>
+static hipError_t rows_inv(int mode, const Grid2dArgs& a, hipStream_t s) {
+  constexpr int G = 64 / CF::L;
+  const long rows = (long)a.K * a.ny;
+  dim3 grid((unsigned)((rows + G - 1) / G)), block(64);
+  switch (mode) {
+    case C1_FIRST_PROBE: case C1_FIRST_BUF:
+      hipLaunchKernelGGL((k_rows_inv<CF, C1_FIRST_BUF>), grid, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL((k_rows_inv<CF, C1_ITER>), grid, block, 0, s, a); break;
+    case C1_APPLY: hipLaunchKernelGGL((k_rows_inv<CF, C1_APPLY>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class CF>
+static hipError_t cols(const Grid2dArgs& a, hipStream_t s) {
+  constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
+  const size_t lds = ((size_t)a.ny * (NGRP + 1) + (size_t)NG * CF::SPAN) * sizeof(float2);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static bool attr_set = false;   // allow more than the default 64 KiB of dynamic LDS
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_cols<CF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid((a.Gx + NGRP - 1) / NGRP, (unsigned)((long)a.K * a.nc)), block(256);
+  hipLaunchKernelGGL((k_cols<CF>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+size_t grid_cols_lds_bytes(int Gy, int ny) {
+  size_t out = 0;
+  (void)with_line(Gy, [&](auto cf) {
+    using CF = decltype(cf);
+    constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
+    out = ((size_t)ny * (NGRP + 1) + (size_t)NG * CF::SPAN) * sizeof(float2);
+    return hipSuccess;
+  });
+  return out;
+}
+
+hipError_t launch_grid_normal(int mode, const Grid2dArgs& a, hipStream_t s) {
+  hipError_t e = with_line(a.Gx, [&](auto cf) { return rows_fwd<decltype(cf)>(mode, a, s); });
+  if (e != hipSuccess) return e;
+  e = with_line(a.Gy, [&](auto cf) { return cols<decltype(cf)>(a, s); });
+  if (e != hipSuccess) return e;
+  return with_line(a.Gx, [&](auto cf) { return rows_inv<decltype(cf)>(mode, a, s); });
+}
+
+// ---------------------------------------------------------------- row-major accumulation
+__global__ void k_accum_rowmajor(AccumArgs a) {
+  const int n = a.ny * a.nx;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0, si = 0.0, ss = 0.0;
+  for (int k = 0; k < a.K; ++k) {
+    const float2 u = a.x[(size_t)k * n + i];
+    if (a.pmr) {
+      s += (double)u.x;
+      si += (double)u.y;
+      ss += (double)u.x * u.x + (double)u.y * u.y;
+    } else {
+      const float2 v = draw_probe(a.seed, a.first + k, (uint32_t)i, 0u, a.dist);
+      const double re = (double)v.x * u.x + (double)v.y * u.y;
+      const double im = (double)v.x * u.y - (double)v.y * u.x;
+      s += re;
+      si += im;
+      ss += re * re;
+    }
+  }
+  a.sum[i] += s;
+  if (a.sum_im) a.sum_im[i] += si;
+  if (a.sumsq) a.sumsq[i] += ss;
+}
+
+hipError_t launch_accum_rowmajor(const AccumArgs& a, hipStream_t s) {
+  const int n = a.ny * a.nx;
+  hipLaunchKernelGGL(k_accum_rowmajor, dim3((n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- map preparation
+// out[c][y][x] = sg(y, x) sum_d Linv[c][d] maps[d][y][x]; sg = (-1)^(y+x) when fold.
+__global__ void k_prep_maps_rowmajor(const float2* __restrict__ maps, const double* __restrict__ linv,
+                                     float2* __restrict__ out, int nc, int ny, int nx, int fold) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ny * nx) return;
+  const int y = i / nx, x = i % nx;
+  const double sg = (fold && ((y + x) & 1)) ? -1.0 : 1.0;
+  for (int c = 0; c < nc; ++c) {
+    double re = 0.0, im = 0.0;
+    for (int d = 0; d <= c; ++d) {
+      const double lr = linv[2 * (c * nc + d)], li = linv[2 * (c * nc + d) + 1];
+      const float2 m = maps[(size_t)d * ny * nx + i];
+      re += lr * m.x - li * m.y;
+      im += lr * m.y + li * m.x;
+    }
+    out[(size_t)c * ny * nx + i] = make_float2((float)(sg * re), (float)(sg * im));
+  }
+}
+
+hipError_t launch_prep_maps_rowmajor(const float2* maps, const double* linv, float2* out, int nc,
+                                     int ny, int nx, int fold, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_maps_rowmajor, dim3((ny * nx + 255) / 256), dim3(256), 0, s, maps, linv,
+                     out, nc, ny, nx, fold);
+  return hipGetLastError();
+}
+
+// w[kx][ky] = mask[ky][kx] * scale (Cartesian 2-D weights, transposed)
+__global__ void k_mask_weights(const uint8_t* __restrict__ mask, float* __restrict__ w, int ny, int nx,
+                               float scale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ny * nx) return;
+  const int ky = i / nx, kx = i % nx;
+  w[(size_t)kx * ny + ky] = mask[i] ? scale : 0.f;
+}
+
+hipError_t launch_mask_weights(const uint8_t* mask, float* w, int ny, int nx, float scale,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_weights, dim3((ny * nx + 255) / 256), dim3(256), 0, s, mask, w, ny, nx,
+                     scale);
+  return hipGetLastError();
+}
+
+__global__ void k_power_start_rowmajor(float2* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = cscale(draw_probe(0, 0, (uint32_t)i, 3u, 0), rsqrtf((float)n));
+}
+
+hipError_t launch_power_start_rowmajor(float2* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_start_rowmajor, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace pico

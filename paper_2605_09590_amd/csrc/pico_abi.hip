@@ -4,6 +4,11 @@
 // batched-CG workspace) and sequences the kernels of one probe tile:
 //   probe tile -> K independent CG solves (App. A, Algorithm 1, covariance
 //   step) -> FP64 accumulation of conj(v) . u.
+// Two operator layouts share the driver:
+//   separable Cartesian (phase-encode mask): one fused column kernel per
+//     normal-operator application, per-probe fields column-major [K][nx][ny];
+//   2-D grid (Cartesian 2-D mask, non-Cartesian Toeplitz): three kernels per
+//     application, per-probe fields row-major [K][ny][nx].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,15 +46,22 @@ struct pico_op_s {
   int ny = 0, nx = 0, nc = 0, sampling = 0, recon = 0;
   int cg_iters = 0, K = 0;
   double cg_tol = 0.0, lam_rel = 0.0, lam_abs = 0.0;
+  bool colmajor = true;       // separable Cartesian layout
+  int Gy = 0, Gx = 0;         // 2-D grid size
+  int nblk = 0;               // partial-dot blocks per probe (nx or ny)
   hipStream_t last_stream = nullptr;
   // resident operator
-  float2* maps = nullptr;   // [nx][nc][ny]
-  float* maskw = nullptr;   // [ny]
-  float2* twt = nullptr;    // [ny]
-  // batched CG workspace, [K][nx][ny] each
+  float2* maps = nullptr;     // whitened maps (layout per path)
+  float* maskw = nullptr;     // separable path: [ny] mask[k] / ny
+  float2* twt = nullptr;      // separable path: [ny] twiddles
+  float* w = nullptr;         // grid path: [Gx][Gy] real weights
+  float2* twx = nullptr;      // grid path: [Gx] twiddles
+  float2* twy = nullptr;      // grid path: [Gy] twiddles
+  float2* T = nullptr;        // grid path: [K][nc][ny][Gx]
+  // batched CG workspace, K images each
   float2 *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
-  double* partA = nullptr;  // [K][nx][4] partial dots per image column
-  double* mon = nullptr;    // [512] convergence-monitor partials
+  double* part = nullptr;     // [K][nblk][4] partial dots
+  double* mon = nullptr;      // [512] convergence-monitor partials
   double *alpha = nullptr, *beta = nullptr, *rr = nullptr, *rr0 = nullptr;
   int* state = nullptr;
   std::vector<void*> allocs;
@@ -81,6 +93,14 @@ struct pico_op_s {
     }
     return e;
   }
+  void release(void* ptr) {
+    auto it = std::find(allocs.begin(), allocs.end(), ptr);
+    if (it != allocs.end()) {
+      (void)hipFree(ptr);
+      allocs.erase(it);
+    }
+  }
+  size_t image() const { return (size_t)ny * nx; }
 };
 
 namespace {
@@ -128,6 +148,15 @@ bool cholesky_inverse(const double* psi, int n, std::vector<double>& linv_out, s
   return true;
 }
 
+std::vector<float2> twiddle_table(int n) {
+  std::vector<float2> tw(n);
+  for (int m = 0; m < n; ++m) {
+    const double ang = -2.0 * 3.14159265358979323846 * (double)m / (double)n;
+    tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  return tw;
+}
+
 pico_status_t check_op(pico_op_t op) {
   if (!op) return fail(PICO_EINVAL, "NULL operator handle");
   return PICO_OK;
@@ -147,32 +176,77 @@ hipError_t timed(pico_op_t op, int kind, hipStream_t s, F&& launch) {
   return hipSuccess;
 }
 
-pico::Cart1dArgs base_args(pico_op_t op, int K) {
-  pico::Cart1dArgs a{};
-  a.ny = op->ny;
-  a.nx = op->nx;
-  a.nc = op->nc;
-  a.K = K;
-  a.maps = op->maps;
-  a.maskw = op->maskw;
-  a.twt = op->twt;
-  a.x = op->x;
-  a.r = op->r;
-  a.p = op->p;
-  a.q = op->q;
-  a.alpha = op->alpha;
-  a.beta = op->beta;
-  a.part = op->partA;
-  a.lam = (float)op->lam_abs;
-  a.scale = 1.0f;
-  return a;
+// One application of the normal operator to K probes.
+struct NormalCall {
+  uint64_t seed = 0, first = 0;
+  int dist = 0;
+  const float2* src = nullptr;  // C1_APPLY input
+  float2* dst = nullptr;        // C1_APPLY output (default q)
+  float lam = 0.0f;
+  float scale = 1.0f;
+  int x_zero = 0;
+};
+
+hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hipStream_t s) {
+  if (op->colmajor) {
+    pico::Cart1dArgs a{};
+    a.ny = op->ny;
+    a.nx = op->nx;
+    a.nc = op->nc;
+    a.K = K;
+    a.maps = op->maps;
+    a.maskw = op->maskw;
+    a.twt = op->twt;
+    a.src = c.src;
+    a.x = op->x;
+    a.r = op->r;
+    a.p = op->p;
+    a.q = c.dst ? c.dst : op->q;
+    a.alpha = op->alpha;
+    a.beta = op->beta;
+    a.x_zero = c.x_zero;
+    a.part = op->part;
+    a.lam = c.lam;
+    a.scale = c.scale;
+    a.seed = c.seed;
+    a.first = c.first;
+    a.dist = c.dist;
+    return pico::launch_cart1d(mode, a, s);
+  }
+  pico::Grid2dArgs g{};
+  g.ny = op->ny;
+  g.nx = op->nx;
+  g.nc = op->nc;
+  g.K = K;
+  g.Gy = op->Gy;
+  g.Gx = op->Gx;
+  g.maps = op->maps;
+  g.w = op->w;
+  g.twx = op->twx;
+  g.twy = op->twy;
+  g.T = op->T;
+  g.src = c.src;
+  g.x = op->x;
+  g.r = op->r;
+  g.p = op->p;
+  g.q = c.dst ? c.dst : op->q;
+  g.alpha = op->alpha;
+  g.beta = op->beta;
+  g.x_zero = c.x_zero;
+  g.part = op->part;
+  g.lam = c.lam;
+  g.scale = c.scale;
+  g.seed = c.seed;
+  g.first = c.first;
+  g.dist = c.dist;
+  return pico::launch_grid_normal(mode, g, s);
 }
 
 hipError_t scalars(pico_op_t op, int K, bool first, hipStream_t s) {
   pico::ScalarArgs sa{};
   sa.K = K;
-  sa.part = op->partA;
-  sa.nblk = op->nx;
+  sa.part = op->part;
+  sa.nblk = op->nblk;
   sa.alpha = op->alpha;
   sa.beta = op->beta;
   sa.rr = op->rr;
@@ -184,26 +258,27 @@ hipError_t scalars(pico_op_t op, int K, bool first, hipStream_t s) {
 }
 
 // One batched CG solve of (M + lam) x = b for K right-hand sides, x0 = 0.
-// Iteration i's vector update is fused into the kernel that applies the
+// Iteration i's vector update is fused into the kernels that apply the
 // normal operator for iteration i + 1; the last one runs on its own.  The
 // first normal-operator application uses ``first_mode`` (probe draw or the
 // right-hand side already in r); the solution ends in op->x.
 hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t first, int dist,
                     hipStream_t s) {
-  pico::Cart1dArgs a = base_args(op, K);
-  a.seed = seed;
-  a.first = first;
-  a.dist = dist;
-  hipError_t e = timed(op, PICO_PROF_NORMAL_FIRST, s, [&] { return pico::launch_cart1d(first_mode, a, s); });
+  NormalCall c;
+  c.seed = seed;
+  c.first = first;
+  c.dist = dist;
+  c.lam = (float)op->lam_abs;
+  hipError_t e = timed(op, PICO_PROF_NORMAL_FIRST, s, [&] { return launch_normal(op, K, first_mode, c, s); });
   if (e != hipSuccess) return e;
   if ((e = scalars(op, K, true, s)) != hipSuccess) return e;
   for (int it = 1; it < op->cg_iters; ++it) {
-    a.x_zero = (it == 1);
-    if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return pico::launch_cart1d(pico::C1_ITER, a, s); })) != hipSuccess) return e;
+    c.x_zero = (it == 1);
+    if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return launch_normal(op, K, pico::C1_ITER, c, s); })) != hipSuccess) return e;
     if ((e = scalars(op, K, false, s)) != hipSuccess) return e;
   }
   pico::FinalArgs f{};
-  f.n = op->ny * op->nx;
+  f.n = (int)op->image();
   f.K = K;
   f.x = op->x;
   f.p = op->p;
@@ -218,12 +293,31 @@ hipError_t apply_sigma(pico_op_t op, int K, int first_mode, uint64_t seed, uint6
                        hipStream_t s) {
   hipError_t e = cg_solve(op, K, first_mode, seed, first, dist, s);
   if (e != hipSuccess || op->lam_abs == 0.0) return e;
-  pico::Cart1dArgs a = base_args(op, K);
-  a.src = op->x;
-  a.q = op->r;     // t = M w lands in r, the next right-hand side
-  a.lam = 0.0f;
-  if ((e = timed(op, PICO_PROF_OTHER, s, [&] { return pico::launch_cart1d(pico::C1_APPLY, a, s); })) != hipSuccess) return e;
+  NormalCall c;
+  c.src = op->x;
+  c.dst = op->r;   // t = M w lands in r, the next right-hand side
+  c.lam = 0.0f;
+  if ((e = timed(op, PICO_PROF_OTHER, s, [&] { return launch_normal(op, K, pico::C1_APPLY, c, s); })) != hipSuccess) return e;
   return cg_solve(op, K, pico::C1_FIRST_BUF, 0, 0, 0, s);
+}
+
+hipError_t accumulate(pico_op_t op, int K, const pico_accum_t* acc, uint64_t seed, uint64_t first,
+                      int dist, int pmr, hipStream_t s) {
+  pico::AccumArgs aa{};
+  aa.ny = op->ny;
+  aa.nx = op->nx;
+  aa.K = K;
+  aa.x = op->x;
+  aa.sum = acc->sum;
+  aa.sum_im = acc->sum_im;
+  aa.sumsq = acc->sumsq;
+  aa.seed = seed;
+  aa.first = first;
+  aa.dist = dist;
+  aa.pmr = pmr;
+  return timed(op, PICO_PROF_ACCUM, s, [&] {
+    return op->colmajor ? pico::launch_accum_colmajor(aa, s) : pico::launch_accum_rowmajor(aa, s);
+  });
 }
 
 struct StatAcc {
@@ -260,6 +354,38 @@ pico_status_t write_stats(pico_op_t op, const StatAcc& sa, pico_stats_t* st) {
   return PICO_OK;
 }
 
+pico_status_t validate(const pico_op_desc_t* d) {
+  if (d->recon != PICO_CGSENSE) return fail(PICO_EUNSUPPORTED, "only CG-SENSE reconstructions are built");
+  if (d->sampling != PICO_CART_1D && d->sampling != PICO_CART_2D && d->sampling != PICO_NONCART)
+    return fail(PICO_EUNSUPPORTED, "unknown sampling kind");
+  if (d->ncoils < 1 || d->ncoils > 64) return fail(PICO_EINVAL, "ncoils must be in 1..64");
+  if (d->nx < 2 || d->ny < 2 || (d->ny & 1) || (d->nx & 1)) return fail(PICO_EINVAL, "ny and nx must be even and >= 2");
+  if ((int64_t)d->ny * d->nx >= (int64_t)1 << 31) return fail(PICO_EINVAL, "image too large");
+  if (d->sampling == PICO_CART_1D) {
+    if (!pico::cart1d_supported(d->ny))
+      return fail(PICO_EINVAL, "ny=" + std::to_string(d->ny) +
+                                   " has no built column FFT (64 96 128 160 192 256 288 320 384 512)");
+  } else {
+    const int f = d->sampling == PICO_NONCART ? 2 : 1;
+    if (!pico::grid_line_supported(f * d->ny) || !pico::grid_line_supported(f * d->nx))
+      return fail(PICO_EINVAL, "grid " + std::to_string(f * d->ny) + "x" + std::to_string(f * d->nx) +
+                                   " has no built FFT length (64 96 128 160 192 256 288 320 384 512 576 640 768)");
+    if (pico::grid_cols_lds_bytes(f * d->ny, d->ny) > 160 * 1024)
+      return fail(PICO_EINVAL, "column pass does not fit the 160 KiB LDS");
+  }
+  if (d->cg_iters < 1) return fail(PICO_EINVAL, "cg_iters must be >= 1");
+  if (d->probe_tile < 1 || d->probe_tile > 65535) return fail(PICO_EINVAL, "probe_tile must be in 1..65535");
+  if (!(d->lambda >= 0.0) || !std::isfinite(d->lambda)) return fail(PICO_EINVAL, "lambda must be finite and >= 0");
+  if (!(d->cg_tol >= 0.0)) return fail(PICO_EINVAL, "cg_tol must be >= 0");
+  if (!d->maps) return fail(PICO_EINVAL, "maps are required");
+  if (d->sampling != PICO_NONCART && !d->mask) return fail(PICO_EINVAL, "mask is required for Cartesian sampling");
+  if (d->sampling == PICO_NONCART && (!d->traj || d->nsamples < 1 || d->nsamples > ((int64_t)1 << 30)))
+    return fail(PICO_EINVAL, "traj and 1 <= nsamples <= 2^30 are required for non-Cartesian sampling");
+  if (d->lambda > 0.0 && (d->power_iters < 1 || !(d->power_margin > 0.0)))
+    return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
+  return PICO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -269,24 +395,8 @@ const char* pico_last_error(void) { return g_err.c_str(); }
 pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   if (!d || !out) return fail(PICO_EINVAL, "NULL descriptor or output handle");
   *out = nullptr;
+  if (pico_status_t st = validate(d)) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (d->recon != PICO_CGSENSE) return fail(PICO_EUNSUPPORTED, "only CG-SENSE reconstructions are built");
-  if (d->sampling != PICO_CART_1D)
-    return fail(PICO_EUNSUPPORTED, "only phase-encode (1-D) Cartesian sampling is built");
-  if (d->ncoils < 1 || d->ncoils > 64) return fail(PICO_EINVAL, "ncoils must be in 1..64");
-  if (d->nx < 1 || d->ny < 2 || (d->ny & 1)) return fail(PICO_EINVAL, "ny must be even and nx >= 1");
-  if (!pico::cart1d_supported(d->ny))
-    return fail(PICO_EINVAL, "ny=" + std::to_string(d->ny) +
-                                 " has no built FFT plan (64 96 128 160 192 256 288 320 384 512)");
-  if ((int64_t)d->ny * d->nx >= (int64_t)1 << 31) return fail(PICO_EINVAL, "image too large");
-  if (d->cg_iters < 1) return fail(PICO_EINVAL, "cg_iters must be >= 1");
-  if (d->probe_tile < 1 || d->probe_tile > 65535) return fail(PICO_EINVAL, "probe_tile must be in 1..65535");
-  if (!(d->lambda >= 0.0) || !std::isfinite(d->lambda)) return fail(PICO_EINVAL, "lambda must be finite and >= 0");
-  if (!(d->cg_tol >= 0.0)) return fail(PICO_EINVAL, "cg_tol must be >= 0");
-  if (!d->maps || !d->mask) return fail(PICO_EINVAL, "maps and mask are required");
-  if (d->lambda > 0.0 && (d->power_iters < 1 || !(d->power_margin > 0.0)))
-    return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
-
   const int nc = d->ncoils, ny = d->ny, nx = d->nx;
   std::vector<double> linv;
   if (d->psi) {
@@ -308,7 +418,14 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   op->lam_rel = d->lambda;
   op->K = d->probe_tile;
   op->last_stream = s;
-  const size_t n = (size_t)ny * nx;
+  op->colmajor = d->sampling == PICO_CART_1D;
+  op->nblk = op->colmajor ? nx : ny;
+  if (!op->colmajor) {
+    const int f = d->sampling == PICO_NONCART ? 2 : 1;
+    op->Gy = f * ny;
+    op->Gx = f * nx;
+  }
+  const size_t n = op->image();
   const int K = op->K;
 
   double* linv_d = nullptr;
@@ -320,13 +437,11 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
     return fail(PICO_EDEVICE, std::string(what) + ": " + hipGetErrorString(err));
   };
   if ((e = op->alloc(&op->maps, n * nc)) != hipSuccess) return bad(e, "maps");
-  if ((e = op->alloc(&op->maskw, ny)) != hipSuccess) return bad(e, "mask");
-  if ((e = op->alloc(&op->twt, ny)) != hipSuccess) return bad(e, "twiddles");
   if ((e = op->alloc(&op->x, n * K)) != hipSuccess) return bad(e, "workspace x");
   if ((e = op->alloc(&op->r, n * K)) != hipSuccess) return bad(e, "workspace r");
   if ((e = op->alloc(&op->p, n * K)) != hipSuccess) return bad(e, "workspace p");
   if ((e = op->alloc(&op->q, n * K)) != hipSuccess) return bad(e, "workspace q");
-  if ((e = op->alloc(&op->partA, (size_t)K * nx * 4)) != hipSuccess) return bad(e, "partials");
+  if ((e = op->alloc(&op->part, (size_t)K * op->nblk * 4)) != hipSuccess) return bad(e, "partials");
   if ((e = op->alloc(&op->mon, 512)) != hipSuccess) return bad(e, "monitor");
   if ((e = op->alloc(&op->alpha, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&op->beta, K)) != hipSuccess) return bad(e, "scalars");
@@ -334,57 +449,68 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   if ((e = op->alloc(&op->rr0, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&op->state, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&linv_d, linv.size())) != hipSuccess) return bad(e, "whitening");
-
-  // sampling weights: the centred DFT is (-1)^(ny/2) D F D with D = (-1)^y,
-  // so the centred-order mask applies unchanged to the plain FFT output;
-  // w[k] = mask[k] / ny carries the orthonormal scaling of F^H P F.
-  std::vector<uint8_t> mask_h(ny);
-  if ((e = hipMemcpyAsync(mask_h.data(), d->mask, ny, hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "mask copy");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "mask copy");
-  std::vector<float> w(ny);
-  for (int k = 0; k < ny; ++k) w[k] = mask_h[k] ? (float)(1.0 / ny) : 0.0f;
-  std::vector<float2> tw(ny);
-  for (int m = 0; m < ny; ++m) {
-    const double ang = -2.0 * 3.14159265358979323846 * (double)m / (double)ny;
-    tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-  }
-  if ((e = hipMemcpyAsync(op->maskw, w.data(), ny * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
-  if ((e = hipMemcpyAsync(op->twt, tw.data(), ny * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
   if ((e = hipMemcpyAsync(linv_d, linv.data(), linv.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
-  if ((e = pico::launch_prep_maps_cart1d((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, s)) != hipSuccess) return bad(e, "prep maps");
-  if ((e = hipMemsetAsync(op->state, 0, K * sizeof(int), s)) != hipSuccess) return bad(e, "memset");
+
+  if (op->colmajor) {
+    // sampling weights: the centred DFT is (-1)^(ny/2) D F D with D = (-1)^y,
+    // so the centred-order mask applies unchanged to the plain FFT output;
+    // w[k] = mask[k] / ny carries the orthonormal scaling of F^H P F.
+    if ((e = op->alloc(&op->maskw, ny)) != hipSuccess) return bad(e, "mask");
+    if ((e = op->alloc(&op->twt, ny)) != hipSuccess) return bad(e, "twiddles");
+    std::vector<uint8_t> mask_h(ny);
+    if ((e = hipMemcpyAsync(mask_h.data(), d->mask, ny, hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "mask copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "mask copy");
+    std::vector<float> w(ny);
+    for (int k = 0; k < ny; ++k) w[k] = mask_h[k] ? (float)(1.0 / ny) : 0.0f;
+    std::vector<float2> tw = twiddle_table(ny);
+    if ((e = hipMemcpyAsync(op->maskw, w.data(), ny * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+    if ((e = hipMemcpyAsync(op->twt, tw.data(), ny * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+    if ((e = pico::launch_prep_maps_cart1d((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, s)) != hipSuccess) return bad(e, "prep maps");
+  } else {
+    const int Gy = op->Gy, Gx = op->Gx;
+    if ((e = op->alloc(&op->w, (size_t)Gy * Gx)) != hipSuccess) return bad(e, "weights");
+    if ((e = op->alloc(&op->twx, Gx)) != hipSuccess) return bad(e, "twiddles");
+    if ((e = op->alloc(&op->twy, Gy)) != hipSuccess) return bad(e, "twiddles");
+    if ((e = op->alloc(&op->T, (size_t)K * nc * ny * Gx)) != hipSuccess) return bad(e, "grid workspace");
+    std::vector<float2> tx = twiddle_table(Gx), ty = twiddle_table(Gy);
+    if ((e = hipMemcpyAsync(op->twx, tx.data(), Gx * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+    if ((e = hipMemcpyAsync(op->twy, ty.data(), Gy * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+    const int fold = d->sampling == PICO_CART_2D;
+    if ((e = pico::launch_prep_maps_rowmajor((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, fold, s)) != hipSuccess) return bad(e, "prep maps");
+    if (d->sampling == PICO_CART_2D) {
+      if ((e = pico::launch_mask_weights(d->mask, op->w, ny, nx, (float)(1.0 / ((double)ny * nx)), s)) != hipSuccess) return bad(e, "weights");
+    } else {
+      if ((e = pico::build_toeplitz_weights(d->traj, d->nsamples, ny, nx, op->w, s)) != hipSuccess) return bad(e, "Toeplitz weights");
+    }
+  }
 
   // spectral normalisation (Sec. 3.2.1, 3.3): lambda_max of M by power steps
   if (d->lambda > 0.0) {
-    if ((e = pico::launch_power_start(op->p, ny, nx, s)) != hipSuccess) return bad(e, "power");
+    if ((e = op->colmajor ? pico::launch_power_start(op->p, ny, nx, s)
+                          : pico::launch_power_start_rowmajor(op->p, (int)n, s)) != hipSuccess) return bad(e, "power");
     double lam_hat = 0.0;
-    double scale = 1.0;
-    float2* src = op->p;
-    float2* dst = op->q;
+    float2* bufs[2] = {op->p, op->q};
+    NormalCall c;
+    c.lam = 0.0f;
+    std::vector<double> part((size_t)op->nblk * 4);
     for (int it = 0; it < d->power_iters; ++it) {
-      pico::Cart1dArgs a = base_args(op, 1);
-      a.src = src;
-      a.q = dst;
-      a.lam = 0.0f;
-      a.scale = (float)scale;
-      if ((e = pico::launch_cart1d(pico::C1_APPLY, a, s)) != hipSuccess) return bad(e, "power");
-      std::vector<double> part((size_t)nx * 4);
-      if ((e = hipMemcpyAsync(part.data(), op->partA, part.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "power");
+      c.src = bufs[it & 1];
+      c.dst = bufs[(it + 1) & 1];
+      if ((e = launch_normal(op, 1, pico::C1_APPLY, c, s)) != hipSuccess) return bad(e, "power");
+      if ((e = hipMemcpyAsync(part.data(), op->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "power");
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "power");
       double vq = 0.0, qq = 0.0;
-      for (int c = 0; c < nx; ++c) {
-        vq += part[4 * c + 1];
-        qq += part[4 * c + 2];
+      for (int b = 0; b < op->nblk; ++b) {
+        vq += part[4 * b + 1];
+        qq += part[4 * b + 2];
       }
       lam_hat = vq;              // Rayleigh quotient of the unit vector (scale * src)
-      scale = 1.0 / std::sqrt(qq);
-      std::swap(src, dst);
+      c.scale = (float)(1.0 / std::sqrt(qq));
     }
     op->lam_abs = d->lambda * d->power_margin * lam_hat;
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "init");
-  (void)hipFree(linv_d);
-  op->allocs.erase(std::remove(op->allocs.begin(), op->allocs.end(), (void*)linv_d), op->allocs.end());
+  op->release(linv_d);
   *out = op;
   return PICO_OK;
 }
@@ -397,9 +523,12 @@ pico_status_t pico_apply_cov(pico_op_t op, const void* v, void* u, int32_t k, vo
   if (k < 1 || k > op->K) return fail(PICO_EINVAL, "k must be in 1..probe_tile");
   hipStream_t s = (hipStream_t)stream;
   op->last_stream = s;
-  HIP_OR_RETURN(pico::launch_transpose_in((const float2*)v, op->r, k, op->ny, op->nx, s));
+  const size_t bytes = (size_t)k * op->image() * sizeof(float2);
+  if (op->colmajor) HIP_OR_RETURN(pico::launch_transpose_in((const float2*)v, op->r, k, op->ny, op->nx, s));
+  else HIP_OR_RETURN(hipMemcpyAsync(op->r, v, bytes, hipMemcpyDeviceToDevice, s));
   HIP_OR_RETURN(apply_sigma(op, k, pico::C1_FIRST_BUF, 0, 0, 0, s));
-  HIP_OR_RETURN(pico::launch_transpose_out(op->x, (float2*)u, k, op->ny, op->nx, s));
+  if (op->colmajor) HIP_OR_RETURN(pico::launch_transpose_out(op->x, (float2*)u, k, op->ny, op->nx, s));
+  else HIP_OR_RETURN(hipMemcpyAsync(u, op->x, bytes, hipMemcpyDeviceToDevice, s));
   return PICO_OK;
 }
 
@@ -416,19 +545,7 @@ pico_status_t pico_noise_map(pico_op_t op, uint64_t seed, int64_t first_probe, i
     const int K = (int)std::min<int64_t>(op->K, nprobes - done);
     const uint64_t first = (uint64_t)(first_probe + done);
     HIP_OR_RETURN(apply_sigma(op, K, pico::C1_FIRST_PROBE, seed, first, dist, s));
-    pico::AccumArgs aa{};
-    aa.ny = op->ny;
-    aa.nx = op->nx;
-    aa.K = K;
-    aa.x = op->x;
-    aa.sum = acc->sum;
-    aa.sum_im = acc->sum_im;
-    aa.sumsq = acc->sumsq;
-    aa.seed = seed;
-    aa.first = first;
-    aa.dist = dist;
-    aa.pmr = 0;
-    HIP_OR_RETURN(timed(op, PICO_PROF_ACCUM, s, [&] { return pico::launch_accum_colmajor(aa, s); }));
+    HIP_OR_RETURN(accumulate(op, K, acc, seed, first, dist, 0, s));
     if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));
     done += K;
   }
@@ -441,7 +558,7 @@ pico_status_t pico_finalize(pico_op_t op, const pico_accum_t* acc, double* var, 
   if (pico_status_t st = check_op(op)) return st;
   if (!acc || !acc->sum || !var) return fail(PICO_EINVAL, "NULL accumulator or output");
   if (acc->count < 1) return fail(PICO_EINVAL, "no probes accumulated");
-  HIP_OR_RETURN(pico::launch_finalize(acc->sum, var, (int64_t)op->ny * op->nx, 1.0 / (double)acc->count,
+  HIP_OR_RETURN(pico::launch_finalize(acc->sum, var, (int64_t)op->image(), 1.0 / (double)acc->count,
                                       (hipStream_t)stream));
   return PICO_OK;
 }
@@ -452,27 +569,19 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
   if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq)
     return fail(PICO_EINVAL, "PMR needs sum, sum_im and sumsq buffers");
   if (nrep < 0 || first < 0) return fail(PICO_EINVAL, "negative replica range");
+  if (!op->colmajor) return fail(PICO_EUNSUPPORTED, "PMR is built for phase-encode Cartesian sampling");
   hipStream_t s = (hipStream_t)stream;
   op->last_stream = s;
   StatAcc sa;
   for (int64_t done = 0; done < nrep;) {
     const int K = (int)std::min<int64_t>(op->K, nrep - done);
     const uint64_t f = (uint64_t)(first + done);
-    pico::Cart1dArgs a = base_args(op, K);
-    a.seed = seed;
-    a.first = f;
-    HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] { return pico::launch_cart1d(pico::C1_PMR_RHS, a, s); }));
+    NormalCall c;
+    c.seed = seed;
+    c.first = f;
+    HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] { return launch_normal(op, K, pico::C1_PMR_RHS, c, s); }));
     HIP_OR_RETURN(cg_solve(op, K, pico::C1_FIRST_BUF, 0, 0, 0, s));
-    pico::AccumArgs aa{};
-    aa.ny = op->ny;
-    aa.nx = op->nx;
-    aa.K = K;
-    aa.x = op->x;
-    aa.sum = acc->sum;
-    aa.sum_im = acc->sum_im;
-    aa.sumsq = acc->sumsq;
-    aa.pmr = 1;
-    HIP_OR_RETURN(timed(op, PICO_PROF_ACCUM, s, [&] { return pico::launch_accum_colmajor(aa, s); }));
+    HIP_OR_RETURN(accumulate(op, K, acc, 0, 0, 0, 1, s));
     if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));
     done += K;
   }
@@ -487,18 +596,18 @@ pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* v
     return fail(PICO_EINVAL, "NULL accumulator field or output");
   if (acc->count < 2) return fail(PICO_EINVAL, "need at least 2 replicas");
   HIP_OR_RETURN(pico::launch_pmr_finalize(acc->sum, acc->sum_im, acc->sumsq, var,
-                                          (int64_t)op->ny * op->nx, (double)acc->count,
+                                          (int64_t)op->image(), (double)acc->count,
                                           (hipStream_t)stream));
   return PICO_OK;
 }
 
 pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const double* ref_var,
-                                double* nrmse, void* stream) {
+                                 double* nrmse, void* stream) {
   if (pico_status_t st = check_op(op)) return st;
   if (!acc || !acc->sum || !ref_var || !nrmse) return fail(PICO_EINVAL, "NULL accumulator, reference or output");
   if (acc->count < 1) return fail(PICO_EINVAL, "no probes accumulated");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = (int64_t)op->ny * op->nx;
+  const int64_t n = (int64_t)op->image();
   const int nblk = (int)std::min<int64_t>(256, (n + 255) / 256);
   std::vector<double> part(2 * nblk);
   HIP_OR_RETURN(pico::launch_nrmse_partials(acc->sum, 1.0 / (double)acc->count, ref_var, n,
@@ -517,7 +626,7 @@ pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const do
 pico_status_t pico_exact_diag(pico_op_t op, double* var, void* stream) {
   if (pico_status_t st = check_op(op)) return st;
   if (!var) return fail(PICO_EINVAL, "NULL output");
-  if (op->sampling != PICO_CART_1D) return fail(PICO_EUNSUPPORTED, "exact diagonal needs a phase-encode mask");
+  if (!op->colmajor) return fail(PICO_EUNSUPPORTED, "exact diagonal needs a phase-encode mask");
   hipStream_t s = (hipStream_t)stream;
   for (int y0 = 0; y0 < op->ny; y0 += op->K) {
     const int k = std::min(op->K, op->ny - y0);

@@ -71,7 +71,40 @@ struct AccumArgs {
   int pmr;                     // 1: accumulate x itself (PMR); 0: conj(v) x (PICO)
 };
 
+// 2-D grid normal operator (Cartesian 2-D masks, Toeplitz non-Cartesian)
+struct Grid2dArgs {
+  int ny, nx, nc, K, Gy, Gx;
+  const float2* maps;          // [nc][ny][nx] whitened (and sign-folded for Cartesian)
+  const float* w;              // [Gx][Gy] real weights
+  const float2* twx;           // [Gx] W_Gx^m
+  const float2* twy;           // [Gy] W_Gy^m
+  float2* T;                   // [K][nc][ny][Gx] row-transformed planes
+  const float2* src;           // C1_APPLY input [K][ny][nx]
+  float2* x;                   // [K][ny][nx]
+  float2* r;
+  float2* p;
+  float2* q;
+  const double* alpha;
+  const double* beta;
+  int x_zero;
+  double* part;                // [K][ny][4]
+  float lam, scale;
+  uint64_t seed, first;
+  int dist;
+};
+
 bool cart1d_supported(int ny);
+bool grid_line_supported(int n);
+size_t grid_cols_lds_bytes(int Gy, int ny);
+hipError_t launch_grid_normal(int mode, const Grid2dArgs& a, hipStream_t s);
+hipError_t launch_accum_rowmajor(const AccumArgs& a, hipStream_t s);
+hipError_t launch_prep_maps_rowmajor(const float2* maps, const double* linv, float2* out, int nc,
+                                     int ny, int nx, int fold, hipStream_t s);
+hipError_t launch_mask_weights(const uint8_t* mask, float* w, int ny, int nx, float scale,
+                               hipStream_t s);
+hipError_t launch_power_start_rowmajor(float2* p, int n, hipStream_t s);
+hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, float* w,
+                                  hipStream_t s);
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
 hipError_t launch_final_x(const FinalArgs& a, hipStream_t s);
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);

@@ -1,0 +1,183 @@
+// Construction of the Toeplitz weights for a non-Cartesian trajectory, once
+// per operator, in float64:
+//   psf(d) = N_x^-1 sum_m exp(i w_m . d),  d in [-(ny-1), ny-1] x [-(nx-1), nx-1],
+// evaluated separably as a complex matrix product psf = E_y^T E_x with
+// E_y[m][j] = exp(i w_y,m (j - ny + 1)), E_x likewise (a dense contraction
+// over the M samples); circulant embedding in a 2ny x 2nx grid; its DFT by
+// two more products with DFT matrices; W = Re(DFT) / (4 ny nx), transposed.
+#include <hip/hip_runtime.h>
+
+#include "runtime.h"
+
+namespace pico {
+
+struct z64 { double x, y; };
+
+__global__ void k_exp_table(const float* __restrict__ traj, int comp, int d0, int D, int M,
+                            z64* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)M * D) return;
+  const int m = (int)(i / D), j = (int)(i % D);
+  const double w = (double)traj[2 * (size_t)m + comp];
+  double s, c;
+  sincos(w * (double)(d0 + j), &s, &c);
+  out[i] = {c, s};
+}
+
+// C[z][i][j] = sum_{kk in slice z} op(A)[i][kk] B[kk][j]; op(A) = A (A: [Mr][Kd]) or
+// A^T (A: [Kd][Mr]); B: [Kd][Nc]; row-major complex128; 32x32 tile per block.
+__global__ __launch_bounds__(256) void k_zgemm(const z64* __restrict__ A, const z64* __restrict__ B,
+                                               z64* __restrict__ C, int Mr, int Nc, int Kd,
+                                               int transA, int kslice) {
+  __shared__ z64 As[16][33];
+  __shared__ z64 Bs[16][33];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  const int kbeg = blockIdx.z * kslice, kend = min(Kd, kbeg + kslice);
+  double acc[2][2][2] = {};
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 32; e += 256) {
+      const int kk = e / 32, ii = e % 32;
+      const int gk = k0 + kk, gi = i0 + ii, gj = j0 + ii;
+      z64 av = {0.0, 0.0}, bv = {0.0, 0.0};
+      if (gk < kend && gi < Mr) av = transA ? A[(size_t)gk * Mr + gi] : A[(size_t)gi * Kd + gk];
+      if (gk < kend && gj < Nc) bv = B[(size_t)gk * Nc + gj];
+      As[kk][ii] = av;
+      Bs[kk][ii] = bv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const z64 x = As[kk][ty + 16 * a];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const z64 y = Bs[kk][tx + 16 * b];
+          acc[a][b][0] = fma(x.x, y.x, fma(-x.y, y.y, acc[a][b][0]));
+          acc[a][b][1] = fma(x.x, y.y, fma(x.y, y.x, acc[a][b][1]));
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int gi = i0 + ty + 16 * a, gj = j0 + tx + 16 * b;
+      if (gi < Mr && gj < Nc)
+        C[((size_t)blockIdx.z * Mr + gi) * Nc + gj] = {acc[a][b][0], acc[a][b][1]};
+    }
+}
+
+// sum over split-K slices in slice order, scaled
+__global__ void k_zsum_slices(const z64* __restrict__ parts, z64* __restrict__ out, long n, int S,
+                              double scale) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < S; ++z) {
+    re += parts[(size_t)z * n + i].x;
+    im += parts[(size_t)z * n + i].y;
+  }
+  out[i] = {re * scale, im * scale};
+}
+
+// k[dy mod Gy][dx mod Gx] = psf[dy + ny - 1][dx + nx - 1]; zero elsewhere
+__global__ void k_embed(const z64* __restrict__ psf, z64* __restrict__ kg, int ny, int nx, int Gy,
+                        int Gx) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)Gy * Gx) return;
+  const int ky = (int)(i / Gx), kx = (int)(i % Gx);
+  const int dy = ky < ny ? ky : ky - Gy;  // index ny maps to -ny: outside the PSF support
+  const int dx = kx < nx ? kx : kx - Gx;
+  z64 v = {0.0, 0.0};
+  if (dy > -ny && dy < ny && dx > -nx && dx < nx)
+    v = psf[(size_t)(dy + ny - 1) * (2 * nx - 1) + (dx + nx - 1)];
+  kg[i] = v;
+}
+
+// F[k][n] = exp(-2 pi i k n / G)
+__global__ void k_dft_matrix(z64* __restrict__ F, int G) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)G * G) return;
+  const long k = i / G, n = i % G;
+  double s, c;
+  sincospi(-2.0 * (double)((k * n) % G) / (double)G, &s, &c);
+  F[i] = {c, s};
+}
+
+// w[kx][ky] = Re(Kh[ky][kx]) * scale
+__global__ void k_real_weights(const z64* __restrict__ kh, float* __restrict__ w, int Gy, int Gx,
+                               double scale) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)Gy * Gx) return;
+  const int ky = (int)(i / Gx), kx = (int)(i % Gx);
+  w[(size_t)kx * Gy + ky] = (float)(kh[i].x * scale);
+}
+
+static hipError_t zgemm(const z64* A, const z64* B, z64* C, int Mr, int Nc, int Kd, int transA,
+                        int splits, hipStream_t s) {
+  const int kslice = ((Kd + splits - 1) / splits + 15) / 16 * 16;
+  const int S = (Kd + kslice - 1) / kslice;
+  dim3 grid((Nc + 31) / 32, (Mr + 31) / 32, S), block(256);
+  hipLaunchKernelGGL(k_zgemm, grid, block, 0, s, A, B, C, Mr, Nc, Kd, transA, kslice);
+  return hipGetLastError();
+}
+
+static int zgemm_slices(int Kd, int splits) {
+  const int kslice = ((Kd + splits - 1) / splits + 15) / 16 * 16;
+  return (Kd + kslice - 1) / kslice;
+}
+
+#define TZ_CHECK(x)                       \
+  do {                                    \
+    hipError_t e_ = (x);                  \
+    if (e_ != hipSuccess) { cleanup(); return e_; } \
+  } while (0)
+
+hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, float* w,
+                                  hipStream_t s) {
+  const int Dy = 2 * ny - 1, Dx = 2 * nx - 1, Gy = 2 * ny, Gx = 2 * nx;
+  const int splits = (int)std::min<long>(16, std::max<long>(1, M / 4096));
+  const int S = zgemm_slices((int)M, splits);
+  z64 *Ey = nullptr, *Ex = nullptr, *parts = nullptr, *psf = nullptr, *kg = nullptr, *Fy = nullptr,
+      *Fx = nullptr, *t1 = nullptr, *kh = nullptr;
+  auto cleanup = [&] {
+    for (z64* p : {Ey, Ex, parts, psf, kg, Fy, Fx, t1, kh}) (void)hipFree(p);
+  };
+  TZ_CHECK(hipMalloc(&Ey, sizeof(z64) * M * Dy));
+  TZ_CHECK(hipMalloc(&Ex, sizeof(z64) * M * Dx));
+  TZ_CHECK(hipMalloc(&parts, sizeof(z64) * (size_t)S * Dy * Dx));
+  TZ_CHECK(hipMalloc(&psf, sizeof(z64) * (size_t)Dy * Dx));
+  TZ_CHECK(hipMalloc(&kg, sizeof(z64) * (size_t)Gy * Gx));
+  TZ_CHECK(hipMalloc(&Fy, sizeof(z64) * (size_t)Gy * Gy));
+  TZ_CHECK(hipMalloc(&Fx, sizeof(z64) * (size_t)Gx * Gx));
+  TZ_CHECK(hipMalloc(&t1, sizeof(z64) * (size_t)Gy * Gx));
+  TZ_CHECK(hipMalloc(&kh, sizeof(z64) * (size_t)Gy * Gx));
+  hipLaunchKernelGGL(k_exp_table, dim3((unsigned)((M * Dy + 255) / 256)), dim3(256), 0, s, traj, 0,
+                     -(ny - 1), Dy, (int)M, Ey);
+  hipLaunchKernelGGL(k_exp_table, dim3((unsigned)((M * Dx + 255) / 256)), dim3(256), 0, s, traj, 1,
+                     -(nx - 1), Dx, (int)M, Ex);
+  TZ_CHECK(hipGetLastError());
+  TZ_CHECK(zgemm(Ey, Ex, parts, Dy, Dx, (int)M, 1, splits, s));
+  const long npsf = (long)Dy * Dx;
+  hipLaunchKernelGGL(k_zsum_slices, dim3((unsigned)((npsf + 255) / 256)), dim3(256), 0, s, parts, psf,
+                     npsf, S, 1.0 / ((double)ny * nx));
+  const long ng = (long)Gy * Gx;
+  hipLaunchKernelGGL(k_embed, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, psf, kg, ny, nx, Gy, Gx);
+  hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)(((long)Gy * Gy + 255) / 256)), dim3(256), 0, s, Fy, Gy);
+  hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)(((long)Gx * Gx + 255) / 256)), dim3(256), 0, s, Fx, Gx);
+  TZ_CHECK(hipGetLastError());
+  TZ_CHECK(zgemm(Fy, kg, t1, Gy, Gx, Gy, 0, 1, s));
+  TZ_CHECK(zgemm(t1, Fx, kh, Gy, Gx, Gx, 0, 1, s));
+  hipLaunchKernelGGL(k_real_weights, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, kh, w, Gy, Gx,
+                     1.0 / ((double)Gy * Gx));
+  TZ_CHECK(hipGetLastError());
+  TZ_CHECK(hipStreamSynchronize(s));
+  cleanup();
+  return hipSuccess;
+}
+
+}  // namespace pico

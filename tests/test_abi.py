@@ -56,7 +56,8 @@ def _desc(p, **kw):
 @pytest.mark.parametrize("kw,status", [
     ({"ny": 63}, 1), ({"ny": 100}, 1), ({"ncoils": 0}, 1), ({"ncoils": 65}, 1),
     ({"cg_iters": 0}, 1), ({"probe_tile": 0}, 1), ({"lambda_": -1.0}, 1),
-    ({"maps": None}, 1), ({"recon": 7}, 4), ({"sampling": 2}, 4),
+    ({"maps": None}, 1), ({"recon": 7}, 4), ({"sampling": 2}, 1), ({"sampling": 9}, 4),
+    ({"sampling": 1, "nx": 100}, 1),
     ({"lambda_": 0.1, "power_iters": 0}, 1),
 ])
 def test_init_rejects_bad_descriptors(lib, kw, status):

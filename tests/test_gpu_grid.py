@@ -1,0 +1,176 @@
+"""GPU parity of the 2-D grid path (Cartesian 2-D masks and the spiral
+Toeplitz operator) against the FP64 oracle on the same seeded probes.
+
+The GPU receives the trajectory in float32; the oracle is fed the same
+float32-rounded trajectory so that both sides define the same operator.
+Bar: relative 2-norm error <= 1e-4 (float32 storage).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import nufft as onufft
+from oracle import pico as opico
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2605_09590_amd import pico as lib
+    lib.load()
+    assert torch.cuda.is_available()
+    return lib
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _gpu_map(lib, h, n, seed, first, nprobes, stats=None):
+    acc_t = [torch.zeros(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    acc = lib.make_accum(*acc_t)
+    lib.pico_noise_map(h, seed, first, nprobes, 0, acc, stats)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in acc_t]
+
+
+def _spiral_problem(n=64, nc=4, R=2, inter=16, samples=512, seed=3, lam=0.1, cg=20):
+    rng = np.random.default_rng(seed)
+    maps = workloads.coil_maps(n, n, nc, rng)
+    psi = workloads.noise_cov(nc, rng)
+    traj = workloads.spiral_traj(n, R, inter, samples).astype(np.float32)
+    return maps, psi, traj, lam, cg
+
+
+def _init_noncart(lib, maps, psi, traj, lam, cg, tile):
+    n = maps.shape[1]
+    return lib.pico_init(n, n, _dev(maps.astype(np.complex64)), psi, None,
+                         sampling=lib.PICO_NONCART, lam=lam, cg_iters=cg, probe_tile=tile,
+                         traj=_dev(traj), nsamples=traj.shape[0])
+
+
+def test_cart2d_poisson_disc_parity(lib):
+    say("case: Cartesian 2-D Poisson-disc mask 96x64, 5 coils, 6 probes in tiles of 4, CG 20")
+    rng = np.random.default_rng(11)
+    maps = workloads.coil_maps(96, 64, 5, rng)
+    psi = workloads.noise_cov(5, rng)
+    mask = workloads.poisson_disc_mask(96, 64, 2.0, 12, seed=1)
+    h = lib.pico_init(96, 64, _dev(maps.astype(np.complex64)), psi, _dev(mask),
+                      sampling=lib.PICO_CART_2D, cg_iters=20, probe_tile=4)
+    st = lib.pico_stats_t()
+    s, si, ss = _gpu_map(lib, h, 96 * 64, 5, 2, 6, st)
+    lib.pico_destroy(h)
+    cov = opico.Covariance(opico.cartesian(maps, psi, mask), 0.0, 20)
+    ref = opico.noise_map(cov, 5, 2, 6)
+    err = _rel(s, ref["sum"].ravel())
+    say(f"  rel err {err:.2e}; CG relres max {st.max_relres:.2e}")
+    assert err < TOL
+    assert _rel(ss, ref["sumsq"].ravel()) < TOL
+
+
+def test_cart2d_tikhonov_apply_cov(lib):
+    say("case: Cartesian 2-D uniform 2x2 mask 64x64, lambda 0.05, apply_cov on 2 probes")
+    rng = np.random.default_rng(12)
+    maps = workloads.coil_maps(64, 64, 6, rng)
+    psi = workloads.noise_cov(6, rng)
+    mask = workloads.cart_mask_2d_uniform(64, 64, 2, 2)
+    h = lib.pico_init(64, 64, _dev(maps.astype(np.complex64)), psi, _dev(mask),
+                      sampling=lib.PICO_CART_2D, lam=0.05, cg_iters=25, probe_tile=2)
+    v = np.stack([opico.probe_image(3, i, (64, 64)) for i in range(2)])
+    vt = _dev(v.astype(np.complex64))
+    ut = torch.empty_like(vt)
+    lib.pico_apply_cov(h, vt, ut, 2)
+    torch.cuda.synchronize()
+    lam_abs = lib.pico_lambda_abs(h)
+    lib.pico_destroy(h)
+    cov = opico.Covariance(opico.cartesian(maps, psi, mask), 0.05, 25)
+    assert abs(lam_abs - cov.lam) < 1e-5 * cov.lam
+    u = ut.cpu().numpy()
+    for k in range(2):
+        err = _rel(u[k], cov.apply(v[k]))
+        say(f"  probe {k}: rel err {err:.2e}")
+        assert err < TOL
+
+
+def test_spiral_toeplitz_noise_map_parity(lib):
+    say("case: spiral Toeplitz 64x64, 4 coils, 16x512 R=2, lambda 0.1, 6 probes in tiles of 4")
+    maps, psi, traj, lam, cg = _spiral_problem()
+    h = _init_noncart(lib, maps, psi, traj, lam, cg, 4)
+    st = lib.pico_stats_t()
+    s, _, _ = _gpu_map(lib, h, 64 * 64, 9, 0, 6, st)
+    lam_abs = lib.pico_lambda_abs(h)
+    lib.pico_destroy(h)
+    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64))
+    cov = opico.Covariance(op, lam, cg)
+    say(f"  lambda_abs gpu {lam_abs:.8e} oracle {cov.lam:.8e}")
+    assert abs(lam_abs - cov.lam) < 1e-5 * cov.lam
+    ref = opico.noise_map(cov, 9, 0, 6)
+    err = _rel(s, ref["sum"].ravel())
+    say(f"  rel err {err:.2e}; CG relres max {st.max_relres:.2e}")
+    assert err < TOL
+
+
+def test_spiral_toeplitz_nonsquare_grid(lib):
+    # lambda > 0: a spiral samples a disc of k-space, so at lambda = 0 the
+    # normal operator is singular (its corners are in the null space)
+    say("case: spiral Toeplitz 48x80 (grid 96x160), 3 coils, lambda 0.05, apply_cov 3 probes")
+    rng = np.random.default_rng(5)
+    maps = workloads.coil_maps(48, 80, 3, rng)
+    psi = workloads.noise_cov(3, rng)
+    traj = workloads.spiral_traj(80, 1, 12, 600).astype(np.float32)
+    h = lib.pico_init(48, 80, _dev(maps.astype(np.complex64)), psi, None,
+                      sampling=lib.PICO_NONCART, lam=0.05, cg_iters=40, probe_tile=3,
+                      traj=_dev(traj), nsamples=traj.shape[0])
+    v = np.stack([opico.probe_image(1, i, (48, 80)) for i in range(3)])
+    vt = _dev(v.astype(np.complex64))
+    ut = torch.empty_like(vt)
+    lib.pico_apply_cov(h, vt, ut, 3)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64))
+    cov = opico.Covariance(op, 0.05, 40)
+    u = ut.cpu().numpy()
+    for k in range(3):
+        err = _rel(u[k], cov.apply(v[k]))
+        say(f"  probe {k}: rel err {err:.2e}")
+        assert err < TOL
+
+
+def test_spiral_full_size_sampled_probes(lib):
+    say("case: spiral 256x256, 16 coils, 48x4096 R=2 (98304 samples), lambda 0.1, CG 30, "
+        "K=256 right-hand sides in one launch; probes 0, 137, 255 checked")
+    prob = workloads.config(3, seed=0)
+    traj = prob.traj.astype(np.float32)
+    h = _init_noncart(lib, prob.maps, prob.psi, traj, prob.lam, prob.cg_iters, 256)
+    v = np.stack([opico.probe_image(42, i, (256, 256)) for i in range(256)]).astype(np.complex64)
+    vt = _dev(v)
+    ut = torch.empty_like(vt)
+    lib.pico_apply_cov(h, vt, ut, 256)
+    torch.cuda.synchronize()
+    lam_abs = lib.pico_lambda_abs(h)
+    lib.pico_destroy(h)
+    u = ut.cpu().numpy()
+    op = onufft.NonCartOp(prob.maps, prob.psi, traj.astype(np.float64))
+    cov = opico.Covariance(op, prob.lam, prob.cg_iters)
+    say(f"  lambda_abs gpu {lam_abs:.8e} oracle {cov.lam:.8e}")
+    for k in (0, 137, 255):
+        ref = cov.apply(v[k].astype(np.complex128))
+        err = _rel(u[k], ref)
+        say(f"  probe {k}: rel err {err:.2e}")
+        assert err < TOL
