@@ -1,0 +1,99 @@
+"""Pins of the oracle's wavelet transform, FISTA map and its Jacobian probes.
+
+  * db4 derived by spectral factorisation: unit DC gain sqrt(2), double-shift
+    orthonormality, 4 vanishing moments of the high-pass filter;
+    the 2-D transform is orthonormal (norm preserving, inverse = adjoint);
+    a constant image has no detail energy.
+  * Forward-mode Jacobian of the FISTA map vs central finite differences of
+    the map itself (the map is piecewise linear in b).
+  * lam = 0: FISTA is linear in b, so J w equals the map applied to w.
+  * lam = 0 and many iterations: E|J w|^2 over an exact probe enumeration
+    tends to diag(M^-1) (the least-squares covariance, Sec. 2.1 Eq. (9)).
+"""
+import itertools
+
+import numpy as np
+
+import workloads
+from oracle import cs, pico, sense, wavelet
+
+
+def test_db4_filter_properties():
+    h, g = wavelet.wavelet_filter(4)
+    assert h.size == 8
+    assert abs(h.sum() - np.sqrt(2)) < 1e-14
+    for m in range(4):
+        v = np.dot(h[: 8 - 2 * m], h[2 * m:])
+        assert abs(v - (1.0 if m == 0 else 0.0)) < 1e-14
+    k = np.arange(8)
+    for m in range(4):
+        assert abs(np.sum(g * k ** m)) < 1e-10
+    assert abs(np.sum(g * k ** 4)) > 1.0
+
+
+def test_wavelet_2d_orthonormal_and_constant_image():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((64, 48)) + 1j * rng.standard_normal((64, 48))
+    c = wavelet.wavedec2(x, 3)
+    assert abs(np.linalg.norm(c) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)
+    assert np.abs(wavelet.waverec2(c, 3) - x).max() < 1e-12
+    y = rng.standard_normal((64, 48))
+    assert abs(np.vdot(wavelet.wavedec2(y, 3), c) - np.vdot(y, x)) < 1e-10
+    cc = wavelet.wavedec2(np.full((32, 32), 2.0), 2)
+    m = wavelet.detail_mask((32, 32), 2)
+    assert np.abs(cc[m]).max() < 1e-12
+
+
+def _cs_problem(n=32, nc=2, seed=3, lam=2e-3, iters=12):
+    rng = np.random.default_rng(seed)
+    maps = workloads.coil_maps(n, n, nc, rng)
+    psi = workloads.noise_cov(nc, rng)
+    mask = workloads.poisson_disc_mask(n, n, 2.0, 6, seed=seed)
+    op = pico.cartesian(maps, psi, mask)
+    x = workloads.phantom(n, rng)
+    b = op.forward(x)
+    b = b + 0.01 * op.P[None] * (rng.standard_normal(b.shape) + 1j * rng.standard_normal(b.shape))
+    return op, b, cs.FistaL1Wavelet(op, lam, iters, levels=2)
+
+
+def test_jvp_matches_central_differences():
+    op, b, f = _cs_problem()
+    _, coeffs = f.recon(b, store=True)
+    w = cs.kspace_probe(op, 4, 0)
+    jw = f.jvp(w, coeffs)
+    # small enough that no coefficient crosses the threshold kink
+    eps = 1e-9
+    fd = (f.recon(b + eps * w) - f.recon(b - eps * w)) / (2 * eps)
+    assert np.linalg.norm(jw - fd) < 1e-5 * np.linalg.norm(fd)
+    # and the soft-threshold derivative on its own
+    rng = np.random.default_rng(1)
+    c = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    dc = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    m = np.ones(500, bool)
+    num = (cs.soft(c + 1e-7 * dc, 0.8, m) - cs.soft(c - 1e-7 * dc, 0.8, m)) / 2e-7
+    assert np.abs(cs.dsoft(c, dc, 0.8, m) - num).max() < 1e-6
+
+
+def test_lambda_zero_is_linear():
+    op, b, f = _cs_problem(lam=0.0)
+    _, coeffs = f.recon(b, store=True)
+    w = cs.kspace_probe(op, 4, 1)
+    assert np.linalg.norm(f.jvp(w, coeffs) - f.recon(w)) < 1e-12 * np.linalg.norm(f.recon(w))
+
+
+def test_lambda_zero_long_run_gives_least_squares_variance():
+    # full Cartesian sampling of a 2-coil 4x2 system: for lam = 0 the FISTA map
+    # tends to M^-1 A^H, so diag(J J^H) (by unit k-space probes) -> diag(M^-1)
+    rng = np.random.default_rng(2)
+    maps = workloads.coil_maps(4, 2, 2, rng)
+    psi = workloads.noise_cov(2, rng)
+    op = pico.cartesian(maps, psi, np.ones(4, np.uint8))
+    f = cs.FistaL1Wavelet(op, 0.0, 300, levels=1)
+    _, coeffs = f.recon(np.zeros((2, 4, 2), np.complex128), store=True)
+    exact = np.real(np.diag(np.linalg.inv(op.dense_normal()))).reshape(4, 2)
+    JJ = np.zeros((4, 2))
+    for j in range(16):
+        e = np.zeros(16, np.complex128)
+        e[j] = 1.0
+        JJ += np.abs(f.jvp(e.reshape(2, 4, 2), coeffs)) ** 2
+    assert np.allclose(JJ, exact, rtol=1e-6)
