@@ -95,11 +95,19 @@ typedef struct {
   double power_margin;          /* safety factor on lambda_max (paper: 1.01)       */
   int32_t probe_tile;           /* probes solved together (K); sizes the workspace */
   int32_t recon;                /* pico_recon_t                                    */
+  /* PICO_CS_FISTA_L1WAV only (Sec. 2.2 CS extension, Sec. 3.2.3): */
+  const void* kdata;            /* device complex64 [ncoils][ny][nx] measured
+                                   k-space (un-whitened, centred order)            */
+  int32_t fista_iters;          /* FISTA iterations T (paper: 100)                 */
+  double cs_lambda;             /* L1 weight of the normalised problem            */
+  int32_t wavelet_levels;       /* db4 levels; ny, nx divisible by 2^levels       */
 } pico_op_desc_t;
 
 /* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a
  * host probe count that the library advances.  Zero them before the first
- * call.  sum_im and sumsq may be NULL. */
+ * call.  sum_im and sumsq may be NULL.  For a CS operator pico_noise_map
+ * accumulates sum |u|^2, sum Re u and sum |u|^4 with u = J w (k-space
+ * random-phase probes, Philox stream 2, element (c ny + ky) nx + kx). */
 typedef struct {
   double* sum;                  /* PICO: sum Re(conj v . u); PMR: sum Re x         */
   double* sum_im;               /* PICO: sum Im(conj v . u); PMR: sum Im x         */
@@ -130,6 +138,17 @@ pico_status_t pico_init(const pico_op_desc_t* desc, void* stream, pico_op_t* out
  * Errors: PICO_EINVAL (NULL, k out of range), PICO_ENOTCONV (a right-hand
  * side broke down; u still written), PICO_EDEVICE. */
 pico_status_t pico_apply_cov(pico_op_t op, const void* v, void* u, int32_t k, void* stream);
+
+/* u = J w for k whitened k-space probes w (device complex64 [k][ncoils][ny][nx],
+ * centred order; entries off the mask are ignored), J the Jacobian of the
+ * T-iteration FISTA reconstruction at the operator's data (Sec. 2.2, CS
+ * extension); u device complex64 [k][ny][nx].  Errors: PICO_EUNSUPPORTED on a
+ * CG-SENSE operator (use pico_apply_cov), PICO_EINVAL (NULL, k out of range). */
+pico_status_t pico_apply_jvp(pico_op_t op, const void* w, void* u, int32_t k, void* stream);
+
+/* The reconstruction itself, x (device complex64 [ny][nx]): the FISTA result
+ * at the operator's data for a CS operator.  PICO_EUNSUPPORTED otherwise. */
+pico_status_t pico_recon(pico_op_t op, void* x, void* stream);
 
 /* Add probes [first_probe, first_probe + nprobes) of the counter-based
  * probe sequence ``seed`` into ``acc`` (App. A, Algorithm 1).  Probe i,

@@ -1,0 +1,524 @@
+// Compressed-sensing reconstruction (FISTA with an L1 penalty on a 4-level
+// periodised db4 wavelet transform) and its forward-mode Jacobian probes.
+//
+// Primal, once per operator (step 1 of the normalised problem, Sec. 3.3):
+//   z_k = y_k - (M y_k - A^H b) / s^2,  c_k = Psi z_k (stored),
+//   x_k = Psi^H soft_lam(c_k),  y_{k+1} = x_k + theta_k (x_k - x_{k-1}).
+// Tangent for K probes w at once (Sec. 2.2, CS extension: u = J w):
+//   zd = yd - (M yd - A^H w) / s^2,  xd = Psi^H D_k(Psi zd),
+//   yd' = xd + theta_k (xd - xd_prev),  accumulate |xd_T|^2.
+// D_k is the derivative of complex soft-thresholding at the stored c_k:
+//   |c| > lam: d = dc - (lam/|c|) c^ j Im(conj(c^) dc), c^ = c/|c|;  else 0;
+//   lam = 0: identity.  Only detail coefficients are thresholded.
+//
+// Wavelet: orthonormal, periodised; analysis a[i] = sum_k h[k] x[(2i+k) mod n],
+// d[i] = sum_k g[k] x[(2i+k) mod n], g[k] = (-1)^k h[7-k], stored [a | d];
+// rows then columns of the current low-pass block per level.
+#include "device_common.h"
+#include "runtime.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace pico {
+
+// Daubechies' extremal-phase scaling filter with 4 vanishing moments
+// (8 taps; Daubechies, "Ten Lectures on Wavelets", Table 6.1, N = 4).
+#define PICO_DB4_TAPS                                                                     \
+  0.2303778133088964, 0.7148465705529154, 0.6308807679298587, -0.0279837694168599,      \
+      -0.1870348117190931, 0.0308413818355607, 0.0328830116668852, -0.0105974017850690
+__constant__ float c_h32[8] = {PICO_DB4_TAPS};
+__constant__ double c_h64[8] = {PICO_DB4_TAPS};
+
+template <class R> __device__ __forceinline__ R wav_h(int k);
+template <> __device__ __forceinline__ float wav_h<float>(int k) { return c_h32[k]; }
+template <> __device__ __forceinline__ double wav_h<double>(int k) { return c_h64[k]; }
+template <class R> __device__ __forceinline__ R wav_g(int k) {
+  return (k & 1) ? -wav_h<R>(7 - k) : wav_h<R>(7 - k);
+}
+
+// complex (float2 / double2) accumulate acc + s * v with a real tap s
+__device__ __forceinline__ double2 cfma(double2 acc, double s, double2 a) {
+  return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+template <class C> struct Real;
+template <> struct Real<float2> { using T = float; };
+template <> struct Real<double2> { using T = double; };
+template <class C> __device__ __forceinline__ C czero() { C z; z.x = 0; z.y = 0; return z; }
+
+// analysis along x of the block [by][bx] of each image
+template <class C>
+__global__ void k_dwt_x(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by, int bx) {
+  using R = typename Real<C>::T;
+  const int half = bx / 2;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)by * half) return;
+  const int y = (int)(t / half), i = (int)(t % half);
+  const size_t img = (size_t)blockIdx.y * ny * nx;
+  const C* row = in + img + (size_t)y * nx;
+  C a = czero<C>(), d = czero<C>();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const C v = row[(2 * i + k) % bx];
+    a = cfma(a, wav_h<R>(k), v);
+    d = cfma(d, wav_g<R>(k), v);
+  }
+  out[img + (size_t)y * nx + i] = a;
+  out[img + (size_t)y * nx + half + i] = d;
+}
+
+// analysis along y
+template <class C>
+__global__ void k_dwt_y(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by, int bx) {
+  using R = typename Real<C>::T;
+  const int half = by / 2;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)half * bx) return;
+  const int j = (int)(t / bx), x = (int)(t % bx);
+  const size_t img = (size_t)blockIdx.y * ny * nx;
+  C a = czero<C>(), d = czero<C>();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const C v = in[img + (size_t)((2 * j + k) % by) * nx + x];
+    a = cfma(a, wav_h<R>(k), v);
+    d = cfma(d, wav_g<R>(k), v);
+  }
+  out[img + (size_t)j * nx + x] = a;
+  out[img + (size_t)(half + j) * nx + x] = d;
+}
+
+// synthesis along y: x[m] = sum over taps k = m (mod 2) of h[k] a[n] + g[k] d[n],
+// n = ((m - k) / 2) mod (by / 2)
+template <class C>
+__global__ void k_idwt_y(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by, int bx) {
+  using R = typename Real<C>::T;
+  const int half = by / 2;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)by * bx) return;
+  const int m = (int)(t / bx), x = (int)(t % bx);
+  const size_t img = (size_t)blockIdx.y * ny * nx;
+  C acc = czero<C>();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 2 * kk + (m & 1);
+    int n = (m - k) / 2;            // m - k is even
+    n = ((n % half) + half) % half;
+    acc = cfma(acc, wav_h<R>(k), in[img + (size_t)n * nx + x]);
+    acc = cfma(acc, wav_g<R>(k), in[img + (size_t)(half + n) * nx + x]);
+  }
+  out[img + (size_t)m * nx + x] = acc;
+}
+
+// synthesis along x
+template <class C>
+__global__ void k_idwt_x(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by, int bx) {
+  using R = typename Real<C>::T;
+  const int half = bx / 2;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)by * bx) return;
+  const int y = (int)(t / bx), m = (int)(t % bx);
+  const size_t img = (size_t)blockIdx.y * ny * nx;
+  const C* row = in + img + (size_t)y * nx;
+  C acc = czero<C>();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 2 * kk + (m & 1);
+    int n = (m - k) / 2;
+    n = ((n % half) + half) % half;
+    acc = cfma(acc, wav_h<R>(k), row[n]);
+    acc = cfma(acc, wav_g<R>(k), row[half + n]);
+  }
+  out[img + (size_t)y * nx + m] = acc;
+}
+
+// Psi (forward) or Psi^H (inverse) of K images in place in buf, tmp as scratch
+template <class C>
+static hipError_t wavelet(C* buf, C* tmp, int K, int ny, int nx, int levels, bool inverse, hipStream_t s) {
+  auto grid_for = [&](long work) { return dim3((unsigned)((work + 255) / 256), K); };
+  if (!inverse) {
+    for (int l = 0; l < levels; ++l) {
+      const int by = ny >> l, bx = nx >> l;
+      hipLaunchKernelGGL(k_dwt_x<C>, grid_for((long)by * (bx / 2)), dim3(256), 0, s, buf, tmp, ny, nx, by, bx);
+      hipLaunchKernelGGL(k_dwt_y<C>, grid_for((long)(by / 2) * bx), dim3(256), 0, s, tmp, buf, ny, nx, by, bx);
+    }
+  } else {
+    for (int l = levels - 1; l >= 0; --l) {
+      const int by = ny >> l, bx = nx >> l;
+      hipLaunchKernelGGL(k_idwt_y<C>, grid_for((long)by * bx), dim3(256), 0, s, buf, tmp, ny, nx, by, bx);
+      hipLaunchKernelGGL(k_idwt_x<C>, grid_for((long)by * bx), dim3(256), 0, s, tmp, buf, ny, nx, by, bx);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wavelet(float2* buf, float2* tmp, int K, int ny, int nx, int levels, bool inverse,
+                          hipStream_t s) {
+  return wavelet(buf, tmp, K, ny, nx, levels, inverse, s);
+}
+
+static dim3 grid1(long n, int K = 1) { return dim3((unsigned)((n + 255) / 256), K); }
+
+__device__ __forceinline__ bool is_detail(long i, int nx, int ly, int lx) {
+  const int y = (int)(i / nx), x = (int)(i % nx);
+  return !(y < ly && x < lx);
+}
+
+// z = y - (q - g) * inv_s2 over K images; g has K images or one shared (gK = 0)
+__global__ void k_fista_grad(const float2* __restrict__ y, const float2* __restrict__ q,
+                             const float2* __restrict__ g, float2* __restrict__ z, long n, int gK,
+                             float inv_s2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= n) return;
+  const size_t o = (size_t)k * n + i;
+  const float2 gv = g[(gK ? (size_t)k * n : 0) + i];
+  z[o] = cfma(y[o], -inv_s2, csub(q[o], gv));
+}
+
+// dc <- D(c_k) dc for K tangent images sharing the stored FP64 c_k; the
+// active-set decision |c| > lam is taken in FP64
+__global__ void k_dsoft(float2* __restrict__ dc, const double2* __restrict__ ck, long n, int nx, int ly,
+                        int lx, double lam) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= n || lam == 0.0 || !is_detail(i, nx, ly, lx)) return;
+  const double2 c = ck[i];
+  const double a = sqrt(c.x * c.x + c.y * c.y);
+  const size_t o = (size_t)k * n + i;
+  if (!(a > lam)) {
+    dc[o] = make_float2(0.f, 0.f);
+    return;
+  }
+  const float chx = (float)(c.x / a), chy = (float)(c.y / a);
+  const float2 d = dc[o];
+  const float im = chx * d.y - chy * d.x;        // Im(conj(c^) d)
+  const float f = (float)(lam / a) * im;         // d - f * j * c^
+  dc[o] = make_float2(d.x + f * chy, d.y - f * chx);
+}
+
+// y = xn + theta (xn - xo); xo = xn   (K images)
+__global__ void k_momentum(const float2* __restrict__ xn, float2* __restrict__ xo, float2* __restrict__ y,
+                           long total, float theta) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const float2 a = xn[i], b = xo[i];
+  y[i] = cfma(a, theta, csub(a, b));
+  xo[i] = a;
+}
+
+// sum += |u|^2, sumsq += |u|^4 over the K tangent images, in probe order
+__global__ void k_accum_abs2(const float2* __restrict__ u, double* __restrict__ sum,
+                             double* __restrict__ sum_im, double* __restrict__ sumsq, int K, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0, si = 0.0, ss = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const float2 v = u[(size_t)k * n + i];
+    const double p = (double)v.x * v.x + (double)v.y * v.y;
+    s += p;
+    si += (double)v.x;
+    ss += p * p;
+  }
+  sum[i] += s;
+  if (sum_im) sum_im[i] += si;
+  if (sumsq) sumsq[i] += ss;
+}
+
+__global__ void k_fill_zero(float2* __restrict__ a, long total) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) a[i] = make_float2(0.f, 0.f);
+}
+
+
+hipError_t launch_fista_grad(const float2* y, const float2* q, const float2* g, float2* z, long n, int K,
+                             int gK, float inv_s2, hipStream_t s) {
+  hipLaunchKernelGGL(k_fista_grad, grid1(n, K), dim3(256), 0, s, y, q, g, z, n, gK, inv_s2);
+  return hipGetLastError();
+}
+
+hipError_t launch_dsoft(float2* dc, const double2* ck, long n, int K, int nx, int ly, int lx, double lam,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_dsoft, grid1(n, K), dim3(256), 0, s, dc, ck, n, nx, ly, lx, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_momentum(const float2* xn, float2* xo, float2* y, long total, float theta,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_momentum, grid1(total), dim3(256), 0, s, xn, xo, y, total, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum_abs2(const float2* u, double* sum, double* sum_im, double* sumsq, int K, long n,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_accum_abs2, grid1(n), dim3(256), 0, s, u, sum, sum_im, sumsq, K, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(float2* a, long total, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero, grid1(total), dim3(256), 0, s, a, total);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 linearisation point.  The Jacobian is evaluated at the reconstruction's
+// own trajectory, and the soft-threshold active sets (|c| > lam) decide the
+// tangent map; an FP32 trajectory flips coefficients lying within its rounding
+// of the threshold, so the primal (power method, FISTA, stored c_k) runs in
+// FP64, once per operator.  The normal operator uses the centred orthonormal
+// DFT as dense matrix products: F[k][n] = exp(-2 pi i (k - N/2)(n - N/2) / N) / sqrt(N),
+// symmetric, so A_c y = F_y (S_c y) F_x and A_c^H z = conj(F_y) z conj(F_x).
+
+__global__ void k_centred_dft64(double2* __restrict__ F, int N) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)N * N) return;
+  const long k = i / N - N / 2, m = i % N - N / 2;
+  long p = (k * m) % N;
+  if (p < 0) p += N;
+  double s, c;
+  sincospi(-2.0 * (double)p / (double)N, &s, &c);
+  const double r = 1.0 / sqrt((double)N);
+  F[i] = make_double2(c * r, s * r);
+}
+
+// S[c] = sum_{d <= c} Linv[c][d] maps[d]   (whitened coil maps, centred order)
+__global__ void k_prep_maps64(const float2* __restrict__ maps, const double* __restrict__ linv,
+                              double2* __restrict__ S, int nc, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < nc; ++c) {
+    double re = 0.0, im = 0.0;
+    for (int d = 0; d <= c; ++d) {
+      const double lr = linv[2 * (c * nc + d)], li = linv[2 * (c * nc + d) + 1];
+      const float2 m = maps[(size_t)d * n + i];
+      re += lr * m.x - li * m.y;
+      im += lr * m.y + li * m.x;
+    }
+    S[(size_t)c * n + i] = make_double2(re, im);
+  }
+}
+
+// U[c] = mask * sum_{d <= c} Linv[c][d] kdata[d]   (whitened, sampled k-space)
+__global__ void k_whiten64(const float2* __restrict__ kd, const double* __restrict__ linv,
+                           const uint8_t* __restrict__ mask, double2* __restrict__ U, int nc, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool on = mask[i] != 0;
+  for (int c = 0; c < nc; ++c) {
+    double re = 0.0, im = 0.0;
+    for (int d = 0; on && d <= c; ++d) {
+      const double lr = linv[2 * (c * nc + d)], li = linv[2 * (c * nc + d) + 1];
+      const float2 m = kd[(size_t)d * n + i];
+      re += lr * m.x - li * m.y;
+      im += lr * m.y + li * m.x;
+    }
+    U[(size_t)c * n + i] = make_double2(re, im);
+  }
+}
+
+__global__ void k_mul_maps64(const double2* __restrict__ y, const double2* __restrict__ S,
+                             double2* __restrict__ U, int nc, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = y[i];
+  for (int c = 0; c < nc; ++c) {
+    const double2 m = S[(size_t)c * n + i];
+    U[(size_t)c * n + i] = make_double2(m.x * v.x - m.y * v.y, m.x * v.y + m.y * v.x);
+  }
+}
+
+__global__ void k_mask64(double2* __restrict__ U, const uint8_t* __restrict__ mask, int nc, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || mask[i]) return;
+  for (int c = 0; c < nc; ++c) U[(size_t)c * n + i] = make_double2(0.0, 0.0);
+}
+
+// out = sum_c conj(S_c) U_c
+__global__ void k_combine64(const double2* __restrict__ U, const double2* __restrict__ S,
+                            double2* __restrict__ out, int nc, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const double2 m = S[(size_t)c * n + i], u = U[(size_t)c * n + i];
+    re += m.x * u.x + m.y * u.y;
+    im += m.x * u.y - m.y * u.x;
+  }
+  out[i] = make_double2(re, im);
+}
+
+// unit random-phase start of the power method (Philox stream 3, key 0, draw 0)
+__global__ void k_power_start64(double2* __restrict__ v, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const u32x4 w = philox4x32_10((uint32_t)i, 0u, 0u, 3u, 0u, 0u);
+  double s, c;
+  sincospi((double)(w.w0 >> 8) * 0x1p-23, &s, &c);   // 2 pi f, f = (w0 >> 8) / 2^24
+  const double r = 1.0 / sqrt((double)n);
+  v[i] = make_double2(c * r, s * r);
+}
+
+// per-block partials (Re v^H w, |w|^2), fixed reduction order
+__global__ __launch_bounds__(256) void k_dot64(const double2* __restrict__ v, const double2* __restrict__ w,
+                                               double* __restrict__ part, long n) {
+  __shared__ double sh[2][256];
+  double a = 0.0, b = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const double2 x = v[i], y = w[i];
+    a += x.x * y.x + x.y * y.y;
+    b += y.x * y.x + y.y * y.y;
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0];
+    part[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+__global__ void k_scale64(const double2* __restrict__ w, double2* __restrict__ v, long n, double sc) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = make_double2(w[i].x * sc, w[i].y * sc);
+}
+
+// z = y - (q - g) * inv_s2
+__global__ void k_grad64(const double2* __restrict__ y, const double2* __restrict__ q,
+                         const double2* __restrict__ g, double2* __restrict__ z, long n, double inv_s2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  z[i] = make_double2(y[i].x - (q[i].x - g[i].x) * inv_s2, y[i].y - (q[i].y - g[i].y) * inv_s2);
+}
+
+// c_k stored, then detail coefficients soft-thresholded in place
+__global__ void k_soft_store64(double2* __restrict__ c, double2* __restrict__ store, long n, int nx, int ly,
+                               int lx, double lam) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = c[i];
+  store[i] = v;
+  if (is_detail(i, nx, ly, lx)) {
+    const double a = sqrt(v.x * v.x + v.y * v.y);
+    const double sc = a > lam ? 1.0 - lam / a : 0.0;
+    c[i] = make_double2(v.x * sc, v.y * sc);
+  }
+}
+
+// y = xn + theta (xn - xo); xo = xn
+__global__ void k_momentum64(const double2* __restrict__ xn, double2* __restrict__ xo, double2* __restrict__ y,
+                             long n, double theta) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 a = xn[i], b = xo[i];
+  y[i] = make_double2(fma(theta, a.x - b.x, a.x), fma(theta, a.y - b.y, a.y));
+  xo[i] = a;
+}
+
+__global__ void k_to_f32(const double2* __restrict__ a, float2* __restrict__ b, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+__global__ void k_fill_zero64(double2* __restrict__ a, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = make_double2(0.0, 0.0);
+}
+
+#define CS_CHECK(x)            \
+  do {                         \
+    hipError_t e_ = (x);       \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream_t s) {
+  const long n = (long)o.ny * o.nx;
+  hipLaunchKernelGGL(k_centred_dft64, grid1((long)o.ny * o.ny), dim3(256), 0, s, o.Fy, o.ny);
+  hipLaunchKernelGGL(k_centred_dft64, grid1((long)o.nx * o.nx), dim3(256), 0, s, o.Fx, o.nx);
+  hipLaunchKernelGGL(k_prep_maps64, grid1(n), dim3(256), 0, s, maps, linv, o.S, o.nc, n);
+  return hipGetLastError();
+}
+
+// out = sum_c conj(S_c) A_c^H-part applied to the k-space held in o.U (overwritten)
+static hipError_t cs64_adjoint_u(const Cs64& o, double2* out, hipStream_t s) {
+  const long n = (long)o.ny * o.nx;
+  CS_CHECK(zgemm64(o.Fy, o.U, o.V, o.ny, o.nx, o.ny, 2, 1, s, o.nc, 0, n, n));     // conj(F_y) U_c
+  CS_CHECK(zgemm64(o.V, o.Fx, o.U, o.nc * o.ny, o.nx, o.nx, 4, 1, s));              // . conj(F_x)
+  hipLaunchKernelGGL(k_combine64, grid1(n), dim3(256), 0, s, o.U, o.S, out, o.nc, n);
+  return hipGetLastError();
+}
+
+hipError_t cs64_normal(const Cs64& o, const double2* y, double2* q, hipStream_t s) {
+  const long n = (long)o.ny * o.nx;
+  hipLaunchKernelGGL(k_mul_maps64, grid1(n), dim3(256), 0, s, y, o.S, o.U, o.nc, n);
+  CS_CHECK(zgemm64(o.U, o.Fx, o.V, o.nc * o.ny, o.nx, o.nx, 0, 1, s));              // (S_c y) F_x
+  CS_CHECK(zgemm64(o.Fy, o.V, o.U, o.ny, o.nx, o.ny, 0, 1, s, o.nc, 0, n, n));     // F_y .
+  hipLaunchKernelGGL(k_mask64, grid1(n), dim3(256), 0, s, o.U, o.mask, o.nc, n);
+  return cs64_adjoint_u(o, q, s);
+}
+
+hipError_t cs64_adjoint_kdata(const Cs64& o, const float2* kdata, const double* linv, double2* out,
+                              hipStream_t s) {
+  const long n = (long)o.ny * o.nx;
+  hipLaunchKernelGGL(k_whiten64, grid1(n), dim3(256), 0, s, kdata, linv, o.mask, o.U, o.nc, n);
+  return cs64_adjoint_u(o, out, s);
+}
+
+// lambda_max of M: power steps from the Philox start; Rayleigh quotient of the last step
+hipError_t cs64_power(const Cs64& o, int iters, double2* v, double2* w, double* part_d, double* out,
+                      hipStream_t s) {
+  const long n = (long)o.ny * o.nx;
+  const int nb = (int)std::min<long>((n + 255) / 256, CS64_DOT_BLOCKS);
+  std::vector<double> part(2 * (size_t)nb);
+  hipLaunchKernelGGL(k_power_start64, grid1(n), dim3(256), 0, s, v, n);
+  double lam = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    CS_CHECK(cs64_normal(o, v, w, s));
+    hipLaunchKernelGGL(k_dot64, dim3(nb), dim3(256), 0, s, v, w, part_d, n);
+    CS_CHECK(hipMemcpyAsync(part.data(), part_d, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    CS_CHECK(hipStreamSynchronize(s));
+    double vw = 0.0, ww = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      vw += part[2 * b];
+      ww += part[2 * b + 1];
+    }
+    lam = vw;
+    if (!(ww > 0.0)) break;
+    hipLaunchKernelGGL(k_scale64, grid1(n), dim3(256), 0, s, w, v, n, 1.0 / sqrt(ww));
+  }
+  *out = lam;
+  return hipGetLastError();
+}
+
+// T FISTA iterations at the measured data from x_0 = y_1 = 0; stores c_k = Psi z_k
+// (FP64, [T][ny][nx]) and leaves x_T in x.  Buffers: y, x, z, tmp, q of n each.
+hipError_t cs64_fista(const Cs64& o, const double2* atb, double s2, double lam, int T,
+                      const double* theta, double2* ctraj, double2* y, double2* x, double2* z,
+                      double2* tmp, double2* q, hipStream_t s) {
+  const long n = (long)o.ny * o.nx;
+  const int ly = o.ny >> o.levels, lx = o.nx >> o.levels;
+  hipLaunchKernelGGL(k_fill_zero64, grid1(n), dim3(256), 0, s, y, n);
+  hipLaunchKernelGGL(k_fill_zero64, grid1(n), dim3(256), 0, s, x, n);
+  for (int k = 1; k <= T; ++k) {
+    CS_CHECK(cs64_normal(o, y, q, s));
+    hipLaunchKernelGGL(k_grad64, grid1(n), dim3(256), 0, s, y, q, atb, z, n, 1.0 / s2);
+    CS_CHECK(wavelet(z, tmp, 1, o.ny, o.nx, o.levels, false, s));
+    hipLaunchKernelGGL(k_soft_store64, grid1(n), dim3(256), 0, s, z, ctraj + (size_t)(k - 1) * n, n, o.nx,
+                       ly, lx, lam);
+    CS_CHECK(wavelet(z, tmp, 1, o.ny, o.nx, o.levels, true, s));
+    hipLaunchKernelGGL(k_momentum64, grid1(n), dim3(256), 0, s, z, x, y, n, theta[k - 1]);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double2* a, float2* b, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, grid1(n), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+}  // namespace pico

@@ -342,6 +342,168 @@ hipError_t launch_grid_normal(int mode, const Grid2dArgs& a, hipStream_t s) {
   return with_line(a.Gx, [&](auto cf) { return rows_inv<decltype(cf)>(mode, a, s); });
 }
 
+// ---------------------------------------------------------------- standalone batched 2-D FFT
+// In-place unnormalised transform of B planes [B][ny][nx] (rows, then columns).
+template <class CF, bool INV>
+__global__ __launch_bounds__(64) void k_fft_lines(float2* data, long nlines, const float2* twt) {
+  constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
+  __shared__ float2 lds_all[NG * CF::SPAN];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const long line = (long)blockIdx.x * G + g;
+  const bool active = g < G && line < nlines;
+  float2* d = data + (size_t)(active ? line : 0) * CF::N;
+  typename CF::Tw tw;
+  CF::load_tw(tw, twt, lane);
+  float2 v[CF::VMAX];
+#pragma unroll
+  for (int m = 0; m < CF::VA; ++m) v[m] = CF::inA(lane) ? d[CF::posA(lane, m)] : make_float2(0.f, 0.f);
+  CF::template forward<INV>(v, lds_all + g * CF::SPAN, lane, tw);
+  if (active && CF::inB(lane)) {
+#pragma unroll
+    for (int r = 0; r < CF::VB; ++r) d[CF::posB(lane, r)] = v[r];
+  }
+}
+
+template <class CF, bool INV>
+__global__ __launch_bounds__(256) void k_fft_cols(float2* data, int ny, int nx, const float2* twt) {
+  constexpr int L = CF::L, NGRP = 256 / L;
+  constexpr int TS = NGRP + 1;
+  extern __shared__ float2 dyn[];
+  float2* tile = dyn;
+  float2* xch = dyn + (size_t)ny * TS;
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const int x0 = blockIdx.x * NGRP;
+  const size_t plane = (size_t)blockIdx.y * ny * nx;
+  const int ncol = min(NGRP, nx - x0);
+  for (int i = threadIdx.x; i < ny * NGRP; i += 256) {
+    const int yy = i / NGRP, j = i % NGRP;
+    tile[yy * TS + j] = j < ncol ? data[plane + (size_t)yy * nx + x0 + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const bool grp = g < NGRP && g < ncol;
+  typename CF::Tw tw;
+  CF::load_tw(tw, twt, lane);
+  float2 v[CF::VMAX];
+#pragma unroll
+  for (int m = 0; m < CF::VA; ++m)
+    v[m] = (grp && CF::inA(lane)) ? tile[CF::posA(lane, m) * TS + g] : make_float2(0.f, 0.f);
+  CF::template forward<INV>(v, xch + g * CF::SPAN, lane, tw);
+  __syncthreads();   // every group has read its column before rows are overwritten
+  if (grp && CF::inB(lane)) {
+#pragma unroll
+    for (int r = 0; r < CF::VB; ++r) tile[CF::posB(lane, r) * TS + g] = v[r];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ny * NGRP; i += 256) {
+    const int yy = i / NGRP, j = i % NGRP;
+    if (j < ncol) data[plane + (size_t)yy * nx + x0 + j] = tile[yy * TS + j];
+  }
+}
+
+template <class CF, bool INV>
+static hipError_t fft_cols(float2* data, long planes, int ny, int nx, const float2* twt, hipStream_t s) {
+  constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
+  const size_t lds = ((size_t)ny * (NGRP + 1) + (size_t)NG * CF::SPAN) * sizeof(float2);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_cols<CF, INV>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid((nx + NGRP - 1) / NGRP, (unsigned)planes), block(256);
+  hipLaunchKernelGGL((k_fft_cols<CF, INV>), grid, block, lds, s, data, ny, nx, twt);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse, const float2* twx,
+                        const float2* twy, hipStream_t s) {
+  const long nlines = planes * ny;
+  hipError_t e = with_line(nx, [&](auto cf) {
+    using CF = decltype(cf);
+    constexpr int G = 64 / CF::L;
+    dim3 grid((unsigned)((nlines + G - 1) / G)), block(64);
+    if (inverse) hipLaunchKernelGGL((k_fft_lines<CF, true>), grid, block, 0, s, data, nlines, twx);
+    else hipLaunchKernelGGL((k_fft_lines<CF, false>), grid, block, 0, s, data, nlines, twx);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  return with_line(ny, [&](auto cf) {
+    using CF = decltype(cf);
+    return inverse ? fft_cols<CF, true>(data, planes, ny, nx, twy, s)
+                   : fft_cols<CF, false>(data, planes, ny, nx, twy, s);
+  });
+}
+
+// ---------------------------------------------------------------- k-space inputs
+// out[b][c][ky][kx] = f(b, c, ky, kx) * mask[ky][kx] * (-1)^(ky+kx) * scale, where f
+// is the measured data whitened here (src and linv given, b = 0:
+// sum_d Linv[c][d] src[d]), caller k-space arrays already whitened (src only,
+// [B][nc][ny][nx]), or a Philox draw (counter element (c ny + ky) nx + kx, draw first + b, given stream and
+// family).  With scale = (-1)^((ny+nx)/2) / sqrt(ny nx), an unnormalised inverse
+// 2-D FFT and a combine with conj(S') give A^H of the k-space array, since the
+// centred orthonormal DFT is (-1)^((ny+nx)/2) D F D / sqrt(ny nx).
+__global__ void k_kspace_in(const float2* __restrict__ src, const double* __restrict__ linv,
+                            const uint8_t* __restrict__ mask, float2* __restrict__ out, int B, int nc,
+                            int ny, int nx, uint64_t seed, uint64_t first, uint32_t stream, int dist,
+                            float scale) {
+  const long n = (long)ny * nx;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n || b >= B) return;
+  const int ky = (int)(i / nx), kx = (int)(i % nx);
+  const float sg = ((ky + kx) & 1) ? -scale : scale;
+  for (int c = 0; c < nc; ++c) {
+    float2 v = make_float2(0.f, 0.f);
+    if (mask[i]) {
+      if (src && !linv) {
+        v = src[((size_t)b * nc + c) * n + i];   // already whitened, per-b arrays
+      } else if (src) {
+        double re = 0.0, im = 0.0;
+        for (int d = 0; d <= c; ++d) {
+          const double lr = linv[2 * (c * nc + d)], li = linv[2 * (c * nc + d) + 1];
+          const float2 m = src[(size_t)d * n + i];
+          re += lr * m.x - li * m.y;
+          im += lr * m.y + li * m.x;
+        }
+        v = make_float2((float)re, (float)im);
+      } else {
+        v = draw_probe(seed, first + b, (uint32_t)((size_t)c * n + i), stream, dist);
+      }
+    }
+    out[((size_t)b * nc + c) * n + i] = cscale(v, sg);
+  }
+}
+
+hipError_t launch_kspace_in(const float2* src, const double* linv, const uint8_t* mask, float2* out,
+                            int B, int nc, int ny, int nx, uint64_t seed, uint64_t first,
+                            uint32_t stream, int dist, float scale, hipStream_t s) {
+  const long n = (long)ny * nx;
+  dim3 grid((unsigned)((n + 255) / 256), B), block(256);
+  hipLaunchKernelGGL(k_kspace_in, grid, block, 0, s, src, linv, mask, out, B, nc, ny, nx, seed,
+                     first, stream, dist, scale);
+  return hipGetLastError();
+}
+
+// out[b][i] = sum_c conj(S'_c[i]) T[b][c][i]
+__global__ void k_coil_combine(const float2* __restrict__ T, const float2* __restrict__ maps,
+                               float2* __restrict__ out, int nc, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int c = 0; c < nc; ++c) acc = cadd(acc, cmulc(maps[(size_t)c * n + i], T[((size_t)b * nc + c) * n + i]));
+  out[(size_t)b * n + i] = acc;
+}
+
+hipError_t launch_coil_combine(const float2* T, const float2* maps, float2* out, int B, int nc,
+                               long n, hipStream_t s) {
+  dim3 grid((unsigned)((n + 255) / 256), B), block(256);
+  hipLaunchKernelGGL(k_coil_combine, grid, block, 0, s, T, maps, out, nc, n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- row-major accumulation
 __global__ void k_accum_rowmajor(AccumArgs a) {
   const int n = a.ny * a.nx;

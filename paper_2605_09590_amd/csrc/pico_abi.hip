@@ -64,6 +64,16 @@ struct pico_op_s {
   double* mon = nullptr;      // [512] convergence-monitor partials
   double *alpha = nullptr, *beta = nullptr, *rr = nullptr, *rr0 = nullptr;
   int* state = nullptr;
+  // compressed sensing (FISTA + L1 wavelet)
+  bool cs = false;
+  int fista_T = 0, levels = 0;
+  double cs_lam = 0.0;
+  double s2 = 0.0;              // 1.01 lambda_max(M)
+  std::vector<float> theta;     // FISTA momentum weights (tangents)
+  float2 *wA = nullptr, *wB = nullptr;  // wavelet buffers, K images
+  double2* ctraj = nullptr;     // [T][ny][nx] stored Psi z_k of the FP64 primal
+  float2* xrec = nullptr;       // reconstruction
+  uint8_t* mask_d = nullptr;    // [ny][nx] (Cartesian 2-D)
   std::vector<void*> allocs;
   // optional per-kernel-class timing with HIP events on the caller's stream
   bool prof_on = false;
@@ -354,8 +364,104 @@ pico_status_t write_stats(pico_op_t op, const StatAcc& sa, pico_stats_t* st) {
   return PICO_OK;
 }
 
+
+// lambda_max of M (Rayleigh quotient after power_iters steps from a fixed
+// Philox start vector; Sec. 3.2.1, 3.3)
+hipError_t power_lambda(pico_op_t op, int iters, double* out, hipStream_t s) {
+  hipError_t e = op->colmajor ? pico::launch_power_start(op->p, op->ny, op->nx, s)
+                              : pico::launch_power_start_rowmajor(op->p, (int)op->image(), s);
+  if (e != hipSuccess) return e;
+  double lam_hat = 0.0;
+  float2* bufs[2] = {op->p, op->q};
+  NormalCall c;
+  c.lam = 0.0f;
+  std::vector<double> part((size_t)op->nblk * 4);
+  for (int it = 0; it < iters; ++it) {
+    c.src = bufs[it & 1];
+    c.dst = bufs[(it + 1) & 1];
+    if ((e = launch_normal(op, 1, pico::C1_APPLY, c, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(part.data(), op->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    double vq = 0.0, qq = 0.0;
+    for (int b = 0; b < op->nblk; ++b) {
+      vq += part[4 * b + 1];
+      qq += part[4 * b + 2];
+    }
+    lam_hat = vq;              // Rayleigh quotient of the unit vector (scale * src)
+    c.scale = (float)(1.0 / std::sqrt(qq));
+  }
+  *out = lam_hat;
+  return hipSuccess;
+}
+
+// (-1)^((ny+nx)/2) / sqrt(ny nx): the centred orthonormal 2-D DFT's adjoint as an
+// unnormalised inverse FFT between (-1)^(ky+kx) and (-1)^(y+x) sign flips
+float kspace_scale(pico_op_t op) {
+  const float sg = (((op->ny + op->nx) / 2) & 1) ? -1.0f : 1.0f;
+  return sg / std::sqrt((float)op->image());
+}
+
+// out[K][ny][nx] = A^H of K k-space arrays (Cartesian 2-D grid operator): the
+// arrays come from src (whitened with linv when given) or Philox draws
+hipError_t adjoint_kspace(pico_op_t op, int K, const float2* src, const double* linv, uint64_t seed,
+                          uint64_t first, uint32_t stream, int dist, float2* out, hipStream_t s) {
+  hipError_t e = pico::launch_kspace_in(src, linv, op->mask_d, op->T, K, op->nc, op->ny, op->nx, seed,
+                                        first, stream, dist, kspace_scale(op), s);
+  if (e != hipSuccess) return e;
+  if ((e = pico::launch_fft2d(op->T, (long)K * op->nc, op->ny, op->nx, true, op->twx, op->twy, s)) != hipSuccess) return e;
+  return pico::launch_coil_combine(op->T, op->maps, out, K, op->nc, (long)op->image(), s);
+}
+
+// Tangents of the T FISTA iterations for K probes at once: the gradient offset
+// is A^H w (in op->r, per probe), the soft-threshold derivative is taken at
+// the stored FP64 c_k.  The tangent of x_T ends in op->x.
+hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
+  const long n = (long)op->image();
+  const int ly = op->ny >> op->levels, lx = op->nx >> op->levels;
+  hipError_t e;
+  if ((e = pico::launch_fill_zero(op->p, K * n, s)) != hipSuccess) return e;
+  if ((e = pico::launch_fill_zero(op->x, K * n, s)) != hipSuccess) return e;
+  NormalCall c;
+  c.src = op->p;
+  c.dst = op->q;
+  c.lam = 0.0f;
+  const float inv_s2 = (float)(1.0 / op->s2);
+  for (int k = 1; k <= op->fista_T; ++k) {
+    if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return launch_normal(op, K, pico::C1_APPLY, c, s); })) != hipSuccess) return e;
+    if ((e = pico::launch_fista_grad(op->p, op->q, op->r, op->wA, n, K, 1, inv_s2, s)) != hipSuccess) return e;
+    if ((e = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, false, s)) != hipSuccess) return e;
+    const double2* ck = op->ctraj + (size_t)(k - 1) * n;
+    if ((e = pico::launch_dsoft(op->wA, ck, n, K, op->nx, ly, lx, op->cs_lam, s)) != hipSuccess) return e;
+    if ((e = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, true, s)) != hipSuccess) return e;
+    if ((e = pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// K tangents u = J w: probes drawn (src == nullptr: Philox stream 2) or given
+hipError_t cs_tangents(pico_op_t op, int K, const float2* w, uint64_t seed, uint64_t first, int dist,
+                       hipStream_t s) {
+  hipError_t e = timed(op, PICO_PROF_NORMAL_FIRST, s, [&] {
+    return adjoint_kspace(op, K, w, nullptr, seed, first, 2u, dist, op->r, s);
+  });
+  if (e != hipSuccess) return e;
+  return fista_tangent(op, K, s);
+}
+
 pico_status_t validate(const pico_op_desc_t* d) {
-  if (d->recon != PICO_CGSENSE) return fail(PICO_EUNSUPPORTED, "only CG-SENSE reconstructions are built");
+  if (d->recon != PICO_CGSENSE && d->recon != PICO_CS_FISTA_L1WAV)
+    return fail(PICO_EUNSUPPORTED, "unknown reconstruction kind");
+  if (d->recon == PICO_CS_FISTA_L1WAV) {
+    if (d->sampling != PICO_CART_2D)
+      return fail(PICO_EUNSUPPORTED, "compressed sensing is built for 2-D Cartesian masks");
+    if (!d->kdata) return fail(PICO_EINVAL, "compressed sensing needs kdata");
+    if (d->fista_iters < 1 || d->fista_iters > 100000) return fail(PICO_EINVAL, "fista_iters must be in 1..100000");
+    if (!(d->cs_lambda >= 0.0) || !std::isfinite(d->cs_lambda)) return fail(PICO_EINVAL, "cs_lambda must be finite and >= 0");
+    if (d->wavelet_levels < 1 || d->wavelet_levels > 8) return fail(PICO_EINVAL, "wavelet_levels must be in 1..8");
+    const int m = 1 << d->wavelet_levels;
+    if (d->ny % m || d->nx % m) return fail(PICO_EINVAL, "ny and nx must be divisible by 2^wavelet_levels");
+    if (d->power_iters < 1 || !(d->power_margin > 0.0)) return fail(PICO_EINVAL, "compressed sensing needs power_iters >= 1 and power_margin > 0");
+  }
   if (d->sampling != PICO_CART_1D && d->sampling != PICO_CART_2D && d->sampling != PICO_NONCART)
     return fail(PICO_EUNSUPPORTED, "unknown sampling kind");
   if (d->ncoils < 1 || d->ncoils > 64) return fail(PICO_EINVAL, "ncoils must be in 1..64");
@@ -485,29 +591,65 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   }
 
   // spectral normalisation (Sec. 3.2.1, 3.3): lambda_max of M by power steps
-  if (d->lambda > 0.0) {
-    if ((e = op->colmajor ? pico::launch_power_start(op->p, ny, nx, s)
-                          : pico::launch_power_start_rowmajor(op->p, (int)n, s)) != hipSuccess) return bad(e, "power");
+  // (the compressed-sensing operator takes it from its FP64 primal below)
+  if (d->lambda > 0.0 && d->recon == PICO_CGSENSE) {
     double lam_hat = 0.0;
-    float2* bufs[2] = {op->p, op->q};
-    NormalCall c;
-    c.lam = 0.0f;
-    std::vector<double> part((size_t)op->nblk * 4);
-    for (int it = 0; it < d->power_iters; ++it) {
-      c.src = bufs[it & 1];
-      c.dst = bufs[(it + 1) & 1];
-      if ((e = launch_normal(op, 1, pico::C1_APPLY, c, s)) != hipSuccess) return bad(e, "power");
-      if ((e = hipMemcpyAsync(part.data(), op->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return bad(e, "power");
-      if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "power");
-      double vq = 0.0, qq = 0.0;
-      for (int b = 0; b < op->nblk; ++b) {
-        vq += part[4 * b + 1];
-        qq += part[4 * b + 2];
-      }
-      lam_hat = vq;              // Rayleigh quotient of the unit vector (scale * src)
-      c.scale = (float)(1.0 / std::sqrt(qq));
+    if ((e = power_lambda(op, d->power_iters, &lam_hat, s)) != hipSuccess) return bad(e, "power");
+    op->s2 = d->power_margin * lam_hat;
+    op->lam_abs = d->lambda * op->s2;
+  }
+  if (d->sampling == PICO_CART_2D) {
+    if ((e = op->alloc(&op->mask_d, n)) != hipSuccess) return bad(e, "mask");
+    if ((e = hipMemcpyAsync(op->mask_d, d->mask, n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return bad(e, "mask copy");
+  }
+  if (d->recon == PICO_CS_FISTA_L1WAV) {
+    // FISTA primal at the measured data in FP64, storing c_k = Psi z_k
+    // (Sec. 2.2 CS extension, Sec. 3.2.3, 3.3)
+    op->cs = true;
+    op->fista_T = d->fista_iters;
+    op->levels = d->wavelet_levels;
+    op->cs_lam = d->cs_lambda;
+    std::vector<double> theta64;
+    double t = 1.0;
+    for (int k = 0; k < op->fista_T; ++k) {
+      const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+      theta64.push_back((t - 1.0) / tn);
+      op->theta.push_back((float)theta64.back());
+      t = tn;
     }
-    op->lam_abs = d->lambda * d->power_margin * lam_hat;
+    if ((e = op->alloc(&op->wA, n * K)) != hipSuccess) return bad(e, "wavelet buffer");
+    if ((e = op->alloc(&op->wB, n * K)) != hipSuccess) return bad(e, "wavelet buffer");
+    if ((e = op->alloc(&op->ctraj, n * (size_t)op->fista_T)) != hipSuccess) return bad(e, "FISTA trajectory");
+    if ((e = op->alloc(&op->xrec, n)) != hipSuccess) return bad(e, "reconstruction");
+    pico::Cs64 o;
+    o.ny = ny;
+    o.nx = nx;
+    o.nc = nc;
+    o.levels = op->levels;
+    o.mask = op->mask_d;
+    double2 *atb = nullptr, *y = nullptr, *x = nullptr, *z = nullptr, *tmp = nullptr, *q = nullptr;
+    double* part = nullptr;
+    if ((e = op->alloc(&o.S, (size_t)nc * n)) != hipSuccess ||
+        (e = op->alloc(&o.U, (size_t)nc * n)) != hipSuccess ||
+        (e = op->alloc(&o.V, (size_t)nc * n)) != hipSuccess ||
+        (e = op->alloc(&o.Fy, (size_t)ny * ny)) != hipSuccess ||
+        (e = op->alloc(&o.Fx, (size_t)nx * nx)) != hipSuccess || (e = op->alloc(&atb, n)) != hipSuccess ||
+        (e = op->alloc(&y, n)) != hipSuccess || (e = op->alloc(&x, n)) != hipSuccess ||
+        (e = op->alloc(&z, n)) != hipSuccess || (e = op->alloc(&tmp, n)) != hipSuccess ||
+        (e = op->alloc(&q, n)) != hipSuccess || (e = op->alloc(&part, 2 * pico::CS64_DOT_BLOCKS)) != hipSuccess)
+      return bad(e, "FP64 primal workspace");
+    if ((e = pico::cs64_setup(o, (const float2*)d->maps, linv_d, s)) != hipSuccess) return bad(e, "FP64 primal");
+    double lam_hat = 0.0;
+    if ((e = pico::cs64_power(o, d->power_iters, y, x, part, &lam_hat, s)) != hipSuccess) return bad(e, "power");
+    op->s2 = d->power_margin * lam_hat;
+    if ((e = pico::cs64_adjoint_kdata(o, (const float2*)d->kdata, linv_d, atb, s)) != hipSuccess) return bad(e, "A^H b");
+    if ((e = pico::cs64_fista(o, atb, op->s2, op->cs_lam, op->fista_T, theta64.data(), op->ctraj, y, x, z, tmp, q, s)) != hipSuccess)
+      return bad(e, "FISTA");
+    if ((e = pico::launch_to_f32(x, op->xrec, (long)n, s)) != hipSuccess) return bad(e, "reconstruction");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "FISTA");
+    for (void* ptr : {(void*)o.S, (void*)o.U, (void*)o.V, (void*)o.Fy, (void*)o.Fx, (void*)atb, (void*)y,
+                      (void*)x, (void*)z, (void*)tmp, (void*)q, (void*)part})
+      op->release(ptr);
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "init");
   op->release(linv_d);
@@ -517,8 +659,30 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
 
 double pico_lambda_abs(pico_op_t op) { return op ? op->lam_abs : NAN; }
 
+pico_status_t pico_apply_jvp(pico_op_t op, const void* w, void* u, int32_t k, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!op->cs) return fail(PICO_EUNSUPPORTED, "pico_apply_jvp needs a compressed-sensing operator");
+  if (!w || !u) return fail(PICO_EINVAL, "NULL w or u");
+  if (k < 1 || k > op->K) return fail(PICO_EINVAL, "k must be in 1..probe_tile");
+  hipStream_t s = (hipStream_t)stream;
+  op->last_stream = s;
+  HIP_OR_RETURN(cs_tangents(op, k, (const float2*)w, 0, 0, 0, s));
+  HIP_OR_RETURN(hipMemcpyAsync(u, op->x, (size_t)k * op->image() * sizeof(float2), hipMemcpyDeviceToDevice, s));
+  return PICO_OK;
+}
+
+pico_status_t pico_recon(pico_op_t op, void* x, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!op->cs) return fail(PICO_EUNSUPPORTED, "the reconstruction is kept for compressed-sensing operators");
+  if (!x) return fail(PICO_EINVAL, "NULL output");
+  HIP_OR_RETURN(hipMemcpyAsync(x, op->xrec, op->image() * sizeof(float2), hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+  return PICO_OK;
+}
+
 pico_status_t pico_apply_cov(pico_op_t op, const void* v, void* u, int32_t k, void* stream) {
   if (pico_status_t st = check_op(op)) return st;
+  if (op->cs) return fail(PICO_EUNSUPPORTED, "a compressed-sensing operator has no linear covariance; use pico_apply_jvp");
   if (!v || !u) return fail(PICO_EINVAL, "NULL v or u");
   if (k < 1 || k > op->K) return fail(PICO_EINVAL, "k must be in 1..probe_tile");
   hipStream_t s = (hipStream_t)stream;
@@ -540,6 +704,26 @@ pico_status_t pico_noise_map(pico_op_t op, uint64_t seed, int64_t first_probe, i
   if (dist < 0 || dist > 3) return fail(PICO_EINVAL, "unknown probe family");
   hipStream_t s = (hipStream_t)stream;
   op->last_stream = s;
+  if (op->cs) {
+    for (int64_t done = 0; done < nprobes;) {
+      const int K = (int)std::min<int64_t>(op->K, nprobes - done);
+      const uint64_t first = (uint64_t)(first_probe + done);
+      HIP_OR_RETURN(cs_tangents(op, K, nullptr, seed, first, dist, s));
+      HIP_OR_RETURN(timed(op, PICO_PROF_ACCUM, s, [&] {
+        return pico::launch_accum_abs2(op->x, acc->sum, acc->sum_im, acc->sumsq, K, (long)op->image(), s);
+      }));
+      done += K;
+    }
+    acc->count += nprobes;
+    if (stats) {
+      HIP_OR_RETURN(hipStreamSynchronize(s));
+      stats->probes = nprobes;
+      stats->max_relres = stats->mean_relres = 0.0;
+      stats->frozen = 0;
+      stats->lambda_abs = 0.0;
+    }
+    return PICO_OK;
+  }
   StatAcc sa;
   for (int64_t done = 0; done < nprobes;) {
     const int K = (int)std::min<int64_t>(op->K, nprobes - done);
@@ -569,17 +753,25 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
   if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq)
     return fail(PICO_EINVAL, "PMR needs sum, sum_im and sumsq buffers");
   if (nrep < 0 || first < 0) return fail(PICO_EINVAL, "negative replica range");
-  if (!op->colmajor) return fail(PICO_EUNSUPPORTED, "PMR is built for phase-encode Cartesian sampling");
+  if (op->cs) return fail(PICO_EUNSUPPORTED, "PMR is built for CG-SENSE operators");
+  if (op->sampling == PICO_NONCART) return fail(PICO_EUNSUPPORTED, "PMR is built for Cartesian sampling");
   hipStream_t s = (hipStream_t)stream;
   op->last_stream = s;
   StatAcc sa;
   for (int64_t done = 0; done < nrep;) {
     const int K = (int)std::min<int64_t>(op->K, nrep - done);
     const uint64_t f = (uint64_t)(first + done);
-    NormalCall c;
-    c.seed = seed;
-    c.first = f;
-    HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] { return launch_normal(op, K, pico::C1_PMR_RHS, c, s); }));
+    if (op->colmajor) {
+      NormalCall c;
+      c.seed = seed;
+      c.first = f;
+      HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] { return launch_normal(op, K, pico::C1_PMR_RHS, c, s); }));
+    } else {
+      // r = A^H n, white Gaussian k-space noise on the mask (Philox stream 1)
+      HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] {
+        return adjoint_kspace(op, K, nullptr, nullptr, seed, f, 1u, 3, op->r, s);
+      }));
+    }
     HIP_OR_RETURN(cg_solve(op, K, pico::C1_FIRST_BUF, 0, 0, 0, s));
     HIP_OR_RETURN(accumulate(op, K, acc, 0, 0, 0, 1, s));
     if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));

@@ -103,8 +103,54 @@ hipError_t launch_prep_maps_rowmajor(const float2* maps, const double* linv, flo
 hipError_t launch_mask_weights(const uint8_t* mask, float* w, int ny, int nx, float scale,
                                hipStream_t s);
 hipError_t launch_power_start_rowmajor(float2* p, int n, hipStream_t s);
+hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse, const float2* twx,
+                        const float2* twy, hipStream_t s);
+hipError_t launch_kspace_in(const float2* src, const double* linv, const uint8_t* mask, float2* out,
+                            int B, int nc, int ny, int nx, uint64_t seed, uint64_t first,
+                            uint32_t stream, int dist, float scale, hipStream_t s);
+hipError_t launch_coil_combine(const float2* T, const float2* maps, float2* out, int B, int nc,
+                               long n, hipStream_t s);
+hipError_t launch_wavelet(float2* buf, float2* tmp, int K, int ny, int nx, int levels, bool inverse,
+                          hipStream_t s);
+hipError_t launch_fista_grad(const float2* y, const float2* q, const float2* g, float2* z, long n, int K,
+                             int gK, float inv_s2, hipStream_t s);
+hipError_t launch_dsoft(float2* dc, const double2* ck, long n, int K, int nx, int ly, int lx, double lam,
+                        hipStream_t s);
+hipError_t launch_momentum(const float2* xn, float2* xo, float2* y, long total, float theta,
+                           hipStream_t s);
+hipError_t launch_accum_abs2(const float2* u, double* sum, double* sum_im, double* sumsq, int K, long n,
+                             hipStream_t s);
+hipError_t launch_fill_zero(float2* a, long total, hipStream_t s);
 hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, float* w,
                                   hipStream_t s);
+// complex128 GEMM (row-major; flags 1 transA, 2 conjA, 4 conjB; split-K slices
+// land in C[slice]); batch b offsets A, B, C by b * sA, sB, sC
+hipError_t zgemm64(const double2* A, const double2* B, double2* C, int Mr, int Nc, int Kd,
+                   int flags, int splits, hipStream_t s, int batch = 1, long sA = 0, long sB = 0,
+                   long sC = 0);
+
+// FP64 compressed-sensing primal (2-D Cartesian): the normal operator by dense
+// centred-DFT products, power method, FISTA storing its wavelet coefficients
+constexpr int CS64_DOT_BLOCKS = 1024;
+struct Cs64 {
+  int ny = 0, nx = 0, nc = 0, levels = 0;
+  double2* S = nullptr;         // [nc][ny][nx] whitened coil maps
+  double2* Fy = nullptr;        // [ny][ny] centred orthonormal DFT
+  double2* Fx = nullptr;        // [nx][nx]
+  const uint8_t* mask = nullptr;  // [ny][nx]
+  double2* U = nullptr;         // [nc][ny][nx] workspace
+  double2* V = nullptr;         // [nc][ny][nx] workspace
+};
+hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream_t s);
+hipError_t cs64_normal(const Cs64& o, const double2* y, double2* q, hipStream_t s);
+hipError_t cs64_adjoint_kdata(const Cs64& o, const float2* kdata, const double* linv, double2* out,
+                              hipStream_t s);
+hipError_t cs64_power(const Cs64& o, int iters, double2* v, double2* w, double* part_d, double* out,
+                      hipStream_t s);
+hipError_t cs64_fista(const Cs64& o, const double2* atb, double s2, double lam, int T,
+                      const double* theta, double2* ctraj, double2* y, double2* x, double2* z,
+                      double2* tmp, double2* q, hipStream_t s);
+hipError_t launch_to_f32(const double2* a, float2* b, long n, hipStream_t s);
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
 hipError_t launch_final_x(const FinalArgs& a, hipStream_t s);
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);

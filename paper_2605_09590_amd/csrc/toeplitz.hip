@@ -11,7 +11,7 @@
 
 namespace pico {
 
-struct z64 { double x, y; };
+using z64 = double2;
 
 __global__ void k_exp_table(const float* __restrict__ traj, int comp, int d0, int D, int M,
                             z64* __restrict__ out) {
@@ -21,27 +21,37 @@ __global__ void k_exp_table(const float* __restrict__ traj, int comp, int d0, in
   const double w = (double)traj[2 * (size_t)m + comp];
   double s, c;
   sincos(w * (double)(d0 + j), &s, &c);
-  out[i] = {c, s};
+  out[i] = make_double2(c, s);
 }
 
-// C[z][i][j] = sum_{kk in slice z} op(A)[i][kk] B[kk][j]; op(A) = A (A: [Mr][Kd]) or
-// A^T (A: [Kd][Mr]); B: [Kd][Nc]; row-major complex128; 32x32 tile per block.
+// C[z][i][j] = sum_{kk in slice z} op(A)[i][kk] op(B)[kk][j]; op(A) = A (A: [Mr][Kd])
+// or A^T (A: [Kd][Mr]), optionally conjugated; op(B) = B or conj(B), B: [Kd][Nc];
+// row-major complex128; 32x32 tile per block.  flags: 1 transA, 2 conjA, 4 conjB.
+// blockIdx.z = batch * S + slice; batch b offsets A, B, C by b * sA, sB, sC.
 __global__ __launch_bounds__(256) void k_zgemm(const z64* __restrict__ A, const z64* __restrict__ B,
                                                z64* __restrict__ C, int Mr, int Nc, int Kd,
-                                               int transA, int kslice) {
+                                               int flags, int kslice, int S, long sA, long sB,
+                                               long sC) {
+  const int transA = flags & 1;
+  const int bz = blockIdx.z / S, sl = blockIdx.z % S;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
   __shared__ z64 As[16][33];
   __shared__ z64 Bs[16][33];
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
-  const int kbeg = blockIdx.z * kslice, kend = min(Kd, kbeg + kslice);
+  const int kbeg = sl * kslice, kend = min(Kd, kbeg + kslice);
   double acc[2][2][2] = {};
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
     for (int e = threadIdx.x; e < 16 * 32; e += 256) {
       const int kk = e / 32, ii = e % 32;
       const int gk = k0 + kk, gi = i0 + ii, gj = j0 + ii;
-      z64 av = {0.0, 0.0}, bv = {0.0, 0.0};
+      z64 av = make_double2(0.0, 0.0), bv = make_double2(0.0, 0.0);
       if (gk < kend && gi < Mr) av = transA ? A[(size_t)gk * Mr + gi] : A[(size_t)gi * Kd + gk];
       if (gk < kend && gj < Nc) bv = B[(size_t)gk * Nc + gj];
+      if (flags & 2) av.y = -av.y;
+      if (flags & 4) bv.y = -bv.y;
       As[kk][ii] = av;
       Bs[kk][ii] = bv;
     }
@@ -67,7 +77,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const z64* __restrict__ A, const 
     for (int b = 0; b < 2; ++b) {
       const int gi = i0 + ty + 16 * a, gj = j0 + tx + 16 * b;
       if (gi < Mr && gj < Nc)
-        C[((size_t)blockIdx.z * Mr + gi) * Nc + gj] = {acc[a][b][0], acc[a][b][1]};
+        C[((size_t)sl * Mr + gi) * Nc + gj] = make_double2(acc[a][b][0], acc[a][b][1]);
     }
 }
 
@@ -81,7 +91,7 @@ __global__ void k_zsum_slices(const z64* __restrict__ parts, z64* __restrict__ o
     re += parts[(size_t)z * n + i].x;
     im += parts[(size_t)z * n + i].y;
   }
-  out[i] = {re * scale, im * scale};
+  out[i] = make_double2(re * scale, im * scale);
 }
 
 // k[dy mod Gy][dx mod Gx] = psf[dy + ny - 1][dx + nx - 1]; zero elsewhere
@@ -92,7 +102,7 @@ __global__ void k_embed(const z64* __restrict__ psf, z64* __restrict__ kg, int n
   const int ky = (int)(i / Gx), kx = (int)(i % Gx);
   const int dy = ky < ny ? ky : ky - Gy;  // index ny maps to -ny: outside the PSF support
   const int dx = kx < nx ? kx : kx - Gx;
-  z64 v = {0.0, 0.0};
+  z64 v = make_double2(0.0, 0.0);
   if (dy > -ny && dy < ny && dx > -nx && dx < nx)
     v = psf[(size_t)(dy + ny - 1) * (2 * nx - 1) + (dx + nx - 1)];
   kg[i] = v;
@@ -105,7 +115,7 @@ __global__ void k_dft_matrix(z64* __restrict__ F, int G) {
   const long k = i / G, n = i % G;
   double s, c;
   sincospi(-2.0 * (double)((k * n) % G) / (double)G, &s, &c);
-  F[i] = {c, s};
+  F[i] = make_double2(c, s);
 }
 
 // w[kx][ky] = Re(Kh[ky][kx]) * scale
@@ -117,12 +127,12 @@ __global__ void k_real_weights(const z64* __restrict__ kh, float* __restrict__ w
   w[(size_t)kx * Gy + ky] = (float)(kh[i].x * scale);
 }
 
-static hipError_t zgemm(const z64* A, const z64* B, z64* C, int Mr, int Nc, int Kd, int transA,
-                        int splits, hipStream_t s) {
+hipError_t zgemm64(const double2* A, const double2* B, double2* C, int Mr, int Nc, int Kd,
+                   int flags, int splits, hipStream_t s, int batch, long sA, long sB, long sC) {
   const int kslice = ((Kd + splits - 1) / splits + 15) / 16 * 16;
   const int S = (Kd + kslice - 1) / kslice;
-  dim3 grid((Nc + 31) / 32, (Mr + 31) / 32, S), block(256);
-  hipLaunchKernelGGL(k_zgemm, grid, block, 0, s, A, B, C, Mr, Nc, Kd, transA, kslice);
+  dim3 grid((Nc + 31) / 32, (Mr + 31) / 32, S * batch), block(256);
+  hipLaunchKernelGGL(k_zgemm, grid, block, 0, s, A, B, C, Mr, Nc, Kd, flags, kslice, S, sA, sB, sC);
   return hipGetLastError();
 }
 
@@ -161,7 +171,7 @@ hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, flo
   hipLaunchKernelGGL(k_exp_table, dim3((unsigned)((M * Dx + 255) / 256)), dim3(256), 0, s, traj, 1,
                      -(nx - 1), Dx, (int)M, Ex);
   TZ_CHECK(hipGetLastError());
-  TZ_CHECK(zgemm(Ey, Ex, parts, Dy, Dx, (int)M, 1, splits, s));
+  TZ_CHECK(zgemm64(Ey, Ex, parts, Dy, Dx, (int)M, 1, splits, s));
   const long npsf = (long)Dy * Dx;
   hipLaunchKernelGGL(k_zsum_slices, dim3((unsigned)((npsf + 255) / 256)), dim3(256), 0, s, parts, psf,
                      npsf, S, 1.0 / ((double)ny * nx));
@@ -170,8 +180,8 @@ hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, flo
   hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)(((long)Gy * Gy + 255) / 256)), dim3(256), 0, s, Fy, Gy);
   hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)(((long)Gx * Gx + 255) / 256)), dim3(256), 0, s, Fx, Gx);
   TZ_CHECK(hipGetLastError());
-  TZ_CHECK(zgemm(Fy, kg, t1, Gy, Gx, Gy, 0, 1, s));
-  TZ_CHECK(zgemm(t1, Fx, kh, Gy, Gx, Gx, 0, 1, s));
+  TZ_CHECK(zgemm64(Fy, kg, t1, Gy, Gx, Gy, 0, 1, s));
+  TZ_CHECK(zgemm64(t1, Fx, kh, Gy, Gx, Gx, 0, 1, s));
   hipLaunchKernelGGL(k_real_weights, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, kh, w, Gy, Gx,
                      1.0 / ((double)Gy * Gx));
   TZ_CHECK(hipGetLastError());

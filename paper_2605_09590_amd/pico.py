@@ -37,6 +37,10 @@ class pico_op_desc_t(ctypes.Structure):
         ("power_margin", ctypes.c_double),
         ("probe_tile", ctypes.c_int32),
         ("recon", ctypes.c_int32),
+        ("kdata", ctypes.c_void_p),
+        ("fista_iters", ctypes.c_int32),
+        ("cs_lambda", ctypes.c_double),
+        ("wavelet_levels", ctypes.c_int32),
     ]
 
 
@@ -59,7 +63,7 @@ class PicoError(RuntimeError):
 
 _lib = None
 
-EXPORTS = ["pico_init", "pico_apply_cov", "pico_noise_map", "pico_finalize",
+EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_recon", "pico_noise_map", "pico_finalize",
            "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse", "pico_exact_diag",
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error"]
@@ -79,6 +83,8 @@ def load(path: str = LIB_PATH):
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     lib.pico_init.argtypes = [ctypes.POINTER(pico_op_desc_t), vp, ctypes.POINTER(vp)]
     lib.pico_apply_cov.argtypes = [vp, vp, vp, i32, vp]
+    lib.pico_apply_jvp.argtypes = [vp, vp, vp, i32, vp]
+    lib.pico_recon.argtypes = [vp, vp, vp]
     lib.pico_noise_map.argtypes = [vp, u64, i64, i64, i32, ctypes.POINTER(pico_accum_t),
                                    ctypes.POINTER(pico_stats_t), vp]
     lib.pico_finalize.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp, vp]
@@ -97,7 +103,7 @@ def load(path: str = LIB_PATH):
     lib.pico_destroy.restype = None
     lib.pico_last_error.argtypes = []
     lib.pico_last_error.restype = ctypes.c_char_p
-    for name in ("pico_init", "pico_apply_cov", "pico_noise_map", "pico_finalize",
+    for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_recon", "pico_noise_map", "pico_finalize",
                  "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse",
                  "pico_exact_diag", "pico_profile_start", "pico_profile_stop"):
         getattr(lib, name).restype = ctypes.c_int
@@ -127,7 +133,8 @@ def pico_last_error() -> str:
 
 def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
-              traj=None, nsamples=0, stream=None):
+              traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
+              wavelet_levels=4, stream=None):
     """pico_init: ``maps`` complex64 device tensor [nc][ny][nx]; ``psi`` numpy
     complex128 [nc][nc] or None; ``mask`` uint8 device tensor.  Returns the handle."""
     lib = load()
@@ -149,6 +156,10 @@ def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
     d.power_margin = power_margin
     d.probe_tile = probe_tile
     d.recon = recon
+    d.kdata = kdata.data_ptr() if kdata is not None else None
+    d.fista_iters = fista_iters
+    d.cs_lambda = cs_lambda
+    d.wavelet_levels = wavelet_levels
     h = ctypes.c_void_p()
     _check(lib.pico_init(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
     del keep
@@ -157,6 +168,14 @@ def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
 
 def pico_apply_cov(h, v, u, k, stream=None):
     return _check(load().pico_apply_cov(h, _ptr(v), _ptr(u), int(k), _stream(stream)))
+
+
+def pico_apply_jvp(h, w, u, k, stream=None):
+    return _check(load().pico_apply_jvp(h, _ptr(w), _ptr(u), int(k), _stream(stream)))
+
+
+def pico_recon(h, x, stream=None):
+    return _check(load().pico_recon(h, _ptr(x), _stream(stream)))
 
 
 def make_accum(sum_, sum_im=None, sumsq=None, count=0):
