@@ -52,6 +52,72 @@ def normal_op_flops(ny, nx, nc):
     return nc * nx * per_line
 
 
+def cs_kspace(torch, dev, prob, seed=0):
+    """Raw multi-coil k-space b = P F_c (S x) + L n of the CS workload, formed on
+    the GPU with torch.fft (input synthesis, outside every timed region): the
+    phantom x, the raw maps S, centred orthonormal 2-D DFT F_c, noise with
+    covariance Psi = L L^H at the workload's input SNR over the sampled locations."""
+    import numpy as np
+    x = torch.from_numpy(prob.extra["phantom"].astype(np.complex128)).to(dev)
+    maps = torch.from_numpy(prob.maps.astype(np.complex128)).to(dev)
+    mask = torch.from_numpy(prob.mask.astype(np.float64)).to(dev)
+    img = maps * x[None]
+    k = torch.fft.fftshift(torch.fft.fft2(torch.fft.ifftshift(img, dim=(-2, -1)), norm="ortho"),
+                           dim=(-2, -1)) * mask[None]
+    sig = torch.sqrt(torch.mean(torch.abs(k[:, mask > 0]) ** 2)) * 10 ** (-prob.extra["snr_db"] / 20)
+    rng = np.random.default_rng(seed + 1000)
+    nz = rng.standard_normal(k.shape) + 1j * rng.standard_normal(k.shape)
+    L = torch.from_numpy(np.linalg.cholesky(prob.psi)).to(dev)
+    n = torch.einsum("cd,dyx->cyx", L, torch.from_numpy(nz).to(dev)) * (sig / math.sqrt(2.0))
+    return (k + n * mask[None]).to(torch.complex64).contiguous()
+
+
+def cs_leg(lib, workloads, torch, np, dev, steps):
+    """JVPs/s of the CS workload and the HBM roofline of its normal operator."""
+    pr = workloads.config(4, seed=0)
+    K = pr.probes
+    n = pr.ny * pr.nx
+    kd = cs_kspace(torch, dev, pr)
+    maps = torch.from_numpy(pr.maps.astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(pr.mask).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, sampling=lib.PICO_CART_2D,
+                      recon=lib.PICO_CS_FISTA_L1WAV, kdata=kd, fista_iters=pr.extra["fista_iters"],
+                      cs_lambda=pr.extra["cs_lambda"], wavelet_levels=pr.extra["levels"], probe_tile=K)
+    init_s = time.perf_counter() - t0
+    acc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)])
+    lib.pico_noise_map(h, 3, 0, K, 0, acc)                   # warm-up step
+    torch.cuda.synchronize()
+    lib.pico_profile_start(h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        lib.pico_noise_map(h, 3, (i + 1) * K, K, 0, acc)
+    e1.record()
+    torch.cuda.synchronize()
+    prof = lib.pico_profile_stop(h)
+    lib.pico_destroy(h)
+    ms = e0.elapsed_time(e1) / steps
+    it_ms, it_n = prof["normal_iter"]
+    op_s = it_ms / it_n / 1e3
+    # per probe and normal-operator application: coil k-space written, read+written,
+    # read (nc ny nx complex64 each) + p read, q written; maps twice per launch
+    alg = K * (4 * pr.nc * n * 8 + 2 * n * 8) + 2 * pr.nc * n * 8
+    return {
+        "workload": f"CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2 (24x24 calib), "
+                    f"L1-db4 (4 levels) FISTA {pr.extra['fista_iters']} its, lambda "
+                    f"{pr.extra['cs_lambda']}, K={K} JVP probes per step",
+        "jvps_per_s": round(K / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+        "init_s": round(init_s, 3),
+        "roofline": {"bound": "hbm", "achieved": round(alg / op_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(alg / op_s / 1e9 / PEAK_HBM_GBS, 4),
+                     "kernel": "grid normal operator (rows_fwd + cols + rows_inv), C1_APPLY",
+                     "avg_application_us": round(op_s * 1e6, 1), "alg_bytes": alg},
+        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +129,8 @@ def main():
     ap.add_argument("--no-ref", action="store_true", help="skip the exact reference map (implies --no-ttt)")
     ap.add_argument("--spiral-steps", type=int, default=2,
                     help="steps of the spiral Toeplitz leg (0 to skip)")
+    ap.add_argument("--cs-steps", type=int, default=1,
+                    help="steps of the compressed-sensing JVP leg (0 to skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -222,6 +290,11 @@ def main():
             "kernel_ms": {k: round(v[0], 3) for k, v in sprof.items()},
         }
 
+    # --- third workload: CS (FISTA L1-db4), batched Jacobian-vector probes
+    cs_res = None
+    if args.cs_steps > 0:
+        cs_res = cs_leg(lib, workloads, torch, np, dev, args.cs_steps)
+
     # --- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -230,11 +303,11 @@ def main():
         cov = opico.Covariance(op, 0.0, prob.cg_iters)
         t0 = time.perf_counter()
         opico.noise_map(cov, 11, 0, args.cpu_probes)
-        cs = time.perf_counter() - t0
-        cpu = {"value": round(args.cpu_probes / cs, 4), "unit": "probe-solves/s", "cores": 1,
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(args.cpu_probes / cpu_s, 4), "unit": "probe-solves/s", "cores": 1,
                "kind": "oracle",
                "sample": f"{args.cpu_probes} probes of the same 320x320 15-coil workload, "
-                         f"CG 30, FP64 numpy, one process ({cs:.1f} s)"}
+                         f"CG 30, FP64 numpy, one process ({cpu_s:.1f} s)"}
 
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "probe-solves/s", "n_gpus": 1,
@@ -252,6 +325,7 @@ def main():
         "kernel_launches": {k: v[1] for k, v in prof.items()},
         "roofline": roofline, "cpu_baseline": cpu,
         "spiral": spiral,
+        "cs": cs_res,
     }
     if args.copy_calib:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB

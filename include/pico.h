@@ -206,13 +206,17 @@ pico_status_t pico_exact_diag(pico_op_t op, double* var, void* stream);
  * for the recorded events and writes, per class k < PICO_PROF_KINDS, the
  * summed duration in ms and the launch count (either pointer may be NULL). */
 enum {
-  PICO_PROF_NORMAL_FIRST = 0,  /* first normal-operator application of a solve */
+  PICO_PROF_NORMAL_FIRST = 0,  /* first normal-operator application of a solve;
+                                  CS: A^H w of the k-space probes               */
   PICO_PROF_NORMAL_ITER = 1,   /* x += alpha p, r -= alpha q, p = r + beta p
-                                  fused with q = (M + lam) p and its dots       */
+                                  fused with q = (M + lam) p and its dots;
+                                  CS: q = M y of the tangents                   */
   PICO_PROF_CG_UPDATE = 2,     /* last x += alpha p of each solve               */
   PICO_PROF_CG_SCALARS = 3,    /* per-probe alpha / beta reductions             */
   PICO_PROF_ACCUM = 4,         /* FP64 accumulation of conj(v) u                */
-  PICO_PROF_OTHER = 5,         /* Tikhonov middle product, PMR right-hand side  */
+  PICO_PROF_OTHER = 5,         /* Tikhonov middle product, PMR right-hand side;
+                                  CS: gradient step, wavelets, threshold
+                                  derivative and momentum of the tangents       */
   PICO_PROF_KINDS = 8
 };
 pico_status_t pico_profile_start(pico_op_t op);

@@ -428,12 +428,16 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
   const float inv_s2 = (float)(1.0 / op->s2);
   for (int k = 1; k <= op->fista_T; ++k) {
     if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return launch_normal(op, K, pico::C1_APPLY, c, s); })) != hipSuccess) return e;
-    if ((e = pico::launch_fista_grad(op->p, op->q, op->r, op->wA, n, K, 1, inv_s2, s)) != hipSuccess) return e;
-    if ((e = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, false, s)) != hipSuccess) return e;
-    const double2* ck = op->ctraj + (size_t)(k - 1) * n;
-    if ((e = pico::launch_dsoft(op->wA, ck, n, K, op->nx, ly, lx, op->cs_lam, s)) != hipSuccess) return e;
-    if ((e = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, true, s)) != hipSuccess) return e;
-    if ((e = pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s)) != hipSuccess) return e;
+    e = timed(op, PICO_PROF_OTHER, s, [&] {
+      hipError_t e2;
+      if ((e2 = pico::launch_fista_grad(op->p, op->q, op->r, op->wA, n, K, 1, inv_s2, s)) != hipSuccess) return e2;
+      if ((e2 = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, false, s)) != hipSuccess) return e2;
+      const double2* ck = op->ctraj + (size_t)(k - 1) * n;
+      if ((e2 = pico::launch_dsoft(op->wA, ck, n, K, op->nx, ly, lx, op->cs_lam, s)) != hipSuccess) return e2;
+      if ((e2 = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, true, s)) != hipSuccess) return e2;
+      return pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s);
+    });
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
