@@ -225,6 +225,73 @@ pico_status_t pico_profile_stop(pico_op_t op, double* ms, int64_t* launches);
 /* Release the operator and its device memory (waits for its last stream). */
 void pico_destroy(pico_op_t op);
 
+/* Device memory of an operator, counted in 256-byte pieces: *resident is
+ * what pico_init keeps after returning, *peak the most it holds during
+ * pico_init (weight-builder and CS-primal temporaries).
+ * pico_estimate_bytes computes both from the description alone (host only,
+ * no device call; the same validation as pico_init, so PICO_EINVAL /
+ * PICO_EUNSUPPORTED as there); pico_op_bytes reports what an initialised
+ * operator actually took.  Either output pointer may be NULL. */
+pico_status_t pico_estimate_bytes(const pico_op_desc_t* desc, uint64_t* resident, uint64_t* peak);
+pico_status_t pico_op_bytes(pico_op_t op, uint64_t* resident, uint64_t* peak);
+
+/* ------------------------------------------------------------------ serving
+ * Many noise-map requests, each against its own operator, on the current
+ * device (the spec serving mode: HBM-budgeted admission, probe tiles of
+ * all admitted requests in flight at once).
+ *
+ * pico_server_create takes one device allocation of hbm_budget bytes (rounded
+ * down to 256) and starts a worker thread.  Every operator the server builds
+ * lives in that allocation, so serving makes no further hipMalloc / hipFree.
+ * A request is admitted in arrival order when one of max_slots slots is free
+ * and its peak bytes (pico_estimate_bytes) fit beside the resident bytes of
+ * the admitted requests; admitted requests each have their own stream and up
+ * to tiles_in_flight probe tiles (desc->probe_tile probes each) enqueued.  A
+ * finished request frees its operator and slot immediately.
+ *
+ * A request adds probes [first_probe, first_probe + nprobes) into *acc
+ * exactly as pico_noise_map(op, seed, first_probe, nprobes, dist, acc) on a
+ * freshly initialised operator would (same tiles, same order, same values:
+ * results do not depend on what else is being served).  acc->count is not
+ * updated (the count is nprobes, reported back in the request info).
+ *
+ * Lifetimes: pico_server_submit copies the description and the host psi; the
+ * device arrays it points to (maps, mask, traj, kdata) and the accumulator
+ * buffers must stay valid until the request is reported done, and must be
+ * ready when submitted (the server's streams do not wait on the caller's).
+ *
+ * Errors (synchronous, nothing queued): PICO_EINVAL / PICO_EUNSUPPORTED for a
+ * description pico_init would reject or bad arguments, PICO_ENOMEM when the
+ * request's peak bytes exceed the whole budget.  Errors found while serving
+ * are reported per request in pico_request_info_t.status / .error.
+ * Times are milliseconds on a steady clock since pico_server_create. */
+typedef struct pico_server_s* pico_server_t;
+
+typedef struct {
+  uint64_t id;
+  int32_t status;               /* pico_status_t of the request                 */
+  int64_t first_probe, probes;
+  double t_submit_ms, t_admit_ms, t_done_ms;
+  uint64_t bytes_peak, bytes_resident;   /* estimate at submission             */
+  char error[160];              /* message when status != PICO_OK               */
+} pico_request_info_t;
+
+pico_status_t pico_server_create(uint64_t hbm_budget, int32_t max_slots, int32_t tiles_in_flight,
+                                 pico_server_t* out);
+pico_status_t pico_server_submit(pico_server_t srv, const pico_op_desc_t* desc, uint64_t seed,
+                                 int64_t first_probe, int64_t nprobes, int32_t dist,
+                                 const pico_accum_t* acc, uint64_t* req_id);
+/* Moves up to max finished requests (oldest first) into out; *n = how many. */
+pico_status_t pico_server_poll(pico_server_t srv, pico_request_info_t* out, int32_t max, int32_t* n);
+/* Waits until every submitted request has finished (timeout_s < 0: no limit;
+ * PICO_ENOTCONV if the timeout passes first). */
+pico_status_t pico_server_wait_idle(pico_server_t srv, double timeout_s);
+/* Budget, bytes handed out by the arena, queued and admitted request counts. */
+pico_status_t pico_server_usage(pico_server_t srv, uint64_t* budget, uint64_t* arena_used,
+                                int32_t* queued, int32_t* active);
+/* Serves everything already submitted, then stops the worker and frees the budget. */
+void pico_server_destroy(pico_server_t srv);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* pico_last_error(void);
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpico.so")
-SOURCES = ["cart1d.hip", "grid2d.hip", "toeplitz.hip", "cs.hip", "cg.hip", "pico_abi.hip"]
+SOURCES = ["cart1d.hip", "grid2d.hip", "toeplitz.hip", "cs.hip", "cg.hip", "pico_abi.hip", "serve.hip"]
 
 # Packed FP32 instructions stay off: the build relies on scalar / float2 code
 # only, and the compiler must not fuse it into v_pk_* forms.
@@ -50,7 +50,7 @@ def build(verbose: bool = False) -> str:
         for f in futs:
             f.result()
     tmp = OUT + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")

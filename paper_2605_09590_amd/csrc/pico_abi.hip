@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "arena.h"
 #include "pico.h"
 #include "runtime.h"
 
@@ -74,7 +75,11 @@ struct pico_op_s {
   double2* ctraj = nullptr;     // [T][ny][nx] stored Psi z_k of the FP64 primal
   float2* xrec = nullptr;       // reconstruction
   uint8_t* mask_d = nullptr;    // [ny][nx] (Cartesian 2-D)
-  std::vector<void*> allocs;
+  // device memory: from hipMalloc, or from a serving arena when one is set;
+  // bytes are counted in 256-byte pieces (current and peak)
+  pico::DeviceArena* arena = nullptr;
+  std::vector<std::pair<void*, size_t>> allocs;
+  size_t bytes = 0, peak = 0;
   // optional per-kernel-class timing with HIP events on the caller's stream
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
@@ -83,7 +88,11 @@ struct pico_op_s {
 
   ~pico_op_s() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    for (void* ptr : allocs) (void)hipFree(ptr);
+    for (auto& a : allocs) free_raw(a.first);
+  }
+  void free_raw(void* ptr) {
+    if (arena) arena->release(ptr);
+    else (void)hipFree(ptr);
   }
   hipEvent_t next_event() {
     if (ev_used == ev_pool.size()) {
@@ -95,18 +104,26 @@ struct pico_op_s {
   }
   template <class T>
   hipError_t alloc(T** ptr, size_t count) {
+    const size_t nb = pico::OffsetArena::round_up(count * sizeof(T));
     void* raw = nullptr;
-    hipError_t e = hipMalloc(&raw, std::max<size_t>(count, 1) * sizeof(T));
-    if (e == hipSuccess) {
-      allocs.push_back(raw);
-      *ptr = static_cast<T*>(raw);
+    if (arena) {
+      raw = arena->alloc(nb);
+      if (!raw) return hipErrorOutOfMemory;
+    } else {
+      hipError_t e = hipMalloc(&raw, nb);
+      if (e != hipSuccess) return e;
     }
-    return e;
+    allocs.push_back({raw, nb});
+    bytes += nb;
+    peak = std::max(peak, bytes);
+    *ptr = static_cast<T*>(raw);
+    return hipSuccess;
   }
   void release(void* ptr) {
-    auto it = std::find(allocs.begin(), allocs.end(), ptr);
+    auto it = std::find_if(allocs.begin(), allocs.end(), [&](const auto& a) { return a.first == ptr; });
     if (it != allocs.end()) {
-      (void)hipFree(ptr);
+      free_raw(ptr);
+      bytes -= it->second;
       allocs.erase(it);
     }
   }
@@ -502,7 +519,96 @@ extern "C" {
 
 const char* pico_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
+namespace pico {
+
+pico_status_t set_error(pico_status_t st, const std::string& msg) { return fail(st, msg); }
+
+// Device bytes pico_init takes for d: resident after it returns, and the peak
+// during it (temporaries of the weight builders and of the CS primal).  Each
+// allocation is counted in 256-byte pieces, in the order pico_init makes it.
+pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* peak) {
+  if (!d) return fail(PICO_EINVAL, "NULL descriptor");
+  if (pico_status_t st = validate(d)) return st;
+  size_t cur = 0, top = 0;
+  auto add = [&](size_t b) {
+    cur += OffsetArena::round_up(b);
+    top = std::max(top, cur);
+  };
+  auto sub = [&](size_t b) { cur -= OffsetArena::round_up(b); };
+  const size_t nc = d->ncoils, ny = d->ny, nx = d->nx, n = ny * nx, K = d->probe_tile;
+  const bool colmajor = d->sampling == PICO_CART_1D;
+  const size_t f = d->sampling == PICO_NONCART ? 2 : 1, Gy = f * ny, Gx = f * nx;
+  const size_t nblk = colmajor ? nx : ny;
+  add(n * nc * 8);
+  for (int i = 0; i < 4; ++i) add(n * K * 8);
+  add(K * nblk * 4 * 8);
+  add(512 * 8);
+  for (int i = 0; i < 4; ++i) add(K * 8);
+  add(K * 4);
+  const size_t linv = 2 * nc * nc * 8;
+  add(linv);
+  if (colmajor) {
+    add(ny * 4);
+    add(ny * 8);
+  } else {
+    add(Gy * Gx * 4);
+    add(Gx * 8);
+    add(Gy * 8);
+    add(K * nc * ny * Gx * 8);
+    if (d->sampling == PICO_NONCART) {
+      const size_t sc = toeplitz_scratch_bytes(d->nsamples, d->ny, d->nx);
+      add(sc);
+      sub(sc);
+    }
+  }
+  if (d->sampling == PICO_CART_2D) add(n);
+  if (d->recon == PICO_CS_FISTA_L1WAV) {
+    add(n * K * 8);
+    add(n * K * 8);
+    add(n * (size_t)d->fista_iters * 16);
+    add(n * 8);
+    const size_t tmp[] = {nc * n * 16, nc * n * 16, nc * n * 16, ny * ny * 16, nx * nx * 16, n * 16,
+                          n * 16,      n * 16,      n * 16,      n * 16,      n * 16,  2 * CS64_DOT_BLOCKS * 8};
+    for (size_t b : tmp) add(b);
+    for (size_t b : tmp) sub(b);
+  }
+  sub(linv);
+  if (resident) *resident = cur;
+  if (peak) *peak = top;
+  return PICO_OK;
+}
+
+pico_status_t init_in_arena(const pico_op_desc_t* d, void* stream, DeviceArena* arena, pico_op_t* out);
+
+}  // namespace pico
+
+extern "C" {
+
+pico_status_t pico_estimate_bytes(const pico_op_desc_t* d, uint64_t* resident, uint64_t* peak) {
+  size_t r = 0, p = 0;
+  if (pico_status_t st = pico::estimate_bytes(d, &r, &p)) return st;
+  if (resident) *resident = r;
+  if (peak) *peak = p;
+  return PICO_OK;
+}
+
+pico_status_t pico_op_bytes(pico_op_t op, uint64_t* resident, uint64_t* peak) {
+  if (!op) return fail(PICO_EINVAL, "NULL handle");
+  if (resident) *resident = op->bytes;
+  if (peak) *peak = op->peak;
+  return PICO_OK;
+}
+
 pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
+  return pico::init_in_arena(d, stream, nullptr, out);
+}
+
+}  // extern "C"
+
+pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::DeviceArena* arena,
+                                  pico_op_t* out) {
   if (!d || !out) return fail(PICO_EINVAL, "NULL descriptor or output handle");
   *out = nullptr;
   if (pico_status_t st = validate(d)) return st;
@@ -518,6 +624,7 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   }
 
   auto* op = new pico_op_s();
+  op->arena = arena;
   op->ny = ny;
   op->nx = nx;
   op->nc = nc;
@@ -590,7 +697,10 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
     if (d->sampling == PICO_CART_2D) {
       if ((e = pico::launch_mask_weights(d->mask, op->w, ny, nx, (float)(1.0 / ((double)ny * nx)), s)) != hipSuccess) return bad(e, "weights");
     } else {
-      if ((e = pico::build_toeplitz_weights(d->traj, d->nsamples, ny, nx, op->w, s)) != hipSuccess) return bad(e, "Toeplitz weights");
+      char* scratch = nullptr;
+      if ((e = op->alloc(&scratch, pico::toeplitz_scratch_bytes(d->nsamples, ny, nx))) != hipSuccess) return bad(e, "Toeplitz scratch");
+      if ((e = pico::build_toeplitz_weights(d->traj, d->nsamples, ny, nx, op->w, scratch, s)) != hipSuccess) return bad(e, "Toeplitz weights");
+      op->release(scratch);
     }
   }
 
@@ -660,6 +770,8 @@ pico_status_t pico_init(const pico_op_desc_t* d, void* stream, pico_op_t* out) {
   *out = op;
   return PICO_OK;
 }
+
+extern "C" {
 
 double pico_lambda_abs(pico_op_t op) { return op ? op->lam_abs : NAN; }
 

@@ -121,7 +121,9 @@ hipError_t launch_momentum(const float2* xn, float2* xo, float2* y, long total, 
 hipError_t launch_accum_abs2(const float2* u, double* sum, double* sum_im, double* sumsq, int K, long n,
                              hipStream_t s);
 hipError_t launch_fill_zero(float2* a, long total, hipStream_t s);
-hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, float* w,
+size_t toeplitz_scratch_bytes(long M, int ny, int nx);
+// synchronous on s; scratch: toeplitz_scratch_bytes(M, ny, nx) bytes of device memory
+hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, float* w, void* scratch,
                                   hipStream_t s);
 // complex128 GEMM (row-major; flags 1 transA, 2 conjA, 4 conjB; split-K slices
 // land in C[slice]); batch b offsets A, B, C by b * sA, sB, sC

@@ -3,9 +3,11 @@
 //   psf(d) = N_x^-1 sum_m exp(i w_m . d),  d in [-(ny-1), ny-1] x [-(nx-1), nx-1],
 // evaluated separably as a complex matrix product psf = E_y^T E_x with
 // E_y[m][j] = exp(i w_y,m (j - ny + 1)), E_x likewise (a dense contraction
-// over the M samples); circulant embedding in a 2ny x 2nx grid; its DFT by
+// over the M samples, taken in chunks of samples); circulant embedding in a 2ny x 2nx grid; its DFT by
 // two more products with DFT matrices; W = Re(DFT) / (4 ny nx), transposed.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "runtime.h"
 
@@ -81,9 +83,9 @@ __global__ __launch_bounds__(256) void k_zgemm(const z64* __restrict__ A, const 
     }
 }
 
-// sum over split-K slices in slice order, scaled
+// sum over split-K slices in slice order, scaled; added to out when accumulate
 __global__ void k_zsum_slices(const z64* __restrict__ parts, z64* __restrict__ out, long n, int S,
-                              double scale) {
+                              double scale, int accumulate) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double re = 0.0, im = 0.0;
@@ -91,7 +93,12 @@ __global__ void k_zsum_slices(const z64* __restrict__ parts, z64* __restrict__ o
     re += parts[(size_t)z * n + i].x;
     im += parts[(size_t)z * n + i].y;
   }
-  out[i] = make_double2(re * scale, im * scale);
+  z64 v = make_double2(re * scale, im * scale);
+  if (accumulate) {
+    v.x += out[i].x;
+    v.y += out[i].y;
+  }
+  out[i] = v;
 }
 
 // k[dy mod Gy][dx mod Gx] = psf[dy + ny - 1][dx + nx - 1]; zero elsewhere
@@ -141,40 +148,66 @@ static int zgemm_slices(int Kd, int splits) {
   return (Kd + kslice - 1) / kslice;
 }
 
-#define TZ_CHECK(x)                       \
-  do {                                    \
-    hipError_t e_ = (x);                  \
-    if (e_ != hipSuccess) { cleanup(); return e_; } \
+// samples per chunk of the separable PSF product (bounds the exponential tables)
+constexpr long kPsfChunk = 16384;
+constexpr int kPsfSplits = 4;
+
+static size_t piece(size_t count) { return (count * sizeof(z64) + 255) / 256 * 256; }
+
+struct ToeplitzScratch {
+  size_t off[9];
+  size_t total;
+  ToeplitzScratch(long M, int ny, int nx) {
+    const long Mc = std::min<long>(M, kPsfChunk);
+    const size_t Dy = 2 * ny - 1, Dx = 2 * nx - 1, Gy = 2 * ny, Gx = 2 * nx;
+    const int S = zgemm_slices((int)Mc, kPsfSplits);
+    const size_t sizes[9] = {piece(Mc * Dy), piece(Mc * Dx), piece((size_t)S * Dy * Dx), piece(Dy * Dx),
+                             piece(Gy * Gx),  piece(Gy * Gy), piece(Gx * Gx), piece(Gy * Gx), piece(Gy * Gx)};
+    total = 0;
+    for (int i = 0; i < 9; ++i) {
+      off[i] = total;
+      total += sizes[i];
+    }
+  }
+};
+
+size_t toeplitz_scratch_bytes(long M, int ny, int nx) { return ToeplitzScratch(M, ny, nx).total; }
+
+#define TZ_CHECK(x)                \
+  do {                             \
+    hipError_t e_ = (x);           \
+    if (e_ != hipSuccess) return e_; \
   } while (0)
 
-hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, float* w,
+hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, float* w, void* scratch,
                                   hipStream_t s) {
   const int Dy = 2 * ny - 1, Dx = 2 * nx - 1, Gy = 2 * ny, Gx = 2 * nx;
-  const int splits = (int)std::min<long>(16, std::max<long>(1, M / 4096));
-  const int S = zgemm_slices((int)M, splits);
-  z64 *Ey = nullptr, *Ex = nullptr, *parts = nullptr, *psf = nullptr, *kg = nullptr, *Fy = nullptr,
-      *Fx = nullptr, *t1 = nullptr, *kh = nullptr;
-  auto cleanup = [&] {
-    for (z64* p : {Ey, Ex, parts, psf, kg, Fy, Fx, t1, kh}) (void)hipFree(p);
-  };
-  TZ_CHECK(hipMalloc(&Ey, sizeof(z64) * M * Dy));
-  TZ_CHECK(hipMalloc(&Ex, sizeof(z64) * M * Dx));
-  TZ_CHECK(hipMalloc(&parts, sizeof(z64) * (size_t)S * Dy * Dx));
-  TZ_CHECK(hipMalloc(&psf, sizeof(z64) * (size_t)Dy * Dx));
-  TZ_CHECK(hipMalloc(&kg, sizeof(z64) * (size_t)Gy * Gx));
-  TZ_CHECK(hipMalloc(&Fy, sizeof(z64) * (size_t)Gy * Gy));
-  TZ_CHECK(hipMalloc(&Fx, sizeof(z64) * (size_t)Gx * Gx));
-  TZ_CHECK(hipMalloc(&t1, sizeof(z64) * (size_t)Gy * Gx));
-  TZ_CHECK(hipMalloc(&kh, sizeof(z64) * (size_t)Gy * Gx));
-  hipLaunchKernelGGL(k_exp_table, dim3((unsigned)((M * Dy + 255) / 256)), dim3(256), 0, s, traj, 0,
-                     -(ny - 1), Dy, (int)M, Ey);
-  hipLaunchKernelGGL(k_exp_table, dim3((unsigned)((M * Dx + 255) / 256)), dim3(256), 0, s, traj, 1,
-                     -(nx - 1), Dx, (int)M, Ex);
-  TZ_CHECK(hipGetLastError());
-  TZ_CHECK(zgemm64(Ey, Ex, parts, Dy, Dx, (int)M, 1, splits, s));
+  const ToeplitzScratch L(M, ny, nx);
+  char* base = static_cast<char*>(scratch);
+  z64* Ey = reinterpret_cast<z64*>(base + L.off[0]);
+  z64* Ex = reinterpret_cast<z64*>(base + L.off[1]);
+  z64* parts = reinterpret_cast<z64*>(base + L.off[2]);
+  z64* psf = reinterpret_cast<z64*>(base + L.off[3]);
+  z64* kg = reinterpret_cast<z64*>(base + L.off[4]);
+  z64* Fy = reinterpret_cast<z64*>(base + L.off[5]);
+  z64* Fx = reinterpret_cast<z64*>(base + L.off[6]);
+  z64* t1 = reinterpret_cast<z64*>(base + L.off[7]);
+  z64* kh = reinterpret_cast<z64*>(base + L.off[8]);
   const long npsf = (long)Dy * Dx;
-  hipLaunchKernelGGL(k_zsum_slices, dim3((unsigned)((npsf + 255) / 256)), dim3(256), 0, s, parts, psf,
-                     npsf, S, 1.0 / ((double)ny * nx));
+  // psf = (1 / (ny nx)) sum over sample chunks of E_y^T E_x, chunk by chunk in order
+  for (long m0 = 0; m0 < M; m0 += kPsfChunk) {
+    const int Mc = (int)std::min<long>(kPsfChunk, M - m0);
+    const int S = zgemm_slices(Mc, kPsfSplits);
+    const float* tr = traj + 2 * m0;
+    hipLaunchKernelGGL(k_exp_table, dim3((unsigned)(((long)Mc * Dy + 255) / 256)), dim3(256), 0, s, tr, 0,
+                       -(ny - 1), Dy, Mc, Ey);
+    hipLaunchKernelGGL(k_exp_table, dim3((unsigned)(((long)Mc * Dx + 255) / 256)), dim3(256), 0, s, tr, 1,
+                       -(nx - 1), Dx, Mc, Ex);
+    TZ_CHECK(hipGetLastError());
+    TZ_CHECK(zgemm64(Ey, Ex, parts, Dy, Dx, Mc, 1, kPsfSplits, s));
+    hipLaunchKernelGGL(k_zsum_slices, dim3((unsigned)((npsf + 255) / 256)), dim3(256), 0, s, parts, psf,
+                       npsf, S, 1.0 / ((double)ny * nx), m0 > 0 ? 1 : 0);
+  }
   const long ng = (long)Gy * Gx;
   hipLaunchKernelGGL(k_embed, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, psf, kg, ny, nx, Gy, Gx);
   hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)(((long)Gy * Gy + 255) / 256)), dim3(256), 0, s, Fy, Gy);
@@ -185,9 +218,7 @@ hipError_t build_toeplitz_weights(const float* traj, long M, int ny, int nx, flo
   hipLaunchKernelGGL(k_real_weights, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, kh, w, Gy, Gx,
                      1.0 / ((double)Gy * Gx));
   TZ_CHECK(hipGetLastError());
-  TZ_CHECK(hipStreamSynchronize(s));
-  cleanup();
-  return hipSuccess;
+  return hipStreamSynchronize(s);
 }
 
 }  // namespace pico

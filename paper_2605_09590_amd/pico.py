@@ -55,6 +55,15 @@ class pico_stats_t(ctypes.Structure):
                 ("lambda_abs", ctypes.c_double)]
 
 
+class pico_request_info_t(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("first_probe", ctypes.c_int64), ("probes", ctypes.c_int64),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double),
+                ("bytes_peak", ctypes.c_uint64), ("bytes_resident", ctypes.c_uint64),
+                ("error", ctypes.c_char * 160)]
+
+
 class PicoError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"pico status {status}: {msg}")
@@ -66,7 +75,9 @@ _lib = None
 EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_recon", "pico_noise_map", "pico_finalize",
            "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse", "pico_exact_diag",
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
-           "pico_last_error"]
+           "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
+           "pico_server_submit", "pico_server_poll", "pico_server_wait_idle", "pico_server_usage",
+           "pico_server_destroy"]
 PROF_KINDS = 8
 PROF_NAMES = ["normal_first", "normal_iter", "cg_update", "cg_scalars", "accumulate", "other"]
 
@@ -103,9 +114,24 @@ def load(path: str = LIB_PATH):
     lib.pico_destroy.restype = None
     lib.pico_last_error.argtypes = []
     lib.pico_last_error.restype = ctypes.c_char_p
+    lib.pico_estimate_bytes.argtypes = [ctypes.POINTER(pico_op_desc_t), ctypes.POINTER(u64),
+                                        ctypes.POINTER(u64)]
+    lib.pico_op_bytes.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.pico_server_create.argtypes = [u64, i32, i32, ctypes.POINTER(vp)]
+    lib.pico_server_submit.argtypes = [vp, ctypes.POINTER(pico_op_desc_t), u64, i64, i64, i32,
+                                       ctypes.POINTER(pico_accum_t), ctypes.POINTER(u64)]
+    lib.pico_server_poll.argtypes = [vp, ctypes.POINTER(pico_request_info_t), i32,
+                                     ctypes.POINTER(i32)]
+    lib.pico_server_wait_idle.argtypes = [vp, ctypes.c_double]
+    lib.pico_server_usage.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                      ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.pico_server_destroy.argtypes = [vp]
+    lib.pico_server_destroy.restype = None
     for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_recon", "pico_noise_map", "pico_finalize",
                  "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse",
-                 "pico_exact_diag", "pico_profile_start", "pico_profile_stop"):
+                 "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
+                 "pico_estimate_bytes", "pico_op_bytes", "pico_server_create", "pico_server_submit",
+                 "pico_server_poll", "pico_server_wait_idle", "pico_server_usage"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -131,23 +157,30 @@ def pico_last_error() -> str:
     return load().pico_last_error().decode()
 
 
-def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
+def _addr(x):
+    """Device address of a tensor (``data_ptr()``), an int address, or None."""
+    if x is None:
+        return None
+    return int(x) if isinstance(x, int) else x.data_ptr()
+
+
+def make_desc(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
               traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
-              wavelet_levels=4, stream=None):
-    """pico_init: ``maps`` complex64 device tensor [nc][ny][nx]; ``psi`` numpy
-    complex128 [nc][nc] or None; ``mask`` uint8 device tensor.  Returns the handle."""
-    lib = load()
+              wavelet_levels=4, ncoils=None):
+    """pico_op_desc_t for the arguments of pico_init; returns (desc, keep) where
+    ``keep`` holds the host psi array the descriptor points to."""
     d = pico_op_desc_t()
-    d.ny, d.nx, d.ncoils = int(ny), int(nx), int(maps.shape[0])
-    d.maps = maps.data_ptr()
+    d.ny, d.nx = int(ny), int(nx)
+    d.ncoils = int(ncoils if ncoils is not None else maps.shape[0])
+    d.maps = _addr(maps)
     keep = None
     if psi is not None:
         keep = np.ascontiguousarray(np.asarray(psi, np.complex128)).view(np.float64)
         d.psi = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     d.sampling = sampling
-    d.mask = mask.data_ptr() if mask is not None else None
-    d.traj = traj.data_ptr() if traj is not None else None
+    d.mask = _addr(mask)
+    d.traj = _addr(traj)
     d.nsamples = nsamples
     d.lambda_ = lam
     d.cg_iters = cg_iters
@@ -156,14 +189,40 @@ def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
     d.power_margin = power_margin
     d.probe_tile = probe_tile
     d.recon = recon
-    d.kdata = kdata.data_ptr() if kdata is not None else None
+    d.kdata = _addr(kdata)
     d.fista_iters = fista_iters
     d.cs_lambda = cs_lambda
     d.wavelet_levels = wavelet_levels
+    return d, keep
+
+
+def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
+              power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
+              traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
+              wavelet_levels=4, stream=None):
+    """pico_init: ``maps`` complex64 device tensor [nc][ny][nx]; ``psi`` numpy
+    complex128 [nc][nc] or None; ``mask`` uint8 device tensor.  Returns the handle."""
+    lib = load()
+    d, keep = make_desc(ny, nx, maps, psi, mask, sampling, lam, cg_iters, cg_tol, power_iters,
+                        power_margin, probe_tile, recon, traj, nsamples, kdata, fista_iters,
+                        cs_lambda, wavelet_levels)
     h = ctypes.c_void_p()
     _check(lib.pico_init(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
     del keep
     return h
+
+
+def pico_estimate_bytes(desc):
+    """(resident, peak) device bytes pico_init takes for ``desc`` (host only)."""
+    r, p = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().pico_estimate_bytes(ctypes.byref(desc), ctypes.byref(r), ctypes.byref(p)))
+    return r.value, p.value
+
+
+def pico_op_bytes(h):
+    r, p = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().pico_op_bytes(h, ctypes.byref(r), ctypes.byref(p)))
+    return r.value, p.value
 
 
 def pico_apply_cov(h, v, u, k, stream=None):
@@ -233,3 +292,89 @@ def pico_lambda_abs(h) -> float:
 
 def pico_destroy(h) -> None:
     load().pico_destroy(h)
+
+
+def pico_server_create(hbm_budget, max_slots=4, tiles_in_flight=2):
+    h = ctypes.c_void_p()
+    _check(load().pico_server_create(int(hbm_budget), int(max_slots), int(tiles_in_flight),
+                                     ctypes.byref(h)))
+    return h
+
+
+def pico_server_submit(srv, desc, seed, first_probe, nprobes, dist, acc) -> int:
+    rid = ctypes.c_uint64()
+    _check(load().pico_server_submit(srv, ctypes.byref(desc), int(seed), int(first_probe),
+                                     int(nprobes), int(dist), ctypes.byref(acc), ctypes.byref(rid)))
+    return rid.value
+
+
+def pico_server_poll(srv, max_n=256):
+    """Finished requests, oldest first, as dicts of pico_request_info_t fields."""
+    arr = (pico_request_info_t * max_n)()
+    n = ctypes.c_int32()
+    _check(load().pico_server_poll(srv, arr, max_n, ctypes.byref(n)))
+    out = []
+    for i in range(n.value):
+        r = arr[i]
+        out.append({"id": r.id, "status": r.status, "first_probe": r.first_probe,
+                    "probes": r.probes, "t_submit_ms": r.t_submit_ms,
+                    "t_admit_ms": r.t_admit_ms, "t_done_ms": r.t_done_ms,
+                    "bytes_peak": r.bytes_peak, "bytes_resident": r.bytes_resident,
+                    "error": r.error.decode(errors="replace")})
+    return out
+
+
+def pico_server_wait_idle(srv, timeout_s=-1.0):
+    return _check(load().pico_server_wait_idle(srv, float(timeout_s)))
+
+
+def pico_server_usage(srv):
+    b, u = ctypes.c_uint64(), ctypes.c_uint64()
+    q, a = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().pico_server_usage(srv, ctypes.byref(b), ctypes.byref(u), ctypes.byref(q),
+                                    ctypes.byref(a)))
+    return {"budget": b.value, "arena_used": u.value, "queued": q.value, "active": a.value}
+
+
+def pico_server_destroy(srv) -> None:
+    load().pico_server_destroy(srv)
+
+
+class Server:
+    """Owner of a pico_server_t.  ``submit`` takes the pico_init arguments plus
+    the probe range and an accumulator; the tensors it is given stay referenced
+    here until ``poll`` has reported the request."""
+
+    def __init__(self, hbm_budget, max_slots=4, tiles_in_flight=2):
+        self.h = pico_server_create(hbm_budget, max_slots, tiles_in_flight)
+        self._keep = {}
+
+    def submit(self, seed, first_probe, nprobes, acc, dist=0, **desc_kw):
+        d, keep = make_desc(**desc_kw)
+        rid = pico_server_submit(self.h, d, seed, first_probe, nprobes, dist, acc)
+        self._keep[rid] = (desc_kw, acc, keep)
+        return rid
+
+    def poll(self, max_n=256):
+        out = pico_server_poll(self.h, max_n)
+        for r in out:
+            self._keep.pop(r["id"], None)
+        return out
+
+    def wait_idle(self, timeout_s=-1.0):
+        return pico_server_wait_idle(self.h, timeout_s)
+
+    def usage(self):
+        return pico_server_usage(self.h)
+
+    def close(self):
+        if self.h:
+            pico_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

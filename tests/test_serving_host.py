@@ -1,0 +1,72 @@
+"""Host-side pieces of the serving loop: the arena's offset bookkeeping
+(compiled with g++ against the library's own header) and the device-byte
+estimate pico_init's admission uses (no GPU needed)."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2605_09590_amd", "csrc")
+
+
+def test_arena_bookkeeping(tmp_path):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "arena_check")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-I", CSRC, os.path.join(ROOT, "tests", "cpp", "arena_check.cpp"),
+                    "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "arena ok" in r.stdout
+
+
+@pytest.fixture(scope="module")
+def p():
+    from paper_2605_09590_amd import pico as p
+    p.load()
+    return p
+
+
+def _round(b):
+    return (max(b, 1) + 255) // 256 * 256
+
+
+def test_estimate_cart1d_closed_form(p):
+    d, _ = p.make_desc(320, 320, 0x1000, None, 0x2000, ncoils=15, probe_tile=256, cg_iters=30)
+    res, peak = p.pico_estimate_bytes(d)
+    n, K, nc = 320 * 320, 256, 15
+    expect = (_round(n * nc * 8) + 4 * _round(n * K * 8) + _round(K * 320 * 4 * 8) + _round(512 * 8)
+              + 4 * _round(K * 8) + _round(K * 4) + _round(320 * 4) + _round(320 * 8))
+    assert res == expect
+    assert peak == expect + _round(2 * nc * nc * 8)      # the whitening matrix during init
+
+
+def test_estimate_grows_with_tile_and_kind(p):
+    base, _ = p.make_desc(128, 128, 0x1000, None, 0x2000, ncoils=8, probe_tile=16,
+                          sampling=p.PICO_CART_2D)
+    r1, _ = p.pico_estimate_bytes(base)
+    big, _ = p.make_desc(128, 128, 0x1000, None, 0x2000, ncoils=8, probe_tile=32,
+                         sampling=p.PICO_CART_2D)
+    r2, _ = p.pico_estimate_bytes(big)
+    assert r2 > r1
+    cs, _ = p.make_desc(128, 128, 0x1000, None, 0x2000, ncoils=8, probe_tile=16,
+                        sampling=p.PICO_CART_2D, recon=p.PICO_CS_FISTA_L1WAV, kdata=0x3000,
+                        fista_iters=100, wavelet_levels=4)
+    rc, pc = p.pico_estimate_bytes(cs)
+    assert rc >= r1 + 100 * 128 * 128 * 16       # the stored FP64 coefficients
+    assert pc > rc                               # FP64 primal temporaries
+    sp, _ = p.make_desc(128, 128, 0x1000, None, None, ncoils=8, probe_tile=16,
+                        sampling=p.PICO_NONCART, traj=0x4000, nsamples=50000, lam=0.1)
+    rs, ps = p.pico_estimate_bytes(sp)
+    assert ps > rs                               # Toeplitz build scratch
+
+
+def test_estimate_validates(p):
+    d, _ = p.make_desc(63, 64, 0x1000, None, 0x2000, ncoils=4)
+    with pytest.raises(p.PicoError) as ei:
+        p.pico_estimate_bytes(d)
+    assert ei.value.status == p.PICO_EINVAL
