@@ -52,24 +52,150 @@ def normal_op_flops(ny, nx, nc):
     return nc * nx * per_line
 
 
-def cs_kspace(torch, dev, prob, seed=0):
-    """Raw multi-coil k-space b = P F_c (S x) + L n of the CS workload, formed on
-    the GPU with torch.fft (input synthesis, outside every timed region): the
-    phantom x, the raw maps S, centred orthonormal 2-D DFT F_c, noise with
-    covariance Psi = L L^H at the workload's input SNR over the sampled locations."""
+def cs_kspace_arrays(torch, dev, maps, psi, mask, x, snr_db, seed=0):
+    """Raw multi-coil k-space b = P F_c (S x) + L n, formed on the GPU with
+    torch.fft (input synthesis, outside every timed region): phantom x, raw maps
+    S, centred orthonormal 2-D DFT F_c, noise with covariance Psi = L L^H at the
+    given input SNR over the sampled locations."""
     import numpy as np
-    x = torch.from_numpy(prob.extra["phantom"].astype(np.complex128)).to(dev)
-    maps = torch.from_numpy(prob.maps.astype(np.complex128)).to(dev)
-    mask = torch.from_numpy(prob.mask.astype(np.float64)).to(dev)
+    x = torch.from_numpy(x.astype(np.complex128)).to(dev)
+    maps = torch.from_numpy(maps.astype(np.complex128)).to(dev)
+    mask = torch.from_numpy(mask.astype(np.float64)).to(dev)
     img = maps * x[None]
     k = torch.fft.fftshift(torch.fft.fft2(torch.fft.ifftshift(img, dim=(-2, -1)), norm="ortho"),
                            dim=(-2, -1)) * mask[None]
-    sig = torch.sqrt(torch.mean(torch.abs(k[:, mask > 0]) ** 2)) * 10 ** (-prob.extra["snr_db"] / 20)
+    sig = torch.sqrt(torch.mean(torch.abs(k[:, mask > 0]) ** 2)) * 10 ** (-snr_db / 20)
     rng = np.random.default_rng(seed + 1000)
     nz = rng.standard_normal(k.shape) + 1j * rng.standard_normal(k.shape)
-    L = torch.from_numpy(np.linalg.cholesky(prob.psi)).to(dev)
+    L = torch.from_numpy(np.linalg.cholesky(psi)).to(dev)
     n = torch.einsum("cd,dyx->cyx", L, torch.from_numpy(nz).to(dev)) * (sig / math.sqrt(2.0))
     return (k + n * mask[None]).to(torch.complex64).contiguous()
+
+
+def cs_kspace(torch, dev, prob, seed=0):
+    """k-space data of the CS workload (phantom, maps, Psi, mask of ``prob``)."""
+    return cs_kspace_arrays(torch, dev, prob.maps, prob.psi, prob.mask, prob.extra["phantom"],
+                            prob.extra["snr_db"], seed)
+
+
+def serve_requests(workloads, torch, np, dev, n_req, sizes, coils, probes, seed=0):
+    """Seeded request mix of the serving workload: kind Cartesian (phase-encode
+    R=2 + 24 ACS, CG 30) / spiral (48x4096 interleaves at R=2, lambda 0.1, CG 30) /
+    CS (Poisson-disc R=2 + 24x24 calibration, FISTA 100, lambda 1e-3, 4 db4
+    levels) with probabilities 0.4 / 0.4 / 0.2, matrix size from ``sizes``,
+    coils uniform in ``coils``, probes from ``probes``; device inputs resident."""
+    rng = np.random.default_rng(seed)
+    cache = {}
+    out = []
+    for i in range(n_req):
+        kind = ["cart", "spiral", "cs"][rng.choice(3, p=[0.4, 0.4, 0.2])]
+        n = int(rng.choice(sizes))
+        nc = int(rng.integers(coils[0], coils[1] + 1))
+        P = int(rng.choice(probes))
+        r = np.random.default_rng(seed * 1000 + i)
+        maps = workloads.coil_maps(n, n, nc, r)
+        psi = workloads.noise_cov(nc, r)
+        kw = dict(ny=n, nx=n, maps=torch.from_numpy(maps.astype(np.complex64)).to(dev), psi=psi)
+        if kind == "cart":
+            kw.update(mask=torch.from_numpy(workloads.cart_mask_1d(n, 2, 24)).to(dev), cg_iters=30,
+                      probe_tile=min(P, 256))
+        elif kind == "spiral":
+            if ("traj", n) not in cache:
+                cache[("traj", n)] = torch.from_numpy(workloads.spiral_traj(n, 2).astype(np.float32)).to(dev)
+            traj = cache[("traj", n)]
+            kw.update(mask=None, sampling=2, lam=0.1, cg_iters=30, probe_tile=min(P, 128), traj=traj,
+                      nsamples=traj.shape[0])
+        else:
+            if ("pd", n) not in cache:
+                cache[("pd", n)] = workloads.poisson_disc_mask(n, n, 2.0, 24, seed=n)
+            mask = cache[("pd", n)]
+            x = workloads.phantom(n, r)
+            kd = cs_kspace_arrays(torch, dev, maps, psi, mask, x, 45.0, seed=i)
+            kw.update(mask=torch.from_numpy(mask).to(dev), sampling=1, recon=1, kdata=kd,
+                      fista_iters=100, cs_lambda=1e-3, wavelet_levels=4, probe_tile=min(P, 128))
+        out.append({"kind": kind, "n": n, "nc": nc, "probes": P, "kw": kw})
+    return out
+
+
+def serve_run(lib, torch, dev, reqs, budget, slots, depth, arrivals=None, seed=0):
+    """Submit every request (at the given arrival times in s, else all at once)
+    to a fresh server; returns (per-request info in submission order, accumulators)."""
+    import threading
+    accs = [[torch.zeros(r["n"] * r["n"], dtype=torch.float64, device=dev) for _ in range(2)]
+            for r in reqs]
+    torch.cuda.synchronize()
+    srv = lib.Server(budget, slots, depth)
+    ids = [None] * len(reqs)
+    err = []
+
+    def feeder():
+        t0 = time.perf_counter()
+        try:
+            for i, r in enumerate(reqs):
+                if arrivals is not None:
+                    dt = arrivals[i] - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                ids[i] = srv.submit(seed + i, 0, r["probes"], lib.make_accum(accs[i][0], None, accs[i][1]),
+                                    **r["kw"])
+        except Exception as e:     # reported by the caller
+            err.append(e)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    if err:
+        srv.close()
+        raise err[0]
+    srv.wait_idle(600.0)
+    done = {d["id"]: d for d in srv.poll(len(reqs) + 8)}
+    srv.close()
+    torch.cuda.synchronize()
+    return [done[i] for i in ids], accs
+
+
+def serve_leg(lib, workloads, torch, np, dev, full):
+    """p50 / p99 request latency of the serving loop under Poisson arrivals."""
+    if full:
+        sizes, coils, probes, n_req, rhos = [128, 160, 192, 256, 288, 320, 384], (8, 32), \
+            [64, 128, 256, 512], 200, [0.25, 0.5, 0.75, 0.9, 1.1]
+    else:
+        sizes, coils, probes, n_req, rhos = [128, 160, 192, 256], (8, 16), [64, 128, 256], 32, [0.5, 0.9]
+    budget, slots, depth = 64 << 30, 4, 2
+    reqs = serve_requests(workloads, torch, np, dev, n_req, sizes, coils, probes)
+    serve_run(lib, torch, dev, reqs[:3], budget, 1, depth)           # warm-up (first launches)
+    seq, ref = serve_run(lib, torch, dev, reqs, budget, 1, depth)
+    assert all(d["status"] == 0 for d in seq), [d["error"] for d in seq if d["status"]]
+    service = [d["t_done_ms"] - d["t_admit_ms"] for d in seq]
+    span_s = (max(d["t_done_ms"] for d in seq) - min(d["t_submit_ms"] for d in seq)) / 1e3
+    capacity = n_req / span_s
+    rates = []
+    for rho in rhos:
+        lam = rho * capacity
+        arr = np.cumsum(np.random.default_rng(int(rho * 1000)).exponential(1.0 / lam, n_req))
+        info, accs = serve_run(lib, torch, dev, reqs, budget, slots, depth, arrivals=arr)
+        assert all(d["status"] == 0 for d in info), [d["error"] for d in info if d["status"]]
+        lat = np.array([d["t_done_ms"] - d["t_submit_ms"] for d in info])
+        wait = np.array([d["t_admit_ms"] - d["t_submit_ms"] for d in info])
+        span = (max(d["t_done_ms"] for d in info) - min(d["t_submit_ms"] for d in info)) / 1e3
+        same = all(torch.equal(a, b) for x, y in zip(accs, ref) for a, b in zip(x, y))
+        rates.append({"rho": rho, "arrival_rate_per_s": round(lam, 3),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                      "mean_ms": round(float(lat.mean()), 2),
+                      "mean_queue_wait_ms": round(float(wait.mean()), 2),
+                      "makespan_s": round(span, 3),
+                      "probe_solves_per_s": round(sum(r["probes"] for r in reqs) / span, 1),
+                      "results_identical_to_sequential": bool(same)})
+    kinds = {k: sum(r["kind"] == k for r in reqs) for k in ("cart", "spiral", "cs")}
+    return {
+        "workload": f"{n_req} requests (kinds {kinds}), matrix {sizes}, coils U{{{coils[0]}..{coils[1]}}}, "
+                    f"probes {probes}; Poisson arrivals at rho x the sequential capacity; "
+                    f"budget {budget >> 30} GiB, {slots} slots, {depth} tiles in flight",
+        "capacity_req_per_s": round(capacity, 3),
+        "mean_service_ms": round(float(np.mean(service)), 2),
+        "rates": rates,
+    }
 
 
 def cs_leg(lib, workloads, torch, np, dev, steps):
@@ -131,6 +257,8 @@ def main():
                     help="steps of the spiral Toeplitz leg (0 to skip)")
     ap.add_argument("--cs-steps", type=int, default=1,
                     help="steps of the compressed-sensing JVP leg (0 to skip)")
+    ap.add_argument("--serve", choices=["off", "short", "full"], default="short",
+                    help="serving leg: short request mix (default), the full sweep, or off")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -295,6 +423,11 @@ def main():
     if args.cs_steps > 0:
         cs_res = cs_leg(lib, workloads, torch, np, dev, args.cs_steps)
 
+    # --- serving: mixed requests under Poisson arrivals, p50 / p99 latency
+    serving = None
+    if args.serve != "off":
+        serving = serve_leg(lib, workloads, torch, np, dev, args.serve == "full")
+
     # --- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -326,6 +459,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "spiral": spiral,
         "cs": cs_res,
+        "serving": serving,
     }
     if args.copy_calib:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB

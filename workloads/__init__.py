@@ -11,7 +11,9 @@ are not available; these generators stand in for them with the same matrix
 sizes, channel counts, acceleration factors and calibration regions
 (Sec. 3.1-3.2).  No data-set item is reproduced.
 
-Every draw uses ``numpy.random.default_rng(seed)`` in a fixed order.
+Every draw uses ``numpy.random.default_rng(seed)`` in a fixed order, except
+the Poisson-disc dart throwing, which runs in C (poisson_disc.c, built with
+gcc on first use) on a SplitMix64 stream seeded by ``seed``.
 """
 from __future__ import annotations
 
@@ -123,61 +125,40 @@ def spiral_traj(n: int, R: int = 1, interleaves: int = 48, samples: int = 4096) 
     return np.concatenate(out, axis=0)
 
 
-def _poisson_disc(ny: int, nx: int, r0: float, calib: int, rng: np.random.Generator,
-                  k: int = 30) -> np.ndarray:
-    """Bridson dart throwing with radius r(k) = r0 (1 + 2 |k| / kmax)."""
-    cy, cx = ny / 2, nx / 2
-    kmax = math.hypot(cy, cx)
+_PD_LIB = None
 
-    def rad(p):
-        return r0 * (1 + 2 * math.hypot(p[0] - cy, p[1] - cx) / kmax)
 
-    cell = r0 / math.sqrt(2)
-    gh, gw = int(ny / cell) + 1, int(nx / cell) + 1
-    grid = -np.ones((gh, gw), np.int64)
-    pts = []
-    active = []
-    p0 = (cy, cx)
-    pts.append(p0)
-    active.append(0)
-    grid[int(p0[0] / cell), int(p0[1] / cell)] = 0
-    rmax = r0 * 3
-    reach = int(math.ceil(rmax / cell))
-    while active:
-        ai = int(rng.integers(len(active)))
-        base = pts[active[ai]]
-        rb = rad(base)
-        found = False
-        for _ in range(k):
-            rr = rng.uniform(rb, 2 * rb)
-            th = rng.uniform(0, 2 * math.pi)
-            q = (base[0] + rr * math.sin(th), base[1] + rr * math.cos(th))
-            if not (0 <= q[0] < ny and 0 <= q[1] < nx):
-                continue
-            gy, gx = int(q[0] / cell), int(q[1] / cell)
-            rq = rad(q)
-            ok = True
-            for yy in range(max(gy - reach, 0), min(gy + reach + 1, gh)):
-                for xx in range(max(gx - reach, 0), min(gx + reach + 1, gw)):
-                    idx = grid[yy, xx]
-                    if idx >= 0:
-                        o = pts[idx]
-                        if math.hypot(o[0] - q[0], o[1] - q[1]) < min(rq, rad(o)):
-                            ok = False
-                            break
-                if not ok:
-                    break
-            if ok:
-                pts.append(q)
-                grid[gy, gx] = len(pts) - 1
-                active.append(len(pts) - 1)
-                found = True
-                break
-        if not found:
-            active.pop(ai)
+def _pd_lib():
+    """The C dart-throwing sampler (poisson_disc.c), built with gcc on first use."""
+    global _PD_LIB
+    if _PD_LIB is not None:
+        return _PD_LIB
+    import ctypes
+    import os
+    import subprocess
+    import tempfile
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "poisson_disc.c")
+    so = os.path.join(here, "_poisson_disc.so")
+    if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+        fd, tmp = tempfile.mkstemp(suffix=".so", dir=here)
+        os.close(fd)
+        subprocess.run(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src, "-lm"], check=True)
+        os.replace(tmp, so)
+    lib = ctypes.CDLL(so)
+    lib.poisson_disc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_uint64, ctypes.c_void_p]
+    lib.poisson_disc.restype = ctypes.c_int
+    _PD_LIB = lib
+    return lib
+
+
+def _poisson_disc(ny: int, nx: int, r0: float, calib: int, seed: int, k: int = 30) -> np.ndarray:
+    """Bridson dart throwing with radius r(k) = r0 (1 + 2 |k| / kmax), plus the
+    calib x calib fully sampled centre."""
     m = np.zeros((ny, nx), np.uint8)
-    for (py, px) in pts:
-        m[min(int(py), ny - 1), min(int(px), nx - 1)] = 1
+    if _pd_lib().poisson_disc(ny, nx, float(r0), k, seed & (2**64 - 1), m.ctypes.data) < 0:
+        raise MemoryError("poisson_disc")
     m[ny // 2 - calib // 2: ny // 2 + calib // 2, nx // 2 - calib // 2: nx // 2 + calib // 2] = 1
     return m
 
@@ -193,7 +174,7 @@ def poisson_disc_mask(ny: int, nx: int, R: float, calib: int, seed: int,
     best = None
     for _ in range(30):
         r0 = 0.5 * (lo + hi)
-        m = _poisson_disc(ny, nx, r0, calib, np.random.default_rng(seed))
+        m = _poisson_disc(ny, nx, r0, calib, seed)
         acc = m.size / m.sum()
         best = m
         if abs(acc - R) <= tol * R:
