@@ -101,6 +101,14 @@ typedef struct {
   int32_t fista_iters;          /* FISTA iterations T (paper: 100)                 */
   double cs_lambda;             /* L1 weight of the normalised problem            */
   int32_t wavelet_levels;       /* db4 levels; ny, nx divisible by 2^levels       */
+  /* PICO_NONCART data path (A, A^H of sample arrays; PMR replicas) by a
+   * Kaiser-Bessel gridding NUFFT (Sec. 3.2.2, 3.3); kb_width = 0 builds none.
+   * Grid oversamp * n per axis (an integer with a built FFT length), kernel
+   * I0(beta sqrt(1 - (2u/W)^2)), beta = pi sqrt((W/oversamp)^2 (oversamp -
+   * 1/2)^2 - 0.8), W = kb_width even in 2..8.  The normal operator of the
+   * CG solves is the exact Toeplitz form either way. */
+  double oversamp;              /* e.g. 2.0 (or 1.25)                             */
+  int32_t kb_width;             /* e.g. 6 (or 4); 0 = no gridding data path       */
 } pico_op_desc_t;
 
 /* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a
@@ -221,6 +229,17 @@ enum {
 };
 pico_status_t pico_profile_start(pico_op_t op);
 pico_status_t pico_profile_stop(pico_op_t op, double* ms, int64_t* launches);
+
+/* Gridding NUFFT data path of a PICO_NONCART operator built with kb_width > 0
+ * (Sec. 3.2.2, 3.3; the reading of the gridding parameters is the one stated
+ * at pico_op_desc_t.oversamp).  adjoint = 0: out[k][ncoils][nsamples] = A x
+ * for x = in[k][ny][nx]; adjoint = 1: out[k][ny][nx] = A^H y for
+ * y = in[k][ncoils][nsamples] (whitened coil samples).  complex64 device
+ * arrays, 1 <= k <= probe_tile.  Uses the operator's scratch, so calls on one
+ * operator must not overlap.  Errors: PICO_EUNSUPPORTED without a gridding
+ * path, PICO_EINVAL, PICO_EDEVICE. */
+pico_status_t pico_apply_nufft(pico_op_t op, int32_t adjoint, const void* in, void* out, int32_t k,
+                               void* stream);
 
 /* Release the operator and its device memory (waits for its last stream). */
 void pico_destroy(pico_op_t op);

@@ -88,24 +88,35 @@ def toeplitz_kernel(traj: np.ndarray, ny: int, nx: int) -> np.ndarray:
 
 
 class NonCartOp:
-    """Whitened non-Cartesian SENSE operator with an exact (NUDFT) encoding.
+    """Whitened non-Cartesian SENSE operator.
 
-    ``normal`` uses the Toeplitz embedding, which equals A^H A exactly.
+    ``normal`` uses the Toeplitz embedding, which equals the NUDFT's A^H A
+    exactly.  ``forward`` / ``adjoint`` (the data path: reconstruction of
+    k-space data and PMR replicas) are the direct NUDFT, or the Kaiser-Bessel
+    gridding NUFFT of oracle/kbnufft.py when ``kb = (sigma, W)`` is given.
     """
 
-    def __init__(self, maps, psi, traj):
+    def __init__(self, maps, psi, traj, kb=None):
         self.Sw = whiten_maps(maps, psi)
         self.nc, self.ny, self.nx = self.Sw.shape
         self.traj = np.asarray(traj, np.float64)
         self.M = self.traj.shape[0]
         self.Kh = toeplitz_kernel(self.traj, self.ny, self.nx)
+        self.kb = None
+        if kb is not None:
+            from .kbnufft import KBGridding
+            self.kb = KBGridding(self.traj, self.ny, self.nx, *kb)
 
     def forward(self, x):
         """A x -> [nc][M]."""
+        if self.kb is not None:
+            return np.stack([self.kb.forward(self.Sw[c] * x) for c in range(self.nc)])
         return np.stack([nudft_forward(self.Sw[c] * x, self.traj) for c in range(self.nc)])
 
     def adjoint(self, y):
         """A^H y -> image."""
+        if self.kb is not None:
+            return sum(np.conj(self.Sw[c]) * self.kb.adjoint(y[c]) for c in range(self.nc))
         return sum(np.conj(self.Sw[c]) * nudft_adjoint(y[c], self.traj, (self.ny, self.nx))
                    for c in range(self.nc))
 

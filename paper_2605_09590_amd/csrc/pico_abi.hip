@@ -75,6 +75,9 @@ struct pico_op_s {
   double2* ctraj = nullptr;     // [T][ny][nx] stored Psi z_k of the FP64 primal
   float2* xrec = nullptr;       // reconstruction
   uint8_t* mask_d = nullptr;    // [ny][nx] (Cartesian 2-D)
+  // Kaiser-Bessel gridding data path (non-Cartesian, kb_width > 0)
+  bool has_kb = false;
+  pico::KbOp kb;
   // device memory: from hipMalloc, or from a serving arena when one is set;
   // bytes are counted in 256-byte pieces (current and peak)
   pico::DeviceArena* arena = nullptr;
@@ -469,6 +472,75 @@ hipError_t cs_tangents(pico_op_t op, int K, const float2* w, uint64_t seed, uint
   return fista_tangent(op, K, s);
 }
 
+bool kb_grid_dims(const pico_op_desc_t* d, int G[2]);
+
+// Kaiser-Bessel tables of a non-Cartesian operator: device buffers in the
+// kb_layout order, tap weights and the spreading CSR built on the host
+hipError_t build_kb(pico_op_t op, const pico_op_desc_t* d, hipStream_t s) {
+  int G[2];
+  kb_grid_dims(d, G);
+  pico::KbOp& o = op->kb;
+  o.M = d->nsamples;
+  o.W = d->kb_width;
+  o.ny = op->ny;
+  o.nx = op->nx;
+  o.Gy = G[0];
+  o.Gx = G[1];
+  const pico::KbLayout L = pico::kb_layout(o.M, o.W, o.ny, o.nx, o.Gy, o.Gx, op->K);
+  hipError_t e;
+  char* part[pico::KbLayout::kParts];
+  for (int i = 0; i < pico::KbLayout::kParts; ++i)
+    if ((e = op->alloc(&part[i], L.bytes_of(i))) != hipSuccess) return e;
+  o.ky0 = (int*)part[0];
+  o.kx0 = (int*)part[1];
+  o.wy = (float*)part[2];
+  o.wx = (float*)part[3];
+  o.rowptr = (int*)part[4];
+  o.ent_m = (int*)part[5];
+  o.ent_w = (float*)part[6];
+  o.dy = (float*)part[7];
+  o.dx = (float*)part[8];
+  o.twx = (float2*)part[9];
+  o.twy = (float2*)part[10];
+  o.grid = (float2*)part[11];
+  o.samples = (float2*)part[12];
+  std::vector<float> traj((size_t)2 * o.M);
+  if ((e = hipMemcpyAsync(traj.data(), d->traj, traj.size() * sizeof(float), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  std::vector<int> ky0, kx0, rowptr, ent_m;
+  std::vector<float> wy, wx, ent_w, dy, dx;
+  pico::kb_build_host(traj.data(), o.M, o.W, d->oversamp, o.ny, o.nx, o.Gy, o.Gx, ky0, kx0, wy, wx, rowptr,
+                      ent_m, ent_w, dy, dx);
+  const std::vector<float2> tx = twiddle_table(o.Gx), ty = twiddle_table(o.Gy);
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  if ((e = up(o.ky0, ky0.data(), ky0.size() * 4)) != hipSuccess || (e = up(o.kx0, kx0.data(), kx0.size() * 4)) != hipSuccess ||
+      (e = up(o.wy, wy.data(), wy.size() * 4)) != hipSuccess || (e = up(o.wx, wx.data(), wx.size() * 4)) != hipSuccess ||
+      (e = up(o.rowptr, rowptr.data(), rowptr.size() * 4)) != hipSuccess ||
+      (e = up(o.ent_m, ent_m.data(), ent_m.size() * 4)) != hipSuccess ||
+      (e = up(o.ent_w, ent_w.data(), ent_w.size() * 4)) != hipSuccess || (e = up(o.dy, dy.data(), dy.size() * 4)) != hipSuccess ||
+      (e = up(o.dx, dx.data(), dx.size() * 4)) != hipSuccess || (e = up(o.twx, tx.data(), tx.size() * 8)) != hipSuccess ||
+      (e = up(o.twy, ty.data(), ty.size() * 8)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;   // host vectors go out of scope
+  op->has_kb = true;
+  return hipSuccess;
+}
+
+// gridding grid size [Gy, Gx] = oversamp * [ny, nx]; false unless both are integers > n
+bool kb_grid_dims(const pico_op_desc_t* d, int G[2]) {
+  if (!(d->oversamp > 1.0) || !(d->oversamp <= 4.0)) return false;
+  const int n[2] = {d->ny, d->nx};
+  for (int i = 0; i < 2; ++i) {
+    const double g = d->oversamp * n[i];
+    const long r = std::lround(g);
+    if (std::fabs(g - (double)r) > 1e-9 || r <= n[i]) return false;
+    G[i] = (int)r;
+  }
+  return true;
+}
+
 pico_status_t validate(const pico_op_desc_t* d) {
   if (d->recon != PICO_CGSENSE && d->recon != PICO_CS_FISTA_L1WAV)
     return fail(PICO_EUNSUPPORTED, "unknown reconstruction kind");
@@ -510,6 +582,21 @@ pico_status_t validate(const pico_op_desc_t* d) {
     return fail(PICO_EINVAL, "traj and 1 <= nsamples <= 2^30 are required for non-Cartesian sampling");
   if (d->lambda > 0.0 && (d->power_iters < 1 || !(d->power_margin > 0.0)))
     return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
+  if (d->kb_width != 0) {
+    if (d->sampling != PICO_NONCART) return fail(PICO_EINVAL, "kb_width applies to PICO_NONCART only");
+    if (d->kb_width < 2 || d->kb_width > 8 || (d->kb_width & 1))
+      return fail(PICO_EINVAL, "kb_width must be even in 2..8");
+    int G[2];
+    if (!kb_grid_dims(d, G)) return fail(PICO_EINVAL, "oversamp * ny and oversamp * nx must be integers > n");
+    for (int g : G)
+      if (!pico::grid_line_supported(g))
+        return fail(PICO_EINVAL, "gridding length " + std::to_string(g) +
+                                     " has no built FFT length (64 96 128 160 192 256 288 320 384 512 576 640 768)");
+    if (pico::grid_cols_lds_bytes(G[0], G[0]) > 160 * 1024)
+      return fail(PICO_EINVAL, "gridding column pass does not fit the 160 KiB LDS");
+    if ((double)d->nsamples * d->kb_width * d->kb_width >= 2147483647.0)
+      return fail(PICO_EINVAL, "nsamples * kb_width^2 must stay below 2^31");
+  }
   return PICO_OK;
 }
 
@@ -561,6 +648,12 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
       const size_t sc = toeplitz_scratch_bytes(d->nsamples, d->ny, d->nx);
       add(sc);
       sub(sc);
+      if (d->kb_width > 0) {
+        int G[2];
+        kb_grid_dims(d, G);
+        const KbLayout L = kb_layout(d->nsamples, d->kb_width, d->ny, d->nx, G[0], G[1], d->probe_tile);
+        for (int i = 0; i < KbLayout::kParts; ++i) add(L.bytes_of(i));
+      }
     }
   }
   if (d->sampling == PICO_CART_2D) add(n);
@@ -701,6 +794,9 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
       if ((e = op->alloc(&scratch, pico::toeplitz_scratch_bytes(d->nsamples, ny, nx))) != hipSuccess) return bad(e, "Toeplitz scratch");
       if ((e = pico::build_toeplitz_weights(d->traj, d->nsamples, ny, nx, op->w, scratch, s)) != hipSuccess) return bad(e, "Toeplitz weights");
       op->release(scratch);
+      if (d->kb_width > 0) {
+        if ((e = build_kb(op, d, s)) != hipSuccess) return bad(e, "gridding tables");
+      }
     }
   }
 
@@ -796,6 +892,20 @@ pico_status_t pico_recon(pico_op_t op, void* x, void* stream) {
   return PICO_OK;
 }
 
+pico_status_t pico_apply_nufft(pico_op_t op, int32_t adjoint, const void* in, void* out, int32_t k,
+                               void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!op->has_kb) return fail(PICO_EUNSUPPORTED, "the operator has no gridding data path (PICO_NONCART, kb_width > 0)");
+  if (!in || !out) return fail(PICO_EINVAL, "NULL input or output");
+  if (k < 1 || k > op->K) return fail(PICO_EINVAL, "k must be in 1..probe_tile");
+  if (adjoint != 0 && adjoint != 1) return fail(PICO_EINVAL, "adjoint must be 0 or 1");
+  hipStream_t s = (hipStream_t)stream;
+  op->last_stream = s;
+  if (adjoint) HIP_OR_RETURN(pico::kb_adjoint(op->kb, op->maps, op->nc, k, (const float2*)in, 0, 0, (float2*)out, s));
+  else HIP_OR_RETURN(pico::kb_forward(op->kb, op->maps, op->nc, k, (const float2*)in, (float2*)out, s));
+  return PICO_OK;
+}
+
 pico_status_t pico_apply_cov(pico_op_t op, const void* v, void* u, int32_t k, void* stream) {
   if (pico_status_t st = check_op(op)) return st;
   if (op->cs) return fail(PICO_EUNSUPPORTED, "a compressed-sensing operator has no linear covariance; use pico_apply_jvp");
@@ -870,7 +980,8 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
     return fail(PICO_EINVAL, "PMR needs sum, sum_im and sumsq buffers");
   if (nrep < 0 || first < 0) return fail(PICO_EINVAL, "negative replica range");
   if (op->cs) return fail(PICO_EUNSUPPORTED, "PMR is built for CG-SENSE operators");
-  if (op->sampling == PICO_NONCART) return fail(PICO_EUNSUPPORTED, "PMR is built for Cartesian sampling");
+  if (op->sampling == PICO_NONCART && !op->has_kb)
+    return fail(PICO_EUNSUPPORTED, "PMR on non-Cartesian sampling needs the gridding data path (kb_width > 0)");
   hipStream_t s = (hipStream_t)stream;
   op->last_stream = s;
   StatAcc sa;
@@ -882,6 +993,11 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
       c.seed = seed;
       c.first = f;
       HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] { return launch_normal(op, K, pico::C1_PMR_RHS, c, s); }));
+    } else if (op->sampling == PICO_NONCART) {
+      // r = A^H n by gridding, CN(0, I) noise on every coil sample (Philox stream 1)
+      HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] {
+        return pico::kb_adjoint(op->kb, op->maps, op->nc, K, nullptr, seed, f, op->r, s);
+      }));
     } else {
       // r = A^H n, white Gaussian k-space noise on the mask (Philox stream 1)
       HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] {

@@ -1,8 +1,10 @@
-// Internal interface between the host runtime (pico.cpp) and the kernel
+// Internal interface between the host runtime (pico_abi.hip, serve.hip) and the kernel
 // launchers (*.hip).  Not part of the public C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 namespace pico {
@@ -153,6 +155,36 @@ hipError_t cs64_fista(const Cs64& o, const double2* atb, double s2, double lam, 
                       const double* theta, double2* ctraj, double2* y, double2* x, double2* z,
                       double2* tmp, double2* q, hipStream_t s);
 hipError_t launch_to_f32(const double2* a, float2* b, long n, hipStream_t s);
+
+// Kaiser-Bessel gridding NUFFT (non-Cartesian data path)
+struct KbLayout {
+  static constexpr int kParts = 13;   // ky0 kx0 wy wx rowptr ent_m ent_w dy dx twx twy grid samples
+  size_t sizes[kParts];
+  size_t bytes_of(size_t i) const;
+};
+KbLayout kb_layout(long M, int W, int ny, int nx, int Gy, int Gx, int K);
+struct KbOp {
+  long M = 0;
+  int W = 0, ny = 0, nx = 0, Gy = 0, Gx = 0;
+  int *ky0 = nullptr, *kx0 = nullptr;   // [M] first tap index per axis (mod G)
+  float *wy = nullptr, *wx = nullptr;   // [M][W] tap weights
+  int* rowptr = nullptr;                // [Gy Gx + 1] CSR of the spreading gather
+  int* ent_m = nullptr;                 // [M W W] sample of each entry
+  float* ent_w = nullptr;               // [M W W] weight of each entry
+  float *dy = nullptr, *dx = nullptr;   // de-apodisation [ny], [nx]
+  float2 *twx = nullptr, *twy = nullptr;
+  float2* grid = nullptr;               // [K][Gy][Gx]
+  float2* samples = nullptr;            // [K][M] noise staging
+};
+double kb_beta(double sigma, int W);
+void kb_build_host(const float* traj_h, long M, int W, double sigma, int ny, int nx, int Gy, int Gx,
+                   std::vector<int>& ky0, std::vector<int>& kx0, std::vector<float>& wy,
+                   std::vector<float>& wx, std::vector<int>& rowptr, std::vector<int>& ent_m,
+                   std::vector<float>& ent_w, std::vector<float>& dy, std::vector<float>& dx);
+hipError_t kb_adjoint(const KbOp& o, const float2* maps, int nc, int K, const float2* src, uint64_t seed,
+                      uint64_t first, float2* out, hipStream_t s);
+hipError_t kb_forward(const KbOp& o, const float2* maps, int nc, int K, const float2* x, float2* out,
+                      hipStream_t s);
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
 hipError_t launch_final_x(const FinalArgs& a, hipStream_t s);
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);

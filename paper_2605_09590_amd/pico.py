@@ -41,6 +41,8 @@ class pico_op_desc_t(ctypes.Structure):
         ("fista_iters", ctypes.c_int32),
         ("cs_lambda", ctypes.c_double),
         ("wavelet_levels", ctypes.c_int32),
+        ("oversamp", ctypes.c_double),
+        ("kb_width", ctypes.c_int32),
     ]
 
 
@@ -72,7 +74,7 @@ class PicoError(RuntimeError):
 
 _lib = None
 
-EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_recon", "pico_noise_map", "pico_finalize",
+EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
            "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse", "pico_exact_diag",
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
@@ -95,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.pico_init.argtypes = [ctypes.POINTER(pico_op_desc_t), vp, ctypes.POINTER(vp)]
     lib.pico_apply_cov.argtypes = [vp, vp, vp, i32, vp]
     lib.pico_apply_jvp.argtypes = [vp, vp, vp, i32, vp]
+    lib.pico_apply_nufft.argtypes = [vp, i32, vp, vp, i32, vp]
     lib.pico_recon.argtypes = [vp, vp, vp]
     lib.pico_noise_map.argtypes = [vp, u64, i64, i64, i32, ctypes.POINTER(pico_accum_t),
                                    ctypes.POINTER(pico_stats_t), vp]
@@ -127,7 +130,7 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pico_server_destroy.argtypes = [vp]
     lib.pico_server_destroy.restype = None
-    for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_recon", "pico_noise_map", "pico_finalize",
+    for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
                  "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse",
                  "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
                  "pico_estimate_bytes", "pico_op_bytes", "pico_server_create", "pico_server_submit",
@@ -167,7 +170,7 @@ def _addr(x):
 def make_desc(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
               traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
-              wavelet_levels=4, ncoils=None):
+              wavelet_levels=4, oversamp=2.0, kb_width=0, ncoils=None):
     """pico_op_desc_t for the arguments of pico_init; returns (desc, keep) where
     ``keep`` holds the host psi array the descriptor points to."""
     d = pico_op_desc_t()
@@ -193,19 +196,21 @@ def make_desc(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
     d.fista_iters = fista_iters
     d.cs_lambda = cs_lambda
     d.wavelet_levels = wavelet_levels
+    d.oversamp = oversamp
+    d.kb_width = kb_width
     return d, keep
 
 
 def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
               traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
-              wavelet_levels=4, stream=None):
+              wavelet_levels=4, oversamp=2.0, kb_width=0, stream=None):
     """pico_init: ``maps`` complex64 device tensor [nc][ny][nx]; ``psi`` numpy
     complex128 [nc][nc] or None; ``mask`` uint8 device tensor.  Returns the handle."""
     lib = load()
     d, keep = make_desc(ny, nx, maps, psi, mask, sampling, lam, cg_iters, cg_tol, power_iters,
                         power_margin, probe_tile, recon, traj, nsamples, kdata, fista_iters,
-                        cs_lambda, wavelet_levels)
+                        cs_lambda, wavelet_levels, oversamp, kb_width)
     h = ctypes.c_void_p()
     _check(lib.pico_init(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
     del keep
@@ -227,6 +232,10 @@ def pico_op_bytes(h):
 
 def pico_apply_cov(h, v, u, k, stream=None):
     return _check(load().pico_apply_cov(h, _ptr(v), _ptr(u), int(k), _stream(stream)))
+
+
+def pico_apply_nufft(h, adjoint, x, out, k, stream=None):
+    return _check(load().pico_apply_nufft(h, int(adjoint), _ptr(x), _ptr(out), int(k), _stream(stream)))
 
 
 def pico_apply_jvp(h, w, u, k, stream=None):

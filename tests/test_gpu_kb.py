@@ -1,0 +1,115 @@
+"""GPU parity of the Kaiser-Bessel gridding data path of non-Cartesian
+operators (A and A^H through pico_apply_nufft) and of PMR on spiral sampling,
+against the FP64 oracle's gridding NUFFT with the same parameters."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import nufft as onufft
+from oracle import pico as opico
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2605_09590_amd import pico as lib
+    lib.load()
+    assert torch.cuda.is_available()
+    return lib
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _setup(n, nc, R, inter, samples, seed):
+    rng = np.random.default_rng(seed)
+    maps = workloads.coil_maps(n, n, nc, rng)
+    psi = workloads.noise_cov(nc, rng)
+    traj = workloads.spiral_traj(n, R, inter, samples).astype(np.float32)
+    return rng, maps, psi, traj
+
+
+def _init(lib, maps, psi, traj, sigma, W, tile, lam=0.1, cg=20):
+    n = maps.shape[1]
+    return lib.pico_init(n, n, _dev(maps.astype(np.complex64)), psi, None, sampling=lib.PICO_NONCART,
+                         lam=lam, cg_iters=cg, probe_tile=tile, traj=_dev(traj), nsamples=traj.shape[0],
+                         oversamp=sigma, kb_width=W)
+
+
+@pytest.mark.parametrize("n,nc,sigma,W,samples", [(64, 4, 2.0, 6, 512), (128, 3, 1.25, 4, 1024)])
+def test_gridding_forward_adjoint_parity(lib, n, nc, sigma, W, samples):
+    say(f"case: gridding {n}x{n}, {nc} coils, sigma {sigma}, W {W}, 16 interleaves x {samples}, k=3")
+    rng, maps, psi, traj = _setup(n, nc, 2, 16, samples, seed=5)
+    M = traj.shape[0]
+    h = _init(lib, maps, psi, traj, sigma, W, 4)
+    x = (rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))).astype(np.complex64)
+    y = (rng.standard_normal((3, nc, M)) + 1j * rng.standard_normal((3, nc, M))).astype(np.complex64)
+    fo = torch.empty((3, nc, M), dtype=torch.complex64, device="cuda:0")
+    ad = torch.empty((3, n, n), dtype=torch.complex64, device="cuda:0")
+    lib.pico_apply_nufft(h, 0, _dev(x), fo, 3)
+    lib.pico_apply_nufft(h, 1, _dev(y), ad, 3)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64), kb=(sigma, W))
+    for k in range(3):
+        ef = _rel(fo.cpu().numpy()[k], op.forward(x[k].astype(np.complex128)))
+        ea = _rel(ad.cpu().numpy()[k], op.adjoint(y[k].astype(np.complex128)))
+        say(f"  image {k}: forward rel err {ef:.2e}, adjoint rel err {ea:.2e}")
+        assert ef < TOL and ea < TOL
+
+
+def test_spiral_pmr_parity(lib):
+    say("case: PMR on spiral 64x64, 4 coils, 16x512 R=2, gridding sigma 2 W 6, lambda 0.1, "
+        "CG 20, 10 replicas in tiles of 4")
+    rng, maps, psi, traj = _setup(64, 4, 2, 16, 512, seed=8)
+    h = _init(lib, maps, psi, traj, 2.0, 6, 4)
+    n = 64 * 64
+    acc_t = [torch.zeros(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    lib.pico_pmr_baseline(h, 13, 3, 10, lib.make_accum(*acc_t))
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64), kb=(2.0, 6))
+    ref = opico.pmr(opico.Covariance(op, 0.1, 20), 13, 3, 10)
+    for key, t in zip(("sum", "sum_im", "sumsq"), acc_t):
+        e = _rel(t.cpu().numpy(), ref[key].ravel())
+        say(f"  {key}: rel err {e:.2e}")
+        assert e < TOL
+
+
+def test_gridding_full_size(lib):
+    say("case: gridding at the spiral workload's size: 256x256, 16 coils, 48x4096 R=2 "
+        "(98304 samples), sigma 2, W 6, k=2")
+    rng, maps, psi, traj = _setup(256, 16, 2, 48, 4096, seed=0)
+    M = traj.shape[0]
+    h = _init(lib, maps, psi, traj, 2.0, 6, 2, cg=30)
+    x = (rng.standard_normal((2, 256, 256)) + 1j * rng.standard_normal((2, 256, 256))).astype(np.complex64)
+    y = (rng.standard_normal((2, 16, M)) + 1j * rng.standard_normal((2, 16, M))).astype(np.complex64)
+    fo = torch.empty((2, 16, M), dtype=torch.complex64, device="cuda:0")
+    ad = torch.empty((2, 256, 256), dtype=torch.complex64, device="cuda:0")
+    lib.pico_apply_nufft(h, 0, _dev(x), fo, 2)
+    lib.pico_apply_nufft(h, 1, _dev(y), ad, 2)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64), kb=(2.0, 6))
+    for k in range(2):
+        ef = _rel(fo.cpu().numpy()[k], op.forward(x[k].astype(np.complex128)))
+        ea = _rel(ad.cpu().numpy()[k], op.adjoint(y[k].astype(np.complex128)))
+        say(f"  image {k}: forward rel err {ef:.2e}, adjoint rel err {ea:.2e}")
+        assert ef < TOL and ea < TOL

@@ -49,7 +49,7 @@ def _requests():
     out.append(("spiral 64x64 4 coils", dict(
         ny=64, nx=64, maps=_dev(maps.astype(np.complex64)), psi=workloads.noise_cov(4, rng),
         mask=None, sampling=2, lam=0.1, cg_iters=15, probe_tile=5, traj=_dev(traj),
-        nsamples=traj.shape[0]), 12))
+        nsamples=traj.shape[0], oversamp=2.0, kb_width=6), 12))
     maps = workloads.coil_maps(64, 64, 3, rng)
     psi = workloads.noise_cov(3, rng)
     mask = workloads.poisson_disc_mask(64, 64, 2.0, 8, seed=6)

@@ -63,6 +63,18 @@ def test_estimate_grows_with_tile_and_kind(p):
                         sampling=p.PICO_NONCART, traj=0x4000, nsamples=50000, lam=0.1)
     rs, ps = p.pico_estimate_bytes(sp)
     assert ps > rs                               # Toeplitz build scratch
+    kb, _ = p.make_desc(128, 128, 0x1000, None, None, ncoils=8, probe_tile=16,
+                        sampling=p.PICO_NONCART, traj=0x4000, nsamples=50000, lam=0.1,
+                        oversamp=2.0, kb_width=6)
+    rk, _ = p.pico_estimate_bytes(kb)
+    # gridding tables: 2 tap starts + 2 x 6 weights per sample, CSR of 36 entries
+    # per sample (index + weight), the [K][256][256] grid and [K][M] staging
+    assert rk - rs >= 50000 * (8 + 48 + 36 * 8) + 16 * 256 * 256 * 8 + 16 * 50000 * 8
+    bad, _ = p.make_desc(128, 128, 0x1000, None, None, ncoils=8, probe_tile=16,
+                         sampling=p.PICO_NONCART, traj=0x4000, nsamples=50000, oversamp=1.1,
+                         kb_width=6)
+    with pytest.raises(p.PicoError):
+        p.pico_estimate_bytes(bad)               # 1.1 * 128 is not an integer
 
 
 def test_estimate_validates(p):
