@@ -230,6 +230,20 @@ enum {
 pico_status_t pico_profile_start(pico_op_t op);
 pico_status_t pico_profile_stop(pico_op_t op, double* ms, int64_t* launches);
 
+/* Pseudo multiple replica for a compressed-sensing operator (Sec. 1, App. C;
+ * compared with the Jacobian probes in Sec. 3.2.3): replica r reconstructs
+ * the perturbed whitened data b + sigma n_r, with n_r CN(0, I) on the
+ * sampled k-space locations (Philox stream 1, element (c ny + ky) nx + kx,
+ * draw r), by the same FP64 FISTA as the operator's own reconstruction x_0,
+ * and adds d_r = (x_r - x_0) / sigma into acc: sum Re d, sum Im d, sum |d|^2
+ * (all three buffers required; acc->count += nrep).  pico_pmr_finalize then
+ * gives the unbiased sample variance, the replica estimate of diag(J J^H).
+ * Replicas run min(probe_tile, 16) at a time; the first call allocates their
+ * FP64 workspace.  Errors: PICO_EUNSUPPORTED for CG-SENSE operators (use
+ * pico_pmr_baseline), PICO_EINVAL, PICO_ENOMEM, PICO_EDEVICE. */
+pico_status_t pico_pmr_cs(pico_op_t op, uint64_t seed, int64_t first, int64_t nrep, double sigma,
+                          pico_accum_t* acc, void* stream);
+
 /* Gridding NUFFT data path of a PICO_NONCART operator built with kb_width > 0
  * (Sec. 3.2.2, 3.3; the reading of the gridding parameters is the one stated
  * at pico_op_desc_t.oversamp).  adjoint = 0: out[k][ncoils][nsamples] = A x

@@ -110,6 +110,35 @@ class FistaL1Wavelet:
         return x_prev
 
 
+def pmr_cs(fista: FistaL1Wavelet, bw, seed: int, first: int, nrep: int, sigma: float, x0=None,
+           acc=None):
+    """Pseudo multiple replica for the nonlinear reconstruction (Sec. 1, App. C;
+    Sec. 3.2.3 compares it with the Jacobian probes).
+
+    Replica r reconstructs the perturbed whitened data b + sigma n_r, n_r the
+    CN(0, I) k-space noise of oracle.pico.pmr_noise (Philox stream 1, element
+    (c ny + ky) nx + kx, zero off the mask), and accumulates
+    d_r = (x_r - x_0) / sigma with x_0 = f(b): sum Re d, sum Im d, sum |d|^2.
+    The unbiased sample variance of d (oracle.pico.pmr_finalize) is the
+    replica estimate of diag(J J^H); subtracting x_0 leaves it unchanged and
+    keeps the sums well conditioned.
+    """
+    from .pico import pmr_noise
+    if x0 is None:
+        x0 = fista.recon(bw)
+    shape = fista.shape
+    if acc is None:
+        acc = {"sum": np.zeros(shape), "sum_im": np.zeros(shape), "sumsq": np.zeros(shape), "count": 0}
+    for r in range(first, first + nrep):
+        n = pmr_noise(fista.op, seed, r)
+        d = (fista.recon(bw + sigma * n) - x0) / sigma
+        acc["sum"] += d.real
+        acc["sum_im"] += d.imag
+        acc["sumsq"] += np.abs(d) ** 2
+        acc["count"] += 1
+    return acc
+
+
 def kspace_probe(op, seed: int, i: int, dist: str = "phase"):
     """Probe w^(i) in whitened k-space on the sampled locations.
 

@@ -315,15 +315,63 @@ __global__ void k_whiten64(const float2* __restrict__ kd, const double* __restri
   }
 }
 
+// U[b][c] = S_c y[b]   (batch b = blockIdx.y)
 __global__ void k_mul_maps64(const double2* __restrict__ y, const double2* __restrict__ S,
                              double2* __restrict__ U, int nc, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
   if (i >= n) return;
-  const double2 v = y[i];
+  const double2 v = y[(size_t)b * n + i];
+  double2* Ub = U + (size_t)b * nc * n;
   for (int c = 0; c < nc; ++c) {
     const double2 m = S[(size_t)c * n + i];
-    U[(size_t)c * n + i] = make_double2(m.x * v.x - m.y * v.y, m.x * v.y + m.y * v.x);
+    Ub[(size_t)c * n + i] = make_double2(m.x * v.x - m.y * v.y, m.x * v.y + m.y * v.x);
   }
+}
+
+// U[b][c][i] = mask[i] sigma n, n a CN(0, 1) Philox draw (stream 1, element
+// c n + i, draw first + b): the PMR perturbation of whitened k-space
+__global__ void k_noise64(double2* __restrict__ U, const uint8_t* __restrict__ mask, int nc, long n,
+                          uint64_t seed, uint64_t first, double sigma) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n) return;
+  for (int c = 0; c < nc; ++c) {
+    double2 v = make_double2(0.0, 0.0);
+    if (mask[i]) {
+      const float2 d = draw_probe(seed, first + b, (uint32_t)((size_t)c * n + i), 1u, 3);
+      v = make_double2(sigma * (double)d.x, sigma * (double)d.y);
+    }
+    U[((size_t)b * nc + c) * n + i] = v;
+  }
+}
+
+// out[b][i] += base[i]
+__global__ void k_add_bcast64(double2* __restrict__ out, const double2* __restrict__ base, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n) return;
+  double2& o = out[(size_t)b * n + i];
+  o = make_double2(o.x + base[i].x, o.y + base[i].y);
+}
+
+// d = (x[b] - x0) / sigma over the B replicas in order: sum Re d, sum Im d, sum |d|^2
+__global__ void k_accum_pmr64(const double2* __restrict__ x, const double2* __restrict__ x0, double inv_sigma,
+                              double* __restrict__ sum, double* __restrict__ sum_im, double* __restrict__ sumsq,
+                              int B, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0, si = 0.0, ss = 0.0;
+  for (int b = 0; b < B; ++b) {
+    const double2 v = x[(size_t)b * n + i];
+    const double dr = (v.x - x0[i].x) * inv_sigma, di = (v.y - x0[i].y) * inv_sigma;
+    s += dr;
+    si += di;
+    ss += dr * dr + di * di;
+  }
+  sum[i] += s;
+  sum_im[i] += si;
+  sumsq[i] += ss;
 }
 
 __global__ void k_mask64(double2* __restrict__ U, const uint8_t* __restrict__ mask, int nc, long n) {
@@ -332,18 +380,20 @@ __global__ void k_mask64(double2* __restrict__ U, const uint8_t* __restrict__ ma
   for (int c = 0; c < nc; ++c) U[(size_t)c * n + i] = make_double2(0.0, 0.0);
 }
 
-// out = sum_c conj(S_c) U_c
+// out[b] = sum_c conj(S_c) U[b][c]   (batch b = blockIdx.y)
 __global__ void k_combine64(const double2* __restrict__ U, const double2* __restrict__ S,
                             double2* __restrict__ out, int nc, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
   if (i >= n) return;
+  const double2* Ub = U + (size_t)b * nc * n;
   double re = 0.0, im = 0.0;
   for (int c = 0; c < nc; ++c) {
-    const double2 m = S[(size_t)c * n + i], u = U[(size_t)c * n + i];
+    const double2 m = S[(size_t)c * n + i], u = Ub[(size_t)c * n + i];
     re += m.x * u.x + m.y * u.y;
     im += m.x * u.y - m.y * u.x;
   }
-  out[i] = make_double2(re, im);
+  out[(size_t)b * n + i] = make_double2(re, im);
 }
 
 // unit random-phase start of the power method (Philox stream 3, key 0, draw 0)
@@ -396,14 +446,15 @@ __global__ void k_grad64(const double2* __restrict__ y, const double2* __restric
   z[i] = make_double2(y[i].x - (q[i].x - g[i].x) * inv_s2, y[i].y - (q[i].y - g[i].y) * inv_s2);
 }
 
-// c_k stored, then detail coefficients soft-thresholded in place
-__global__ void k_soft_store64(double2* __restrict__ c, double2* __restrict__ store, long n, int nx, int ly,
-                               int lx, double lam) {
+// c_k stored (when store is given), then detail coefficients soft-thresholded
+// in place; total = B images of img pixels each
+__global__ void k_soft_store64(double2* __restrict__ c, double2* __restrict__ store, long total, long img,
+                               int nx, int ly, int lx, double lam) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= total) return;
   const double2 v = c[i];
-  store[i] = v;
-  if (is_detail(i, nx, ly, lx)) {
+  if (store) store[i] = v;
+  if (is_detail(i % img, nx, ly, lx)) {
     const double a = sqrt(v.x * v.x + v.y * v.y);
     const double sc = a > lam ? 1.0 - lam / a : 0.0;
     c[i] = make_double2(v.x * sc, v.y * sc);
@@ -444,29 +495,32 @@ hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream
   return hipGetLastError();
 }
 
-// out = sum_c conj(S_c) A_c^H-part applied to the k-space held in o.U (overwritten)
-static hipError_t cs64_adjoint_u(const Cs64& o, double2* out, hipStream_t s) {
+// out[b] = sum_c conj(S_c) A_c^H of the k-space held in o.U [B][nc] (overwritten)
+static hipError_t cs64_adjoint_u(const Cs64& o, int B, double2* out, hipStream_t s) {
   const long n = (long)o.ny * o.nx;
-  CS_CHECK(zgemm64(o.Fy, o.U, o.V, o.ny, o.nx, o.ny, 2, 1, s, o.nc, 0, n, n));     // conj(F_y) U_c
-  CS_CHECK(zgemm64(o.V, o.Fx, o.U, o.nc * o.ny, o.nx, o.nx, 4, 1, s));              // . conj(F_x)
-  hipLaunchKernelGGL(k_combine64, grid1(n), dim3(256), 0, s, o.U, o.S, out, o.nc, n);
+  const int P = B * o.nc;
+  CS_CHECK(zgemm64(o.Fy, o.U, o.V, o.ny, o.nx, o.ny, 2, 1, s, P, 0, n, n));     // conj(F_y) U_bc
+  CS_CHECK(zgemm64(o.V, o.Fx, o.U, P * o.ny, o.nx, o.nx, 4, 1, s));              // . conj(F_x)
+  hipLaunchKernelGGL(k_combine64, grid1(n, B), dim3(256), 0, s, o.U, o.S, out, o.nc, n);
   return hipGetLastError();
 }
 
-hipError_t cs64_normal(const Cs64& o, const double2* y, double2* q, hipStream_t s) {
+// q[b] = M y[b] for B images
+hipError_t cs64_normal(const Cs64& o, int B, const double2* y, double2* q, hipStream_t s) {
   const long n = (long)o.ny * o.nx;
-  hipLaunchKernelGGL(k_mul_maps64, grid1(n), dim3(256), 0, s, y, o.S, o.U, o.nc, n);
-  CS_CHECK(zgemm64(o.U, o.Fx, o.V, o.nc * o.ny, o.nx, o.nx, 0, 1, s));              // (S_c y) F_x
-  CS_CHECK(zgemm64(o.Fy, o.V, o.U, o.ny, o.nx, o.ny, 0, 1, s, o.nc, 0, n, n));     // F_y .
-  hipLaunchKernelGGL(k_mask64, grid1(n), dim3(256), 0, s, o.U, o.mask, o.nc, n);
-  return cs64_adjoint_u(o, q, s);
+  const int P = B * o.nc;
+  hipLaunchKernelGGL(k_mul_maps64, grid1(n, B), dim3(256), 0, s, y, o.S, o.U, o.nc, n);
+  CS_CHECK(zgemm64(o.U, o.Fx, o.V, P * o.ny, o.nx, o.nx, 0, 1, s));              // (S_c y) F_x
+  CS_CHECK(zgemm64(o.Fy, o.V, o.U, o.ny, o.nx, o.ny, 0, 1, s, P, 0, n, n));     // F_y .
+  hipLaunchKernelGGL(k_mask64, grid1(n), dim3(256), 0, s, o.U, o.mask, P, n);
+  return cs64_adjoint_u(o, B, q, s);
 }
 
 hipError_t cs64_adjoint_kdata(const Cs64& o, const float2* kdata, const double* linv, double2* out,
                               hipStream_t s) {
   const long n = (long)o.ny * o.nx;
   hipLaunchKernelGGL(k_whiten64, grid1(n), dim3(256), 0, s, kdata, linv, o.mask, o.U, o.nc, n);
-  return cs64_adjoint_u(o, out, s);
+  return cs64_adjoint_u(o, 1, out, s);
 }
 
 // lambda_max of M: power steps from the Philox start; Rayleigh quotient of the last step
@@ -478,7 +532,7 @@ hipError_t cs64_power(const Cs64& o, int iters, double2* v, double2* w, double* 
   hipLaunchKernelGGL(k_power_start64, grid1(n), dim3(256), 0, s, v, n);
   double lam = 0.0;
   for (int it = 0; it < iters; ++it) {
-    CS_CHECK(cs64_normal(o, v, w, s));
+    CS_CHECK(cs64_normal(o, 1, v, w, s));
     hipLaunchKernelGGL(k_dot64, dim3(nb), dim3(256), 0, s, v, w, part_d, n);
     CS_CHECK(hipMemcpyAsync(part.data(), part_d, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     CS_CHECK(hipStreamSynchronize(s));
@@ -495,24 +549,40 @@ hipError_t cs64_power(const Cs64& o, int iters, double2* v, double2* w, double* 
   return hipGetLastError();
 }
 
-// T FISTA iterations at the measured data from x_0 = y_1 = 0; stores c_k = Psi z_k
-// (FP64, [T][ny][nx]) and leaves x_T in x.  Buffers: y, x, z, tmp, q of n each.
-hipError_t cs64_fista(const Cs64& o, const double2* atb, double s2, double lam, int T,
+// T FISTA iterations on B images from x_0 = y_1 = 0 (atb [B][n]); stores
+// c_k = Psi z_k ([T][ny][nx], B = 1 only) when ctraj is given and leaves x_T in
+// x.  Buffers y, x, z, tmp, q hold B images each.
+hipError_t cs64_fista(const Cs64& o, int B, const double2* atb, double s2, double lam, int T,
                       const double* theta, double2* ctraj, double2* y, double2* x, double2* z,
                       double2* tmp, double2* q, hipStream_t s) {
-  const long n = (long)o.ny * o.nx;
+  const long n = (long)o.ny * o.nx, tot = n * B;
   const int ly = o.ny >> o.levels, lx = o.nx >> o.levels;
-  hipLaunchKernelGGL(k_fill_zero64, grid1(n), dim3(256), 0, s, y, n);
-  hipLaunchKernelGGL(k_fill_zero64, grid1(n), dim3(256), 0, s, x, n);
+  hipLaunchKernelGGL(k_fill_zero64, grid1(tot), dim3(256), 0, s, y, tot);
+  hipLaunchKernelGGL(k_fill_zero64, grid1(tot), dim3(256), 0, s, x, tot);
   for (int k = 1; k <= T; ++k) {
-    CS_CHECK(cs64_normal(o, y, q, s));
-    hipLaunchKernelGGL(k_grad64, grid1(n), dim3(256), 0, s, y, q, atb, z, n, 1.0 / s2);
-    CS_CHECK(wavelet(z, tmp, 1, o.ny, o.nx, o.levels, false, s));
-    hipLaunchKernelGGL(k_soft_store64, grid1(n), dim3(256), 0, s, z, ctraj + (size_t)(k - 1) * n, n, o.nx,
-                       ly, lx, lam);
-    CS_CHECK(wavelet(z, tmp, 1, o.ny, o.nx, o.levels, true, s));
-    hipLaunchKernelGGL(k_momentum64, grid1(n), dim3(256), 0, s, z, x, y, n, theta[k - 1]);
+    CS_CHECK(cs64_normal(o, B, y, q, s));
+    hipLaunchKernelGGL(k_grad64, grid1(tot), dim3(256), 0, s, y, q, atb, z, tot, 1.0 / s2);
+    CS_CHECK(wavelet(z, tmp, B, o.ny, o.nx, o.levels, false, s));
+    hipLaunchKernelGGL(k_soft_store64, grid1(tot), dim3(256), 0, s, z,
+                       ctraj ? ctraj + (size_t)(k - 1) * n : nullptr, tot, n, o.nx, ly, lx, lam);
+    CS_CHECK(wavelet(z, tmp, B, o.ny, o.nx, o.levels, true, s));
+    hipLaunchKernelGGL(k_momentum64, grid1(tot), dim3(256), 0, s, z, x, y, tot, theta[k - 1]);
   }
+  return hipGetLastError();
+}
+
+// B PMR replicas of the FP64 reconstruction: x_b = f(b_w + sigma n_b), then
+// (x_b - x0) / sigma accumulated into sum, sum_im, sumsq
+hipError_t cs64_pmr(const Cs64& o, int B, const double2* atb0, const double2* x0, double s2, double lam,
+                    int T, const double* theta, uint64_t seed, uint64_t first, double sigma, double2* atb,
+                    double2* y, double2* x, double2* z, double2* tmp, double2* q, double* sum,
+                    double* sum_im, double* sumsq, hipStream_t s) {
+  const long n = (long)o.ny * o.nx;
+  hipLaunchKernelGGL(k_noise64, grid1(n, B), dim3(256), 0, s, o.U, o.mask, o.nc, n, seed, first, sigma);
+  CS_CHECK(cs64_adjoint_u(o, B, atb, s));                                        // A^H (sigma n_b)
+  hipLaunchKernelGGL(k_add_bcast64, grid1(n, B), dim3(256), 0, s, atb, atb0, n);   // + A^H b_w
+  CS_CHECK(cs64_fista(o, B, atb, s2, lam, T, theta, nullptr, y, x, z, tmp, q, s));
+  hipLaunchKernelGGL(k_accum_pmr64, grid1(n), dim3(256), 0, s, x, x0, 1.0 / sigma, sum, sum_im, sumsq, B, n);
   return hipGetLastError();
 }
 

@@ -74,6 +74,13 @@ struct pico_op_s {
   float2 *wA = nullptr, *wB = nullptr;  // wavelet buffers, K images
   double2* ctraj = nullptr;     // [T][ny][nx] stored Psi z_k of the FP64 primal
   float2* xrec = nullptr;       // reconstruction
+  std::vector<double> theta64;  // FISTA momentum weights (FP64 primal)
+  pico::Cs64 c64;               // FP64 operator of the primal (maps, DFT matrices)
+  double2 *atb64 = nullptr, *x64 = nullptr;   // A^H b and x_T in FP64
+  // replica workspace of pico_pmr_cs, allocated on its first call
+  int pmr_B = 0;
+  double2 *pmr_atb = nullptr, *pmr_y = nullptr, *pmr_x = nullptr, *pmr_z = nullptr, *pmr_tmp = nullptr,
+          *pmr_q = nullptr;
   uint8_t* mask_d = nullptr;    // [ny][nx] (Cartesian 2-D)
   // Kaiser-Bessel gridding data path (non-Cartesian, kb_width > 0)
   bool has_kb = false;
@@ -662,8 +669,12 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
     add(n * K * 8);
     add(n * (size_t)d->fista_iters * 16);
     add(n * 8);
-    const size_t tmp[] = {nc * n * 16, nc * n * 16, nc * n * 16, ny * ny * 16, nx * nx * 16, n * 16,
-                          n * 16,      n * 16,      n * 16,      n * 16,      n * 16,  2 * CS64_DOT_BLOCKS * 8};
+    add(nc * n * 16);   // FP64 maps, DFT matrices, A^H b, x_T (resident)
+    add(ny * ny * 16);
+    add(nx * nx * 16);
+    add(n * 16);
+    add(n * 16);
+    const size_t tmp[] = {nc * n * 16, nc * n * 16, n * 16, n * 16, n * 16, n * 16, 2 * CS64_DOT_BLOCKS * 8};
     for (size_t b : tmp) add(b);
     for (size_t b : tmp) sub(b);
   }
@@ -819,47 +830,48 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     op->fista_T = d->fista_iters;
     op->levels = d->wavelet_levels;
     op->cs_lam = d->cs_lambda;
-    std::vector<double> theta64;
     double t = 1.0;
     for (int k = 0; k < op->fista_T; ++k) {
       const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-      theta64.push_back((t - 1.0) / tn);
-      op->theta.push_back((float)theta64.back());
+      op->theta64.push_back((t - 1.0) / tn);
+      op->theta.push_back((float)op->theta64.back());
       t = tn;
     }
     if ((e = op->alloc(&op->wA, n * K)) != hipSuccess) return bad(e, "wavelet buffer");
     if ((e = op->alloc(&op->wB, n * K)) != hipSuccess) return bad(e, "wavelet buffer");
     if ((e = op->alloc(&op->ctraj, n * (size_t)op->fista_T)) != hipSuccess) return bad(e, "FISTA trajectory");
     if ((e = op->alloc(&op->xrec, n)) != hipSuccess) return bad(e, "reconstruction");
-    pico::Cs64 o;
+    // resident FP64 operator (whitened maps, centred DFT matrices), A^H b and
+    // x_T: the linearisation point, kept for the replicas of pico_pmr_cs
+    pico::Cs64& o = op->c64;
     o.ny = ny;
     o.nx = nx;
     o.nc = nc;
     o.levels = op->levels;
     o.mask = op->mask_d;
-    double2 *atb = nullptr, *y = nullptr, *x = nullptr, *z = nullptr, *tmp = nullptr, *q = nullptr;
+    if ((e = op->alloc(&o.S, (size_t)nc * n)) != hipSuccess || (e = op->alloc(&o.Fy, (size_t)ny * ny)) != hipSuccess ||
+        (e = op->alloc(&o.Fx, (size_t)nx * nx)) != hipSuccess || (e = op->alloc(&op->atb64, n)) != hipSuccess ||
+        (e = op->alloc(&op->x64, n)) != hipSuccess)
+      return bad(e, "FP64 operator");
+    double2 *y = nullptr, *z = nullptr, *tmp = nullptr, *q = nullptr;
     double* part = nullptr;
-    if ((e = op->alloc(&o.S, (size_t)nc * n)) != hipSuccess ||
-        (e = op->alloc(&o.U, (size_t)nc * n)) != hipSuccess ||
-        (e = op->alloc(&o.V, (size_t)nc * n)) != hipSuccess ||
-        (e = op->alloc(&o.Fy, (size_t)ny * ny)) != hipSuccess ||
-        (e = op->alloc(&o.Fx, (size_t)nx * nx)) != hipSuccess || (e = op->alloc(&atb, n)) != hipSuccess ||
-        (e = op->alloc(&y, n)) != hipSuccess || (e = op->alloc(&x, n)) != hipSuccess ||
-        (e = op->alloc(&z, n)) != hipSuccess || (e = op->alloc(&tmp, n)) != hipSuccess ||
-        (e = op->alloc(&q, n)) != hipSuccess || (e = op->alloc(&part, 2 * pico::CS64_DOT_BLOCKS)) != hipSuccess)
+    if ((e = op->alloc(&o.U, (size_t)nc * n)) != hipSuccess || (e = op->alloc(&o.V, (size_t)nc * n)) != hipSuccess ||
+        (e = op->alloc(&y, n)) != hipSuccess || (e = op->alloc(&z, n)) != hipSuccess ||
+        (e = op->alloc(&tmp, n)) != hipSuccess || (e = op->alloc(&q, n)) != hipSuccess ||
+        (e = op->alloc(&part, 2 * pico::CS64_DOT_BLOCKS)) != hipSuccess)
       return bad(e, "FP64 primal workspace");
     if ((e = pico::cs64_setup(o, (const float2*)d->maps, linv_d, s)) != hipSuccess) return bad(e, "FP64 primal");
     double lam_hat = 0.0;
-    if ((e = pico::cs64_power(o, d->power_iters, y, x, part, &lam_hat, s)) != hipSuccess) return bad(e, "power");
+    if ((e = pico::cs64_power(o, d->power_iters, y, z, part, &lam_hat, s)) != hipSuccess) return bad(e, "power");
     op->s2 = d->power_margin * lam_hat;
-    if ((e = pico::cs64_adjoint_kdata(o, (const float2*)d->kdata, linv_d, atb, s)) != hipSuccess) return bad(e, "A^H b");
-    if ((e = pico::cs64_fista(o, atb, op->s2, op->cs_lam, op->fista_T, theta64.data(), op->ctraj, y, x, z, tmp, q, s)) != hipSuccess)
+    if ((e = pico::cs64_adjoint_kdata(o, (const float2*)d->kdata, linv_d, op->atb64, s)) != hipSuccess) return bad(e, "A^H b");
+    if ((e = pico::cs64_fista(o, 1, op->atb64, op->s2, op->cs_lam, op->fista_T, op->theta64.data(), op->ctraj, y,
+                              op->x64, z, tmp, q, s)) != hipSuccess)
       return bad(e, "FISTA");
-    if ((e = pico::launch_to_f32(x, op->xrec, (long)n, s)) != hipSuccess) return bad(e, "reconstruction");
+    if ((e = pico::launch_to_f32(op->x64, op->xrec, (long)n, s)) != hipSuccess) return bad(e, "reconstruction");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "FISTA");
-    for (void* ptr : {(void*)o.S, (void*)o.U, (void*)o.V, (void*)o.Fy, (void*)o.Fx, (void*)atb, (void*)y,
-                      (void*)x, (void*)z, (void*)tmp, (void*)q, (void*)part})
-      op->release(ptr);
+    for (void* ptr : {(void*)o.U, (void*)o.V, (void*)y, (void*)z, (void*)tmp, (void*)q, (void*)part}) op->release(ptr);
+    o.U = o.V = nullptr;
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "init");
   op->release(linv_d);
@@ -979,7 +991,7 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
   if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq)
     return fail(PICO_EINVAL, "PMR needs sum, sum_im and sumsq buffers");
   if (nrep < 0 || first < 0) return fail(PICO_EINVAL, "negative replica range");
-  if (op->cs) return fail(PICO_EUNSUPPORTED, "PMR is built for CG-SENSE operators");
+  if (op->cs) return fail(PICO_EUNSUPPORTED, "a compressed-sensing operator takes pico_pmr_cs");
   if (op->sampling == PICO_NONCART && !op->has_kb)
     return fail(PICO_EUNSUPPORTED, "PMR on non-Cartesian sampling needs the gridding data path (kb_width > 0)");
   hipStream_t s = (hipStream_t)stream;
@@ -1011,6 +1023,47 @@ pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int6
   }
   acc->count += nrep;
   if (stats) return write_stats(op, sa, stats);
+  return PICO_OK;
+}
+
+pico_status_t pico_pmr_cs(pico_op_t op, uint64_t seed, int64_t first, int64_t nrep, double sigma,
+                          pico_accum_t* acc, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!op->cs) return fail(PICO_EUNSUPPORTED, "pico_pmr_cs needs a compressed-sensing operator");
+  if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq)
+    return fail(PICO_EINVAL, "PMR needs sum, sum_im and sumsq buffers");
+  if (nrep < 0 || first < 0) return fail(PICO_EINVAL, "negative replica range");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(PICO_EINVAL, "sigma must be finite and > 0");
+  hipStream_t s = (hipStream_t)stream;
+  op->last_stream = s;
+  const size_t n = op->image();
+  pico::Cs64& o = op->c64;
+  if (op->pmr_B == 0) {
+    const int B = std::min(op->K, 16);
+    hipError_t e;
+    if ((e = op->alloc(&o.U, (size_t)B * op->nc * n)) != hipSuccess || (e = op->alloc(&o.V, (size_t)B * op->nc * n)) != hipSuccess ||
+        (e = op->alloc(&op->pmr_atb, B * n)) != hipSuccess || (e = op->alloc(&op->pmr_y, B * n)) != hipSuccess ||
+        (e = op->alloc(&op->pmr_x, B * n)) != hipSuccess || (e = op->alloc(&op->pmr_z, B * n)) != hipSuccess ||
+        (e = op->alloc(&op->pmr_tmp, B * n)) != hipSuccess || (e = op->alloc(&op->pmr_q, B * n)) != hipSuccess) {
+      for (void* p : {(void*)o.U, (void*)o.V, (void*)op->pmr_atb, (void*)op->pmr_y, (void*)op->pmr_x,
+                      (void*)op->pmr_z, (void*)op->pmr_tmp, (void*)op->pmr_q})
+        if (p) op->release(p);
+      o.U = o.V = nullptr;
+      op->pmr_atb = op->pmr_y = op->pmr_x = op->pmr_z = op->pmr_tmp = op->pmr_q = nullptr;
+      return fail(e == hipErrorOutOfMemory ? PICO_ENOMEM : PICO_EDEVICE, "PMR workspace");
+    }
+    op->pmr_B = B;
+  }
+  for (int64_t done = 0; done < nrep;) {
+    const int B = (int)std::min<int64_t>(op->pmr_B, nrep - done);
+    HIP_OR_RETURN(timed(op, PICO_PROF_OTHER, s, [&] {
+      return pico::cs64_pmr(o, B, op->atb64, op->x64, op->s2, op->cs_lam, op->fista_T, op->theta64.data(), seed,
+                            (uint64_t)(first + done), sigma, op->pmr_atb, op->pmr_y, op->pmr_x, op->pmr_z,
+                            op->pmr_tmp, op->pmr_q, acc->sum, acc->sum_im, acc->sumsq, s);
+    }));
+    done += B;
+  }
+  acc->count += nrep;
   return PICO_OK;
 }
 

@@ -142,18 +142,22 @@ struct Cs64 {
   double2* Fy = nullptr;        // [ny][ny] centred orthonormal DFT
   double2* Fx = nullptr;        // [nx][nx]
   const uint8_t* mask = nullptr;  // [ny][nx]
-  double2* U = nullptr;         // [nc][ny][nx] workspace
-  double2* V = nullptr;         // [nc][ny][nx] workspace
+  double2* U = nullptr;         // [B][nc][ny][nx] workspace (B images per call)
+  double2* V = nullptr;         // [B][nc][ny][nx] workspace
 };
 hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream_t s);
-hipError_t cs64_normal(const Cs64& o, const double2* y, double2* q, hipStream_t s);
+hipError_t cs64_normal(const Cs64& o, int B, const double2* y, double2* q, hipStream_t s);
 hipError_t cs64_adjoint_kdata(const Cs64& o, const float2* kdata, const double* linv, double2* out,
                               hipStream_t s);
 hipError_t cs64_power(const Cs64& o, int iters, double2* v, double2* w, double* part_d, double* out,
                       hipStream_t s);
-hipError_t cs64_fista(const Cs64& o, const double2* atb, double s2, double lam, int T,
+hipError_t cs64_fista(const Cs64& o, int B, const double2* atb, double s2, double lam, int T,
                       const double* theta, double2* ctraj, double2* y, double2* x, double2* z,
                       double2* tmp, double2* q, hipStream_t s);
+hipError_t cs64_pmr(const Cs64& o, int B, const double2* atb0, const double2* x0, double s2, double lam,
+                    int T, const double* theta, uint64_t seed, uint64_t first, double sigma, double2* atb,
+                    double2* y, double2* x, double2* z, double2* tmp, double2* q, double* sum,
+                    double* sum_im, double* sumsq, hipStream_t s);
 hipError_t launch_to_f32(const double2* a, float2* b, long n, hipStream_t s);
 
 // Kaiser-Bessel gridding NUFFT (non-Cartesian data path)

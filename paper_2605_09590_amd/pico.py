@@ -75,7 +75,7 @@ class PicoError(RuntimeError):
 _lib = None
 
 EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
-           "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse", "pico_exact_diag",
+           "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse", "pico_exact_diag",
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
            "pico_server_submit", "pico_server_poll", "pico_server_wait_idle", "pico_server_usage",
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
     lib.pico_pmr_baseline.argtypes = [vp, u64, i64, i64, ctypes.POINTER(pico_accum_t),
                                       ctypes.POINTER(pico_stats_t), vp]
     lib.pico_pmr_finalize.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp, vp]
+    lib.pico_pmr_cs.argtypes = [vp, u64, i64, i64, ctypes.c_double, ctypes.POINTER(pico_accum_t), vp]
     lib.pico_monitor_nrmse.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp,
                                        ctypes.POINTER(ctypes.c_double), vp]
     lib.pico_exact_diag.argtypes = [vp, vp, vp]
@@ -131,7 +132,7 @@ def load(path: str = LIB_PATH):
     lib.pico_server_destroy.argtypes = [vp]
     lib.pico_server_destroy.restype = None
     for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
-                 "pico_pmr_baseline", "pico_pmr_finalize", "pico_monitor_nrmse",
+                 "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse",
                  "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
                  "pico_estimate_bytes", "pico_op_bytes", "pico_server_create", "pico_server_submit",
                  "pico_server_poll", "pico_server_wait_idle", "pico_server_usage"):
@@ -266,6 +267,11 @@ def pico_pmr_baseline(h, seed, first, nrep, acc, stats=None, stream=None):
     return _check(load().pico_pmr_baseline(h, int(seed), int(first), int(nrep), ctypes.byref(acc),
                                            None if stats is None else ctypes.byref(stats),
                                            _stream(stream)))
+
+
+def pico_pmr_cs(h, seed, first, nrep, sigma, acc, stream=None):
+    return _check(load().pico_pmr_cs(h, int(seed), int(first), int(nrep), float(sigma), ctypes.byref(acc),
+                                     _stream(stream)))
 
 
 def pico_pmr_finalize(h, acc, var, stream=None):

@@ -158,3 +158,27 @@ def test_cs_full_size_sampled_probes(lib):
         e = _rel(u[k], f.jvp(w[k].astype(np.complex128), coeffs))
         say(f"  probe {k}: rel err {e:.2e}")
         assert e < TOL
+
+
+def test_cs_pmr_parity(lib):
+    say("case: CS PMR 64x64, 3 coils, lam 1e-3, FISTA 20, 3 levels, sigma 0.02, "
+        "10 replicas (FP64 replicas in batches of 4)")
+    maps, psi, mask, op, bw, braw = _cs_setup(64, 3, 2.0, 8, seed=12)
+    h = _init_cs(lib, maps, psi, mask, braw, 1e-3, 20, 3, 4)
+    n = 64 * 64
+    acc_t = [torch.zeros(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    acc = lib.make_accum(*acc_t)
+    lib.pico_pmr_cs(h, 5, 2, 10, 0.02, acc)
+    var = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    lib.pico_pmr_finalize(h, acc, var)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    f = ocs.FistaL1Wavelet(op, 1e-3, 20, levels=3)
+    ref = ocs.pmr_cs(f, bw, 5, 2, 10, 0.02)
+    for key, t in zip(("sum", "sum_im", "sumsq"), acc_t):
+        e = _rel(t.cpu().numpy(), ref[key].ravel())
+        say(f"  {key}: rel err {e:.2e}")
+        assert e < TOL
+    e = _rel(var.cpu().numpy(), opico.pmr_finalize(ref).ravel())
+    say(f"  sample variance: rel err {e:.2e}")
+    assert e < TOL

@@ -97,3 +97,21 @@ def test_lambda_zero_long_run_gives_least_squares_variance():
         e[j] = 1.0
         JJ += np.abs(f.jvp(e.reshape(2, 4, 2), coeffs)) ** 2
     assert np.allclose(JJ, exact, rtol=1e-6)
+
+
+def test_pmr_cs_replicas_are_difference_quotients():
+    # lam = 0: the FISTA map is linear, so every replica's (x_r - x_0) / sigma is
+    # the reconstruction of the noise itself, for any sigma
+    op, b, f = _cs_problem(lam=0.0)
+    acc = cs.pmr_cs(f, b, 7, 0, 3, sigma=0.37)
+    ref = sum(f.recon(pico.pmr_noise(op, 7, r)) for r in range(3))
+    assert np.linalg.norm(acc["sum"] + 1j * acc["sum_im"] - ref) < 1e-10 * np.linalg.norm(ref)
+    # lam > 0, tiny sigma: each replica is the Jacobian applied to its noise
+    # (first order; the step stays off the threshold kinks)
+    op, b, f = _cs_problem()
+    x0, coeffs = f.recon(b, store=True)
+    for r in range(2):
+        a = cs.pmr_cs(f, b, 9, r, 1, sigma=1e-9, x0=x0)
+        jn = f.jvp(pico.pmr_noise(op, 9, r), coeffs)
+        assert np.linalg.norm(a["sum"] + 1j * a["sum_im"] - jn) < 1e-5 * np.linalg.norm(jn)
+        assert np.allclose(a["sumsq"], np.abs(jn) ** 2, rtol=1e-4, atol=1e-8 * np.abs(jn).max() ** 2)
