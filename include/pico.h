@@ -109,6 +109,13 @@ typedef struct {
    * CG solves is the exact Toeplitz form either way. */
   double oversamp;              /* e.g. 2.0 (or 1.25)                             */
   int32_t kb_width;             /* e.g. 6 (or 4); 0 = no gridding data path       */
+  /* Form of the normal operator for PICO_CART_1D (M is block diagonal over
+   * image columns, Sec. 2.1 Eq. (6)): 1 = column FFTs; 2 = the dense ny x ny
+   * block of every column, built once (nx ny^2 complex64 of device memory)
+   * and applied to the probe tile on the FP32 matrix cores (ny a multiple
+   * of 32, <= 512); 0 = the default (column FFTs).
+   * Both give M to FP32 rounding; the PMR right-hand side always uses FFTs. */
+  int32_t normal_form;
 } pico_op_desc_t;
 
 /* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a

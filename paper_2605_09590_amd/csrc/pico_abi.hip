@@ -54,6 +54,9 @@ struct pico_op_s {
   // resident operator
   float2* maps = nullptr;     // whitened maps (layout per path)
   float* maskw = nullptr;     // separable path: [ny] mask[k] / ny
+  bool use_gram = false;      // separable path: dense per-column blocks on the matrix cores
+  float2* gram = nullptr;     // [nx][ny][ny] conj(M_x[i][j]) at [x][j][i]
+  double2* gram_c = nullptr;  // [ny] circulant c(d) (build input)
   float2* twt = nullptr;      // separable path: [ny] twiddles
   float* w = nullptr;         // grid path: [Gx][Gy] real weights
   float2* twx = nullptr;      // grid path: [Gx] twiddles
@@ -248,6 +251,7 @@ hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hip
     a.seed = c.seed;
     a.first = c.first;
     a.dist = c.dist;
+    if (op->use_gram && mode != pico::C1_PMR_RHS) return pico::launch_cart1d_gram(mode, a, op->gram, s);
     return pico::launch_cart1d(mode, a, s);
   }
   pico::Grid2dArgs g{};
@@ -481,6 +485,11 @@ hipError_t cs_tangents(pico_op_t op, int K, const float2* w, uint64_t seed, uint
 
 bool kb_grid_dims(const pico_op_desc_t* d, int G[2]);
 
+bool wants_gram(const pico_op_desc_t* d) {
+  if (d->sampling != PICO_CART_1D || !pico::gram_supported(d->ny)) return false;
+  return d->normal_form == 2;
+}
+
 // Kaiser-Bessel tables of a non-Cartesian operator: device buffers in the
 // kb_layout order, tap weights and the spreading CSR built on the host
 hipError_t build_kb(pico_op_t op, const pico_op_desc_t* d, hipStream_t s) {
@@ -589,6 +598,9 @@ pico_status_t validate(const pico_op_desc_t* d) {
     return fail(PICO_EINVAL, "traj and 1 <= nsamples <= 2^30 are required for non-Cartesian sampling");
   if (d->lambda > 0.0 && (d->power_iters < 1 || !(d->power_margin > 0.0)))
     return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
+  if (d->normal_form < 0 || d->normal_form > 2) return fail(PICO_EINVAL, "normal_form must be 0, 1 or 2");
+  if (d->normal_form == 2 && (d->sampling != PICO_CART_1D || !pico::gram_supported(d->ny)))
+    return fail(PICO_EINVAL, "the dense normal form needs PICO_CART_1D and ny a multiple of 32 in 64..512");
   if (d->kb_width != 0) {
     if (d->sampling != PICO_NONCART) return fail(PICO_EINVAL, "kb_width applies to PICO_NONCART only");
     if (d->kb_width < 2 || d->kb_width > 8 || (d->kb_width & 1))
@@ -646,6 +658,10 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
   if (colmajor) {
     add(ny * 4);
     add(ny * 8);
+    if (wants_gram(d)) {
+      add(gram_bytes(d->ny, d->nx));
+      add(ny * 16);
+    }
   } else {
     add(Gy * Gx * 4);
     add(Gx * 8);
@@ -787,6 +803,12 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if ((e = hipMemcpyAsync(op->maskw, w.data(), ny * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     if ((e = hipMemcpyAsync(op->twt, tw.data(), ny * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     if ((e = pico::launch_prep_maps_cart1d((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, s)) != hipSuccess) return bad(e, "prep maps");
+    if (wants_gram(d)) {
+      if ((e = op->alloc(&op->gram, pico::gram_bytes(ny, nx) / sizeof(float2))) != hipSuccess) return bad(e, "dense blocks");
+      if ((e = op->alloc(&op->gram_c, ny)) != hipSuccess) return bad(e, "dense blocks");
+      if ((e = pico::build_gram(op->maps, w.data(), nc, ny, nx, op->gram, op->gram_c, s)) != hipSuccess) return bad(e, "dense blocks");
+      op->use_gram = true;
+    }
   } else {
     const int Gy = op->Gy, Gx = op->Gx;
     if ((e = op->alloc(&op->w, (size_t)Gy * Gx)) != hipSuccess) return bad(e, "weights");

@@ -190,6 +190,12 @@ hipError_t kb_adjoint(const KbOp& o, const float2* maps, int nc, int K, const fl
 hipError_t kb_forward(const KbOp& o, const float2* maps, int nc, int K, const float2* x, float2* out,
                       hipStream_t s);
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
+// dense per-column normal operator (phase-encode masks, FP32 matrix cores)
+bool gram_supported(int ny);
+size_t gram_bytes(int ny, int nx);
+hipError_t build_gram(const float2* maps, const float* maskw_h, int nc, int ny, int nx, float2* G,
+                      double2* cvec_d, hipStream_t s);
+hipError_t launch_cart1d_gram(int mode, const Cart1dArgs& a, const float2* G, hipStream_t s);
 hipError_t launch_final_x(const FinalArgs& a, hipStream_t s);
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);
 hipError_t launch_accum_colmajor(const AccumArgs& a, hipStream_t s);

@@ -43,6 +43,7 @@ class pico_op_desc_t(ctypes.Structure):
         ("wavelet_levels", ctypes.c_int32),
         ("oversamp", ctypes.c_double),
         ("kb_width", ctypes.c_int32),
+        ("normal_form", ctypes.c_int32),
     ]
 
 
@@ -171,7 +172,7 @@ def _addr(x):
 def make_desc(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
               traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
-              wavelet_levels=4, oversamp=2.0, kb_width=0, ncoils=None):
+              wavelet_levels=4, oversamp=2.0, kb_width=0, normal_form=0, ncoils=None):
     """pico_op_desc_t for the arguments of pico_init; returns (desc, keep) where
     ``keep`` holds the host psi array the descriptor points to."""
     d = pico_op_desc_t()
@@ -199,19 +200,20 @@ def make_desc(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
     d.wavelet_levels = wavelet_levels
     d.oversamp = oversamp
     d.kb_width = kb_width
+    d.normal_form = normal_form
     return d, keep
 
 
 def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=30, cg_tol=0.0,
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
               traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
-              wavelet_levels=4, oversamp=2.0, kb_width=0, stream=None):
+              wavelet_levels=4, oversamp=2.0, kb_width=0, normal_form=0, stream=None):
     """pico_init: ``maps`` complex64 device tensor [nc][ny][nx]; ``psi`` numpy
     complex128 [nc][nc] or None; ``mask`` uint8 device tensor.  Returns the handle."""
     lib = load()
     d, keep = make_desc(ny, nx, maps, psi, mask, sampling, lam, cg_iters, cg_tol, power_iters,
                         power_margin, probe_tile, recon, traj, nsamples, kdata, fista_iters,
-                        cs_lambda, wavelet_levels, oversamp, kb_width)
+                        cs_lambda, wavelet_levels, oversamp, kb_width, normal_form)
     h = ctypes.c_void_p()
     _check(lib.pico_init(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
     del keep

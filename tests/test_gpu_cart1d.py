@@ -36,13 +36,13 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def _init(lib, prob, tile, lam=None, cg_iters=None, cg_tol=0.0):
+def _init(lib, prob, tile, lam=None, cg_iters=None, cg_tol=0.0, form=0):
     maps = _dev(prob.maps.astype(np.complex64))
     mask = _dev(prob.mask)
     return lib.pico_init(prob.ny, prob.nx, maps, prob.psi, mask,
                          lam=prob.lam if lam is None else lam,
                          cg_iters=prob.cg_iters if cg_iters is None else cg_iters,
-                         cg_tol=cg_tol, probe_tile=tile)
+                         cg_tol=cg_tol, probe_tile=tile, normal_form=form)
 
 
 def _gpu_map(lib, h, n, seed, first, nprobes, dist=0, stats=None, acc_t=None):
@@ -173,22 +173,63 @@ def test_pmr_parity(lib):
 
 
 def test_full_size_config2_sampled_columns(lib):
-    say("case: config-2 320x320 15 coils R=2+24 ACS, K=256 probes as one tile, CG 30")
+    say("case: config-2 320x320 15 coils R=2+24 ACS, K=256 probes as one tile, CG 30, "
+        "dense (matrix-core) and FFT normal forms")
     prob = workloads.config(2, seed=0)
     n = prob.ny * prob.nx
-    h = _init(lib, prob, 256)
-    st = lib.pico_stats_t()
-    (s, _, _), acc = _gpu_map(lib, h, n, 2024, 0, 256, stats=st)
-    lib.pico_destroy(h)
-    say(f"  CG relres max {st.max_relres:.2e} mean {st.mean_relres:.2e}, frozen {st.frozen}")
-    assert st.frozen == 0 and acc.count == 256
     op = opico.cartesian(prob.maps, prob.psi, prob.mask)
     cols = [0, 1, 97, 160, 255, 319]
     ref = opico.noise_map_exact_columns(op, prob.mask, 2024, 0, 256, cols)
-    got = s.reshape(prob.ny, prob.nx)[:, cols]
-    err = _rel(got, ref)
-    say(f"  sampled columns {cols}: rel err vs converged oracle {err:.2e}")
-    assert err < TOL
+    for form, name in ((2, "dense"), (1, "FFT")):
+        h = _init(lib, prob, 256, form=form)
+        st = lib.pico_stats_t()
+        (s, _, _), acc = _gpu_map(lib, h, n, 2024, 0, 256, stats=st)
+        lib.pico_destroy(h)
+        say(f"  {name}: CG relres max {st.max_relres:.2e} mean {st.mean_relres:.2e}, frozen {st.frozen}")
+        assert st.frozen == 0 and acc.count == 256
+        got = s.reshape(prob.ny, prob.nx)[:, cols]
+        err = _rel(got, ref)
+        say(f"  {name}: sampled columns {cols}: rel err vs converged oracle {err:.2e}")
+        assert err < TOL
+
+
+@pytest.mark.parametrize("ny,nx,nc,tile,nprobes", [(64, 64, 4, 40, 40), (96, 40, 5, 4, 10),
+                                                   (160, 24, 8, 32, 45), (288, 16, 3, 33, 33)])
+def test_dense_form_parity(lib, ny, nx, nc, tile, nprobes):
+    say(f"case: dense per-column normal operator {ny}x{nx} {nc} coils, {nprobes} probes in tiles of "
+        f"{tile} (probe tiles of 32 on the matrix cores, ragged), CG 20")
+    prob = workloads.config(2, seed=ny, ny=ny, nx=nx, nc=nc, acs=8, cg_iters=20)
+    h = _init(lib, prob, tile, form=2)
+    st = lib.pico_stats_t()
+    (s, si, ss), _ = _gpu_map(lib, h, ny * nx, 31, 2, nprobes, stats=st)
+    lib.pico_destroy(h)
+    cov = opico.Covariance(opico.cartesian(prob.maps, prob.psi, prob.mask), 0.0, 20)
+    ref = opico.noise_map(cov, 31, 2, nprobes)
+    err = _rel(s, ref["sum"].ravel())
+    say(f"  rel err sum {err:.2e}, sumsq {_rel(ss, ref['sumsq'].ravel()):.2e}, CG relres max {st.max_relres:.2e}")
+    assert err < TOL and _rel(ss, ref["sumsq"].ravel()) < TOL
+
+
+def test_dense_form_apply_cov_tikhonov(lib):
+    say("case: dense normal form, apply_cov on 3 probes, lambda 0.1, 64x64, power method on the matrix cores")
+    prob = workloads.config(1, seed=4)
+    rng = np.random.default_rng(8)
+    v = (rng.standard_normal((3, 64, 64)) + 1j * rng.standard_normal((3, 64, 64)))
+    h = _init(lib, prob, 4, lam=0.1, cg_iters=30, form=2)
+    vt = _dev(v.astype(np.complex64))
+    ut = torch.empty_like(vt)
+    lib.pico_apply_cov(h, vt, ut, 3)
+    torch.cuda.synchronize()
+    lam_abs = lib.pico_lambda_abs(h)
+    lib.pico_destroy(h)
+    cov = opico.Covariance(opico.cartesian(prob.maps, prob.psi, prob.mask), 0.1, 30)
+    say(f"  lambda_abs gpu {lam_abs:.8e} oracle {cov.lam:.8e}")
+    assert abs(lam_abs - cov.lam) < 1e-5 * cov.lam
+    u = ut.cpu().numpy()
+    for k in range(3):
+        err = _rel(u[k], cov.apply(v[k]))
+        say(f"  probe {k}: rel err {err:.2e}")
+        assert err < TOL
 
 
 def test_degenerate_single_coil_full_sampling(lib):

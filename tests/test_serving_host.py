@@ -36,13 +36,21 @@ def _round(b):
 
 
 def test_estimate_cart1d_closed_form(p):
-    d, _ = p.make_desc(320, 320, 0x1000, None, 0x2000, ncoils=15, probe_tile=256, cg_iters=30)
-    res, peak = p.pico_estimate_bytes(d)
     n, K, nc = 320 * 320, 256, 15
     expect = (_round(n * nc * 8) + 4 * _round(n * K * 8) + _round(K * 320 * 4 * 8) + _round(512 * 8)
               + 4 * _round(K * 8) + _round(K * 4) + _round(320 * 4) + _round(320 * 8))
+    d, _ = p.make_desc(320, 320, 0x1000, None, 0x2000, ncoils=15, probe_tile=256, cg_iters=30,
+                       normal_form=1)
+    res, peak = p.pico_estimate_bytes(d)
     assert res == expect
     assert peak == expect + _round(2 * nc * nc * 8)      # the whitening matrix during init
+    # dense form: + the 320 blocks of 320 x 320 complex64 and the circulant
+    d, _ = p.make_desc(320, 320, 0x1000, None, 0x2000, ncoils=15, probe_tile=256, cg_iters=30,
+                       normal_form=2)
+    res, peak = p.pico_estimate_bytes(d)
+    assert res == expect + _round(320 * 320 * 320 * 8) + _round(320 * 16)
+    d, _ = p.make_desc(320, 320, 0x1000, None, 0x2000, ncoils=15, probe_tile=256, cg_iters=30)
+    assert p.pico_estimate_bytes(d)[0] == expect         # the default is the FFT form
 
 
 def test_estimate_grows_with_tile_and_kind(p):
