@@ -58,59 +58,126 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   CF::load_tw(tw, a.twx, lane);
 
   const size_t rowoff = ((size_t)k * a.ny + y) * a.nx;
+  // the per-probe fields never alias one another: restrict lets every load of
+  // the row go out before the first store
+  float2* __restrict__ X = a.x;
+  float2* __restrict__ R = a.r;
+  float2* __restrict__ P = a.p;
+  const float2* __restrict__ Q = a.q;
+  const float2* __restrict__ SRC = a.src;
   float2 pv[CF::VMAX];
   double d0 = 0.0;
+  float alpha = 0.f, beta = 0.f;
+  if constexpr (MODE == C1_ITER) {
+    alpha = (float)a.alpha[k];
+    beta = (float)a.beta[k];
+  }
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
     const int xx = CF::posA(lane, m);
+    const bool ok = inA && xx < a.nx;
+    const size_t i = rowoff + (ok ? xx : 0);   // in-bounds address for every lane
     float2 val = make_float2(0.f, 0.f);
-    if (inA && xx < a.nx) {
-      const size_t i = rowoff + xx;
-      if constexpr (MODE == C1_FIRST_PROBE) {
-        val = draw_probe(a.seed, a.first + k, (uint32_t)(y * a.nx + xx), 0u, a.dist);
-        if (active) { a.r[i] = val; a.p[i] = val; }
-        d0 += (double)val.x * val.x + (double)val.y * val.y;
-      } else if constexpr (MODE == C1_FIRST_BUF) {
-        val = a.r[i];
-        if (active) a.p[i] = val;
-        d0 += (double)val.x * val.x + (double)val.y * val.y;
-      } else if constexpr (MODE == C1_ITER) {
-        const float alpha = (float)a.alpha[k], beta = (float)a.beta[k];
-        const float2 po = a.p[i], qo = a.q[i];
-        const float2 xo = a.x_zero ? make_float2(0.f, 0.f) : a.x[i];
-        const float2 rn = cfma(a.r[i], -alpha, qo);
-        val = cfma(rn, beta, po);
-        if (active) {
-          a.x[i] = cfma(xo, alpha, po);
-          a.r[i] = rn;
-          a.p[i] = val;
-        }
-        d0 += (double)rn.x * rn.x + (double)rn.y * rn.y;
-      } else {  // C1_APPLY
-        val = cscale(a.src[i], a.scale);
-      }
+    if constexpr (MODE == C1_FIRST_PROBE) {
+      val = draw_probe(a.seed, a.first + k, (uint32_t)(y * a.nx + xx), 0u, a.dist);
+      if (!ok) val = make_float2(0.f, 0.f);
+      if (active && ok) { R[i] = val; P[i] = val; }
+      d0 += (double)val.x * val.x + (double)val.y * val.y;
+    } else if constexpr (MODE == C1_FIRST_BUF) {
+      val = ok ? R[i] : make_float2(0.f, 0.f);
+      if (active && ok) P[i] = val;
+      d0 += (double)val.x * val.x + (double)val.y * val.y;
+    } else if constexpr (MODE == C1_ITER) {
+      val = make_float2(0.f, 0.f);   // the update runs below, all loads first
+    } else {  // C1_APPLY
+      val = ok ? cscale(SRC[i], a.scale) : make_float2(0.f, 0.f);
     }
     pv[m] = val;
+  }
+  if constexpr (MODE == C1_ITER) {
+    // finish iteration i-1 and start i: x += alpha p, r -= alpha q, p = r + beta p.
+    // Every load of the row is issued before the first store.
+    float2 po[CF::VMAX], qo[CF::VMAX], ro[CF::VMAX], xo[CF::VMAX];
+#pragma unroll
+    for (int m = 0; m < VA; ++m) {
+      const int xx = CF::posA(lane, m);
+      const size_t i = rowoff + ((inA && xx < a.nx) ? xx : 0);
+      po[m] = P[i];
+      qo[m] = Q[i];
+      ro[m] = R[i];
+      xo[m] = X[i];
+    }
+    const bool xz = a.x_zero != 0;
+#pragma unroll
+    for (int m = 0; m < VA; ++m) {
+      const int xx = CF::posA(lane, m);
+      const bool ok = inA && xx < a.nx;
+      const size_t i = rowoff + (ok ? xx : 0);
+      const float2 rn = ok ? cfma(ro[m], -alpha, qo[m]) : make_float2(0.f, 0.f);
+      pv[m] = ok ? cfma(rn, beta, po[m]) : make_float2(0.f, 0.f);
+      if (active && ok) {
+        X[i] = cfma(xz ? make_float2(0.f, 0.f) : xo[m], alpha, po[m]);
+        R[i] = rn;
+        P[i] = pv[m];
+      }
+      d0 += (double)rn.x * rn.x + (double)rn.y * rn.y;
+    }
   }
   if constexpr (MODE != C1_APPLY) {
     d0 = group_reduce2<L>(d0, red, lane);
     if (active && lane == 0) a.part[((size_t)k * a.ny + y) * 4] = d0;
   }
 
+  float2* __restrict__ T = a.T;
   for (int c = 0; c < a.nc; ++c) {
     const float2* __restrict__ s = a.maps + ((size_t)c * a.ny + y) * a.nx;
     float2 v[CF::VMAX];
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
       const int xx = CF::posA(lane, m);
-      v[m] = (inA && xx < a.nx) ? cmul(s[xx], pv[m]) : make_float2(0.f, 0.f);
+      const bool ok = inA && xx < a.nx;
+      const float2 sv = s[ok ? xx : 0];
+      v[m] = ok ? cmul(sv, pv[m]) : make_float2(0.f, 0.f);
     }
     CF::template forward<false>(v, lds, lane, tw);
     if (active && inB) {
-      float2* t = a.T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+      float2* t = T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
 #pragma unroll
       for (int r = 0; r < VB; ++r) t[CF::posB(lane, r)] = v[r];
     }
+  }
+}
+
+// ---------------------------------------------------------------- column strips
+// Strip of `ncol` (<= ngrp) adjacent columns of one plane to / from an LDS tile
+// [rows][ts].  Loads go out in batches of 8 per thread before any is consumed,
+// so a workgroup keeps 8 x 256 loads in flight instead of one per thread.
+__device__ __forceinline__ void strip_load(float2* __restrict__ tile, const float2* __restrict__ src,
+                                           int rows, int ngrp, int ts, int ncol, long stride) {
+  constexpr int B = 8;
+  const int total = rows * ngrp;
+  for (int i0 = threadIdx.x; i0 < total; i0 += B * 256) {
+    float2 v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = i0 + u * 256;
+      const int yy = i / ngrp, j = i % ngrp;
+      v[u] = (i < total && j < ncol) ? src[(size_t)yy * stride + j] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = i0 + u * 256;
+      if (i < total) tile[(i / ngrp) * ts + i % ngrp] = v[u];
+    }
+  }
+}
+
+__device__ __forceinline__ void strip_store(const float2* __restrict__ tile, float2* __restrict__ dst,
+                                            int rows, int ngrp, int ts, int ncol, long stride) {
+  const int total = rows * ngrp;
+  for (int i = threadIdx.x; i < total; i += 256) {
+    const int yy = i / ngrp, j = i % ngrp;
+    if (j < ncol) dst[(size_t)yy * stride + j] = tile[yy * ts + j];
   }
 }
 
@@ -129,10 +196,7 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
   const int x0 = blockIdx.x * NGRP;
   const size_t plane = (size_t)blockIdx.y * a.ny * a.Gx;
   const int ncol = min(NGRP, a.Gx - x0);
-  for (int i = threadIdx.x; i < a.ny * NGRP; i += 256) {
-    const int yy = i / NGRP, j = i % NGRP;
-    tile[yy * TS + j] = j < ncol ? a.T[plane + (size_t)yy * a.Gx + x0 + j] : make_float2(0.f, 0.f);
-  }
+  strip_load(tile, a.T + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
   __syncthreads();
   const bool grp = g < NGRP && g < ncol;
   const bool inA = CF::inA(lane), inB = CF::inB(lane);
@@ -160,10 +224,7 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < a.ny * NGRP; i += 256) {
-    const int yy = i / NGRP, j = i % NGRP;
-    if (j < ncol) a.T[plane + (size_t)yy * a.Gx + x0 + j] = tile[yy * TS + j];
-  }
+  strip_store(tile, a.T + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
 }
 
 // ---------------------------------------------------------------- row pass 2
@@ -184,18 +245,27 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   CF::load_tw(tw, a.twx, lane);
   const size_t rowoff = ((size_t)k * a.ny + y) * a.nx;
 
-  float2 qa[CF::VMAX];
+  const float2* __restrict__ P = a.p;
+  const float2* __restrict__ R = a.r;
+  const float2* __restrict__ SRC = a.src;
+  const float2* __restrict__ T = a.T;
+  float2* __restrict__ Qo = a.q;
+  // p (or scale * src) of this row, loaded once: lam p now, the dots at the end
+  float2 pa[CF::VMAX];
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
     const int xx = CF::posA(lane, m);
-    float2 pval = make_float2(0.f, 0.f);
-    if (inA && xx < a.nx && a.lam != 0.f)
-      pval = MODE == C1_APPLY ? cscale(a.src[rowoff + xx], a.scale) : a.p[rowoff + xx];
-    qa[m] = cscale(pval, a.lam);
+    const bool ok = inA && xx < a.nx;
+    const size_t i = rowoff + (ok ? xx : 0);
+    const float2 pval = MODE == C1_APPLY ? cscale(SRC[i], a.scale) : P[i];
+    pa[m] = ok ? pval : make_float2(0.f, 0.f);
   }
+  float2 qa[CF::VMAX];
+#pragma unroll
+  for (int m = 0; m < VA; ++m) qa[m] = cscale(pa[m], a.lam);
   for (int c = 0; c < a.nc; ++c) {
     float2 v[CF::VMAX];
-    const float2* t = a.T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+    const float2* t = T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
 #pragma unroll
     for (int r = 0; r < VB; ++r) v[r] = inB ? t[CF::posB(lane, r)] : make_float2(0.f, 0.f);
     CF::template inverse<true>(v, lds, lane, tw);
@@ -203,21 +273,23 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
       const int xx = CF::posA(lane, m);
-      if (inA && xx < a.nx) qa[m] = cadd(qa[m], cmulc(s[xx], v[m]));
+      const bool ok = inA && xx < a.nx;
+      const float2 sv = s[ok ? xx : 0];
+      if (ok) qa[m] = cadd(qa[m], cmulc(sv, v[m]));
     }
   }
   double d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
     const int xx = CF::posA(lane, m);
-    if (inA && xx < a.nx) {
-      const size_t i = rowoff + xx;
-      const float2 pval = MODE == C1_APPLY ? cscale(a.src[i], a.scale) : a.p[i];
-      const float2 rval = MODE == C1_ITER ? a.r[i] : pval;
-      if (active) a.q[i] = qa[m];
-      d1 += (double)pval.x * qa[m].x + (double)pval.y * qa[m].y;
+    const bool ok = inA && xx < a.nx;
+    const size_t i = rowoff + (ok ? xx : 0);
+    const float2 rv = MODE == C1_ITER ? R[i] : pa[m];
+    if (ok) {
+      if (active) Qo[i] = qa[m];
+      d1 += (double)pa[m].x * qa[m].x + (double)pa[m].y * qa[m].y;
       d2 += (double)qa[m].x * qa[m].x + (double)qa[m].y * qa[m].y;
-      d3 += (double)rval.x * qa[m].x + (double)rval.y * qa[m].y;
+      d3 += (double)rv.x * qa[m].x + (double)rv.y * qa[m].y;
     }
   }
   d1 = group_reduce2<L>(d1, red, lane);
@@ -375,10 +447,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(float2* data, int ny, int nx, 
   const int x0 = blockIdx.x * NGRP;
   const size_t plane = (size_t)blockIdx.y * ny * nx;
   const int ncol = min(NGRP, nx - x0);
-  for (int i = threadIdx.x; i < ny * NGRP; i += 256) {
-    const int yy = i / NGRP, j = i % NGRP;
-    tile[yy * TS + j] = j < ncol ? data[plane + (size_t)yy * nx + x0 + j] : make_float2(0.f, 0.f);
-  }
+  strip_load(tile, data + plane + x0, ny, NGRP, TS, ncol, nx);
   __syncthreads();
   const bool grp = g < NGRP && g < ncol;
   typename CF::Tw tw;
@@ -394,10 +463,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(float2* data, int ny, int nx, 
     for (int r = 0; r < CF::VB; ++r) tile[CF::posB(lane, r) * TS + g] = v[r];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ny * NGRP; i += 256) {
-    const int yy = i / NGRP, j = i % NGRP;
-    if (j < ncol) data[plane + (size_t)yy * nx + x0 + j] = tile[yy * TS + j];
-  }
+  strip_store(tile, data + plane + x0, ny, NGRP, TS, ncol, nx);
 }
 
 template <class CF, bool INV>
