@@ -96,31 +96,38 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   }
   if constexpr (MODE == C1_ITER) {
     // finish iteration i-1 and start i: x += alpha p, r -= alpha q, p = r + beta p.
-    // Every load of the row is issued before the first store.
-    float2 po[CF::VMAX], qo[CF::VMAX], ro[CF::VMAX], xo[CF::VMAX];
-#pragma unroll
-    for (int m = 0; m < VA; ++m) {
-      const int xx = CF::posA(lane, m);
-      const size_t i = rowoff + ((inA && xx < a.nx) ? xx : 0);
-      po[m] = P[i];
-      qo[m] = Q[i];
-      ro[m] = R[i];
-      xo[m] = X[i];
-    }
+    // In chunks of H elements, every load of a chunk is issued before its first store.
+    constexpr int H = VA > 8 ? 8 : VA;
     const bool xz = a.x_zero != 0;
 #pragma unroll
-    for (int m = 0; m < VA; ++m) {
-      const int xx = CF::posA(lane, m);
-      const bool ok = inA && xx < a.nx;
-      const size_t i = rowoff + (ok ? xx : 0);
-      const float2 rn = ok ? cfma(ro[m], -alpha, qo[m]) : make_float2(0.f, 0.f);
-      pv[m] = ok ? cfma(rn, beta, po[m]) : make_float2(0.f, 0.f);
-      if (active && ok) {
-        X[i] = cfma(xz ? make_float2(0.f, 0.f) : xo[m], alpha, po[m]);
-        R[i] = rn;
-        P[i] = pv[m];
+    for (int m0 = 0; m0 < VA; m0 += H) {
+      float2 po[H], qo[H], ro[H], xo[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        if (m0 + h >= VA) break;
+        const int xx = CF::posA(lane, m0 + h);
+        const size_t i = rowoff + ((inA && xx < a.nx) ? xx : 0);
+        po[h] = P[i];
+        qo[h] = Q[i];
+        ro[h] = R[i];
+        xo[h] = X[i];
       }
-      d0 += (double)rn.x * rn.x + (double)rn.y * rn.y;
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int m = m0 + h;
+        if (m >= VA) break;
+        const int xx = CF::posA(lane, m);
+        const bool ok = inA && xx < a.nx;
+        const size_t i = rowoff + (ok ? xx : 0);
+        const float2 rn = ok ? cfma(ro[h], -alpha, qo[h]) : make_float2(0.f, 0.f);
+        pv[m] = ok ? cfma(rn, beta, po[h]) : make_float2(0.f, 0.f);
+        if (active && ok) {
+          X[i] = cfma(xz ? make_float2(0.f, 0.f) : xo[h], alpha, po[h]);
+          R[i] = rn;
+          P[i] = pv[m];
+        }
+        d0 += (double)rn.x * rn.x + (double)rn.y * rn.y;
+      }
     }
   }
   if constexpr (MODE != C1_APPLY) {
@@ -250,19 +257,27 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   const float2* __restrict__ SRC = a.src;
   const float2* __restrict__ T = a.T;
   float2* __restrict__ Qo = a.q;
-  // p (or scale * src) of this row, loaded once: lam p now, the dots at the end
-  float2 pa[CF::VMAX];
+  // p (or scale * src) of this row: lam p enters q first (when lam != 0); the
+  // dots at the end load it again
+  auto load_p = [&](float2* pa) {
 #pragma unroll
-  for (int m = 0; m < VA; ++m) {
-    const int xx = CF::posA(lane, m);
-    const bool ok = inA && xx < a.nx;
-    const size_t i = rowoff + (ok ? xx : 0);
-    const float2 pval = MODE == C1_APPLY ? cscale(SRC[i], a.scale) : P[i];
-    pa[m] = ok ? pval : make_float2(0.f, 0.f);
-  }
+    for (int m = 0; m < VA; ++m) {
+      const int xx = CF::posA(lane, m);
+      const bool ok = inA && xx < a.nx;
+      const size_t i = rowoff + (ok ? xx : 0);
+      const float2 pval = MODE == C1_APPLY ? cscale(SRC[i], a.scale) : P[i];
+      pa[m] = ok ? pval : make_float2(0.f, 0.f);
+    }
+  };
   float2 qa[CF::VMAX];
+  if (a.lam != 0.f) {
+    load_p(qa);
 #pragma unroll
-  for (int m = 0; m < VA; ++m) qa[m] = cscale(pa[m], a.lam);
+    for (int m = 0; m < VA; ++m) qa[m] = cscale(qa[m], a.lam);
+  } else {
+#pragma unroll
+    for (int m = 0; m < VA; ++m) qa[m] = make_float2(0.f, 0.f);
+  }
   for (int c = 0; c < a.nc; ++c) {
     float2 v[CF::VMAX];
     const float2* t = T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
@@ -278,13 +293,21 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
       if (ok) qa[m] = cadd(qa[m], cmulc(sv, v[m]));
     }
   }
+  float2 pa[CF::VMAX], ra[CF::VMAX];
+  load_p(pa);
+#pragma unroll
+  for (int m = 0; m < VA; ++m) {
+    const int xx = CF::posA(lane, m);
+    const size_t i = rowoff + ((inA && xx < a.nx) ? xx : 0);
+    ra[m] = MODE == C1_ITER ? R[i] : pa[m];
+  }
   double d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
     const int xx = CF::posA(lane, m);
     const bool ok = inA && xx < a.nx;
     const size_t i = rowoff + (ok ? xx : 0);
-    const float2 rv = MODE == C1_ITER ? R[i] : pa[m];
+    const float2 rv = ra[m];
     if (ok) {
       if (active) Qo[i] = qa[m];
       d1 += (double)pa[m].x * qa[m].x + (double)pa[m].y * qa[m].y;
