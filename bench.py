@@ -320,6 +320,18 @@ def main():
         out["n_at_1pct"] = n_hit
         out["nrmse_curve"] = curve[:12]
 
+    # --- adaptive stopping without a reference: probe tiles until the
+    # standard-error proxy of the std map reaches 1 %; NRMSE vs exact reported
+    if not args.no_ref:
+        acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        acc = lib.make_accum(*acc_t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        used, proxy = lib.pico_noise_map_adaptive(h, 7, 0, 4096, 0.01, 0, acc)
+        t_ad = time.perf_counter() - t0
+        out["adaptive_1pct"] = {"seconds": round(t_ad, 5), "probes": used, "proxy": round(proxy, 5),
+                                "nrmse_vs_exact": round(lib.pico_monitor_nrmse(h, acc, ref), 5)}
+
     # --- steady-state throughput: K=256 probes per step
     acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
     acc = lib.make_accum(*acc_t)

@@ -207,6 +207,25 @@ double pico_lambda_abs(pico_op_t op);
 pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const double* ref_var,
                                  double* nrmse, void* stream);
 
+/* Reference-free error estimate of a running map, for adaptive stopping
+ * (Sec. 4 discussion: stopping on the per-voxel standard error): with m =
+ * sum / N and s2 = (sumsq - N m^2) / (N - 1) the sample variance of the N
+ * per-probe terms Re(conj v u), the estimate m has variance s2 / N, and the
+ * std map sqrt(m) an error of about s2 / (4 N m) (first order); *proxy =
+ * sqrt(sum_k s2_k / (4 N m_k) / sum_k m_k) over voxels with m_k > 0, the
+ * expected NRMSE of the std map.  Needs acc->sumsq and count >= 2; waits for
+ * ``stream``; reuses the operator's scratch (no overlap with other calls).
+ *
+ * pico_noise_map_adaptive adds probe tiles (probe_tile probes each, from
+ * first_probe on) until *proxy <= target or max_probes probes are in; *used
+ * and *proxy (either may be NULL) report where it stopped.  Same accumulator
+ * and stats semantics as pico_noise_map; CG-SENSE operators only
+ * (PICO_EUNSUPPORTED for CS).  Errors: PICO_EINVAL, PICO_EDEVICE, PICO_ENOTCONV. */
+pico_status_t pico_monitor_stderr(pico_op_t op, const pico_accum_t* acc, double* proxy, void* stream);
+pico_status_t pico_noise_map_adaptive(pico_op_t op, uint64_t seed, int64_t first_probe, int64_t max_probes,
+                                      double target, int32_t dist, pico_accum_t* acc, pico_stats_t* stats,
+                                      int64_t* used, double* proxy, void* stream);
+
 /* Exact variance map diag(Sigma) into var (device float64 [ny*nx]) for a
  * phase-encode (PICO_CART_1D) operator: Sigma is block diagonal over image
  * columns (the mask is constant along kx), so the probe equal to 1 on one

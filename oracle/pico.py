@@ -200,6 +200,23 @@ def nrmse_std(var_est, var_ref):
     return float(np.linalg.norm(s - s0) / np.linalg.norm(s0))
 
 
+def stderr_proxy(acc):
+    """Reference-free estimate of the std-map NRMSE of the running estimate.
+
+    m = sum / N per voxel; the N per-probe terms Re(conj v u) have sample
+    variance s2 = (sumsq - N m^2) / (N - 1), so m has variance s2 / N and,
+    to first order, sqrt(m) has variance s2 / (4 N m).  The proxy is
+    sqrt(sum_k s2_k / (4 N m_k) / sum_k m_k) over voxels with m_k > 0: the
+    expected ||sqrt(m) - sigma|| / ||sigma|| (adaptive stopping on the
+    per-voxel standard error, Sec. 4 discussion).
+    """
+    N = float(acc["count"])
+    m = acc["sum"] / N
+    s2 = np.maximum((acc["sumsq"] - N * m * m) / (N - 1.0), 0.0)
+    pos = m > 0
+    return float(np.sqrt(np.sum(s2[pos] / (4.0 * N * m[pos])) / np.sum(m[pos])))
+
+
 def nrmse_var(var_est, var_ref):
     """NRMSE of variance maps."""
     return float(np.linalg.norm(var_est - var_ref) / np.linalg.norm(var_ref))

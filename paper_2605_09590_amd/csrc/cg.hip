@@ -118,6 +118,44 @@ hipError_t launch_nrmse_partials(const double* sum, double inv_count, const doub
   return hipGetLastError();
 }
 
+// Reference-free error proxy of the running map (adaptive stopping): per voxel
+// the sample variance of the N per-probe terms, s2 = (sumsq - N m^2) / (N - 1),
+// m = sum / N, gives the variance of m as s2 / N; through sigma = sqrt(m) the
+// std map's error is s2 / (4 N m).  Partials: sum of s2 / (4 N m) and of m over
+// voxels with m > 0.
+__global__ __launch_bounds__(256) void k_stderr_partials(const double* __restrict__ sum,
+                                                         const double* __restrict__ sumsq, double N,
+                                                         int64_t n, double* __restrict__ part) {
+  double num = 0.0, den = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double m = sum[i] / N;
+    if (m > 0.0) {
+      const double s2 = fmax((sumsq[i] - N * m * m) / (N - 1.0), 0.0);
+      num += s2 / (4.0 * N * m);
+      den += m;
+    }
+  }
+  num = group_sum<64>(num);
+  den = group_sum<64>(den);
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = num;
+    red[1][w] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    part[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+hipError_t launch_stderr_partials(const double* sum, const double* sumsq, double count, int64_t n,
+                                  double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_stderr_partials, dim3(nblk), dim3(256), 0, s, sum, sumsq, count, n, part);
+  return hipGetLastError();
+}
+
 // var = sum / N  (App. A, Algorithm 1, last step)
 __global__ void k_finalize(const double* __restrict__ sum, double* __restrict__ var, int64_t n, double inv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -1100,6 +1100,64 @@ pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* v
   return PICO_OK;
 }
 
+pico_status_t pico_monitor_stderr(pico_op_t op, const pico_accum_t* acc, double* proxy, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!acc || !acc->sum || !acc->sumsq || !proxy) return fail(PICO_EINVAL, "NULL accumulator field or output");
+  if (acc->count < 2) return fail(PICO_EINVAL, "need at least 2 probes");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = (int64_t)op->image();
+  const int nblk = (int)std::min<int64_t>(256, (n + 255) / 256);
+  std::vector<double> part(2 * nblk);
+  HIP_OR_RETURN(pico::launch_stderr_partials(acc->sum, acc->sumsq, (double)acc->count, n, op->mon, nblk, s));
+  HIP_OR_RETURN(hipMemcpyAsync(part.data(), op->mon, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OR_RETURN(hipStreamSynchronize(s));
+  double num = 0.0, den = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    num += part[2 * b];
+    den += part[2 * b + 1];
+  }
+  *proxy = den > 0.0 ? std::sqrt(num / den) : INFINITY;
+  return PICO_OK;
+}
+
+pico_status_t pico_noise_map_adaptive(pico_op_t op, uint64_t seed, int64_t first_probe, int64_t max_probes,
+                                      double target, int32_t dist, pico_accum_t* acc, pico_stats_t* stats,
+                                      int64_t* used, double* proxy, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!acc || !acc->sum || !acc->sumsq) return fail(PICO_EINVAL, "adaptive stopping needs sum and sumsq buffers");
+  if (op->cs) return fail(PICO_EUNSUPPORTED, "adaptive stopping uses the Re(conj v u) terms of CG-SENSE operators");
+  if (max_probes < 2 || first_probe < 0) return fail(PICO_EINVAL, "max_probes must be >= 2, first_probe >= 0");
+  if (!(target > 0.0)) return fail(PICO_EINVAL, "target must be > 0");
+  int64_t done = 0;
+  double px = INFINITY;
+  pico_stats_t st{}, tot{};
+  while (done < max_probes) {
+    const int64_t k = std::min<int64_t>(op->K, max_probes - done);
+    pico_status_t r = pico_noise_map(op, seed, first_probe + done, k, dist, acc, stats ? &st : nullptr, stream);
+    if (r != PICO_OK && r != PICO_ENOTCONV) return r;
+    if (stats) {
+      tot.max_relres = std::max(tot.max_relres, st.max_relres);
+      tot.mean_relres = (tot.mean_relres * (double)tot.probes + st.mean_relres * (double)st.probes) /
+                        (double)(tot.probes + st.probes);
+      tot.frozen += st.frozen;
+      tot.probes += st.probes;
+      tot.lambda_abs = st.lambda_abs;
+    }
+    done += k;
+    if (acc->count >= 2) {
+      if (pico_status_t e = pico_monitor_stderr(op, acc, &px, stream)) return e;
+      if (px <= target) break;
+    }
+  }
+  if (used) *used = done;
+  if (proxy) *proxy = px;
+  if (stats) {
+    *stats = tot;
+    if (tot.frozen) return fail(PICO_ENOTCONV, "CG breakdown in " + std::to_string(tot.frozen) + " right-hand side(s)");
+  }
+  return PICO_OK;
+}
+
 pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const double* ref_var,
                                  double* nrmse, void* stream) {
   if (pico_status_t st = check_op(op)) return st;

@@ -211,6 +211,8 @@ hipError_t launch_power_start(float2* p, int ny, int nx, hipStream_t s);
 hipError_t launch_unit_rows(float2* r, int K, int y0, int ny, int nx, hipStream_t s);
 hipError_t launch_extract_rows(const float2* x, double* var, int K, int y0, int ny, int nx,
                                hipStream_t s);
+hipError_t launch_stderr_partials(const double* sum, const double* sumsq, double count, int64_t n,
+                                  double* part, int nblk, hipStream_t s);
 hipError_t launch_nrmse_partials(const double* sum, double inv_count, const double* ref, int64_t n,
                                  double* part, int nblk, hipStream_t s);
 

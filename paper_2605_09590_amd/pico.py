@@ -76,7 +76,7 @@ class PicoError(RuntimeError):
 _lib = None
 
 EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
-           "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse", "pico_exact_diag",
+           "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse", "pico_monitor_stderr", "pico_noise_map_adaptive", "pico_exact_diag",
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
            "pico_server_submit", "pico_server_poll", "pico_server_wait_idle", "pico_server_usage",
@@ -110,6 +110,10 @@ def load(path: str = LIB_PATH):
     lib.pico_monitor_nrmse.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp,
                                        ctypes.POINTER(ctypes.c_double), vp]
     lib.pico_exact_diag.argtypes = [vp, vp, vp]
+    lib.pico_monitor_stderr.argtypes = [vp, ctypes.POINTER(pico_accum_t), ctypes.POINTER(ctypes.c_double), vp]
+    lib.pico_noise_map_adaptive.argtypes = [vp, u64, i64, i64, ctypes.c_double, i32, ctypes.POINTER(pico_accum_t),
+                                            ctypes.POINTER(pico_stats_t), ctypes.POINTER(i64),
+                                            ctypes.POINTER(ctypes.c_double), vp]
     lib.pico_profile_start.argtypes = [vp]
     lib.pico_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]
@@ -135,6 +139,7 @@ def load(path: str = LIB_PATH):
     for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
                  "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse",
                  "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
+                 "pico_monitor_stderr", "pico_noise_map_adaptive",
                  "pico_estimate_bytes", "pico_op_bytes", "pico_server_create", "pico_server_submit",
                  "pico_server_poll", "pico_server_wait_idle", "pico_server_usage"):
         getattr(lib, name).restype = ctypes.c_int
@@ -285,6 +290,22 @@ def pico_monitor_nrmse(h, acc, ref_var, stream=None) -> float:
     _check(load().pico_monitor_nrmse(h, ctypes.byref(acc), _ptr(ref_var), ctypes.byref(out),
                                      _stream(stream)))
     return out.value
+
+
+def pico_monitor_stderr(h, acc, stream=None) -> float:
+    v = ctypes.c_double()
+    _check(load().pico_monitor_stderr(h, ctypes.byref(acc), ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def pico_noise_map_adaptive(h, seed, first_probe, max_probes, target, dist, acc, stats=None, stream=None):
+    """Returns (probes used, final proxy)."""
+    used, px = ctypes.c_int64(), ctypes.c_double()
+    _check(load().pico_noise_map_adaptive(h, int(seed), int(first_probe), int(max_probes), float(target),
+                                          int(dist), ctypes.byref(acc),
+                                          ctypes.byref(stats) if stats is not None else None,
+                                          ctypes.byref(used), ctypes.byref(px), _stream(stream)))
+    return used.value, px.value
 
 
 def pico_exact_diag(h, var, stream=None):

@@ -267,3 +267,29 @@ def test_exact_diag_and_monitor(lib):
     say(f"  exact diag rel err {err:.2e}; monitor NRMSE gpu {e_gpu:.6f} oracle {e_ref:.6f}")
     assert err < TOL
     assert abs(e_gpu - e_ref) < 1e-6
+
+
+def test_stderr_proxy_and_adaptive_stopping(lib):
+    say("case: reference-free error proxy and adaptive stopping, 160x24 8 coils R=2 + 16 ACS, tiles of 16")
+    prob = workloads.config(2, seed=1, ny=160, nx=24, nc=8, acs=16, cg_iters=40)
+    n = prob.ny * prob.nx
+    h = _init(lib, prob, 16)
+    (s, si, ss), acc = _gpu_map(lib, h, n, 9, 0, 48)
+    px = lib.pico_monitor_stderr(h, acc)
+    cov = opico.Covariance(opico.cartesian(prob.maps, prob.psi, prob.mask), 0.0, 40)
+    ref = opico.noise_map(cov, 9, 0, 48)
+    p_ref = opico.stderr_proxy(ref)
+    say(f"  proxy gpu {px:.6f} oracle {p_ref:.6f}")
+    assert abs(px - p_ref) < 1e-4 * p_ref
+    # adaptive run to a 5 % proxy; check the std-map NRMSE against the exact map
+    ex = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    lib.pico_exact_diag(h, ex)
+    acc_t = [torch.zeros(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    acc2 = lib.make_accum(*acc_t)
+    used, pfin = lib.pico_noise_map_adaptive(h, 17, 0, 4096, 0.05, 0, acc2)
+    err = lib.pico_monitor_nrmse(h, acc2, ex)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    say(f"  adaptive: stopped at N={used} with proxy {pfin:.4f}; NRMSE vs exact {err:.4f}")
+    assert used % 16 == 0 and used < 4096 and pfin <= 0.05
+    assert err < 0.075

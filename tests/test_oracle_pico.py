@@ -159,3 +159,35 @@ def test_exact_columns_estimator_matches_converged_cg():
     acc_l = pico.noise_map(cov_l, 5, 0, 3)
     ex_l = pico.noise_map_exact_columns(op, op.P[:, 0], 5, 0, 3, cols, lam=cov_l.lam)
     assert np.allclose(acc_l["sum"][:, cols], ex_l, rtol=1e-9, atol=1e-12)
+
+
+def test_stderr_proxy_matches_closed_form_and_monte_carlo():
+    # per-voxel variance of the random-phase terms: E[s2_k] = 1/2 sum_{l!=k} |Sigma_kl|^2
+    # (Re part of App. B, Eq. (A1)); and the proxy predicts the RMS std-map NRMSE
+    # of independent N-probe runs against the exact diagonal
+    op = _op(16, 8, nc=3, R=2)
+    Sigma = np.linalg.inv(op.dense_normal())
+    off = np.abs(Sigma) ** 2
+    np.fill_diagonal(off, 0)
+    half = 0.5 * off.sum(1)
+    exact = np.real(np.diag(Sigma))
+    cov = pico.Covariance(op, 0.0, cg_iters=60)
+    big = pico.noise_map(cov, 3, 0, 2000)
+    N = big["count"]
+    m = big["sum"].ravel() / N
+    s2 = (big["sumsq"].ravel() - N * m * m) / (N - 1)
+    assert abs(s2.mean() / half.mean() - 1.0) < 0.06
+    errs, proxies = [], []
+    for r in range(40):
+        acc = pico.noise_map(cov, 5, 24 * r, 24)
+        errs.append(pico.nrmse_std(pico.finalize(acc), exact.reshape(acc["sum"].shape)))
+        proxies.append(pico.stderr_proxy(acc))
+    rms = float(np.sqrt(np.mean(np.square(errs))))
+    assert abs(np.mean(proxies) / rms - 1.0) < 0.2
+    # a diagonal covariance (full sampling, one coil of unit magnitude) makes
+    # every probe exact: zero spread, zero proxy
+    yy, xx = np.meshgrid(np.arange(8), np.arange(4), indexing="ij")
+    maps = np.exp(2j * np.pi * 0.1 * yy)[None] * np.ones((1, 8, 4))
+    op1 = pico.cartesian(maps, np.array([[2.0]]), np.ones(8, np.uint8))
+    acc = pico.noise_map(pico.Covariance(op1, 0.0, cg_iters=4), 1, 0, 5)
+    assert pico.stderr_proxy(acc) < 1e-7          # rounding of sumsq - N m^2 only
