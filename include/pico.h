@@ -208,7 +208,7 @@ pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const do
                                  double* nrmse, void* stream);
 
 /* Reference-free error estimate of a running map, for adaptive stopping
- * (Sec. 4 discussion: stopping on the per-voxel standard error): with m =
+ * (Sec. 5, Discussion: stopping on the per-voxel standard error): with m =
  * sum / N and s2 = (sumsq - N m^2) / (N - 1) the sample variance of the N
  * per-probe terms Re(conj v u), the estimate m has variance s2 / N, and the
  * std map sqrt(m) an error of about s2 / (4 N m) (first order); *proxy =

@@ -208,7 +208,7 @@ def stderr_proxy(acc):
     to first order, sqrt(m) has variance s2 / (4 N m).  The proxy is
     sqrt(sum_k s2_k / (4 N m_k) / sum_k m_k) over voxels with m_k > 0: the
     expected ||sqrt(m) - sigma|| / ||sigma|| (adaptive stopping on the
-    per-voxel standard error, Sec. 4 discussion).
+    per-voxel standard error, Sec. 5, Discussion).
     """
     N = float(acc["count"])
     m = acc["sum"] / N
