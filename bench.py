@@ -320,6 +320,47 @@ def main():
         out["n_at_1pct"] = n_hit
         out["nrmse_curve"] = curve[:12]
 
+    # --- the PMR baseline on the same workload and reference: replicas in chunks
+    # of 32 until the std map of the unbiased sample variance is within 1 %
+    if not (args.no_ttt or args.no_ref):
+        acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        acc = lib.make_accum(*acc_t)
+        var = torch.empty(n, dtype=torch.float64, device=dev)
+        s_ref = torch.sqrt(torch.clamp(ref, min=0.0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, hit = 0, None
+        while done < 8192:
+            lib.pico_pmr_baseline(h, 3, done, 32, acc)
+            done += 32
+            lib.pico_pmr_finalize(h, acc, var)
+            e = float(torch.linalg.norm(torch.sqrt(torch.clamp(var, min=0.0)) - s_ref) / torch.linalg.norm(s_ref))
+            if e <= 0.01:
+                hit = (time.perf_counter() - t0, done)
+                break
+        out["pmr_time_to_1pct_s"] = round(hit[0], 5) if hit else None
+        out["pmr_n_at_1pct"] = hit[1] if hit else None
+        out["pmr_nrmse_at_stop"] = round(e, 5)
+
+    # --- probe families (Sec. 2.2, Eqs. (18)-(20)): probes to a 1 % std map
+    if not (args.no_ttt or args.no_ref):
+        fam = {}
+        for name, dist in (("random_phase", 0), ("qpsk", 1), ("rademacher", 2), ("gaussian", 3)):
+            acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+            acc = lib.make_accum(acc_t[0], None, acc_t[1])
+            done, n_hit, e64 = 0, None, None
+            while done < 4096:
+                lib.pico_noise_map(h, 41, done, 32, dist, acc)
+                done += 32
+                e = lib.pico_monitor_nrmse(h, acc, ref)
+                if done == 64:
+                    e64 = round(e, 5)
+                if e <= 0.01:
+                    n_hit = done
+                    break
+            fam[name] = {"n_at_1pct": n_hit, "nrmse_at_64": e64}
+        out["probe_families"] = fam
+
     # --- adaptive stopping without a reference: probe tiles until the
     # standard-error proxy of the std map reaches 1 %; NRMSE vs exact reported
     if not args.no_ref:
@@ -364,7 +405,7 @@ def main():
     it_ms, it_n = prof["normal_iter"]
     avg_s = it_ms / it_n / 1e3
     flops = normal_op_flops(ny, nx, nc) * K
-    bytes_alg = K * 4 * 8 * n + nc * n * 8           # read r, p; write p, q; maps once
+    bytes_alg = K * 8 * 8 * n + nc * n * 8           # x, r, p, q read and written; maps once
     achieved_tf = flops / avg_s / 1e12
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic_normal_iter_cart1d_320x320x15_K256.json")
