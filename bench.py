@@ -244,6 +244,47 @@ def cs_leg(lib, workloads, torch, np, dev, steps):
     }
 
 
+def cs_robustness(lib, workloads, torch, np, dev, N=128):
+    """Noise-level sweep of the CS workload (Sec. 3.2.3, robustness): data at
+    input SNR 45 dB - 20 log10(scale); per level the Jacobian-probe std map
+    (N probes) against the PMR std map (N replicas perturbed at the data's own
+    noise level, normalised by it); both per unit whitened noise."""
+    pr = workloads.config(4, seed=0)
+    n = pr.ny * pr.nx
+    maps = torch.from_numpy(pr.maps.astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(pr.mask).to(dev)
+    rows = []
+    for scale in (1, 5, 10, 50, 100, 200):
+        snr = 45.0 - 20.0 * math.log10(scale)
+        kd = cs_kspace_arrays(torch, dev, pr.maps, pr.psi, pr.mask, pr.extra["phantom"], snr, seed=0)
+        # whitened noise std of the data: the signal rms on the mask times 10^(-snr/20)
+        xs = torch.from_numpy(pr.extra["phantom"].astype(np.complex128)).to(dev)
+        mk = torch.from_numpy(pr.mask.astype(np.float64)).to(dev)
+        k0 = torch.fft.fftshift(torch.fft.fft2(torch.fft.ifftshift(
+            torch.from_numpy(pr.maps.astype(np.complex128)).to(dev) * xs[None], dim=(-2, -1)), norm="ortho"),
+            dim=(-2, -1)) * mk[None]
+        sigma = float(torch.sqrt(torch.mean(torch.abs(k0[:, mk > 0]) ** 2))) * 10 ** (-snr / 20)
+        h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, sampling=lib.PICO_CART_2D,
+                          recon=lib.PICO_CS_FISTA_L1WAV, kdata=kd, fista_iters=pr.extra["fista_iters"],
+                          cs_lambda=pr.extra["cs_lambda"], wavelet_levels=pr.extra["levels"], probe_tile=128)
+        a1 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+        lib.pico_noise_map(h, 3, 0, N, 0, lib.make_accum(a1[0], None, a1[1]))
+        a2 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        acc2 = lib.make_accum(*a2)
+        lib.pico_pmr_cs(h, 5, 0, N, sigma, acc2)
+        var = torch.empty(n, dtype=torch.float64, device=dev)
+        lib.pico_pmr_finalize(h, acc2, var)
+        torch.cuda.synchronize()
+        lib.pico_destroy(h)
+        s_pico = torch.sqrt(torch.clamp(a1[0] / N, min=0.0))
+        s_pmr = torch.sqrt(torch.clamp(var, min=0.0))
+        rows.append({"scale": scale, "snr_db": round(snr, 1), "sigma": sigma,
+                     "nrmse_pmr_vs_pico": round(float(torch.linalg.norm(s_pmr - s_pico) / torch.linalg.norm(s_pico)), 4),
+                     "mean_std_pico": float(s_pico.mean()), "mean_std_pmr": float(s_pmr.mean())})
+    return {"workload": f"CS 320x320, 8 coils, lambda 1e-3, FISTA 100; N={N} probes and {N} replicas per level",
+            "levels": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +300,8 @@ def main():
                     help="steps of the compressed-sensing JVP leg (0 to skip)")
     ap.add_argument("--serve", choices=["off", "short", "full"], default="short",
                     help="serving leg: short request mix (default), the full sweep, or off")
+    ap.add_argument("--cs-robustness", action="store_true",
+                    help="also run the CS noise-level sweep (PICO vs PMR std maps)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -476,6 +519,8 @@ def main():
     if args.cs_steps > 0:
         cs_res = cs_leg(lib, workloads, torch, np, dev, args.cs_steps)
 
+    robust = cs_robustness(lib, workloads, torch, np, dev) if args.cs_robustness else None
+
     # --- serving: mixed requests under Poisson arrivals, p50 / p99 latency
     serving = None
     if args.serve != "off":
@@ -514,6 +559,8 @@ def main():
         "cs": cs_res,
         "serving": serving,
     }
+    if robust is not None:
+        res["cs_robustness"] = robust
     if args.copy_calib:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         b = torch.empty_like(a)
