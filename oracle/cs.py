@@ -110,6 +110,133 @@ class FistaL1Wavelet:
         return x_prev
 
 
+# ---------------------------------------------------------------- TV model
+# The paper's CS reconstruction (Sec. 3.2.3) penalises lam_TV ||grad x||_1 and
+# runs FISTA; it does not say how the TV proximal step is computed.  Readings:
+# isotropic TV of the complex image, TV(x) = sum_r sqrt(|D_y x|_r^2 + |D_x x|_r^2),
+# forward differences with periodic wrap (D_y x[y] = x[y+1] - x[y]); the
+# proximal step prox_{lam TV}(z) by the fast gradient projection on the dual
+# (Beck and Teboulle, IEEE TIP 2009): p, r in C^{2 x ny x nx}, from r = p = 0,
+#     w = r + (1 / (8 lam)) D (z - lam D^H r),  p' = P(w),
+#     r' = p' + ((s - 1) / s') (p' - p),  s' = (1 + sqrt(1 + 4 s^2)) / 2,
+# with P the per-pixel projection onto {|p_y|^2 + |p_x|^2 <= 1}, for a fixed
+# number of inner iterations, and x = z - lam D^H p.  The reconstruction map
+# is then a composition of steps differentiable almost everywhere; its
+# forward-mode derivative runs through the unrolled inner iterations (what
+# automatic differentiation of such an implementation evaluates), with
+# dP(w) dw = dw for |w| <= 1 and (dw - w^ Re(w^H dw)) / |w| otherwise.
+
+
+def tv_grad(x):
+    """D x: forward differences along y and x, periodic; shape (2, ny, nx)."""
+    return np.stack([np.roll(x, -1, axis=-2) - x, np.roll(x, -1, axis=-1) - x])
+
+
+def tv_grad_adj(p):
+    """D^H p (the negative divergence): p_y[y-1] - p_y[y] + p_x[x-1] - p_x[x]."""
+    return (np.roll(p[0], 1, axis=-2) - p[0]) + (np.roll(p[1], 1, axis=-1) - p[1])
+
+
+def ball_proj(w):
+    n = np.sqrt(np.abs(w[0]) ** 2 + np.abs(w[1]) ** 2)
+    return w / np.maximum(n, 1.0)
+
+
+def ball_dproj(w, dw):
+    n = np.sqrt(np.abs(w[0]) ** 2 + np.abs(w[1]) ** 2)
+    out = np.array(dw, copy=True)
+    big = n > 1.0
+    if np.any(big):
+        wh = w[:, big] / n[big]
+        re = np.real(np.conj(wh[0]) * dw[0][big] + np.conj(wh[1]) * dw[1][big])
+        out[:, big] = (dw[:, big] - wh * re) / n[big]
+    return out
+
+
+def tv_prox(z, lam, inner):
+    """prox_{lam TV}(z) by ``inner`` dual fast-gradient-projection steps from zero."""
+    if lam == 0.0:
+        return np.array(z, copy=True)
+    p = np.zeros((2,) + z.shape, np.complex128)
+    r = p.copy()
+    s = 1.0
+    for _ in range(inner):
+        w = r + tv_grad(z - lam * tv_grad_adj(r)) / (8.0 * lam)
+        pn = ball_proj(w)
+        sn = (1.0 + np.sqrt(1.0 + 4.0 * s * s)) / 2.0
+        r = pn + ((s - 1.0) / sn) * (pn - p)
+        p, s = pn, sn
+    return z - lam * tv_grad_adj(p)
+
+
+def tv_dprox(z, dz, lam, inner):
+    """Forward-mode derivative of tv_prox at z applied to dz (same iterations)."""
+    if lam == 0.0:
+        return np.array(dz, copy=True)
+    p = np.zeros((2,) + z.shape, np.complex128)
+    r, dp, dr = p.copy(), p.copy(), p.copy()
+    s = 1.0
+    for _ in range(inner):
+        w = r + tv_grad(z - lam * tv_grad_adj(r)) / (8.0 * lam)
+        dw = dr + tv_grad(dz - lam * tv_grad_adj(dr)) / (8.0 * lam)
+        pn, dpn = ball_proj(w), ball_dproj(w, dw)
+        sn = (1.0 + np.sqrt(1.0 + 4.0 * s * s)) / 2.0
+        th = (s - 1.0) / sn
+        r, dr = pn + th * (pn - p), dpn + th * (dpn - dp)
+        p, dp, s = pn, dpn, sn
+    return dz - lam * tv_grad_adj(dp)
+
+
+class FistaTV:
+    """T-iteration FISTA with the TV proximal step and its forward-mode Jacobian.
+
+    Same outer iteration, step and normalisation as FistaL1Wavelet; the
+    proximal step is tv_prox(z_k, lam, inner).  ``recon(store=True)`` keeps
+    z_k, from which ``jvp`` recomputes each inner trajectory.
+    """
+
+    def __init__(self, op, lam: float, iters: int = 100, inner: int = 10, power_iters: int = 15,
+                 margin: float = 1.01):
+        self.op = op
+        self.lam = lam
+        self.T = iters
+        self.inner = inner
+        self.shape = (op.ny, op.nx)
+        self.s2 = power_method(op.normal, self.shape, power_iters, margin)
+        t = [1.0]
+        for _ in range(iters):
+            t.append((1.0 + np.sqrt(1.0 + 4.0 * t[-1] ** 2)) / 2.0)
+        self.t = t
+
+    def theta(self, k):
+        return (self.t[k - 1] - 1.0) / self.t[k]
+
+    def recon(self, b, store=False):
+        atb = self.op.adjoint(b)
+        x_prev = np.zeros(self.shape, np.complex128)
+        y = x_prev.copy()
+        zs = []
+        for k in range(1, self.T + 1):
+            z = y - (self.op.normal(y) - atb) / self.s2
+            if store:
+                zs.append(z)
+            x = tv_prox(z, self.lam, self.inner)
+            y = x + self.theta(k) * (x - x_prev)
+            x_prev = x
+        return (x_prev, zs) if store else x_prev
+
+    def jvp(self, w, zs):
+        g = self.op.adjoint(w)
+        x_prev = np.zeros(self.shape, np.complex128)
+        y = x_prev.copy()
+        for k in range(1, self.T + 1):
+            dz = y - (self.op.normal(y) - g) / self.s2
+            x = tv_dprox(zs[k - 1], dz, self.lam, self.inner)
+            y = x + self.theta(k) * (x - x_prev)
+            x_prev = x
+        return x_prev
+
+
 def pmr_cs(fista: FistaL1Wavelet, bw, seed: int, first: int, nrep: int, sigma: float, x0=None,
            acc=None):
     """Pseudo multiple replica for the nonlinear reconstruction (Sec. 1, App. C;
@@ -149,7 +276,7 @@ def kspace_probe(op, seed: int, i: int, dist: str = "phase"):
     return op.P[None] * w
 
 
-def noise_map_jvp(fista: FistaL1Wavelet, cs, seed: int, first: int, nprobes: int,
+def noise_map_jvp(fista, cs, seed: int, first: int, nprobes: int,
                   dist: str = "phase", acc=None):
     """Accumulate |J w|^2 (sum) and Re/Im of J w over probes."""
     shape = fista.shape

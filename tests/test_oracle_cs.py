@@ -115,3 +115,80 @@ def test_pmr_cs_replicas_are_difference_quotients():
         jn = f.jvp(pico.pmr_noise(op, 9, r), coeffs)
         assert np.linalg.norm(a["sum"] + 1j * a["sum_im"] - jn) < 1e-5 * np.linalg.norm(jn)
         assert np.allclose(a["sumsq"], np.abs(jn) ** 2, rtol=1e-4, atol=1e-8 * np.abs(jn).max() ** 2)
+
+
+# ---------------------------------------------------------------- TV model
+def _chambolle_prox(z, lam, iters=4000, tau=0.125):
+    """Chambolle's projection algorithm (J. Math. Imaging Vis. 2004), written
+    independently of the oracle: p <- (p + tau g) / (1 + tau |g|) with
+    g = grad(div p - z / lam), div p = -(D^H p); prox = z - lam div p."""
+    def grad(x):
+        return np.stack([np.roll(x, -1, axis=0) - x, np.roll(x, -1, axis=1) - x])
+
+    def div(p):
+        return (p[0] - np.roll(p[0], 1, axis=0)) + (p[1] - np.roll(p[1], 1, axis=1))
+
+    p = np.zeros((2,) + z.shape, np.complex128)
+    for _ in range(iters):
+        g = grad(div(p) - z / lam)
+        n = np.sqrt(np.abs(g[0]) ** 2 + np.abs(g[1]) ** 2)
+        p = (p + tau * g) / (1.0 + tau * n)
+    return z - lam * div(p)
+
+
+def test_tv_operators_and_prox():
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((12, 10)) + 1j * rng.standard_normal((12, 10))
+    q = rng.standard_normal((2, 12, 10)) + 1j * rng.standard_normal((2, 12, 10))
+    assert abs(np.vdot(q, cs.tv_grad(x)) - np.vdot(cs.tv_grad_adj(q), x)) < 1e-12 * np.abs(np.vdot(q, cs.tv_grad(x)))
+    v = x.copy()
+    for _ in range(300):          # ||D||^2 <= 8 makes 1 / (8 lam) a valid dual step
+        v = cs.tv_grad_adj(cs.tv_grad(v))
+        lam_max = np.linalg.norm(v)
+        v /= lam_max
+    assert lam_max <= 8.0 + 1e-9
+    # the dual fast gradient projection converges to the prox an independent
+    # algorithm finds, and the prox minimises 1/2 |x - z|^2 + lam TV(x)
+    z = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    lam = 0.3
+    a = cs.tv_prox(z, lam, 3000)
+    b = _chambolle_prox(z, lam)
+    assert np.linalg.norm(a - b) < 1e-4 * np.linalg.norm(a)
+
+    def obj(u):
+        g = cs.tv_grad(u)
+        return 0.5 * np.linalg.norm(u - z) ** 2 + lam * np.sum(np.sqrt(np.abs(g[0]) ** 2 + np.abs(g[1]) ** 2))
+
+    f0 = obj(a)
+    for _ in range(20):
+        e = rng.standard_normal(z.shape) + 1j * rng.standard_normal(z.shape)
+        assert obj(a + 1e-3 * e) >= f0 - 1e-9
+    assert np.allclose(cs.tv_prox(np.full((8, 8), 2.0 + 1j), lam, 50), 2.0 + 1j)
+
+
+def test_tv_prox_derivative_matches_differences():
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal((2, 6, 6)) + 1j * rng.standard_normal((2, 6, 6))
+    dw = rng.standard_normal((2, 6, 6)) + 1j * rng.standard_normal((2, 6, 6))
+    num = (cs.ball_proj(w + 1e-7 * dw) - cs.ball_proj(w - 1e-7 * dw)) / 2e-7
+    assert np.abs(cs.ball_dproj(w, dw) - num).max() < 1e-6
+    z = rng.standard_normal((10, 12)) + 1j * rng.standard_normal((10, 12))
+    dz = rng.standard_normal((10, 12)) + 1j * rng.standard_normal((10, 12))
+    eps = 1e-8
+    num = (cs.tv_prox(z + eps * dz, 0.4, 15) - cs.tv_prox(z - eps * dz, 0.4, 15)) / (2 * eps)
+    d = cs.tv_dprox(z, dz, 0.4, 15)
+    assert np.linalg.norm(d - num) < 1e-5 * np.linalg.norm(num)
+
+
+def test_tv_fista_jvp_matches_central_differences_and_lambda_zero():
+    op, b, _ = _cs_problem()
+    f = cs.FistaTV(op, 2e-3, 12, inner=8)
+    _, zs = f.recon(b, store=True)
+    w = cs.kspace_probe(op, 4, 0)
+    jw = f.jvp(w, zs)
+    eps = 1e-9
+    fd = (f.recon(b + eps * w) - f.recon(b - eps * w)) / (2 * eps)
+    assert np.linalg.norm(jw - fd) < 1e-5 * np.linalg.norm(fd)
+    f0 = cs.FistaTV(op, 0.0, 12, inner=8)
+    _, zs0 = f0.recon(b, store=True)
+    assert np.linalg.norm(f0.jvp(w, zs0) - f0.recon(w)) < 1e-12 * np.linalg.norm(f0.recon(w))
