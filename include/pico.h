@@ -63,7 +63,10 @@ typedef enum {
 
 typedef enum {
   PICO_CGSENSE = 0,        /* linear Tikhonov / least-squares CG-SENSE          */
-  PICO_CS_FISTA_L1WAV = 1  /* nonlinear compressed sensing (Jacobian probing)   */
+  PICO_CS_FISTA_L1WAV = 1, /* nonlinear compressed sensing, L1 on db4 wavelet
+                              details (Jacobian probing)                        */
+  PICO_CS_FISTA_TV = 2     /* nonlinear compressed sensing, isotropic total
+                              variation (Sec. 3.2.3 model; Jacobian probing)    */
 } pico_recon_t;
 
 typedef enum {
@@ -95,12 +98,14 @@ typedef struct {
   double power_margin;          /* safety factor on lambda_max (paper: 1.01)       */
   int32_t probe_tile;           /* probes solved together (K); sizes the workspace */
   int32_t recon;                /* pico_recon_t                                    */
-  /* PICO_CS_FISTA_L1WAV only (Sec. 2.2 CS extension, Sec. 3.2.3): */
+  /* PICO_CS_FISTA_L1WAV and PICO_CS_FISTA_TV (Sec. 2.2 CS extension,
+   * Sec. 3.2.3): */
   const void* kdata;            /* device complex64 [ncoils][ny][nx] measured
                                    k-space (un-whitened, centred order)            */
   int32_t fista_iters;          /* FISTA iterations T (paper: 100)                 */
-  double cs_lambda;             /* L1 weight of the normalised problem            */
-  int32_t wavelet_levels;       /* db4 levels; ny, nx divisible by 2^levels       */
+  double cs_lambda;             /* L1 / TV weight of the normalised problem
+                                   (paper's TV weight: 1e-2)                        */
+  int32_t wavelet_levels;       /* L1WAV: db4 levels; ny, nx divisible by 2^levels */
   /* PICO_NONCART data path (A, A^H of sample arrays; PMR replicas) by a
    * Kaiser-Bessel gridding NUFFT (Sec. 3.2.2, 3.3); kb_width = 0 builds none.
    * Grid oversamp * n per axis (an integer with a built FFT length), kernel
@@ -116,6 +121,12 @@ typedef struct {
    * of 32, <= 512); 0 = the default (column FFTs).
    * Both give M to FP32 rounding; the PMR right-hand side always uses FFTs. */
   int32_t normal_form;
+  /* PICO_CS_FISTA_TV: dual fast-gradient-projection steps per proximal step
+   * (Beck and Teboulle 2009), from a zero dual start each FISTA iteration,
+   * 1..1000.  The tangents keep the projection data of every step of the
+   * primal: fista_iters * tv_inner_iters * ny * nx * 20 bytes of device
+   * memory. */
+  int32_t tv_inner_iters;
 } pico_op_desc_t;
 
 /* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a

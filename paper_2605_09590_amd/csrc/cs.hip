@@ -549,11 +549,12 @@ hipError_t cs64_power(const Cs64& o, int iters, double2* v, double2* w, double* 
   return hipGetLastError();
 }
 
-// T FISTA iterations on B images from x_0 = y_1 = 0 (atb [B][n]); stores
-// c_k = Psi z_k ([T][ny][nx], B = 1 only) when ctraj is given and leaves x_T in
-// x.  Buffers y, x, z, tmp, q hold B images each.
+// T FISTA iterations on B images from x_0 = y_1 = 0 (atb [B][n]), leaving x_T
+// in x.  With store (B = 1 only) the trajectory the tangents need is kept:
+// c_k = Psi z_k in o.ctraj (wavelet prox) or the TV projection data in
+// o.tv_what / o.tv_invn.  Buffers y, x, z, tmp, q hold B images each.
 hipError_t cs64_fista(const Cs64& o, int B, const double2* atb, double s2, double lam, int T,
-                      const double* theta, double2* ctraj, double2* y, double2* x, double2* z,
+                      const double* theta, bool store, double2* y, double2* x, double2* z,
                       double2* tmp, double2* q, hipStream_t s) {
   const long n = (long)o.ny * o.nx, tot = n * B;
   const int ly = o.ny >> o.levels, lx = o.nx >> o.levels;
@@ -562,10 +563,15 @@ hipError_t cs64_fista(const Cs64& o, int B, const double2* atb, double s2, doubl
   for (int k = 1; k <= T; ++k) {
     CS_CHECK(cs64_normal(o, B, y, q, s));
     hipLaunchKernelGGL(k_grad64, grid1(tot), dim3(256), 0, s, y, q, atb, z, tot, 1.0 / s2);
-    CS_CHECK(wavelet(z, tmp, B, o.ny, o.nx, o.levels, false, s));
-    hipLaunchKernelGGL(k_soft_store64, grid1(tot), dim3(256), 0, s, z,
-                       ctraj ? ctraj + (size_t)(k - 1) * n : nullptr, tot, n, o.nx, ly, lx, lam);
-    CS_CHECK(wavelet(z, tmp, B, o.ny, o.nx, o.levels, true, s));
+    if (o.tv_inner > 0) {
+      const size_t off = (size_t)(k - 1) * o.tv_inner * n;
+      CS_CHECK(tv64_prox(o, B, z, lam, store ? o.tv_what + off : nullptr, store ? o.tv_invn + off : nullptr, s));
+    } else {
+      CS_CHECK(wavelet(z, tmp, B, o.ny, o.nx, o.levels, false, s));
+      hipLaunchKernelGGL(k_soft_store64, grid1(tot), dim3(256), 0, s, z,
+                         store ? o.ctraj + (size_t)(k - 1) * n : nullptr, tot, n, o.nx, ly, lx, lam);
+      CS_CHECK(wavelet(z, tmp, B, o.ny, o.nx, o.levels, true, s));
+    }
     hipLaunchKernelGGL(k_momentum64, grid1(tot), dim3(256), 0, s, z, x, y, tot, theta[k - 1]);
   }
   return hipGetLastError();
@@ -581,7 +587,7 @@ hipError_t cs64_pmr(const Cs64& o, int B, const double2* atb0, const double2* x0
   hipLaunchKernelGGL(k_noise64, grid1(n, B), dim3(256), 0, s, o.U, o.mask, o.nc, n, seed, first, sigma);
   CS_CHECK(cs64_adjoint_u(o, B, atb, s));                                        // A^H (sigma n_b)
   hipLaunchKernelGGL(k_add_bcast64, grid1(n, B), dim3(256), 0, s, atb, atb0, n);   // + A^H b_w
-  CS_CHECK(cs64_fista(o, B, atb, s2, lam, T, theta, nullptr, y, x, z, tmp, q, s));
+  CS_CHECK(cs64_fista(o, B, atb, s2, lam, T, theta, false, y, x, z, tmp, q, s));
   hipLaunchKernelGGL(k_accum_pmr64, grid1(n), dim3(256), 0, s, x, x0, 1.0 / sigma, sum, sum_im, sumsq, B, n);
   return hipGetLastError();
 }

@@ -68,9 +68,15 @@ struct pico_op_s {
   double* mon = nullptr;      // [512] convergence-monitor partials
   double *alpha = nullptr, *beta = nullptr, *rr = nullptr, *rr0 = nullptr;
   int* state = nullptr;
-  // compressed sensing (FISTA + L1 wavelet)
+  // compressed sensing (FISTA + L1 wavelet or TV)
   bool cs = false;
   int fista_T = 0, levels = 0;
+  int tv_inner = 0;                 // TV prox steps (0: wavelet prox)
+  std::vector<double> tv_th64;      // dual momentum weights of the TV prox
+  std::vector<float> tv_th;
+  float4* tv_what = nullptr;        // [T][inner][ny][nx] projection data of the primal
+  float* tv_invn = nullptr;         // [T][inner][ny][nx]
+  float2 *tv_dp = nullptr, *tv_drA = nullptr, *tv_drB = nullptr;  // [K][2][ny][nx] dual tangents
   double cs_lam = 0.0;
   double s2 = 0.0;              // 1.01 lambda_max(M)
   std::vector<float> theta;     // FISTA momentum weights (tangents)
@@ -83,7 +89,7 @@ struct pico_op_s {
   // replica workspace of pico_pmr_cs, allocated on its first call
   int pmr_B = 0;
   double2 *pmr_atb = nullptr, *pmr_y = nullptr, *pmr_x = nullptr, *pmr_z = nullptr, *pmr_tmp = nullptr,
-          *pmr_q = nullptr;
+          *pmr_q = nullptr, *pmr_tv_r = nullptr, *pmr_tv_p = nullptr, *pmr_tv_u = nullptr;
   uint8_t* mask_d = nullptr;    // [ny][nx] (Cartesian 2-D)
   // Kaiser-Bessel gridding data path (non-Cartesian, kb_width > 0)
   bool has_kb = false;
@@ -444,8 +450,9 @@ hipError_t adjoint_kspace(pico_op_t op, int K, const float2* src, const double* 
 }
 
 // Tangents of the T FISTA iterations for K probes at once: the gradient offset
-// is A^H w (in op->r, per probe), the soft-threshold derivative is taken at
-// the stored FP64 c_k.  The tangent of x_T ends in op->x.
+// is A^H w (in op->r, per probe); the prox derivative is the soft threshold's
+// at the stored FP64 c_k, or the TV prox's through its inner steps at the
+// stored projection data.  The tangent of x_T ends in op->x.
 hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
   const long n = (long)op->image();
   const int ly = op->ny >> op->levels, lx = op->nx >> op->levels;
@@ -462,6 +469,17 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
     e = timed(op, PICO_PROF_OTHER, s, [&] {
       hipError_t e2;
       if ((e2 = pico::launch_fista_grad(op->p, op->q, op->r, op->wA, n, K, 1, inv_s2, s)) != hipSuccess) return e2;
+      if (op->tv_inner > 0) {
+        // TV prox tangent at the stored projection data of iteration k
+        if (op->cs_lam == 0.0) return pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s);
+        const size_t off = (size_t)(k - 1) * op->tv_inner * n;
+        if ((e2 = pico::tv_tangent_prox(op->wA, op->tv_drA, op->tv_drB, op->tv_dp, op->tv_what + off,
+                                        op->tv_invn + off, op->ny, op->nx, K, op->tv_inner, op->tv_th.data(),
+                                        (float)op->cs_lam, s)) != hipSuccess)
+          return e2;
+        return pico::tv_tangent_final(op->wA, op->tv_dp, op->x, op->p, op->ny, op->nx, K, (float)op->cs_lam,
+                                      op->theta[k - 1], s);
+      }
       if ((e2 = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, false, s)) != hipSuccess) return e2;
       const double2* ck = op->ctraj + (size_t)(k - 1) * n;
       if ((e2 = pico::launch_dsoft(op->wA, ck, n, K, op->nx, ly, lx, op->cs_lam, s)) != hipSuccess) return e2;
@@ -558,17 +576,21 @@ bool kb_grid_dims(const pico_op_desc_t* d, int G[2]) {
 }
 
 pico_status_t validate(const pico_op_desc_t* d) {
-  if (d->recon != PICO_CGSENSE && d->recon != PICO_CS_FISTA_L1WAV)
+  if (d->recon != PICO_CGSENSE && d->recon != PICO_CS_FISTA_L1WAV && d->recon != PICO_CS_FISTA_TV)
     return fail(PICO_EUNSUPPORTED, "unknown reconstruction kind");
-  if (d->recon == PICO_CS_FISTA_L1WAV) {
+  if (d->recon == PICO_CS_FISTA_L1WAV || d->recon == PICO_CS_FISTA_TV) {
     if (d->sampling != PICO_CART_2D)
       return fail(PICO_EUNSUPPORTED, "compressed sensing is built for 2-D Cartesian masks");
     if (!d->kdata) return fail(PICO_EINVAL, "compressed sensing needs kdata");
     if (d->fista_iters < 1 || d->fista_iters > 100000) return fail(PICO_EINVAL, "fista_iters must be in 1..100000");
     if (!(d->cs_lambda >= 0.0) || !std::isfinite(d->cs_lambda)) return fail(PICO_EINVAL, "cs_lambda must be finite and >= 0");
-    if (d->wavelet_levels < 1 || d->wavelet_levels > 8) return fail(PICO_EINVAL, "wavelet_levels must be in 1..8");
-    const int m = 1 << d->wavelet_levels;
-    if (d->ny % m || d->nx % m) return fail(PICO_EINVAL, "ny and nx must be divisible by 2^wavelet_levels");
+    if (d->recon == PICO_CS_FISTA_L1WAV) {
+      if (d->wavelet_levels < 1 || d->wavelet_levels > 8) return fail(PICO_EINVAL, "wavelet_levels must be in 1..8");
+      const int m = 1 << d->wavelet_levels;
+      if (d->ny % m || d->nx % m) return fail(PICO_EINVAL, "ny and nx must be divisible by 2^wavelet_levels");
+    } else if (d->tv_inner_iters < 1 || d->tv_inner_iters > 1000) {
+      return fail(PICO_EINVAL, "tv_inner_iters must be in 1..1000");
+    }
     if (d->power_iters < 1 || !(d->power_margin > 0.0)) return fail(PICO_EINVAL, "compressed sensing needs power_iters >= 1 and power_margin > 0");
   }
   if (d->sampling != PICO_CART_1D && d->sampling != PICO_CART_2D && d->sampling != PICO_NONCART)
@@ -680,19 +702,27 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
     }
   }
   if (d->sampling == PICO_CART_2D) add(n);
-  if (d->recon == PICO_CS_FISTA_L1WAV) {
+  if (d->recon == PICO_CS_FISTA_L1WAV || d->recon == PICO_CS_FISTA_TV) {
+    const bool tv = d->recon == PICO_CS_FISTA_TV;
     add(n * K * 8);
-    add(n * K * 8);
-    add(n * (size_t)d->fista_iters * 16);
+    if (tv) {
+      for (int i = 0; i < 3; ++i) add(2 * n * K * 8);
+      add(n * (size_t)d->fista_iters * d->tv_inner_iters * 16);
+      add(n * (size_t)d->fista_iters * d->tv_inner_iters * 4);
+    } else {
+      add(n * K * 8);
+      add(n * (size_t)d->fista_iters * 16);
+    }
     add(n * 8);
     add(nc * n * 16);   // FP64 maps, DFT matrices, A^H b, x_T (resident)
     add(ny * ny * 16);
     add(nx * nx * 16);
     add(n * 16);
     add(n * 16);
-    const size_t tmp[] = {nc * n * 16, nc * n * 16, n * 16, n * 16, n * 16, n * 16, 2 * CS64_DOT_BLOCKS * 8};
-    for (size_t b : tmp) add(b);
-    for (size_t b : tmp) sub(b);
+    const size_t tmp[] = {nc * n * 16, nc * n * 16, n * 16, n * 16, n * 16, n * 16, 2 * CS64_DOT_BLOCKS * 8,
+                          tv ? 2 * n * 16 : 0, tv ? 2 * n * 16 : 0, tv ? n * 16 : 0};
+    for (size_t b : tmp) if (b) add(b);
+    for (size_t b : tmp) if (b) sub(b);
   }
   sub(linv);
   if (resident) *resident = cur;
@@ -845,23 +875,39 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if ((e = op->alloc(&op->mask_d, n)) != hipSuccess) return bad(e, "mask");
     if ((e = hipMemcpyAsync(op->mask_d, d->mask, n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return bad(e, "mask copy");
   }
-  if (d->recon == PICO_CS_FISTA_L1WAV) {
-    // FISTA primal at the measured data in FP64, storing c_k = Psi z_k
-    // (Sec. 2.2 CS extension, Sec. 3.2.3, 3.3)
+  if (d->recon == PICO_CS_FISTA_L1WAV || d->recon == PICO_CS_FISTA_TV) {
+    // FISTA primal at the measured data in FP64, storing the trajectory the
+    // tangents need: c_k = Psi z_k, or the TV projection data of every inner
+    // step (Sec. 2.2 CS extension, Sec. 3.2.3, 3.3)
+    const bool tv = d->recon == PICO_CS_FISTA_TV;
     op->cs = true;
     op->fista_T = d->fista_iters;
-    op->levels = d->wavelet_levels;
+    op->levels = tv ? 0 : d->wavelet_levels;
+    op->tv_inner = tv ? d->tv_inner_iters : 0;
     op->cs_lam = d->cs_lambda;
-    double t = 1.0;
-    for (int k = 0; k < op->fista_T; ++k) {
-      const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-      op->theta64.push_back((t - 1.0) / tn);
-      op->theta.push_back((float)op->theta64.back());
-      t = tn;
+    auto momentum = [](int count, std::vector<double>& w64, std::vector<float>& w32) {
+      double t = 1.0;
+      for (int k = 0; k < count; ++k) {
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        w64.push_back((t - 1.0) / tn);
+        w32.push_back((float)w64.back());
+        t = tn;
+      }
+    };
+    momentum(op->fista_T, op->theta64, op->theta);
+    momentum(op->tv_inner, op->tv_th64, op->tv_th);
+    if ((e = op->alloc(&op->wA, n * K)) != hipSuccess) return bad(e, "tangent buffer");
+    if (tv) {
+      const size_t steps = (size_t)op->fista_T * op->tv_inner;
+      if ((e = op->alloc(&op->tv_dp, 2 * n * K)) != hipSuccess || (e = op->alloc(&op->tv_drA, 2 * n * K)) != hipSuccess ||
+          (e = op->alloc(&op->tv_drB, 2 * n * K)) != hipSuccess)
+        return bad(e, "TV dual tangents");
+      if ((e = op->alloc(&op->tv_what, n * steps)) != hipSuccess || (e = op->alloc(&op->tv_invn, n * steps)) != hipSuccess)
+        return bad(e, "TV projection data");
+    } else {
+      if ((e = op->alloc(&op->wB, n * K)) != hipSuccess) return bad(e, "wavelet buffer");
+      if ((e = op->alloc(&op->ctraj, n * (size_t)op->fista_T)) != hipSuccess) return bad(e, "FISTA trajectory");
     }
-    if ((e = op->alloc(&op->wA, n * K)) != hipSuccess) return bad(e, "wavelet buffer");
-    if ((e = op->alloc(&op->wB, n * K)) != hipSuccess) return bad(e, "wavelet buffer");
-    if ((e = op->alloc(&op->ctraj, n * (size_t)op->fista_T)) != hipSuccess) return bad(e, "FISTA trajectory");
     if ((e = op->alloc(&op->xrec, n)) != hipSuccess) return bad(e, "reconstruction");
     // resident FP64 operator (whitened maps, centred DFT matrices), A^H b and
     // x_T: the linearisation point, kept for the replicas of pico_pmr_cs
@@ -871,6 +917,11 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     o.nc = nc;
     o.levels = op->levels;
     o.mask = op->mask_d;
+    o.ctraj = op->ctraj;
+    o.tv_inner = op->tv_inner;
+    o.tv_th = op->tv_th64.data();
+    o.tv_what = op->tv_what;
+    o.tv_invn = op->tv_invn;
     if ((e = op->alloc(&o.S, (size_t)nc * n)) != hipSuccess || (e = op->alloc(&o.Fy, (size_t)ny * ny)) != hipSuccess ||
         (e = op->alloc(&o.Fx, (size_t)nx * nx)) != hipSuccess || (e = op->alloc(&op->atb64, n)) != hipSuccess ||
         (e = op->alloc(&op->x64, n)) != hipSuccess)
@@ -882,18 +933,24 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
         (e = op->alloc(&tmp, n)) != hipSuccess || (e = op->alloc(&q, n)) != hipSuccess ||
         (e = op->alloc(&part, 2 * pico::CS64_DOT_BLOCKS)) != hipSuccess)
       return bad(e, "FP64 primal workspace");
+    if (tv && ((e = op->alloc(&o.tv_r, 2 * n)) != hipSuccess || (e = op->alloc(&o.tv_p, 2 * n)) != hipSuccess ||
+               (e = op->alloc(&o.tv_u, n)) != hipSuccess))
+      return bad(e, "FP64 TV workspace");
     if ((e = pico::cs64_setup(o, (const float2*)d->maps, linv_d, s)) != hipSuccess) return bad(e, "FP64 primal");
     double lam_hat = 0.0;
     if ((e = pico::cs64_power(o, d->power_iters, y, z, part, &lam_hat, s)) != hipSuccess) return bad(e, "power");
     op->s2 = d->power_margin * lam_hat;
     if ((e = pico::cs64_adjoint_kdata(o, (const float2*)d->kdata, linv_d, op->atb64, s)) != hipSuccess) return bad(e, "A^H b");
-    if ((e = pico::cs64_fista(o, 1, op->atb64, op->s2, op->cs_lam, op->fista_T, op->theta64.data(), op->ctraj, y,
+    if ((e = pico::cs64_fista(o, 1, op->atb64, op->s2, op->cs_lam, op->fista_T, op->theta64.data(), true, y,
                               op->x64, z, tmp, q, s)) != hipSuccess)
       return bad(e, "FISTA");
     if ((e = pico::launch_to_f32(op->x64, op->xrec, (long)n, s)) != hipSuccess) return bad(e, "reconstruction");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "FISTA");
-    for (void* ptr : {(void*)o.U, (void*)o.V, (void*)y, (void*)z, (void*)tmp, (void*)q, (void*)part}) op->release(ptr);
+    for (void* ptr : {(void*)o.U, (void*)o.V, (void*)y, (void*)z, (void*)tmp, (void*)q, (void*)part, (void*)o.tv_r,
+                      (void*)o.tv_p, (void*)o.tv_u})
+      if (ptr) op->release(ptr);
     o.U = o.V = nullptr;
+    o.tv_r = o.tv_p = o.tv_u = nullptr;
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "init");
   op->release(linv_d);
@@ -1063,17 +1120,26 @@ pico_status_t pico_pmr_cs(pico_op_t op, uint64_t seed, int64_t first, int64_t nr
   if (op->pmr_B == 0) {
     const int B = std::min(op->K, 16);
     hipError_t e;
+    const bool tv = op->tv_inner > 0;
     if ((e = op->alloc(&o.U, (size_t)B * op->nc * n)) != hipSuccess || (e = op->alloc(&o.V, (size_t)B * op->nc * n)) != hipSuccess ||
         (e = op->alloc(&op->pmr_atb, B * n)) != hipSuccess || (e = op->alloc(&op->pmr_y, B * n)) != hipSuccess ||
         (e = op->alloc(&op->pmr_x, B * n)) != hipSuccess || (e = op->alloc(&op->pmr_z, B * n)) != hipSuccess ||
-        (e = op->alloc(&op->pmr_tmp, B * n)) != hipSuccess || (e = op->alloc(&op->pmr_q, B * n)) != hipSuccess) {
+        (e = op->alloc(&op->pmr_tmp, B * n)) != hipSuccess || (e = op->alloc(&op->pmr_q, B * n)) != hipSuccess ||
+        (tv && ((e = op->alloc(&op->pmr_tv_r, 2 * B * n)) != hipSuccess ||
+                (e = op->alloc(&op->pmr_tv_p, 2 * B * n)) != hipSuccess ||
+                (e = op->alloc(&op->pmr_tv_u, B * n)) != hipSuccess))) {
       for (void* p : {(void*)o.U, (void*)o.V, (void*)op->pmr_atb, (void*)op->pmr_y, (void*)op->pmr_x,
-                      (void*)op->pmr_z, (void*)op->pmr_tmp, (void*)op->pmr_q})
+                      (void*)op->pmr_z, (void*)op->pmr_tmp, (void*)op->pmr_q, (void*)op->pmr_tv_r,
+                      (void*)op->pmr_tv_p, (void*)op->pmr_tv_u})
         if (p) op->release(p);
       o.U = o.V = nullptr;
       op->pmr_atb = op->pmr_y = op->pmr_x = op->pmr_z = op->pmr_tmp = op->pmr_q = nullptr;
+      op->pmr_tv_r = op->pmr_tv_p = op->pmr_tv_u = nullptr;
       return fail(e == hipErrorOutOfMemory ? PICO_ENOMEM : PICO_EDEVICE, "PMR workspace");
     }
+    o.tv_r = op->pmr_tv_r;
+    o.tv_p = op->pmr_tv_p;
+    o.tv_u = op->pmr_tv_u;
     op->pmr_B = B;
   }
   for (int64_t done = 0; done < nrep;) {

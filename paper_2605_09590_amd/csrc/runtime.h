@@ -144,6 +144,18 @@ struct Cs64 {
   const uint8_t* mask = nullptr;  // [ny][nx]
   double2* U = nullptr;         // [B][nc][ny][nx] workspace (B images per call)
   double2* V = nullptr;         // [B][nc][ny][nx] workspace
+  // proximal step: the L1 wavelet threshold (tv_inner = 0) or TV by tv_inner
+  // dual fast-gradient-projection steps with momentum weights tv_th (host)
+  int tv_inner = 0;
+  const double* tv_th = nullptr;
+  double2* tv_r = nullptr;      // [B][2][ny][nx] dual workspace
+  double2* tv_p = nullptr;      // [B][2][ny][nx]
+  double2* tv_u = nullptr;      // [B][ny][nx]
+  // primal trajectory stored for the tangents (B = 1 with store): wavelet
+  // c_k = Psi z_k [T][ny][nx], or the TV projection data [T][tv_inner][ny][nx]
+  double2* ctraj = nullptr;
+  float4* tv_what = nullptr;
+  float* tv_invn = nullptr;
 };
 hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream_t s);
 hipError_t cs64_normal(const Cs64& o, int B, const double2* y, double2* q, hipStream_t s);
@@ -152,13 +164,24 @@ hipError_t cs64_adjoint_kdata(const Cs64& o, const float2* kdata, const double* 
 hipError_t cs64_power(const Cs64& o, int iters, double2* v, double2* w, double* part_d, double* out,
                       hipStream_t s);
 hipError_t cs64_fista(const Cs64& o, int B, const double2* atb, double s2, double lam, int T,
-                      const double* theta, double2* ctraj, double2* y, double2* x, double2* z,
+                      const double* theta, bool store, double2* y, double2* x, double2* z,
                       double2* tmp, double2* q, hipStream_t s);
 hipError_t cs64_pmr(const Cs64& o, int B, const double2* atb0, const double2* x0, double s2, double lam,
                     int T, const double* theta, uint64_t seed, uint64_t first, double sigma, double2* atb,
                     double2* y, double2* x, double2* z, double2* tmp, double2* q, double* sum,
                     double* sum_im, double* sumsq, hipStream_t s);
 hipError_t launch_to_f32(const double2* a, float2* b, long n, hipStream_t s);
+// TV prox of B FP64 images in place (o.tv_* workspace); what / invn: the
+// projection data of its o.tv_inner steps ([tv_inner][ny][nx]) or NULL
+hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what, float* invn, hipStream_t s);
+// tangent of the TV prox for K FP32 images: inner fused steps on dz (kept),
+// dual tangents dp [K][2][n] (result) and the ping-pong pair drA / drB
+hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dp, const float4* what,
+                           const float* invn, int ny, int nx, int K, int inner, const float* th, float lam,
+                           hipStream_t s);
+// dx = dz - lam D^H dp, then the FISTA momentum: yo = dx + theta (dx - xo), xo = dx
+hipError_t tv_tangent_final(const float2* dz, const float2* dp, float2* xo, float2* yo, int ny, int nx, int K,
+                            float lam, float theta, hipStream_t s);
 
 // Kaiser-Bessel gridding NUFFT (non-Cartesian data path)
 struct KbLayout {

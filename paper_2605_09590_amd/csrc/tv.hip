@@ -1,0 +1,238 @@
+// Total-variation proximal step of the compressed-sensing reconstruction
+// (FISTA with lam_TV ||grad x||_1, Sec. 3.2.3 of the paper's CS experiment)
+// and its forward-mode derivative for the Jacobian probes.
+//
+// TV(x) = sum_pixels sqrt(|(D_y x)|^2 + |(D_x x)|^2), D = periodic forward
+// differences; D^H p = p_y[y-1] - p_y[y] + p_x[x-1] - p_x[x].  The prox
+// prox_{lam TV}(z) = z - lam D^H p* solves the dual over pointwise unit balls
+// by Beck and Teboulle's fast gradient projection (IEEE TIP 2009), a fixed
+// number of inner steps from p = r = 0, step 1/(8 lam) since ||D||^2 <= 8:
+//   u = z - lam D^H r,   w = r + D u / (8 lam),   p' = P(w),
+//   r = p' + th_i (p' - p),   p = p',   th_i = (s_i - 1) / s_{i+1}.
+// P(w) = w / max(1, |w|) per pixel, |w| = sqrt(|w_y|^2 + |w_x|^2).
+//
+// Primal (FP64, once per operator): every inner step stores the projection's
+// derivative data, w^ = w/|w| and 1/|w| where |w| > 1, else w^ = 0 and 1, so
+// the tangent map is dP(w) dw = (dw - w^ Re(w^H dw)) / |w| for all pixels,
+// with the inside / outside decision taken in FP64.  Tangent (FP32, K probes
+// at once): the same steps on (dz, dr, dp) with that stored dP, one fused
+// kernel per inner step (u and w of a tile from LDS, halo recomputed).
+//
+// Dual fields are [image][2][ny][nx] (y component, then x component).
+#include "device_common.h"
+#include "runtime.h"
+
+#include <algorithm>
+
+namespace pico {
+
+namespace {
+
+__device__ __forceinline__ int wrap(int v, int n) { return (v % n + n) % n; }
+
+__device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// out = z - lam D^H r over B images (blockIdx.y); out may alias z
+__global__ void k_tv_u64(const double2* z, const double2* __restrict__ r, double2* out, int ny, int nx,
+                         double lam) {
+  const long n = (long)ny * nx;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = blockIdx.y;
+  const int y = (int)(i / nx), x = (int)(i - (long)y * nx);
+  const int ym = y ? y - 1 : ny - 1, xm = x ? x - 1 : nx - 1;
+  const double2* ry = r + (size_t)b * 2 * n;
+  const double2* rx = ry + n;
+  const double2 a = ry[(long)ym * nx + x], c = ry[i], d = rx[(long)y * nx + xm], e = rx[i];
+  const double hx = a.x - c.x + d.x - e.x, hy = a.y - c.y + d.y - e.y;
+  const double2 zv = z[(size_t)b * n + i];
+  out[(size_t)b * n + i] = make_double2(fma(-lam, hx, zv.x), fma(-lam, hy, zv.y));
+}
+
+// w = r + c8 D u, p' = P(w), r = p' + th (p' - p), p = p'; stores dP data
+// (what, invn: [ny*nx], image 0 only) when what is given
+__global__ void k_tv_w64(const double2* __restrict__ u, double2* __restrict__ r, double2* __restrict__ p,
+                         int ny, int nx, double c8, double th, float4* __restrict__ what,
+                         float* __restrict__ invn) {
+  const long n = (long)ny * nx;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = blockIdx.y;
+  const int y = (int)(i / nx), x = (int)(i - (long)y * nx);
+  const int yp = y + 1 < ny ? y + 1 : 0, xp = x + 1 < nx ? x + 1 : 0;
+  const double2* ub = u + (size_t)b * n;
+  const double2 u0 = ub[i], uy = ub[(long)yp * nx + x], ux = ub[(long)y * nx + xp];
+  double2* ry = r + (size_t)b * 2 * n;
+  double2* py = p + (size_t)b * 2 * n;
+  const double2 ry0 = ry[i], rx0 = ry[n + i];
+  double2 wy = make_double2(fma(c8, uy.x - u0.x, ry0.x), fma(c8, uy.y - u0.y, ry0.y));
+  double2 wx = make_double2(fma(c8, ux.x - u0.x, rx0.x), fma(c8, ux.y - u0.y, rx0.y));
+  const double nn = sqrt(wy.x * wy.x + wy.y * wy.y + wx.x * wx.x + wx.y * wx.y);
+  float4 wh = make_float4(0.f, 0.f, 0.f, 0.f);
+  float iv = 1.f;
+  if (nn > 1.0) {
+    const double sc = 1.0 / nn;
+    wy = make_double2(wy.x * sc, wy.y * sc);
+    wx = make_double2(wx.x * sc, wx.y * sc);
+    wh = make_float4((float)wy.x, (float)wy.y, (float)wx.x, (float)wx.y);
+    iv = (float)sc;
+  }
+  if (what && b == 0) {
+    what[i] = wh;
+    invn[i] = iv;
+  }
+  const double2 oy = py[i], ox = py[n + i];
+  ry[i] = make_double2(fma(th, wy.x - oy.x, wy.x), fma(th, wy.y - oy.y, wy.y));
+  ry[n + i] = make_double2(fma(th, wx.x - ox.x, wx.x), fma(th, wx.y - ox.y, wx.y));
+  py[i] = wy;
+  py[n + i] = wx;
+}
+
+__global__ void k_tv_zero64(double2* __restrict__ a, long total) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) a[i] = make_double2(0.0, 0.0);
+}
+
+// One tangent inner step for a TY x TX tile and tangents k0 .. k0+kper-1:
+// du = dz - lam D^H dr over the tile and its +1 halo (LDS), then
+// dw = dr + c8 D du, dp' = dP(w) dw, dr' = dp' + th (dp' - dp), dp = dp'.
+// dr is read from drA and written to drB (neighbours are read); dp in place.
+// first: dr = dp = 0 (the step from the zero start).
+constexpr int kTY = 8, kTX = 32;
+__global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz, const float2* __restrict__ drA,
+                                                  float2* __restrict__ drB, float2* __restrict__ dp,
+                                                  const float4* __restrict__ what, const float* __restrict__ invn,
+                                                  int ny, int nx, int K, int kper, float lam, float c8, float th,
+                                                  int first) {
+  __shared__ float2 sRy[kTY + 2][kTX + 1];   // dr_y rows y0-1 .. y0+TY, cols x0 .. x0+TX
+  __shared__ float2 sRx[kTY + 1][kTX + 2];   // dr_x rows y0 .. y0+TY, cols x0-1 .. x0+TX
+  __shared__ float2 sU[kTY + 1][kTX + 1];    // du rows y0 .. y0+TY, cols x0 .. x0+TX
+  const long n = (long)ny * nx;
+  const int tilesx = (nx + kTX - 1) / kTX;
+  const int y0 = (int)(blockIdx.x / tilesx) * kTY, x0 = (int)(blockIdx.x % tilesx) * kTX;
+  const int t = threadIdx.x, ty = t / kTX, tx = t % kTX;
+  const int y = y0 + ty, x = x0 + tx;
+  const bool own = y < ny && x < nx;
+  const long i = (long)y * nx + x;
+  float4 wh = make_float4(0.f, 0.f, 0.f, 0.f);
+  float iv = 1.f;
+  if (own) {
+    wh = what[i];
+    iv = invn[i];
+  }
+  const int k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
+  for (int k = k0; k < k1; ++k) {
+    const float2* zk = dz + (size_t)k * n;
+    if (!first) {
+      const float2* ry = drA + (size_t)k * 2 * n;
+      const float2* rx = ry + n;
+      for (int e = t; e < (kTY + 2) * (kTX + 1); e += 256) {
+        const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
+        sRy[rr][cc] = ry[(long)wrap(y0 - 1 + rr, ny) * nx + wrap(x0 + cc, nx)];
+      }
+      for (int e = t; e < (kTY + 1) * (kTX + 2); e += 256) {
+        const int rr = e / (kTX + 2), cc = e - rr * (kTX + 2);
+        sRx[rr][cc] = rx[(long)wrap(y0 + rr, ny) * nx + wrap(x0 - 1 + cc, nx)];
+      }
+      __syncthreads();
+    }
+    for (int e = t; e < (kTY + 1) * (kTX + 1); e += 256) {
+      const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
+      float2 u = zk[(long)wrap(y0 + rr, ny) * nx + wrap(x0 + cc, nx)];
+      if (!first) {
+        const float hx = sRy[rr][cc].x - sRy[rr + 1][cc].x + sRx[rr][cc].x - sRx[rr][cc + 1].x;
+        const float hy = sRy[rr][cc].y - sRy[rr + 1][cc].y + sRx[rr][cc].y - sRx[rr][cc + 1].y;
+        u = make_float2(fmaf(-lam, hx, u.x), fmaf(-lam, hy, u.y));
+      }
+      sU[rr][cc] = u;
+    }
+    __syncthreads();
+    if (own) {
+      const float2 u0 = sU[ty][tx], uy = sU[ty + 1][tx], ux = sU[ty][tx + 1];
+      float2 wy = make_float2(c8 * (uy.x - u0.x), c8 * (uy.y - u0.y));
+      float2 wx = make_float2(c8 * (ux.x - u0.x), c8 * (ux.y - u0.y));
+      float2 oy = make_float2(0.f, 0.f), ox = oy;
+      float2* pk = dp + (size_t)k * 2 * n;
+      if (!first) {
+        wy = cadd(wy, sRy[ty + 1][tx]);
+        wx = cadd(wx, sRx[ty][tx + 1]);
+        oy = pk[i];
+        ox = pk[n + i];
+      }
+      const float re = wh.x * wy.x + wh.y * wy.y + wh.z * wx.x + wh.w * wx.y;   // Re(w^H dw)
+      const float2 qy = make_float2((wy.x - wh.x * re) * iv, (wy.y - wh.y * re) * iv);
+      const float2 qx = make_float2((wx.x - wh.z * re) * iv, (wx.y - wh.w * re) * iv);
+      float2* rb = drB + (size_t)k * 2 * n;
+      rb[i] = make_float2(fmaf(th, qy.x - oy.x, qy.x), fmaf(th, qy.y - oy.y, qy.y));
+      rb[n + i] = make_float2(fmaf(th, qx.x - ox.x, qx.x), fmaf(th, qx.y - ox.y, qx.y));
+      pk[i] = qy;
+      pk[n + i] = qx;
+    }
+    __syncthreads();
+  }
+}
+
+// dx = dz - lam D^H dp; y = dx + theta (dx - xo); xo = dx   (K images)
+__global__ void k_tv_final(const float2* __restrict__ dz, const float2* __restrict__ dp, float2* __restrict__ xo,
+                           float2* __restrict__ yo, int ny, int nx, float lam, float theta) {
+  const long n = (long)ny * nx;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = blockIdx.y;
+  const int y = (int)(i / nx), x = (int)(i - (long)y * nx);
+  const int ym = y ? y - 1 : ny - 1, xm = x ? x - 1 : nx - 1;
+  const float2* py = dp + (size_t)k * 2 * n;
+  const float2* px = py + n;
+  const float2 a = py[(long)ym * nx + x], c = py[i], d = px[(long)y * nx + xm], e = px[i];
+  const size_t o = (size_t)k * n + i;
+  const float2 zv = dz[o];
+  const float2 dx = make_float2(fmaf(-lam, a.x - c.x + d.x - e.x, zv.x), fmaf(-lam, a.y - c.y + d.y - e.y, zv.y));
+  const float2 b = xo[o];
+  yo[o] = make_float2(fmaf(theta, dx.x - b.x, dx.x), fmaf(theta, dx.y - b.y, dx.y));
+  xo[o] = dx;
+}
+
+dim3 grid_img(long n, int B) { return dim3((unsigned)((n + 255) / 256), (unsigned)B); }
+
+}  // namespace
+
+hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what, float* invn, hipStream_t s) {
+  if (lam == 0.0) return hipSuccess;
+  const long n = (long)o.ny * o.nx;
+  const long dual = 2 * n * B;
+  hipLaunchKernelGGL(k_tv_zero64, grid_img(dual, 1), dim3(256), 0, s, o.tv_r, dual);
+  hipLaunchKernelGGL(k_tv_zero64, grid_img(dual, 1), dim3(256), 0, s, o.tv_p, dual);
+  const double c8 = 1.0 / (8.0 * lam);
+  for (int it = 0; it < o.tv_inner; ++it) {
+    hipLaunchKernelGGL(k_tv_u64, grid_img(n, B), dim3(256), 0, s, z, o.tv_r, o.tv_u, o.ny, o.nx, lam);
+    hipLaunchKernelGGL(k_tv_w64, grid_img(n, B), dim3(256), 0, s, o.tv_u, o.tv_r, o.tv_p, o.ny, o.nx, c8,
+                       o.tv_th[it], what ? what + (size_t)it * n : nullptr, what ? invn + (size_t)it * n : nullptr);
+  }
+  hipLaunchKernelGGL(k_tv_u64, grid_img(n, B), dim3(256), 0, s, z, o.tv_p, z, o.ny, o.nx, lam);
+  return hipGetLastError();
+}
+
+hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dp, const float4* what,
+                           const float* invn, int ny, int nx, int K, int inner, const float* th, float lam,
+                           hipStream_t s) {
+  const long n = (long)ny * nx;
+  const int tiles = ((ny + kTY - 1) / kTY) * ((nx + kTX - 1) / kTX);
+  int kper = 8;
+  while (kper > 1 && (long)tiles * ((K + kper - 1) / kper) < 2048) kper >>= 1;
+  const dim3 grid((unsigned)tiles, (unsigned)((K + kper - 1) / kper));
+  const float c8 = 1.0f / (8.0f * lam);
+  for (int it = 0; it < inner; ++it) {
+    hipLaunchKernelGGL(k_tv_inner, grid, dim3(256), 0, s, dz, drA, drB, dp, what + (size_t)it * n,
+                       invn + (size_t)it * n, ny, nx, K, kper, lam, c8, th[it], it == 0 ? 1 : 0);
+    std::swap(drA, drB);
+  }
+  return hipGetLastError();
+}
+
+hipError_t tv_tangent_final(const float2* dz, const float2* dp, float2* xo, float2* yo, int ny, int nx, int K,
+                            float lam, float theta, hipStream_t s) {
+  hipLaunchKernelGGL(k_tv_final, grid_img((long)ny * nx, K), dim3(256), 0, s, dz, dp, xo, yo, ny, nx, lam, theta);
+  return hipGetLastError();
+}
+
+}  // namespace pico

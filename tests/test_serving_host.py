@@ -90,3 +90,21 @@ def test_estimate_validates(p):
     with pytest.raises(p.PicoError) as ei:
         p.pico_estimate_bytes(d)
     assert ei.value.status == p.PICO_EINVAL
+
+
+def test_estimate_tv_counts_projection_data(p):
+    kw = dict(ncoils=8, probe_tile=16, sampling=p.PICO_CART_2D, recon=p.PICO_CS_FISTA_TV, kdata=0x3000,
+              fista_iters=50)
+    d10, _ = p.make_desc(128, 96, 0x1000, None, 0x2000, tv_inner_iters=10, **kw)
+    d20, _ = p.make_desc(128, 96, 0x1000, None, 0x2000, tv_inner_iters=20, **kw)
+    r10, p10 = p.pico_estimate_bytes(d10)
+    r20, _ = p.pico_estimate_bytes(d20)
+    # 20 bytes (w^ as 2 complex64 and 1/|w| as float32) per pixel per inner step
+    assert r20 - r10 == _round(50 * 20 * 128 * 96 * 16) + _round(50 * 20 * 128 * 96 * 4) \
+        - _round(50 * 10 * 128 * 96 * 16) - _round(50 * 10 * 128 * 96 * 4)
+    assert p10 > r10                             # FP64 primal and dual temporaries
+    for bad in (0, 1001):
+        d, _ = p.make_desc(128, 96, 0x1000, None, 0x2000, tv_inner_iters=bad, **kw)
+        with pytest.raises(p.PicoError) as ei:
+            p.pico_estimate_bytes(d)
+        assert ei.value.status == p.PICO_EINVAL
