@@ -244,12 +244,70 @@ def cs_leg(lib, workloads, torch, np, dev, steps):
     }
 
 
-def cs_robustness(lib, workloads, torch, np, dev, N=128):
+def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000):
+    """The paper's CS model (Sec. 3.2.3): TV-regularised FISTA, 320 x 320, 15
+    coils, Poisson-disc R=2, lambda_TV 1e-2, 100 iterations (10 dual steps per
+    prox).  Jacobian probes per second (K per step) against FP64 PMR replicas
+    per second on the same operator, and the time each needs for the paper's
+    converged sample count (5000 for both methods, its appendix on references)."""
+    pr = workloads.config(4, seed=0, reg="tv")
+    K = pr.probes
+    n = pr.ny * pr.nx
+    kd = cs_kspace(torch, dev, pr)
+    maps = torch.from_numpy(pr.maps.astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(pr.mask).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, sampling=lib.PICO_CART_2D,
+                      recon=lib.PICO_CS_FISTA_TV, kdata=kd, fista_iters=pr.extra["fista_iters"],
+                      cs_lambda=pr.extra["cs_lambda"], tv_inner_iters=pr.extra["tv_inner"], probe_tile=K)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    resident, _ = lib.pico_op_bytes(h)
+    acc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)])
+    lib.pico_noise_map(h, 3, 0, K, 0, acc)                   # warm-up step
+    torch.cuda.synchronize()
+    lib.pico_profile_start(h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        lib.pico_noise_map(h, 3, (i + 1) * K, K, 0, acc)
+    e1.record()
+    torch.cuda.synchronize()
+    prof = lib.pico_profile_stop(h)
+    ms = e0.elapsed_time(e1) / steps
+    # PMR: one batch of FP64 replicas (the finite difference at a small sigma needs FP64)
+    nrep = 16
+    pacc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)])
+    lib.pico_pmr_cs(h, 5, 0, 4, 1e-3, pacc)                  # workspace + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lib.pico_pmr_cs(h, 5, 4, nrep, 1e-3, pacc)
+    torch.cuda.synchronize()
+    pmr_s = (time.perf_counter() - t0) / nrep
+    lib.pico_destroy(h)
+    jvps = K / (ms / 1e3)
+    return {
+        "workload": f"TV-CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2 (24x24 calib), "
+                    f"FISTA {pr.extra['fista_iters']} its x {pr.extra['tv_inner']} dual steps, lambda_TV "
+                    f"{pr.extra['cs_lambda']}, K={K} JVP probes per step",
+        "jvps_per_s": round(jvps, 2), "ms_per_step": round(ms, 3), "init_s": round(init_s, 3),
+        "resident_bytes": int(resident),
+        "pmr_replicas_per_s": round(1.0 / pmr_s, 2), "pmr_precision": "f64",
+        "n_converged": n_conv,
+        "pico_s_at_n": round(n_conv / jvps, 2), "pmr_s_at_n": round(n_conv * pmr_s, 2),
+        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+    }
+
+
+def cs_robustness(lib, workloads, torch, np, dev, N=128, reg="l1wav"):
     """Noise-level sweep of the CS workload (Sec. 3.2.3, robustness): data at
     input SNR 45 dB - 20 log10(scale); per level the Jacobian-probe std map
     (N probes) against the PMR std map (N replicas perturbed at the data's own
-    noise level, normalised by it); both per unit whitened noise."""
-    pr = workloads.config(4, seed=0)
+    noise level, normalised by it); both per unit whitened noise.  reg "tv"
+    sweeps the TV model of the paper's experiment."""
+    pr = workloads.config(4, seed=0, reg=reg)
+    tv = reg == "tv"
     n = pr.ny * pr.nx
     maps = torch.from_numpy(pr.maps.astype(np.complex64)).to(dev)
     mask = torch.from_numpy(pr.mask).to(dev)
@@ -265,8 +323,10 @@ def cs_robustness(lib, workloads, torch, np, dev, N=128):
             dim=(-2, -1)) * mk[None]
         sigma = float(torch.sqrt(torch.mean(torch.abs(k0[:, mk > 0]) ** 2))) * 10 ** (-snr / 20)
         h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, sampling=lib.PICO_CART_2D,
-                          recon=lib.PICO_CS_FISTA_L1WAV, kdata=kd, fista_iters=pr.extra["fista_iters"],
-                          cs_lambda=pr.extra["cs_lambda"], wavelet_levels=pr.extra["levels"], probe_tile=128)
+                          recon=lib.PICO_CS_FISTA_TV if tv else lib.PICO_CS_FISTA_L1WAV, kdata=kd,
+                          fista_iters=pr.extra["fista_iters"], cs_lambda=pr.extra["cs_lambda"],
+                          wavelet_levels=pr.extra["levels"], tv_inner_iters=pr.extra["tv_inner"],
+                          probe_tile=128)
         a1 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
         lib.pico_noise_map(h, 3, 0, N, 0, lib.make_accum(a1[0], None, a1[1]))
         a2 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
@@ -281,7 +341,10 @@ def cs_robustness(lib, workloads, torch, np, dev, N=128):
         rows.append({"scale": scale, "snr_db": round(snr, 1), "sigma": sigma,
                      "nrmse_pmr_vs_pico": round(float(torch.linalg.norm(s_pmr - s_pico) / torch.linalg.norm(s_pico)), 4),
                      "mean_std_pico": float(s_pico.mean()), "mean_std_pmr": float(s_pmr.mean())})
-    return {"workload": f"CS 320x320, 8 coils, lambda 1e-3, FISTA 100; N={N} probes and {N} replicas per level",
+    model = (f"TV (lambda_TV {pr.extra['cs_lambda']}, {pr.extra['tv_inner']} dual steps)" if tv
+             else f"L1-db4 (lambda {pr.extra['cs_lambda']})")
+    return {"workload": f"CS {pr.ny}x{pr.nx}, {pr.nc} coils, {model}, FISTA {pr.extra['fista_iters']}; "
+                        f"N={N} probes and {N} replicas per level",
             "levels": rows}
 
 
@@ -298,10 +361,12 @@ def main():
                     help="steps of the spiral Toeplitz leg (0 to skip)")
     ap.add_argument("--cs-steps", type=int, default=1,
                     help="steps of the compressed-sensing JVP leg (0 to skip)")
+    ap.add_argument("--cs-tv-steps", type=int, default=1,
+                    help="steps of the TV compressed-sensing JVP leg (0 to skip)")
     ap.add_argument("--serve", choices=["off", "short", "full"], default="short",
                     help="serving leg: short request mix (default), the full sweep, or off")
-    ap.add_argument("--cs-robustness", action="store_true",
-                    help="also run the CS noise-level sweep (PICO vs PMR std maps)")
+    ap.add_argument("--cs-robustness", choices=["off", "l1wav", "tv"], default="off",
+                    help="also run the CS noise-level sweep (PICO vs PMR std maps) for that model")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -519,7 +584,13 @@ def main():
     if args.cs_steps > 0:
         cs_res = cs_leg(lib, workloads, torch, np, dev, args.cs_steps)
 
-    robust = cs_robustness(lib, workloads, torch, np, dev) if args.cs_robustness else None
+    # --- the paper's CS model: TV-regularised FISTA, Jacobian probes vs FP64 PMR replicas
+    cs_tv = None
+    if args.cs_tv_steps > 0:
+        cs_tv = cs_tv_leg(lib, workloads, torch, np, dev, args.cs_tv_steps)
+
+    robust = (cs_robustness(lib, workloads, torch, np, dev, reg=args.cs_robustness)
+              if args.cs_robustness != "off" else None)
 
     # --- serving: mixed requests under Poisson arrivals, p50 / p99 latency
     serving = None
@@ -557,6 +628,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "spiral": spiral,
         "cs": cs_res,
+        "cs_tv": cs_tv,
         "serving": serving,
     }
     if robust is not None:

@@ -28,9 +28,9 @@ namespace pico {
 
 namespace {
 
-__device__ __forceinline__ int wrap(int v, int n) { return (v % n + n) % n; }
-
-__device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// v in [-n, 2n) folded into [0, n): the halo of a tile reaches one row or
+// column past the image, and tiles start inside it
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // out = z - lam D^H r over B images (blockIdx.y); out may alias z
 __global__ void k_tv_u64(const double2* z, const double2* __restrict__ r, double2* out, int ny, int nx,
@@ -97,8 +97,52 @@ __global__ void k_tv_zero64(double2* __restrict__ a, long total) {
 // du = dz - lam D^H dr over the tile and its +1 halo (LDS), then
 // dw = dr + c8 D du, dp' = dP(w) dw, dr' = dp' + th (dp' - dp), dp = dp'.
 // dr is read from drA and written to drB (neighbours are read); dp in place.
-// first: dr = dp = 0 (the step from the zero start).
+// first: dr = dp = 0 (the step from the zero start).  Every global load of
+// tangent k + 1 is issued before tangent k is computed.  Needs ny >= TY + 2
+// and nx >= TX + 2 (the halo wraps at most once).
 constexpr int kTY = 8, kTX = 32;
+constexpr int kRy = (kTY + 2) * (kTX + 1), kRx = (kTY + 1) * (kTX + 2), kRu = (kTY + 1) * (kTX + 1);
+constexpr int kPer = (kRy + 255) / 256;    // region elements per thread (2 for each region)
+static_assert(kRx <= kPer * 256 && kRu <= kPer * 256, "region split");
+
+struct TangentLoads {
+  float2 ry[kPer], rx[kPer], z[kPer], py, px;
+};
+
+__device__ __forceinline__ void tv_load(TangentLoads& L, const float2* __restrict__ dz, const float2* __restrict__ drA,
+                                        const float2* __restrict__ dp, int k, long n, int ny, int nx, int y0, int x0,
+                                        int t, bool own, long i, bool first) {
+  const float2* zk = dz + (size_t)k * n;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int e = t + 256 * j;
+    if (e < kRu) {
+      const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
+      L.z[j] = zk[(long)wrap(y0 + rr, ny) * nx + wrap(x0 + cc, nx)];
+    }
+  }
+  if (first) return;
+  const float2* ry = drA + (size_t)k * 2 * n;
+  const float2* rx = ry + n;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int e = t + 256 * j;
+    if (e < kRy) {
+      const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
+      L.ry[j] = ry[(long)wrap(y0 - 1 + rr, ny) * nx + wrap(x0 + cc, nx)];
+    }
+    if (e < kRx) {
+      const int rr = e / (kTX + 2), cc = e - rr * (kTX + 2);
+      L.rx[j] = rx[(long)wrap(y0 + rr, ny) * nx + wrap(x0 - 1 + cc, nx)];
+    }
+  }
+  if (own) {
+    const float2* pk = dp + (size_t)k * 2 * n;
+    L.py = pk[i];
+    L.px = pk[n + i];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz, const float2* __restrict__ drA,
                                                   float2* __restrict__ drB, float2* __restrict__ dp,
                                                   const float4* __restrict__ what, const float* __restrict__ invn,
@@ -114,6 +158,7 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
   const int y = y0 + ty, x = x0 + tx;
   const bool own = y < ny && x < nx;
   const long i = (long)y * nx + x;
+  const bool fst = first != 0;
   float4 wh = make_float4(0.f, 0.f, 0.f, 0.f);
   float iv = 1.f;
   if (own) {
@@ -121,48 +166,56 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
     iv = invn[i];
   }
   const int k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
+  TangentLoads cur;
+  cur.py = cur.px = make_float2(0.f, 0.f);
+  if (k0 < k1) tv_load(cur, dz, drA, dp, k0, n, ny, nx, y0, x0, t, own, i, fst);
   for (int k = k0; k < k1; ++k) {
-    const float2* zk = dz + (size_t)k * n;
-    if (!first) {
-      const float2* ry = drA + (size_t)k * 2 * n;
-      const float2* rx = ry + n;
-      for (int e = t; e < (kTY + 2) * (kTX + 1); e += 256) {
-        const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
-        sRy[rr][cc] = ry[(long)wrap(y0 - 1 + rr, ny) * nx + wrap(x0 + cc, nx)];
-      }
-      for (int e = t; e < (kTY + 1) * (kTX + 2); e += 256) {
-        const int rr = e / (kTX + 2), cc = e - rr * (kTX + 2);
-        sRx[rr][cc] = rx[(long)wrap(y0 + rr, ny) * nx + wrap(x0 - 1 + cc, nx)];
+    if (!fst) {
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int e = t + 256 * j;
+        if (e < kRy) {
+          const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
+          sRy[rr][cc] = cur.ry[j];
+        }
+        if (e < kRx) {
+          const int rr = e / (kTX + 2), cc = e - rr * (kTX + 2);
+          sRx[rr][cc] = cur.rx[j];
+        }
       }
       __syncthreads();
     }
-    for (int e = t; e < (kTY + 1) * (kTX + 1); e += 256) {
-      const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
-      float2 u = zk[(long)wrap(y0 + rr, ny) * nx + wrap(x0 + cc, nx)];
-      if (!first) {
-        const float hx = sRy[rr][cc].x - sRy[rr + 1][cc].x + sRx[rr][cc].x - sRx[rr][cc + 1].x;
-        const float hy = sRy[rr][cc].y - sRy[rr + 1][cc].y + sRx[rr][cc].y - sRx[rr][cc + 1].y;
-        u = make_float2(fmaf(-lam, hx, u.x), fmaf(-lam, hy, u.y));
+    float2 oy = cur.py, ox = cur.px;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int e = t + 256 * j;
+      if (e < kRu) {
+        const int rr = e / (kTX + 1), cc = e - rr * (kTX + 1);
+        float2 u = cur.z[j];
+        if (!fst) {
+          const float hx = sRy[rr][cc].x - sRy[rr + 1][cc].x + sRx[rr][cc].x - sRx[rr][cc + 1].x;
+          const float hy = sRy[rr][cc].y - sRy[rr + 1][cc].y + sRx[rr][cc].y - sRx[rr][cc + 1].y;
+          u = make_float2(fmaf(-lam, hx, u.x), fmaf(-lam, hy, u.y));
+        }
+        sU[rr][cc] = u;
       }
-      sU[rr][cc] = u;
+    }
+    float2 ryo = make_float2(0.f, 0.f), rxo = ryo;
+    if (own && !fst) {
+      ryo = sRy[ty + 1][tx];
+      rxo = sRx[ty][tx + 1];
     }
     __syncthreads();
+    if (k + 1 < k1) tv_load(cur, dz, drA, dp, k + 1, n, ny, nx, y0, x0, t, own, i, fst);
     if (own) {
       const float2 u0 = sU[ty][tx], uy = sU[ty + 1][tx], ux = sU[ty][tx + 1];
-      float2 wy = make_float2(c8 * (uy.x - u0.x), c8 * (uy.y - u0.y));
-      float2 wx = make_float2(c8 * (ux.x - u0.x), c8 * (ux.y - u0.y));
-      float2 oy = make_float2(0.f, 0.f), ox = oy;
-      float2* pk = dp + (size_t)k * 2 * n;
-      if (!first) {
-        wy = cadd(wy, sRy[ty + 1][tx]);
-        wx = cadd(wx, sRx[ty][tx + 1]);
-        oy = pk[i];
-        ox = pk[n + i];
-      }
+      const float2 wy = make_float2(fmaf(c8, uy.x - u0.x, ryo.x), fmaf(c8, uy.y - u0.y, ryo.y));
+      const float2 wx = make_float2(fmaf(c8, ux.x - u0.x, rxo.x), fmaf(c8, ux.y - u0.y, rxo.y));
       const float re = wh.x * wy.x + wh.y * wy.y + wh.z * wx.x + wh.w * wx.y;   // Re(w^H dw)
       const float2 qy = make_float2((wy.x - wh.x * re) * iv, (wy.y - wh.y * re) * iv);
       const float2 qx = make_float2((wx.x - wh.z * re) * iv, (wx.y - wh.w * re) * iv);
       float2* rb = drB + (size_t)k * 2 * n;
+      float2* pk = dp + (size_t)k * 2 * n;
       rb[i] = make_float2(fmaf(th, qy.x - oy.x, qy.x), fmaf(th, qy.y - oy.y, qy.y));
       rb[n + i] = make_float2(fmaf(th, qx.x - ox.x, qx.x), fmaf(th, qx.y - ox.y, qx.y));
       pk[i] = qy;
@@ -215,6 +268,7 @@ hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what,
 hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dp, const float4* what,
                            const float* invn, int ny, int nx, int K, int inner, const float* th, float lam,
                            hipStream_t s) {
+  if (ny < kTY + 2 || nx < kTX + 2) return hipErrorInvalidValue;
   const long n = (long)ny * nx;
   const int tiles = ((ny + kTY - 1) / kTY) * ((nx + kTX - 1) / kTX);
   int kper = 8;

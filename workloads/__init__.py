@@ -239,8 +239,12 @@ def config(i: int, seed: int = 0, **kw) -> Problem:
     2: 320x320, 15 coils, R=2 uniform + 24 centre lines, 256 probes, CG 30 its.
     3: spiral 256x256, 16 coils, 48x4096 interleaves subsampled by R (kw R=2),
        lambda 0.1, CG 30 its, 256 probes.
-    4: 320x320 CS, 8 coils, Poisson-disc R=2 with 24x24 calibration, 128 probes.
-    Keyword overrides: ny, nx, nc, R, acs, probes, cg_iters, lam.
+    4: 320x320 CS, 8 coils, Poisson-disc R=2 with 24x24 calibration, 128 probes,
+       L1-db4 FISTA 100 its, lambda 1e-3; with reg="tv" the model of the paper's
+       CS experiment (Sec. 3.2.3): 15 coils, TV weight 1e-2, 10 dual steps per
+       proximal step.
+    Keyword overrides: ny, nx, nc, R, acs, probes, cg_iters, lam (and for 4:
+    calib, fista_iters, cs_lambda, snr_db, reg, tv_inner).
     """
     rng = np.random.default_rng(seed)
     if i == 1:
@@ -269,16 +273,18 @@ def config(i: int, seed: int = 0, **kw) -> Problem:
                        probes=kw.get("probes", 256),
                        extra={"oversamp": kw.get("oversamp", 2.0), "kb_width": kw.get("kb_width", 6)})
     if i == 4:
-        n = kw.get("ny", 320); nc = kw.get("nc", 8)
+        tv = kw.get("reg", "l1wav") == "tv"
+        n = kw.get("ny", 320); nc = kw.get("nc", 15 if tv else 8)
         maps = coil_maps(n, n, nc, rng)
         psi = noise_cov(nc, rng)
         x = phantom(n, rng)
         mask = poisson_disc_mask(n, n, kw.get("R", 2.0), kw.get("calib", 24), seed)
-        return Problem(f"cs-{n}-{nc}c", n, n, maps, psi, "cart2d", mask=mask,
+        return Problem(f"cs-{'tv' if tv else 'l1wav'}-{n}-{nc}c", n, n, maps, psi, "cart2d", mask=mask,
                        recon="cs", probes=kw.get("probes", 128),
                        extra={"phantom": x, "fista_iters": kw.get("fista_iters", 100),
-                              "cs_lambda": kw.get("cs_lambda", 1e-3), "levels": 4,
-                              "snr_db": kw.get("snr_db", 45.0)})
+                              "cs_lambda": kw.get("cs_lambda", 1e-2 if tv else 1e-3), "levels": 4,
+                              "snr_db": kw.get("snr_db", 45.0), "reg": "tv" if tv else "l1wav",
+                              "tv_inner": kw.get("tv_inner", 10)})
     raise ValueError(f"unknown workload {i}")
 
 
