@@ -76,6 +76,17 @@ typedef enum {
   PICO_GAUSSIAN = 3        /* v ~ CN(0, 1), Sec. 2.2 Eq. (18)                   */
 } pico_probe_t;
 
+typedef enum {
+  PICO_FP32 = 0,           /* complex64 maps and intermediates (default)        */
+  PICO_BF16_MAPS = 1,      /* whitened maps rounded to bfloat16 (nearest even)
+                              and stored packed; the operator is the one of the
+                              rounded maps on every path                          */
+  PICO_BF16_STREAM = 2     /* as 1, plus the row-transformed coil planes of the
+                              2-D grid path (Cartesian 2-D, Toeplitz) stored as
+                              bfloat16 between its passes; arithmetic, CG vectors,
+                              dots and accumulators stay FP32 / FP64            */
+} pico_storage_t;
+
 /* Operator description.  Pointers are read during pico_init only. */
 typedef struct {
   int32_t ny, nx, ncoils;       /* image size and coil count (1..64)              */
@@ -127,6 +138,10 @@ typedef struct {
    * primal: fista_iters * tv_inner_iters * ny * nx * 20 bytes of device
    * memory. */
   int32_t tv_inner_iters;
+  /* pico_storage_t: precision of stored maps and streamed intermediates
+   * (mixed precision; bfloat16 results agree with FP32 storage to about
+   * 1e-2 relative). */
+  int32_t storage;
 } pico_op_desc_t;
 
 /* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a
@@ -307,8 +322,8 @@ pico_status_t pico_op_bytes(pico_op_t op, uint64_t* resident, uint64_t* peak);
 
 /* ------------------------------------------------------------------ serving
  * Many noise-map requests, each against its own operator, on the current
- * device (the spec serving mode: HBM-budgeted admission, probe tiles of
- * all admitted requests in flight at once).
+ * device (serving: HBM-budgeted admission, probe tiles of all admitted
+ * requests in flight at once).
  *
  * pico_server_create takes one device allocation of hbm_budget bytes (rounded
  * down to 256) and starts a worker thread.  Every operator the server builds

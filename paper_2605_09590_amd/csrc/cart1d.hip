@@ -25,7 +25,7 @@ namespace pico {
 // FFT (B -> A) -> accumulate conj(S') times the result.
 template <class CF>
 __device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 (&qa)[CF::VMAX],
-                                           float lam, const float2* __restrict__ mcol, int nc,
+                                           float lam, MapRef mcol, int nc,
                                            uint32_t mbits, float2* lds, int lane,
                                            const typename CF::Tw& tw) {
   constexpr int N = CF::N;
@@ -34,7 +34,7 @@ __device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 
 #pragma unroll
   for (int m = 0; m < CF::VA; ++m) qa[m] = cscale(pv[m], lam);
   for (int c = 0; c < nc; ++c) {
-    const float2* __restrict__ s = mcol + (size_t)c * N;
+    const MapRef s = mcol + (size_t)c * N;
     float2 v[CF::VMAX];
 #pragma unroll
     for (int m = 0; m < CF::VA; ++m) v[m] = inA ? cmul(s[CF::posA(lane, m)], pv[m]) : make_float2(0.f, 0.f);
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
   }
 
   const size_t base = ((size_t)kk * a.nx + col) * N;
-  const float2* __restrict__ mcol = a.maps + (size_t)col * a.nc * N;
+  const MapRef mcol = MapRef{a.maps, a.maps_bf} + (size_t)col * a.nc * N;
   float2 pv[CF::VMAX];
   double d0 = 0.0;
 
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
         }
       }
       CF::template inverse<true>(v, lds, lane, tw);
-      const float2* __restrict__ s = mcol + (size_t)c * N;
+      const MapRef s = mcol + (size_t)c * N;
       if (inA) {
 #pragma unroll
         for (int m = 0; m < VA; ++m) pv[m] = cadd(pv[m], cmulc(s[CF::posA(lane, m)], v[m]));

@@ -2,6 +2,7 @@
 //
 //  * complex float2 arithmetic,
 //  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) for probes and noise,
+//  * bfloat16 storage of complex values,
 //  * compile-time sines/cosines for in-register DFT constants,
 //  * a compile-time loop helper.
 #pragma once
@@ -33,6 +34,28 @@ template <bool INV>
 __device__ __forceinline__ float2 mul_mj(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
+
+// ---------------------------------------------------------------- bfloat16 storage
+// A complex value as two bfloat16 halves of one 32-bit word (real in the low
+// half).  Packing rounds FP32 to nearest, ties to even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint32_t pack_bf16x2(float2 v) { return bf16_rne(v.x) | (bf16_rne(v.y) << 16); }
+__device__ __forceinline__ float2 unpack_bf16x2(uint32_t w) {
+  return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
+// Coil maps as complex64, or (b non-null) as packed bfloat16 pairs; the
+// choice is uniform over a launch.
+struct MapRef {
+  const float2* f;
+  const uint32_t* b;
+  __device__ __forceinline__ float2 operator[](size_t i) const { return b ? unpack_bf16x2(b[i]) : f[i]; }
+  __device__ __forceinline__ MapRef operator+(size_t o) const { return MapRef{f + o, b ? b + o : nullptr}; }
+};
 
 // ---------------------------------------------------------------- Philox4x32-10
 struct u32x4 { uint32_t w0, w1, w2, w3; };

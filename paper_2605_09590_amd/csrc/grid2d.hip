@@ -136,8 +136,9 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   }
 
   float2* __restrict__ T = a.T;
+  uint32_t* __restrict__ Tb = a.Tb;
   for (int c = 0; c < a.nc; ++c) {
-    const float2* __restrict__ s = a.maps + ((size_t)c * a.ny + y) * a.nx;
+    const MapRef s = MapRef{a.maps, a.maps_bf} + ((size_t)c * a.ny + y) * a.nx;
     float2 v[CF::VMAX];
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
@@ -148,9 +149,14 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
     }
     CF::template forward<false>(v, lds, lane, tw);
     if (active && inB) {
-      float2* t = T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+      const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+      if (Tb) {
 #pragma unroll
-      for (int r = 0; r < VB; ++r) t[CF::posB(lane, r)] = v[r];
+        for (int r = 0; r < VB; ++r) Tb[off + CF::posB(lane, r)] = pack_bf16x2(v[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < VB; ++r) T[off + CF::posB(lane, r)] = v[r];
+      }
     }
   }
 }
@@ -159,32 +165,40 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
 // Strip of `ncol` (<= ngrp) adjacent columns of one plane to / from an LDS tile
 // [rows][ts].  Loads go out in batches of 8 per thread before any is consumed,
 // so a workgroup keeps 8 x 256 loads in flight instead of one per thread.
-__device__ __forceinline__ void strip_load(float2* __restrict__ tile, const float2* __restrict__ src,
+__device__ __forceinline__ float2 widen(float2 v) { return v; }
+__device__ __forceinline__ float2 widen(uint32_t v) { return unpack_bf16x2(v); }
+__device__ __forceinline__ void narrow(float2& d, float2 v) { d = v; }
+__device__ __forceinline__ void narrow(uint32_t& d, float2 v) { d = pack_bf16x2(v); }
+
+// E: float2 (complex64 planes) or uint32_t (packed bfloat16 pairs)
+template <class E>
+__device__ __forceinline__ void strip_load(float2* __restrict__ tile, const E* __restrict__ src,
                                            int rows, int ngrp, int ts, int ncol, long stride) {
   constexpr int B = 8;
   const int total = rows * ngrp;
   for (int i0 = threadIdx.x; i0 < total; i0 += B * 256) {
-    float2 v[B];
+    E v[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int i = i0 + u * 256;
       const int yy = i / ngrp, j = i % ngrp;
-      v[u] = (i < total && j < ncol) ? src[(size_t)yy * stride + j] : make_float2(0.f, 0.f);
+      v[u] = (i < total && j < ncol) ? src[(size_t)yy * stride + j] : E{};
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int i = i0 + u * 256;
-      if (i < total) tile[(i / ngrp) * ts + i % ngrp] = v[u];
+      if (i < total) tile[(i / ngrp) * ts + i % ngrp] = widen(v[u]);
     }
   }
 }
 
-__device__ __forceinline__ void strip_store(const float2* __restrict__ tile, float2* __restrict__ dst,
+template <class E>
+__device__ __forceinline__ void strip_store(const float2* __restrict__ tile, E* __restrict__ dst,
                                             int rows, int ngrp, int ts, int ncol, long stride) {
   const int total = rows * ngrp;
   for (int i = threadIdx.x; i < total; i += 256) {
     const int yy = i / ngrp, j = i % ngrp;
-    if (j < ncol) dst[(size_t)yy * stride + j] = tile[yy * ts + j];
+    if (j < ncol) narrow(dst[(size_t)yy * stride + j], tile[yy * ts + j]);
   }
 }
 
@@ -203,7 +217,8 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
   const int x0 = blockIdx.x * NGRP;
   const size_t plane = (size_t)blockIdx.y * a.ny * a.Gx;
   const int ncol = min(NGRP, a.Gx - x0);
-  strip_load(tile, a.T + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
+  if (a.Tb) strip_load(tile, a.Tb + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
+  else strip_load(tile, a.T + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
   __syncthreads();
   const bool grp = g < NGRP && g < ncol;
   const bool inA = CF::inA(lane), inB = CF::inB(lane);
@@ -231,7 +246,8 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
     }
   }
   __syncthreads();
-  strip_store(tile, a.T + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
+  if (a.Tb) strip_store(tile, a.Tb + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
+  else strip_store(tile, a.T + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
 }
 
 // ---------------------------------------------------------------- row pass 2
@@ -280,11 +296,16 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   }
   for (int c = 0; c < a.nc; ++c) {
     float2 v[CF::VMAX];
-    const float2* t = T + (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+    const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+    if (a.Tb) {
 #pragma unroll
-    for (int r = 0; r < VB; ++r) v[r] = inB ? t[CF::posB(lane, r)] : make_float2(0.f, 0.f);
+      for (int r = 0; r < VB; ++r) v[r] = inB ? unpack_bf16x2(a.Tb[off + CF::posB(lane, r)]) : make_float2(0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int r = 0; r < VB; ++r) v[r] = inB ? T[off + CF::posB(lane, r)] : make_float2(0.f, 0.f);
+    }
     CF::template inverse<true>(v, lds, lane, tw);
-    const float2* __restrict__ s = a.maps + ((size_t)c * a.ny + y) * a.nx;
+    const MapRef s = MapRef{a.maps, a.maps_bf} + ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
       const int xx = CF::posA(lane, m);
@@ -659,6 +680,19 @@ __global__ void k_mask_weights(const uint8_t* __restrict__ mask, float* __restri
   if (i >= ny * nx) return;
   const int ky = i / nx, kx = i % nx;
   w[(size_t)kx * ny + ky] = mask[i] ? scale : 0.f;
+}
+
+__global__ void k_quantise_maps(float2* __restrict__ maps, uint32_t* __restrict__ bf, long count) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t w = pack_bf16x2(maps[i]);
+  bf[i] = w;
+  maps[i] = unpack_bf16x2(w);
+}
+
+hipError_t launch_quantise_maps(float2* maps, uint32_t* bf, long count, hipStream_t s) {
+  hipLaunchKernelGGL(k_quantise_maps, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, maps, bf, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_mask_weights(const uint8_t* mask, float* w, int ny, int nx, float scale,

@@ -53,6 +53,8 @@ struct pico_op_s {
   hipStream_t last_stream = nullptr;
   // resident operator
   float2* maps = nullptr;     // whitened maps (layout per path)
+  uint32_t* maps_bf = nullptr;  // bfloat16 storage: the same maps packed (maps then hold the rounded values)
+  bool stream_bf = false;     // grid path: row-transformed planes T kept as bfloat16
   float* maskw = nullptr;     // separable path: [ny] mask[k] / ny
   bool use_gram = false;      // separable path: dense per-column blocks on the matrix cores
   float2* gram = nullptr;     // [nx][ny][ny] conj(M_x[i][j]) at [x][j][i]
@@ -241,6 +243,7 @@ hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hip
     a.nc = op->nc;
     a.K = K;
     a.maps = op->maps;
+    a.maps_bf = op->maps_bf;
     a.maskw = op->maskw;
     a.twt = op->twt;
     a.src = c.src;
@@ -268,10 +271,12 @@ hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hip
   g.Gy = op->Gy;
   g.Gx = op->Gx;
   g.maps = op->maps;
+  g.maps_bf = op->maps_bf;
   g.w = op->w;
   g.twx = op->twx;
   g.twy = op->twy;
   g.T = op->T;
+  g.Tb = op->stream_bf ? reinterpret_cast<uint32_t*>(op->T) : nullptr;
   g.src = c.src;
   g.x = op->x;
   g.r = op->r;
@@ -596,6 +601,8 @@ pico_status_t validate(const pico_op_desc_t* d) {
   if (d->sampling != PICO_CART_1D && d->sampling != PICO_CART_2D && d->sampling != PICO_NONCART)
     return fail(PICO_EUNSUPPORTED, "unknown sampling kind");
   if (d->ncoils < 1 || d->ncoils > 64) return fail(PICO_EINVAL, "ncoils must be in 1..64");
+  if (d->storage != PICO_FP32 && d->storage != PICO_BF16_MAPS && d->storage != PICO_BF16_STREAM)
+    return fail(PICO_EINVAL, "unknown storage kind");
   if (d->nx < 2 || d->ny < 2 || (d->ny & 1) || (d->nx & 1)) return fail(PICO_EINVAL, "ny and nx must be even and >= 2");
   if ((int64_t)d->ny * d->nx >= (int64_t)1 << 31) return fail(PICO_EINVAL, "image too large");
   if (d->sampling == PICO_CART_1D) {
@@ -670,6 +677,7 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
   const size_t f = d->sampling == PICO_NONCART ? 2 : 1, Gy = f * ny, Gx = f * nx;
   const size_t nblk = colmajor ? nx : ny;
   add(n * nc * 8);
+  if (d->storage != PICO_FP32) add(n * nc * 4);
   for (int i = 0; i < 4; ++i) add(n * K * 8);
   add(K * nblk * 4 * 8);
   add(512 * 8);
@@ -804,6 +812,8 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     return fail(PICO_EDEVICE, std::string(what) + ": " + hipGetErrorString(err));
   };
   if ((e = op->alloc(&op->maps, n * nc)) != hipSuccess) return bad(e, "maps");
+  if (d->storage != PICO_FP32 && (e = op->alloc(&op->maps_bf, n * nc)) != hipSuccess) return bad(e, "bfloat16 maps");
+  op->stream_bf = d->storage == PICO_BF16_STREAM && d->sampling != PICO_CART_1D;
   if ((e = op->alloc(&op->x, n * K)) != hipSuccess) return bad(e, "workspace x");
   if ((e = op->alloc(&op->r, n * K)) != hipSuccess) return bad(e, "workspace r");
   if ((e = op->alloc(&op->p, n * K)) != hipSuccess) return bad(e, "workspace p");
@@ -833,6 +843,7 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if ((e = hipMemcpyAsync(op->maskw, w.data(), ny * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     if ((e = hipMemcpyAsync(op->twt, tw.data(), ny * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     if ((e = pico::launch_prep_maps_cart1d((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, s)) != hipSuccess) return bad(e, "prep maps");
+    if (op->maps_bf && (e = pico::launch_quantise_maps(op->maps, op->maps_bf, (long)(n * nc), s)) != hipSuccess) return bad(e, "bfloat16 maps");
     if (wants_gram(d)) {
       if ((e = op->alloc(&op->gram, pico::gram_bytes(ny, nx) / sizeof(float2))) != hipSuccess) return bad(e, "dense blocks");
       if ((e = op->alloc(&op->gram_c, ny)) != hipSuccess) return bad(e, "dense blocks");
@@ -850,6 +861,7 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if ((e = hipMemcpyAsync(op->twy, ty.data(), Gy * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     const int fold = d->sampling == PICO_CART_2D;
     if ((e = pico::launch_prep_maps_rowmajor((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, fold, s)) != hipSuccess) return bad(e, "prep maps");
+    if (op->maps_bf && (e = pico::launch_quantise_maps(op->maps, op->maps_bf, (long)(n * nc), s)) != hipSuccess) return bad(e, "bfloat16 maps");
     if (d->sampling == PICO_CART_2D) {
       if ((e = pico::launch_mask_weights(d->mask, op->w, ny, nx, (float)(1.0 / ((double)ny * nx)), s)) != hipSuccess) return bad(e, "weights");
     } else {
@@ -937,6 +949,8 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
                (e = op->alloc(&o.tv_u, n)) != hipSuccess))
       return bad(e, "FP64 TV workspace");
     if ((e = pico::cs64_setup(o, (const float2*)d->maps, linv_d, s)) != hipSuccess) return bad(e, "FP64 primal");
+    // bfloat16 storage defines the operator by the rounded maps: the primal uses them too
+    if (op->maps_bf && (e = pico::cs64_maps_from_folded(o, op->maps, s)) != hipSuccess) return bad(e, "FP64 primal");
     double lam_hat = 0.0;
     if ((e = pico::cs64_power(o, d->power_iters, y, z, part, &lam_hat, s)) != hipSuccess) return bad(e, "power");
     op->s2 = d->power_margin * lam_hat;

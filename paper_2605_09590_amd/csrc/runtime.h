@@ -24,6 +24,7 @@ enum Cart1dMode : int {
 struct Cart1dArgs {
   int ny, nx, nc, K;           // K probes in this launch
   const float2* maps;          // [nx][nc][ny] whitened, (-1)^y folded
+  const uint32_t* maps_bf;     // the same maps as packed bfloat16 pairs, or NULL
   const float* maskw;          // [ny] weight mask[k] / ny (0 off the mask)
   const float2* twt;           // [ny] W_ny^m = exp(-2 pi i m / ny)
   const float2* src;           // input field   (mode dependent)
@@ -77,10 +78,12 @@ struct AccumArgs {
 struct Grid2dArgs {
   int ny, nx, nc, K, Gy, Gx;
   const float2* maps;          // [nc][ny][nx] whitened (and sign-folded for Cartesian)
+  const uint32_t* maps_bf;     // the same maps as packed bfloat16 pairs, or NULL
   const float* w;              // [Gx][Gy] real weights
   const float2* twx;           // [Gx] W_Gx^m
   const float2* twy;           // [Gy] W_Gy^m
   float2* T;                   // [K][nc][ny][Gx] row-transformed planes
+  uint32_t* Tb;                // non-NULL: T kept as packed bfloat16 pairs here instead
   const float2* src;           // C1_APPLY input [K][ny][nx]
   float2* x;                   // [K][ny][nx]
   float2* r;
@@ -104,6 +107,9 @@ hipError_t launch_prep_maps_rowmajor(const float2* maps, const double* linv, flo
                                      int ny, int nx, int fold, hipStream_t s);
 hipError_t launch_mask_weights(const uint8_t* mask, float* w, int ny, int nx, float scale,
                                hipStream_t s);
+// maps rounded to bfloat16 (nearest even): packed copy in bf, and the rounded
+// values written back to maps, so every reader sees the same operator
+hipError_t launch_quantise_maps(float2* maps, uint32_t* bf, long count, hipStream_t s);
 hipError_t launch_power_start_rowmajor(float2* p, int n, hipStream_t s);
 hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse, const float2* twx,
                         const float2* twy, hipStream_t s);
@@ -158,6 +164,9 @@ struct Cs64 {
   float* tv_invn = nullptr;
 };
 hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream_t s);
+// FP64 maps of the primal from already whitened, (-1)^(y+x)-folded maps
+// (bfloat16 storage: the primal uses the rounded operator too)
+hipError_t cs64_maps_from_folded(Cs64& o, const float2* folded, hipStream_t s);
 hipError_t cs64_normal(const Cs64& o, int B, const double2* y, double2* q, hipStream_t s);
 hipError_t cs64_adjoint_kdata(const Cs64& o, const float2* kdata, const double* linv, double2* out,
                               hipStream_t s);

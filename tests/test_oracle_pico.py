@@ -191,3 +191,29 @@ def test_stderr_proxy_matches_closed_form_and_monte_carlo():
     op1 = pico.cartesian(maps, np.array([[2.0]]), np.ones(8, np.uint8))
     acc = pico.noise_map(pico.Covariance(op1, 0.0, cg_iters=4), 1, 0, 5)
     assert pico.stderr_proxy(acc) < 1e-7          # rounding of sumsq - N m^2 only
+
+
+def test_bf16_rounding_matches_library_conversion():
+    """oracle.storage rounds like torch's CPU float32 -> bfloat16 conversion
+    (round to nearest, ties to even), including exact ties, signed zeros,
+    infinities and values next to the largest finite bfloat16."""
+    import torch
+    from oracle import storage
+    rng = np.random.default_rng(0)
+    x = np.concatenate([
+        rng.standard_normal(20000).astype(np.float32) * 10.0 ** rng.integers(-30, 30, 20000),
+        # exact ties: low 16 bits 0x8000 over odd and even kept halves
+        (np.arange(0x3F800000, 0x3F800000 + 64 * 0x10000, 0x10000, dtype=np.uint32) + 0x8000).view(np.float32),
+        np.array([0.0, -0.0, np.inf, -np.inf, 3.3895314e38, -3.3895314e38, 1e-40], np.float32),
+    ])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = storage.bf16_round_real(x)
+    assert np.array_equal(got, ref)
+    assert np.isnan(storage.bf16_round_real(np.array([np.nan], np.float32))[0])
+    # relative rounding error is at most the unit roundoff 2^-8 (8 significant bits)
+    ok = np.isfinite(ref) & (np.abs(x) > 1e-30)
+    assert np.max(np.abs(got[ok] - x[ok]) / np.abs(x[ok])) <= 2.0 ** -8
+    z = (rng.standard_normal(50) + 1j * rng.standard_normal(50)).astype(np.complex64)
+    zq = storage.bf16_round(z)
+    assert np.array_equal(zq.real, storage.bf16_round_real(z.real))
+    assert np.array_equal(zq.imag, storage.bf16_round_real(z.imag))

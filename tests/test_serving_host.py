@@ -108,3 +108,16 @@ def test_estimate_tv_counts_projection_data(p):
         with pytest.raises(p.PicoError) as ei:
             p.pico_estimate_bytes(d)
         assert ei.value.status == p.PICO_EINVAL
+
+
+def test_estimate_counts_bf16_maps(p):
+    base = dict(ncoils=8, probe_tile=16, sampling=p.PICO_CART_2D)
+    d0, _ = p.make_desc(128, 96, 0x1000, None, 0x2000, **base)
+    r0, _ = p.pico_estimate_bytes(d0)
+    for st in (p.PICO_BF16_MAPS, p.PICO_BF16_STREAM):
+        d, _ = p.make_desc(128, 96, 0x1000, None, 0x2000, storage=st, **base)
+        assert p.pico_estimate_bytes(d)[0] == r0 + _round(8 * 128 * 96 * 4)   # packed bfloat16 maps
+    d, _ = p.make_desc(128, 96, 0x1000, None, 0x2000, storage=3, **base)
+    with pytest.raises(p.PicoError) as ei:
+        p.pico_estimate_bytes(d)
+    assert ei.value.status == p.PICO_EINVAL
