@@ -198,7 +198,61 @@ def serve_leg(lib, workloads, torch, np, dev, full):
     }
 
 
-def cs_leg(lib, workloads, torch, np, dev, steps):
+def spiral_leg(lib, workloads, torch, np, dev, steps, storage):
+    """Probe-solves/s of the spiral workload and the HBM roofline of its
+    Toeplitz normal operator; storage PICO_BF16_STREAM keeps maps and the
+    row-transformed coil planes in bfloat16 (half the plane bytes)."""
+    sp = workloads.config(3, seed=0)
+    Ks = 256
+    traj = torch.from_numpy(sp.traj.astype(np.float32)).to(dev)
+    smaps = torch.from_numpy(sp.maps.astype(np.complex64)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs = lib.pico_init(sp.ny, sp.nx, smaps, sp.psi, None, sampling=lib.PICO_NONCART,
+                       lam=sp.lam, cg_iters=sp.cg_iters, probe_tile=Ks, traj=traj,
+                       nsamples=traj.shape[0], storage=storage)
+    sinit = time.perf_counter() - t0
+    ns = sp.ny * sp.nx
+    sacc = lib.make_accum(*[torch.zeros(ns, dtype=torch.float64, device=dev) for _ in range(2)])
+    lib.pico_noise_map(hs, 5, 0, Ks, 0, sacc)            # warm-up step
+    torch.cuda.synchronize()
+    lib.pico_profile_start(hs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        lib.pico_noise_map(hs, 5, (i + 1) * Ks, Ks, 0, sacc)
+    e1.record()
+    torch.cuda.synchronize()
+    sprof = lib.pico_profile_stop(hs)
+    lib.pico_destroy(hs)
+    sms = e0.elapsed_time(e1) / steps
+    it_ms, it_n = sprof["normal_iter"]
+    sop_s = it_ms / it_n / 1e3
+    Gx = 2 * sp.nx
+    # per probe and normal-operator application: T written, read+written, read
+    # (nc ny Gx elements of 8 B, or 4 B in bfloat16) + per-probe fields (rows
+    # pass: x r p q in, x r p out; inverse pass: p r in, q out) + maps twice
+    # per launch
+    eb = 4 if storage == lib.PICO_BF16_STREAM else 8
+    t_bytes = 4 * sp.nc * sp.ny * Gx * eb
+    f_bytes = 10 * ns * 8
+    sbytes = Ks * (t_bytes + f_bytes) + 2 * sp.nc * ns * (4 if storage else 8)
+    return {
+        "workload": "spiral 256x256, 16 coils, 48x4096 interleaves R=2 (98304 samples), "
+                    "lambda 0.1, K=256 probes, CG 30 per solve (2 solves + 1 M per probe)",
+        "storage": ["f32", "bf16 maps", "bf16 maps + planes"][storage],
+        "probe_solves_per_s": round(Ks / (sms / 1e3), 2), "ms_per_step": round(sms, 3),
+        "init_s": round(sinit, 3),
+        "roofline": {"bound": "hbm", "achieved": round(sbytes / sop_s / 1e9, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(sbytes / sop_s / 1e9 / PEAK_HBM_GBS, 4),
+                     "kernel": "grid normal operator (rows_fwd + cols + rows_inv), C1_ITER",
+                     "avg_application_us": round(sop_s * 1e6, 1), "alg_bytes": sbytes},
+        "kernel_ms": {k: round(v[0], 3) for k, v in sprof.items()},
+    }
+
+
+def cs_leg(lib, workloads, torch, np, dev, steps, storage=0):
     """JVPs/s of the CS workload and the HBM roofline of its normal operator."""
     pr = workloads.config(4, seed=0)
     K = pr.probes
@@ -210,7 +264,8 @@ def cs_leg(lib, workloads, torch, np, dev, steps):
     t0 = time.perf_counter()
     h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, sampling=lib.PICO_CART_2D,
                       recon=lib.PICO_CS_FISTA_L1WAV, kdata=kd, fista_iters=pr.extra["fista_iters"],
-                      cs_lambda=pr.extra["cs_lambda"], wavelet_levels=pr.extra["levels"], probe_tile=K)
+                      cs_lambda=pr.extra["cs_lambda"], wavelet_levels=pr.extra["levels"], probe_tile=K,
+                      storage=storage)
     init_s = time.perf_counter() - t0
     acc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)])
     lib.pico_noise_map(h, 3, 0, K, 0, acc)                   # warm-up step
@@ -228,12 +283,15 @@ def cs_leg(lib, workloads, torch, np, dev, steps):
     it_ms, it_n = prof["normal_iter"]
     op_s = it_ms / it_n / 1e3
     # per probe and normal-operator application: coil k-space written, read+written,
-    # read (nc ny nx complex64 each) + p read, q written; maps twice per launch
-    alg = K * (4 * pr.nc * n * 8 + 2 * n * 8) + 2 * pr.nc * n * 8
+    # read (nc ny nx elements of 8 B, 4 B in bfloat16) + p read, q written; maps
+    # twice per launch
+    eb = 4 if storage == lib.PICO_BF16_STREAM else 8
+    alg = K * (4 * pr.nc * n * eb + 2 * n * 8) + 2 * pr.nc * n * (4 if storage else 8)
     return {
         "workload": f"CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2 (24x24 calib), "
                     f"L1-db4 (4 levels) FISTA {pr.extra['fista_iters']} its, lambda "
                     f"{pr.extra['cs_lambda']}, K={K} JVP probes per step",
+        "storage": ["f32", "bf16 maps", "bf16 maps + planes"][storage],
         "jvps_per_s": round(K / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
         "init_s": round(init_s, 3),
         "roofline": {"bound": "hbm", "achieved": round(alg / op_s / 1e9, 1), "peak": PEAK_HBM_GBS,
@@ -530,59 +588,18 @@ def main():
         "hbm_GBs_alg": round(bytes_alg / avg_s / 1e9, 1),
     }
 
-    # --- second workload: spiral CG-SENSE, Toeplitz normal operator (HBM-bound path)
-    spiral = None
+    # --- second workload: spiral CG-SENSE, Toeplitz normal operator (HBM-bound path),
+    # complex64 planes and the bfloat16-stream variant
+    spiral = spiral_bf16 = None
     if args.spiral_steps > 0:
-        sp = workloads.config(3, seed=0)
-        Ks = 256
-        traj = torch.from_numpy(sp.traj.astype(np.float32)).to(dev)
-        smaps = torch.from_numpy(sp.maps.astype(np.complex64)).to(dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hs = lib.pico_init(sp.ny, sp.nx, smaps, sp.psi, None, sampling=lib.PICO_NONCART,
-                           lam=sp.lam, cg_iters=sp.cg_iters, probe_tile=Ks, traj=traj,
-                           nsamples=traj.shape[0])
-        sinit = time.perf_counter() - t0
-        ns = sp.ny * sp.nx
-        sacc = lib.make_accum(*[torch.zeros(ns, dtype=torch.float64, device=dev) for _ in range(2)])
-        lib.pico_noise_map(hs, 5, 0, Ks, 0, sacc)            # warm-up step
-        torch.cuda.synchronize()
-        lib.pico_profile_start(hs)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for i in range(args.spiral_steps):
-            lib.pico_noise_map(hs, 5, (i + 1) * Ks, Ks, 0, sacc)
-        e1.record()
-        torch.cuda.synchronize()
-        sprof = lib.pico_profile_stop(hs)
-        lib.pico_destroy(hs)
-        sms = e0.elapsed_time(e1) / args.spiral_steps
-        it_ms, it_n = sprof["normal_iter"]
-        sop_s = it_ms / it_n / 1e3
-        Gy, Gx = 2 * sp.ny, 2 * sp.nx
-        # per probe and normal-operator application: T written, read+written, read
-        # (nc ny Gx complex64 each) + per-probe fields (rows pass: x r p q in, x r p out;
-        # inverse pass: p r in, q out) + maps twice per launch
-        t_bytes = 4 * sp.nc * sp.ny * Gx * 8
-        f_bytes = 10 * ns * 8
-        sbytes = Ks * (t_bytes + f_bytes) + 2 * sp.nc * ns * 8
-        spiral = {
-            "workload": "spiral 256x256, 16 coils, 48x4096 interleaves R=2 (98304 samples), "
-                        "lambda 0.1, K=256 probes, CG 30 per solve (2 solves + 1 M per probe)",
-            "probe_solves_per_s": round(Ks / (sms / 1e3), 2), "ms_per_step": round(sms, 3),
-            "init_s": round(sinit, 3),
-            "roofline": {"bound": "hbm", "achieved": round(sbytes / sop_s / 1e9, 1),
-                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(sbytes / sop_s / 1e9 / PEAK_HBM_GBS, 4),
-                         "kernel": "grid normal operator (rows_fwd + cols + rows_inv), C1_ITER",
-                         "avg_application_us": round(sop_s * 1e6, 1), "alg_bytes": sbytes},
-            "kernel_ms": {k: round(v[0], 3) for k, v in sprof.items()},
-        }
+        spiral = spiral_leg(lib, workloads, torch, np, dev, args.spiral_steps, lib.PICO_FP32)
+        spiral_bf16 = spiral_leg(lib, workloads, torch, np, dev, args.spiral_steps, lib.PICO_BF16_STREAM)
 
     # --- third workload: CS (FISTA L1-db4), batched Jacobian-vector probes
-    cs_res = None
+    cs_res = cs_bf16 = None
     if args.cs_steps > 0:
         cs_res = cs_leg(lib, workloads, torch, np, dev, args.cs_steps)
+        cs_bf16 = cs_leg(lib, workloads, torch, np, dev, args.cs_steps, lib.PICO_BF16_STREAM)
 
     # --- the paper's CS model: TV-regularised FISTA, Jacobian probes vs FP64 PMR replicas
     cs_tv = None
@@ -627,7 +644,9 @@ def main():
         "kernel_launches": {k: v[1] for k, v in prof.items()},
         "roofline": roofline, "cpu_baseline": cpu,
         "spiral": spiral,
+        "spiral_bf16": spiral_bf16,
         "cs": cs_res,
+        "cs_bf16": cs_bf16,
         "cs_tv": cs_tv,
         "serving": serving,
     }

@@ -10,8 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpico.so")
-SOURCES = ["cart1d.hip", "gram.hip", "grid2d.hip", "toeplitz.hip", "kb.hip", "cs.hip", "tv.hip", "cg.hip", "pico_abi.hip",
-           "serve.hip"]
+SOURCES = ["cart1d.hip", "cart1d_bf16.hip", "gram.hip", "grid2d.hip", "grid2d_bf16.hip", "toeplitz.hip", "kb.hip",
+           "cs.hip", "tv.hip", "cg.hip", "pico_abi.hip", "serve.hip"]
 
 # Packed FP32 instructions stay off: the build relies on scalar / float2 code
 # only, and the compiler must not fuse it into v_pk_* forms.

@@ -1,246 +1,9 @@
-// Separable Cartesian SENSE normal operator and the CG building blocks.
-//
-// With a phase-encode mask that is constant along kx, the whitened normal
-// operator M = sum_c S_c^H F^H P F S_c (Sec. 2.1, Eqs. (3), (6)) is block
-// diagonal over image columns: F_x^H F_x = I cancels, leaving one 1-D
-// transform along y per column and coil.  For even ny the centred
-// orthonormal DFT (fftshift o fft o ifftshift) equals (-1)^(ny/2) D F D / sqrt(ny)
-// with D = diag((-1)^y) and F the plain DFT, so F_c^H P F_c = D F^H P F D / ny:
-// D is folded into the whitened maps once, the centred-order mask applies
-// unchanged, and each coil costs one forward and one inverse unnormalised
-// FFT with the weight mask[k] / ny in between.
-//
-// Layout: every per-probe field is stored column-major, [K][nx][ny], so a
-// column is one contiguous line; maps are [nx][nc][ny].  One workgroup is one
-// wavefront holding G = 64/L probe columns of the same image column; each
-// column FFT lives in the registers of a group of L lanes and exchanges
-// through LDS.
-#include "fft.h"
-#include "runtime.h"
+// Separable Cartesian SENSE: launch of the normal operator (kernels in
+// cart1d_normal.h; cart1d_bf16.hip holds the bfloat16-map instantiation) and
+// the CG building blocks of the column-major layout.
+#include "cart1d_normal.h"
 
 namespace pico {
-
-// q = (M + lam) p for one probe column held in layout A by the lanes of one
-// group: per coil, S' p -> FFT (layout A -> B) -> weight mask[k]/ny -> inverse
-// FFT (B -> A) -> accumulate conj(S') times the result.
-template <class CF>
-__device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 (&qa)[CF::VMAX],
-                                           float lam, MapRef mcol, int nc,
-                                           uint32_t mbits, float2* lds, int lane,
-                                           const typename CF::Tw& tw) {
-  constexpr int N = CF::N;
-  constexpr float minv = 1.0f / N;
-  const bool inA = CF::inA(lane);
-#pragma unroll
-  for (int m = 0; m < CF::VA; ++m) qa[m] = cscale(pv[m], lam);
-  for (int c = 0; c < nc; ++c) {
-    const MapRef s = mcol + (size_t)c * N;
-    float2 v[CF::VMAX];
-#pragma unroll
-    for (int m = 0; m < CF::VA; ++m) v[m] = inA ? cmul(s[CF::posA(lane, m)], pv[m]) : make_float2(0.f, 0.f);
-    CF::template forward<false>(v, lds, lane, tw);
-#pragma unroll
-    for (int r = 0; r < CF::VB; ++r)
-      v[r] = ((mbits >> r) & 1u) ? cscale(v[r], minv) : make_float2(0.f, 0.f);
-    CF::template inverse<true>(v, lds, lane, tw);
-    if (inA) {
-#pragma unroll
-      for (int m = 0; m < CF::VA; ++m) qa[m] = cadd(qa[m], cmulc(s[CF::posA(lane, m)], v[m]));
-    }
-  }
-}
-
-// Sum of one double per lane over each lane group of L lanes, in lane order
-// (bitwise reproducible); the result is valid in the group's first lane.
-template <int L>
-__device__ __forceinline__ double group_reduce(double v, double* red, int lane) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (lane == 0) {
-    const int base = threadIdx.x;
-    for (int i = 0; i < L; ++i) s += red[base + i];
-  }
-  __syncthreads();
-  return s;
-}
-
-template <class CF, int MODE>
-__global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
-  constexpr int N = CF::N, L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
-  constexpr int VA = CF::VA, VB = CF::VB;
-  __shared__ float2 lds_all[NG * CF::SPAN];
-  __shared__ double red[64];
-  const int g = threadIdx.x / L;
-  const int lane = threadIdx.x % L;
-  const int col = blockIdx.y;
-  const int k = blockIdx.x * G + g;
-  const bool active = g < G && k < a.K;
-  const int kk = active ? k : 0;  // idle lanes work on probe 0 but never store
-  const bool inA = CF::inA(lane), inB = CF::inB(lane);
-  float2* lds = lds_all + g * CF::SPAN;
-
-  typename CF::Tw tw;
-  CF::load_tw(tw, a.twt, lane);
-  uint32_t mbits = 0;
-  if (inB) {
-#pragma unroll
-    for (int r = 0; r < VB; ++r) mbits |= (a.maskw[CF::posB(lane, r)] != 0.f ? 1u : 0u) << r;
-  }
-
-  const size_t base = ((size_t)kk * a.nx + col) * N;
-  const MapRef mcol = MapRef{a.maps, a.maps_bf} + (size_t)col * a.nc * N;
-  float2 pv[CF::VMAX];
-  double d0 = 0.0;
-
-  if constexpr (MODE == C1_PMR_RHS) {
-    // r = A^H n = sum_c conj(S_w,c) F_c^H P n_c with F_c^H = (-1)^(ny/2) D F^H D / sqrt(ny):
-    // per coil, w[k] = (-1)^(ny/2 + k) n[k] / sqrt(ny) on the sampled lines,
-    // unnormalised inverse FFT, times conj(S') (D already folded into S').
-    const float rs = rsqrtf((float)N);
-#pragma unroll
-    for (int m = 0; m < VA; ++m) pv[m] = make_float2(0.f, 0.f);
-    for (int c = 0; c < a.nc; ++c) {
-      float2 v[CF::VMAX];
-#pragma unroll
-      for (int r = 0; r < VB; ++r) {
-        const int kc = CF::posB(lane, r);
-        if ((mbits >> r) & 1u) {
-          const uint32_t elem = (uint32_t)(((size_t)c * N + kc) * a.nx + col);
-          const float2 n = draw_probe(a.seed, a.first + kk, elem, 1u, 3);
-          v[r] = cscale(n, ((kc + N / 2) & 1) ? -rs : rs);
-        } else {
-          v[r] = make_float2(0.f, 0.f);
-        }
-      }
-      CF::template inverse<true>(v, lds, lane, tw);
-      const MapRef s = mcol + (size_t)c * N;
-      if (inA) {
-#pragma unroll
-        for (int m = 0; m < VA; ++m) pv[m] = cadd(pv[m], cmulc(s[CF::posA(lane, m)], v[m]));
-      }
-    }
-    if (inA) {
-#pragma unroll
-      for (int m = 0; m < VA; ++m) {
-        if (active) a.r[base + CF::posA(lane, m)] = pv[m];
-        d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
-      }
-    }
-    d0 = group_reduce<L>(d0, red, lane);
-    if (active && lane == 0) a.part[((size_t)k * a.nx + col) * 4] = d0;
-    return;
-  } else {
-    // rv keeps r_i for the d3 = Re(r^H q) partial; pv = p_i enters the normal operator
-    float2 rv[CF::VMAX];
-    if (inA) {
-      if constexpr (MODE == C1_FIRST_PROBE) {
-#pragma unroll
-        for (int m = 0; m < VA; ++m) {
-          const int y = CF::posA(lane, m);
-          pv[m] = draw_probe(a.seed, a.first + kk, (uint32_t)(y * a.nx + col), 0u, a.dist);
-          rv[m] = pv[m];
-          if (active) { a.r[base + y] = pv[m]; a.p[base + y] = pv[m]; }
-        }
-      } else if constexpr (MODE == C1_FIRST_BUF) {
-#pragma unroll
-        for (int m = 0; m < VA; ++m) {
-          const int y = CF::posA(lane, m);
-          pv[m] = a.r[base + y];
-          rv[m] = pv[m];
-          if (active) a.p[base + y] = pv[m];
-        }
-      } else if constexpr (MODE == C1_ITER) {
-        // finish iteration i-1 and start iteration i:
-        //   x += alpha p, r -= alpha q, p = r + beta p
-        const float alpha = (float)a.alpha[kk];
-        const float beta = (float)a.beta[kk];
-#pragma unroll
-        for (int m = 0; m < VA; ++m) {
-          const int y = CF::posA(lane, m);
-          const float2 po = a.p[base + y];
-          const float2 qo = a.q[base + y];
-          const float2 xo = a.x_zero ? make_float2(0.f, 0.f) : a.x[base + y];
-          rv[m] = cfma(a.r[base + y], -alpha, qo);
-          pv[m] = cfma(rv[m], beta, po);
-          if (active) {
-            a.x[base + y] = cfma(xo, alpha, po);
-            a.r[base + y] = rv[m];
-            a.p[base + y] = pv[m];
-          }
-        }
-      } else {  // C1_APPLY
-#pragma unroll
-        for (int m = 0; m < VA; ++m) {
-          pv[m] = cscale(a.src[base + CF::posA(lane, m)], a.scale);
-          rv[m] = make_float2(0.f, 0.f);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int m = 0; m < VA; ++m) {
-        pv[m] = make_float2(0.f, 0.f);
-        rv[m] = make_float2(0.f, 0.f);
-      }
-    }
-
-    float2 qa[CF::VMAX];
-    normal_col<CF>(pv, qa, a.lam, mcol, a.nc, mbits, lds, lane, tw);
-
-    double d1 = 0.0, d2 = 0.0, d3 = 0.0;
-    if (inA) {
-#pragma unroll
-      for (int m = 0; m < VA; ++m) {
-        if (active) a.q[base + CF::posA(lane, m)] = qa[m];
-        d0 += (double)rv[m].x * rv[m].x + (double)rv[m].y * rv[m].y;
-        d1 += (double)pv[m].x * qa[m].x + (double)pv[m].y * qa[m].y;
-        d2 += (double)qa[m].x * qa[m].x + (double)qa[m].y * qa[m].y;
-        d3 += (double)rv[m].x * qa[m].x + (double)rv[m].y * qa[m].y;
-      }
-    }
-    d0 = group_reduce<L>(d0, red, lane);
-    d1 = group_reduce<L>(d1, red, lane);
-    d2 = group_reduce<L>(d2, red, lane);
-    d3 = group_reduce<L>(d3, red, lane);
-    if (active && lane == 0) {
-      double* pp = a.part + ((size_t)k * a.nx + col) * 4;
-      pp[0] = d0;
-      pp[1] = d1;
-      pp[2] = d2;
-      pp[3] = d3;
-    }
-  }
-}
-
-// ------------------------------------------------------------ dispatch
-template <class CF>
-static hipError_t launch_plan(int mode, const Cart1dArgs& a, hipStream_t s) {
-  constexpr int G = 64 / CF::L;
-  dim3 grid((a.K + G - 1) / G, a.nx), block(64);
-  switch (mode) {
-    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_cart1d<CF, C1_FIRST_PROBE>), grid, block, 0, s, a); break;
-    case C1_FIRST_BUF: hipLaunchKernelGGL((k_cart1d<CF, C1_FIRST_BUF>), grid, block, 0, s, a); break;
-    case C1_ITER: hipLaunchKernelGGL((k_cart1d<CF, C1_ITER>), grid, block, 0, s, a); break;
-    case C1_APPLY: hipLaunchKernelGGL((k_cart1d<CF, C1_APPLY>), grid, block, 0, s, a); break;
-    case C1_PMR_RHS: hipLaunchKernelGGL((k_cart1d<CF, C1_PMR_RHS>), grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-// Column-FFT layouts per line length.  Stockham plans keep N/T values on T
-// lanes through every pass; two-step plans split N = LA * VA over LA lanes
-// with a single LDS transpose per transform.
-using Col64 = TwoStep<8, 8>;
-using Col96 = StockhamCol<FFTPlan<96, 8, 12, 4, 2>>;
-using Col128 = StockhamCol<FFTPlan<128, 16, 8, 4, 4>>;
-using Col160 = StockhamCol<FFTPlan<160, 8, 20, 4, 2>>;
-using Col192 = StockhamCol<FFTPlan<192, 16, 12, 4, 4>>;
-using Col256 = TwoStep<16, 16>;
-using Col288 = StockhamCol<FFTPlan<288, 16, 18, 2, 2, 2, 2>>;
-using Col320 = TwoStep<20, 16>;
-using Col384 = StockhamCol<FFTPlan<384, 16, 24, 4, 4>>;
-using Col512 = StockhamCol<FFTPlan<512, 32, 16, 16, 2>>;
 
 bool cart1d_supported(int ny) {
   switch (ny) {
@@ -252,19 +15,8 @@ bool cart1d_supported(int ny) {
 }
 
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s) {
-  switch (a.ny) {
-    case 64: return launch_plan<Col64>(mode, a, s);
-    case 96: return launch_plan<Col96>(mode, a, s);
-    case 128: return launch_plan<Col128>(mode, a, s);
-    case 160: return launch_plan<Col160>(mode, a, s);
-    case 192: return launch_plan<Col192>(mode, a, s);
-    case 256: return launch_plan<Col256>(mode, a, s);
-    case 288: return launch_plan<Col288>(mode, a, s);
-    case 320: return launch_plan<Col320>(mode, a, s);
-    case 384: return launch_plan<Col384>(mode, a, s);
-    case 512: return launch_plan<Col512>(mode, a, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (a.maps_bf) return launch_cart1d_bf16(mode, a, s);
+  return cart1d_dispatch<false>(mode, a, s);
 }
 
 // ------------------------------------------------------------ map preparation

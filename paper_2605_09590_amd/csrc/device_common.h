@@ -48,15 +48,6 @@ __device__ __forceinline__ float2 unpack_bf16x2(uint32_t w) {
   return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
 }
 
-// Coil maps as complex64, or (b non-null) as packed bfloat16 pairs; the
-// choice is uniform over a launch.
-struct MapRef {
-  const float2* f;
-  const uint32_t* b;
-  __device__ __forceinline__ float2 operator[](size_t i) const { return b ? unpack_bf16x2(b[i]) : f[i]; }
-  __device__ __forceinline__ MapRef operator+(size_t o) const { return MapRef{f + o, b ? b + o : nullptr}; }
-};
-
 // ---------------------------------------------------------------- Philox4x32-10
 struct u32x4 { uint32_t w0, w1, w2, w3; };
 

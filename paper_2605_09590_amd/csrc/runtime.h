@@ -102,6 +102,7 @@ bool cart1d_supported(int ny);
 bool grid_line_supported(int n);
 size_t grid_cols_lds_bytes(int Gy, int ny);
 hipError_t launch_grid_normal(int mode, const Grid2dArgs& a, hipStream_t s);
+hipError_t launch_grid_normal_bf16(int mode, const Grid2dArgs& a, hipStream_t s);   // a.maps_bf set
 hipError_t launch_accum_rowmajor(const AccumArgs& a, hipStream_t s);
 hipError_t launch_prep_maps_rowmajor(const float2* maps, const double* linv, float2* out, int nc,
                                      int ny, int nx, int fold, hipStream_t s);
@@ -222,6 +223,7 @@ hipError_t kb_adjoint(const KbOp& o, const float2* maps, int nc, int K, const fl
 hipError_t kb_forward(const KbOp& o, const float2* maps, int nc, int K, const float2* x, float2* out,
                       hipStream_t s);
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
+hipError_t launch_cart1d_bf16(int mode, const Cart1dArgs& a, hipStream_t s);   // a.maps_bf set
 // dense per-column normal operator (phase-encode masks, FP32 matrix cores)
 bool gram_supported(int ny);
 size_t gram_bytes(int ny, int nx);
