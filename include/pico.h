@@ -261,6 +261,36 @@ pico_status_t pico_noise_map_adaptive(pico_op_t op, uint64_t seed, int64_t first
  * samplings, PICO_EINVAL, PICO_EDEVICE. */
 pico_status_t pico_exact_diag(pico_op_t op, double* var, void* stream);
 
+/* Reduced-resolution noise grid (Sec. 5, Discussion: noise maps follow the
+ * smooth coil geometry and can be estimated on a coarser grid, then
+ * interpolated back to the native one).
+ *
+ * pico_init_reduced builds the operator of the same acquisition restricted to
+ * the central (ny/f) x (nx/f) block of k-space on an (ny/f) x (nx/f) grid:
+ * coarse pixel m sits at native pixel f m (the centred DFT keeps pixel N/2 on
+ * both grids), so the coarse maps are desc->maps at every f-th pixel, the
+ * mask is its central block, and a non-Cartesian sample w (rad per native
+ * pixel) is kept as f w when -pi/f <= w_y, w_x < pi/f.  Every other field of
+ * desc (psi, lambda, CG, probe tile, storage, gridding) applies unchanged;
+ * the handle works with every call of a CG-SENSE operator at the coarse size
+ * (maps, accumulators and references are (ny/f) x (nx/f)).  The coarse map
+ * estimates the native variance at the coarse pixels with no rescaling (unit
+ * white k-space noise and orthonormal transforms keep the pixel level).
+ * desc is read during the call only.  Errors: PICO_EINVAL (factor < 2, ny or
+ * nx not divisible by f, an odd margin ny - ny/f or nx - nx/f, no sample in
+ * the coarse band, or a coarse size the build does not cover),
+ * PICO_EUNSUPPORTED (compressed-sensing reconstructions), PICO_ENOMEM,
+ * PICO_EDEVICE.
+ *
+ * pico_upsample_map writes the native map var (device float64
+ * [f ny_c][f nx_c]) from a coarse one (device float64 [ny_c][nx_c]) of a
+ * reduced operator: native pixel (y, x) lies at coarse coordinate
+ * (y / f, x / f), periodic bilinear weights (coarse values kept at the
+ * coarse pixels).  Errors: PICO_EUNSUPPORTED (not a reduced operator),
+ * PICO_EINVAL (NULL). */
+pico_status_t pico_init_reduced(const pico_op_desc_t* desc, int32_t factor, void* stream, pico_op_t* out);
+pico_status_t pico_upsample_map(pico_op_t coarse_op, const double* coarse, double* var, void* stream);
+
 /* Kernel-class timing with HIP events recorded on the caller's stream.
  * pico_profile_start clears and enables recording; pico_profile_stop waits
  * for the recorded events and writes, per class k < PICO_PROF_KINDS, the

@@ -45,6 +45,7 @@ pico_status_t fail(pico_status_t st, const std::string& msg) {
 
 struct pico_op_s {
   int ny = 0, nx = 0, nc = 0, sampling = 0, recon = 0;
+  int reduce_f = 0;           // reduced-grid operator: coarsening factor (0 = native)
   int cg_iters = 0, K = 0;
   double cg_tol = 0.0, lam_rel = 0.0, lam_abs = 0.0;
   bool colmajor = true;       // separable Cartesian layout
@@ -1257,6 +1258,97 @@ pico_status_t pico_monitor_nrmse(pico_op_t op, const pico_accum_t* acc, const do
     den += part[2 * b + 1];
   }
   *nrmse = den > 0.0 ? std::sqrt(num / den) : NAN;
+  return PICO_OK;
+}
+
+pico_status_t pico_init_reduced(const pico_op_desc_t* d, int32_t factor, void* stream, pico_op_t* out) {
+  if (!d || !out) return fail(PICO_EINVAL, "NULL descriptor or output handle");
+  *out = nullptr;
+  if (factor < 2) return fail(PICO_EINVAL, "factor must be >= 2");
+  if (d->recon != PICO_CGSENSE)
+    return fail(PICO_EUNSUPPORTED, "the reduced grid is built for CG-SENSE operators");
+  if (d->ny < 2 || d->nx < 2 || d->ny % factor || d->nx % factor)
+    return fail(PICO_EINVAL, "ny and nx must be divisible by the factor");
+  const int ny = d->ny, nx = d->nx, nc = d->ncoils, cy = ny / factor, cx = nx / factor;
+  if (((ny - cy) & 1) || ((nx - cx) & 1)) return fail(PICO_EINVAL, "the central k-space block must sit on whole samples");
+  if (nc < 1 || nc > 64 || !d->maps) return fail(PICO_EINVAL, "maps and ncoils in 1..64 required");
+  hipStream_t s = (hipStream_t)stream;
+  pico_op_desc_t c = *d;
+  c.ny = cy;
+  c.nx = cx;
+  float2* maps_c = nullptr;
+  uint8_t* mask_c = nullptr;
+  float* traj_c = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : {(void*)maps_c, (void*)mask_c, (void*)traj_c})
+      if (p) (void)hipFree(p);
+  };
+  auto dev_fail = [&](hipError_t e, const char* what) {
+    cleanup();
+    if (e == hipErrorOutOfMemory) return fail(PICO_ENOMEM, std::string(what) + ": out of device memory");
+    return fail(PICO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&maps_c, (size_t)nc * cy * cx * sizeof(float2))) != hipSuccess) return dev_fail(e, "coarse maps");
+  if ((e = pico::launch_subsample_maps((const float2*)d->maps, maps_c, nc, ny, nx, factor, s)) != hipSuccess)
+    return dev_fail(e, "coarse maps");
+  c.maps = maps_c;
+  if (d->sampling == PICO_CART_1D || d->sampling == PICO_CART_2D) {
+    if (!d->mask) {
+      cleanup();
+      return fail(PICO_EINVAL, "NULL mask");
+    }
+    if (d->sampling == PICO_CART_1D) {
+      if ((e = hipMalloc(&mask_c, cy)) != hipSuccess ||
+          (e = hipMemcpyAsync(mask_c, d->mask + (ny - cy) / 2, cy, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return dev_fail(e, "coarse mask");
+    } else {
+      if ((e = hipMalloc(&mask_c, (size_t)cy * cx)) != hipSuccess ||
+          (e = hipMemcpy2DAsync(mask_c, cx, d->mask + (size_t)((ny - cy) / 2) * nx + (nx - cx) / 2, nx, cx, cy,
+                                hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return dev_fail(e, "coarse mask");
+    }
+    c.mask = mask_c;
+  } else if (d->sampling == PICO_NONCART) {
+    if (!d->traj || d->nsamples < 1) {
+      cleanup();
+      return fail(PICO_EINVAL, "non-Cartesian sampling needs traj and nsamples >= 1");
+    }
+    std::vector<float> t((size_t)2 * d->nsamples), kept;
+    if ((e = hipMemcpyAsync(t.data(), d->traj, t.size() * sizeof(float), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return dev_fail(e, "trajectory");
+    const double lim = M_PI / factor;
+    for (int64_t m = 0; m < d->nsamples; ++m) {
+      const double wy = t[2 * m], wx = t[2 * m + 1];
+      if (wy >= -lim && wy < lim && wx >= -lim && wx < lim) {
+        kept.push_back((float)(factor * wy));
+        kept.push_back((float)(factor * wx));
+      }
+    }
+    if (kept.empty()) {
+      cleanup();
+      return fail(PICO_EINVAL, "no sample inside the coarse band");
+    }
+    if ((e = hipMalloc(&traj_c, kept.size() * sizeof(float))) != hipSuccess ||
+        (e = hipMemcpyAsync(traj_c, kept.data(), kept.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return dev_fail(e, "coarse trajectory");
+    c.traj = traj_c;
+    c.nsamples = (int64_t)kept.size() / 2;
+  }
+  const pico_status_t st = pico::init_in_arena(&c, stream, nullptr, out);
+  cleanup();
+  if (st == PICO_OK) (*out)->reduce_f = factor;
+  return st;
+}
+
+pico_status_t pico_upsample_map(pico_op_t op, const double* coarse, double* var, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (op->reduce_f < 2) return fail(PICO_EUNSUPPORTED, "pico_upsample_map needs an operator from pico_init_reduced");
+  if (!coarse || !var) return fail(PICO_EINVAL, "NULL map");
+  HIP_OR_RETURN(pico::launch_upsample_bilinear(coarse, var, op->ny, op->nx, op->reduce_f, (hipStream_t)stream));
   return PICO_OK;
 }
 

@@ -111,6 +111,10 @@ hipError_t launch_mask_weights(const uint8_t* mask, float* w, int ny, int nx, fl
 // maps rounded to bfloat16 (nearest even): packed copy in bf, and the rounded
 // values written back to maps, so every reader sees the same operator
 hipError_t launch_quantise_maps(float2* maps, uint32_t* bf, long count, hipStream_t s);
+// reduced-resolution grid: maps [nc][ny][nx] -> [nc][ny/f][nx/f] at native pixels
+// (f my, f mx); coarse map [cy][cx] -> [f cy][f cx] by periodic bilinear weights
+hipError_t launch_subsample_maps(const float2* maps, float2* out, int nc, int ny, int nx, int f, hipStream_t s);
+hipError_t launch_upsample_bilinear(const double* coarse, double* out, int cy, int cx, int f, hipStream_t s);
 hipError_t launch_power_start_rowmajor(float2* p, int n, hipStream_t s);
 hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse, const float2* twx,
                         const float2* twy, hipStream_t s);

@@ -80,6 +80,7 @@ _lib = None
 
 EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
            "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse", "pico_monitor_stderr", "pico_noise_map_adaptive", "pico_exact_diag",
+           "pico_init_reduced", "pico_upsample_map",
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
            "pico_server_submit", "pico_server_poll", "pico_server_wait_idle", "pico_server_usage",
@@ -99,6 +100,8 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     lib.pico_init.argtypes = [ctypes.POINTER(pico_op_desc_t), vp, ctypes.POINTER(vp)]
+    lib.pico_init_reduced.argtypes = [ctypes.POINTER(pico_op_desc_t), i32, vp, ctypes.POINTER(vp)]
+    lib.pico_upsample_map.argtypes = [vp, vp, vp, vp]
     lib.pico_apply_cov.argtypes = [vp, vp, vp, i32, vp]
     lib.pico_apply_jvp.argtypes = [vp, vp, vp, i32, vp]
     lib.pico_apply_nufft.argtypes = [vp, i32, vp, vp, i32, vp]
@@ -318,6 +321,23 @@ def pico_noise_map_adaptive(h, seed, first_probe, max_probes, target, dist, acc,
 
 def pico_exact_diag(h, var, stream=None):
     return _check(load().pico_exact_diag(h, _ptr(var), _stream(stream)))
+
+
+def pico_init_reduced(factor, ny, nx, maps, psi, mask, stream=None, **kw):
+    """pico_init_reduced: the coarse operator of factor ``factor`` for the
+    native problem described by the arguments of pico_init (native ny, nx,
+    maps, mask or trajectory).  Returns the handle of the coarse operator."""
+    lib = load()
+    d, keep = make_desc(ny, nx, maps, psi, mask, **kw)
+    h = ctypes.c_void_p()
+    _check(lib.pico_init_reduced(ctypes.byref(d), int(factor), _stream(stream), ctypes.byref(h)))
+    del keep
+    return h
+
+
+def pico_upsample_map(h, coarse, var, stream=None):
+    """Native map ``var`` from the coarse map of a reduced operator."""
+    return _check(load().pico_upsample_map(h, _ptr(coarse), _ptr(var), _stream(stream)))
 
 
 def pico_profile_start(h):
