@@ -79,7 +79,7 @@ struct pico_op_s {
   std::vector<float> tv_th;
   float4* tv_what = nullptr;        // [T][inner][ny][nx] projection data of the primal
   float* tv_invn = nullptr;         // [T][inner][ny][nx]
-  float2 *tv_dp = nullptr, *tv_drA = nullptr, *tv_drB = nullptr;  // [K][2][ny][nx] dual tangents
+  float2 *tv_dp = nullptr, *tv_dpB = nullptr, *tv_drA = nullptr, *tv_drB = nullptr;  // [K][2][ny][nx] dual tangents
   double cs_lam = 0.0;
   double s2 = 0.0;              // 1.01 lambda_max(M)
   std::vector<float> theta;     // FISTA momentum weights (tangents)
@@ -479,11 +479,12 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
         // TV prox tangent at the stored projection data of iteration k
         if (op->cs_lam == 0.0) return pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s);
         const size_t off = (size_t)(k - 1) * op->tv_inner * n;
-        if ((e2 = pico::tv_tangent_prox(op->wA, op->tv_drA, op->tv_drB, op->tv_dp, op->tv_what + off,
+        float2* dp = nullptr;
+        if ((e2 = pico::tv_tangent_prox(op->wA, op->tv_drA, op->tv_drB, op->tv_dp, op->tv_dpB, op->tv_what + off,
                                         op->tv_invn + off, op->ny, op->nx, K, op->tv_inner, op->tv_th.data(),
-                                        (float)op->cs_lam, s)) != hipSuccess)
+                                        (float)op->cs_lam, &dp, s)) != hipSuccess)
           return e2;
-        return pico::tv_tangent_final(op->wA, op->tv_dp, op->x, op->p, op->ny, op->nx, K, (float)op->cs_lam,
+        return pico::tv_tangent_final(op->wA, dp, op->x, op->p, op->ny, op->nx, K, (float)op->cs_lam,
                                       op->theta[k - 1], s);
       }
       if ((e2 = pico::launch_wavelet(op->wA, op->wB, K, op->ny, op->nx, op->levels, false, s)) != hipSuccess) return e2;
@@ -715,7 +716,7 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
     const bool tv = d->recon == PICO_CS_FISTA_TV;
     add(n * K * 8);
     if (tv) {
-      for (int i = 0; i < 3; ++i) add(2 * n * K * 8);
+      for (int i = 0; i < 4; ++i) add(2 * n * K * 8);
       add(n * (size_t)d->fista_iters * d->tv_inner_iters * 16);
       add(n * (size_t)d->fista_iters * d->tv_inner_iters * 4);
     } else {
@@ -912,8 +913,8 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if ((e = op->alloc(&op->wA, n * K)) != hipSuccess) return bad(e, "tangent buffer");
     if (tv) {
       const size_t steps = (size_t)op->fista_T * op->tv_inner;
-      if ((e = op->alloc(&op->tv_dp, 2 * n * K)) != hipSuccess || (e = op->alloc(&op->tv_drA, 2 * n * K)) != hipSuccess ||
-          (e = op->alloc(&op->tv_drB, 2 * n * K)) != hipSuccess)
+      if ((e = op->alloc(&op->tv_dp, 2 * n * K)) != hipSuccess || (e = op->alloc(&op->tv_dpB, 2 * n * K)) != hipSuccess ||
+          (e = op->alloc(&op->tv_drA, 2 * n * K)) != hipSuccess || (e = op->alloc(&op->tv_drB, 2 * n * K)) != hipSuccess)
         return bad(e, "TV dual tangents");
       if ((e = op->alloc(&op->tv_what, n * steps)) != hipSuccess || (e = op->alloc(&op->tv_invn, n * steps)) != hipSuccess)
         return bad(e, "TV projection data");

@@ -15,8 +15,9 @@
 // derivative data, w^ = w/|w| and 1/|w| where |w| > 1, else w^ = 0 and 1, so
 // the tangent map is dP(w) dw = (dw - w^ Re(w^H dw)) / |w| for all pixels,
 // with the inside / outside decision taken in FP64.  Tangent (FP32, K probes
-// at once): the same steps on (dz, dr, dp) with that stored dP, one fused
-// kernel per inner step (u and w of a tile from LDS, halo recomputed).
+// at once): the same steps on (dz, dr, dp) with that stored dP, two inner
+// steps per fused kernel (u and w of a tile and its halo from LDS, the halo
+// recomputed), one single-step kernel first when the count is odd.
 //
 // Dual fields are [image][2][ny][nx] (y component, then x component).
 #include "device_common.h"
@@ -225,6 +226,146 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
   }
 }
 
+// Two tangent inner steps i and i+1 in one pass over a TY x TX tile T:
+// step i on T grown by one pixel on every side (B1), then step i+1 on T.
+// Inputs on the grown boxes (LDS, coordinates of the box B2 = T grown by 2,
+// index [a][b] = pixel (y0 - 2 + a, x0 - 2 + b), periodic):
+//   r_i on B2, p_i on B1, dz on B1 grown by one towards +y / +x.
+// Step i:   u_i = dz - lam D^H r_i (B1 and its +y / +x neighbours),
+//           p_{i+1} = dP_i(r_i + c8 D u_i), r_{i+1} = p_{i+1} + th_i (p_{i+1} - p_i)   on B1;
+// step i+1: u_{i+1} on T and its +y / +x neighbours, then p_{i+2}, r_{i+2} on T.
+// r and p are read from (rA, pA) and written to (rB, pB): neighbouring tiles
+// read the halo of both.  first: r_i = p_i = 0 (step 0 from the zero start).
+// Needs ny >= TY + 4 and nx >= TX + 4 (the halo wraps at most once).
+constexpr int kBY = kTY + 4, kBX = kTX + 4;         // box B2
+constexpr int kB2 = kBY * kBX;
+
+__global__ __launch_bounds__(256) void k_tv_inner2(const float2* __restrict__ dz, const float2* __restrict__ rA,
+                                                   float2* __restrict__ rB, const float2* __restrict__ pA,
+                                                   float2* __restrict__ pB, const float4* __restrict__ what0,
+                                                   const float* __restrict__ invn0, const float4* __restrict__ what1,
+                                                   const float* __restrict__ invn1, int ny, int nx, int K, int kper,
+                                                   float lam, float c8, float th0, float th1, int first) {
+  __shared__ float2 sRy[kBY][kBX], sRx[kBY][kBX];   // r_i, then r_{i+1} (in place)
+  __shared__ float2 sPy[kBY][kBX], sPx[kBY][kBX];   // p_i, then p_{i+1} (in place)
+  __shared__ float2 sZ[kBY][kBX];                   // dz
+  __shared__ float2 sU[kBY][kBX];                   // u_i, then u_{i+1}
+  __shared__ float4 sW[kBY][kBX];                   // projection data of step i (w^)
+  __shared__ float sV[kBY][kBX];                    // and 1/|w|
+  const long n = (long)ny * nx;
+  const int tilesx = (nx + kTX - 1) / kTX;
+  const int y0 = (int)(blockIdx.x / tilesx) * kTY, x0 = (int)(blockIdx.x % tilesx) * kTX;
+  const int t = threadIdx.x;
+  const bool fst = first != 0;
+  auto gidx = [&](int a, int b) { return (long)wrap(y0 - 2 + a, ny) * nx + wrap(x0 - 2 + b, nx); };
+  // projection data of step i on B1 (box rows / cols 1 .. TY+2 / TX+2), shared by all tangents
+  for (int e = t; e < kB2; e += 256) {
+    const int a = e / kBX, b = e - a * kBX;
+    if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
+      const long g = gidx(a, b);
+      sW[a][b] = what0[g];
+      sV[a][b] = invn0[g];
+    }
+  }
+  // own pixel: step i+1's projection data
+  const int ty = t / kTX, tx = t % kTX;
+  const int y = y0 + ty, x = x0 + tx;
+  const bool own = y < ny && x < nx;
+  const long i = (long)y * nx + x;
+  float4 wh1 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float iv1 = 1.f;
+  if (own) {
+    wh1 = what1[i];
+    iv1 = invn1[i];
+  }
+  const int k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
+  for (int k = k0; k < k1; ++k) {
+    const float2* zk = dz + (size_t)k * n;
+    const float2* ry = rA + (size_t)k * 2 * n;
+    const float2* py = pA + (size_t)k * 2 * n;
+    const float2 zero = make_float2(0.f, 0.f);
+    // phase A: loads
+    for (int e = t; e < kB2; e += 256) {
+      const int a = e / kBX, b = e - a * kBX;
+      const long g = gidx(a, b);
+      float2 vy = zero, vx = zero, qy = zero, qx = zero, z = zero;
+      if (!fst) {
+        vy = ry[g];
+        vx = ry[n + g];
+        if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
+          qy = py[g];
+          qx = py[n + g];
+        }
+      }
+      if (a >= 1 && b >= 1) z = zk[g];
+      sRy[a][b] = vy;
+      sRx[a][b] = vx;
+      sPy[a][b] = qy;
+      sPx[a][b] = qx;
+      sZ[a][b] = z;
+    }
+    __syncthreads();
+    // phase B: u_i on rows / cols 1 .. TY+3 / TX+3
+    for (int e = t; e < kB2; e += 256) {
+      const int a = e / kBX, b = e - a * kBX;
+      if (a >= 1 && b >= 1) {
+        const float hx = sRy[a - 1][b].x - sRy[a][b].x + sRx[a][b - 1].x - sRx[a][b].x;
+        const float hy = sRy[a - 1][b].y - sRy[a][b].y + sRx[a][b - 1].y - sRx[a][b].y;
+        sU[a][b] = make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
+      }
+    }
+    __syncthreads();
+    // phase C: step i on B1; r and p replaced in place (each point reads only itself)
+    for (int e = t; e < kB2; e += 256) {
+      const int a = e / kBX, b = e - a * kBX;
+      if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
+        const float2 u0 = sU[a][b], uy = sU[a + 1][b], ux = sU[a][b + 1];
+        const float2 wy = make_float2(fmaf(c8, uy.x - u0.x, sRy[a][b].x), fmaf(c8, uy.y - u0.y, sRy[a][b].y));
+        const float2 wx = make_float2(fmaf(c8, ux.x - u0.x, sRx[a][b].x), fmaf(c8, ux.y - u0.y, sRx[a][b].y));
+        const float4 wh = sW[a][b];
+        const float iv = sV[a][b];
+        const float re = wh.x * wy.x + wh.y * wy.y + wh.z * wx.x + wh.w * wx.y;
+        const float2 qy = make_float2((wy.x - wh.x * re) * iv, (wy.y - wh.y * re) * iv);
+        const float2 qx = make_float2((wx.x - wh.z * re) * iv, (wx.y - wh.w * re) * iv);
+        const float2 oy = sPy[a][b], ox = sPx[a][b];
+        sRy[a][b] = make_float2(fmaf(th0, qy.x - oy.x, qy.x), fmaf(th0, qy.y - oy.y, qy.y));
+        sRx[a][b] = make_float2(fmaf(th0, qx.x - ox.x, qx.x), fmaf(th0, qx.y - ox.y, qx.y));
+        sPy[a][b] = qy;
+        sPx[a][b] = qx;
+      }
+    }
+    __syncthreads();
+    // phase D: u_{i+1} on rows / cols 2 .. TY+2 / TX+2 (T and its +y / +x neighbours)
+    for (int e = t; e < kB2; e += 256) {
+      const int a = e / kBX, b = e - a * kBX;
+      if (a >= 2 && a <= kTY + 2 && b >= 2 && b <= kTX + 2) {
+        const float hx = sRy[a - 1][b].x - sRy[a][b].x + sRx[a][b - 1].x - sRx[a][b].x;
+        const float hy = sRy[a - 1][b].y - sRy[a][b].y + sRx[a][b - 1].y - sRx[a][b].y;
+        sU[a][b] = make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
+      }
+    }
+    __syncthreads();
+    // phase E: step i+1 on T, written out
+    if (own) {
+      const int a = ty + 2, b = tx + 2;
+      const float2 u0 = sU[a][b], uy = sU[a + 1][b], ux = sU[a][b + 1];
+      const float2 wy = make_float2(fmaf(c8, uy.x - u0.x, sRy[a][b].x), fmaf(c8, uy.y - u0.y, sRy[a][b].y));
+      const float2 wx = make_float2(fmaf(c8, ux.x - u0.x, sRx[a][b].x), fmaf(c8, ux.y - u0.y, sRx[a][b].y));
+      const float re = wh1.x * wy.x + wh1.y * wy.y + wh1.z * wx.x + wh1.w * wx.y;
+      const float2 qy = make_float2((wy.x - wh1.x * re) * iv1, (wy.y - wh1.y * re) * iv1);
+      const float2 qx = make_float2((wx.x - wh1.z * re) * iv1, (wx.y - wh1.w * re) * iv1);
+      const float2 oy = sPy[a][b], ox = sPx[a][b];
+      float2* rb = rB + (size_t)k * 2 * n;
+      float2* pb = pB + (size_t)k * 2 * n;
+      rb[i] = make_float2(fmaf(th1, qy.x - oy.x, qy.x), fmaf(th1, qy.y - oy.y, qy.y));
+      rb[n + i] = make_float2(fmaf(th1, qx.x - ox.x, qx.x), fmaf(th1, qx.y - ox.y, qx.y));
+      pb[i] = qy;
+      pb[n + i] = qx;
+    }
+    __syncthreads();
+  }
+}
+
 // dx = dz - lam D^H dp; y = dx + theta (dx - xo); xo = dx   (K images)
 __global__ void k_tv_final(const float2* __restrict__ dz, const float2* __restrict__ dp, float2* __restrict__ xo,
                            float2* __restrict__ yo, int ny, int nx, float lam, float theta) {
@@ -265,21 +406,31 @@ hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what,
   return hipGetLastError();
 }
 
-hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dp, const float4* what,
-                           const float* invn, int ny, int nx, int K, int inner, const float* th, float lam,
-                           hipStream_t s) {
-  if (ny < kTY + 2 || nx < kTX + 2) return hipErrorInvalidValue;
+hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
+                           const float4* what, const float* invn, int ny, int nx, int K, int inner,
+                           const float* th, float lam, float2** dp_out, hipStream_t s) {
+  if (ny < kTY + 4 || nx < kTX + 4) return hipErrorInvalidValue;
   const long n = (long)ny * nx;
   const int tiles = ((ny + kTY - 1) / kTY) * ((nx + kTX - 1) / kTX);
   int kper = 8;
   while (kper > 1 && (long)tiles * ((K + kper - 1) / kper) < 2048) kper >>= 1;
   const dim3 grid((unsigned)tiles, (unsigned)((K + kper - 1) / kper));
   const float c8 = 1.0f / (8.0f * lam);
-  for (int it = 0; it < inner; ++it) {
-    hipLaunchKernelGGL(k_tv_inner, grid, dim3(256), 0, s, dz, drA, drB, dp, what + (size_t)it * n,
-                       invn + (size_t)it * n, ny, nx, K, kper, lam, c8, th[it], it == 0 ? 1 : 0);
+  int it = 0;
+  if (inner & 1) {   // an odd count starts with one single step (dp updated in place)
+    hipLaunchKernelGGL(k_tv_inner, grid, dim3(256), 0, s, dz, drA, drB, dpA, what, invn, ny, nx, K, kper, lam, c8,
+                       th[0], 1);
     std::swap(drA, drB);
+    it = 1;
   }
+  for (; it < inner; it += 2) {
+    hipLaunchKernelGGL(k_tv_inner2, grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what + (size_t)it * n,
+                       invn + (size_t)it * n, what + (size_t)(it + 1) * n, invn + (size_t)(it + 1) * n, ny, nx, K,
+                       kper, lam, c8, th[it], th[it + 1], it == 0 ? 1 : 0);
+    std::swap(drA, drB);
+    std::swap(dpA, dpB);
+  }
+  *dp_out = dpA;
   return hipGetLastError();
 }
 

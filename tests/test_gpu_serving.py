@@ -32,7 +32,9 @@ def _dev(a):
 
 
 def _requests():
-    """Four small requests of the four operator kinds (kwargs of pico_init)."""
+    """Small requests of every operator kind (kwargs of pico_init): phase-encode,
+    2-D Cartesian, spiral with gridding, L1 and TV compressed sensing, and
+    bfloat16 storage."""
     out = []
     rng = np.random.default_rng(21)
     maps = workloads.coil_maps(64, 64, 4, rng)
@@ -62,6 +64,15 @@ def _requests():
         ny=64, nx=64, maps=_dev(maps.astype(np.complex64)), psi=psi, mask=_dev(mask), sampling=1,
         recon=1, kdata=_dev(braw), fista_iters=20, cs_lambda=1e-3, wavelet_levels=3,
         probe_tile=4), 10))
+    out.append(("TV-CS 64x64 3 coils", dict(
+        ny=64, nx=64, maps=_dev(maps.astype(np.complex64)), psi=psi, mask=_dev(mask), sampling=1,
+        recon=2, kdata=_dev(braw), fista_iters=12, cs_lambda=1e-2, tv_inner_iters=4,
+        probe_tile=3), 7))
+    maps = workloads.coil_maps(96, 64, 4, rng)
+    out.append(("cart2d 96x64 4 coils, bfloat16 maps and planes", dict(
+        ny=96, nx=64, maps=_dev(maps.astype(np.complex64)), psi=workloads.noise_cov(4, rng),
+        mask=_dev(workloads.poisson_disc_mask(96, 64, 2.0, 8, seed=7)), sampling=1, cg_iters=12,
+        probe_tile=4, storage=2), 9))
     return out
 
 
