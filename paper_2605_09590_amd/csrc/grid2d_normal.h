@@ -224,8 +224,15 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
   float2* tile = dyn;                                  // [ny][TS]
   float2* xch = dyn + (size_t)a.ny * TS;               // NG exchange regions
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
-  const int x0 = blockIdx.x * NGRP;
-  const size_t plane = (size_t)blockIdx.y * a.ny * a.Gx;
+  // Workgroups go to the eight XCDs in turn; workgroup b takes the strip at
+  // v = (b mod 8) * ceil(W / 8) + b / 8 of the order (plane, strip), so each
+  // XCD runs a contiguous run of strips and the cache lines that adjacent
+  // strips share stay in one L2
+  const long S = (a.Gx + NGRP - 1) / NGRP, W = S * (long)a.K * a.nc, per = (W + 7) / 8;
+  const long vb = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (vb >= W) return;
+  const int x0 = (int)(vb % S) * NGRP;
+  const size_t plane = (size_t)(vb / S) * a.ny * a.Gx;
   const int ncol = min(NGRP, a.Gx - x0);
   if constexpr (TB) strip_load(tile, a.Tb + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
   else strip_load(tile, a.T + plane + x0, a.ny, NGRP, TS, ncol, a.Gx);
@@ -434,7 +441,8 @@ static hipError_t cols(const Grid2dArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  dim3 grid((a.Gx + NGRP - 1) / NGRP, (unsigned)((long)a.K * a.nc)), block(256);
+  const long W = (long)((a.Gx + NGRP - 1) / NGRP) * a.K * a.nc;
+  dim3 grid((unsigned)(8 * ((W + 7) / 8))), block(256);
   hipLaunchKernelGGL((k_cols<CF, TB>), grid, block, lds, s, a);
   return hipGetLastError();
 }
