@@ -32,7 +32,6 @@ namespace pico {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kTile = 32;            // probes per workgroup
-constexpr int kPad = kTile + 1;      // LDS row stride of the p tile (float2)
 
 // G[x][j][i] = conj(M_x[i][j]), FP64 sums rounded once to FP32
 __global__ void k_build_gram(const float2* __restrict__ maps, const double2* __restrict__ cvec,
@@ -59,10 +58,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(1024) void k_cart1d_gram(Cart1dArgs a, const float2* __restrict__ G) {
-  extern __shared__ float2 pt[];                   // [ny][kPad] p tile, then q tile
-  __shared__ double red[16][2][kTile][2];          // [wave][half][probe] (d1, d2)
+// Element (row, probe) of the p / q tile: rows of 32 float2 (256 B), the
+// probe index XOR-swizzled by the row so that both the column writes of the
+// prologue and the row reads of the matrix loop spread over the LDS banks.
+__device__ __forceinline__ int tile_at(int row, int j) { return row * kTile + (j ^ (row & 31)); }
+
+// SMALL: ny <= 320 (at most 10 waves, an 80 KB tile): registers kept within
+// six waves per SIMD so that two workgroups share a CU and one's memory
+// phases overlap the other's matrix loop.
+template <int MODE, bool SMALL>
+__global__ __launch_bounds__(SMALL ? 640 : 1024, SMALL ? 6 : 1) void k_cart1d_gram(Cart1dArgs a,
+                                                                                  const float2* __restrict__ G) {
+  extern __shared__ float2 pt[];                   // [ny][32] p tile, then q tile, then reduction
   const int ny = a.ny, nw = ny / 32;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   // workgroups of one column stay on one XCD (blocks are dealt to the 8 XCDs
@@ -111,7 +118,7 @@ __global__ __launch_bounds__(1024) void k_cart1d_gram(Cart1dArgs a, const float2
         }
       }
       d0 += (double)rv.x * rv.x + (double)rv.y * rv.y;
-      pt[y * kPad + j] = pv;
+      pt[tile_at(y, j)] = pv;
     }
     d0 = wave_sum(d0);
     if (active && lane == 0) a.part[((size_t)k * a.nx + col) * 4] = d0;
@@ -127,7 +134,7 @@ __global__ __launch_bounds__(1024) void k_cart1d_gram(Cart1dArgs a, const float2
     accR[v] = 0.f;
     accI[v] = 0.f;
   }
-  constexpr int U = 8;
+  constexpr int U = SMALL ? 4 : 8;
   float2 mA[U], mB[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) mA[u] = Gc[(size_t)u * ny];
@@ -136,8 +143,8 @@ __global__ __launch_bounds__(1024) void k_cart1d_gram(Cart1dArgs a, const float2
     for (int u = 0; u < U; ++u) mB[u] = Gc[(size_t)(c + U + u) * ny];   // ny is a multiple of 32
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const float2 m = mA[u];                      // conj(M[i][j]), j = c + u
-      const float2 pp = pt[(c + u) * kPad + li];   // p[j][probe li]
+      const float2 m = mA[u];                           // conj(M[i][j]), j = c + u
+      const float2 pp = pt[tile_at(c + u, li)];         // p[j][probe li]
       const float bv = kk ? pp.y : pp.x;
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(kk ? m.y : m.x, bv, accR, 0, 0, 0);
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(kk ? m.x : -m.y, bv, accI, 0, 0, 0);
@@ -149,33 +156,28 @@ __global__ __launch_bounds__(1024) void k_cart1d_gram(Cart1dArgs a, const float2
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const float2 m = mB[u];
-      const float2 pp = pt[(c + U + u) * kPad + li];
+      const float2 pp = pt[tile_at(c + U + u, li)];
       const float bv = kk ? pp.y : pp.x;
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(kk ? m.y : m.x, bv, accR, 0, 0, 0);
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(kk ? m.x : -m.y, bv, accI, 0, 0, 0);
     }
   }
+  __syncthreads();   // every wave is done reading the p tile
 
-  // ---- q = acc + lam p; (Re p^H q, |q|^2) per probe; q replaces p in LDS
-  float2 qv[16];
+  // ---- q = acc + lam p on the wave's own rows, (Re p^H q, |q|^2) partials;
+  // q replaces p row by row (only this wave touches these rows now)
   double d1 = 0.0, d2 = 0.0;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int row = 32 * w + 8 * (v / 4) + 4 * kk + (v % 4);
-    const float2 p = pt[row * kPad + li];
+    const float2 p = pt[tile_at(row, li)];
     const float2 q = make_float2(fmaf(a.lam, p.x, accR[v]), fmaf(a.lam, p.y, accI[v]));
-    qv[v] = q;
     d1 += (double)p.x * q.x + (double)p.y * q.y;
     d2 += (double)q.x * q.x + (double)q.y * q.y;
+    pt[tile_at(row, li)] = q;
   }
-  red[w][kk][li][0] = d1;
-  red[w][kk][li][1] = d2;
-  __syncthreads();   // every wave is done with the p tile
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int row = 32 * w + 8 * (v / 4) + 4 * kk + (v % 4);
-    pt[row * kPad + li] = qv[v];
-  }
+  d1 += __shfl_xor(d1, 32, 64);   // both halves of the wave hold probe li
+  d2 += __shfl_xor(d2, 32, 64);
   __syncthreads();
 
   // ---- epilogue: store q and the Re r^H q partial (|r|^2 went out with the prologue)
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(1024) void k_cart1d_gram(Cart1dArgs a, const float2
     const size_t base = ((size_t)k * a.nx + col) * ny;
     double d3 = 0.0;
     for (int y = lane; y < ny; y += 64) {
-      const float2 q = pt[y * kPad + j];
+      const float2 q = pt[tile_at(y, j)];
       a.q[base + y] = q;
       if constexpr (MODE != C1_APPLY) {
         const float2 r = a.r[base + y];
@@ -193,17 +195,27 @@ __global__ __launch_bounds__(1024) void k_cart1d_gram(Cart1dArgs a, const float2
       }
     }
     d3 = wave_sum(d3);
-    if (lane == 0) {
+    if (lane == 0) a.part[((size_t)k * a.nx + col) * 4 + 3] = d3;
+  }
+  __syncthreads();   // the q tile is consumed: its space takes the per-wave partials
+
+  double* red = reinterpret_cast<double*>(pt);     // [nw][32][2]
+  if (kk == 0) {
+    red[(w * kTile + li) * 2] = d1;
+    red[(w * kTile + li) * 2 + 1] = d2;
+  }
+  __syncthreads();
+  if (lane < kTile && w == 0) {
+    const int k = k0 + lane;
+    if (k < a.K) {
       double s1 = 0.0, s2 = 0.0;
-      for (int ww = 0; ww < nw; ++ww)
-        for (int h = 0; h < 2; ++h) {
-          s1 += red[ww][h][j][0];
-          s2 += red[ww][h][j][1];
-        }
+      for (int ww = 0; ww < nw; ++ww) {
+        s1 += red[(ww * kTile + lane) * 2];
+        s2 += red[(ww * kTile + lane) * 2 + 1];
+      }
       double* pp = a.part + ((size_t)k * a.nx + col) * 4;
       pp[1] = s1;
       pp[2] = s2;
-      pp[3] = d3;
     }
   }
 }
@@ -235,16 +247,16 @@ hipError_t build_gram(const float2* maps, const float* maskw_h, int nc, int ny, 
   return hipStreamSynchronize(s);   // cv leaves scope
 }
 
-hipError_t launch_cart1d_gram(int mode, const Cart1dArgs& a, const float2* G, hipStream_t s) {
-  if (!gram_supported(a.ny)) return hipErrorInvalidValue;
+template <bool SMALL>
+static hipError_t launch_gram(int mode, const Cart1dArgs& a, const float2* G, hipStream_t s) {
   const int nw = a.ny / 32;
-  const size_t lds = (size_t)a.ny * kPad * sizeof(float2);
+  const size_t lds = (size_t)a.ny * kTile * sizeof(float2);
   static bool attr_set[4] = {false, false, false, false};
-  const void* fn[4] = {(const void*)k_cart1d_gram<C1_FIRST_PROBE>, (const void*)k_cart1d_gram<C1_FIRST_BUF>,
-                       (const void*)k_cart1d_gram<C1_ITER>, (const void*)k_cart1d_gram<C1_APPLY>};
+  const void* fn[4] = {(const void*)k_cart1d_gram<C1_FIRST_PROBE, SMALL>, (const void*)k_cart1d_gram<C1_FIRST_BUF, SMALL>,
+                       (const void*)k_cart1d_gram<C1_ITER, SMALL>, (const void*)k_cart1d_gram<C1_APPLY, SMALL>};
   if (mode < 0 || mode > 3) return hipErrorInvalidValue;
   if (!attr_set[mode]) {
-    hipError_t e = hipFuncSetAttribute(fn[mode], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 16384);
+    hipError_t e = hipFuncSetAttribute(fn[mode], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set[mode] = true;
   }
@@ -252,12 +264,18 @@ hipError_t launch_cart1d_gram(int mode, const Cart1dArgs& a, const float2* G, hi
   const int cgroups = (a.nx + 7) / 8;
   dim3 grid((unsigned)(8 * ntiles * cgroups)), block(64 * nw);
   switch (mode) {
-    case C1_FIRST_PROBE: hipLaunchKernelGGL(k_cart1d_gram<C1_FIRST_PROBE>, grid, block, lds, s, a, G); break;
-    case C1_FIRST_BUF: hipLaunchKernelGGL(k_cart1d_gram<C1_FIRST_BUF>, grid, block, lds, s, a, G); break;
-    case C1_ITER: hipLaunchKernelGGL(k_cart1d_gram<C1_ITER>, grid, block, lds, s, a, G); break;
-    default: hipLaunchKernelGGL(k_cart1d_gram<C1_APPLY>, grid, block, lds, s, a, G); break;
+    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_cart1d_gram<C1_FIRST_PROBE, SMALL>), grid, block, lds, s, a, G); break;
+    case C1_FIRST_BUF: hipLaunchKernelGGL((k_cart1d_gram<C1_FIRST_BUF, SMALL>), grid, block, lds, s, a, G); break;
+    case C1_ITER: hipLaunchKernelGGL((k_cart1d_gram<C1_ITER, SMALL>), grid, block, lds, s, a, G); break;
+    default: hipLaunchKernelGGL((k_cart1d_gram<C1_APPLY, SMALL>), grid, block, lds, s, a, G); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_cart1d_gram(int mode, const Cart1dArgs& a, const float2* G, hipStream_t s) {
+  if (!gram_supported(a.ny)) return hipErrorInvalidValue;
+  if (a.ny <= 320) return launch_gram<true>(mode, a, G, s);
+  return launch_gram<false>(mode, a, G, s);
 }
 
 }  // namespace pico
