@@ -278,6 +278,37 @@ def plain_leg(torch, np, dev, prob, ref, max_probes=1024, check=None):
     return res
 
 
+def dense_leg(lib, torch, np, dev, prob, steps=3):
+    """The main workload with the dense per-column normal operator on the FP32
+    matrix cores (normal_form 2): throughput and the matrix-core roofline of
+    its CG-iteration kernel (8 ny^2 flops per probe and column)."""
+    ny, nx, K = prob.ny, prob.nx, 256
+    maps = torch.from_numpy(prob.maps.astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    h = lib.pico_init(ny, nx, maps, prob.psi, mask, cg_iters=prob.cg_iters, probe_tile=K, normal_form=2)
+    acc = lib.make_accum(*[torch.zeros(ny * nx, dtype=torch.float64, device=dev) for _ in range(2)])
+    lib.pico_noise_map(h, 3, 0, K, 0, acc)
+    torch.cuda.synchronize()
+    lib.pico_profile_start(h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        lib.pico_noise_map(h, 3, K * (i + 1), K, 0, acc)
+    e1.record()
+    torch.cuda.synchronize()
+    prof = lib.pico_profile_stop(h)
+    lib.pico_destroy(h)
+    it_ms, it_n = prof["normal_iter"]
+    avg_s = it_ms / it_n / 1e3
+    flops = 8.0 * ny * ny * K * nx
+    return {"form": "dense per-column blocks on the FP32 matrix cores (normal_form 2)",
+            "probe_solves_per_s": round(steps * K / (e0.elapsed_time(e1) / 1e3), 2),
+            "roofline": {"bound": "mfma", "achieved": round(flops / avg_s / 1e12, 2), "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(flops / avg_s / 1e12 / PEAK_FP32_TFLOPS, 4),
+                         "kernel": "k_cart1d_gram<C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
+                         "flops_per_launch": flops}}
+
+
 def reduced_leg(lib, torch, np, dev, prob, ref, factor=2, max_probes=1024):
     """Reduced-resolution grid (Sec. 5, Discussion) on the main workload: the
     coarse operator of the same acquisition, its map upsampled to the native
@@ -556,6 +587,8 @@ def main():
                     help="serving leg: short request mix (default), the full sweep, or off")
     ap.add_argument("--cs-robustness", choices=["off", "l1wav", "tv"], default="off",
                     help="also run the CS noise-level sweep (PICO vs PMR std maps) for that model")
+    ap.add_argument("--no-dense", dest="dense", action="store_false",
+                    help="skip the dense (matrix-core) form of the main workload")
     ap.add_argument("--no-plain", dest="plain", action="store_false",
                     help="skip the plain FP32 per-probe comparison form")
     ap.add_argument("--copy-calib", action="store_true",
@@ -729,6 +762,9 @@ def main():
         "hbm_GBs_alg": round(bytes_alg / avg_s / 1e9, 1),
     }
 
+    # --- the same workload with the dense per-column operator on the matrix cores
+    dense = dense_leg(lib, torch, np, dev, prob) if args.dense else None
+
     # --- second workload: spiral CG-SENSE, Toeplitz normal operator (HBM-bound path),
     # complex64 planes and the bfloat16-stream variant
     spiral = spiral_bf16 = None
@@ -784,6 +820,7 @@ def main():
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
         "kernel_launches": {k: v[1] for k, v in prof.items()},
         "roofline": roofline, "cpu_baseline": cpu,
+        "dense_form": dense,
         "spiral": spiral,
         "spiral_bf16": spiral_bf16,
         "cs": cs_res,
