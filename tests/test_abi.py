@@ -91,3 +91,37 @@ def test_null_handles(lib):
     lib.pico_destroy(None)
     import math
     assert math.isnan(lib.pico_lambda_abs(None))
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the size and field offsets the C compiler gives
+    the structs of include/pico.h (a mismatch would misread fields silently)."""
+    import shutil
+    import subprocess
+    from paper_2605_09590_amd import pico as p
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"pico_op_desc_t": p.pico_op_desc_t, "pico_accum_t": p.pico_accum_t,
+               "pico_stats_t": p.pico_stats_t, "pico_request_info_t": p.pico_request_info_t}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "pico.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, what, val = line.split()
+        py = structs[cname]
+        if what == "size":
+            assert ctypes.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, what).offset == int(val), (cname, what)
