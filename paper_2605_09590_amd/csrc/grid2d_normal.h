@@ -147,16 +147,26 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
 
   float2* __restrict__ T = a.T;
   uint32_t* __restrict__ Tb = a.Tb;
-  for (int c = 0; c < a.nc; ++c) {
+  // the map row of coil c + 1 is loaded while coil c is transformed
+  float2 svn[CF::VMAX];
+  auto load_maps = [&](int c) {
     const size_t moff = ((size_t)c * a.ny + y) * a.nx;
+#pragma unroll
+    for (int m = 0; m < VA; ++m) {
+      const int xx = CF::posA(lane, m);
+      svn[m] = map_at<ST>(a, moff + ((inA && xx < a.nx) ? xx : 0));
+    }
+  };
+  load_maps(0);
+  for (int c = 0; c < a.nc; ++c) {
     float2 v[CF::VMAX];
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
       const int xx = CF::posA(lane, m);
       const bool ok = inA && xx < a.nx;
-      const float2 sv = map_at<ST>(a, moff + (ok ? xx : 0));
-      v[m] = ok ? cmul(sv, pv[m]) : make_float2(0.f, 0.f);
+      v[m] = ok ? cmul(svn[m], pv[m]) : make_float2(0.f, 0.f);
     }
+    if (c + 1 < a.nc) load_maps(c + 1);
     CF::template forward<false>(v, lds, lane, tw);
     if (active && inB) {
       const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
@@ -311,16 +321,24 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
 #pragma unroll
     for (int m = 0; m < VA; ++m) qa[m] = make_float2(0.f, 0.f);
   }
-  for (int c = 0; c < a.nc; ++c) {
-    float2 v[CF::VMAX];
+  // the transformed row of coil c + 1 is loaded while coil c is inverted
+  float2 tn[CF::VMAX];
+  auto load_row = [&](int c) {
     const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
     if constexpr (ST == 2) {
 #pragma unroll
-      for (int r = 0; r < VB; ++r) v[r] = inB ? unpack_bf16x2(a.Tb[off + CF::posB(lane, r)]) : make_float2(0.f, 0.f);
+      for (int r = 0; r < VB; ++r) tn[r] = inB ? unpack_bf16x2(a.Tb[off + CF::posB(lane, r)]) : make_float2(0.f, 0.f);
     } else {
 #pragma unroll
-      for (int r = 0; r < VB; ++r) v[r] = inB ? T[off + CF::posB(lane, r)] : make_float2(0.f, 0.f);
+      for (int r = 0; r < VB; ++r) tn[r] = inB ? T[off + CF::posB(lane, r)] : make_float2(0.f, 0.f);
     }
+  };
+  load_row(0);
+  for (int c = 0; c < a.nc; ++c) {
+    float2 v[CF::VMAX];
+#pragma unroll
+    for (int r = 0; r < VB; ++r) v[r] = tn[r];
+    if (c + 1 < a.nc) load_row(c + 1);
     CF::template inverse<true>(v, lds, lane, tw);
     const size_t moff = ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
