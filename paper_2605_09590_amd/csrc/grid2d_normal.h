@@ -26,16 +26,25 @@
 //            partial dots of the CG step.
 #pragma once
 
+#include <type_traits>
+
 #include "fft.h"
 #include "runtime.h"
 
 namespace pico {
-// Coil map value i: complex64, or (ST >= 1) a packed bfloat16 pair
+// Coil map value i as stored (complex64, or for ST >= 1 a packed bfloat16
+// pair) and widened; prefetched values stay in storage form until use, so
+// the loads are not waited on at the point of issue
+template <int ST> using MapElem = std::conditional_t<(ST >= 1), uint32_t, float2>;
 template <int ST>
-__device__ __forceinline__ float2 map_at(const Grid2dArgs& a, size_t i) {
-  if constexpr (ST >= 1) return unpack_bf16x2(a.maps_bf[i]);
+__device__ __forceinline__ MapElem<ST> map_raw(const Grid2dArgs& a, size_t i) {
+  if constexpr (ST >= 1) return a.maps_bf[i];
   else return a.maps[i];
 }
+__device__ __forceinline__ float2 widen(float2 v) { return v; }
+__device__ __forceinline__ float2 widen(uint32_t v) { return unpack_bf16x2(v); }
+template <int ST>
+__device__ __forceinline__ float2 map_at(const Grid2dArgs& a, size_t i) { return widen(map_raw<ST>(a, i)); }
 
 
 template <int L>
@@ -147,26 +156,40 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
 
   float2* __restrict__ T = a.T;
   uint32_t* __restrict__ Tb = a.Tb;
-  // the map row of coil c + 1 is loaded while coil c is transformed
-  float2 svn[CF::VMAX];
+  // Rows of 384 points and more: the map row of coil c + 1 is loaded while
+  // coil c is transformed (measured: 512-point spiral rows 6.63 -> 5.53 ms per
+  // application; for 320-point rows it only costs a wave per SIMD)
+  constexpr bool PF = CF::N >= 384;
+  MapElem<ST> svn[CF::VMAX];
   auto load_maps = [&](int c) {
     const size_t moff = ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
       const int xx = CF::posA(lane, m);
-      svn[m] = map_at<ST>(a, moff + ((inA && xx < a.nx) ? xx : 0));
+      svn[m] = map_raw<ST>(a, moff + ((inA && xx < a.nx) ? xx : 0));
     }
   };
-  load_maps(0);
+  if constexpr (PF) load_maps(0);
   for (int c = 0; c < a.nc; ++c) {
     float2 v[CF::VMAX];
+    if constexpr (PF) {
 #pragma unroll
-    for (int m = 0; m < VA; ++m) {
-      const int xx = CF::posA(lane, m);
-      const bool ok = inA && xx < a.nx;
-      v[m] = ok ? cmul(svn[m], pv[m]) : make_float2(0.f, 0.f);
+      for (int m = 0; m < VA; ++m) {
+        const int xx = CF::posA(lane, m);
+        const bool ok = inA && xx < a.nx;
+        v[m] = ok ? cmul(widen(svn[m]), pv[m]) : make_float2(0.f, 0.f);
+      }
+      if (c + 1 < a.nc) load_maps(c + 1);
+    } else {
+      const size_t moff = ((size_t)c * a.ny + y) * a.nx;
+#pragma unroll
+      for (int m = 0; m < VA; ++m) {
+        const int xx = CF::posA(lane, m);
+        const bool ok = inA && xx < a.nx;
+        const float2 sv = map_at<ST>(a, moff + (ok ? xx : 0));
+        v[m] = ok ? cmul(sv, pv[m]) : make_float2(0.f, 0.f);
+      }
     }
-    if (c + 1 < a.nc) load_maps(c + 1);
     CF::template forward<false>(v, lds, lane, tw);
     if (active && inB) {
       const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
@@ -185,8 +208,6 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
 // Strip of `ncol` (<= ngrp) adjacent columns of one plane to / from an LDS tile
 // [rows][ts].  Loads go out in batches of 8 per thread before any is consumed,
 // so a workgroup keeps 8 x 256 loads in flight instead of one per thread.
-__device__ __forceinline__ float2 widen(float2 v) { return v; }
-__device__ __forceinline__ float2 widen(uint32_t v) { return unpack_bf16x2(v); }
 __device__ __forceinline__ void narrow(float2& d, float2 v) { d = v; }
 __device__ __forceinline__ void narrow(uint32_t& d, float2 v) { d = pack_bf16x2(v); }
 
@@ -321,24 +342,37 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
 #pragma unroll
     for (int m = 0; m < VA; ++m) qa[m] = make_float2(0.f, 0.f);
   }
-  // the transformed row of coil c + 1 is loaded while coil c is inverted
-  float2 tn[CF::VMAX];
+  // rows of 384 points and more: the transformed row of coil c + 1 is loaded
+  // while coil c is inverted (raw storage form, unconditional loads from
+  // in-row addresses; lanes outside layout B get zeros at use)
+  constexpr bool PF = CF::N >= 384;
+  std::conditional_t<ST == 2, uint32_t, float2> tn[CF::VMAX];
   auto load_row = [&](int c) {
     const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
-    if constexpr (ST == 2) {
 #pragma unroll
-      for (int r = 0; r < VB; ++r) tn[r] = inB ? unpack_bf16x2(a.Tb[off + CF::posB(lane, r)]) : make_float2(0.f, 0.f);
-    } else {
-#pragma unroll
-      for (int r = 0; r < VB; ++r) tn[r] = inB ? T[off + CF::posB(lane, r)] : make_float2(0.f, 0.f);
+    for (int r = 0; r < VB; ++r) {
+      const size_t j = off + (inB ? CF::posB(lane, r) : 0);
+      if constexpr (ST == 2) tn[r] = a.Tb[j];
+      else tn[r] = T[j];
     }
   };
-  load_row(0);
+  if constexpr (PF) load_row(0);
   for (int c = 0; c < a.nc; ++c) {
     float2 v[CF::VMAX];
+    if constexpr (PF) {
 #pragma unroll
-    for (int r = 0; r < VB; ++r) v[r] = tn[r];
-    if (c + 1 < a.nc) load_row(c + 1);
+      for (int r = 0; r < VB; ++r) v[r] = inB ? widen(tn[r]) : make_float2(0.f, 0.f);
+      if (c + 1 < a.nc) load_row(c + 1);
+    } else {
+      const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
+      if constexpr (ST == 2) {
+#pragma unroll
+        for (int r = 0; r < VB; ++r) v[r] = inB ? unpack_bf16x2(a.Tb[off + CF::posB(lane, r)]) : make_float2(0.f, 0.f);
+      } else {
+#pragma unroll
+        for (int r = 0; r < VB; ++r) v[r] = inB ? T[off + CF::posB(lane, r)] : make_float2(0.f, 0.f);
+      }
+    }
     CF::template inverse<true>(v, lds, lane, tw);
     const size_t moff = ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
