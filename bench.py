@@ -414,6 +414,76 @@ def spiral_leg(lib, workloads, torch, np, dev, steps, storage):
     }
 
 
+def spiral_ttt_leg(lib, workloads, torch, np, dev, n_ref=16384, chunk=64, max_n=16384):
+    """Time to a 1 % std map on the spiral workload, the paper's non-Cartesian
+    comparison (Sec. 3.2.2; its appendix certifies a high-count reference):
+    no exact map exists at 256^2 (65536 solves), so the reference is a
+    separate PICO map of n_ref probes (seed 101).  Its own std-map error e_ref
+    (the standard-error proxy of its accumulator) adds in quadrature to the
+    measured NRMSE of an independent run, so a run counts as within 1 % when
+    sqrt(NRMSE^2 - e_ref^2) <= 1 %; the raw NRMSE at that point is reported.
+    PICO (seed 7) and PMR (seed 3) add samples in chunks; the clocks include
+    the monitor."""
+    sp = workloads.config(3, seed=0)
+    traj = torch.from_numpy(sp.traj.astype(np.float32)).to(dev)
+    smaps = torch.from_numpy(sp.maps.astype(np.complex64)).to(dev)
+    h = lib.pico_init(sp.ny, sp.nx, smaps, sp.psi, None, sampling=lib.PICO_NONCART, lam=sp.lam,
+                      cg_iters=sp.cg_iters, probe_tile=256, traj=traj, nsamples=traj.shape[0],
+                      oversamp=2.0, kb_width=6)
+    n = sp.ny * sp.nx
+    ra = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    racc = lib.make_accum(*ra)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lib.pico_noise_map(h, 101, 0, n_ref, 0, racc)
+    ref = torch.empty(n, dtype=torch.float64, device=dev)
+    lib.pico_finalize(h, racc, ref)
+    torch.cuda.synchronize()
+    ref_s = time.perf_counter() - t0
+    e_ref = lib.pico_monitor_stderr(h, racc)
+    s_ref = torch.sqrt(torch.clamp(ref, min=0.0))
+
+    def within(e):
+        return e * e - e_ref * e_ref <= 1e-4
+    # PICO
+    acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    acc = lib.make_accum(acc_t[0], None, acc_t[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, hit, ep = 0, None, None
+    while done < max_n:
+        lib.pico_noise_map(h, 7, done, chunk, 0, acc)
+        done += chunk
+        ep = lib.pico_monitor_nrmse(h, acc, ref)
+        if within(ep):
+            hit = (time.perf_counter() - t0, done)
+            break
+    # PMR (noise replicas through the gridding adjoint and one CG solve each)
+    pa = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    pacc = lib.make_accum(*pa)
+    var = torch.empty(n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pdone, phit, e = 0, None, None
+    while pdone < 4 * max_n:
+        lib.pico_pmr_baseline(h, 3, pdone, chunk, pacc)
+        pdone += chunk
+        lib.pico_pmr_finalize(h, pacc, var)
+        e = float(torch.linalg.norm(torch.sqrt(torch.clamp(var, min=0.0)) - s_ref) / torch.linalg.norm(s_ref))
+        if within(e):
+            phit = (time.perf_counter() - t0, pdone)
+            break
+    lib.pico_destroy(h)
+    return {"workload": "spiral 256x256, 16 coils, 48x4096 interleaves R=2, lambda 0.1, CG 30; Kaiser-Bessel "
+                        "gridding (2.0, W 6) for the PMR data path",
+            "reference": f"PICO map of {n_ref} probes ({ref_s:.2f} s), own std-map error {e_ref:.4f}",
+            "pico_time_to_1pct_s": round(hit[0], 4) if hit else None, "pico_n_at_1pct": hit[1] if hit else None,
+            "pico_raw_nrmse_at_stop": round(ep, 5) if ep is not None else None,
+            "pmr_time_to_1pct_s": round(phit[0], 4) if phit else None, "pmr_n_at_1pct": phit[1] if phit else None,
+            "pmr_raw_nrmse_at_stop": round(e, 5) if e is not None else None,
+            "paper_context": "paper, GE spiral phantom R=2 on its own hardware: 64 s (PICO) vs 462 s (PMR)"}
+
+
 def cs_leg(lib, workloads, torch, np, dev, steps, storage=0):
     """JVPs/s of the CS workload and the HBM roofline of its normal operator."""
     pr = workloads.config(4, seed=0)
@@ -772,6 +842,10 @@ def main():
         spiral = spiral_leg(lib, workloads, torch, np, dev, args.spiral_steps, lib.PICO_FP32)
         spiral_bf16 = spiral_leg(lib, workloads, torch, np, dev, args.spiral_steps, lib.PICO_BF16_STREAM)
 
+    spiral_ttt = None
+    if args.spiral_steps > 0 and not args.no_ttt:
+        spiral_ttt = spiral_ttt_leg(lib, workloads, torch, np, dev)
+
     # --- third workload: CS (FISTA L1-db4), batched Jacobian-vector probes
     cs_res = cs_bf16 = None
     if args.cs_steps > 0:
@@ -823,6 +897,7 @@ def main():
         "dense_form": dense,
         "spiral": spiral,
         "spiral_bf16": spiral_bf16,
+        "spiral_time_to_1pct": spiral_ttt,
         "cs": cs_res,
         "cs_bf16": cs_bf16,
         "cs_tv": cs_tv,
