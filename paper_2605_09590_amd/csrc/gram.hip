@@ -251,15 +251,19 @@ template <bool SMALL>
 static hipError_t launch_gram(int mode, const Cart1dArgs& a, const float2* G, hipStream_t s) {
   const int nw = a.ny / 32;
   const size_t lds = (size_t)a.ny * kTile * sizeof(float2);
-  static bool attr_set[4] = {false, false, false, false};
-  const void* fn[4] = {(const void*)k_cart1d_gram<C1_FIRST_PROBE, SMALL>, (const void*)k_cart1d_gram<C1_FIRST_BUF, SMALL>,
-                       (const void*)k_cart1d_gram<C1_ITER, SMALL>, (const void*)k_cart1d_gram<C1_APPLY, SMALL>};
   if (mode < 0 || mode > 3) return hipErrorInvalidValue;
-  if (!attr_set[mode]) {
-    hipError_t e = hipFuncSetAttribute(fn[mode], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set[mode] = true;
-  }
+  // allow up to 160 KiB of dynamic LDS for every mode (once per process,
+  // thread-safe initialisation)
+  static const hipError_t attr = [] {
+    const void* fn[4] = {(const void*)k_cart1d_gram<C1_FIRST_PROBE, SMALL>, (const void*)k_cart1d_gram<C1_FIRST_BUF, SMALL>,
+                         (const void*)k_cart1d_gram<C1_ITER, SMALL>, (const void*)k_cart1d_gram<C1_APPLY, SMALL>};
+    for (const void* f : fn) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }();
+  if (attr != hipSuccess) return attr;
   const int ntiles = (a.K + kTile - 1) / kTile;
   const int cgroups = (a.nx + 7) / 8;
   dim3 grid((unsigned)(8 * ntiles * cgroups)), block(64 * nw);

@@ -89,13 +89,11 @@ static hipError_t fft_cols(float2* data, long planes, int ny, int nx, const floa
   constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
   const size_t lds = ((size_t)ny * (NGRP + 1) + (size_t)NG * CF::SPAN) * sizeof(float2);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fft_cols<CF, INV>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // allow more than the default 64 KiB of dynamic LDS (once per process,
+  // thread-safe initialisation)
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_fft_cols<CF, INV>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) return attr;
   dim3 grid((nx + NGRP - 1) / NGRP, (unsigned)planes), block(256);
   hipLaunchKernelGGL((k_fft_cols<CF, INV>), grid, block, lds, s, data, ny, nx, twt);
   return hipGetLastError();

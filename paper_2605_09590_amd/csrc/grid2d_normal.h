@@ -486,13 +486,11 @@ static hipError_t cols(const Grid2dArgs& a, hipStream_t s) {
   constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
   const size_t lds = ((size_t)a.ny * (NGRP + 1) + (size_t)NG * CF::SPAN) * sizeof(float2);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  static bool attr_set = false;   // allow more than the default 64 KiB of dynamic LDS
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_cols<CF, TB>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // allow more than the default 64 KiB of dynamic LDS (once per process,
+  // thread-safe initialisation)
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_cols<CF, TB>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) return attr;
   const long W = (long)((a.Gx + NGRP - 1) / NGRP) * a.K * a.nc;
   dim3 grid((unsigned)(8 * ((W + 7) / 8))), block(256);
   hipLaunchKernelGGL((k_cols<CF, TB>), grid, block, lds, s, a);
