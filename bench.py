@@ -278,14 +278,20 @@ def plain_leg(torch, np, dev, prob, ref, max_probes=1024, check=None):
     return res
 
 
-def dense_leg(lib, torch, np, dev, prob, steps=3):
-    """The main workload with the dense per-column normal operator on the FP32
-    matrix cores (normal_form 2): throughput and the matrix-core roofline of
-    its CG-iteration kernel (8 ny^2 flops per probe and column)."""
+def dense_leg(lib, torch, np, dev, prob, form=2, steps=3):
+    """The main workload with the dense per-column normal operator on the
+    matrix cores: normal_form 2 (FP32 products) or 3 (FP16 products of split
+    FP32 operands, three per product, FP32 accumulation).  Throughput, and the
+    roofline of its CG-iteration kernel: the FP32 matrix peak for form 2 (8
+    ny^2 flops per probe and column); for form 3, whose three FP16 products
+    take a fraction of the time of the kernel's fused CG update, HBM: the
+    update's 64 bytes per probe and pixel (x, r, p, q read and written) plus
+    the blocks read once (8 ny^2 bytes per column), with the FP32-equivalent
+    GEMM rate beside it."""
     ny, nx, K = prob.ny, prob.nx, 256
     maps = torch.from_numpy(prob.maps.astype(np.complex64)).to(dev)
     mask = torch.from_numpy(prob.mask).to(dev)
-    h = lib.pico_init(ny, nx, maps, prob.psi, mask, cg_iters=prob.cg_iters, probe_tile=K, normal_form=2)
+    h = lib.pico_init(ny, nx, maps, prob.psi, mask, cg_iters=prob.cg_iters, probe_tile=K, normal_form=form)
     acc = lib.make_accum(*[torch.zeros(ny * nx, dtype=torch.float64, device=dev) for _ in range(2)])
     lib.pico_noise_map(h, 3, 0, K, 0, acc)
     torch.cuda.synchronize()
@@ -301,12 +307,22 @@ def dense_leg(lib, torch, np, dev, prob, steps=3):
     it_ms, it_n = prof["normal_iter"]
     avg_s = it_ms / it_n / 1e3
     flops = 8.0 * ny * ny * K * nx
-    return {"form": "dense per-column blocks on the FP32 matrix cores (normal_form 2)",
-            "probe_solves_per_s": round(steps * K / (e0.elapsed_time(e1) / 1e3), 2),
-            "roofline": {"bound": "mfma", "achieved": round(flops / avg_s / 1e12, 2), "peak": PEAK_FP32_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(flops / avg_s / 1e12 / PEAK_FP32_TFLOPS, 4),
-                         "kernel": "k_cart1d_gram<C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
-                         "flops_per_launch": flops}}
+    rate = steps * K / (e0.elapsed_time(e1) / 1e3)
+    if form == 2:
+        return {"form": "dense per-column blocks on the FP32 matrix cores (normal_form 2)",
+                "probe_solves_per_s": round(rate, 2),
+                "roofline": {"bound": "mfma", "achieved": round(flops / avg_s / 1e12, 2), "peak": PEAK_FP32_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(flops / avg_s / 1e12 / PEAK_FP32_TFLOPS, 4),
+                             "kernel": "k_cart1d_gram<C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
+                             "flops_per_launch": flops}}
+    nbytes = 64.0 * ny * nx * K + 8.0 * ny * ny * nx
+    return {"form": "dense per-column blocks, split-FP16 products on the FP16 matrix cores (normal_form 3)",
+            "probe_solves_per_s": round(rate, 2),
+            "roofline": {"bound": "hbm", "achieved": round(nbytes / avg_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(nbytes / avg_s / 1e9 / PEAK_HBM_GBS, 4),
+                         "kernel": "k_cart1d_gram16<C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
+                         "bytes_per_launch": nbytes,
+                         "gemm_tflops_fp32_equivalent": round(flops / avg_s / 1e12, 2)}}
 
 
 def reduced_leg(lib, torch, np, dev, prob, ref, factor=2, max_probes=1024):
@@ -833,7 +849,8 @@ def main():
     }
 
     # --- the same workload with the dense per-column operator on the matrix cores
-    dense = dense_leg(lib, torch, np, dev, prob) if args.dense else None
+    dense = dense_leg(lib, torch, np, dev, prob, form=2) if args.dense else None
+    dense16 = dense_leg(lib, torch, np, dev, prob, form=3) if args.dense else None
 
     # --- second workload: spiral CG-SENSE, Toeplitz normal operator (HBM-bound path),
     # complex64 planes and the bfloat16-stream variant
@@ -895,6 +912,7 @@ def main():
         "kernel_launches": {k: v[1] for k, v in prof.items()},
         "roofline": roofline, "cpu_baseline": cpu,
         "dense_form": dense,
+        "dense_form_split_fp16": dense16,
         "spiral": spiral,
         "spiral_bf16": spiral_bf16,
         "spiral_time_to_1pct": spiral_ttt,

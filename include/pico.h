@@ -129,8 +129,14 @@ typedef struct {
    * image columns, Sec. 2.1 Eq. (6)): 1 = column FFTs; 2 = the dense ny x ny
    * block of every column, built once (nx ny^2 complex64 of device memory)
    * and applied to the probe tile on the FP32 matrix cores (ny a multiple
-   * of 32, <= 512); 0 = the default (column FFTs).
-   * Both give M to FP32 rounding; the PMR right-hand side always uses FFTs. */
+   * of 32, <= 512); 3 = the same blocks applied on the FP16 matrix cores
+   * with each FP32 operand split into two FP16 parts and three partial
+   * products accumulated in FP32 (Ootomo and Yokota 2022), operands scaled
+   * by powers of two per column block and per probe (the same device
+   * memory as 2, plus nx * ceil(probe_tile / 32) * 32 ints of exponents);
+   * 0 = the default (column FFTs).
+   * All give M to FP32 rounding (the split keeps ~22 significand bits of
+   * each operand); the PMR right-hand side always uses FFTs. */
   int32_t normal_form;
   /* PICO_CS_FISTA_TV: dual fast-gradient-projection steps per proximal step
    * (Beck and Teboulle 2009), from a zero dual start each FISTA iteration,

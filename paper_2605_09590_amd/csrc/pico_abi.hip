@@ -60,6 +60,10 @@ struct pico_op_s {
   bool use_gram = false;      // separable path: dense per-column blocks on the matrix cores
   float2* gram = nullptr;     // [nx][ny][ny] conj(M_x[i][j]) at [x][j][i]
   double2* gram_c = nullptr;  // [ny] circulant c(d) (build input)
+  bool use_gram16 = false;    // the same blocks split into FP16 pairs (FP16 matrix cores)
+  uint32_t* gram16 = nullptr; // [nx][ny/32][ny/8][hi, lo][64 lanes][4] packed FP16 pairs
+  int* gram16_exp = nullptr;  // [nx] block scale exponents
+  int* gram16_pexp = nullptr; // [nx][tiles][32] probe scale exponents (kernel scratch)
   float2* twt = nullptr;      // separable path: [ny] twiddles
   float* w = nullptr;         // grid path: [Gx][Gy] real weights
   float2* twx = nullptr;      // grid path: [Gx] twiddles
@@ -262,6 +266,8 @@ hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hip
     a.first = c.first;
     a.dist = c.dist;
     if (op->use_gram && mode != pico::C1_PMR_RHS) return pico::launch_cart1d_gram(mode, a, op->gram, s);
+    if (op->use_gram16 && mode != pico::C1_PMR_RHS)
+      return pico::launch_cart1d_gram16(mode, a, op->gram16, op->gram16_exp, op->gram16_pexp, s);
     return pico::launch_cart1d(mode, a, s);
   }
   pico::Grid2dArgs g{};
@@ -515,6 +521,11 @@ bool wants_gram(const pico_op_desc_t* d) {
   return d->normal_form == 2;
 }
 
+bool wants_gram16(const pico_op_desc_t* d) {
+  if (d->sampling != PICO_CART_1D || !pico::gram_supported(d->ny)) return false;
+  return d->normal_form == 3;
+}
+
 // Kaiser-Bessel tables of a non-Cartesian operator: device buffers in the
 // kb_layout order, tap weights and the spreading CSR built on the host
 hipError_t build_kb(pico_op_t op, const pico_op_desc_t* d, hipStream_t s) {
@@ -629,8 +640,8 @@ pico_status_t validate(const pico_op_desc_t* d) {
     return fail(PICO_EINVAL, "traj and 1 <= nsamples <= 2^30 are required for non-Cartesian sampling");
   if (d->lambda > 0.0 && (d->power_iters < 1 || !(d->power_margin > 0.0)))
     return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
-  if (d->normal_form < 0 || d->normal_form > 2) return fail(PICO_EINVAL, "normal_form must be 0, 1 or 2");
-  if (d->normal_form == 2 && (d->sampling != PICO_CART_1D || !pico::gram_supported(d->ny)))
+  if (d->normal_form < 0 || d->normal_form > 3) return fail(PICO_EINVAL, "normal_form must be 0, 1, 2 or 3");
+  if (d->normal_form >= 2 && (d->sampling != PICO_CART_1D || !pico::gram_supported(d->ny)))
     return fail(PICO_EINVAL, "the dense normal form needs PICO_CART_1D and ny a multiple of 32 in 64..512");
   if (d->kb_width != 0) {
     if (d->sampling != PICO_NONCART) return fail(PICO_EINVAL, "kb_width applies to PICO_NONCART only");
@@ -693,6 +704,12 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
     if (wants_gram(d)) {
       add(gram_bytes(d->ny, d->nx));
       add(ny * 16);
+    }
+    if (wants_gram16(d)) {
+      add(gram_bytes(d->ny, d->nx));
+      add(ny * 16);
+      add(d->nx * 4);
+      add(pico::gram16_pexp_count(d->nx, K) * 4);
     }
   } else {
     add(Gy * Gx * 4);
@@ -851,6 +868,15 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
       if ((e = op->alloc(&op->gram_c, ny)) != hipSuccess) return bad(e, "dense blocks");
       if ((e = pico::build_gram(op->maps, w.data(), nc, ny, nx, op->gram, op->gram_c, s)) != hipSuccess) return bad(e, "dense blocks");
       op->use_gram = true;
+    }
+    if (wants_gram16(d)) {
+      if ((e = op->alloc(&op->gram16, pico::gram_bytes(ny, nx) / sizeof(uint32_t))) != hipSuccess) return bad(e, "dense blocks");
+      if ((e = op->alloc(&op->gram_c, ny)) != hipSuccess) return bad(e, "dense blocks");
+      if ((e = op->alloc(&op->gram16_exp, nx)) != hipSuccess) return bad(e, "dense blocks");
+      if ((e = op->alloc(&op->gram16_pexp, pico::gram16_pexp_count(nx, op->K))) != hipSuccess) return bad(e, "dense blocks");
+      if ((e = pico::build_gram16(op->maps, w.data(), nc, ny, nx, op->gram16, op->gram16_exp, op->gram_c, s)) != hipSuccess)
+        return bad(e, "dense blocks");
+      op->use_gram16 = true;
     }
   } else {
     const int Gy = op->Gy, Gx = op->Gx;

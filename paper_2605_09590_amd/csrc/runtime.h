@@ -235,6 +235,13 @@ size_t gram_bytes(int ny, int nx);
 hipError_t build_gram(const float2* maps, const float* maskw_h, int nc, int ny, int nx, float2* G,
                       double2* cvec_d, hipStream_t s);
 hipError_t launch_cart1d_gram(int mode, const Cart1dArgs& a, const float2* G, hipStream_t s);
+// the same blocks split into FP16 pairs for the FP16 matrix cores: G16 has
+// gram_bytes / 4 words, gexp nx column exponents, pexp gram16_pexp_count ints
+size_t gram16_pexp_count(int nx, int K);
+hipError_t build_gram16(const float2* maps, const float* maskw_h, int nc, int ny, int nx, uint32_t* G16, int* gexp,
+                        double2* cvec_d, hipStream_t s);
+hipError_t launch_cart1d_gram16(int mode, const Cart1dArgs& a, const uint32_t* G16, const int* gexp, int* pexp,
+                                hipStream_t s);
 hipError_t launch_final_x(const FinalArgs& a, hipStream_t s);
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);
 hipError_t launch_accum_colmajor(const AccumArgs& a, hipStream_t s);

@@ -180,7 +180,7 @@ def test_full_size_config2_sampled_columns(lib):
     op = opico.cartesian(prob.maps, prob.psi, prob.mask)
     cols = [0, 1, 97, 160, 255, 319]
     ref = opico.noise_map_exact_columns(op, prob.mask, 2024, 0, 256, cols)
-    for form, name in ((2, "dense"), (1, "FFT")):
+    for form, name in ((2, "dense"), (3, "dense split-FP16"), (1, "FFT")):
         h = _init(lib, prob, 256, form=form)
         st = lib.pico_stats_t()
         (s, _, _), acc = _gpu_map(lib, h, n, 2024, 0, 256, stats=st)
@@ -193,13 +193,15 @@ def test_full_size_config2_sampled_columns(lib):
         assert err < TOL
 
 
+@pytest.mark.parametrize("form", [2, 3])
 @pytest.mark.parametrize("ny,nx,nc,tile,nprobes", [(64, 64, 4, 40, 40), (96, 40, 5, 4, 10),
-                                                   (160, 24, 8, 32, 45), (288, 16, 3, 33, 33)])
-def test_dense_form_parity(lib, ny, nx, nc, tile, nprobes):
-    say(f"case: dense per-column normal operator {ny}x{nx} {nc} coils, {nprobes} probes in tiles of "
-        f"{tile} (probe tiles of 32 on the matrix cores, ragged), CG 20")
+                                                   (160, 24, 8, 32, 45), (288, 16, 3, 33, 33),
+                                                   (512, 8, 2, 32, 32)])
+def test_dense_form_parity(lib, ny, nx, nc, tile, nprobes, form):
+    say(f"case: dense per-column normal operator (form {form}) {ny}x{nx} {nc} coils, {nprobes} probes "
+        f"in tiles of {tile} (probe tiles of 32 on the matrix cores, ragged), CG 20")
     prob = workloads.config(2, seed=ny, ny=ny, nx=nx, nc=nc, acs=8, cg_iters=20)
-    h = _init(lib, prob, tile, form=2)
+    h = _init(lib, prob, tile, form=form)
     st = lib.pico_stats_t()
     (s, si, ss), _ = _gpu_map(lib, h, ny * nx, 31, 2, nprobes, stats=st)
     lib.pico_destroy(h)
@@ -210,12 +212,14 @@ def test_dense_form_parity(lib, ny, nx, nc, tile, nprobes):
     assert err < TOL and _rel(ss, ref["sumsq"].ravel()) < TOL
 
 
-def test_dense_form_apply_cov_tikhonov(lib):
-    say("case: dense normal form, apply_cov on 3 probes, lambda 0.1, 64x64, power method on the matrix cores")
+@pytest.mark.parametrize("form", [2, 3])
+def test_dense_form_apply_cov_tikhonov(lib, form):
+    say(f"case: dense normal form {form}, apply_cov on 3 probes, lambda 0.1, 64x64, power method on the "
+        "matrix cores")
     prob = workloads.config(1, seed=4)
     rng = np.random.default_rng(8)
     v = (rng.standard_normal((3, 64, 64)) + 1j * rng.standard_normal((3, 64, 64)))
-    h = _init(lib, prob, 4, lam=0.1, cg_iters=30, form=2)
+    h = _init(lib, prob, 4, lam=0.1, cg_iters=30, form=form)
     vt = _dev(v.astype(np.complex64))
     ut = torch.empty_like(vt)
     lib.pico_apply_cov(h, vt, ut, 3)
