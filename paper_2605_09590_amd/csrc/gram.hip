@@ -96,10 +96,10 @@ __device__ __forceinline__ float wave_max_abs(float v) {   // v >= 0 on every la
 __device__ __forceinline__ int tile_at(int row, int j) { return row * kTile + (j ^ (row & 31)); }
 
 // The fused CG update in front of the product for one probe k of the tile
-// (rows y = lane + 64 m, m < NM): writes x, r, p as the mode requires, returns
-// p (the tile values) and adds |r|^2 to d0.  Every load of the column is
-// issued before the first store, so a wave keeps the whole column in flight.
-// Inactive probes (k >= K) give zeros.
+// (rows y = lane + 64 m, m < NM): writes x, r, p as the mode requires,
+// returns p (the tile values) and adds |r|^2 to d0.  Every load of the
+// column is issued before the first store, so a wave keeps the whole column
+// in flight.  Inactive probes (k >= K) give zeros.
 template <int MODE, int NM>
 __device__ __forceinline__ void probe_column(const Cart1dArgs& a, int k, bool active, size_t base, int col, int lane,
                                              float alpha, float beta, float2 (&pv)[NM], double& d0) {
@@ -410,66 +410,51 @@ __global__ void k_gram16_build(const float2* __restrict__ maps, const double2* _
   o[64] = lo;
 }
 
-template <int MODE, bool SMALL>
-__global__ __launch_bounds__(SMALL ? 640 : 1024, SMALL ? 5 : 1) void k_cart1d_gram16(Cart1dArgs a,
-                                                                                    const word4* __restrict__ G16,
-                                                                                    const int* __restrict__ gexp,
-                                                                                    int* __restrict__ pexp) {
-  extern __shared__ float2 pt[];                   // split p tile, then the FP32 q tile, then reduction
-  uint32_t* bt = reinterpret_cast<uint32_t*>(pt);  // [32][ny] hi words, then [32][ny] lo words
-  const int ny = a.ny, nw = ny / 32, nst = ny / 8;
-  const int sw = (ny / 4) % 16 == 0 ? 15 : 7;      // chunk swizzle within the row's 16-chunk groups
-  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int ntiles = (a.K + kTile - 1) / kTile;
-  const int b = blockIdx.x, xcd = b % 8, rest = b / 8;
-  const int tile = rest % ntiles, col = xcd + 8 * (rest / ntiles);
-  if (col >= a.nx) return;
-  const int k0 = tile * kTile;
-  constexpr int kRowsPerLane = SMALL ? 5 : 8;      // rows y = lane + 64 m of a column (ny <= 320 / 512)
-  int* __restrict__ pe = pexp + ((size_t)col * ntiles + tile) * kTile;   // probe scale exponents
-
-  // ---- prologue: the CG update as in the FP32 form, then the probe's scale
-  // and split; wave w prepares probes j = w, w + nw, ...
-  constexpr int kMaxY = kRowsPerLane;
-  for (int j = w; j < kTile; j += nw) {
-    const int k = k0 + j;
-    const bool active = k < a.K;
-    const size_t base = ((size_t)(active ? k : 0) * a.nx + col) * ny;
-    const float alpha = (MODE == C1_ITER && active) ? (float)a.alpha[k] : 0.f;
-    const float beta = (MODE == C1_ITER && active) ? (float)a.beta[k] : 0.f;
-    double d0 = 0.0;
-    float2 pv[kMaxY];
-    probe_column<MODE>(a, k, active, base, col, lane, alpha, beta, pv, d0);
-    float mx = 0.f;
+// One probe column j of the tile ahead of the product: the CG update as in the
+// FP32 form, the probe's scale exponent (to pe[j]) and its split into the
+// tile bt ([32][ny] hi words, then [32][ny] lo words).
+template <int MODE, int NM>
+__device__ __forceinline__ void split_column(const Cart1dArgs& a, uint32_t* bt, int* pe, int j, int k0, int col,
+                                             int lane, int sw) {
+  const int ny = a.ny, k = k0 + j;
+  const bool active = k < a.K;
+  const size_t base = ((size_t)(active ? k : 0) * a.nx + col) * ny;
+  const float alpha = (MODE == C1_ITER && active) ? (float)a.alpha[k] : 0.f;
+  const float beta = (MODE == C1_ITER && active) ? (float)a.beta[k] : 0.f;
+  double d0 = 0.0;
+  float2 pv[NM];
+  probe_column<MODE>(a, k, active, base, col, lane, alpha, beta, pv, d0);
+  float mx = 0.f;
 #pragma unroll
-    for (int m = 0; m < kMaxY; ++m) mx = fmaxf(mx, fmaxf(fabsf(pv[m].x), fabsf(pv[m].y)));
-    mx = wave_max_abs(mx);
-    int e = 0;
-    if (mx > 0.f && mx < INFINITY) frexpf(mx, &e);
-    const int sp = 15 - e;
+  for (int m = 0; m < NM; ++m) mx = fmaxf(mx, fmaxf(fabsf(pv[m].x), fabsf(pv[m].y)));
+  mx = wave_max_abs(mx);
+  int e = 0;
+  if (mx > 0.f && mx < INFINITY) frexpf(mx, &e);
+  const int sp = 15 - e;
 #pragma unroll
-    for (int m = 0; m < kMaxY; ++m) {
-      const int y = lane + 64 * m;
-      if (y < ny) {
-        const float xr = ldexpf(pv[m].x, sp), xi = ldexpf(pv[m].y, sp);
-        const _Float16 hr = (_Float16)xr, hm = (_Float16)xi;
-        const int at = btile_at(j, y, ny, sw);
-        bt[at] = pack_h2(hr, hm);
-        bt[kTile * ny + at] = pack_h2((_Float16)(xr - (float)hr), (_Float16)(xi - (float)hm));
-      }
-    }
-    d0 = wave_sum(d0);
-    if (lane == 0) {
-      pe[j] = sp;
-      if (active) a.part[((size_t)k * a.nx + col) * 4] = d0;
+  for (int m = 0; m < NM; ++m) {
+    const int y = lane + 64 * m;
+    if (y < ny) {
+      const float xr = ldexpf(pv[m].x, sp), xi = ldexpf(pv[m].y, sp);
+      const _Float16 hr = (_Float16)xr, hm = (_Float16)xi;
+      const int at = btile_at(j, y, ny, sw);
+      bt[at] = pack_h2(hr, hm);
+      bt[kTile * ny + at] = pack_h2((_Float16)(xr - (float)hr), (_Float16)(xi - (float)hm));
     }
   }
-  __syncthreads();   // the tile and the probe exponents (global, this workgroup's) are complete
+  d0 = wave_sum(d0);
+  if (lane == 0) {
+    pe[j] = sp;
+    if (active) a.part[((size_t)k * a.nx + col) * 4] = d0;
+  }
+}
 
-  // ---- q = M_x p: rows [32 w, 32 w + 32) x 32 probes, three products per k step
-  const int li = lane % 32, kk = lane / 32, bsw = li & sw;
+// The product on the matrix cores for rows [32 w, 32 w + 32) x 32 probes of
+// the split tile bt, three partial products per k step (8 columns j).
+__device__ __forceinline__ void tile_product(const uint32_t* bt, const word4* __restrict__ G16, int col, int w, int nw,
+                                             int ny, int lane, int sw, floatx16& accR, floatx16& accI) {
+  const int nst = ny / 8, li = lane % 32, kk = lane / 32, bsw = li & sw;
   const uint32_t* brow = bt + li * ny;
-  floatx16 accR, accI;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     accR[v] = 0.f;
@@ -517,24 +502,64 @@ __global__ __launch_bounds__(SMALL ? 640 : 1024, SMALL ? 5 : 1) void k_cart1d_gr
     l1 = gload(n1, 1);
     __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// p of rows 32 w + 8 g + 4 kk + t (t = 0..3), probe li, from the split tile,
+// unscaled by the probe exponent sp
+__device__ __forceinline__ void tile_p4(const uint32_t* bt, int ny, int w, int g, int lane, int sw, int sp,
+                                        float2 (&p)[4]) {
+  const int li = lane % 32, kk = lane / 32;
+  const uint32_t* brow = bt + li * ny;
+  const int off = ((8 * w + 2 * g + kk) ^ (li & sw)) << 2;
+  const word4 ph = *reinterpret_cast<const word4*>(brow + off);
+  const word4 pl = *reinterpret_cast<const word4*>(brow + kTile * ny + off);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float2 h = unpack_h2(ph[t]), l = unpack_h2(pl[t]);
+    p[t] = make_float2(ldexpf(h.x + l.x, -sp), ldexpf(h.y + l.y, -sp));
+  }
+}
+
+template <int MODE, bool SMALL>
+__global__ __launch_bounds__(SMALL ? 640 : 1024, SMALL ? 5 : 1) void k_cart1d_gram16(Cart1dArgs a,
+                                                                                    const word4* __restrict__ G16,
+                                                                                    const int* __restrict__ gexp,
+                                                                                    int* __restrict__ pexp) {
+  extern __shared__ float2 pt[];                   // split p tile, then the FP32 q tile, then reduction
+  uint32_t* bt = reinterpret_cast<uint32_t*>(pt);  // [32][ny] hi words, then [32][ny] lo words
+  const int ny = a.ny, nw = ny / 32;
+  const int sw = (ny / 4) % 16 == 0 ? 15 : 7;      // chunk swizzle within the row's 16-chunk groups
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int ntiles = (a.K + kTile - 1) / kTile;
+  const int b = blockIdx.x, xcd = b % 8, rest = b / 8;
+  const int tile = rest % ntiles, col = xcd + 8 * (rest / ntiles);
+  if (col >= a.nx) return;
+  const int k0 = tile * kTile;
+  constexpr int kRowsPerLane = SMALL ? 5 : 8;      // rows y = lane + 64 m of a column (ny <= 320 / 512)
+  int* __restrict__ pe = pexp + ((size_t)col * ntiles + tile) * kTile;   // probe scale exponents
+
+  // ---- prologue: wave w prepares probes j = w, w + nw, ...
+  for (int j = w; j < kTile; j += nw) split_column<MODE, kRowsPerLane>(a, bt, pe, j, k0, col, lane, sw);
+  __syncthreads();   // the tile and the probe exponents (global, this workgroup's) are complete
+
+  const int li = lane % 32, kk = lane / 32;
+  floatx16 accR, accI;
+  tile_product(bt, G16, col, w, nw, ny, lane, sw, accR, accI);
 
   // ---- q = 2^-(gexp + pexp) acc + lam p on the wave's own rows, with the
-  // (Re p^H q, |q|^2) partials; p is the split tile's value, unscaled
+  // (Re p^H q, |q|^2) partials
   const int sp = pe[li];
   const int sq = -(gexp[col] + sp);
   double d1 = 0.0, d2 = 0.0;   // q replaces acc in place
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const int off = ((8 * w + 2 * g + kk) ^ bsw) << 2;   // rows 32 w + 8 g + 4 kk + 0..3
-    const word4 ph = *reinterpret_cast<const word4*>(brow + off);
-    const word4 pl = *reinterpret_cast<const word4*>(brow + kTile * ny + off);
+    float2 p[4];
+    tile_p4(bt, ny, w, g, lane, sw, sp, p);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int v = 4 * g + t;
-      const float2 h = unpack_h2(ph[t]), l = unpack_h2(pl[t]);
-      const float2 p = make_float2(ldexpf(h.x + l.x, -sp), ldexpf(h.y + l.y, -sp));
-      const float2 q = make_float2(fmaf(a.lam, p.x, ldexpf(accR[v], sq)), fmaf(a.lam, p.y, ldexpf(accI[v], sq)));
-      d1 += (double)p.x * q.x + (double)p.y * q.y;
+      const float2 q = make_float2(fmaf(a.lam, p[t].x, ldexpf(accR[v], sq)), fmaf(a.lam, p[t].y, ldexpf(accI[v], sq)));
+      d1 += (double)p[t].x * q.x + (double)p[t].y * q.y;
       d2 += (double)q.x * q.x + (double)q.y * q.y;
       accR[v] = q.x;
       accI[v] = q.y;

@@ -50,7 +50,7 @@ def test_estimate_cart1d_closed_form(p):
     res, peak = p.pico_estimate_bytes(d)
     assert res == expect + _round(320 * 320 * 320 * 8) + _round(320 * 16)
     # split-FP16 dense form: the same blocks as FP16 pairs, plus the column
-    # exponents and the per-tile probe exponents
+    # and per-tile probe exponents
     d, _ = p.make_desc(320, 320, 0x1000, None, 0x2000, ncoils=15, probe_tile=256, cg_iters=30,
                        normal_form=3)
     res, _ = p.pico_estimate_bytes(d)
