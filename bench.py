@@ -40,6 +40,14 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def gram16_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("gram.hip", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2605_09590_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def normal_op_flops(ny, nx, nc):
     """Algorithmic FLOPs of one application of M to one probe (separable path).
 
@@ -316,10 +324,17 @@ def dense_leg(lib, torch, np, dev, prob, form=2, steps=3):
                              "kernel": "k_cart1d_gram<C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
                              "flops_per_launch": flops}}
     nbytes = 64.0 * ny * nx * K + 8.0 * ny * ny * nx
+    traffic = None   # counter-measured HBM bytes, while the kernel sources match the measured ones
+    tfile = os.path.join(ROOT, "profiles", "traffic_gram16_iter_cart1d_320x320x15_K256.json")
+    if (ny, nx, K) == (320, 320, 256) and os.path.exists(tfile):
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        if tj.get("kernel_src_sha") == gram16_source_digest():
+            traffic = tj.get("hbm_bytes_per_launch")
     return {"form": "dense per-column blocks, split-FP16 products on the FP16 matrix cores (normal_form 3)",
             "probe_solves_per_s": round(rate, 2),
             "roofline": {"bound": "hbm", "achieved": round(nbytes / avg_s / 1e9, 1), "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": round(nbytes / avg_s / 1e9 / PEAK_HBM_GBS, 4),
+                         "unit": "GB/s", "frac": round(nbytes / avg_s / 1e9 / PEAK_HBM_GBS, 4), "traffic": traffic,
                          "kernel": "k_cart1d_gram16<C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
                          "bytes_per_launch": nbytes,
                          "gemm_tflops_fp32_equivalent": round(flops / avg_s / 1e12, 2)}}
