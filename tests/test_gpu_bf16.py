@@ -59,11 +59,13 @@ def _gpu_map(lib, h, n, seed, first, nprobes):
     return acc_t[0].cpu().numpy()
 
 
-def test_bf16_maps_phase_encode(lib):
-    say("case: phase-encode 64x64, 4 coils, R=2, 16 probes in tiles of 8, CG 20, bfloat16 maps")
+@pytest.mark.parametrize("form", [0, 2, 3])
+def test_bf16_maps_phase_encode(lib, form):
+    say(f"case: phase-encode 64x64, 4 coils, R=2, 16 probes in tiles of 8, CG 20, bfloat16 maps, "
+        f"normal form {form} (the dense blocks are built from the rounded maps)")
     prob = workloads.config(1, seed=0)
     h = lib.pico_init(64, 64, _dev(prob.maps.astype(np.complex64)), prob.psi, _dev(prob.mask),
-                      cg_iters=20, probe_tile=8, storage=lib.PICO_BF16_MAPS)
+                      cg_iters=20, probe_tile=8, storage=lib.PICO_BF16_MAPS, normal_form=form)
     s = _gpu_map(lib, h, 64 * 64, 4, 0, 16)
     lib.pico_destroy(h)
     wq = ostore.bf16_whitened_maps(prob.maps, prob.psi)

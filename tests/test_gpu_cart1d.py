@@ -125,6 +125,25 @@ def test_apply_cov_parity_and_tikhonov(lib):
             assert err < TOL
 
 
+@pytest.mark.parametrize("form", [0, 3])
+def test_cg_tolerance_mode_parity(lib, form):
+    say(f"case: CG to ||r||/||r0|| <= 1e-5 (at most 200 iterations), 96x40 5 coils R=2 + 8 ACS, "
+        f"12 probes in tiles of 8, normal form {form}")
+    prob = workloads.config(2, seed=8, ny=96, nx=40, nc=5, acs=8, cg_iters=200)
+    h = _init(lib, prob, 8, cg_tol=1e-5, form=form)
+    st = lib.pico_stats_t()
+    (s, _, _), _ = _gpu_map(lib, h, prob.ny * prob.nx, 13, 0, 12, stats=st)
+    lib.pico_destroy(h)
+    cov = opico.Covariance(opico.cartesian(prob.maps, prob.psi, prob.mask), 0.0, 200, tol=1e-5)
+    ref = opico.noise_map(cov, 13, 0, 12)
+    err = _rel(s, ref["sum"].ravel())
+    say(f"  rel err {err:.2e}, CG relres max {st.max_relres:.2e}, frozen {st.frozen}")
+    # every solve stopped by the tolerance; a stop one iteration apart from the
+    # oracle's moves x by ~1e-5 relative, far inside the bar
+    assert st.max_relres <= 1e-5 and st.frozen == 0
+    assert err < TOL
+
+
 def test_tikhonov_noise_map_parity(lib):
     say("case: Tikhonov lambda 0.1 noise map, 128x48 6 coils, 6 probes")
     prob = workloads.config(2, seed=5, ny=128, nx=48, nc=6, acs=8, cg_iters=20, lam=0.1)
@@ -138,11 +157,12 @@ def test_tikhonov_noise_map_parity(lib):
     assert err < TOL
 
 
-def test_resume_split_is_bitwise(lib):
-    say("case: probes [0,8)+[8,16) vs [0,16), tile 8")
+@pytest.mark.parametrize("form", [0, 3])
+def test_resume_split_is_bitwise(lib, form):
+    say(f"case: probes [0,8)+[8,16) vs [0,16), tile 8, normal form {form}")
     prob = workloads.config(1, seed=6)
     n = prob.ny * prob.nx
-    h = _init(lib, prob, 8)
+    h = _init(lib, prob, 8, form=form)
     (a, _, _), _ = _gpu_map(lib, h, n, 9, 0, 16)
     acc_t = [torch.zeros(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
     _gpu_map(lib, h, n, 9, 0, 8, acc_t=acc_t)
@@ -151,11 +171,12 @@ def test_resume_split_is_bitwise(lib):
     assert np.array_equal(a, b)
 
 
-def test_pmr_parity(lib):
-    say("case: PMR 24 replicas, 64x64 4 coils, tile 8")
+@pytest.mark.parametrize("form", [0, 3])
+def test_pmr_parity(lib, form):
+    say(f"case: PMR 24 replicas, 64x64 4 coils, tile 8, normal form {form}")
     prob = workloads.config(1, seed=7)
     n = prob.ny * prob.nx
-    h = _init(lib, prob, 8)
+    h = _init(lib, prob, 8, form=form)
     acc_t = [torch.zeros(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
     acc = lib.make_accum(*acc_t)
     lib.pico_pmr_baseline(h, 21, 0, 24, acc)
