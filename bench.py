@@ -286,7 +286,7 @@ def plain_leg(torch, np, dev, prob, ref, max_probes=1024, check=None):
     return res
 
 
-def dense_leg(lib, torch, np, dev, prob, form=2, steps=3):
+def dense_leg(lib, torch, np, dev, prob, form=2, steps=3, ref=None):
     """The main workload with the dense per-column normal operator on the
     matrix cores: normal_form 2 (FP32 products) or 3 (FP16 products of split
     FP32 operands, three per product, FP32 accumulation).  Throughput, and the
@@ -311,6 +311,19 @@ def dense_leg(lib, torch, np, dev, prob, form=2, steps=3):
     e1.record()
     torch.cuda.synchronize()
     prof = lib.pico_profile_stop(h)
+    ttt = None
+    if ref is not None:   # time to 1 % NRMSE of the std map, as the main leg's (chunks of 32, monitor each)
+        acc_t = [torch.zeros(ny * nx, dtype=torch.float64, device=dev) for _ in range(2)]
+        acc2 = lib.make_accum(acc_t[0], None, acc_t[1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < 4096:
+            lib.pico_noise_map(h, 7, done, 32, 0, acc2)
+            done += 32
+            if lib.pico_monitor_nrmse(h, acc2, ref) <= 0.01:
+                ttt = {"time_to_1pct_s": round(time.perf_counter() - t0, 5), "n_at_1pct": done}
+                break
     lib.pico_destroy(h)
     it_ms, it_n = prof["normal_iter"]
     avg_s = it_ms / it_n / 1e3
@@ -332,7 +345,7 @@ def dense_leg(lib, torch, np, dev, prob, form=2, steps=3):
         if tj.get("kernel_src_sha") == gram16_source_digest():
             traffic = tj.get("hbm_bytes_per_launch")
     return {"form": "dense per-column blocks, split-FP16 products on the FP16 matrix cores (normal_form 3)",
-            "probe_solves_per_s": round(rate, 2),
+            "probe_solves_per_s": round(rate, 2), "time_to_1pct": ttt,
             "roofline": {"bound": "hbm", "achieved": round(nbytes / avg_s / 1e9, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(nbytes / avg_s / 1e9 / PEAK_HBM_GBS, 4), "traffic": traffic,
                          "kernel": "k_cart1d_gram16<C1_ITER>", "avg_launch_us": round(avg_s * 1e6, 2),
@@ -865,7 +878,7 @@ def main():
 
     # --- the same workload with the dense per-column operator on the matrix cores
     dense = dense_leg(lib, torch, np, dev, prob, form=2) if args.dense else None
-    dense16 = dense_leg(lib, torch, np, dev, prob, form=3) if args.dense else None
+    dense16 = dense_leg(lib, torch, np, dev, prob, form=3, ref=None if args.no_ref else ref) if args.dense else None
 
     # --- second workload: spiral CG-SENSE, Toeplitz normal operator (HBM-bound path),
     # complex64 planes and the bfloat16-stream variant
