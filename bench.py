@@ -621,6 +621,18 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000):
     pmr_s = (time.perf_counter() - t0) / nrep
     lib.pico_destroy(h)
     jvps = K / (ms / 1e3)
+    it_ms, it_n = prof["normal_iter"]
+    op_s = it_ms / it_n / 1e3
+    alg = K * (4 * pr.nc * n * 8 + 2 * n * 8) + 2 * pr.nc * n * 8   # as the CS leg's (complex64)
+    # the TV tangent (the rest of the step): per prox, the first launch of dual
+    # steps (one step when the count is odd, else a pair) starts from zero,
+    # reads dz and writes dr, dp (40 B per tangent and pixel); each later pair
+    # reads dz, dr, dp and writes dr, dp (72 B).  The projection data (20 B per
+    # pixel and step) is shared by the tangents of a workgroup and not counted.
+    inner, T = pr.extra["tv_inner"], pr.extra["fista_iters"]
+    later = inner // 2 if inner % 2 else inner // 2 - 1
+    tv_bytes = T * K * n * (40 + 72 * later)
+    tv_s = prof["other"][0] / 1e3 / steps
     return {
         "workload": f"TV-CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2 (24x24 calib), "
                     f"FISTA {pr.extra['fista_iters']} its x {pr.extra['tv_inner']} dual steps, lambda_TV "
@@ -630,6 +642,15 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000):
         "pmr_replicas_per_s": round(1.0 / pmr_s, 2), "pmr_precision": "f64",
         "n_converged": n_conv,
         "pico_s_at_n": round(n_conv / jvps, 2), "pmr_s_at_n": round(n_conv * pmr_s, 2),
+        "roofline": {"bound": "hbm", "achieved": round(alg / op_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(alg / op_s / 1e9 / PEAK_HBM_GBS, 4),
+                     "kernel": "grid normal operator (rows_fwd + cols + rows_inv), C1_APPLY",
+                     "avg_application_us": round(op_s * 1e6, 1), "alg_bytes": alg},
+        "tv_tangent": {"bound": "hbm", "ms_per_step": round(tv_s * 1e3, 3), "alg_bytes_per_step": tv_bytes,
+                       "achieved_GBs": round(tv_bytes / tv_s / 1e9, 1),
+                       "frac": round(tv_bytes / tv_s / 1e9 / PEAK_HBM_GBS, 4),
+                       "note": "time of the step outside the normal-operator applications: the dual-step "
+                               "kernels plus the FISTA momentum and gradient kernels"},
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
     }
 
