@@ -279,32 +279,55 @@ __global__ __launch_bounds__(256) void k_tv_inner2(const float2* __restrict__ dz
     iv1 = invn1[i];
   }
   const int k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
-  for (int k = k0; k < k1; ++k) {
+  // phase A: a tangent's box values (r on B2, p on B1, dz on rows / cols >= 1)
+  // for this thread's points e = t, t + 256; tangent k + 1's are loaded into
+  // registers while tangent k's phases run, and stored to LDS at the top of
+  // the next pass
+  static_assert(kB2 <= 512, "two box points per thread");
+  struct BoxPt {
+    float2 vy, vx, qy, qx, z;
+  };
+  BoxPt nb[2];
+  auto box_load = [&](int k) {
     const float2* zk = dz + (size_t)k * n;
     const float2* ry = rA + (size_t)k * 2 * n;
     const float2* py = pA + (size_t)k * 2 * n;
     const float2 zero = make_float2(0.f, 0.f);
-    // phase A: loads
-    for (int e = t; e < kB2; e += 256) {
-      const int a = e / kBX, b = e - a * kBX;
-      const long g = gidx(a, b);
-      float2 vy = zero, vx = zero, qy = zero, qx = zero, z = zero;
-      if (!fst) {
-        vy = ry[g];
-        vx = ry[n + g];
-        if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
-          qy = py[g];
-          qx = py[n + g];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int e = t + 256 * it;
+      nb[it].vy = nb[it].vx = nb[it].qy = nb[it].qx = nb[it].z = zero;
+      if (e < kB2) {
+        const int a = e / kBX, b = e - a * kBX;
+        const long g = gidx(a, b);
+        if (!fst) {
+          nb[it].vy = ry[g];
+          nb[it].vx = ry[n + g];
+          if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
+            nb[it].qy = py[g];
+            nb[it].qx = py[n + g];
+          }
         }
+        if (a >= 1 && b >= 1) nb[it].z = zk[g];
       }
-      if (a >= 1 && b >= 1) z = zk[g];
-      sRy[a][b] = vy;
-      sRx[a][b] = vx;
-      sPy[a][b] = qy;
-      sPx[a][b] = qx;
-      sZ[a][b] = z;
+    }
+  };
+  if (k0 < k1) box_load(k0);
+  for (int k = k0; k < k1; ++k) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int e = t + 256 * it;
+      if (e < kB2) {
+        const int a = e / kBX, b = e - a * kBX;
+        sRy[a][b] = nb[it].vy;
+        sRx[a][b] = nb[it].vx;
+        sPy[a][b] = nb[it].qy;
+        sPx[a][b] = nb[it].qx;
+        sZ[a][b] = nb[it].z;
+      }
     }
     __syncthreads();
+    if (k + 1 < k1) box_load(k + 1);   // in flight during this tangent's phases
     // phase B: u_i on rows / cols 1 .. TY+3 / TX+3
     for (int e = t; e < kB2; e += 256) {
       const int a = e / kBX, b = e - a * kBX;
