@@ -286,6 +286,36 @@ def plain_leg(torch, np, dev, prob, ref, max_probes=1024, check=None):
     return res
 
 
+def stream_ceiling(torch, dev):
+    """Practical HBM rates of plain torch streams over 2 GiB buffers (fill,
+    copy, sum, axpy): the ceiling a streaming kernel can reach on this GPU,
+    beside the published 8 TB/s."""
+    n = 1 << 28
+    a = torch.empty(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.fill_(2.0)
+    torch.cuda.synchronize()
+
+    def rate(fn, nbytes, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9, 1)
+
+    nb = n * 8
+    out = {"write_GBs": rate(lambda: a.fill_(3.0), nb), "copy_GBs": rate(lambda: b.copy_(a), 2 * nb),
+           "read_GBs": rate(lambda: a.sum(), nb), "axpy_GBs": rate(lambda: b.add_(a, alpha=0.5), 3 * nb)}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def dense_leg(lib, torch, np, dev, prob, form=2, steps=3, ref=None):
     """The main workload with the dense per-column normal operator on the
     matrix cores: normal_form 2 (FP32 products) or 3 (FP16 products of split
@@ -898,6 +928,7 @@ def main():
     }
 
     # --- the same workload with the dense per-column operator on the matrix cores
+    ceiling = stream_ceiling(torch, dev)
     dense = dense_leg(lib, torch, np, dev, prob, form=2) if args.dense else None
     dense16 = dense_leg(lib, torch, np, dev, prob, form=3, ref=None if args.no_ref else ref) if args.dense else None
 
@@ -960,6 +991,7 @@ def main():
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
         "kernel_launches": {k: v[1] for k, v in prof.items()},
         "roofline": roofline, "cpu_baseline": cpu,
+        "hbm_stream_ceiling": ceiling,
         "dense_form": dense,
         "dense_form_split_fp16": dense16,
         "spiral": spiral,
