@@ -71,11 +71,13 @@ def test_empty_range_and_single_probe_tiles(lib):
     assert e < TOL
 
 
-def test_largest_phase_encode_length(lib):
-    say("case: phase-encode 512x512 (largest column FFT), 2 coils R=2 + 24 ACS, 4 probes, CG 20")
+@pytest.mark.parametrize("form", [0, 3])
+def test_largest_phase_encode_length(lib, form):
+    say(f"case: phase-encode 512x512 (largest column FFT, largest dense block), 2 coils R=2 + 24 ACS, "
+        f"4 probes, CG 20, normal form {form}")
     prob = workloads.config(2, seed=7, ny=512, nx=512, nc=2, acs=24, cg_iters=20)
     h = lib.pico_init(512, 512, _dev(prob.maps.astype(np.complex64)), prob.psi, _dev(prob.mask),
-                      cg_iters=20, probe_tile=4)
+                      cg_iters=20, probe_tile=4, normal_form=form)
     t = _acc(512 * 512)
     lib.pico_noise_map(h, 8, 0, 4, 0, lib.make_accum(*t))
     torch.cuda.synchronize()
@@ -131,13 +133,15 @@ def test_single_line_mask_with_tikhonov(lib):
         assert e < TOL
 
 
-def test_empty_mask_reports_breakdown(lib):
-    say("case: no sampled line (M = 0), lambda 0: every CG right-hand side breaks down at once; "
-        "PICO_ENOTCONV with all probes frozen, the map written as zeros")
+@pytest.mark.parametrize("form", [0, 2, 3])
+def test_empty_mask_reports_breakdown(lib, form):
+    say(f"case: no sampled line (M = 0), lambda 0: every CG right-hand side breaks down at once; "
+        f"PICO_ENOTCONV with all probes frozen, the map written as zeros; normal form {form} "
+        f"(dense blocks of zeros)")
     rng = np.random.default_rng(4)
     maps = workloads.coil_maps(64, 16, 1, rng)
     h = lib.pico_init(64, 16, _dev(maps.astype(np.complex64)), None, _dev(np.zeros(64, np.uint8)),
-                      cg_iters=10, probe_tile=4)
+                      cg_iters=10, probe_tile=4, normal_form=form)
     t = _acc(64 * 16)
     st = lib.pico_stats_t()
     with pytest.raises(lib.PicoError) as ei:

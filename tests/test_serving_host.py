@@ -99,6 +99,27 @@ def test_estimate_validates(p):
     assert ei.value.status == p.PICO_EINVAL
 
 
+def test_estimate_validates_normal_form(p):
+    # the dense forms need a phase-encode mask and ny a multiple of 32 in 64..512
+    ok, _ = p.make_desc(96, 40, 0x1000, None, 0x2000, ncoils=4, normal_form=3)
+    p.pico_estimate_bytes(ok)
+    for form in (2, 3):
+        for ny in (100, 32, 544):
+            d, _ = p.make_desc(ny, 40, 0x1000, None, 0x2000, ncoils=4, normal_form=form)
+            with pytest.raises(p.PicoError) as ei:
+                p.pico_estimate_bytes(d)
+            assert ei.value.status == p.PICO_EINVAL
+        d, _ = p.make_desc(96, 40, 0x1000, None, 0x2000, ncoils=4, sampling=p.PICO_CART_2D, normal_form=form)
+        with pytest.raises(p.PicoError) as ei:
+            p.pico_estimate_bytes(d)
+        assert ei.value.status == p.PICO_EINVAL
+    for bad in (-1, 4):
+        d, _ = p.make_desc(96, 40, 0x1000, None, 0x2000, ncoils=4, normal_form=bad)
+        with pytest.raises(p.PicoError) as ei:
+            p.pico_estimate_bytes(d)
+        assert ei.value.status == p.PICO_EINVAL
+
+
 def test_estimate_tv_counts_projection_data(p):
     kw = dict(ncoils=8, probe_tile=16, sampling=p.PICO_CART_2D, recon=p.PICO_CS_FISTA_TV, kdata=0x3000,
               fista_iters=50)
