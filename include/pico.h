@@ -135,8 +135,9 @@ typedef struct {
    * by powers of two per column block and per probe (the same device
    * memory as 2, plus nx * ceil(probe_tile / 32) * 32 ints of exponents);
    * 0 = the default (column FFTs).
-   * All give M to FP32 rounding (the split keeps ~22 significand bits of
-   * each operand); the PMR right-hand side always uses FFTs. */
+   * Forms 1 and 2 give M to FP32 rounding, form 3 to about 2.4 times that
+   * (the split keeps 22 significand bits of each operand); the PMR
+   * right-hand side always uses FFTs. */
   int32_t normal_form;
   /* PICO_CS_FISTA_TV: dual fast-gradient-projection steps per proximal step
    * (Beck and Teboulle 2009), from a zero dual start each FISTA iteration,

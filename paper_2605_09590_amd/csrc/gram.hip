@@ -301,10 +301,10 @@ __global__ __launch_bounds__(SMALL ? 640 : 1024, SMALL ? 6 : 1) void k_cart1d_gr
 //     a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi
 // with FP32 accumulation (Ootomo and Yokota, IJHPCA 2022, "Recovering single
 // precision accuracy from Tensor Cores while surpassing the FP32 theoretical
-// peak performance").  The split keeps ~22 of FP32's 24 significand bits and
-// the dropped a_lo b_lo is below 2^-22 |a b|, the FP32 level of the other
-// forms.  Both operands are scaled by powers of two (exact) so that their
-// largest magnitude lies in [2^14, 2^15): the block of a column by its
+// peak performance").  The split keeps 22 of FP32's 24 significand bits and
+// the dropped a_lo b_lo is below 2^-22 |a b|: per product about 2.4 times the
+// error of an FP32 product.  Both operands are scaled by powers of two
+// (exact) so that their largest magnitude lies in [2^14, 2^15): the block of a column by its
 // largest diagonal entry (M_x is Hermitian positive semidefinite, so
 // |M_x[i][j]| <= max_i M_x[i][i]), each probe of the tile by its largest
 // component.  No part then overflows, and the low parts stay normal FP16
