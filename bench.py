@@ -608,7 +608,7 @@ def cs_leg(lib, workloads, torch, np, dev, steps, storage=0):
     }
 
 
-def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000):
+def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr=True):
     """The paper's CS model (Sec. 3.2.3): TV-regularised FISTA, 320 x 320, 15
     coils, Poisson-disc R=2, lambda_TV 1e-2, 100 iterations (10 dual steps per
     prox).  Jacobian probes per second (K per step) against FP64 PMR replicas
@@ -624,7 +624,8 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000):
     t0 = time.perf_counter()
     h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, sampling=lib.PICO_CART_2D,
                       recon=lib.PICO_CS_FISTA_TV, kdata=kd, fista_iters=pr.extra["fista_iters"],
-                      cs_lambda=pr.extra["cs_lambda"], tv_inner_iters=pr.extra["tv_inner"], probe_tile=K)
+                      cs_lambda=pr.extra["cs_lambda"], tv_inner_iters=pr.extra["tv_inner"], probe_tile=K,
+                      storage=storage)
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t0
     resident, _ = lib.pico_op_bytes(h)
@@ -642,18 +643,21 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000):
     ms = e0.elapsed_time(e1) / steps
     # PMR: one batch of FP64 replicas (the finite difference at a small sigma needs FP64)
     nrep = 16
-    pacc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)])
-    lib.pico_pmr_cs(h, 5, 0, 4, 1e-3, pacc)                  # workspace + warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lib.pico_pmr_cs(h, 5, 4, nrep, 1e-3, pacc)
-    torch.cuda.synchronize()
-    pmr_s = (time.perf_counter() - t0) / nrep
+    pmr_s = None
+    if pmr:
+        pacc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)])
+        lib.pico_pmr_cs(h, 5, 0, 4, 1e-3, pacc)                  # workspace + warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lib.pico_pmr_cs(h, 5, 4, nrep, 1e-3, pacc)
+        torch.cuda.synchronize()
+        pmr_s = (time.perf_counter() - t0) / nrep
     lib.pico_destroy(h)
     jvps = K / (ms / 1e3)
     it_ms, it_n = prof["normal_iter"]
     op_s = it_ms / it_n / 1e3
-    alg = K * (4 * pr.nc * n * 8 + 2 * n * 8) + 2 * pr.nc * n * 8   # as the CS leg's (complex64)
+    eb = 4 if storage == lib.PICO_BF16_STREAM else 8
+    alg = K * (4 * pr.nc * n * eb + 2 * n * 8) + 2 * pr.nc * n * (4 if storage else 8)   # as the CS leg's
     # the TV tangent (the rest of the step): per prox, the first launch of dual
     # steps (one step when the count is odd, else a pair) starts from zero,
     # reads dz and writes dr, dp (40 B per tangent and pixel); each later pair
@@ -668,10 +672,11 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000):
                     f"FISTA {pr.extra['fista_iters']} its x {pr.extra['tv_inner']} dual steps, lambda_TV "
                     f"{pr.extra['cs_lambda']}, K={K} JVP probes per step",
         "jvps_per_s": round(jvps, 2), "ms_per_step": round(ms, 3), "init_s": round(init_s, 3),
+        "storage": ["f32", "bf16 maps", "bf16 maps + planes"][storage],
         "resident_bytes": int(resident),
-        "pmr_replicas_per_s": round(1.0 / pmr_s, 2), "pmr_precision": "f64",
+        "pmr_replicas_per_s": round(1.0 / pmr_s, 2) if pmr_s else None, "pmr_precision": "f64",
         "n_converged": n_conv,
-        "pico_s_at_n": round(n_conv / jvps, 2), "pmr_s_at_n": round(n_conv * pmr_s, 2),
+        "pico_s_at_n": round(n_conv / jvps, 2), "pmr_s_at_n": round(n_conv * pmr_s, 2) if pmr_s else None,
         "roofline": {"bound": "hbm", "achieved": round(alg / op_s / 1e9, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(alg / op_s / 1e9 / PEAK_HBM_GBS, 4),
                      "kernel": "grid normal operator (rows_fwd + cols + rows_inv), C1_APPLY",
@@ -950,9 +955,11 @@ def main():
         cs_bf16 = cs_leg(lib, workloads, torch, np, dev, args.cs_steps, lib.PICO_BF16_STREAM)
 
     # --- the paper's CS model: TV-regularised FISTA, Jacobian probes vs FP64 PMR replicas
-    cs_tv = None
+    cs_tv = cs_tv_bf16 = None
     if args.cs_tv_steps > 0:
         cs_tv = cs_tv_leg(lib, workloads, torch, np, dev, args.cs_tv_steps)
+        cs_tv_bf16 = cs_tv_leg(lib, workloads, torch, np, dev, args.cs_tv_steps, storage=lib.PICO_BF16_STREAM,
+                               pmr=False)
 
     robust = (cs_robustness(lib, workloads, torch, np, dev, reg=args.cs_robustness)
               if args.cs_robustness != "off" else None)
@@ -1000,6 +1007,7 @@ def main():
         "cs": cs_res,
         "cs_bf16": cs_bf16,
         "cs_tv": cs_tv,
+        "cs_tv_bf16": cs_tv_bf16,
         "serving": serving,
     }
     if robust is not None:

@@ -170,6 +170,45 @@ def test_bf16_cs_jvp(lib, storage):
         assert eq < (TOL if storage == 1 else TOL_BF16)
 
 
+@pytest.mark.parametrize("storage", [1, 2])
+def test_bf16_tv_cs_jvp(lib, storage):
+    say(f"case: TV-CS 64x96, 4 coils, Poisson-disc R=2 (8x8 calib), lam_TV 1e-2, FISTA 30 x 10 dual "
+        f"steps; recon and 2 JVPs, storage {storage}")
+    rng = np.random.default_rng(5)
+    maps = workloads.coil_maps(64, 96, 4, rng)
+    psi = workloads.noise_cov(4, rng)
+    x = workloads.phantom(96, rng)[:64, :96]
+    mask = workloads.poisson_disc_mask(64, 96, 2.0, 8, seed=5)
+    op = opico.cartesian(maps, psi, mask)
+    bw = op.forward(x)
+    bw = bw + 1e-3 * op.P[None] * (rng.standard_normal(bw.shape) + 1j * rng.standard_normal(bw.shape))
+    braw = np.einsum("cd,dyx->cyx", np.linalg.cholesky(psi), bw)
+    h = lib.pico_init(64, 96, _dev(maps.astype(np.complex64)), psi, _dev(mask), sampling=lib.PICO_CART_2D,
+                      recon=lib.PICO_CS_FISTA_TV, kdata=_dev(braw.astype(np.complex64)), fista_iters=30,
+                      cs_lambda=1e-2, tv_inner_iters=10, probe_tile=2, storage=storage)
+    w = np.stack([ocs.kspace_probe(op, 8, i) for i in range(2)])
+    ut = torch.empty((2, 64, 96), dtype=torch.complex64, device="cuda:0")
+    lib.pico_apply_jvp(h, _dev(w.astype(np.complex64)), ut, 2)
+    xg = torch.empty((64, 96), dtype=torch.complex64, device="cuda:0")
+    lib.pico_recon(h, xg)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    fq = ocs.FistaTV(opico.cartesian(ostore.bf16_whitened_maps(maps, psi), None, mask), 1e-2, 30, 10)
+    f = ocs.FistaTV(op, 1e-2, 30, 10)
+    xq, zq = fq.recon(bw, store=True)
+    xr, zr = f.recon(bw, store=True)
+    eq, e = _rel(xg.cpu().numpy(), xq), _rel(xg.cpu().numpy(), xr)
+    say(f"  reconstruction: vs rounded-map oracle {eq:.2e}; vs FP64 maps {e:.2e}")
+    assert eq < TOL and e < TOL_BF16
+    # as for the L1 model: the bar is against the rounded-map oracle (storage 1),
+    # the plane rounding of storage 2 perturbs the tangents alone (1e-2 bar)
+    u = ut.cpu().numpy()
+    for k in range(2):
+        eq, e = _rel(u[k], fq.jvp(w[k], zq)), _rel(u[k], f.jvp(w[k], zr))
+        say(f"  jvp probe {k}: vs rounded-map oracle {eq:.2e}; vs FP64 maps {e:.2e} (reported)")
+        assert eq < (TOL if storage == 1 else TOL_BF16)
+
+
 def test_bf16_stream_spiral_full_size(lib):
     say("case: spiral 256x256, 16 coils, 48x4096 R=2 (98304 samples), lambda 0.1, CG 30, K=256 in one "
         "launch, bfloat16 maps and planes; apply_cov on probes 0 and 255 checked")
