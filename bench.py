@@ -658,14 +658,24 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     op_s = it_ms / it_n / 1e3
     eb = 4 if storage == lib.PICO_BF16_STREAM else 8
     alg = K * (4 * pr.nc * n * eb + 2 * n * 8) + 2 * pr.nc * n * (4 if storage else 8)   # as the CS leg's
-    # the TV tangent (the rest of the step): per prox, the first launch of dual
-    # steps (one step when the count is odd, else a pair) starts from zero,
-    # reads dz and writes dr, dp (40 B per tangent and pixel); each later pair
-    # reads dz, dr, dp and writes dr, dp (72 B).  The projection data (20 B per
-    # pixel and step) is shared by the tangents of a workgroup and not counted.
+    # the TV tangent (the rest of the step): per prox, the library runs one
+    # single step first when the count is odd, then passes of four dual steps
+    # while four remain, then pairs.  The first pass starts from zero, reads dz
+    # and writes dr, dp (40 B per tangent and pixel); each later pass reads dz,
+    # dr, dp and writes dr, dp (72 B).  The projection data (20 B per pixel and
+    # step) is shared by the tangents of a workgroup and not counted.
     inner, T = pr.extra["tv_inner"], pr.extra["fista_iters"]
-    later = inner // 2 if inner % 2 else inner // 2 - 1
-    tv_bytes = T * K * n * (40 + 72 * later)
+    passes, it = [], 0
+    if inner % 2:
+        passes.append(1)
+        it = 1
+    while inner - it >= 4 and min(pr.ny, pr.nx) >= 24:
+        passes.append(4)
+        it += 4
+    while it < inner:
+        passes.append(2)
+        it += 2
+    tv_bytes = T * K * n * (40 + 72 * (len(passes) - 1))
     tv_s = prof["other"][0] / 1e3 / steps
     return {
         "workload": f"TV-CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2 (24x24 calib), "
@@ -681,7 +691,8 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
                      "unit": "GB/s", "frac": round(alg / op_s / 1e9 / PEAK_HBM_GBS, 4),
                      "kernel": "grid normal operator (rows_fwd + cols + rows_inv), C1_APPLY",
                      "avg_application_us": round(op_s * 1e6, 1), "alg_bytes": alg},
-        "tv_tangent": {"bound": "hbm", "ms_per_step": round(tv_s * 1e3, 3), "alg_bytes_per_step": tv_bytes,
+        "tv_tangent": {"bound": "hbm", "ms_per_step": round(tv_s * 1e3, 3), "passes_per_prox": passes,
+                       "alg_bytes_per_step": tv_bytes,
                        "achieved_GBs": round(tv_bytes / tv_s / 1e9, 1),
                        "frac": round(tv_bytes / tv_s / 1e9 / PEAK_HBM_GBS, 4),
                        "note": "time of the step outside the normal-operator applications: the dual-step "

@@ -226,99 +226,132 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
   }
 }
 
-// Two tangent inner steps i and i+1 in one pass over a TY x TX tile T:
-// step i on T grown by one pixel on every side (B1), then step i+1 on T.
-// Inputs on the grown boxes (LDS, coordinates of the box B2 = T grown by 2,
-// index [a][b] = pixel (y0 - 2 + a, x0 - 2 + b), periodic):
-//   r_i on B2, p_i on B1, dz on B1 grown by one towards +y / +x.
-// Step i:   u_i = dz - lam D^H r_i (B1 and its +y / +x neighbours),
-//           p_{i+1} = dP_i(r_i + c8 D u_i), r_{i+1} = p_{i+1} + th_i (p_{i+1} - p_i)   on B1;
-// step i+1: u_{i+1} on T and its +y / +x neighbours, then p_{i+2}, r_{i+2} on T.
-// r and p are read from (rA, pA) and written to (rB, pB): neighbouring tiles
-// read the halo of both.  first: r_i = p_i = 0 (step 0 from the zero start).
-// Needs ny >= TY + 4 and nx >= TX + 4 (the halo wraps at most once).
-constexpr int kBY = kTY + 4, kBX = kTX + 4;         // box B2
-constexpr int kB2 = kBY * kBX;
+// S tangent inner steps i .. i+S-1 in one pass over a TY x TX tile T
+// (S = 2 on 8 x 32 tiles, S = 4 on 16 x 16).  The LDS box B is T grown by S on
+// every side, index [a][b] = pixel (y0 - S + a, x0 - S + b), periodic.  Step
+// s (from 0) updates r and p on R_s = rows [s+1, BY-2-s] x cols [s+1, BX-2-s]
+// from u_s = dz - lam D^H r_s on U_s = R_s grown by one towards +y / +x; u_s
+// reads r on R_{s-1} (the whole box for s = 0), so R_{S-1} = T:
+//   w = r_s + c8 D u_s,  p_{s+1} = dP_s(w),  r_{s+1} = p_{s+1} + th_s (p_{s+1} - p_s).
+// Inputs: r_i on B, p_i on R_0, dz on U_0; the projection data of steps
+// s < S-1 on R_s (LDS, shared by the block's tangents), of the last step at
+// the thread's own pixel.  r and p are read from (rA, pA) and the last step's
+// written to (rB, pB): neighbouring tiles read the halo of both.  first: r_i =
+// p_i = 0 (step 0 from the zero start).  Tangent k + 1's box is loaded into
+// registers while tangent k's steps run.  Needs ny >= TY + 2S and nx >= TX + 2S
+// (the halo wraps at most once).
+template <int S, int TY, int TX>
+struct TvSteps {
+  static constexpr int BY = TY + 2 * S, BX = TX + 2 * S, NB = BY * BX;
+  static constexpr int NPT = (NB + 255) / 256;   // box points per thread
+  __host__ __device__ static constexpr int ry(int s) { return BY - 2 - 2 * s; }   // R_s rows
+  __host__ __device__ static constexpr int rx(int s) { return BX - 2 - 2 * s; }   // R_s cols
+  __host__ __device__ static constexpr int proj_off(int s) {
+    int o = 0;
+    for (int q = 0; q < s; ++q) o += ry(q) * rx(q);
+    return o;
+  }
+  static constexpr int NPROJ = proj_off(S - 1) > 0 ? proj_off(S - 1) : 1;   // steps 0 .. S-2
+};
 
-__global__ __launch_bounds__(256) void k_tv_inner2(const float2* __restrict__ dz, const float2* __restrict__ rA,
-                                                   float2* __restrict__ rB, const float2* __restrict__ pA,
-                                                   float2* __restrict__ pB, const float4* __restrict__ what0,
-                                                   const float* __restrict__ invn0, const float4* __restrict__ what1,
-                                                   const float* __restrict__ invn1, int ny, int nx, int K, int kper,
-                                                   float lam, float c8, float th0, float th1, int first) {
-  __shared__ float2 sRy[kBY][kBX], sRx[kBY][kBX];   // r_i, then r_{i+1} (in place)
-  __shared__ float2 sPy[kBY][kBX], sPx[kBY][kBX];   // p_i, then p_{i+1} (in place)
-  __shared__ float2 sZ[kBY][kBX];                   // dz
-  __shared__ float2 sU[kBY][kBX];                   // u_i, then u_{i+1}
-  __shared__ float4 sW[kBY][kBX];                   // projection data of step i (w^)
-  __shared__ float sV[kBY][kBX];                    // and 1/|w|
+struct TvTheta {
+  float th[4];
+};
+
+template <int S, int TY, int TX>
+__global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz, const float2* __restrict__ rA,
+                                                  float2* __restrict__ rB, const float2* __restrict__ pA,
+                                                  float2* __restrict__ pB, const float4* __restrict__ what,
+                                                  const float* __restrict__ invn, int ny, int nx, int K, int kper,
+                                                  float lam, float c8, TvTheta th, int first) {
+  using C = TvSteps<S, TY, TX>;
+  constexpr int BY = C::BY, BX = C::BX, NB = C::NB, NPT = C::NPT;
+  static_assert(TY * TX == 256, "one output pixel per thread");
+  __shared__ float2 sRy[BY][BX], sRx[BY][BX];   // r_s (in place)
+  __shared__ float2 sPy[BY][BX], sPx[BY][BX];   // p_s (in place)
+  __shared__ float2 sZ[BY][BX];                 // dz
+  __shared__ float2 sU[BY][BX];                 // u_s
+  __shared__ float4 sW[C::NPROJ];               // projection data of steps 0 .. S-2 on R_s (w^)
+  __shared__ float sV[C::NPROJ];                // and 1/|w|
   const long n = (long)ny * nx;
-  const int tilesx = (nx + kTX - 1) / kTX;
-  const int y0 = (int)(blockIdx.x / tilesx) * kTY, x0 = (int)(blockIdx.x % tilesx) * kTX;
+  const int tilesx = (nx + TX - 1) / TX;
+  const int y0 = (int)(blockIdx.x / tilesx) * TY, x0 = (int)(blockIdx.x % tilesx) * TX;
   const int t = threadIdx.x;
   const bool fst = first != 0;
-  auto gidx = [&](int a, int b) { return (long)wrap(y0 - 2 + a, ny) * nx + wrap(x0 - 2 + b, nx); };
-  // projection data of step i on B1 (box rows / cols 1 .. TY+2 / TX+2), shared by all tangents
-  for (int e = t; e < kB2; e += 256) {
-    const int a = e / kBX, b = e - a * kBX;
-    if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
+  auto gidx = [&](int a, int b) { return (long)wrap(y0 - S + a, ny) * nx + wrap(x0 - S + b, nx); };
+  // projection data of steps 0 .. S-2 on their regions (step s at what + s n)
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s) {
+    const int RY = C::ry(s), RX = C::rx(s), off = C::proj_off(s);
+    for (int e = t; e < RY * RX; e += 256) {
+      const int a = s + 1 + e / RX, b = s + 1 + e % RX;
       const long g = gidx(a, b);
-      sW[a][b] = what0[g];
-      sV[a][b] = invn0[g];
+      sW[off + e] = what[(size_t)s * n + g];
+      sV[off + e] = invn[(size_t)s * n + g];
     }
   }
-  // own pixel: step i+1's projection data
-  const int ty = t / kTX, tx = t % kTX;
+  // own pixel: the last step's projection data
+  const int ty = t / TX, tx = t % TX;
   const int y = y0 + ty, x = x0 + tx;
   const bool own = y < ny && x < nx;
   const long i = (long)y * nx + x;
-  float4 wh1 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float iv1 = 1.f;
+  float4 whl = make_float4(0.f, 0.f, 0.f, 0.f);
+  float ivl = 1.f;
   if (own) {
-    wh1 = what1[i];
-    iv1 = invn1[i];
+    whl = what[(size_t)(S - 1) * n + i];
+    ivl = invn[(size_t)(S - 1) * n + i];
   }
   const int k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
-  // phase A: a tangent's box values (r on B2, p on B1, dz on rows / cols >= 1)
-  // for this thread's points e = t, t + 256; tangent k + 1's are loaded into
-  // registers while tangent k's phases run, and stored to LDS at the top of
-  // the next pass
-  static_assert(kB2 <= 512, "two box points per thread");
   struct BoxPt {
     float2 vy, vx, qy, qx, z;
   };
-  BoxPt nb[2];
+  BoxPt nb[NPT];
   auto box_load = [&](int k) {
     const float2* zk = dz + (size_t)k * n;
-    const float2* ry = rA + (size_t)k * 2 * n;
-    const float2* py = pA + (size_t)k * 2 * n;
+    const float2* ryk = rA + (size_t)k * 2 * n;
+    const float2* pyk = pA + (size_t)k * 2 * n;
     const float2 zero = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < NPT; ++it) {
       const int e = t + 256 * it;
       nb[it].vy = nb[it].vx = nb[it].qy = nb[it].qx = nb[it].z = zero;
-      if (e < kB2) {
-        const int a = e / kBX, b = e - a * kBX;
+      if (e < NB) {
+        const int a = e / BX, b = e - a * BX;
         const long g = gidx(a, b);
         if (!fst) {
-          nb[it].vy = ry[g];
-          nb[it].vx = ry[n + g];
-          if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
-            nb[it].qy = py[g];
-            nb[it].qx = py[n + g];
+          nb[it].vy = ryk[g];
+          nb[it].vx = ryk[n + g];
+          if (a >= 1 && a <= BY - 2 && b >= 1 && b <= BX - 2) {   // R_0
+            nb[it].qy = pyk[g];
+            nb[it].qx = pyk[n + g];
           }
         }
-        if (a >= 1 && b >= 1) nb[it].z = zk[g];
+        if (a >= 1 && b >= 1) nb[it].z = zk[g];                  // U_0
       }
     }
+  };
+  // u_s at (a, b): dz - lam D^H r
+  auto u_at = [&](int a, int b) {
+    const float hx = sRy[a - 1][b].x - sRy[a][b].x + sRx[a][b - 1].x - sRx[a][b].x;
+    const float hy = sRy[a - 1][b].y - sRy[a][b].y + sRx[a][b - 1].y - sRx[a][b].y;
+    return make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
+  };
+  // dP(w) dw for w = r + c8 D u at (a, b): (qy, qx)
+  auto proj_at = [&](int a, int b, float4 wh, float iv, float2& qy, float2& qx) {
+    const float2 u0 = sU[a][b], uy = sU[a + 1][b], ux = sU[a][b + 1];
+    const float2 wy = make_float2(fmaf(c8, uy.x - u0.x, sRy[a][b].x), fmaf(c8, uy.y - u0.y, sRy[a][b].y));
+    const float2 wx = make_float2(fmaf(c8, ux.x - u0.x, sRx[a][b].x), fmaf(c8, ux.y - u0.y, sRx[a][b].y));
+    const float re = wh.x * wy.x + wh.y * wy.y + wh.z * wx.x + wh.w * wx.y;   // Re(w^H dw)
+    qy = make_float2((wy.x - wh.x * re) * iv, (wy.y - wh.y * re) * iv);
+    qx = make_float2((wx.x - wh.z * re) * iv, (wx.y - wh.w * re) * iv);
   };
   if (k0 < k1) box_load(k0);
   for (int k = k0; k < k1; ++k) {
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < NPT; ++it) {
       const int e = t + 256 * it;
-      if (e < kB2) {
-        const int a = e / kBX, b = e - a * kBX;
+      if (e < NB) {
+        const int a = e / BX, b = e - a * BX;
         sRy[a][b] = nb[it].vy;
         sRx[a][b] = nb[it].vx;
         sPy[a][b] = nb[it].qy;
@@ -327,65 +360,45 @@ __global__ __launch_bounds__(256) void k_tv_inner2(const float2* __restrict__ dz
       }
     }
     __syncthreads();
-    if (k + 1 < k1) box_load(k + 1);   // in flight during this tangent's phases
-    // phase B: u_i on rows / cols 1 .. TY+3 / TX+3
-    for (int e = t; e < kB2; e += 256) {
-      const int a = e / kBX, b = e - a * kBX;
-      if (a >= 1 && b >= 1) {
-        const float hx = sRy[a - 1][b].x - sRy[a][b].x + sRx[a][b - 1].x - sRx[a][b].x;
-        const float hy = sRy[a - 1][b].y - sRy[a][b].y + sRx[a][b - 1].y - sRx[a][b].y;
-        sU[a][b] = make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
+    if (k + 1 < k1) box_load(k + 1);   // in flight during this tangent's steps
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      {   // u_s on U_s = rows [s+1, BY-1-s] x cols [s+1, BX-1-s]
+        const int UY = BY - 1 - 2 * s, UX = BX - 1 - 2 * s;
+        for (int e = t; e < UY * UX; e += 256) {
+          const int a = s + 1 + e / UX, b = s + 1 + e % UX;
+          sU[a][b] = u_at(a, b);
+        }
       }
-    }
-    __syncthreads();
-    // phase C: step i on B1; r and p replaced in place (each point reads only itself)
-    for (int e = t; e < kB2; e += 256) {
-      const int a = e / kBX, b = e - a * kBX;
-      if (a >= 1 && a <= kTY + 2 && b >= 1 && b <= kTX + 2) {
-        const float2 u0 = sU[a][b], uy = sU[a + 1][b], ux = sU[a][b + 1];
-        const float2 wy = make_float2(fmaf(c8, uy.x - u0.x, sRy[a][b].x), fmaf(c8, uy.y - u0.y, sRy[a][b].y));
-        const float2 wx = make_float2(fmaf(c8, ux.x - u0.x, sRx[a][b].x), fmaf(c8, ux.y - u0.y, sRx[a][b].y));
-        const float4 wh = sW[a][b];
-        const float iv = sV[a][b];
-        const float re = wh.x * wy.x + wh.y * wy.y + wh.z * wx.x + wh.w * wx.y;
-        const float2 qy = make_float2((wy.x - wh.x * re) * iv, (wy.y - wh.y * re) * iv);
-        const float2 qx = make_float2((wx.x - wh.z * re) * iv, (wx.y - wh.w * re) * iv);
+      __syncthreads();
+      if (s < S - 1) {   // step s on R_s; r and p replaced in place (each point reads only itself)
+        const int RY = C::ry(s), RX = C::rx(s), off = C::proj_off(s);
+        const float ths = th.th[s];
+        for (int e = t; e < RY * RX; e += 256) {
+          const int a = s + 1 + e / RX, b = s + 1 + e % RX;
+          float2 qy, qx;
+          proj_at(a, b, sW[off + e], sV[off + e], qy, qx);
+          const float2 oy = sPy[a][b], ox = sPx[a][b];
+          sRy[a][b] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
+          sRx[a][b] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
+          sPy[a][b] = qy;
+          sPx[a][b] = qx;
+        }
+      } else if (own) {   // the last step on T, written out
+        const int a = S + ty, b = S + tx;
+        float2 qy, qx;
+        proj_at(a, b, whl, ivl, qy, qx);
         const float2 oy = sPy[a][b], ox = sPx[a][b];
-        sRy[a][b] = make_float2(fmaf(th0, qy.x - oy.x, qy.x), fmaf(th0, qy.y - oy.y, qy.y));
-        sRx[a][b] = make_float2(fmaf(th0, qx.x - ox.x, qx.x), fmaf(th0, qx.y - ox.y, qx.y));
-        sPy[a][b] = qy;
-        sPx[a][b] = qx;
+        const float ths = th.th[S - 1];
+        float2* rb = rB + (size_t)k * 2 * n;
+        float2* pb = pB + (size_t)k * 2 * n;
+        rb[i] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
+        rb[n + i] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
+        pb[i] = qy;
+        pb[n + i] = qx;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    // phase D: u_{i+1} on rows / cols 2 .. TY+2 / TX+2 (T and its +y / +x neighbours)
-    for (int e = t; e < kB2; e += 256) {
-      const int a = e / kBX, b = e - a * kBX;
-      if (a >= 2 && a <= kTY + 2 && b >= 2 && b <= kTX + 2) {
-        const float hx = sRy[a - 1][b].x - sRy[a][b].x + sRx[a][b - 1].x - sRx[a][b].x;
-        const float hy = sRy[a - 1][b].y - sRy[a][b].y + sRx[a][b - 1].y - sRx[a][b].y;
-        sU[a][b] = make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
-      }
-    }
-    __syncthreads();
-    // phase E: step i+1 on T, written out
-    if (own) {
-      const int a = ty + 2, b = tx + 2;
-      const float2 u0 = sU[a][b], uy = sU[a + 1][b], ux = sU[a][b + 1];
-      const float2 wy = make_float2(fmaf(c8, uy.x - u0.x, sRy[a][b].x), fmaf(c8, uy.y - u0.y, sRy[a][b].y));
-      const float2 wx = make_float2(fmaf(c8, ux.x - u0.x, sRx[a][b].x), fmaf(c8, ux.y - u0.y, sRx[a][b].y));
-      const float re = wh1.x * wy.x + wh1.y * wy.y + wh1.z * wx.x + wh1.w * wx.y;
-      const float2 qy = make_float2((wy.x - wh1.x * re) * iv1, (wy.y - wh1.y * re) * iv1);
-      const float2 qx = make_float2((wx.x - wh1.z * re) * iv1, (wx.y - wh1.w * re) * iv1);
-      const float2 oy = sPy[a][b], ox = sPx[a][b];
-      float2* rb = rB + (size_t)k * 2 * n;
-      float2* pb = pB + (size_t)k * 2 * n;
-      rb[i] = make_float2(fmaf(th1, qy.x - oy.x, qy.x), fmaf(th1, qy.y - oy.y, qy.y));
-      rb[n + i] = make_float2(fmaf(th1, qx.x - ox.x, qx.x), fmaf(th1, qx.y - ox.y, qx.y));
-      pb[i] = qy;
-      pb[n + i] = qx;
-    }
-    __syncthreads();
   }
 }
 
@@ -429,6 +442,20 @@ hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what,
   return hipGetLastError();
 }
 
+template <int S, int TY, int TX>
+static void launch_tv_steps(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB, const float4* what,
+                            const float* invn, const float* th, int ny, int nx, int K, float lam, float c8, int first,
+                            hipStream_t s) {
+  const int tiles = ((ny + TY - 1) / TY) * ((nx + TX - 1) / TX);
+  int kper = 8;
+  while (kper > 1 && (long)tiles * ((K + kper - 1) / kper) < 2048) kper >>= 1;
+  const dim3 grid((unsigned)tiles, (unsigned)((K + kper - 1) / kper));
+  TvTheta tt{};
+  for (int q = 0; q < S; ++q) tt.th[q] = th[q];
+  hipLaunchKernelGGL((k_tv_steps<S, TY, TX>), grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what, invn, ny, nx, K,
+                     kper, lam, c8, tt, first);
+}
+
 hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
                            const float4* what, const float* invn, int ny, int nx, int K, int inner,
                            const float* th, float lam, float2** dp_out, hipStream_t s) {
@@ -446,10 +473,17 @@ hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* d
     std::swap(drA, drB);
     it = 1;
   }
+  // four steps per pass while four remain (16 x 16 tiles, halo 4), then pairs
+  const bool four = ny >= 16 + 8 && nx >= 16 + 8;
+  for (; four && inner - it >= 4; it += 4) {
+    launch_tv_steps<4, 16, 16>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it, ny, nx,
+                               K, lam, c8, it == 0 ? 1 : 0, s);
+    std::swap(drA, drB);
+    std::swap(dpA, dpB);
+  }
   for (; it < inner; it += 2) {
-    hipLaunchKernelGGL(k_tv_inner2, grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what + (size_t)it * n,
-                       invn + (size_t)it * n, what + (size_t)(it + 1) * n, invn + (size_t)(it + 1) * n, ny, nx, K,
-                       kper, lam, c8, th[it], th[it + 1], it == 0 ? 1 : 0);
+    launch_tv_steps<2, kTY, kTX>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it, ny,
+                                 nx, K, lam, c8, it == 0 ? 1 : 0, s);
     std::swap(drA, drB);
     std::swap(dpA, dpB);
   }
