@@ -131,18 +131,126 @@ __global__ void k_idwt_x(const C* __restrict__ in, C* __restrict__ out, int ny, 
   out[img + (size_t)y * nx + m] = acc;
 }
 
-// Psi (forward) or Psi^H (inverse) of K images in place in buf, tmp as scratch
+// The first analysis level of the block (by, bx) of each image with both axes
+// in one pass through LDS, out of place (in -> out, the layout the two
+// one-axis passes leave: [a | d] along x, then along y).  A workgroup takes
+// 16 x 16 positions of each subband from input rows / cols 2 j0 .. 2 j0 + 37
+// (periodic in the block), so the level reads and writes the block once.
+constexpr int kWT = 16, kWIn = 2 * kWT + 6;
 template <class C>
-static hipError_t wavelet(C* buf, C* tmp, int K, int ny, int nx, int levels, bool inverse, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by,
+                                              int bx) {
+  using R = typename Real<C>::T;
+  __shared__ C sT[kWIn][kWIn + 1];     // input tile
+  __shared__ C sX[kWIn][2 * kWT + 1];  // after the x pass: [a | d], 16 each
+  const int hy = by / 2, hx = bx / 2;
+  const int tilesx = (hx + kWT - 1) / kWT;
+  const int j0 = (int)(blockIdx.x / tilesx) * kWT, i0 = (int)(blockIdx.x % tilesx) * kWT;
+  const size_t img = (size_t)blockIdx.y * ny * nx;
+  const int t = threadIdx.x;
+  for (int e = t; e < kWIn * kWIn; e += 256) {
+    const int a = e / kWIn, b = e % kWIn;
+    sT[a][b] = in[img + (size_t)((2 * j0 + a) % by) * nx + (2 * i0 + b) % bx];
+  }
+  __syncthreads();
+  for (int e = t; e < kWIn * kWT; e += 256) {
+    const int a = e / kWT, i = e % kWT;
+    C lo = czero<C>(), hi = czero<C>();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const C v = sT[a][2 * i + k];
+      lo = cfma(lo, wav_h<R>(k), v);
+      hi = cfma(hi, wav_g<R>(k), v);
+    }
+    sX[a][i] = lo;
+    sX[a][kWT + i] = hi;
+  }
+  __syncthreads();
+  for (int e = t; e < 2 * kWT * kWT; e += 256) {
+    const int j = e / (2 * kWT), c = e % (2 * kWT);   // c < 16: x-low column i = c, else x-high
+    C lo = czero<C>(), hi = czero<C>();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const C v = sX[2 * j + k][c];
+      lo = cfma(lo, wav_h<R>(k), v);
+      hi = cfma(hi, wav_g<R>(k), v);
+    }
+    const int gj = j0 + j, gi = i0 + c % kWT;
+    if (gj < hy && gi < hx) {
+      const int col = (c < kWT ? 0 : hx) + gi;
+      out[img + (size_t)gj * nx + col] = lo;
+      out[img + (size_t)(hy + gj) * nx + col] = hi;
+    }
+  }
+}
+
+// The last synthesis level of the block (by, bx) with both axes in one pass,
+// out of place: 32 x 32 output points per workgroup from 20 x 20 windows of
+// the four subbands (coefficient rows / cols m0 / 2 - 4 .. m0 / 2 + 15,
+// periodic in the half block), y synthesis into LDS, then x synthesis.
+constexpr int kST = 32, kSW = kST / 2 + 4;
+__device__ __forceinline__ int pmod(int v, int n) { return ((v % n) + n) % n; }
+template <class C>
+__global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by,
+                                               int bx) {
+  using R = typename Real<C>::T;
+  __shared__ C sC[2 * kSW][2 * kSW + 1];   // [y-low | y-high] x [x-low | x-high] windows
+  __shared__ C sY[kST][2 * kSW + 1];       // after the y synthesis: 32 rows x [x-low | x-high]
+  const int hy = by / 2, hx = bx / 2;
+  const int tilesx = (bx + kST - 1) / kST;
+  const int m0 = (int)(blockIdx.x / tilesx) * kST, c0 = (int)(blockIdx.x % tilesx) * kST;
+  const int wy = m0 / 2 - 4, wx = c0 / 2 - 4;   // window starts (periodic)
+  const size_t img = (size_t)blockIdx.y * ny * nx;
+  const int t = threadIdx.x;
+  for (int e = t; e < 4 * kSW * kSW; e += 256) {
+    const int a = e / (2 * kSW), b = e % (2 * kSW);
+    const int ry = a < kSW ? pmod(wy + a, hy) : hy + pmod(wy + a - kSW, hy);
+    const int rx = b < kSW ? pmod(wx + b, hx) : hx + pmod(wx + b - kSW, hx);
+    sC[a][b] = in[img + (size_t)ry * nx + rx];
+  }
+  __syncthreads();
+  // x[m] = sum over taps k = m (mod 2) of h[k] a[n] + g[k] d[n], n = (m - k) / 2
+  for (int e = t; e < kST * 2 * kSW; e += 256) {
+    const int mm = e / (2 * kSW), b = e % (2 * kSW), m = m0 + mm;
+    C acc = czero<C>();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 2 * kk + (m & 1);
+      const int ln = (m - k) / 2 - wy;   // 1 .. 19
+      acc = cfma(acc, wav_h<R>(k), sC[ln][b]);
+      acc = cfma(acc, wav_g<R>(k), sC[kSW + ln][b]);
+    }
+    sY[mm][b] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < kST * kST; e += 256) {
+    const int mm = e / kST, cc = e % kST, c = c0 + cc;
+    C acc = czero<C>();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 2 * kk + (c & 1);
+      const int ln = (c - k) / 2 - wx;
+      acc = cfma(acc, wav_h<R>(k), sY[mm][ln]);
+      acc = cfma(acc, wav_g<R>(k), sY[mm][kSW + ln]);
+    }
+    if (m0 + mm < by && c < bx) out[img + (size_t)(m0 + mm) * nx + c] = acc;
+  }
+}
+
+// Psi (forward) or Psi^H (inverse) of K images in place in buf, tmp as scratch
+// levels l0 .. levels - 1 only (the block of level l is (ny >> l) x (nx >> l))
+template <class C>
+static hipError_t wavelet_levels(C* buf, C* tmp, int K, int ny, int nx, int l0, int levels, bool inverse,
+                                 hipStream_t s) {
   auto grid_for = [&](long work) { return dim3((unsigned)((work + 255) / 256), K); };
   if (!inverse) {
-    for (int l = 0; l < levels; ++l) {
+    for (int l = l0; l < levels; ++l) {
       const int by = ny >> l, bx = nx >> l;
       hipLaunchKernelGGL(k_dwt_x<C>, grid_for((long)by * (bx / 2)), dim3(256), 0, s, buf, tmp, ny, nx, by, bx);
       hipLaunchKernelGGL(k_dwt_y<C>, grid_for((long)(by / 2) * bx), dim3(256), 0, s, tmp, buf, ny, nx, by, bx);
     }
   } else {
-    for (int l = levels - 1; l >= 0; --l) {
+    for (int l = levels - 1; l >= l0; --l) {
       const int by = ny >> l, bx = nx >> l;
       hipLaunchKernelGGL(k_idwt_y<C>, grid_for((long)by * bx), dim3(256), 0, s, buf, tmp, ny, nx, by, bx);
       hipLaunchKernelGGL(k_idwt_x<C>, grid_for((long)by * bx), dim3(256), 0, s, tmp, buf, ny, nx, by, bx);
@@ -151,9 +259,32 @@ static hipError_t wavelet(C* buf, C* tmp, int K, int ny, int nx, int levels, boo
   return hipGetLastError();
 }
 
-hipError_t launch_wavelet(float2* buf, float2* tmp, int K, int ny, int nx, int levels, bool inverse,
-                          hipStream_t s) {
-  return wavelet(buf, tmp, K, ny, nx, levels, inverse, s);
+template <class C>
+static hipError_t wavelet(C* buf, C* tmp, int K, int ny, int nx, int levels, bool inverse, hipStream_t s) {
+  return wavelet_levels(buf, tmp, K, ny, nx, 0, levels, inverse, s);
+}
+
+// Out of place: the first (finest) level fused over both axes between src and
+// dst, the coarser levels in place in dst with src as scratch.  Forward:
+// image in src (clobbered) -> coefficients in dst; inverse: coefficients in
+// src (clobbered) -> image in dst.
+hipError_t launch_wavelet_oop(float2* src, float2* dst, int K, int ny, int nx, int levels, bool inverse,
+                              hipStream_t s) {
+  if (levels < 1) return hipMemcpyAsync(dst, src, (size_t)K * ny * nx * sizeof(float2), hipMemcpyDeviceToDevice, s);
+  const dim3 fgrid((unsigned)(((ny / 2 + kWT - 1) / kWT) * ((nx / 2 + kWT - 1) / kWT)), (unsigned)K);
+  const dim3 igrid((unsigned)(((ny + kST - 1) / kST) * ((nx + kST - 1) / kST)), (unsigned)K);
+  if (!inverse) {
+    hipLaunchKernelGGL(k_dwt2<float2>, fgrid, dim3(256), 0, s, src, dst, ny, nx, ny, nx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || levels == 1) return e;
+    return wavelet_levels(dst, src, K, ny, nx, 1, levels, false, s);
+  }
+  if (levels > 1) {
+    const hipError_t e = wavelet_levels(src, dst, K, ny, nx, 1, levels, true, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_idwt2<float2>, igrid, dim3(256), 0, s, src, dst, ny, nx, ny, nx);
+  return hipGetLastError();
 }
 
 static dim3 grid1(long n, int K = 1) { return dim3((unsigned)((n + 255) / 256), K); }

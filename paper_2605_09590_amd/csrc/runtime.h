@@ -123,8 +123,10 @@ hipError_t launch_kspace_in(const float2* src, const double* linv, const uint8_t
                             uint32_t stream, int dist, float scale, hipStream_t s);
 hipError_t launch_coil_combine(const float2* T, const float2* maps, float2* out, int B, int nc,
                                long n, hipStream_t s);
-hipError_t launch_wavelet(float2* buf, float2* tmp, int K, int ny, int nx, int levels, bool inverse,
-                          hipStream_t s);
+// out of place: forward src image (clobbered) -> dst coefficients; inverse
+// src coefficients (clobbered) -> dst image
+hipError_t launch_wavelet_oop(float2* src, float2* dst, int K, int ny, int nx, int levels, bool inverse,
+                              hipStream_t s);
 hipError_t launch_fista_grad(const float2* y, const float2* q, const float2* g, float2* z, long n, int K,
                              int gK, float inv_s2, hipStream_t s);
 hipError_t launch_dsoft(float2* dc, const double2* ck, long n, int K, int nx, int ly, int lx, double lam,
