@@ -46,6 +46,18 @@ template <> struct Real<float2> { using T = float; };
 template <> struct Real<double2> { using T = double; };
 template <class C> __device__ __forceinline__ C czero() { C z; z.x = 0; z.y = 0; return z; }
 
+// Derivative of complex soft-thresholding at the stored coefficient c (FP64,
+// the active-set decision in FP64) applied to the tangent d:
+//   |c| > lam: d - (lam / |c|) c^ j Im(conj(c^) d), c^ = c / |c|;  else 0.
+__device__ __forceinline__ float2 dsoft_one(float2 d, double2 c, double lam) {
+  const double a = sqrt(c.x * c.x + c.y * c.y);
+  if (!(a > lam)) return make_float2(0.f, 0.f);
+  const float chx = (float)(c.x / a), chy = (float)(c.y / a);
+  const float im = chx * d.y - chy * d.x;        // Im(conj(c^) d)
+  const float f = (float)(lam / a) * im;         // d - f * j * c^
+  return make_float2(d.x + f * chy, d.y - f * chx);
+}
+
 // analysis along x of the block [by][bx] of each image
 template <class C>
 __global__ void k_dwt_x(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by, int bx) {
@@ -137,9 +149,9 @@ __global__ void k_idwt_x(const C* __restrict__ in, C* __restrict__ out, int ny, 
 // 16 x 16 positions of each subband from input rows / cols 2 j0 .. 2 j0 + 37
 // (periodic in the block), so the level reads and writes the block once.
 constexpr int kWT = 16, kWIn = 2 * kWT + 6;
-template <class C>
+template <class C, bool DSOFT>
 __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by,
-                                              int bx) {
+                                              int bx, const double2* __restrict__ ck, double lam) {
   using R = typename Real<C>::T;
   __shared__ C sT[kWIn][kWIn + 1];     // input tile
   __shared__ C sX[kWIn][2 * kWT + 1];  // after the x pass: [a | d], 16 each
@@ -178,8 +190,13 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, C* __res
     const int gj = j0 + j, gi = i0 + c % kWT;
     if (gj < hy && gi < hx) {
       const int col = (c < kWT ? 0 : hx) + gi;
-      out[img + (size_t)gj * nx + col] = lo;
-      out[img + (size_t)(hy + gj) * nx + col] = hi;
+      const size_t ilo = (size_t)gj * nx + col, ihi = (size_t)(hy + gj) * nx + col;
+      if constexpr (DSOFT) {   // the level's details are final here: threshold derivative applied
+        if (c >= kWT) lo = dsoft_one(lo, ck[ilo], lam);
+        hi = dsoft_one(hi, ck[ihi], lam);
+      }
+      out[img + ilo] = lo;
+      out[img + ihi] = hi;
     }
   }
 }
@@ -190,9 +207,9 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, C* __res
 // periodic in the half block), y synthesis into LDS, then x synthesis.
 constexpr int kST = 32, kSW = kST / 2 + 4;
 __device__ __forceinline__ int pmod(int v, int n) { return ((v % n) + n) % n; }
-template <class C>
+template <class C, bool MOM>
 __global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by,
-                                               int bx) {
+                                               int bx, C* __restrict__ y, float theta) {
   using R = typename Real<C>::T;
   __shared__ C sC[2 * kSW][2 * kSW + 1];   // [y-low | y-high] x [x-low | x-high] windows
   __shared__ C sY[kST][2 * kSW + 1];       // after the y synthesis: 32 rows x [x-low | x-high]
@@ -233,7 +250,14 @@ __global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, C* __re
       acc = cfma(acc, wav_h<R>(k), sY[mm][ln]);
       acc = cfma(acc, wav_g<R>(k), sY[mm][kSW + ln]);
     }
-    if (m0 + mm < by && c < bx) out[img + (size_t)(m0 + mm) * nx + c] = acc;
+    if (m0 + mm < by && c < bx) {
+      const size_t o = img + (size_t)(m0 + mm) * nx + c;
+      if constexpr (MOM) {   // FISTA momentum on the image: y = x + theta (x - x_prev), x_prev = x (in out)
+        const C xo = out[o];
+        y[o] = cfma(acc, theta, csub(acc, xo));
+      }
+      out[o] = acc;
+    }
   }
 }
 
@@ -264,29 +288,6 @@ static hipError_t wavelet(C* buf, C* tmp, int K, int ny, int nx, int levels, boo
   return wavelet_levels(buf, tmp, K, ny, nx, 0, levels, inverse, s);
 }
 
-// Out of place: the first (finest) level fused over both axes between src and
-// dst, the coarser levels in place in dst with src as scratch.  Forward:
-// image in src (clobbered) -> coefficients in dst; inverse: coefficients in
-// src (clobbered) -> image in dst.
-hipError_t launch_wavelet_oop(float2* src, float2* dst, int K, int ny, int nx, int levels, bool inverse,
-                              hipStream_t s) {
-  if (levels < 1) return hipMemcpyAsync(dst, src, (size_t)K * ny * nx * sizeof(float2), hipMemcpyDeviceToDevice, s);
-  const dim3 fgrid((unsigned)(((ny / 2 + kWT - 1) / kWT) * ((nx / 2 + kWT - 1) / kWT)), (unsigned)K);
-  const dim3 igrid((unsigned)(((ny + kST - 1) / kST) * ((nx + kST - 1) / kST)), (unsigned)K);
-  if (!inverse) {
-    hipLaunchKernelGGL(k_dwt2<float2>, fgrid, dim3(256), 0, s, src, dst, ny, nx, ny, nx);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || levels == 1) return e;
-    return wavelet_levels(dst, src, K, ny, nx, 1, levels, false, s);
-  }
-  if (levels > 1) {
-    const hipError_t e = wavelet_levels(src, dst, K, ny, nx, 1, levels, true, s);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_idwt2<float2>, igrid, dim3(256), 0, s, src, dst, ny, nx, ny, nx);
-  return hipGetLastError();
-}
-
 static dim3 grid1(long n, int K = 1) { return dim3((unsigned)((n + 255) / 256), K); }
 
 __device__ __forceinline__ bool is_detail(long i, int nx, int ly, int lx) {
@@ -306,25 +307,18 @@ __global__ void k_fista_grad(const float2* __restrict__ y, const float2* __restr
   z[o] = cfma(y[o], -inv_s2, csub(q[o], gv));
 }
 
-// dc <- D(c_k) dc for K tangent images sharing the stored FP64 c_k; the
-// active-set decision |c| > lam is taken in FP64
-__global__ void k_dsoft(float2* __restrict__ dc, const double2* __restrict__ ck, long n, int nx, int ly,
-                        int lx, double lam) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (i >= n || lam == 0.0 || !is_detail(i, nx, ly, lx)) return;
-  const double2 c = ck[i];
-  const double a = sqrt(c.x * c.x + c.y * c.y);
-  const size_t o = (size_t)k * n + i;
-  if (!(a > lam)) {
-    dc[o] = make_float2(0.f, 0.f);
-    return;
-  }
-  const float chx = (float)(c.x / a), chy = (float)(c.y / a);
-  const float2 d = dc[o];
-  const float im = chx * d.y - chy * d.x;        // Im(conj(c^) d)
-  const float f = (float)(lam / a) * im;         // d - f * j * c^
-  dc[o] = make_float2(d.x + f * chy, d.y - f * chx);
+// dc = D_k(dc) for K tangent images sharing the stored FP64 c_k, on the
+// detail coefficients of the top-left ry x rx region (the LL block ly x lx is
+// left alone); the active-set decision |c| > lam is taken in FP64
+__global__ void k_dsoft(float2* __restrict__ dc, const double2* __restrict__ ck, long n, int nx, int ry, int rx,
+                        int ly, int lx, double lam) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)ry * rx) return;
+  const int yy = (int)(t / rx), xx = (int)(t % rx);
+  if (yy < ly && xx < lx) return;
+  const long i = (long)yy * nx + xx;
+  const size_t o = (size_t)blockIdx.y * n + i;
+  dc[o] = dsoft_one(dc[o], ck[i], lam);
 }
 
 // y = xn + theta (xn - xo); xo = xn   (K images)
@@ -367,9 +361,39 @@ hipError_t launch_fista_grad(const float2* y, const float2* q, const float2* g, 
   return hipGetLastError();
 }
 
-hipError_t launch_dsoft(float2* dc, const double2* ck, long n, int K, int nx, int ly, int lx, double lam,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_dsoft, grid1(n, K), dim3(256), 0, s, dc, ck, n, nx, ly, lx, lam);
+// Tangent analysis: image in src (clobbered) -> coefficients in dst with the
+// soft-threshold derivative at ck applied to every detail coefficient.  The
+// finest level runs fused over both axes (its details thresholded as they are
+// written), the coarser levels in place in dst with src as scratch, then the
+// derivative on their details (the top-left (ny/2) x (nx/2) block).
+hipError_t launch_cs_analysis(float2* src, float2* dst, int K, int ny, int nx, int levels, const double2* ck,
+                              double lam, int ly, int lx, hipStream_t s) {
+  if (levels < 1) return hipErrorInvalidValue;
+  const long n = (long)ny * nx;
+  const dim3 grid((unsigned)(((ny / 2 + kWT - 1) / kWT) * ((nx / 2 + kWT - 1) / kWT)), (unsigned)K);
+  if (lam != 0.0) hipLaunchKernelGGL((k_dwt2<float2, true>), grid, dim3(256), 0, s, src, dst, ny, nx, ny, nx, ck, lam);
+  else hipLaunchKernelGGL((k_dwt2<float2, false>), grid, dim3(256), 0, s, src, dst, ny, nx, ny, nx, ck, lam);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || levels == 1) return e;
+  if ((e = wavelet_levels(dst, src, K, ny, nx, 1, levels, false, s)) != hipSuccess) return e;
+  if (lam == 0.0) return hipSuccess;
+  const int ry = ny / 2, rx = nx / 2;
+  hipLaunchKernelGGL(k_dsoft, grid1((long)ry * rx, K), dim3(256), 0, s, dst, ck, n, nx, ry, rx, ly, lx, lam);
+  return hipGetLastError();
+}
+
+// Tangent synthesis with the FISTA momentum: coefficients in src (clobbered),
+// scratch for the coarser levels; the image x replaces x_prev in xo and
+// y = x + theta (x - x_prev).  The finest level runs fused over both axes.
+hipError_t launch_cs_synthesis(float2* src, float2* scratch, int K, int ny, int nx, int levels, float2* xo, float2* y,
+                               float theta, hipStream_t s) {
+  if (levels < 1) return hipErrorInvalidValue;
+  if (levels > 1) {
+    const hipError_t e = wavelet_levels(src, scratch, K, ny, nx, 1, levels, true, s);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid((unsigned)(((ny + kST - 1) / kST) * ((nx + kST - 1) / kST)), (unsigned)K);
+  hipLaunchKernelGGL((k_idwt2<float2, true>), grid, dim3(256), 0, s, src, xo, ny, nx, ny, nx, y, theta);
   return hipGetLastError();
 }
 

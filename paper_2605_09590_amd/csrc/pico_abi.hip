@@ -493,12 +493,13 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
         return pico::tv_tangent_final(op->wA, dp, op->x, op->p, op->ny, op->nx, K, (float)op->cs_lam,
                                       op->theta[k - 1], s);
       }
-      // coefficients in wB (the image in wA is consumed), back to wA
-      if ((e2 = pico::launch_wavelet_oop(op->wA, op->wB, K, op->ny, op->nx, op->levels, false, s)) != hipSuccess) return e2;
+      // xd = Psi^H D_k(Psi zd): coefficients in wB (the image in wA is consumed),
+      // the synthesis applying the momentum into (x, p) directly
       const double2* ck = op->ctraj + (size_t)(k - 1) * n;
-      if ((e2 = pico::launch_dsoft(op->wB, ck, n, K, op->nx, ly, lx, op->cs_lam, s)) != hipSuccess) return e2;
-      if ((e2 = pico::launch_wavelet_oop(op->wB, op->wA, K, op->ny, op->nx, op->levels, true, s)) != hipSuccess) return e2;
-      return pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s);
+      if ((e2 = pico::launch_cs_analysis(op->wA, op->wB, K, op->ny, op->nx, op->levels, ck, op->cs_lam, ly, lx, s)) !=
+          hipSuccess)
+        return e2;
+      return pico::launch_cs_synthesis(op->wB, op->wA, K, op->ny, op->nx, op->levels, op->x, op->p, op->theta[k - 1], s);
     });
     if (e != hipSuccess) return e;
   }
