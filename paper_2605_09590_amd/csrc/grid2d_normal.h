@@ -26,6 +26,7 @@
 //            partial dots of the CG step.
 #pragma once
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fft.h"
@@ -252,8 +253,10 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
   constexpr int VA = CF::VA, VB = CF::VB;
   constexpr int TS = NGRP + 1;  // padded tile row
   extern __shared__ float2 dyn[];
-  float2* tile = dyn;                                  // [ny][TS]
-  float2* xch = dyn + (size_t)a.ny * TS;               // NG exchange regions
+  // [ny][TS] tile; once every group holds its column in registers, the same
+  // LDS serves as the NG exchange regions of the transforms
+  float2* tile = dyn;
+  float2* xch = dyn;
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
   // Workgroups go to the eight XCDs in turn; workgroup b takes the strip at
   // v = (b mod 8) * ceil(W / 8) + b / 8 of the order (plane, strip), so each
@@ -278,6 +281,7 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
     const int yy = CF::posA(lane, m);
     v[m] = (grp && inA && yy < a.ny) ? tile[yy * TS + g] : make_float2(0.f, 0.f);
   }
+  __syncthreads();
   float2* lds = xch + g * CF::SPAN;
   CF::template forward<false>(v, lds, lane, tw);
   const float* __restrict__ wcol = a.w + (size_t)(grp ? x0 + g : 0) * a.Gy;
@@ -484,7 +488,7 @@ static hipError_t rows_inv(int mode, const Grid2dArgs& a, hipStream_t s) {
 template <class CF, bool TB>
 static hipError_t cols(const Grid2dArgs& a, hipStream_t s) {
   constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
-  const size_t lds = ((size_t)a.ny * (NGRP + 1) + (size_t)NG * CF::SPAN) * sizeof(float2);
+  const size_t lds = std::max((size_t)a.ny * (NGRP + 1), (size_t)NG * CF::SPAN) * sizeof(float2);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   // allow more than the default 64 KiB of dynamic LDS (once per process,
   // thread-safe initialisation)
