@@ -143,15 +143,23 @@ __global__ void k_idwt_x(const C* __restrict__ in, C* __restrict__ out, int ny, 
   out[img + (size_t)y * nx + m] = acc;
 }
 
-// The first analysis level of the block (by, bx) of each image with both axes
-// in one pass through LDS, out of place (in -> out, the layout the two
-// one-axis passes leave: [a | d] along x, then along y).  A workgroup takes
-// 16 x 16 positions of each subband from input rows / cols 2 j0 .. 2 j0 + 37
-// (periodic in the block), so the level reads and writes the block once.
+// One analysis level of the block (by, bx) of each image with both axes in
+// one pass through LDS (the layout the two one-axis passes leave: [a | d]
+// along x, then along y).  A workgroup takes 16 x 16 positions of each
+// subband from input rows / cols 2 j0 .. 2 j0 + 37 (periodic in the block),
+// so the level reads and writes the block once.  The input block starts at
+// row ri of `in`; the details go to their final places in `out`, the
+// low-low subband to `ll` from row rl (the next level's input, or its final
+// place at the last level).  DSOFT: the soft-threshold derivative at ck is
+// applied to the details as they are written.  GRAD: the input is the FISTA
+// gradient point y - (q - g) / s^2 of three fields (in = y), formed as the
+// tile is loaded.
 constexpr int kWT = 16, kWIn = 2 * kWT + 6;
-template <class C, bool DSOFT>
-__global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by,
-                                              int bx, const double2* __restrict__ ck, double lam) {
+template <class C, bool DSOFT, bool GRAD>
+__global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, int ri, C* __restrict__ out,
+                                              C* __restrict__ ll, int rl, int ny, int nx, int by, int bx,
+                                              const double2* __restrict__ ck, double lam, const C* __restrict__ q,
+                                              const C* __restrict__ gr, float inv_s2) {
   using R = typename Real<C>::T;
   __shared__ C sT[kWIn][kWIn + 1];     // input tile
   __shared__ C sX[kWIn][2 * kWT + 1];  // after the x pass: [a | d], 16 each
@@ -162,7 +170,9 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, C* __res
   const int t = threadIdx.x;
   for (int e = t; e < kWIn * kWIn; e += 256) {
     const int a = e / kWIn, b = e % kWIn;
-    sT[a][b] = in[img + (size_t)((2 * j0 + a) % by) * nx + (2 * i0 + b) % bx];
+    const size_t o = img + (size_t)(ri + (2 * j0 + a) % by) * nx + (2 * i0 + b) % bx;
+    if constexpr (GRAD) sT[a][b] = cfma(in[o], -inv_s2, csub(q[o], gr[o]));
+    else sT[a][b] = in[o];
   }
   __syncthreads();
   for (int e = t; e < kWIn * kWT; e += 256) {
@@ -189,27 +199,32 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, C* __res
     }
     const int gj = j0 + j, gi = i0 + c % kWT;
     if (gj < hy && gi < hx) {
-      const int col = (c < kWT ? 0 : hx) + gi;
-      const size_t ilo = (size_t)gj * nx + col, ihi = (size_t)(hy + gj) * nx + col;
-      if constexpr (DSOFT) {   // the level's details are final here: threshold derivative applied
-        if (c >= kWT) lo = dsoft_one(lo, ck[ilo], lam);
-        hi = dsoft_one(hi, ck[ihi], lam);
+      if (c < kWT) {
+        ll[img + (size_t)(rl + gj) * nx + gi] = lo;
+      } else {
+        const size_t ilo = (size_t)gj * nx + hx + gi;
+        if constexpr (DSOFT) lo = dsoft_one(lo, ck[ilo], lam);
+        out[img + ilo] = lo;
       }
-      out[img + ilo] = lo;
+      const size_t ihi = (size_t)(hy + gj) * nx + (c < kWT ? 0 : hx) + gi;
+      if constexpr (DSOFT) hi = dsoft_one(hi, ck[ihi], lam);
       out[img + ihi] = hi;
     }
   }
 }
 
-// The last synthesis level of the block (by, bx) with both axes in one pass,
-// out of place: 32 x 32 output points per workgroup from 20 x 20 windows of
-// the four subbands (coefficient rows / cols m0 / 2 - 4 .. m0 / 2 + 15,
-// periodic in the half block), y synthesis into LDS, then x synthesis.
+// One synthesis level of the block (by, bx) with both axes in one pass, out
+// of place: 32 x 32 output points per workgroup from 20 x 20 windows of the
+// four subbands (coefficient rows / cols m0 / 2 - 4 .. m0 / 2 + 15, periodic
+// in the half block), y synthesis into LDS, then x synthesis.  The details
+// come from `in`, the low-low subband from `llb` from row rl; the block is
+// written to `out` from row ro.  MOM: FISTA momentum on the image.
 constexpr int kST = 32, kSW = kST / 2 + 4;
 __device__ __forceinline__ int pmod(int v, int n) { return ((v % n) + n) % n; }
 template <class C, bool MOM>
-__global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, C* __restrict__ out, int ny, int nx, int by,
-                                               int bx, C* __restrict__ y, float theta) {
+__global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, const C* __restrict__ llb, int rl,
+                                               C* __restrict__ out, int ro, int ny, int nx, int by, int bx,
+                                               C* __restrict__ y, float theta) {
   using R = typename Real<C>::T;
   __shared__ C sC[2 * kSW][2 * kSW + 1];   // [y-low | y-high] x [x-low | x-high] windows
   __shared__ C sY[kST][2 * kSW + 1];       // after the y synthesis: 32 rows x [x-low | x-high]
@@ -221,9 +236,10 @@ __global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, C* __re
   const int t = threadIdx.x;
   for (int e = t; e < 4 * kSW * kSW; e += 256) {
     const int a = e / (2 * kSW), b = e % (2 * kSW);
-    const int ry = a < kSW ? pmod(wy + a, hy) : hy + pmod(wy + a - kSW, hy);
-    const int rx = b < kSW ? pmod(wx + b, hx) : hx + pmod(wx + b - kSW, hx);
-    sC[a][b] = in[img + (size_t)ry * nx + rx];
+    const bool lly = a < kSW, llx = b < kSW;
+    const int ry = lly ? pmod(wy + a, hy) : hy + pmod(wy + a - kSW, hy);
+    const int rx = llx ? pmod(wx + b, hx) : hx + pmod(wx + b - kSW, hx);
+    sC[a][b] = (lly && llx) ? llb[img + (size_t)(rl + ry) * nx + rx] : in[img + (size_t)ry * nx + rx];
   }
   __syncthreads();
   // x[m] = sum over taps k = m (mod 2) of h[k] a[n] + g[k] d[n], n = (m - k) / 2
@@ -251,7 +267,7 @@ __global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, C* __re
       acc = cfma(acc, wav_g<R>(k), sY[mm][kSW + ln]);
     }
     if (m0 + mm < by && c < bx) {
-      const size_t o = img + (size_t)(m0 + mm) * nx + c;
+      const size_t o = img + (size_t)(ro + m0 + mm) * nx + c;
       if constexpr (MOM) {   // FISTA momentum on the image: y = x + theta (x - x_prev), x_prev = x (in out)
         const C xo = out[o];
         y[o] = cfma(acc, theta, csub(acc, xo));
@@ -307,20 +323,6 @@ __global__ void k_fista_grad(const float2* __restrict__ y, const float2* __restr
   z[o] = cfma(y[o], -inv_s2, csub(q[o], gv));
 }
 
-// dc = D_k(dc) for K tangent images sharing the stored FP64 c_k, on the
-// detail coefficients of the top-left ry x rx region (the LL block ly x lx is
-// left alone); the active-set decision |c| > lam is taken in FP64
-__global__ void k_dsoft(float2* __restrict__ dc, const double2* __restrict__ ck, long n, int nx, int ry, int rx,
-                        int ly, int lx, double lam) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)ry * rx) return;
-  const int yy = (int)(t / rx), xx = (int)(t % rx);
-  if (yy < ly && xx < lx) return;
-  const long i = (long)yy * nx + xx;
-  const size_t o = (size_t)blockIdx.y * n + i;
-  dc[o] = dsoft_one(dc[o], ck[i], lam);
-}
-
 // y = xn + theta (xn - xo); xo = xn   (K images)
 __global__ void k_momentum(const float2* __restrict__ xn, float2* __restrict__ xo, float2* __restrict__ y,
                            long total, float theta) {
@@ -361,40 +363,66 @@ hipError_t launch_fista_grad(const float2* y, const float2* q, const float2* g, 
   return hipGetLastError();
 }
 
-// Tangent analysis: image in src (clobbered) -> coefficients in dst with the
-// soft-threshold derivative at ck applied to every detail coefficient.  The
-// finest level runs fused over both axes (its details thresholded as they are
-// written), the coarser levels in place in dst with src as scratch, then the
-// derivative on their details (the top-left (ny/2) x (nx/2) block).
-hipError_t launch_cs_analysis(float2* src, float2* dst, int K, int ny, int nx, int levels, const double2* ck,
-                              double lam, int ly, int lx, hipStream_t s) {
+// Tangent analysis of the gradient point z = y - (q - g) * inv_s2 (K images
+// each) into coefficients in dst, the soft-threshold derivative at ck applied
+// to every detail coefficient as it is written.  Each level is one fused
+// pass; level l (block by = ny >> l) reads its input block from scratch rows
+// [by, 2 by) (level 0: z, formed as the tiles load) and writes its low-low
+// subband to scratch rows [by / 2, by), disjoint from its input (the last
+// level: to its final place in dst).
+hipError_t launch_cs_analysis(const float2* y, const float2* q, const float2* g, float inv_s2, float2* scratch,
+                              float2* dst, int K, int ny, int nx, int levels, const double2* ck, double lam,
+                              hipStream_t s) {
   if (levels < 1) return hipErrorInvalidValue;
-  const long n = (long)ny * nx;
-  const dim3 grid((unsigned)(((ny / 2 + kWT - 1) / kWT) * ((nx / 2 + kWT - 1) / kWT)), (unsigned)K);
-  if (lam != 0.0) hipLaunchKernelGGL((k_dwt2<float2, true>), grid, dim3(256), 0, s, src, dst, ny, nx, ny, nx, ck, lam);
-  else hipLaunchKernelGGL((k_dwt2<float2, false>), grid, dim3(256), 0, s, src, dst, ny, nx, ny, nx, ck, lam);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || levels == 1) return e;
-  if ((e = wavelet_levels(dst, src, K, ny, nx, 1, levels, false, s)) != hipSuccess) return e;
-  if (lam == 0.0) return hipSuccess;
-  const int ry = ny / 2, rx = nx / 2;
-  hipLaunchKernelGGL(k_dsoft, grid1((long)ry * rx, K), dim3(256), 0, s, dst, ck, n, nx, ry, rx, ly, lx, lam);
-  return hipGetLastError();
-}
-
-// Tangent synthesis with the FISTA momentum: coefficients in src (clobbered),
-// scratch for the coarser levels; the image x replaces x_prev in xo and
-// y = x + theta (x - x_prev).  The finest level runs fused over both axes.
-hipError_t launch_cs_synthesis(float2* src, float2* scratch, int K, int ny, int nx, int levels, float2* xo, float2* y,
-                               float theta, hipStream_t s) {
-  if (levels < 1) return hipErrorInvalidValue;
-  if (levels > 1) {
-    const hipError_t e = wavelet_levels(src, scratch, K, ny, nx, 1, levels, true, s);
+  const bool ds = lam != 0.0;
+  for (int l = 0; l < levels; ++l) {
+    const int by = ny >> l, bx = nx >> l;
+    const dim3 grid((unsigned)(((by / 2 + kWT - 1) / kWT) * ((bx / 2 + kWT - 1) / kWT)), (unsigned)K);
+    const bool last = l == levels - 1;
+    float2* ll = last ? dst : scratch;
+    const int rl = last ? 0 : by / 2;
+    if (l == 0) {
+      if (ds) hipLaunchKernelGGL((k_dwt2<float2, true, true>), grid, dim3(256), 0, s, y, 0, dst, ll, rl, ny, nx, by,
+                                 bx, ck, lam, q, g, inv_s2);
+      else hipLaunchKernelGGL((k_dwt2<float2, false, true>), grid, dim3(256), 0, s, y, 0, dst, ll, rl, ny, nx, by,
+                              bx, ck, lam, q, g, inv_s2);
+    } else {
+      const float2* in = scratch;
+      if (ds) hipLaunchKernelGGL((k_dwt2<float2, true, false>), grid, dim3(256), 0, s, in, by, dst, ll, rl, ny, nx,
+                                 by, bx, ck, lam, q, g, inv_s2);
+      else hipLaunchKernelGGL((k_dwt2<float2, false, false>), grid, dim3(256), 0, s, in, by, dst, ll, rl, ny, nx,
+                              by, bx, ck, lam, q, g, inv_s2);
+    }
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const dim3 grid((unsigned)(((ny + kST - 1) / kST) * ((nx + kST - 1) / kST)), (unsigned)K);
-  hipLaunchKernelGGL((k_idwt2<float2, true>), grid, dim3(256), 0, s, src, xo, ny, nx, ny, nx, y, theta);
-  return hipGetLastError();
+  return hipSuccess;
+}
+
+// Tangent synthesis of the coefficients in src (read only) with the FISTA
+// momentum: the image x replaces x_prev in xo and y = x + theta (x - x_prev).
+// Each level is one fused pass; level l (block by = ny >> l) takes its
+// low-low subband from scratch rows [by / 2, by) (the coarsest level: from
+// src) and writes its block to scratch rows [by, 2 by), disjoint from that
+// input (level 0: the image, into xo with the momentum).
+hipError_t launch_cs_synthesis(const float2* src, float2* scratch, int K, int ny, int nx, int levels, float2* xo,
+                               float2* y, float theta, hipStream_t s) {
+  if (levels < 1) return hipErrorInvalidValue;
+  for (int l = levels - 1; l >= 0; --l) {
+    const int by = ny >> l, bx = nx >> l;
+    const dim3 grid((unsigned)(((by + kST - 1) / kST) * ((bx + kST - 1) / kST)), (unsigned)K);
+    const float2* llb = l == levels - 1 ? src : scratch;
+    const int rl = l == levels - 1 ? 0 : by / 2;
+    if (l == 0)
+      hipLaunchKernelGGL((k_idwt2<float2, true>), grid, dim3(256), 0, s, src, llb, rl, xo, 0, ny, nx, by, bx, y,
+                         theta);
+    else
+      hipLaunchKernelGGL((k_idwt2<float2, false>), grid, dim3(256), 0, s, src, llb, rl, scratch, by, ny, nx, by, bx,
+                         y, theta);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_momentum(const float2* xn, float2* xo, float2* y, long total, float theta,

@@ -467,7 +467,6 @@ hipError_t adjoint_kspace(pico_op_t op, int K, const float2* src, const double* 
 // stored projection data.  The tangent of x_T ends in op->x.
 hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
   const long n = (long)op->image();
-  const int ly = op->ny >> op->levels, lx = op->nx >> op->levels;
   hipError_t e;
   if ((e = pico::launch_fill_zero(op->p, K * n, s)) != hipSuccess) return e;
   if ((e = pico::launch_fill_zero(op->x, K * n, s)) != hipSuccess) return e;
@@ -480,8 +479,8 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
     if ((e = timed(op, PICO_PROF_NORMAL_ITER, s, [&] { return launch_normal(op, K, pico::C1_APPLY, c, s); })) != hipSuccess) return e;
     e = timed(op, PICO_PROF_OTHER, s, [&] {
       hipError_t e2;
-      if ((e2 = pico::launch_fista_grad(op->p, op->q, op->r, op->wA, n, K, 1, inv_s2, s)) != hipSuccess) return e2;
       if (op->tv_inner > 0) {
+        if ((e2 = pico::launch_fista_grad(op->p, op->q, op->r, op->wA, n, K, 1, inv_s2, s)) != hipSuccess) return e2;
         // TV prox tangent at the stored projection data of iteration k
         if (op->cs_lam == 0.0) return pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s);
         const size_t off = (size_t)(k - 1) * op->tv_inner * n;
@@ -493,11 +492,11 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
         return pico::tv_tangent_final(op->wA, dp, op->x, op->p, op->ny, op->nx, K, (float)op->cs_lam,
                                       op->theta[k - 1], s);
       }
-      // xd = Psi^H D_k(Psi zd): coefficients in wB (the image in wA is consumed),
-      // the synthesis applying the momentum into (x, p) directly
+      // xd = Psi^H D_k(Psi zd): zd formed inside the analysis, coefficients in wB
+      // (wA scratch), the synthesis applying the momentum into (x, p) directly
       const double2* ck = op->ctraj + (size_t)(k - 1) * n;
-      if ((e2 = pico::launch_cs_analysis(op->wA, op->wB, K, op->ny, op->nx, op->levels, ck, op->cs_lam, ly, lx, s)) !=
-          hipSuccess)
+      if ((e2 = pico::launch_cs_analysis(op->p, op->q, op->r, inv_s2, op->wA, op->wB, K, op->ny, op->nx, op->levels,
+                                         ck, op->cs_lam, s)) != hipSuccess)
         return e2;
       return pico::launch_cs_synthesis(op->wB, op->wA, K, op->ny, op->nx, op->levels, op->x, op->p, op->theta[k - 1], s);
     });

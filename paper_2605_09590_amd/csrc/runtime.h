@@ -123,14 +123,15 @@ hipError_t launch_kspace_in(const float2* src, const double* linv, const uint8_t
                             uint32_t stream, int dist, float scale, hipStream_t s);
 hipError_t launch_coil_combine(const float2* T, const float2* maps, float2* out, int B, int nc,
                                long n, hipStream_t s);
-// CS tangents: analysis of the image in src (clobbered) into dst with the
-// soft-threshold derivative at ck on the details; synthesis of src
-// (clobbered, scratch for the coarser levels) with the FISTA momentum into
-// (xo, y)
-hipError_t launch_cs_analysis(float2* src, float2* dst, int K, int ny, int nx, int levels, const double2* ck,
-                              double lam, int ly, int lx, hipStream_t s);
-hipError_t launch_cs_synthesis(float2* src, float2* scratch, int K, int ny, int nx, int levels, float2* xo, float2* y,
-                               float theta, hipStream_t s);
+// CS tangents: analysis of the gradient point y - (q - g) * inv_s2 into dst
+// with the soft-threshold derivative at ck on the details (scratch holds the
+// coarser levels' inputs); synthesis of src (read only; scratch for the
+// coarser levels) with the FISTA momentum into (xo, y)
+hipError_t launch_cs_analysis(const float2* y, const float2* q, const float2* g, float inv_s2, float2* scratch,
+                              float2* dst, int K, int ny, int nx, int levels, const double2* ck, double lam,
+                              hipStream_t s);
+hipError_t launch_cs_synthesis(const float2* src, float2* scratch, int K, int ny, int nx, int levels, float2* xo,
+                               float2* y, float theta, hipStream_t s);
 hipError_t launch_fista_grad(const float2* y, const float2* q, const float2* g, float2* z, long n, int K,
                              int gK, float inv_s2, hipStream_t s);
 hipError_t launch_momentum(const float2* xn, float2* xo, float2* y, long total, float theta,
