@@ -182,3 +182,39 @@ def test_cs_pmr_parity(lib):
     e = _rel(var.cpu().numpy(), opico.pmr_finalize(ref).ravel())
     say(f"  sample variance: rel err {e:.2e}")
     assert e < TOL
+
+
+@pytest.mark.parametrize("ny,nx,lev", [(64, 96, 4), (96, 64, 1)])
+def test_cs_nonsquare_and_level_counts(lib, ny, nx, lev):
+    say(f"case: CS {ny}x{nx}, 3 coils, Poisson-disc R=2, lam 1e-3, FISTA 20, {lev} level(s), 3 tangents")
+    rng = np.random.default_rng(11)
+    maps = workloads.coil_maps(ny, nx, 3, rng)
+    psi = workloads.noise_cov(3, rng)
+    x = workloads.phantom(max(ny, nx), rng)[:ny, :nx]
+    mask = workloads.poisson_disc_mask(ny, nx, 2.0, 8, seed=11)
+    op = opico.cartesian(maps, psi, mask)
+    bw = op.forward(x)
+    L = np.linalg.cholesky(psi)
+    braw = np.einsum("cd,dyx->cyx", L, bw)
+    lam, T = 1e-3, 20
+    h = lib.pico_init(ny, nx, _dev(maps.astype(np.complex64)), psi, _dev(mask),
+                      sampling=lib.PICO_CART_2D, recon=lib.PICO_CS_FISTA_L1WAV,
+                      kdata=_dev(braw.astype(np.complex64)), fista_iters=T,
+                      cs_lambda=lam, wavelet_levels=lev, probe_tile=3)
+    xg = torch.empty((ny, nx), dtype=torch.complex64, device="cuda:0")
+    lib.pico_recon(h, xg)
+    w = np.stack([ocs.kspace_probe(op, 5, i) for i in range(3)])
+    ut = torch.empty((3, ny, nx), dtype=torch.complex64, device="cuda:0")
+    lib.pico_apply_jvp(h, _dev(w.astype(np.complex64)), ut, 3)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    f = ocs.FistaL1Wavelet(op, lam, T, levels=lev)
+    xr, coeffs = f.recon(bw, store=True)
+    err = _rel(xg.cpu().numpy(), xr)
+    say(f"  reconstruction rel err {err:.2e}")
+    assert err < TOL
+    u = ut.cpu().numpy()
+    for k in range(3):
+        e = _rel(u[k], f.jvp(w[k], coeffs))
+        say(f"  jvp probe {k}: rel err {e:.2e}")
+        assert e < TOL
