@@ -662,8 +662,9 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     # single step first when the count is odd, then passes of four dual steps
     # while four remain, then pairs.  The first pass starts from zero, reads dz
     # and writes dr, dp (40 B per tangent and pixel); each later pass reads dz,
-    # dr, dp and writes dr, dp (72 B).  The projection data (20 B per pixel and
-    # step) is shared by the tangents of a workgroup and not counted.
+    # dr, dp and writes dr, dp (72 B); the last pass of several steps writes no
+    # dr (16 B less).  The projection data (20 B per pixel and step) is shared
+    # by the tangents of a workgroup and not counted.
     inner, T = pr.extra["tv_inner"], pr.extra["fista_iters"]
     passes, it = [], 0
     if inner % 2:
@@ -675,7 +676,10 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     while it < inner:
         passes.append(2)
         it += 2
-    tv_bytes = T * K * n * (40 + 72 * (len(passes) - 1))
+    pass_bytes = [40 if j == 0 else 72 for j in range(len(passes))]
+    if passes[-1] > 1:
+        pass_bytes[-1] -= 16
+    tv_bytes = T * K * n * sum(pass_bytes)
     tv_s = prof["other"][0] / 1e3 / steps
     return {
         "workload": f"TV-CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2 (24x24 calib), "

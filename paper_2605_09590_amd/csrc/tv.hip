@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
                                                   float2* __restrict__ rB, const float2* __restrict__ pA,
                                                   float2* __restrict__ pB, const float4* __restrict__ what,
                                                   const float* __restrict__ invn, int ny, int nx, int K, int kper,
-                                                  float lam, float c8, TvTheta th, int first) {
+                                                  float lam, float c8, TvTheta th, int first, int last) {
   using C = TvSteps<S, TY, TX>;
   constexpr int BY = C::BY, BX = C::BX, NB = C::NB, NPT = C::NPT;
   static_assert(TY * TX == 256, "one output pixel per thread");
@@ -390,10 +390,12 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
         proj_at(a, b, whl, ivl, qy, qx);
         const float2 oy = sPy[a][b], ox = sPx[a][b];
         const float ths = th.th[S - 1];
-        float2* rb = rB + (size_t)k * 2 * n;
         float2* pb = pB + (size_t)k * 2 * n;
-        rb[i] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
-        rb[n + i] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
+        if (!last) {   // the prox's last pass: only p is read afterwards
+          float2* rb = rB + (size_t)k * 2 * n;
+          rb[i] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
+          rb[n + i] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
+        }
         pb[i] = qy;
         pb[n + i] = qx;
       }
@@ -445,7 +447,7 @@ hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what,
 template <int S, int TY, int TX>
 static void launch_tv_steps(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB, const float4* what,
                             const float* invn, const float* th, int ny, int nx, int K, float lam, float c8, int first,
-                            hipStream_t s) {
+                            int last, hipStream_t s) {
   const int tiles = ((ny + TY - 1) / TY) * ((nx + TX - 1) / TX);
   int kper = 8;
   while (kper > 1 && (long)tiles * ((K + kper - 1) / kper) < 2048) kper >>= 1;
@@ -453,7 +455,7 @@ static void launch_tv_steps(const float2* dz, float2* drA, float2* drB, float2* 
   TvTheta tt{};
   for (int q = 0; q < S; ++q) tt.th[q] = th[q];
   hipLaunchKernelGGL((k_tv_steps<S, TY, TX>), grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what, invn, ny, nx, K,
-                     kper, lam, c8, tt, first);
+                     kper, lam, c8, tt, first, last);
 }
 
 hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
@@ -477,13 +479,13 @@ hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* d
   const bool four = ny >= 16 + 8 && nx >= 16 + 8;
   for (; four && inner - it >= 4; it += 4) {
     launch_tv_steps<4, 16, 16>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it, ny, nx,
-                               K, lam, c8, it == 0 ? 1 : 0, s);
+                               K, lam, c8, it == 0 ? 1 : 0, it + 4 == inner ? 1 : 0, s);
     std::swap(drA, drB);
     std::swap(dpA, dpB);
   }
   for (; it < inner; it += 2) {
     launch_tv_steps<2, kTY, kTX>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it, ny,
-                                 nx, K, lam, c8, it == 0 ? 1 : 0, s);
+                                 nx, K, lam, c8, it == 0 ? 1 : 0, it + 2 >= inner ? 1 : 0, s);
     std::swap(drA, drB);
     std::swap(dpA, dpB);
   }
