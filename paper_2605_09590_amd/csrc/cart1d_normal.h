@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
   constexpr int N = CF::N, L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
   constexpr int VA = CF::VA, VB = CF::VB;
   __shared__ float2 lds_all[NG * CF::SPAN];
-  __shared__ double red[64];
+  __shared__ double red[64 + L];   // lane 0 of a partial last group reads L entries
   const int g = threadIdx.x / L;
   const int lane = threadIdx.x % L;
   const int col = blockIdx.y;

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
   constexpr int VA = CF::VA, VB = CF::VB;
   __shared__ float2 lds_all[NG * CF::SPAN];
-  __shared__ double red[64];
+  __shared__ double red[64 + L];   // lane 0 of a partial last group reads L entries
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
   const long gid = (long)blockIdx.x * G + g;
   const bool active = g < G && gid < (long)a.K * a.ny;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
   constexpr int VA = CF::VA, VB = CF::VB;
   __shared__ float2 lds_all[NG * CF::SPAN];
-  __shared__ double red[64];
+  __shared__ double red[64 + L];   // lane 0 of a partial last group reads L entries
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
   const long gid = (long)blockIdx.x * G + g;
   const bool active = g < G && gid < (long)a.K * a.ny;
