@@ -155,6 +155,14 @@ __global__ void k_idwt_x(const C* __restrict__ in, C* __restrict__ out, int ny, 
 // gradient point y - (q - g) / s^2 of three fields (in = y), formed as the
 // tile is loaded.
 constexpr int kWT = 16, kWIn = 2 * kWT + 6;
+// v mod n (n > 0), a compare and an add when v is within one period of
+// [0, n) (every index of a tile whose block is at least the tile's span)
+__device__ __forceinline__ int wrapmod(int v, int n) {
+  if (v >= 0 && v < n) return v;
+  if (v < 0 && v >= -n) return v + n;
+  if (v >= n && v < 2 * n) return v - n;
+  return ((v % n) + n) % n;
+}
 template <class C, bool DSOFT, bool GRAD>
 __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, int ri, C* __restrict__ out,
                                               C* __restrict__ ll, int rl, int ny, int nx, int by, int bx,
@@ -170,7 +178,7 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, int ri, 
   const int t = threadIdx.x;
   for (int e = t; e < kWIn * kWIn; e += 256) {
     const int a = e / kWIn, b = e % kWIn;
-    const size_t o = img + (size_t)(ri + (2 * j0 + a) % by) * nx + (2 * i0 + b) % bx;
+    const size_t o = img + (size_t)(ri + wrapmod(2 * j0 + a, by)) * nx + wrapmod(2 * i0 + b, bx);
     if constexpr (GRAD) sT[a][b] = cfma(in[o], -inv_s2, csub(q[o], gr[o]));
     else sT[a][b] = in[o];
   }
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, int ri, 
 // come from `in`, the low-low subband from `llb` from row rl; the block is
 // written to `out` from row ro.  MOM: FISTA momentum on the image.
 constexpr int kST = 32, kSW = kST / 2 + 4;
-__device__ __forceinline__ int pmod(int v, int n) { return ((v % n) + n) % n; }
+__device__ __forceinline__ int pmod(int v, int n) { return wrapmod(v, n); }
 template <class C, bool MOM>
 __global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, const C* __restrict__ llb, int rl,
                                                C* __restrict__ out, int ro, int ny, int nx, int by, int bx,
