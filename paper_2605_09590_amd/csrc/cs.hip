@@ -176,11 +176,23 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, int ri, 
   const int j0 = (int)(blockIdx.x / tilesx) * kWT, i0 = (int)(blockIdx.x % tilesx) * kWT;
   const size_t img = (size_t)blockIdx.y * ny * nx;
   const int t = threadIdx.x;
-  for (int e = t; e < kWIn * kWIn; e += 256) {
-    const int a = e / kWIn, b = e % kWIn;
-    const size_t o = img + (size_t)(ri + wrapmod(2 * j0 + a, by)) * nx + wrapmod(2 * i0 + b, bx);
-    if constexpr (GRAD) sT[a][b] = cfma(in[o], -inv_s2, csub(q[o], gr[o]));
-    else sT[a][b] = in[o];
+  // every load of the tile is issued before the first LDS store
+  constexpr int NT = kWIn * kWIn, NIT = (NT + 255) / 256;
+  C tv[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = t + 256 * it;
+    if (e < NT) {
+      const int a = e / kWIn, b = e % kWIn;
+      const size_t o = img + (size_t)(ri + wrapmod(2 * j0 + a, by)) * nx + wrapmod(2 * i0 + b, bx);
+      if constexpr (GRAD) tv[it] = cfma(in[o], -inv_s2, csub(q[o], gr[o]));
+      else tv[it] = in[o];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = t + 256 * it;
+    if (e < NT) sT[e / kWIn][e % kWIn] = tv[it];
   }
   __syncthreads();
   for (int e = t; e < kWIn * kWT; e += 256) {
@@ -242,12 +254,24 @@ __global__ __launch_bounds__(256) void k_idwt2(const C* __restrict__ in, const C
   const int wy = m0 / 2 - 4, wx = c0 / 2 - 4;   // window starts (periodic)
   const size_t img = (size_t)blockIdx.y * ny * nx;
   const int t = threadIdx.x;
-  for (int e = t; e < 4 * kSW * kSW; e += 256) {
-    const int a = e / (2 * kSW), b = e % (2 * kSW);
-    const bool lly = a < kSW, llx = b < kSW;
-    const int ry = lly ? pmod(wy + a, hy) : hy + pmod(wy + a - kSW, hy);
-    const int rx = llx ? pmod(wx + b, hx) : hx + pmod(wx + b - kSW, hx);
-    sC[a][b] = (lly && llx) ? llb[img + (size_t)(rl + ry) * nx + rx] : in[img + (size_t)ry * nx + rx];
+  // every load of the windows is issued before the first LDS store
+  constexpr int NW = 4 * kSW * kSW, NIT = (NW + 255) / 256;
+  C wv[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = t + 256 * it;
+    if (e < NW) {
+      const int a = e / (2 * kSW), b = e % (2 * kSW);
+      const bool lly = a < kSW, llx = b < kSW;
+      const int ry = lly ? pmod(wy + a, hy) : hy + pmod(wy + a - kSW, hy);
+      const int rx = llx ? pmod(wx + b, hx) : hx + pmod(wx + b - kSW, hx);
+      wv[it] = (lly && llx) ? llb[img + (size_t)(rl + ry) * nx + rx] : in[img + (size_t)ry * nx + rx];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = t + 256 * it;
+    if (e < NW) sC[e / (2 * kSW)][e % (2 * kSW)] = wv[it];
   }
   __syncthreads();
   // x[m] = sum over taps k = m (mod 2) of h[k] a[n] + g[k] d[n], n = (m - k) / 2
