@@ -176,23 +176,11 @@ __global__ __launch_bounds__(256) void k_dwt2(const C* __restrict__ in, int ri, 
   const int j0 = (int)(blockIdx.x / tilesx) * kWT, i0 = (int)(blockIdx.x % tilesx) * kWT;
   const size_t img = (size_t)blockIdx.y * ny * nx;
   const int t = threadIdx.x;
-  // every load of the tile is issued before the first LDS store
-  constexpr int NT = kWIn * kWIn, NIT = (NT + 255) / 256;
-  C tv[NIT];
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int e = t + 256 * it;
-    if (e < NT) {
-      const int a = e / kWIn, b = e % kWIn;
-      const size_t o = img + (size_t)(ri + wrapmod(2 * j0 + a, by)) * nx + wrapmod(2 * i0 + b, bx);
-      if constexpr (GRAD) tv[it] = cfma(in[o], -inv_s2, csub(q[o], gr[o]));
-      else tv[it] = in[o];
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int e = t + 256 * it;
-    if (e < NT) sT[e / kWIn][e % kWIn] = tv[it];
+  for (int e = t; e < kWIn * kWIn; e += 256) {
+    const int a = e / kWIn, b = e % kWIn;
+    const size_t o = img + (size_t)(ri + wrapmod(2 * j0 + a, by)) * nx + wrapmod(2 * i0 + b, bx);
+    if constexpr (GRAD) sT[a][b] = cfma(in[o], -inv_s2, csub(q[o], gr[o]));
+    else sT[a][b] = in[o];
   }
   __syncthreads();
   for (int e = t; e < kWIn * kWT; e += 256) {
