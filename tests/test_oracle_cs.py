@@ -9,7 +9,18 @@
   * lam = 0: FISTA is linear in b, so J w equals the map applied to w.
   * lam = 0 and many iterations: E|J w|^2 over an exact probe enumeration
     tends to diag(M^-1) (the least-squares covariance, Sec. 2.1 Eq. (9)).
+  * db4 taps equal the published table (Daubechies, Ten Lectures, Table 6.1;
+    tests/golden/db4_taps.txt), which fixes the spectral-factorisation root
+    choice the filter identities leave open.
+  * FISTA at lam > 0 solves the stated problem: after many iterations the
+    L1-db4 iterate meets the first-order optimality conditions of
+    1/2 ||A x - b||^2 / s^2 + lam ||(Psi x)_detail||_1, and the TV iterate is
+    a fixed point of the exact proximal-gradient map (the prox by an
+    independent solver); the objective gap obeys Beck and Teboulle's
+    O(1/k^2) bound (SIAM J. Imaging Sci. 2009, Thm. 4.4) at every k; the
+    momentum weights start at 0 and follow Nesterov's sequence.
 """
+import os
 import itertools
 
 import numpy as np
@@ -192,3 +203,93 @@ def test_tv_fista_jvp_matches_central_differences_and_lambda_zero():
     f0 = cs.FistaTV(op, 0.0, 12, inner=8)
     _, zs0 = f0.recon(b, store=True)
     assert np.linalg.norm(f0.jvp(w, zs0) - f0.recon(w)) < 1e-12 * np.linalg.norm(f0.recon(w))
+
+
+# ------------------------------------------------ FISTA at lam > 0 (pins)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_db4_matches_published_taps():
+    h, _ = wavelet.wavelet_filter(4)
+    ref = np.loadtxt(os.path.join(GOLDEN, "db4_taps.txt"))
+    assert ref.shape == (8,)
+    assert np.abs(h - ref).max() < 1e-13
+
+
+def test_fista_momentum_weights():
+    # Beck and Teboulle: t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, so
+    # t_{k+1}^2 - t_{k+1} = t_k^2, t_k >= (k + 1) / 2, and the first weight
+    # (t_1 - 1) / t_2 is 0 (the first step is a plain proximal-gradient step)
+    op, _, f = _cs_problem(iters=40)
+    t = np.array(f.t)
+    assert t[0] == 1.0
+    assert np.allclose(t[1:] ** 2 - t[1:], t[:-1] ** 2, rtol=1e-13)
+    assert np.all(t >= (np.arange(1, t.size + 1) + 1) / 2 - 1e-12)
+    assert f.theta(1) == 0.0
+    for k in range(1, 41):
+        assert abs(f.theta(k) - (t[k - 1] - 1.0) / t[k]) < 1e-15
+    g = cs.FistaTV(op, 1e-3, 40, inner=3)
+    assert g.theta(1) == 0.0 and np.allclose(g.t, f.t, rtol=0, atol=0)
+
+
+def _l1_objective(op, f, b, u):
+    r = op.forward(u) - b
+    c = wavelet.wavedec2(u, f.levels)
+    return 0.5 * np.vdot(r, r).real / f.s2 + f.lam * np.abs(c[f.mask]).sum()
+
+
+def _tv_objective(op, f, b, u):
+    r = op.forward(u) - b
+    g = cs.tv_grad(u)
+    return 0.5 * np.vdot(r, r).real / f.s2 + f.lam * np.sum(np.sqrt(np.abs(g[0]) ** 2 + np.abs(g[1]) ** 2))
+
+
+def test_fista_l1_first_order_optimality():
+    # minimiser of F(x) = 1/2 ||A x - b||^2 / s^2 + lam sum_detail |c_i|, c = Psi x:
+    # with g = Psi A^H (b - A x) / s^2 (minus the gradient, in coefficients),
+    # g = 0 on the approximation band, g = lam c / |c| on detail c != 0, and
+    # |g| <= lam on detail c = 0
+    op, b, f = _cs_problem(lam=2e-3, iters=1000)
+    x = f.recon(b)
+    g = wavelet.wavedec2(op.adjoint(b) - op.normal(x), f.levels) / f.s2
+    c = wavelet.wavedec2(x, f.levels)
+    a = np.abs(c)
+    det = f.mask
+    act = det & (a > 1e-8)
+    off = det & ~act
+    assert act.sum() > 100 and off.sum() > 20          # both cases occur
+    assert np.abs(g[~det]).max() < 1e-6 * f.lam
+    assert np.abs(g[act] - f.lam * c[act] / a[act]).max() < 1e-5 * f.lam
+    assert np.abs(g[off]).max() <= f.lam * (1 + 1e-9)
+    # a wrong threshold scale would move the active-set condition by that factor
+    assert np.abs(g[act] - 1.05 * f.lam * c[act] / a[act]).max() > 1e-2 * f.lam
+
+
+def test_fista_l1_objective_gap_bound():
+    op, b, f = _cs_problem(lam=2e-3, iters=1000)
+    xs = f.recon(b)
+    fs = _l1_objective(op, f, b, xs)
+    bound0 = 2.0 * np.vdot(xs, xs).real           # 2 L ||x_0 - x*||^2, L = 1, x_0 = 0
+    for k in (1, 2, 3, 5, 10, 20, 50):
+        xk = cs.FistaL1Wavelet(op, f.lam, k, levels=f.levels).recon(b)
+        gap = _l1_objective(op, f, b, xk) - fs
+        assert -1e-12 <= gap <= bound0 / (k + 1) ** 2
+
+
+def test_fista_tv_fixed_point_of_exact_prox_gradient_map():
+    # with near-exact inner solves the TV iterate is the minimiser of
+    # 1/2 ||A x - b||^2 / s^2 + lam TV(x): x = prox_{lam TV}(x - grad f(x)),
+    # the prox taken by the independent Chambolle solver above
+    op, b, _ = _cs_problem(n=24, lam=2e-3)
+    f = cs.FistaTV(op, 2e-3, 200, inner=200)
+    x = f.recon(b)
+    z = x - (op.normal(x) - op.adjoint(b)) / f.s2
+    assert np.linalg.norm(_chambolle_prox(z, f.lam, iters=20000) - x) < 1e-6 * np.linalg.norm(x)
+    # the same map with a mis-scaled prox weight is not at its fixed point
+    assert np.linalg.norm(_chambolle_prox(z, 1.1 * f.lam, iters=20000) - x) > 1e-4 * np.linalg.norm(x)
+    fs = _tv_objective(op, f, b, x)
+    bound0 = 2.0 * np.vdot(x, x).real
+    for k in (1, 2, 5, 10, 20):
+        xk = cs.FistaTV(op, f.lam, k, inner=200).recon(b)
+        gap = _tv_objective(op, f, b, xk) - fs
+        assert -1e-9 <= gap <= bound0 / (k + 1) ** 2
