@@ -171,6 +171,23 @@ typedef struct {
   double lambda_abs;            /* lambda * power_margin * lambda_max              */
 } pico_stats_t;
 
+/* Device allocator for every library workspace, so that the caller (e.g.
+ * PyTorch's caching allocator) owns all device memory.  alloc(bytes, ctx) returns device memory of the current device, aligned to
+ * 256 bytes, or NULL on failure (the calling entry point then reports
+ * PICO_ENOMEM, or PICO_EDEVICE for a misaligned pointer, which is handed back
+ * to free first); free_fn(ptr, ctx) releases it.  Every later allocation of
+ * pico_init, pico_init_reduced (its temporaries included), pico_pmr_cs (its
+ * replica workspace) and pico_server_create (the budget) goes through them,
+ * and each block returns to the pair (and ctx) that made it, even if another
+ * pair is installed meanwhile.  The library frees a block only after the work
+ * it enqueued on it has finished (pico_destroy waits for the operator's last
+ * stream).  Both NULL restores hipMalloc / hipFree (the default).  The
+ * callbacks may run on any thread that calls into the library and must not
+ * call back into it.  Process-wide; takes effect for allocations made after
+ * it returns.  Errors: PICO_EINVAL when exactly one callback is NULL. */
+pico_status_t pico_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* ptr, void* ctx),
+                                 void* ctx);
+
 /* Build the operator: whitens the maps (Cholesky of psi on the host in
  * float64; Sec. 2.1 Eq. (3)), prepares the sampling structures, runs the
  * power method when lambda > 0 (Sec. 3.2.1, 3.3) and allocates the CG

@@ -16,7 +16,9 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "arena.h"
@@ -42,6 +44,40 @@ pico_status_t fail(pico_status_t st, const std::string& msg) {
   } while (0)
 
 }  // namespace
+
+namespace pico {
+
+namespace {
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;   // guarded by g_alloc_mu; both NULL: hipMalloc / hipFree
+}  // namespace
+
+hipError_t dev_alloc(void** ptr, size_t bytes, DevAllocator* by) {
+  DevAllocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+  }
+  *by = a;
+  *ptr = nullptr;
+  if (!a.alloc) return hipMalloc(ptr, bytes);
+  void* p = a.alloc(bytes, a.ctx);
+  if (!p) return hipErrorOutOfMemory;
+  if (reinterpret_cast<uintptr_t>(p) % OffsetArena::kAlign) {
+    a.free(p, a.ctx);
+    return hipErrorInvalidValue;
+  }
+  *ptr = p;
+  return hipSuccess;
+}
+
+void dev_free(void* ptr, const DevAllocator& by) {
+  if (!ptr) return;
+  if (by.free) by.free(ptr, by.ctx);
+  else (void)hipFree(ptr);
+}
+
+}  // namespace pico
 
 struct pico_op_s {
   int ny = 0, nx = 0, nc = 0, sampling = 0, recon = 0;
@@ -101,10 +137,16 @@ struct pico_op_s {
   // Kaiser-Bessel gridding data path (non-Cartesian, kb_width > 0)
   bool has_kb = false;
   pico::KbOp kb;
-  // device memory: from hipMalloc, or from a serving arena when one is set;
-  // bytes are counted in 256-byte pieces (current and peak)
+  // device memory: from the allocator in effect (pico_set_allocator, else
+  // hipMalloc), or from a serving arena when one is set; bytes are counted in
+  // 256-byte pieces (current and peak)
+  struct Alloc {
+    void* ptr;
+    size_t bytes;
+    pico::DevAllocator by;
+  };
   pico::DeviceArena* arena = nullptr;
-  std::vector<std::pair<void*, size_t>> allocs;
+  std::vector<Alloc> allocs;
   size_t bytes = 0, peak = 0;
   // optional per-kernel-class timing with HIP events on the caller's stream
   bool prof_on = false;
@@ -114,11 +156,11 @@ struct pico_op_s {
 
   ~pico_op_s() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    for (auto& a : allocs) free_raw(a.first);
+    for (auto& a : allocs) free_raw(a);
   }
-  void free_raw(void* ptr) {
-    if (arena) arena->release(ptr);
-    else (void)hipFree(ptr);
+  void free_raw(const Alloc& a) {
+    if (arena) arena->release(a.ptr);
+    else pico::dev_free(a.ptr, a.by);
   }
   hipEvent_t next_event() {
     if (ev_used == ev_pool.size()) {
@@ -132,24 +174,25 @@ struct pico_op_s {
   hipError_t alloc(T** ptr, size_t count) {
     const size_t nb = pico::OffsetArena::round_up(count * sizeof(T));
     void* raw = nullptr;
+    pico::DevAllocator by;
     if (arena) {
       raw = arena->alloc(nb);
       if (!raw) return hipErrorOutOfMemory;
     } else {
-      hipError_t e = hipMalloc(&raw, nb);
+      hipError_t e = pico::dev_alloc(&raw, nb, &by);
       if (e != hipSuccess) return e;
     }
-    allocs.push_back({raw, nb});
+    allocs.push_back({raw, nb, by});
     bytes += nb;
     peak = std::max(peak, bytes);
     *ptr = static_cast<T*>(raw);
     return hipSuccess;
   }
   void release(void* ptr) {
-    auto it = std::find_if(allocs.begin(), allocs.end(), [&](const auto& a) { return a.first == ptr; });
+    auto it = std::find_if(allocs.begin(), allocs.end(), [&](const Alloc& a) { return a.ptr == ptr; });
     if (it != allocs.end()) {
-      free_raw(ptr);
-      bytes -= it->second;
+      free_raw(*it);
+      bytes -= it->bytes;
       allocs.erase(it);
     }
   }
@@ -667,6 +710,17 @@ pico_status_t validate(const pico_op_desc_t* d) {
 extern "C" {
 
 const char* pico_last_error(void) { return g_err.c_str(); }
+
+pico_status_t pico_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* ptr, void* ctx),
+                                 void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(PICO_EINVAL, "pico_set_allocator needs both callbacks, or neither to restore hipMalloc / hipFree");
+  std::lock_guard<std::mutex> lk(pico::g_alloc_mu);
+  pico::g_alloc.alloc = alloc;
+  pico::g_alloc.free = free_fn;
+  pico::g_alloc.ctx = alloc ? ctx : nullptr;
+  return PICO_OK;
+}
 
 }  // extern "C"
 
@@ -1307,10 +1361,18 @@ pico_status_t pico_init_reduced(const pico_op_desc_t* d, int32_t factor, void* s
   float2* maps_c = nullptr;
   uint8_t* mask_c = nullptr;
   float* traj_c = nullptr;
+  pico::DevAllocator by_maps, by_mask, by_traj;   // temporaries, from the allocator in effect
+  auto tmp_alloc = [](auto** p, size_t bytes, pico::DevAllocator* by) {
+    void* raw = nullptr;
+    const hipError_t e = pico::dev_alloc(&raw, pico::OffsetArena::round_up(bytes), by);
+    *p = static_cast<std::remove_reference_t<decltype(**p)>*>(raw);
+    return e;
+  };
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(s);
-    for (void* p : {(void*)maps_c, (void*)mask_c, (void*)traj_c})
-      if (p) (void)hipFree(p);
+    pico::dev_free(maps_c, by_maps);
+    pico::dev_free(mask_c, by_mask);
+    pico::dev_free(traj_c, by_traj);
   };
   auto dev_fail = [&](hipError_t e, const char* what) {
     cleanup();
@@ -1318,7 +1380,7 @@ pico_status_t pico_init_reduced(const pico_op_desc_t* d, int32_t factor, void* s
     return fail(PICO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
   };
   hipError_t e;
-  if ((e = hipMalloc(&maps_c, (size_t)nc * cy * cx * sizeof(float2))) != hipSuccess) return dev_fail(e, "coarse maps");
+  if ((e = tmp_alloc(&maps_c, (size_t)nc * cy * cx * sizeof(float2), &by_maps)) != hipSuccess) return dev_fail(e, "coarse maps");
   if ((e = pico::launch_subsample_maps((const float2*)d->maps, maps_c, nc, ny, nx, factor, s)) != hipSuccess)
     return dev_fail(e, "coarse maps");
   c.maps = maps_c;
@@ -1328,11 +1390,11 @@ pico_status_t pico_init_reduced(const pico_op_desc_t* d, int32_t factor, void* s
       return fail(PICO_EINVAL, "NULL mask");
     }
     if (d->sampling == PICO_CART_1D) {
-      if ((e = hipMalloc(&mask_c, cy)) != hipSuccess ||
+      if ((e = tmp_alloc(&mask_c, cy, &by_mask)) != hipSuccess ||
           (e = hipMemcpyAsync(mask_c, d->mask + (ny - cy) / 2, cy, hipMemcpyDeviceToDevice, s)) != hipSuccess)
         return dev_fail(e, "coarse mask");
     } else {
-      if ((e = hipMalloc(&mask_c, (size_t)cy * cx)) != hipSuccess ||
+      if ((e = tmp_alloc(&mask_c, (size_t)cy * cx, &by_mask)) != hipSuccess ||
           (e = hipMemcpy2DAsync(mask_c, cx, d->mask + (size_t)((ny - cy) / 2) * nx + (nx - cx) / 2, nx, cx, cy,
                                 hipMemcpyDeviceToDevice, s)) != hipSuccess)
         return dev_fail(e, "coarse mask");
@@ -1359,7 +1421,7 @@ pico_status_t pico_init_reduced(const pico_op_desc_t* d, int32_t factor, void* s
       cleanup();
       return fail(PICO_EINVAL, "no sample inside the coarse band");
     }
-    if ((e = hipMalloc(&traj_c, kept.size() * sizeof(float))) != hipSuccess ||
+    if ((e = tmp_alloc(&traj_c, kept.size() * sizeof(float), &by_traj)) != hipSuccess ||
         (e = hipMemcpyAsync(traj_c, kept.data(), kept.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return dev_fail(e, "coarse trajectory");

@@ -9,6 +9,22 @@
 
 namespace pico {
 
+// Device allocator in effect for library workspaces: the caller's callbacks
+// (pico_set_allocator) or, with both NULL, hipMalloc / hipFree.  Each
+// allocation remembers the allocator that made it, so it is returned to the
+// same one even if the caller installs another in between.
+struct DevAllocator {
+  void* (*alloc)(size_t bytes, void* ctx) = nullptr;
+  void (*free)(void* ptr, void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+// Allocates `bytes` (256-byte aligned) with the allocator in effect, which it
+// reports in *by; hipErrorOutOfMemory when the callback returns NULL, and
+// hipErrorInvalidValue for a pointer that is not 256-byte aligned (it is
+// handed back to the callback first).
+hipError_t dev_alloc(void** ptr, size_t bytes, DevAllocator* by);
+void dev_free(void* ptr, const DevAllocator& by);
+
 // Per-probe CG state flags
 enum : int { CG_ACTIVE = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
 

@@ -29,6 +29,7 @@
 
 #include "arena.h"
 #include "pico.h"
+#include "runtime.h"
 
 namespace pico {
 pico_status_t set_error(pico_status_t st, const std::string& msg);
@@ -58,6 +59,7 @@ using Clock = std::chrono::steady_clock;
 
 struct pico_server_s {
   pico::DeviceArena arena;
+  pico::DevAllocator base_by;       // allocator that made arena.base
   int device = 0;
   int max_slots = 1, depth = 2;
   std::vector<hipStream_t> streams;
@@ -247,7 +249,7 @@ pico_status_t pico_server_create(uint64_t hbm_budget, int32_t max_slots, int32_t
   if (hipGetDevice(&srv->device) != hipSuccess) return pico::set_error(PICO_EDEVICE, "no current device");
   srv->arena.book.reset(hbm_budget);
   void* base = nullptr;
-  hipError_t e = hipMalloc(&base, srv->arena.book.capacity());
+  hipError_t e = pico::dev_alloc(&base, srv->arena.book.capacity(), &srv->base_by);
   if (e != hipSuccess)
     return pico::set_error(e == hipErrorOutOfMemory ? PICO_ENOMEM : PICO_EDEVICE,
                            std::string("server budget: ") + hipGetErrorString(e));
@@ -256,7 +258,7 @@ pico_status_t pico_server_create(uint64_t hbm_budget, int32_t max_slots, int32_t
     hipStream_t s = nullptr;
     if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) {
       for (hipStream_t t : srv->streams) (void)hipStreamDestroy(t);
-      (void)hipFree(base);
+      pico::dev_free(base, srv->base_by);
       return pico::set_error(PICO_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
     }
     srv->streams.push_back(s);
@@ -357,7 +359,7 @@ void pico_server_destroy(pico_server_t srv) {
   if (srv->worker.joinable()) srv->worker.join();   // serves what was submitted, then exits
   for (hipEvent_t e : srv->ev_pool) (void)hipEventDestroy(e);
   for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
-  (void)hipFree(srv->arena.base);
+  pico::dev_free(srv->arena.base, srv->base_by);
   delete srv;
 }
 

@@ -78,13 +78,17 @@ class PicoError(RuntimeError):
 
 _lib = None
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_keep = None     # the installed callback objects (ctypes needs them alive)
+
 EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
            "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse", "pico_monitor_stderr", "pico_noise_map_adaptive", "pico_exact_diag",
            "pico_init_reduced", "pico_upsample_map",
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
            "pico_server_submit", "pico_server_poll", "pico_server_wait_idle", "pico_server_usage",
-           "pico_server_destroy"]
+           "pico_server_destroy", "pico_set_allocator"]
 PROF_KINDS = 8
 PROF_NAMES = ["normal_first", "normal_iter", "cg_update", "cg_scalars", "accumulate", "other"]
 
@@ -142,12 +146,13 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pico_server_destroy.argtypes = [vp]
     lib.pico_server_destroy.restype = None
+    lib.pico_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
     for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
                  "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse",
                  "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
                  "pico_monitor_stderr", "pico_noise_map_adaptive",
                  "pico_estimate_bytes", "pico_op_bytes", "pico_server_create", "pico_server_submit",
-                 "pico_server_poll", "pico_server_wait_idle", "pico_server_usage"):
+                 "pico_server_poll", "pico_server_wait_idle", "pico_server_usage", "pico_set_allocator"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -167,6 +172,38 @@ def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def pico_set_allocator(alloc=None, free=None, ctx=None):
+    """pico_set_allocator with Python callables alloc(nbytes) -> int address
+    (0 on failure) and free(address); both None restores hipMalloc / hipFree."""
+    global _allocator_keep
+    lib = load()
+    if alloc is None and free is None:
+        _check(lib.pico_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator_keep = None
+        return
+    a = ALLOC_FN(lambda nbytes, _ctx: alloc(int(nbytes)) or None)
+    f = FREE_FN(lambda ptr, _ctx: free(int(ptr)))
+    _check(lib.pico_set_allocator(a, f, ctx))
+    _allocator_keep = (a, f)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route every library workspace through torch's caching allocator
+    (torch.cuda.caching_allocator_alloc / _delete on the current device and
+    stream), or back to hipMalloc / hipFree."""
+    if not enable:
+        return pico_set_allocator()
+    import torch
+
+    def alloc(nbytes):
+        try:
+            return torch.cuda.caching_allocator_alloc(nbytes)
+        except RuntimeError:     # out of memory: the library reports PICO_ENOMEM
+            return 0
+
+    pico_set_allocator(alloc, torch.cuda.caching_allocator_delete)
 
 
 def pico_last_error() -> str:

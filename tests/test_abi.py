@@ -125,3 +125,19 @@ def test_struct_layouts_match_the_header(tmp_path):
             assert ctypes.sizeof(py) == int(val), cname
         else:
             assert getattr(py, what).offset == int(val), (cname, what)
+
+
+def test_set_allocator_arguments(lib):
+    # host-only: installing and removing callbacks touches no device
+    from paper_2605_09590_amd import pico as p
+    calls = []
+    cb_a = p.ALLOC_FN(lambda n, ctx: calls.append(n) or None)
+    cb_f = p.FREE_FN(lambda ptr, ctx: None)
+    assert lib.pico_set_allocator(cb_a, p.FREE_FN(), None) == p.PICO_EINVAL
+    assert "both callbacks" in p.pico_last_error()
+    assert lib.pico_set_allocator(p.ALLOC_FN(), cb_f, None) == p.PICO_EINVAL
+    assert lib.pico_set_allocator(cb_a, cb_f, None) == p.PICO_OK
+    assert lib.pico_set_allocator(p.ALLOC_FN(), p.FREE_FN(), None) == p.PICO_OK
+    p.pico_set_allocator(lambda n: 0, lambda ptr: None)
+    p.pico_set_allocator()
+    assert calls == []
