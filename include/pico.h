@@ -240,6 +240,20 @@ pico_status_t pico_finalize(pico_op_t op, const pico_accum_t* acc, double* var, 
 pico_status_t pico_pmr_baseline(pico_op_t op, uint64_t seed, int64_t first, int64_t nrep,
                                 pico_accum_t* acc, pico_stats_t* stats, void* stream);
 
+/* pico_pmr_cs for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same replicas, batches and sums as pico_pmr_cs (bitwise), with the
+ * replica workspace in a fixed 64 MiB device array of the library (one per
+ * GPU, held until the process ends) instead of device memory allocated on
+ * the first call.  The workspace of B = min(probe_tile, 16) replicas,
+ * B (2 ncoils + 6) ny nx 16 bytes (TV: B (2 ncoils + 11) ny nx 16), must fit
+ * in it: larger operators get PICO_EINVAL and nothing is enqueued.  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (any operator, any stream) race: a caller must
+ * order them (one stream, or events).  Errors: as pico_pmr_cs. */
+pico_status_t pico_pmr_cs_noalloc(pico_op_t op, uint64_t seed, int64_t first, int64_t nrep, double sigma,
+                                  pico_accum_t* acc, void* stream);
+
 /* Unbiased replica variance (sumsq - |sum|^2 / N) / (N - 1) into var
  * (device float64 [ny*nx]).  Errors: PICO_EINVAL (count < 2, NULL fields). */
 pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* var, void* stream);

@@ -1252,6 +1252,93 @@ pico_status_t pico_pmr_cs(pico_op_t op, uint64_t seed, int64_t first, int64_t nr
   return PICO_OK;
 }
 
+}  // extern "C"
+
+// Workspace of pico_pmr_cs_noalloc: a fixed device array, one copy per GPU,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device memory: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+static constexpr size_t kNoallocBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoallocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+char* g_scratch_dev[kMaxDevices] = {};   // guarded by g_scratch_mu
+
+// Device address of `scratch` on the current device (looked up on first use)
+pico_status_t scratch_address(char** out) {
+  int dev = -1;
+  HIP_OR_RETURN(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PICO_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIP_OR_RETURN(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(PICO_EDEVICE, "no device address for the static workspace");
+    g_scratch_dev[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return PICO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pico_status_t pico_pmr_cs_noalloc(pico_op_t op, uint64_t seed, int64_t first, int64_t nrep, double sigma,
+                                  pico_accum_t* acc, void* stream) {
+  if (pico_status_t st = check_op(op)) return st;
+  if (!op->cs) return fail(PICO_EUNSUPPORTED, "pico_pmr_cs_noalloc needs a compressed-sensing operator");
+  if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq)
+    return fail(PICO_EINVAL, "PMR needs sum, sum_im and sumsq buffers");
+  if (nrep < 0 || first < 0) return fail(PICO_EINVAL, "negative replica range");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(PICO_EINVAL, "sigma must be finite and > 0");
+  // the same replica batches as pico_pmr_cs, so the sums agree bit for bit
+  const int B = std::min(op->K, 16);
+  const size_t n = op->image();
+  const bool tv = op->tv_inner > 0;
+  const size_t img = pico::OffsetArena::round_up((size_t)B * n * sizeof(double2));
+  const size_t coil = pico::OffsetArena::round_up((size_t)B * op->nc * n * sizeof(double2));
+  const size_t need = 2 * coil + 6 * img + (tv ? 5 * img : 0);
+  if (need > kNoallocBytes)
+    return fail(PICO_EINVAL, "replica workspace of " + std::to_string(need) + " bytes (" + std::to_string(B) +
+                                 " replicas of " + std::to_string(op->ny) + "x" + std::to_string(op->nx) + "x" +
+                                 std::to_string(op->nc) + ") exceeds the static " +
+                                 std::to_string(kNoallocBytes >> 20) + " MiB workspace");
+  char* base = nullptr;
+  if (pico_status_t st = scratch_address(&base)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  op->last_stream = s;
+  // every piece is written before it is read (noise draw, zero starts), so
+  // nothing left by an earlier call needs clearing
+  pico::Cs64 o = op->c64;
+  char* cur = base;
+  auto take = [&](size_t bytes) {
+    double2* p = reinterpret_cast<double2*>(cur);
+    cur += bytes;
+    return p;
+  };
+  o.U = take(coil);
+  o.V = take(coil);
+  double2 *atb = take(img), *y = take(img), *x = take(img), *z = take(img), *tmp = take(img), *q = take(img);
+  if (tv) {
+    o.tv_r = take(2 * img);
+    o.tv_p = take(2 * img);
+    o.tv_u = take(img);
+  }
+  for (int64_t done = 0; done < nrep;) {
+    const int b = (int)std::min<int64_t>(B, nrep - done);
+    HIP_OR_RETURN(pico::cs64_pmr(o, b, op->atb64, op->x64, op->s2, op->cs_lam, op->fista_T, op->theta64.data(), seed,
+                                 (uint64_t)(first + done), sigma, atb, y, x, z, tmp, q, acc->sum, acc->sum_im,
+                                 acc->sumsq, s));
+    done += b;
+  }
+  acc->count += nrep;
+  return PICO_OK;
+}
+
 pico_status_t pico_pmr_finalize(pico_op_t op, const pico_accum_t* acc, double* var, void* stream) {
   if (pico_status_t st = check_op(op)) return st;
   if (!acc || !acc->sum || !acc->sum_im || !acc->sumsq || !var)

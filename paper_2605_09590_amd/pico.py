@@ -88,7 +88,7 @@ EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", 
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
            "pico_server_submit", "pico_server_poll", "pico_server_wait_idle", "pico_server_usage",
-           "pico_server_destroy", "pico_set_allocator"]
+           "pico_server_destroy", "pico_set_allocator", "pico_pmr_cs_noalloc"]
 PROF_KINDS = 8
 PROF_NAMES = ["normal_first", "normal_iter", "cg_update", "cg_scalars", "accumulate", "other"]
 
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(pico_stats_t), vp]
     lib.pico_pmr_finalize.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp, vp]
     lib.pico_pmr_cs.argtypes = [vp, u64, i64, i64, ctypes.c_double, ctypes.POINTER(pico_accum_t), vp]
+    lib.pico_pmr_cs_noalloc.argtypes = [vp, u64, i64, i64, ctypes.c_double, ctypes.POINTER(pico_accum_t), vp]
     lib.pico_monitor_nrmse.argtypes = [vp, ctypes.POINTER(pico_accum_t), vp,
                                        ctypes.POINTER(ctypes.c_double), vp]
     lib.pico_exact_diag.argtypes = [vp, vp, vp]
@@ -148,8 +149,8 @@ def load(path: str = LIB_PATH):
     lib.pico_server_destroy.restype = None
     lib.pico_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
     for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
-                 "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_monitor_nrmse",
-                 "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
+                 "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_pmr_cs_noalloc",
+                 "pico_monitor_nrmse", "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
                  "pico_monitor_stderr", "pico_noise_map_adaptive",
                  "pico_estimate_bytes", "pico_op_bytes", "pico_server_create", "pico_server_submit",
                  "pico_server_poll", "pico_server_wait_idle", "pico_server_usage", "pico_set_allocator"):
@@ -327,6 +328,11 @@ def pico_pmr_baseline(h, seed, first, nrep, acc, stats=None, stream=None):
 def pico_pmr_cs(h, seed, first, nrep, sigma, acc, stream=None):
     return _check(load().pico_pmr_cs(h, int(seed), int(first), int(nrep), float(sigma), ctypes.byref(acc),
                                      _stream(stream)))
+
+
+def pico_pmr_cs_noalloc(h, seed, first, nrep, sigma, acc, stream=None):
+    return _check(load().pico_pmr_cs_noalloc(h, int(seed), int(first), int(nrep), float(sigma),
+                                             ctypes.byref(acc), _stream(stream)))
 
 
 def pico_pmr_finalize(h, acc, var, stream=None):

@@ -87,14 +87,19 @@ def test_torch_allocator_holds_every_operator_byte(lib):
     lib.pico_noise_map(h, 11, 0, 8, 0, lib.make_accum(s1))
     torch.cuda.synchronize()
     assert torch.equal(s0, s1)                          # same kernels, same result
+    del s1
     lib.pico_destroy(h)
     assert cnt.live == {}
     assert torch.cuda.memory_allocated() == base
     say(f"  resident {resident} B in {cnt.calls} blocks (peak {peak} B), all returned")
 
-    # the reduced-grid temporaries and operator go through it too
+    # the reduced-grid temporaries and operator go through it too (128^2 -> 64^2)
+    rng = np.random.default_rng(4)
+    maps2 = _dev(workloads.coil_maps(128, 128, 4, rng).astype(np.complex64))
+    psi2 = workloads.noise_cov(4, rng)
+    mask2 = _dev(workloads.cart_mask_1d(128, 2, 8))
     calls = cnt.calls
-    hr = lib.pico_init_reduced(2, prob.ny, prob.nx, maps, prob.psi, mask, cg_iters=20, probe_tile=8)
+    hr = lib.pico_init_reduced(2, 128, 128, maps2, psi2, mask2, cg_iters=20, probe_tile=8)
     r_res, _ = lib.pico_op_bytes(hr)
     assert cnt.calls > calls and sum(cnt.live.values()) == r_res
     lib.pico_destroy(hr)
