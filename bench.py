@@ -330,7 +330,8 @@ def dense_leg(lib, torch, np, dev, prob, form=2, steps=3, ref=None):
     maps = torch.from_numpy(prob.maps.astype(np.complex64)).to(dev)
     mask = torch.from_numpy(prob.mask).to(dev)
     h = lib.pico_init(ny, nx, maps, prob.psi, mask, cg_iters=prob.cg_iters, probe_tile=K, normal_form=form)
-    acc = lib.make_accum(*[torch.zeros(ny * nx, dtype=torch.float64, device=dev) for _ in range(2)])
+    acc_keep = [torch.zeros(ny * nx, dtype=torch.float64, device=dev) for _ in range(2)]
+    acc = lib.make_accum(*acc_keep)
     lib.pico_noise_map(h, 3, 0, K, 0, acc)
     torch.cuda.synchronize()
     lib.pico_profile_start(h)
@@ -407,8 +408,8 @@ def reduced_leg(lib, torch, np, dev, prob, ref, factor=2, max_probes=1024):
     floor = nrmse(up)
     acc_t = [torch.zeros(cy * cx, dtype=torch.float64, device=dev) for _ in range(2)]
     acc = lib.make_accum(acc_t[0], None, acc_t[1])
-    lib.pico_noise_map(h, 17, 0, 256, 0, lib.make_accum(*[torch.zeros(cy * cx, dtype=torch.float64, device=dev)
-                                                          for _ in range(2)]))   # warm-up
+    warm_t = [torch.zeros(cy * cx, dtype=torch.float64, device=dev) for _ in range(2)]
+    lib.pico_noise_map(h, 17, 0, 256, 0, lib.make_accum(*warm_t))   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     curve, done = [], 0
@@ -449,7 +450,8 @@ def spiral_leg(lib, workloads, torch, np, dev, steps, storage):
                        nsamples=traj.shape[0], storage=storage)
     sinit = time.perf_counter() - t0
     ns = sp.ny * sp.nx
-    sacc = lib.make_accum(*[torch.zeros(ns, dtype=torch.float64, device=dev) for _ in range(2)])
+    sacc_t = [torch.zeros(ns, dtype=torch.float64, device=dev) for _ in range(2)]
+    sacc = lib.make_accum(*sacc_t)
     lib.pico_noise_map(hs, 5, 0, Ks, 0, sacc)            # warm-up step
     torch.cuda.synchronize()
     lib.pico_profile_start(hs)
@@ -558,6 +560,12 @@ def spiral_ttt_leg(lib, workloads, torch, np, dev, n_ref=16384, chunk=64, max_n=
             "paper_context": "paper, GE spiral phantom R=2 on its own hardware: 64 s (PICO) vs 462 s (PMR)"}
 
 
+def std_map_nrmse(torch, a, ref):
+    """||sqrt(a) - sqrt(ref)|| / ||sqrt(ref)|| of two variance maps (std maps)."""
+    sa, sr = torch.sqrt(torch.clamp(a, min=0.0)), torch.sqrt(torch.clamp(ref, min=0.0))
+    return float(torch.linalg.norm(sa - sr) / torch.linalg.norm(sr))
+
+
 def cs_leg(lib, workloads, torch, np, dev, steps, storage=0):
     """JVPs/s of the CS workload and the HBM roofline of its normal operator."""
     pr = workloads.config(4, seed=0)
@@ -573,7 +581,8 @@ def cs_leg(lib, workloads, torch, np, dev, steps, storage=0):
                       cs_lambda=pr.extra["cs_lambda"], wavelet_levels=pr.extra["levels"], probe_tile=K,
                       storage=storage)
     init_s = time.perf_counter() - t0
-    acc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)])
+    acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    acc = lib.make_accum(*acc_t)
     lib.pico_noise_map(h, 3, 0, K, 0, acc)                   # warm-up step
     torch.cuda.synchronize()
     lib.pico_profile_start(h)
@@ -585,6 +594,7 @@ def cs_leg(lib, workloads, torch, np, dev, steps, storage=0):
     torch.cuda.synchronize()
     prof = lib.pico_profile_stop(h)
     lib.pico_destroy(h)
+    vmap = acc_t[0].cpu()
     ms = e0.elapsed_time(e1) / steps
     it_ms, it_n = prof["normal_iter"]
     op_s = it_ms / it_n / 1e3
@@ -605,6 +615,7 @@ def cs_leg(lib, workloads, torch, np, dev, steps, storage=0):
                      "kernel": "grid normal operator (rows_fwd + cols + rows_inv), C1_APPLY",
                      "avg_application_us": round(op_s * 1e6, 1), "alg_bytes": alg},
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "_map": vmap, "probes_accumulated": K * (steps + 1),
     }
 
 
@@ -629,7 +640,8 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t0
     resident, _ = lib.pico_op_bytes(h)
-    acc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)])
+    acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    acc = lib.make_accum(*acc_t)
     lib.pico_noise_map(h, 3, 0, K, 0, acc)                   # warm-up step
     torch.cuda.synchronize()
     lib.pico_profile_start(h)
@@ -645,7 +657,8 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     nrep = 16
     pmr_s = None
     if pmr:
-        pacc = lib.make_accum(*[torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)])
+        pacc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        pacc = lib.make_accum(*pacc_t)
         lib.pico_pmr_cs(h, 5, 0, 4, 1e-3, pacc)                  # workspace + warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -653,6 +666,7 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
         torch.cuda.synchronize()
         pmr_s = (time.perf_counter() - t0) / nrep
     lib.pico_destroy(h)
+    vmap = acc_t[0].cpu()
     jvps = K / (ms / 1e3)
     it_ms, it_n = prof["normal_iter"]
     op_s = it_ms / it_n / 1e3
@@ -702,6 +716,7 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
                        "note": "time of the step outside the normal-operator applications: the dual-step "
                                "kernels plus the FISTA momentum and gradient kernels"},
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "_map": vmap, "probes_accumulated": K * (steps + 1),
     }
 
 
@@ -975,6 +990,20 @@ def main():
         cs_tv = cs_tv_leg(lib, workloads, torch, np, dev, args.cs_tv_steps)
         cs_tv_bf16 = cs_tv_leg(lib, workloads, torch, np, dev, args.cs_tv_steps, storage=lib.PICO_BF16_STREAM,
                                pmr=False)
+
+    # bfloat16 storage against FP32 storage: the same probes, so the maps differ
+    # by the storage rounding alone
+    for leg, ref_leg in ((cs_bf16, cs_res), (cs_tv_bf16, cs_tv)):
+        if leg is not None and ref_leg is not None:
+            leg["map_vs_f32_storage"] = {
+                "std_map_nrmse": round(std_map_nrmse(torch, leg["_map"], ref_leg["_map"]), 6),
+                "var_map_rel": round(float(torch.linalg.norm(leg["_map"] - ref_leg["_map"]) /
+                                           torch.linalg.norm(ref_leg["_map"])), 6),
+                "probes": leg["probes_accumulated"]}
+    for leg in (cs_res, cs_bf16, cs_tv, cs_tv_bf16):
+        if leg is not None:
+            leg.pop("_map", None)
+            leg.pop("probes_accumulated", None)
 
     robust = (cs_robustness(lib, workloads, torch, np, dev, reg=args.cs_robustness)
               if args.cs_robustness != "off" else None)

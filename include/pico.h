@@ -79,8 +79,12 @@ typedef enum {
 typedef enum {
   PICO_FP32 = 0,           /* complex64 maps and intermediates (default)        */
   PICO_BF16_MAPS = 1,      /* whitened maps rounded to bfloat16 (nearest even)
-                              and stored packed; the operator is the one of the
-                              rounded maps on every path                          */
+                              and stored packed.  CG-SENSE: the operator is the
+                              one of the rounded maps on every path.  Compressed
+                              sensing: only the tangents' normal-operator reads
+                              use them; the FP64 reconstruction (the point the
+                              Jacobian is taken at) and the probes' k-space
+                              adjoint keep the unrounded maps                     */
   PICO_BF16_STREAM = 2     /* as 1, plus the row-transformed coil planes of the
                               2-D grid path (Cartesian 2-D, Toeplitz) stored as
                               bfloat16 between its passes; arithmetic, CG vectors,

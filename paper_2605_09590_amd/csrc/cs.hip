@@ -500,19 +500,6 @@ __global__ void k_prep_maps64(const float2* __restrict__ maps, const double* __r
   }
 }
 
-// S[c] = (-1)^(y+x) folded[c]: the FP64 primal's maps from the maps of the
-// FP32 operator (whitened, sign-folded)
-__global__ void k_unfold_maps64(const float2* __restrict__ folded, double2* __restrict__ S, int nc, int nx,
-                                long n) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double sg = (((i / nx) + (i % nx)) & 1) ? -1.0 : 1.0;
-  for (int c = 0; c < nc; ++c) {
-    const float2 m = folded[(size_t)c * n + i];
-    S[(size_t)c * n + i] = make_double2(sg * m.x, sg * m.y);
-  }
-}
-
 // U[c] = mask * sum_{d <= c} Linv[c][d] kdata[d]   (whitened, sampled k-space)
 __global__ void k_whiten64(const float2* __restrict__ kd, const double* __restrict__ linv,
                            const uint8_t* __restrict__ mask, double2* __restrict__ U, int nc, long n) {
@@ -708,12 +695,6 @@ hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream
   hipLaunchKernelGGL(k_centred_dft64, grid1((long)o.ny * o.ny), dim3(256), 0, s, o.Fy, o.ny);
   hipLaunchKernelGGL(k_centred_dft64, grid1((long)o.nx * o.nx), dim3(256), 0, s, o.Fx, o.nx);
   hipLaunchKernelGGL(k_prep_maps64, grid1(n), dim3(256), 0, s, maps, linv, o.S, o.nc, n);
-  return hipGetLastError();
-}
-
-hipError_t cs64_maps_from_folded(Cs64& o, const float2* folded, hipStream_t s) {
-  const long n = (long)o.ny * o.nx;
-  hipLaunchKernelGGL(k_unfold_maps64, grid1(n), dim3(256), 0, s, folded, o.S, o.nc, o.nx, n);
   return hipGetLastError();
 }
 

@@ -254,16 +254,17 @@ __global__ void k_mask_weights(const uint8_t* __restrict__ mask, float* __restri
   w[(size_t)kx * ny + ky] = mask[i] ? scale : 0.f;
 }
 
-__global__ void k_quantise_maps(float2* __restrict__ maps, uint32_t* __restrict__ bf, long count) {
+__global__ void k_quantise_maps(float2* __restrict__ maps, uint32_t* __restrict__ bf, long count, int round_copy) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const uint32_t w = pack_bf16x2(maps[i]);
   bf[i] = w;
-  maps[i] = unpack_bf16x2(w);
+  if (round_copy) maps[i] = unpack_bf16x2(w);
 }
 
-hipError_t launch_quantise_maps(float2* maps, uint32_t* bf, long count, hipStream_t s) {
-  hipLaunchKernelGGL(k_quantise_maps, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, maps, bf, count);
+hipError_t launch_quantise_maps(float2* maps, uint32_t* bf, long count, bool round_copy, hipStream_t s) {
+  hipLaunchKernelGGL(k_quantise_maps, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, maps, bf, count,
+                     round_copy ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -917,7 +917,7 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if ((e = hipMemcpyAsync(op->maskw, w.data(), ny * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     if ((e = hipMemcpyAsync(op->twt, tw.data(), ny * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     if ((e = pico::launch_prep_maps_cart1d((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, s)) != hipSuccess) return bad(e, "prep maps");
-    if (op->maps_bf && (e = pico::launch_quantise_maps(op->maps, op->maps_bf, (long)(n * nc), s)) != hipSuccess) return bad(e, "bfloat16 maps");
+    if (op->maps_bf && (e = pico::launch_quantise_maps(op->maps, op->maps_bf, (long)(n * nc), true, s)) != hipSuccess) return bad(e, "bfloat16 maps");
     if (wants_gram(d)) {
       if ((e = op->alloc(&op->gram, pico::gram_bytes(ny, nx) / sizeof(float2))) != hipSuccess) return bad(e, "dense blocks");
       if ((e = op->alloc(&op->gram_c, ny)) != hipSuccess) return bad(e, "dense blocks");
@@ -944,7 +944,12 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if ((e = hipMemcpyAsync(op->twy, ty.data(), Gy * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
     const int fold = d->sampling == PICO_CART_2D;
     if ((e = pico::launch_prep_maps_rowmajor((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, fold, s)) != hipSuccess) return bad(e, "prep maps");
-    if (op->maps_bf && (e = pico::launch_quantise_maps(op->maps, op->maps_bf, (long)(n * nc), s)) != hipSuccess) return bad(e, "bfloat16 maps");
+    // CG-SENSE: the rounded maps define the operator on every path (the FP32
+    // copy is rounded too).  Compressed sensing: bfloat16 is a storage form of
+    // the normal-operator reads in the tangents only; the FP64 primal (the
+    // linearisation point and its active set) and the k-space adjoint of the
+    // probes keep the unrounded maps.
+    if (op->maps_bf && (e = pico::launch_quantise_maps(op->maps, op->maps_bf, (long)(n * nc), d->recon == PICO_CGSENSE, s)) != hipSuccess) return bad(e, "bfloat16 maps");
     if (d->sampling == PICO_CART_2D) {
       if ((e = pico::launch_mask_weights(d->mask, op->w, ny, nx, (float)(1.0 / ((double)ny * nx)), s)) != hipSuccess) return bad(e, "weights");
     } else {
@@ -1032,8 +1037,6 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
                (e = op->alloc(&o.tv_u, n)) != hipSuccess))
       return bad(e, "FP64 TV workspace");
     if ((e = pico::cs64_setup(o, (const float2*)d->maps, linv_d, s)) != hipSuccess) return bad(e, "FP64 primal");
-    // bfloat16 storage defines the operator by the rounded maps: the primal uses them too
-    if (op->maps_bf && (e = pico::cs64_maps_from_folded(o, op->maps, s)) != hipSuccess) return bad(e, "FP64 primal");
     double lam_hat = 0.0;
     if ((e = pico::cs64_power(o, d->power_iters, y, z, part, &lam_hat, s)) != hipSuccess) return bad(e, "power");
     op->s2 = d->power_margin * lam_hat;

@@ -124,9 +124,9 @@ hipError_t launch_prep_maps_rowmajor(const float2* maps, const double* linv, flo
                                      int ny, int nx, int fold, hipStream_t s);
 hipError_t launch_mask_weights(const uint8_t* mask, float* w, int ny, int nx, float scale,
                                hipStream_t s);
-// maps rounded to bfloat16 (nearest even): packed copy in bf, and the rounded
-// values written back to maps, so every reader sees the same operator
-hipError_t launch_quantise_maps(float2* maps, uint32_t* bf, long count, hipStream_t s);
+// bf = maps rounded to bfloat16 (nearest even); round_copy: maps too become
+// the rounded values (the FP32 copy then describes the same operator)
+hipError_t launch_quantise_maps(float2* maps, uint32_t* bf, long count, bool round_copy, hipStream_t s);
 // reduced-resolution grid: maps [nc][ny][nx] -> [nc][ny/f][nx/f] at native pixels
 // (f my, f mx); coarse map [cy][cx] -> [f cy][f cx] by periodic bilinear weights
 hipError_t launch_subsample_maps(const float2* maps, float2* out, int nc, int ny, int nx, int f, hipStream_t s);
@@ -190,9 +190,6 @@ struct Cs64 {
   float* tv_invn = nullptr;
 };
 hipError_t cs64_setup(Cs64& o, const float2* maps, const double* linv, hipStream_t s);
-// FP64 maps of the primal from already whitened, (-1)^(y+x)-folded maps
-// (bfloat16 storage: the primal uses the rounded operator too)
-hipError_t cs64_maps_from_folded(Cs64& o, const float2* folded, hipStream_t s);
 hipError_t cs64_normal(const Cs64& o, int B, const double2* y, double2* q, hipStream_t s);
 hipError_t cs64_adjoint_kdata(const Cs64& o, const float2* kdata, const double* linv, double2* out,
                               hipStream_t s);

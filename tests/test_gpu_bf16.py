@@ -8,9 +8,13 @@ Two comparisons per case:
   bar 1e-2.
 With PICO_BF16_STREAM the grid path also keeps its row-transformed coil
 planes in bfloat16; that rounding sits inside the operator and only the
-1e-2 bar applies.  For the nonlinear CS map the bars are against the
-rounded-map oracle (its Jacobian depends on the primal, which the rounded
-operator moves).
+1e-2 bar applies.  For the nonlinear CS map bfloat16 is a storage form of
+the tangents' normal-operator reads only: the FP64 primal (the linearisation
+point, whose active set fixes the Jacobian) and the k-space adjoint of the
+probes use the unrounded maps, so the reconstruction meets the FP32 bar
+against the FP64-map oracle and the Jacobian probes and their noise map the
+1e-2 bar; at full size the bfloat16 noise map is compared with the FP32-storage
+map of the same probes.
 """
 import sys
 
@@ -127,86 +131,96 @@ def test_bf16_spiral_noise_map(lib, storage):
         assert eq < TOL
 
 
-@pytest.mark.parametrize("storage", [1, 2])
-def test_bf16_cs_jvp(lib, storage):
-    say(f"case: CS L1-db4 64x64, 4 coils, Poisson-disc R=2, lam 1e-3, FISTA 30, 3 levels; recon and "
-        f"2 JVPs, storage {storage}")
-    rng = np.random.default_rng(3)
-    maps = workloads.coil_maps(64, 64, 4, rng)
-    psi = workloads.noise_cov(4, rng)
-    x = workloads.phantom(64, rng)
-    mask = workloads.poisson_disc_mask(64, 64, 2.0, 8, seed=3)
+def _std_nrmse(a, b):
+    sa, sb = np.sqrt(np.maximum(a, 0)), np.sqrt(np.maximum(b, 0))
+    return float(np.linalg.norm(sa - sb) / np.linalg.norm(sb))
+
+
+def _cs_case(n_y, n_x, nc, seed, calib=8):
+    rng = np.random.default_rng(seed)
+    maps = workloads.coil_maps(n_y, n_x, nc, rng)
+    psi = workloads.noise_cov(nc, rng)
+    x = workloads.phantom(max(n_y, n_x), rng)[:n_y, :n_x]
+    mask = workloads.poisson_disc_mask(n_y, n_x, 2.0, calib, seed=seed)
     op = opico.cartesian(maps, psi, mask)
     bw = op.forward(x)
     bw = bw + 1e-3 * op.P[None] * (rng.standard_normal(bw.shape) + 1j * rng.standard_normal(bw.shape))
     braw = np.einsum("cd,dyx->cyx", np.linalg.cholesky(psi), bw)
+    return maps, psi, mask, op, bw, braw
+
+
+def _cs_check(lib, h, f, op, bw, shape, nprobe_map=6):
+    """Reconstruction (FP32 bar), 2 Jacobian probes and a 6-probe |J w|^2 map
+    (1e-2 bar) against the FP64-map oracle ``f``."""
+    ny, nx = shape
+    w = np.stack([ocs.kspace_probe(op, 8, i) for i in range(2)])
+    ut = torch.empty((2, ny, nx), dtype=torch.complex64, device="cuda:0")
+    lib.pico_apply_jvp(h, _dev(w.astype(np.complex64)), ut, 2)
+    xg = torch.empty((ny, nx), dtype=torch.complex64, device="cuda:0")
+    lib.pico_recon(h, xg)
+    g = _gpu_map(lib, h, ny * nx, 21, 0, nprobe_map)
+    torch.cuda.synchronize()
+    xr, cr = f.recon(bw, store=True)
+    e = _rel(xg.cpu().numpy(), xr)
+    say(f"  reconstruction vs FP64-map oracle {e:.2e}")
+    assert e < TOL                       # the primal never sees the rounded maps
+    u = ut.cpu().numpy()
+    for k in range(2):
+        e = _rel(u[k], f.jvp(w[k], cr))
+        say(f"  jvp probe {k} vs FP64-map oracle {e:.2e}")
+        assert e < TOL_BF16
+    ref = ocs.noise_map_jvp(f, cr, 21, 0, nprobe_map)["sum"].ravel()
+    e, es = _rel(g, ref), _std_nrmse(g, ref)
+    say(f"  |J w|^2 map ({nprobe_map} probes) vs FP64-map oracle: var {e:.2e}, std map {es:.2e}")
+    assert e < TOL_BF16 and es < TOL_BF16
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_bf16_cs_jvp(lib, storage):
+    say(f"case: CS L1-db4 64x64, 4 coils, Poisson-disc R=2, lam 1e-3, FISTA 30, 3 levels; recon, "
+        f"2 JVPs and a 6-probe map, storage {storage}")
+    maps, psi, mask, op, bw, braw = _cs_case(64, 64, 4, 3)
     h = lib.pico_init(64, 64, _dev(maps.astype(np.complex64)), psi, _dev(mask), sampling=lib.PICO_CART_2D,
                       recon=lib.PICO_CS_FISTA_L1WAV, kdata=_dev(braw.astype(np.complex64)), fista_iters=30,
                       cs_lambda=1e-3, wavelet_levels=3, probe_tile=2, storage=storage)
-    w = np.stack([ocs.kspace_probe(op, 8, i) for i in range(2)])
-    ut = torch.empty((2, 64, 64), dtype=torch.complex64, device="cuda:0")
-    lib.pico_apply_jvp(h, _dev(w.astype(np.complex64)), ut, 2)
-    xg = torch.empty((64, 64), dtype=torch.complex64, device="cuda:0")
-    lib.pico_recon(h, xg)
-    torch.cuda.synchronize()
-    lib.pico_destroy(h)
-    op_q = opico.cartesian(ostore.bf16_whitened_maps(maps, psi), None, mask)
-    fq = ocs.FistaL1Wavelet(op_q, 1e-3, 30, levels=3)
-    f = ocs.FistaL1Wavelet(op, 1e-3, 30, levels=3)
-    xq, cq = fq.recon(bw, store=True)
-    xr, cr = f.recon(bw, store=True)
-    eq, e = _rel(xg.cpu().numpy(), xq), _rel(xg.cpu().numpy(), xr)
-    say(f"  reconstruction: vs rounded-map oracle {eq:.2e}; vs FP64 maps {e:.2e}")
-    assert eq < TOL and e < TOL_BF16      # the primal is FP64 on the rounded maps
-    # The Jacobian of the nonlinear map changes with its linearisation point
-    # wherever a coefficient crosses the threshold, so rounded maps (a
-    # different operator, hence a different primal) give a different J: the
-    # bar is against the rounded-map oracle, and the FP64-map figure is
-    # reported only.  Plane rounding (storage 2) perturbs the tangents alone.
-    u = ut.cpu().numpy()
-    for k in range(2):
-        eq, e = _rel(u[k], fq.jvp(w[k], cq)), _rel(u[k], f.jvp(w[k], cr))
-        say(f"  jvp probe {k}: vs rounded-map oracle {eq:.2e}; vs FP64 maps {e:.2e} (reported)")
-        assert eq < (TOL if storage == 1 else TOL_BF16)
+    try:
+        _cs_check(lib, h, ocs.FistaL1Wavelet(op, 1e-3, 30, levels=3), op, bw, (64, 64))
+    finally:
+        lib.pico_destroy(h)
 
 
 @pytest.mark.parametrize("storage", [1, 2])
 def test_bf16_tv_cs_jvp(lib, storage):
     say(f"case: TV-CS 64x96, 4 coils, Poisson-disc R=2 (8x8 calib), lam_TV 1e-2, FISTA 30 x 10 dual "
-        f"steps; recon and 2 JVPs, storage {storage}")
-    rng = np.random.default_rng(5)
-    maps = workloads.coil_maps(64, 96, 4, rng)
-    psi = workloads.noise_cov(4, rng)
-    x = workloads.phantom(96, rng)[:64, :96]
-    mask = workloads.poisson_disc_mask(64, 96, 2.0, 8, seed=5)
-    op = opico.cartesian(maps, psi, mask)
-    bw = op.forward(x)
-    bw = bw + 1e-3 * op.P[None] * (rng.standard_normal(bw.shape) + 1j * rng.standard_normal(bw.shape))
-    braw = np.einsum("cd,dyx->cyx", np.linalg.cholesky(psi), bw)
+        f"steps; recon, 2 JVPs and a 6-probe map, storage {storage}")
+    maps, psi, mask, op, bw, braw = _cs_case(64, 96, 4, 5)
     h = lib.pico_init(64, 96, _dev(maps.astype(np.complex64)), psi, _dev(mask), sampling=lib.PICO_CART_2D,
                       recon=lib.PICO_CS_FISTA_TV, kdata=_dev(braw.astype(np.complex64)), fista_iters=30,
                       cs_lambda=1e-2, tv_inner_iters=10, probe_tile=2, storage=storage)
-    w = np.stack([ocs.kspace_probe(op, 8, i) for i in range(2)])
-    ut = torch.empty((2, 64, 96), dtype=torch.complex64, device="cuda:0")
-    lib.pico_apply_jvp(h, _dev(w.astype(np.complex64)), ut, 2)
-    xg = torch.empty((64, 96), dtype=torch.complex64, device="cuda:0")
-    lib.pico_recon(h, xg)
-    torch.cuda.synchronize()
-    lib.pico_destroy(h)
-    fq = ocs.FistaTV(opico.cartesian(ostore.bf16_whitened_maps(maps, psi), None, mask), 1e-2, 30, 10)
-    f = ocs.FistaTV(op, 1e-2, 30, 10)
-    xq, zq = fq.recon(bw, store=True)
-    xr, zr = f.recon(bw, store=True)
-    eq, e = _rel(xg.cpu().numpy(), xq), _rel(xg.cpu().numpy(), xr)
-    say(f"  reconstruction: vs rounded-map oracle {eq:.2e}; vs FP64 maps {e:.2e}")
-    assert eq < TOL and e < TOL_BF16
-    # as for the L1 model: the bar is against the rounded-map oracle (storage 1),
-    # the plane rounding of storage 2 perturbs the tangents alone (1e-2 bar)
-    u = ut.cpu().numpy()
-    for k in range(2):
-        eq, e = _rel(u[k], fq.jvp(w[k], zq)), _rel(u[k], f.jvp(w[k], zr))
-        say(f"  jvp probe {k}: vs rounded-map oracle {eq:.2e}; vs FP64 maps {e:.2e} (reported)")
-        assert eq < (TOL if storage == 1 else TOL_BF16)
+    try:
+        _cs_check(lib, h, ocs.FistaTV(op, 1e-2, 30, 10), op, bw, (64, 96))
+    finally:
+        lib.pico_destroy(h)
+
+
+@pytest.mark.parametrize("recon,nc,K", [("l1", 8, 128), ("tv", 15, 64)])
+def test_bf16_cs_full_size_map_vs_fp32_storage(lib, recon, nc, K):
+    tv = recon == "tv"
+    say(f"case: {'TV' if tv else 'L1-db4'} CS 320x320, {nc} coils, Poisson-disc R=2 (24x24 calib), FISTA 100, "
+        f"K={K} in one launch; noise map of bfloat16 maps + planes vs FP32 storage")
+    maps, psi, mask, op, bw, braw = _cs_case(320, 320, nc, 11, calib=24)
+    maps_t, mask_t, kd_t = _dev(maps.astype(np.complex64)), _dev(mask), _dev(braw.astype(np.complex64))
+    kw = dict(sampling=lib.PICO_CART_2D, recon=lib.PICO_CS_FISTA_TV if tv else lib.PICO_CS_FISTA_L1WAV,
+              kdata=kd_t, fista_iters=100, cs_lambda=1e-2 if tv else 1e-3, wavelet_levels=4,
+              tv_inner_iters=10, probe_tile=K)
+    maps_out = {}
+    for storage in (0, 2):
+        h = lib.pico_init(320, 320, maps_t, psi, mask_t, storage=storage, **kw)
+        maps_out[storage] = _gpu_map(lib, h, 320 * 320, 31, 0, K)
+        lib.pico_destroy(h)
+    e, es = _rel(maps_out[2], maps_out[0]), _std_nrmse(maps_out[2], maps_out[0])
+    say(f"  bfloat16 vs FP32 storage, {K} probes: variance map {e:.2e}, std map {es:.2e}")
+    assert es < TOL_BF16 and e < TOL_BF16
 
 
 def test_bf16_stream_spiral_full_size(lib):
