@@ -153,6 +153,15 @@ typedef struct {
    * (mixed precision; bfloat16 results agree with FP32 storage to about
    * 1e-2 relative). */
   int32_t storage;
+  /* 1: pico_noise_map runs each probe tile as one HIP graph (the tile's whole
+   * kernel sequence: probe draw, every CG iteration, the Tikhonov middle
+   * product or the CS tangent iterations, the FP64 accumulation), captured on
+   * first use per (tile size, probe family, accumulator buffers) and
+   * replayed with the tile's (seed, first probe) read from device memory;
+   * results are bitwise those of direct launches.  Up to 8 graphs per
+   * operator are kept (least recently used evicted).  Not used while kernel
+   * profiling is on (pico_profile_start).  0: direct launches. */
+  int32_t graph;
 } pico_op_desc_t;
 
 /* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a

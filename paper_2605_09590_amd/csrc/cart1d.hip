@@ -112,7 +112,7 @@ __global__ void k_accum_colmajor(AccumArgs a) {
       si += (double)u.y;
       ss += (double)u.x * u.x + (double)u.y * u.y;
     } else {
-      const float2 v = draw_probe(a.seed, a.first + k, vox, 0u, a.dist);
+      const float2 v = draw_probe(arg_seed(a), arg_first(a) + k, vox, 0u, a.dist);
       const double re = (double)v.x * u.x + (double)v.y * u.y;
       const double im = (double)v.x * u.y - (double)v.y * u.x;
       s += re;

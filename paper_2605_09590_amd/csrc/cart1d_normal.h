@@ -127,7 +127,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
         const int kc = CF::posB(lane, r);
         if ((mbits >> r) & 1u) {
           const uint32_t elem = (uint32_t)(((size_t)c * N + kc) * a.nx + col);
-          const float2 n = draw_probe(a.seed, a.first + kk, elem, 1u, 3);
+          const float2 n = draw_probe(arg_seed(a), arg_first(a) + kk, elem, 1u, 3);
           v[r] = cscale(n, ((kc + N / 2) & 1) ? -rs : rs);
         } else {
           v[r] = make_float2(0.f, 0.f);
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
 #pragma unroll
         for (int m = 0; m < VA; ++m) {
           const int y = CF::posA(lane, m);
-          pv[m] = draw_probe(a.seed, a.first + kk, (uint32_t)(y * a.nx + col), 0u, a.dist);
+          pv[m] = draw_probe(arg_seed(a), arg_first(a) + kk, (uint32_t)(y * a.nx + col), 0u, a.dist);
           rv[m] = pv[m];
           if (active) { a.r[base + y] = pv[m]; a.p[base + y] = pv[m]; }
         }

@@ -20,6 +20,19 @@ __global__ __launch_bounds__(256) void k_final_x(FinalArgs a) {
   }
 }
 
+// tp = (seed, first): the probe-sequence position a replayed tile graph reads
+__global__ void k_set_tile(uint64_t* __restrict__ tp, uint64_t seed, uint64_t first) {
+  if (threadIdx.x == 0) {
+    tp[0] = seed;
+    tp[1] = first;
+  }
+}
+
+hipError_t launch_set_tile(uint64_t* tp, uint64_t seed, uint64_t first, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_tile, dim3(1), dim3(64), 0, s, tp, seed, first);
+  return hipGetLastError();
+}
+
 hipError_t launch_final_x(const FinalArgs& a, hipStream_t s) {
   const int nblk = (a.n + 1023) / 1024;
   dim3 grid(nblk < 1024 ? nblk : 1024, a.K), block(256);

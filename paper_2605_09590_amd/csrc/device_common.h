@@ -97,6 +97,18 @@ __device__ __forceinline__ float2 draw_probe(uint64_t seed, uint64_t draw, uint3
   }
 }
 
+// Position of a launch in the probe sequence: (seed, first) from the kernel
+// arguments, or from device memory at a.tp when set (a graph replayed per
+// probe tile reads them there, so one captured graph serves every tile).
+template <class A>
+__device__ __forceinline__ uint64_t arg_seed(const A& a) {
+  return a.tp ? a.tp[0] : a.seed;
+}
+template <class A>
+__device__ __forceinline__ uint64_t arg_first(const A& a) {
+  return a.tp ? a.tp[1] : a.first;
+}
+
 // ---------------------------------------------------------------- compile-time trig
 // cos / sin of 2 pi m / R in double, by Taylor series after reduction to
 // (-pi, pi]; used only for in-register DFT constants.

@@ -133,7 +133,7 @@ __device__ __forceinline__ void probe_column(const Cart1dArgs& a, int k, bool ac
       a.r[base + y] = rv;
       a.p[base + y] = pv[m];
     } else if constexpr (MODE == C1_FIRST_PROBE) {
-      pv[m] = draw_probe(a.seed, a.first + k, (uint32_t)(y * a.nx + col), 0u, a.dist);
+      pv[m] = draw_probe(arg_seed(a), arg_first(a) + k, (uint32_t)(y * a.nx + col), 0u, a.dist);
       rv = pv[m];
       a.r[base + y] = rv;
       a.p[base + y] = rv;

@@ -128,8 +128,8 @@ hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse,
 // centred orthonormal DFT is (-1)^((ny+nx)/2) D F D / sqrt(ny nx).
 __global__ void k_kspace_in(const float2* __restrict__ src, const double* __restrict__ linv,
                             const uint8_t* __restrict__ mask, float2* __restrict__ out, int B, int nc,
-                            int ny, int nx, uint64_t seed, uint64_t first, uint32_t stream, int dist,
-                            float scale) {
+                            int ny, int nx, uint64_t seed, uint64_t first, const uint64_t* __restrict__ tp,
+                            uint32_t stream, int dist, float scale) {
   const long n = (long)ny * nx;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
@@ -151,7 +151,8 @@ __global__ void k_kspace_in(const float2* __restrict__ src, const double* __rest
         }
         v = make_float2((float)re, (float)im);
       } else {
-        v = draw_probe(seed, first + b, (uint32_t)((size_t)c * n + i), stream, dist);
+        v = tp ? draw_probe(tp[0], tp[1] + b, (uint32_t)((size_t)c * n + i), stream, dist)
+               : draw_probe(seed, first + b, (uint32_t)((size_t)c * n + i), stream, dist);
       }
     }
     out[((size_t)b * nc + c) * n + i] = cscale(v, sg);
@@ -160,11 +161,11 @@ __global__ void k_kspace_in(const float2* __restrict__ src, const double* __rest
 
 hipError_t launch_kspace_in(const float2* src, const double* linv, const uint8_t* mask, float2* out,
                             int B, int nc, int ny, int nx, uint64_t seed, uint64_t first,
-                            uint32_t stream, int dist, float scale, hipStream_t s) {
+                            const uint64_t* tp, uint32_t stream, int dist, float scale, hipStream_t s) {
   const long n = (long)ny * nx;
   dim3 grid((unsigned)((n + 255) / 256), B), block(256);
   hipLaunchKernelGGL(k_kspace_in, grid, block, 0, s, src, linv, mask, out, B, nc, ny, nx, seed,
-                     first, stream, dist, scale);
+                     first, tp, stream, dist, scale);
   return hipGetLastError();
 }
 
@@ -199,7 +200,7 @@ __global__ void k_accum_rowmajor(AccumArgs a) {
       si += (double)u.y;
       ss += (double)u.x * u.x + (double)u.y * u.y;
     } else {
-      const float2 v = draw_probe(a.seed, a.first + k, (uint32_t)i, 0u, a.dist);
+      const float2 v = draw_probe(arg_seed(a), arg_first(a) + k, (uint32_t)i, 0u, a.dist);
       const double re = (double)v.x * u.x + (double)v.y * u.y;
       const double im = (double)v.x * u.y - (double)v.y * u.x;
       s += re;

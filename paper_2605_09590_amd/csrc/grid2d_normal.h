@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
     const size_t i = rowoff + (ok ? xx : 0);   // in-bounds address for every lane
     float2 val = make_float2(0.f, 0.f);
     if constexpr (MODE == C1_FIRST_PROBE) {
-      val = draw_probe(a.seed, a.first + k, (uint32_t)(y * a.nx + xx), 0u, a.dist);
+      val = draw_probe(arg_seed(a), arg_first(a) + k, (uint32_t)(y * a.nx + xx), 0u, a.dist);
       if (!ok) val = make_float2(0.f, 0.f);
       if (active && ok) { R[i] = val; P[i] = val; }
       d0 += (double)val.x * val.x + (double)val.y * val.y;

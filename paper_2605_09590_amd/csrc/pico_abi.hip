@@ -148,6 +148,20 @@ struct pico_op_s {
   pico::DeviceArena* arena = nullptr;
   std::vector<Alloc> allocs;
   size_t bytes = 0, peak = 0;
+  // probe tiles replayed from HIP graphs (desc.graph): one captured kernel
+  // sequence per (tile size, probe family, accumulator buffers); (seed, first)
+  // of the replayed tile in tile_par
+  struct TileGraph {
+    int K, dist;
+    const double *sum, *sum_im, *sumsq;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  bool use_graph = false;
+  uint64_t* tile_par = nullptr;   // device [2]
+  hipStream_t cap_stream = nullptr;
+  std::vector<TileGraph> graphs;
+  uint64_t graph_clock = 0;
   // optional per-kernel-class timing with HIP events on the caller's stream
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
@@ -155,6 +169,8 @@ struct pico_op_s {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_recs;
 
   ~pico_op_s() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (auto& a : allocs) free_raw(a);
   }
@@ -275,6 +291,7 @@ hipError_t timed(pico_op_t op, int kind, hipStream_t s, F&& launch) {
 // One application of the normal operator to K probes.
 struct NormalCall {
   uint64_t seed = 0, first = 0;
+  const uint64_t* tp = nullptr;   // graph replay: (seed, first) in device memory
   int dist = 0;
   const float2* src = nullptr;  // C1_APPLY input
   float2* dst = nullptr;        // C1_APPLY output (default q)
@@ -307,6 +324,7 @@ hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hip
     a.scale = c.scale;
     a.seed = c.seed;
     a.first = c.first;
+    a.tp = c.tp;
     a.dist = c.dist;
     if (op->use_gram && mode != pico::C1_PMR_RHS) return pico::launch_cart1d_gram(mode, a, op->gram, s);
     if (op->use_gram16 && mode != pico::C1_PMR_RHS)
@@ -340,6 +358,7 @@ hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hip
   g.scale = c.scale;
   g.seed = c.seed;
   g.first = c.first;
+  g.tp = c.tp;
   g.dist = c.dist;
   return pico::launch_grid_normal(mode, g, s);
 }
@@ -365,10 +384,11 @@ hipError_t scalars(pico_op_t op, int K, bool first, hipStream_t s) {
 // first normal-operator application uses ``first_mode`` (probe draw or the
 // right-hand side already in r); the solution ends in op->x.
 hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t first, int dist,
-                    hipStream_t s) {
+                    hipStream_t s, const uint64_t* tp = nullptr) {
   NormalCall c;
   c.seed = seed;
   c.first = first;
+  c.tp = tp;
   c.dist = dist;
   c.lam = (float)op->lam_abs;
   hipError_t e = timed(op, PICO_PROF_NORMAL_FIRST, s, [&] { return launch_normal(op, K, first_mode, c, s); });
@@ -392,8 +412,8 @@ hipError_t cg_solve(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t
 // u = Sigma v for the K right-hand sides (probes drawn in-kernel or already
 // in r): one solve for lam = 0, else solve, M, solve (Sec. 2.1, Eq. (8)).
 hipError_t apply_sigma(pico_op_t op, int K, int first_mode, uint64_t seed, uint64_t first, int dist,
-                       hipStream_t s) {
-  hipError_t e = cg_solve(op, K, first_mode, seed, first, dist, s);
+                       hipStream_t s, const uint64_t* tp = nullptr) {
+  hipError_t e = cg_solve(op, K, first_mode, seed, first, dist, s, tp);
   if (e != hipSuccess || op->lam_abs == 0.0) return e;
   NormalCall c;
   c.src = op->x;
@@ -404,7 +424,7 @@ hipError_t apply_sigma(pico_op_t op, int K, int first_mode, uint64_t seed, uint6
 }
 
 hipError_t accumulate(pico_op_t op, int K, const pico_accum_t* acc, uint64_t seed, uint64_t first,
-                      int dist, int pmr, hipStream_t s) {
+                      int dist, int pmr, hipStream_t s, const uint64_t* tp = nullptr) {
   pico::AccumArgs aa{};
   aa.ny = op->ny;
   aa.nx = op->nx;
@@ -415,6 +435,7 @@ hipError_t accumulate(pico_op_t op, int K, const pico_accum_t* acc, uint64_t see
   aa.sumsq = acc->sumsq;
   aa.seed = seed;
   aa.first = first;
+  aa.tp = tp;
   aa.dist = dist;
   aa.pmr = pmr;
   return timed(op, PICO_PROF_ACCUM, s, [&] {
@@ -496,9 +517,10 @@ float kspace_scale(pico_op_t op) {
 // out[K][ny][nx] = A^H of K k-space arrays (Cartesian 2-D grid operator): the
 // arrays come from src (whitened with linv when given) or Philox draws
 hipError_t adjoint_kspace(pico_op_t op, int K, const float2* src, const double* linv, uint64_t seed,
-                          uint64_t first, uint32_t stream, int dist, float2* out, hipStream_t s) {
+                          uint64_t first, uint32_t stream, int dist, float2* out, hipStream_t s,
+                          const uint64_t* tp = nullptr) {
   hipError_t e = pico::launch_kspace_in(src, linv, op->mask_d, op->T, K, op->nc, op->ny, op->nx, seed,
-                                        first, stream, dist, kspace_scale(op), s);
+                                        first, tp, stream, dist, kspace_scale(op), s);
   if (e != hipSuccess) return e;
   if ((e = pico::launch_fft2d(op->T, (long)K * op->nc, op->ny, op->nx, true, op->twx, op->twy, s)) != hipSuccess) return e;
   return pico::launch_coil_combine(op->T, op->maps, out, K, op->nc, (long)op->image(), s);
@@ -550,12 +572,65 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
 
 // K tangents u = J w: probes drawn (src == nullptr: Philox stream 2) or given
 hipError_t cs_tangents(pico_op_t op, int K, const float2* w, uint64_t seed, uint64_t first, int dist,
-                       hipStream_t s) {
+                       hipStream_t s, const uint64_t* tp = nullptr) {
   hipError_t e = timed(op, PICO_PROF_NORMAL_FIRST, s, [&] {
-    return adjoint_kspace(op, K, w, nullptr, seed, first, 2u, dist, op->r, s);
+    return adjoint_kspace(op, K, w, nullptr, seed, first, 2u, dist, op->r, s, tp);
   });
   if (e != hipSuccess) return e;
   return fista_tangent(op, K, s);
+}
+
+// One probe tile of pico_noise_map: K probes from ``first`` through Sigma (or
+// J for CS) and the FP64 accumulation.  tp non-NULL: the kernels read
+// (seed, first) there instead (graph capture).
+hipError_t noise_tile(pico_op_t op, int K, const pico_accum_t* acc, uint64_t seed, uint64_t first, int dist,
+                      const uint64_t* tp, hipStream_t s) {
+  hipError_t e;
+  if (op->cs) {
+    if ((e = cs_tangents(op, K, nullptr, seed, first, dist, s, tp)) != hipSuccess) return e;
+    return timed(op, PICO_PROF_ACCUM, s, [&] {
+      return pico::launch_accum_abs2(op->x, acc->sum, acc->sum_im, acc->sumsq, K, (long)op->image(), s);
+    });
+  }
+  if ((e = apply_sigma(op, K, pico::C1_FIRST_PROBE, seed, first, dist, s, tp)) != hipSuccess) return e;
+  return accumulate(op, K, acc, seed, first, dist, 0, s, tp);
+}
+
+// The same tile replayed from a graph captured (on the operator's own stream,
+// which is never run) the first time this (K, dist, accumulator) is seen.
+hipError_t noise_tile_graph(pico_op_t op, int K, const pico_accum_t* acc, uint64_t seed, uint64_t first, int dist,
+                            hipStream_t s) {
+  pico_op_s::TileGraph* g = nullptr;
+  for (auto& t : op->graphs)
+    if (t.K == K && t.dist == dist && t.sum == acc->sum && t.sum_im == acc->sum_im && t.sumsq == acc->sumsq) g = &t;
+  hipError_t e;
+  if (!g) {
+    if (!op->cap_stream && (e = hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return e;
+    if ((e = hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    const hipError_t ec = noise_tile(op, K, acc, 0, 0, dist, op->tile_par, op->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(op->cap_stream, &graph);
+    if (ec != hipSuccess || ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ec != hipSuccess ? ec : ee;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (op->graphs.size() >= 8) {
+      auto lru = std::min_element(op->graphs.begin(), op->graphs.end(),
+                                  [](const auto& a, const auto& b) { return a.used < b.used; });
+      (void)hipGraphExecDestroy(lru->exec);
+      op->graphs.erase(lru);
+    }
+    op->graphs.push_back({K, dist, acc->sum, acc->sum_im, acc->sumsq, exec, 0});
+    g = &op->graphs.back();
+  }
+  g->used = ++op->graph_clock;
+  if ((e = pico::launch_set_tile(op->tile_par, seed, first, s)) != hipSuccess) return e;
+  return hipGraphLaunch(g->exec, s);
 }
 
 bool kb_grid_dims(const pico_op_desc_t* d, int G[2]);
@@ -685,6 +760,7 @@ pico_status_t validate(const pico_op_desc_t* d) {
   if (d->lambda > 0.0 && (d->power_iters < 1 || !(d->power_margin > 0.0)))
     return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
   if (d->normal_form < 0 || d->normal_form > 3) return fail(PICO_EINVAL, "normal_form must be 0, 1, 2 or 3");
+  if (d->graph != 0 && d->graph != 1) return fail(PICO_EINVAL, "graph must be 0 or 1");
   if (d->normal_form >= 2 && (d->sampling != PICO_CART_1D || !pico::gram_supported(d->ny)))
     return fail(PICO_EINVAL, "the dense normal form needs PICO_CART_1D and ny a multiple of 32 in 64..512");
   if (d->kb_width != 0) {
@@ -751,6 +827,7 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
   add(512 * 8);
   for (int i = 0; i < 4; ++i) add(K * 8);
   add(K * 4);
+  if (d->graph) add(2 * 8);
   const size_t linv = 2 * nc * nc * 8;
   add(linv);
   if (colmajor) {
@@ -899,6 +976,8 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
   if ((e = op->alloc(&op->rr, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&op->rr0, K)) != hipSuccess) return bad(e, "scalars");
   if ((e = op->alloc(&op->state, K)) != hipSuccess) return bad(e, "scalars");
+  op->use_graph = d->graph != 0;
+  if (op->use_graph && (e = op->alloc(&op->tile_par, 2)) != hipSuccess) return bad(e, "tile parameters");
   if ((e = op->alloc(&linv_d, linv.size())) != hipSuccess) return bad(e, "whitening");
   if ((e = hipMemcpyAsync(linv_d, linv.data(), linv.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
 
@@ -1121,14 +1200,15 @@ pico_status_t pico_noise_map(pico_op_t op, uint64_t seed, int64_t first_probe, i
   if (dist < 0 || dist > 3) return fail(PICO_EINVAL, "unknown probe family");
   hipStream_t s = (hipStream_t)stream;
   op->last_stream = s;
+  const bool graph = op->use_graph && !op->prof_on;
+  auto tile = [&](int K, uint64_t first) {
+    return graph ? noise_tile_graph(op, K, acc, seed, first, dist, s)
+                 : noise_tile(op, K, acc, seed, first, dist, nullptr, s);
+  };
   if (op->cs) {
     for (int64_t done = 0; done < nprobes;) {
       const int K = (int)std::min<int64_t>(op->K, nprobes - done);
-      const uint64_t first = (uint64_t)(first_probe + done);
-      HIP_OR_RETURN(cs_tangents(op, K, nullptr, seed, first, dist, s));
-      HIP_OR_RETURN(timed(op, PICO_PROF_ACCUM, s, [&] {
-        return pico::launch_accum_abs2(op->x, acc->sum, acc->sum_im, acc->sumsq, K, (long)op->image(), s);
-      }));
+      HIP_OR_RETURN(tile(K, (uint64_t)(first_probe + done)));
       done += K;
     }
     acc->count += nprobes;
@@ -1144,9 +1224,7 @@ pico_status_t pico_noise_map(pico_op_t op, uint64_t seed, int64_t first_probe, i
   StatAcc sa;
   for (int64_t done = 0; done < nprobes;) {
     const int K = (int)std::min<int64_t>(op->K, nprobes - done);
-    const uint64_t first = (uint64_t)(first_probe + done);
-    HIP_OR_RETURN(apply_sigma(op, K, pico::C1_FIRST_PROBE, seed, first, dist, s));
-    HIP_OR_RETURN(accumulate(op, K, acc, seed, first, dist, 0, s));
+    HIP_OR_RETURN(tile(K, (uint64_t)(first_probe + done)));
     if (stats) HIP_OR_RETURN(collect_stats(op, K, s, sa));
     done += K;
   }

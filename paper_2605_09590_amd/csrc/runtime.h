@@ -55,6 +55,7 @@ struct Cart1dArgs {
   float lam;                   // added to M p
   float scale;                 // C1_APPLY input scale
   uint64_t seed, first;        // probe / noise draw
+  const uint64_t* tp;          // non-NULL: (seed, first) read from device memory here
   int dist;                    // probe family
 };
 
@@ -86,6 +87,7 @@ struct AccumArgs {
   double* sum_im;              // may be null
   double* sumsq;               // may be null
   uint64_t seed, first;
+  const uint64_t* tp;          // non-NULL: (seed, first) read from device memory here
   int dist;
   int pmr;                     // 1: accumulate x itself (PMR); 0: conj(v) x (PICO)
 };
@@ -111,6 +113,7 @@ struct Grid2dArgs {
   double* part;                // [K][ny][4]
   float lam, scale;
   uint64_t seed, first;
+  const uint64_t* tp;          // non-NULL: (seed, first) read from device memory here
   int dist;
 };
 
@@ -136,7 +139,7 @@ hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse,
                         const float2* twy, hipStream_t s);
 hipError_t launch_kspace_in(const float2* src, const double* linv, const uint8_t* mask, float2* out,
                             int B, int nc, int ny, int nx, uint64_t seed, uint64_t first,
-                            uint32_t stream, int dist, float scale, hipStream_t s);
+                            const uint64_t* tp, uint32_t stream, int dist, float scale, hipStream_t s);
 hipError_t launch_coil_combine(const float2* T, const float2* maps, float2* out, int B, int nc,
                                long n, hipStream_t s);
 // CS tangents: analysis of the gradient point y - (q - g) * inv_s2 into dst
@@ -260,6 +263,8 @@ hipError_t build_gram16(const float2* maps, const float* maskw_h, int nc, int ny
                         double2* cvec_d, hipStream_t s);
 hipError_t launch_cart1d_gram16(int mode, const Cart1dArgs& a, const uint32_t* G16, const int* gexp, int* pexp,
                                 hipStream_t s);
+// device (seed, first) of the next replayed probe tile
+hipError_t launch_set_tile(uint64_t* tp, uint64_t seed, uint64_t first, hipStream_t s);
 hipError_t launch_final_x(const FinalArgs& a, hipStream_t s);
 hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);
 hipError_t launch_accum_colmajor(const AccumArgs& a, hipStream_t s);

@@ -193,13 +193,13 @@ def test_pmr_parity(lib, form):
     assert _rel(var.cpu().numpy(), opico.pmr_finalize(ref).ravel()) < TOL
 
 
-def test_full_size_config2_sampled_columns(lib):
+def test_full_size_config2_all_columns(lib):
     say("case: config-2 320x320 15 coils R=2+24 ACS, K=256 probes as one tile, CG 30, "
-        "dense (matrix-core) and FFT normal forms")
+        "dense (matrix-core) and FFT normal forms; every column against the converged oracle")
     prob = workloads.config(2, seed=0)
     n = prob.ny * prob.nx
     op = opico.cartesian(prob.maps, prob.psi, prob.mask)
-    cols = [0, 1, 97, 160, 255, 319]
+    cols = list(range(prob.nx))
     ref = opico.noise_map_exact_columns(op, prob.mask, 2024, 0, 256, cols)
     for form, name in ((2, "dense"), (3, "dense split-FP16"), (1, "FFT")):
         h = _init(lib, prob, 256, form=form)
@@ -210,8 +210,10 @@ def test_full_size_config2_sampled_columns(lib):
         assert st.frozen == 0 and acc.count == 256
         got = s.reshape(prob.ny, prob.nx)[:, cols]
         err = _rel(got, ref)
-        say(f"  {name}: sampled columns {cols}: rel err vs converged oracle {err:.2e}")
-        assert err < TOL
+        vox = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        say(f"  {name}: all {len(cols)} columns: rel err vs converged oracle {err:.2e}, "
+            f"max voxel error / max |ref| {vox:.2e}")
+        assert err < TOL and vox < 10 * TOL
 
 
 @pytest.mark.parametrize("form", [2, 3])

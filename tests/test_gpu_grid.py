@@ -172,5 +172,16 @@ def test_spiral_full_size_sampled_probes(lib):
     for k in (0, 137, 255):
         ref = cov.apply(v[k].astype(np.complex128))
         err = _rel(u[k], ref)
-        say(f"  probe {k}: rel err {err:.2e}")
-        assert err < TOL
+        vox = float(np.max(np.abs(u[k] - ref)) / np.max(np.abs(ref)))
+        say(f"  probe {k}: rel err {err:.2e}, max voxel error / max |ref| {vox:.2e}")
+        assert err < TOL and vox < 10 * TOL
+    # every right-hand side of the launch: Sigma = (M + l)^-1 M (M + l)^-1 is
+    # Hermitian with eigenvalues t / (t + l)^2 in [0, 1 / (4 l)], so
+    # 0 < Re <v, Sigma v> <= |v|^2 / (4 l) and Im <v, Sigma v> = 0 (to rounding)
+    q = np.einsum("kyx,kyx->k", np.conj(v.astype(np.complex128)), u.astype(np.complex128))
+    vv = np.sum(np.abs(v.astype(np.complex128)) ** 2, axis=(1, 2))
+    assert np.all(q.real > 0)
+    assert np.all(q.real <= vv / (4 * lam_abs) * (1 + 1e-4))
+    assert np.max(np.abs(q.imag) / q.real) < 1e-4
+    say(f"  all 256 probes: Re<v, u> / |v|^2 in [{(q.real / vv).min():.3e}, {(q.real / vv).max():.3e}] "
+        f"(bound {1 / (4 * lam_abs):.3e}), max |Im| / Re {np.max(np.abs(q.imag) / q.real):.1e}")
