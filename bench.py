@@ -86,33 +86,38 @@ def cs_kspace(torch, dev, prob, seed=0):
                             prob.extra["snr_db"], seed)
 
 
-def serve_requests(workloads, torch, np, dev, n_req, sizes, coils, probes, seed=0):
-    """Seeded request mix of the serving workload: kind Cartesian (phase-encode
-    R=2 + 24 ACS, CG 30) / spiral (48x4096 interleaves at R=2, lambda 0.1, CG 30) /
-    CS (Poisson-disc R=2 + 24x24 calibration, FISTA 100, lambda 1e-3, 4 db4
-    levels) with probabilities 0.4 / 0.4 / 0.2, matrix size from ``sizes``,
-    coils uniform in ``coils``, probes from ``probes``; device inputs resident."""
+def serve_pool(workloads, torch, np, dev, n_ops, sizes, coils, seed=0):
+    """Seeded pool of distinct operators (protocols) for the serving workload:
+    kind Cartesian (phase-encode R=2 + 24 ACS, CG 30) / spiral (48x4096
+    interleaves at R=2, lambda 0.1, CG 30) / CS (Poisson-disc R=2 + 24x24
+    calibration, FISTA 100, lambda 1e-3, 4 db4 levels) with probabilities
+    0.4 / 0.4 / 0.2, matrix size from ``sizes``, coils uniform in ``coils``;
+    the first operator is forced to the largest size and coil count, the second
+    to the smallest, so the pool spans the ranges.  probe_tile 0 (the server
+    takes the tuned tile), graph replay on; device inputs resident."""
     rng = np.random.default_rng(seed)
     cache = {}
     out = []
-    for i in range(n_req):
+    for i in range(n_ops):
         kind = ["cart", "spiral", "cs"][rng.choice(3, p=[0.4, 0.4, 0.2])]
         n = int(rng.choice(sizes))
         nc = int(rng.integers(coils[0], coils[1] + 1))
-        P = int(rng.choice(probes))
+        if i == 0:
+            kind, n, nc = "spiral", max(sizes), coils[1]
+        elif i == 1:
+            kind, n, nc = "cart", min(sizes), coils[0]
         r = np.random.default_rng(seed * 1000 + i)
         maps = workloads.coil_maps(n, n, nc, r)
         psi = workloads.noise_cov(nc, r)
-        kw = dict(ny=n, nx=n, maps=torch.from_numpy(maps.astype(np.complex64)).to(dev), psi=psi)
+        kw = dict(ny=n, nx=n, maps=torch.from_numpy(maps.astype(np.complex64)).to(dev), psi=psi,
+                  probe_tile=0, graph=1)
         if kind == "cart":
-            kw.update(mask=torch.from_numpy(workloads.cart_mask_1d(n, 2, 24)).to(dev), cg_iters=30,
-                      probe_tile=min(P, 256))
+            kw.update(mask=torch.from_numpy(workloads.cart_mask_1d(n, 2, 24)).to(dev), cg_iters=30)
         elif kind == "spiral":
             if ("traj", n) not in cache:
                 cache[("traj", n)] = torch.from_numpy(workloads.spiral_traj(n, 2).astype(np.float32)).to(dev)
             traj = cache[("traj", n)]
-            kw.update(mask=None, sampling=2, lam=0.1, cg_iters=30, probe_tile=min(P, 128), traj=traj,
-                      nsamples=traj.shape[0])
+            kw.update(mask=None, sampling=2, lam=0.1, cg_iters=30, traj=traj, nsamples=traj.shape[0])
         else:
             if ("pd", n) not in cache:
                 cache[("pd", n)] = workloads.poisson_disc_mask(n, n, 2.0, 24, seed=n)
@@ -120,19 +125,29 @@ def serve_requests(workloads, torch, np, dev, n_req, sizes, coils, probes, seed=
             x = workloads.phantom(n, r)
             kd = cs_kspace_arrays(torch, dev, maps, psi, mask, x, 45.0, seed=i)
             kw.update(mask=torch.from_numpy(mask).to(dev), sampling=1, recon=1, kdata=kd,
-                      fista_iters=100, cs_lambda=1e-3, wavelet_levels=4, probe_tile=min(P, 128))
-        out.append({"kind": kind, "n": n, "nc": nc, "probes": P, "kw": kw})
+                      fista_iters=100, cs_lambda=1e-3, wavelet_levels=4)
+        out.append({"kind": kind, "n": n, "nc": nc, "kw": kw})
     return out
 
 
-def serve_run(lib, torch, dev, reqs, budget, slots, depth, arrivals=None, seed=0):
-    """Submit every request (at the given arrival times in s, else all at once)
-    to a fresh server; returns (per-request info in submission order, accumulators)."""
+def serve_requests(np, pool, n_req, probes, seed=0):
+    """Requests: an operator of the pool (uniform), a probe count from ``probes``."""
+    rng = np.random.default_rng(seed + 7)
+    out = []
+    for i in range(n_req):
+        j = int(rng.integers(len(pool)))
+        out.append(dict(pool[j], op=j, probes=int(rng.choice(probes))))
+    return out
+
+
+def serve_run(lib, torch, dev, srv, reqs, arrivals=None, seed=0):
+    """Submit the requests to the server (at the given arrival times in s, else
+    one after the other, each waiting for the previous); returns (per-request
+    info in submission order, accumulators)."""
     import threading
     accs = [[torch.zeros(r["n"] * r["n"], dtype=torch.float64, device=dev) for _ in range(2)]
             for r in reqs]
     torch.cuda.synchronize()
-    srv = lib.Server(budget, slots, depth)
     ids = [None] * len(reqs)
     err = []
 
@@ -146,6 +161,8 @@ def serve_run(lib, torch, dev, reqs, budget, slots, depth, arrivals=None, seed=0
                         time.sleep(dt)
                 ids[i] = srv.submit(seed + i, 0, r["probes"], lib.make_accum(accs[i][0], None, accs[i][1]),
                                     **r["kw"])
+                if arrivals is None:
+                    srv.wait_idle(600.0)
         except Exception as e:     # reported by the caller
             err.append(e)
 
@@ -153,57 +170,110 @@ def serve_run(lib, torch, dev, reqs, budget, slots, depth, arrivals=None, seed=0
     th.start()
     th.join()
     if err:
-        srv.close()
         raise err[0]
     srv.wait_idle(600.0)
     done = {d["id"]: d for d in srv.poll(len(reqs) + 8)}
-    srv.close()
     torch.cuda.synchronize()
     return [done[i] for i in ids], accs
 
 
-def serve_leg(lib, workloads, torch, np, dev, full):
-    """p50 / p99 request latency of the serving loop under Poisson arrivals."""
-    if full:
-        sizes, coils, probes, n_req, rhos = [128, 160, 192, 256, 288, 320, 384], (8, 32), \
-            [64, 128, 256, 512], 200, [0.25, 0.5, 0.75, 0.9, 1.1]
-    else:
-        sizes, coils, probes, n_req, rhos = [128, 160, 192, 256], (8, 16), [64, 128, 256], 32, [0.5, 0.9]
-    budget, slots, depth = 64 << 30, 4, 2
-    reqs = serve_requests(workloads, torch, np, dev, n_req, sizes, coils, probes)
-    serve_run(lib, torch, dev, reqs[:3], budget, 1, depth)           # warm-up (first launches)
-    seq, ref = serve_run(lib, torch, dev, reqs, budget, 1, depth)
+def _lat_stats(np, info):
+    lat = np.array([d["t_done_ms"] - d["t_submit_ms"] for d in info])
+    if lat.size == 0:
+        return None
+    return {"n": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2)}
+
+
+def serve_leg(lib, workloads, torch, np, dev, n_req=24, rhos=(0.5, 0.9, 1.2), n_ops=10):
+    """Serving mix over the stated ranges (matrix 128-384, coils 8-32, probes
+    64-512; Cartesian / spiral / CS): a pool of distinct operators, tile shapes
+    from the autotuner, graph replay, resident operators.  Cold pass (every
+    operator built), warm sequential pass (capacity), then Poisson arrivals at
+    rho x capacity on the same server: p50 / p99 latency, cold and warm."""
+    import tempfile
+    sizes, coils, probes = [128, 160, 192, 256, 288, 320, 384], (8, 32), [64, 128, 256, 512]
+    budget, slots, depth = 96 << 30, 4, 2
+    pool = serve_pool(workloads, torch, np, dev, n_ops, sizes, coils)
+    tune_path = os.path.join(tempfile.mkdtemp(prefix="pico_tune_"), "tiles.txt")
+    t0 = time.perf_counter()
+    tuned = []
+    for op in pool:
+        d, keep = lib.make_desc(**dict(op["kw"], probe_tile=1))
+        t = lib.pico_autotune(d, 16 << 30, tune_path)
+        tuned.append({"kind": op["kind"], "n": op["n"], "coils": op["nc"], "probe_tile": t["probe_tile"],
+                      "normal_form": t["normal_form"], "graph": t["graph"],
+                      "probes_per_s": round(t["probes_per_s"], 1)})
+    tune_s = time.perf_counter() - t0
+    reqs = serve_requests(np, pool, n_req, probes)
+    srv = lib.Server(budget, slots, depth)
+    srv.set_tuning(tune_path)
+    cold_reqs = [dict(op, op=j, probes=64) for j, op in enumerate(pool)]
+    cold, _ = serve_run(lib, torch, dev, srv, cold_reqs, seed=500)
+    assert all(d["status"] == 0 for d in cold), [d["error"] for d in cold if d["status"]]
+    seq, ref = serve_run(lib, torch, dev, srv, reqs)
     assert all(d["status"] == 0 for d in seq), [d["error"] for d in seq if d["status"]]
     service = [d["t_done_ms"] - d["t_admit_ms"] for d in seq]
-    span_s = (max(d["t_done_ms"] for d in seq) - min(d["t_submit_ms"] for d in seq)) / 1e3
-    capacity = n_req / span_s
+    capacity = 1e3 / float(np.mean(service))
     rates = []
     for rho in rhos:
         lam = rho * capacity
         arr = np.cumsum(np.random.default_rng(int(rho * 1000)).exponential(1.0 / lam, n_req))
-        info, accs = serve_run(lib, torch, dev, reqs, budget, slots, depth, arrivals=arr)
+        info, accs = serve_run(lib, torch, dev, srv, reqs, arrivals=arr)
         assert all(d["status"] == 0 for d in info), [d["error"] for d in info if d["status"]]
-        lat = np.array([d["t_done_ms"] - d["t_submit_ms"] for d in info])
         wait = np.array([d["t_admit_ms"] - d["t_submit_ms"] for d in info])
         span = (max(d["t_done_ms"] for d in info) - min(d["t_submit_ms"] for d in info)) / 1e3
         same = all(torch.equal(a, b) for x, y in zip(accs, ref) for a, b in zip(x, y))
-        rates.append({"rho": rho, "arrival_rate_per_s": round(lam, 3),
-                      "p50_ms": round(float(np.percentile(lat, 50)), 2),
-                      "p99_ms": round(float(np.percentile(lat, 99)), 2),
-                      "mean_ms": round(float(lat.mean()), 2),
-                      "mean_queue_wait_ms": round(float(wait.mean()), 2),
-                      "makespan_s": round(span, 3),
+        rates.append({"rho": rho, "arrival_rate_per_s": round(lam, 3), **_lat_stats(np, info),
+                      "warm": _lat_stats(np, [d for d in info if d["op_reused"]]),
+                      "cold": _lat_stats(np, [d for d in info if not d["op_reused"]]),
+                      "mean_queue_wait_ms": round(float(wait.mean()), 2), "makespan_s": round(span, 3),
                       "probe_solves_per_s": round(sum(r["probes"] for r in reqs) / span, 1),
                       "results_identical_to_sequential": bool(same)})
+    cache = srv.cache_stats()
+    srv.close()
     kinds = {k: sum(r["kind"] == k for r in reqs) for k in ("cart", "spiral", "cs")}
     return {
-        "workload": f"{n_req} requests (kinds {kinds}), matrix {sizes}, coils U{{{coils[0]}..{coils[1]}}}, "
-                    f"probes {probes}; Poisson arrivals at rho x the sequential capacity; "
-                    f"budget {budget >> 30} GiB, {slots} slots, {depth} tiles in flight",
+        "workload": f"{n_req} requests per rate over a pool of {n_ops} operators (request kinds {kinds}), "
+                    f"matrix {sizes}, coils U{{{coils[0]}..{coils[1]}}}, probes {probes}; Poisson arrivals at "
+                    f"rho x the warm sequential capacity; budget {budget >> 30} GiB, {slots} slots, {depth} "
+                    "tiles in flight; autotuned tiles, graph replay, resident operators",
+        "pool": tuned, "autotune_s": round(tune_s, 2),
+        "cold_first_requests": _lat_stats(np, cold),
         "capacity_req_per_s": round(capacity, 3),
         "mean_service_ms": round(float(np.mean(service)), 2),
         "rates": rates,
+        "resident_cache": cache,
     }
+
+
+def graph_leg(lib, workloads, torch, np, dev, steps=10):
+    """ms per probe tile with graph replay against direct launches, on a
+    launch-bound serving-sized operator (128^2, 8 coils) and on the headline one."""
+    out = {}
+    for name, cfg in (("cart1d_128x128x8_K64_cg30", dict(i=2, ny=128, nx=128, nc=8, K=64)),
+                      ("cart1d_320x320x15_K256_cg30", dict(i=2, ny=320, nx=320, nc=15, K=256))):
+        pr = workloads.config(cfg["i"], seed=0, ny=cfg["ny"], nx=cfg["nx"], nc=cfg["nc"])
+        maps = torch.from_numpy(pr.maps.astype(np.complex64)).to(dev)
+        mask = torch.from_numpy(pr.mask).to(dev)
+        res = {}
+        for g in (0, 1):
+            h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, cg_iters=30, probe_tile=cfg["K"], graph=g)
+            at = [torch.zeros(pr.ny * pr.nx, dtype=torch.float64, device=dev) for _ in range(2)]
+            acc = lib.make_accum(at[0], None, at[1])
+            lib.pico_noise_map(h, 3, 0, cfg["K"], 0, acc)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(steps):
+                lib.pico_noise_map(h, 3, (i + 1) * cfg["K"], cfg["K"], 0, acc)
+            e1.record()
+            torch.cuda.synchronize()
+            res["graph" if g else "direct"] = round(e0.elapsed_time(e1) / steps, 4)
+            lib.pico_destroy(h)
+        res["speedup"] = round(res["direct"] / res["graph"], 4)
+        out[name] = {"ms_per_tile": res}
+    return out
 
 
 def plain_leg(torch, np, dev, prob, ref, max_probes=1024, check=None):
@@ -784,7 +854,7 @@ def main():
     ap.add_argument("--cs-tv-steps", type=int, default=1,
                     help="steps of the TV compressed-sensing JVP leg (0 to skip)")
     ap.add_argument("--serve", choices=["off", "short", "full"], default="short",
-                    help="serving leg: short request mix (default), the full sweep, or off")
+                    help="serving leg: 24 requests at 3 rates (default), 100 at 6 rates, or off")
     ap.add_argument("--cs-robustness", choices=["off", "l1wav", "tv"], default="off",
                     help="also run the CS noise-level sweep (PICO vs PMR std maps) for that model")
     ap.add_argument("--no-dense", dest="dense", action="store_false",
@@ -1011,7 +1081,9 @@ def main():
     # --- serving: mixed requests under Poisson arrivals, p50 / p99 latency
     serving = None
     if args.serve != "off":
-        serving = serve_leg(lib, workloads, torch, np, dev, args.serve == "full")
+        serving = serve_leg(lib, workloads, torch, np, dev, **({"n_req": 100, "rhos": (0.25, 0.5, 0.75, 0.9, 1.1, 1.3)}
+                                                                 if args.serve == "full" else {}))
+    graphs = graph_leg(lib, workloads, torch, np, dev)
 
     # --- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
@@ -1053,6 +1125,7 @@ def main():
         "cs_tv": cs_tv,
         "cs_tv_bf16": cs_tv_bf16,
         "serving": serving,
+        "graph_vs_direct": graphs,
     }
     if robust is not None:
         res["cs_robustness"] = robust

@@ -388,6 +388,32 @@ pico_status_t pico_pmr_cs(pico_op_t op, uint64_t seed, int64_t first, int64_t nr
 pico_status_t pico_apply_nufft(pico_op_t op, int32_t adjoint, const void* in, void* out, int32_t k,
                                void* stream);
 
+/* Tile-shape autotuner.  For the operator description desc (its device
+ * arrays must be valid), times short noise-map runs (a warm-up tile, then at
+ * least 2 tiles and 20 ms) of the candidates: probe_tile doubling from 16 to
+ * 512 while its peak device bytes (pico_estimate_bytes) fit in max_bytes (0:
+ * no limit) and the rate still grows by 3 % or more, for each phase-encode
+ * normal form (column FFTs, dense FP32 blocks, split-FP16 blocks) of a
+ * PICO_CART_1D CG-SENSE operator, with graph replay; then direct launches at
+ * the fastest shape.  The fastest choice goes
+ * to *out and, when cache_path is non-NULL, into that text file under a key
+ * of the problem's shape (sampling, reconstruction, ny x nx, coils in buckets
+ * of 8, CG iterations, Tikhonov or not, storage, FISTA / TV / wavelet
+ * parameters, non-Cartesian samples in buckets of 4096).  A key already in the
+ * file is returned without timing (out->from_cache = 1).  Every candidate
+ * initialises its own operator (device memory from the allocator in effect);
+ * synchronous on stream.  Errors: as pico_init; PICO_ENOMEM when no candidate
+ * fits; PICO_EINVAL when the cache file cannot be written. */
+typedef struct {
+  int32_t probe_tile;           /* right-hand sides per batched solve / tangent batch */
+  int32_t normal_form;          /* pico_op_desc_t.normal_form to use               */
+  int32_t graph;                /* pico_op_desc_t.graph to use                     */
+  double probes_per_s;          /* measured rate of the choice                     */
+  int32_t from_cache;           /* 1: read from the cache file, not timed now      */
+} pico_tune_t;
+pico_status_t pico_autotune(const pico_op_desc_t* desc, uint64_t max_bytes, const char* cache_path, void* stream,
+                            pico_tune_t* out);
+
 /* Release the operator and its device memory (waits for its last stream). */
 void pico_destroy(pico_op_t op);
 
@@ -410,10 +436,16 @@ pico_status_t pico_op_bytes(pico_op_t op, uint64_t* resident, uint64_t* peak);
  * down to 256) and starts a worker thread.  Every operator the server builds
  * lives in that allocation, so serving makes no further hipMalloc / hipFree.
  * A request is admitted in arrival order when one of max_slots slots is free
- * and its peak bytes (pico_estimate_bytes) fit beside the resident bytes of
- * the admitted requests; admitted requests each have their own stream and up
- * to tiles_in_flight probe tiles (desc->probe_tile probes each) enqueued.  A
- * finished request frees its operator and slot immediately.
+ * and either an idle resident operator has its key or its peak bytes
+ * (pico_estimate_bytes) fit beside the resident operators (idle ones are
+ * evicted, least recently used first, to make room); admitted requests each
+ * have their own stream and up to tiles_in_flight probe tiles
+ * (desc->probe_tile probes each) enqueued.  A finished request frees its slot
+ * immediately; its operator stays resident, keyed by the content of the
+ * description (scalar fields, psi, and a hash of the maps, mask, trajectory
+ * and k-space data read on the device at admission), and a later request with
+ * the same key runs on it without pico_init.  desc->probe_tile = 0 asks for
+ * the tile shape of pico_server_set_tuning.
  *
  * A request adds probes [first_probe, first_probe + nprobes) into *acc
  * exactly as pico_noise_map(op, seed, first_probe, nprobes, dist, acc) on a
@@ -439,6 +471,8 @@ typedef struct {
   int64_t first_probe, probes;
   double t_submit_ms, t_admit_ms, t_done_ms;
   uint64_t bytes_peak, bytes_resident;   /* estimate at submission             */
+  int32_t probe_tile;           /* tile the request ran with                    */
+  int32_t op_reused;            /* 1: served on a resident operator (no init)   */
   char error[160];              /* message when status != PICO_OK               */
 } pico_request_info_t;
 
@@ -455,6 +489,16 @@ pico_status_t pico_server_wait_idle(pico_server_t srv, double timeout_s);
 /* Budget, bytes handed out by the arena, queued and admitted request counts. */
 pico_status_t pico_server_usage(pico_server_t srv, uint64_t* budget, uint64_t* arena_used,
                                 int32_t* queued, int32_t* active);
+/* Tile shapes for requests submitted with probe_tile = 0: read from the
+ * autotuner's cache file at cache_path (pico_autotune; NULL or "" = none).
+ * A request whose key is not in the file gets a power-of-two tile in 16..256
+ * of about 2^23 voxels, and graph replay.  Errors: PICO_EINVAL (NULL server). */
+pico_status_t pico_server_set_tuning(pico_server_t srv, const char* cache_path);
+/* Resident operators kept between requests (busy or idle), their device
+ * bytes, and how many admissions found an idle operator with the request's
+ * key (hits) or built one (misses).  Any pointer may be NULL. */
+pico_status_t pico_server_cache_stats(pico_server_t srv, int32_t* resident_ops, uint64_t* resident_bytes,
+                                      int64_t* hits, int64_t* misses);
 /* Serves everything already submitted, then stops the worker and frees the budget. */
 void pico_server_destroy(pico_server_t srv);
 

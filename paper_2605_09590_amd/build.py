@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpico.so")
 SOURCES = ["cart1d.hip", "cart1d_bf16.hip", "gram.hip", "grid2d.hip", "grid2d_bf16.hip", "toeplitz.hip", "kb.hip",
-           "cs.hip", "tv.hip", "cg.hip", "reduced.hip", "pico_abi.hip", "serve.hip"]
+           "cs.hip", "tv.hip", "cg.hip", "reduced.hip", "pico_abi.hip", "serve.hip", "tune.hip"]
 
 # Packed FP32 instructions stay off: the build relies on scalar / float2 code
 # only, and the compiler must not fuse it into v_pk_* forms.

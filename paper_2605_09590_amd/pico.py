@@ -68,7 +68,13 @@ class pico_request_info_t(ctypes.Structure):
                 ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
                 ("t_done_ms", ctypes.c_double),
                 ("bytes_peak", ctypes.c_uint64), ("bytes_resident", ctypes.c_uint64),
+                ("probe_tile", ctypes.c_int32), ("op_reused", ctypes.c_int32),
                 ("error", ctypes.c_char * 160)]
+
+
+class pico_tune_t(ctypes.Structure):
+    _fields_ = [("probe_tile", ctypes.c_int32), ("normal_form", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("probes_per_s", ctypes.c_double), ("from_cache", ctypes.c_int32)]
 
 
 class PicoError(RuntimeError):
@@ -89,7 +95,8 @@ EXPORTS = ["pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", 
            "pico_profile_start", "pico_profile_stop", "pico_lambda_abs", "pico_destroy",
            "pico_last_error", "pico_estimate_bytes", "pico_op_bytes", "pico_server_create",
            "pico_server_submit", "pico_server_poll", "pico_server_wait_idle", "pico_server_usage",
-           "pico_server_destroy", "pico_set_allocator", "pico_pmr_cs_noalloc"]
+           "pico_server_destroy", "pico_set_allocator", "pico_pmr_cs_noalloc", "pico_autotune",
+           "pico_server_set_tuning", "pico_server_cache_stats"]
 PROF_KINDS = 8
 PROF_NAMES = ["normal_first", "normal_iter", "cg_update", "cg_scalars", "accumulate", "other"]
 
@@ -149,12 +156,18 @@ def load(path: str = LIB_PATH):
     lib.pico_server_destroy.argtypes = [vp]
     lib.pico_server_destroy.restype = None
     lib.pico_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+    lib.pico_autotune.argtypes = [ctypes.POINTER(pico_op_desc_t), u64, ctypes.c_char_p, vp,
+                                  ctypes.POINTER(pico_tune_t)]
+    lib.pico_server_set_tuning.argtypes = [vp, ctypes.c_char_p]
+    lib.pico_server_cache_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(u64), ctypes.POINTER(i64),
+                                            ctypes.POINTER(i64)]
     for name in ("pico_init", "pico_apply_cov", "pico_apply_jvp", "pico_apply_nufft", "pico_recon", "pico_noise_map", "pico_finalize",
                  "pico_pmr_baseline", "pico_pmr_finalize", "pico_pmr_cs", "pico_pmr_cs_noalloc",
                  "pico_monitor_nrmse", "pico_exact_diag", "pico_profile_start", "pico_profile_stop",
                  "pico_monitor_stderr", "pico_noise_map_adaptive",
                  "pico_estimate_bytes", "pico_op_bytes", "pico_server_create", "pico_server_submit",
-                 "pico_server_poll", "pico_server_wait_idle", "pico_server_usage", "pico_set_allocator"):
+                 "pico_server_poll", "pico_server_wait_idle", "pico_server_usage", "pico_set_allocator",
+                 "pico_autotune", "pico_server_set_tuning", "pico_server_cache_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -431,6 +444,7 @@ def pico_server_poll(srv, max_n=256):
                     "probes": r.probes, "t_submit_ms": r.t_submit_ms,
                     "t_admit_ms": r.t_admit_ms, "t_done_ms": r.t_done_ms,
                     "bytes_peak": r.bytes_peak, "bytes_resident": r.bytes_resident,
+                    "probe_tile": r.probe_tile, "op_reused": r.op_reused,
                     "error": r.error.decode(errors="replace")})
     return out
 
@@ -445,6 +459,26 @@ def pico_server_usage(srv):
     _check(load().pico_server_usage(srv, ctypes.byref(b), ctypes.byref(u), ctypes.byref(q),
                                     ctypes.byref(a)))
     return {"budget": b.value, "arena_used": u.value, "queued": q.value, "active": a.value}
+
+
+def pico_autotune(desc, max_bytes=0, cache_path=None, stream=None):
+    """pico_autotune: returns dict(probe_tile, normal_form, graph, probes_per_s, from_cache)."""
+    t = pico_tune_t()
+    _check(load().pico_autotune(ctypes.byref(desc), int(max_bytes),
+                                None if cache_path is None else os.fsencode(cache_path), _stream(stream),
+                                ctypes.byref(t)))
+    return {"probe_tile": t.probe_tile, "normal_form": t.normal_form, "graph": t.graph,
+            "probes_per_s": t.probes_per_s, "from_cache": bool(t.from_cache)}
+
+
+def pico_server_set_tuning(srv, cache_path):
+    return _check(load().pico_server_set_tuning(srv, None if cache_path is None else os.fsencode(cache_path)))
+
+
+def pico_server_cache_stats(srv):
+    n, b, h, m = ctypes.c_int32(), ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().pico_server_cache_stats(srv, ctypes.byref(n), ctypes.byref(b), ctypes.byref(h), ctypes.byref(m)))
+    return {"resident_ops": n.value, "resident_bytes": b.value, "hits": h.value, "misses": m.value}
 
 
 def pico_server_destroy(srv) -> None:
@@ -477,6 +511,12 @@ class Server:
 
     def usage(self):
         return pico_server_usage(self.h)
+
+    def set_tuning(self, cache_path):
+        return pico_server_set_tuning(self.h, cache_path)
+
+    def cache_stats(self):
+        return pico_server_cache_stats(self.h)
 
     def close(self):
         if self.h:

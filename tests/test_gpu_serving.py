@@ -176,3 +176,93 @@ def test_served_request_matches_oracle(lib):
     e = float(np.linalg.norm(got - ref["sum"].ravel()) / np.linalg.norm(ref["sum"]))
     say(f"  rel err {e:.2e}")
     assert e < 1e-4
+
+
+def _serve_seq(lib, srv, reqs, seed=17):
+    """Submit requests one after the other (each waits for the previous)."""
+    accs, info = [], []
+    for name, kw, nprobes in reqs:
+        t = _acc(kw["ny"] * kw["nx"])
+        torch.cuda.synchronize()
+        rid = srv.submit(seed, 0, nprobes, lib.make_accum(*t), **kw)
+        srv.wait_idle(120.0)
+        info += [r for r in srv.poll() if r["id"] == rid]
+        accs.append(t)
+    torch.cuda.synchronize()
+    return accs, info
+
+
+def test_resident_operators_are_reused_by_content(lib):
+    reqs = _requests()
+    name, kw, n = reqs[0]
+    kw = dict(kw, graph=1)
+    say(f"case: {name} served 3 times on one resident operator, then with changed map contents")
+    srv = lib.Server(4 << 30, 2, 2)
+    accs, info = _serve_seq(lib, srv, [(name, kw, n)] * 3)
+    assert [r["op_reused"] for r in info] == [0, 1, 1]
+    st = srv.cache_stats()
+    assert st["hits"] == 2 and st["misses"] == 1 and st["resident_ops"] == 1
+    d, _ = _direct(lib, kw, 17, n)
+    for a in accs:
+        for x, y in zip(d, a):
+            assert torch.equal(x, y)
+    # same device pointer, different contents: a different key, a new operator
+    kw["maps"].mul_(1.25)
+    torch.cuda.synchronize()
+    accs2, info2 = _serve_seq(lib, srv, [(name, kw, n)])
+    assert info2[0]["op_reused"] == 0 and srv.cache_stats()["resident_ops"] == 2
+    d2, _ = _direct(lib, kw, 17, n)
+    for x, y in zip(d2, accs2[0]):
+        assert torch.equal(x, y)
+    assert not torch.equal(d2[0], d[0])
+    kw["maps"].div_(1.25)
+    srv.close()
+
+
+def test_idle_operators_are_evicted_for_room(lib):
+    reqs = _requests()[:3]
+    peaks = []
+    for _, kw, _ in reqs:
+        d, keep = lib.make_desc(**kw)
+        peaks.append(lib.pico_estimate_bytes(d)[1])
+    budget = int(max(peaks) * 1.05)
+    say(f"case: 3 kinds in a budget of 1.05 x the largest peak ({budget} B), served in turn twice")
+    srv = lib.Server(budget, 1, 2)
+    accs, info = _serve_seq(lib, srv, reqs + reqs)
+    assert all(r["status"] == 0 for r in info)
+    st = srv.cache_stats()
+    assert st["resident_ops"] >= 1 and st["resident_bytes"] <= budget
+    srv.close()
+    for (name, kw, n), a in zip(reqs + reqs, accs):
+        d, _ = _direct(lib, kw, 17, n)
+        for x, y in zip(d, a):
+            assert torch.equal(x, y), name
+
+
+def test_autotune_and_auto_tile_requests(lib, tmp_path):
+    rng = np.random.default_rng(41)
+    maps = workloads.coil_maps(64, 64, 4, rng)
+    psi = workloads.noise_cov(4, rng)
+    kw = dict(ny=64, nx=64, maps=_dev(maps.astype(np.complex64)), psi=psi,
+              mask=_dev(workloads.cart_mask_1d(64, 2, 8)), cg_iters=20, probe_tile=0)
+    cache = str(tmp_path / "tune.txt")
+    say("case: autotune a 64x64 4-coil phase-encode operator (tiles 16..512, three normal forms, graph "
+        "or not), then a served request with probe_tile 0 takes the cached shape")
+    d, keep = lib.make_desc(**dict(kw, probe_tile=1))
+    t1 = lib.pico_autotune(d, 1 << 30, cache)
+    say(f"  tuned: {t1}")
+    assert not t1["from_cache"] and t1["probe_tile"] in (16, 32, 64, 128, 256, 512)
+    assert t1["normal_form"] in (1, 2, 3) and t1["probes_per_s"] > 0
+    t2 = lib.pico_autotune(d, 1 << 30, cache)
+    assert t2["from_cache"] and t2["probe_tile"] == t1["probe_tile"]
+    srv = lib.Server(2 << 30, 2, 2)
+    accs, info = _serve_seq(lib, srv, [("auto, untuned", kw, 40)])
+    assert info[0]["probe_tile"] == 64 and info[0]["status"] == 0     # size rule: 256 at 64^2, cut to < 2 x 40 probes
+    srv.set_tuning(cache)
+    accs, info = _serve_seq(lib, srv, [("auto, tuned", kw, 40)])
+    assert info[0]["probe_tile"] == t1["probe_tile"] and info[0]["status"] == 0
+    srv.close()
+    dk = dict(kw, probe_tile=t1["probe_tile"], normal_form=t1["normal_form"], graph=t1["graph"])
+    ref, _ = _direct(lib, dk, 17, 40)
+    for x, y in zip(ref, accs[0]):
+        assert torch.equal(x, y)
