@@ -126,7 +126,7 @@ typedef struct {
    * Grid oversamp * n per axis (an integer with a built FFT length), kernel
    * I0(beta sqrt(1 - (2u/W)^2)), beta = pi sqrt((W/oversamp)^2 (oversamp -
    * 1/2)^2 - 0.8), W = kb_width even in 2..8.  The normal operator of the
-   * CG solves is the exact Toeplitz form either way. */
+   * CG solves is the exact Toeplitz form unless noncart_normal = 1. */
   double oversamp;              /* e.g. 2.0 (or 1.25)                             */
   int32_t kb_width;             /* e.g. 6 (or 4); 0 = no gridding data path       */
   /* Form of the normal operator for PICO_CART_1D (M is block diagonal over
@@ -162,6 +162,13 @@ typedef struct {
    * operator are kept (least recently used evicted).  Not used while kernel
    * profiling is on (pico_profile_start).  0: direct launches. */
   int32_t graph;
+  /* PICO_NONCART: normal operator of the CG solves.  0: the exact Toeplitz
+   * form (point-spread function by the direct NUDFT).  1: the gridding form
+   * M = sum_c S_c^H A_c^H A_c S_c with the Kaiser-Bessel A_c of oversamp /
+   * kb_width (kb_width > 0, oversamp * n a multiple of 16): per coil and
+   * probe, grid FFT, interpolation and spread fused per 16 x 16 grid tile
+   * (samples sorted into tile bins once), inverse grid FFT; deterministic. */
+  int32_t noncart_normal;
 } pico_op_desc_t;
 
 /* Caller-owned device float64 accumulators, each [ny*nx] row-major, and a

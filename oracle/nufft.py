@@ -91,12 +91,18 @@ class NonCartOp:
     """Whitened non-Cartesian SENSE operator.
 
     ``normal`` uses the Toeplitz embedding, which equals the NUDFT's A^H A
-    exactly.  ``forward`` / ``adjoint`` (the data path: reconstruction of
-    k-space data and PMR replicas) are the direct NUDFT, or the Kaiser-Bessel
-    gridding NUFFT of oracle/kbnufft.py when ``kb = (sigma, W)`` is given.
+    exactly, or, with ``normal_mode="gridding"``, the normal operator of the
+    gridding NUFFT itself, sum_c S_c^H A_grid^H A_grid S_c (its plain
+    definition: forward, then adjoint, per coil).  ``forward`` / ``adjoint``
+    (the data path: reconstruction of k-space data and PMR replicas) are the
+    direct NUDFT, or the Kaiser-Bessel gridding NUFFT of oracle/kbnufft.py when
+    ``kb = (sigma, W)`` is given.
     """
 
-    def __init__(self, maps, psi, traj, kb=None):
+    def __init__(self, maps, psi, traj, kb=None, normal_mode="toeplitz"):
+        if normal_mode not in ("toeplitz", "gridding") or (normal_mode == "gridding" and kb is None):
+            raise ValueError("normal_mode is 'toeplitz', or 'gridding' with kb = (sigma, W)")
+        self.normal_mode = normal_mode
         self.Sw = whiten_maps(maps, psi)
         self.nc, self.ny, self.nx = self.Sw.shape
         self.traj = np.asarray(traj, np.float64)
@@ -128,8 +134,16 @@ class NonCartOp:
         return np.fft.ifft2(self.Kh * np.fft.fft2(pad))[:ny, :nx]
 
     def normal(self, x):
-        """M x = sum_c conj(S_c) psf * (S_c x)."""
+        """M x = sum_c conj(S_c) psf * (S_c x) (Toeplitz), or
+        sum_c conj(S_c) A_grid^H A_grid (S_c x) (gridding)."""
+        if self.normal_mode == "gridding":
+            return self.normal_gridding(x)
         return sum(np.conj(self.Sw[c]) * self.conv(self.Sw[c] * x) for c in range(self.nc))
+
+    def normal_gridding(self, x):
+        """M_grid x = sum_c conj(S_c) A_grid^H A_grid (S_c x), with the gridding NUFFT."""
+        return sum(np.conj(self.Sw[c]) * self.kb.adjoint(self.kb.forward(self.Sw[c] * x))
+                   for c in range(self.nc))
 
     def normal_nudft(self, x):
         """M x through the NUDFT forward and adjoint (slow; for checks)."""

@@ -1,6 +1,6 @@
-// Kaiser-Bessel gridding NUFFT for non-Cartesian operators: the data path
-// (A x and A^H y per coil; PMR replicas) of the spiral reconstruction
-// (Sec. 3.2.2, 3.3).  The normal operator stays the exact Toeplitz form.
+// Kaiser-Bessel gridding NUFFT for non-Cartesian operators (Sec. 3.2.2, 3.3):
+// the data path (A x and A^H y per coil; PMR replicas) and, on request, the
+// gridding normal operator A^H A of the CG solves.
 //
 // Grid G = sigma N per axis, image placed at grid index r mod G (r centred),
 // plain 2-D FFT on the grid, W x W separable Kaiser-Bessel taps per sample at
@@ -8,10 +8,17 @@
 // kernel's Fourier transform at r / G, scale N^-1/2.  The adjoint is the
 // exact adjoint: spread with the same weights, inverse FFT, crop.
 //
-// Spreading is a gather over a CSR list built once per operator (for every
-// grid point, the (sample, weight) pairs whose footprint covers it, in sample
-// order), so A^H is deterministic and free of atomics; interpolation gathers
-// the W x W taps of each sample.
+// Samples are sorted once per operator into bins of 16 x 16 grid cells by the
+// cell of their first tap.  A workgroup owns one 16 x 16 tile of the output
+// grid and gathers the contributions of the samples of its bin and of the
+// three bins below and left of it (the only ones whose W-wide footprints
+// reach the tile, W <= 8): their values (read, drawn, or interpolated from
+// the input grid staged in LDS with a W - 1 halo) are compacted into LDS in
+// bin order, and every thread sums, for its own grid point, the samples that
+// cover it in that order.  Each grid point is written once, by its own tile,
+// so the spread is deterministic and needs no atomics and no halo pass; the
+// fused form (interpolate, then spread back) applies P^H P of the
+// interpolation P per tile without storing the samples.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,37 +70,34 @@ double kb_beta(double sigma, int W) {
 
 size_t KbLayout::bytes_of(size_t i) const { return sizes[i]; }
 
-KbLayout kb_layout(long M, int W, int ny, int nx, int Gy, int Gx, int K) {
+KbLayout kb_layout(long M, int W, int ny, int nx, int Gy, int Gx, int K, bool normal) {
   KbLayout L;
+  const size_t nb = (size_t)(Gy / kKbTile) * (Gx / kKbTile);
   const size_t s[KbLayout::kParts] = {
-      (size_t)M * 4,                  // ky0
-      (size_t)M * 4,                  // kx0
-      (size_t)M * W * 4,              // wy
-      (size_t)M * W * 4,              // wx
-      ((size_t)Gy * Gx + 1) * 4,      // rowptr
-      (size_t)M * W * W * 4,          // entry sample
-      (size_t)M * W * W * 4,          // entry weight
-      (size_t)ny * 4,                 // dy
-      (size_t)nx * 4,                 // dx
-      (size_t)Gx * 8,                 // twiddles x
-      (size_t)Gy * 8,                 // twiddles y
-      (size_t)K * Gy * Gx * 8,        // grid [K][Gy][Gx]
-      (size_t)K * M * 8,              // samples [K][M]
+      (size_t)M * 4,                       // sky0
+      (size_t)M * 4,                       // skx0
+      (size_t)M * W * 4,                   // swy
+      (size_t)M * W * 4,                   // swx
+      (size_t)M * 4,                       // perm
+      (nb + 1) * 4,                        // bin_ptr
+      (size_t)ny * 4,                      // dy
+      (size_t)nx * 4,                      // dx
+      (size_t)Gx * 8,                      // twiddles x
+      (size_t)Gy * 8,                      // twiddles y
+      (size_t)K * Gy * Gx * 8,             // grid [K][Gy][Gx]
+      normal ? (size_t)K * Gy * Gx * 8 : 0,   // grid2 [K][Gy][Gx]
   };
   for (int i = 0; i < KbLayout::kParts; ++i) L.sizes[i] = s[i];
   return L;
 }
 
-// Fill the tables (host double precision, stored float32).  traj_h: [M][2].
 void kb_build_host(const float* traj_h, long M, int W, double sigma, int ny, int nx, int Gy, int Gx,
-                   std::vector<int>& ky0, std::vector<int>& kx0, std::vector<float>& wy,
-                   std::vector<float>& wx, std::vector<int>& rowptr, std::vector<int>& ent_m,
-                   std::vector<float>& ent_w, std::vector<float>& dy, std::vector<float>& dx) {
+                   std::vector<int>& sky0, std::vector<int>& skx0, std::vector<float>& swy,
+                   std::vector<float>& swx, std::vector<int>& perm, std::vector<int>& bin_ptr,
+                   std::vector<float>& dy, std::vector<float>& dx) {
   const double beta = kb_beta(sigma, W);
-  ky0.resize(M);
-  kx0.resize(M);
-  wy.resize((size_t)M * W);
-  wx.resize((size_t)M * W);
+  std::vector<int> ky0(M), kx0(M);
+  std::vector<float> wy((size_t)M * W), wx((size_t)M * W);
   auto taps = [&](double w, int G, int& k0m, float* wt) {
     const double kappa = w * G / (2.0 * M_PI);
     const long k0 = (long)std::floor(kappa) - W / 2 + 1;
@@ -104,27 +108,28 @@ void kb_build_host(const float* traj_h, long M, int W, double sigma, int ny, int
     taps((double)traj_h[2 * m], Gy, ky0[m], &wy[(size_t)m * W]);
     taps((double)traj_h[2 * m + 1], Gx, kx0[m], &wx[(size_t)m * W]);
   }
-  // CSR over grid points, entries in (sample, ty, tx) order within a row
-  const size_t G2 = (size_t)Gy * Gx;
-  rowptr.assign(G2 + 1, 0);
-  for (long m = 0; m < M; ++m)
-    for (int a = 0; a < W; ++a)
-      for (int b = 0; b < W; ++b) {
-        const int iy = (ky0[m] + a) % Gy, ix = (kx0[m] + b) % Gx;
-        ++rowptr[(size_t)iy * Gx + ix + 1];
-      }
-  for (size_t g = 0; g < G2; ++g) rowptr[g + 1] += rowptr[g];
-  ent_m.resize((size_t)M * W * W);
-  ent_w.resize((size_t)M * W * W);
-  std::vector<int> fill(rowptr.begin(), rowptr.end() - 1);
-  for (long m = 0; m < M; ++m)
-    for (int a = 0; a < W; ++a)
-      for (int b = 0; b < W; ++b) {
-        const int iy = (ky0[m] + a) % Gy, ix = (kx0[m] + b) % Gx;
-        const int pos = fill[(size_t)iy * Gx + ix]++;
-        ent_m[pos] = (int)m;
-        ent_w[pos] = wy[(size_t)m * W + a] * wx[(size_t)m * W + b];
-      }
+  // counting sort by bin of the first tap (stable: sample order within a bin)
+  const int nbx = Gx / kKbTile, nby = Gy / kKbTile;
+  auto bin_of = [&](long m) { return (ky0[m] / kKbTile) * nbx + kx0[m] / kKbTile; };
+  bin_ptr.assign((size_t)nby * nbx + 1, 0);
+  for (long m = 0; m < M; ++m) ++bin_ptr[bin_of(m) + 1];
+  for (size_t b = 0; b + 1 < bin_ptr.size(); ++b) bin_ptr[b + 1] += bin_ptr[b];
+  std::vector<int> fill(bin_ptr.begin(), bin_ptr.end() - 1);
+  perm.resize(M);
+  sky0.resize(M);
+  skx0.resize(M);
+  swy.resize((size_t)M * W);
+  swx.resize((size_t)M * W);
+  for (long m = 0; m < M; ++m) {
+    const int j = fill[bin_of(m)]++;
+    perm[j] = (int)m;
+    sky0[j] = ky0[m];
+    skx0[j] = kx0[m];
+    for (int t = 0; t < W; ++t) {
+      swy[(size_t)j * W + t] = wy[(size_t)m * W + t];
+      swx[(size_t)j * W + t] = wx[(size_t)m * W + t];
+    }
+  }
   dy.resize(ny);
   dx.resize(nx);
   for (int y = 0; y < ny; ++y) dy[y] = (float)(1.0 / kb_phi_hat((double)(y - ny / 2) / Gy, W, beta));
@@ -133,25 +138,137 @@ void kb_build_host(const float* traj_h, long M, int W, double sigma, int ny, int
 
 // ------------------------------------------------------------------ kernels
 
-// nbuf[b][m] = CN(0, 1) Philox draw (stream 1, element c M + m, draw first + b)
-__global__ void k_kb_noise(float2* __restrict__ nbuf, int M, int c, uint64_t seed, uint64_t first) {
-  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y;
-  if (m >= M) return;
-  nbuf[(size_t)b * M + m] = draw_probe(seed, first + b, (uint32_t)((size_t)c * M + m), 1u, 3);
+enum KbSrc : int { KB_READ = 0, KB_NOISE = 1, KB_INTERP = 2 };
+
+// One 16 x 16 tile of the output grid per workgroup (blockIdx.x), probe
+// blockIdx.y: gout[k][tile] = sum over the samples whose footprint covers each
+// point of weight x value, the samples taken from the tile's bin and the three
+// bins below / left of it in bin order.  Sample values:
+//   KB_READ    src[k * bstride + m] (m the sample's index),
+//   KB_NOISE   CN(0, 1) Philox draw (stream 1, element c M + m, draw first + k),
+//   KB_INTERP  interpolation of gin[k] (the tile's window in LDS).
+template <int W, int SRC>
+__global__ __launch_bounds__(256) void k_kb_tile_spread(KbOp o, const float2* __restrict__ src, long bstride, int c,
+                                                        uint64_t seed, uint64_t first, const float2* __restrict__ gin,
+                                                        float2* __restrict__ gout) {
+  constexpr int T = kKbTile, WIN = T + 2 * W - 2, CH = 256, REACH = T + W - 1;
+  static_assert(T * T == CH, "one output point per thread");
+  __shared__ float2 win[SRC == KB_INTERP ? WIN * WIN : 1];
+  __shared__ float2 sv[CH];
+  __shared__ int soff[CH];        // oy | ox << 16: first tap in window coordinates
+  __shared__ float sw[CH][2 * W];
+  __shared__ int wcnt[4];
+  const int ty = blockIdx.x / o.nbx, tx = blockIdx.x % o.nbx, k = blockIdx.y;
+  const int y0 = ty * T, x0 = tx * T, wy0 = y0 - (W - 1), wx0 = x0 - (W - 1);
+  const long G2 = (long)o.Gy * o.Gx;
+  if constexpr (SRC == KB_INTERP) {
+    const float2* gk = gin + (size_t)k * G2;
+    for (int i = threadIdx.x; i < WIN * WIN; i += CH) {
+      int gy = wy0 + i / WIN, gx = wx0 + i % WIN;   // the window spans less than one period
+      gy += gy < 0 ? o.Gy : 0;
+      gy -= gy >= o.Gy ? o.Gy : 0;
+      gx += gx < 0 ? o.Gx : 0;
+      gx -= gx >= o.Gx ? o.Gx : 0;
+      win[i] = gk[(size_t)gy * o.Gx + gx];
+    }
+    __syncthreads();
+  }
+  const int py = threadIdx.x / T, px = threadIdx.x % T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int nb = 0; nb < 4; ++nb) {
+    int by = ty - 1 + (nb >> 1), bx = tx - 1 + (nb & 1);
+    by += by < 0 ? o.nby : 0;
+    bx += bx < 0 ? o.nbx : 0;
+    const int bin = by * o.nbx + bx;
+    const int p0 = o.bin_ptr[bin], p1 = o.bin_ptr[bin + 1];
+    for (int c0 = p0; c0 < p1; c0 += CH) {
+      const int j = c0 + threadIdx.x;
+      bool take = false;
+      int oy = 0, ox = 0;
+      float wyv[W], wxv[W];
+      float2 v = make_float2(0.f, 0.f);
+      if (j < p1) {
+        oy = o.sky0[j] - wy0;
+        ox = o.skx0[j] - wx0;
+        oy += oy < 0 ? o.Gy : 0;
+        oy -= oy >= o.Gy ? o.Gy : 0;
+        ox += ox < 0 ? o.Gx : 0;
+        ox -= ox >= o.Gx ? o.Gx : 0;
+        take = oy < REACH && ox < REACH;   // the footprint meets the tile
+      }
+      if (take) {
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          wyv[t] = o.swy[(size_t)j * W + t];
+          wxv[t] = o.swx[(size_t)j * W + t];
+        }
+        if constexpr (SRC == KB_READ) {
+          v = src[(size_t)k * bstride + o.perm[j]];
+        } else if constexpr (SRC == KB_NOISE) {
+          v = draw_probe(seed, first + k, (uint32_t)((size_t)c * o.M + o.perm[j]), 1u, 3);
+        } else {
+#pragma unroll
+          for (int a = 0; a < W; ++a) {
+            float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int t = 0; t < W; ++t) r = cfma(r, wxv[t], win[(oy + a) * WIN + ox + t]);
+            v = cfma(v, wyv[a], r);
+          }
+        }
+      }
+      // compaction that keeps bin order: wave ballots, wave offsets in LDS
+      const uint64_t mask = __ballot(take);
+      const int before = __popcll(mask & ((1ull << lane) - 1ull));
+      if (lane == 0) wcnt[wave] = __popcll(mask);
+      __syncthreads();
+      int base = 0;
+      for (int w = 0; w < wave; ++w) base += wcnt[w];
+      const int total = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+      if (take) {
+        const int pos = base + before;
+        sv[pos] = v;
+        soff[pos] = oy | (ox << 16);
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          sw[pos][t] = wyv[t];
+          sw[pos][W + t] = wxv[t];
+        }
+      }
+      __syncthreads();
+      for (int q = 0; q < total; ++q) {
+        const int off = soff[q];
+        const int dyy = py + W - 1 - (off & 0xffff), dxx = px + W - 1 - (off >> 16);
+        if ((unsigned)dyy < (unsigned)W && (unsigned)dxx < (unsigned)W)
+          acc = cfma(acc, sw[q][dyy] * sw[q][W + dxx], sv[q]);
+      }
+      __syncthreads();   // the lists are rewritten by the next chunk
+    }
+  }
+  gout[(size_t)k * G2 + (size_t)(y0 + py) * o.Gx + x0 + px] = acc;
 }
 
-// grid[b][g] = sum over the CSR row g of w * src[b * bstride + m]
-__global__ void k_kb_spread(const float2* __restrict__ src, long bstride, const int* __restrict__ rowptr,
-                            const int* __restrict__ ent_m, const float* __restrict__ ent_w,
-                            float2* __restrict__ grid, long G2) {
-  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// out[b * bstride + m] = sum_{a, t} wy[a] wx[t] grid[b][ky0 + a][kx0 + t], one
+// thread per sample in bin order (neighbouring threads read neighbouring cells)
+template <int W>
+__global__ __launch_bounds__(256) void k_kb_interp(KbOp o, const float2* __restrict__ grid, float2* __restrict__ out,
+                                                   long bstride) {
+  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
-  if (g >= G2) return;
-  const float2* sb = src + (size_t)b * bstride;
+  if (j >= o.M) return;
+  const float2* gb = grid + (size_t)b * o.Gy * o.Gx;
   float2 acc = make_float2(0.f, 0.f);
-  for (int e = rowptr[g], e1 = rowptr[g + 1]; e < e1; ++e) acc = cfma(acc, ent_w[e], sb[ent_m[e]]);
-  grid[(size_t)b * G2 + g] = acc;
+  int iy = o.sky0[j];
+  for (int a = 0; a < W; ++a, ++iy) {
+    if (iy >= o.Gy) iy -= o.Gy;
+    const float wa = o.swy[(size_t)j * W + a];
+    int ix = o.skx0[j];
+    for (int t = 0; t < W; ++t, ++ix) {
+      if (ix >= o.Gx) ix -= o.Gx;
+      acc = cfma(acc, wa * o.swx[(size_t)j * W + t], gb[(size_t)iy * o.Gx + ix]);
+    }
+  }
+  out[(size_t)b * bstride + o.perm[j]] = acc;
 }
 
 // out[b][y][x] (= or +=) conj(S_c[y][x]) grid[b][(y - ny/2) mod Gy][(x - nx/2) mod Gx] dy dx scale
@@ -189,52 +306,45 @@ __global__ void k_kb_expand(const float2* __restrict__ xin, const float2* __rest
   grid[(size_t)b * Gy * Gx + g] = v;
 }
 
-// out[b * bstride + m] = sum_{a, t} wy[m][a] wx[m][t] grid[b][ky0 + a][kx0 + t]
-__global__ void k_kb_interp(const float2* __restrict__ grid, const int* __restrict__ ky0,
-                            const int* __restrict__ kx0, const float* __restrict__ wy,
-                            const float* __restrict__ wx, float2* __restrict__ out, long bstride, int M,
-                            int W, int Gy, int Gx) {
-  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y;
-  if (m >= M) return;
-  const float2* gb = grid + (size_t)b * Gy * Gx;
-  float2 acc = make_float2(0.f, 0.f);
-  int iy = ky0[m];
-  for (int a = 0; a < W; ++a, ++iy) {
-    if (iy >= Gy) iy -= Gy;
-    const float wa = wy[(size_t)m * W + a];
-    int ix = kx0[m];
-    for (int t = 0; t < W; ++t, ++ix) {
-      if (ix >= Gx) ix -= Gx;
-      acc = cfma(acc, wa * wx[(size_t)m * W + t], gb[(size_t)iy * Gx + ix]);
-    }
+static dim3 kb_grid(long n, int K) { return dim3((unsigned)((n + 255) / 256), K); }
+
+template <int SRC>
+static hipError_t tile_spread(const KbOp& o, int K, const float2* src, long bstride, int c, uint64_t seed,
+                              uint64_t first, const float2* gin, float2* gout, hipStream_t s) {
+  const dim3 grid((unsigned)(o.nby * o.nbx), K), block(256);
+  switch (o.W) {
+    case 2: hipLaunchKernelGGL((k_kb_tile_spread<2, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
+    case 4: hipLaunchKernelGGL((k_kb_tile_spread<4, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
+    case 6: hipLaunchKernelGGL((k_kb_tile_spread<6, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
+    case 8: hipLaunchKernelGGL((k_kb_tile_spread<8, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
+    default: return hipErrorInvalidValue;
   }
-  out[(size_t)b * bstride + m] = acc;
+  return hipGetLastError();
 }
 
-static dim3 kb_grid(long n, int K) { return dim3((unsigned)((n + 255) / 256), K); }
+static hipError_t interp(const KbOp& o, int K, const float2* grid, float2* out, long bstride, hipStream_t s) {
+  const dim3 g = kb_grid(o.M, K), block(256);
+  switch (o.W) {
+    case 2: hipLaunchKernelGGL(k_kb_interp<2>, g, block, 0, s, o, grid, out, bstride); break;
+    case 4: hipLaunchKernelGGL(k_kb_interp<4>, g, block, 0, s, o, grid, out, bstride); break;
+    case 6: hipLaunchKernelGGL(k_kb_interp<6>, g, block, 0, s, o, grid, out, bstride); break;
+    case 8: hipLaunchKernelGGL(k_kb_interp<8>, g, block, 0, s, o, grid, out, bstride); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 // out[K][ny][nx] = A^H of K multi-coil sample arrays: src [K][nc][M] (whitened),
 // or Philox CN(0, 1) noise (src == nullptr; stream 1, element c M + m)
 hipError_t kb_adjoint(const KbOp& o, const float2* maps, int nc, int K, const float2* src, uint64_t seed,
                       uint64_t first, float2* out, hipStream_t s) {
-  const long G2 = (long)o.Gy * o.Gx, n = (long)o.ny * o.nx;
+  const long n = (long)o.ny * o.nx;
   const float scale = (float)(1.0 / std::sqrt((double)n));
   for (int c = 0; c < nc; ++c) {
-    const float2* sp;
-    long bstride;
-    if (src) {
-      sp = src + (size_t)c * o.M;
-      bstride = (long)nc * o.M;
-    } else {
-      hipLaunchKernelGGL(k_kb_noise, kb_grid(o.M, K), dim3(256), 0, s, o.samples, (int)o.M, c, seed, first);
-      sp = o.samples;
-      bstride = o.M;
-    }
-    hipLaunchKernelGGL(k_kb_spread, kb_grid(G2, K), dim3(256), 0, s, sp, bstride, o.rowptr, o.ent_m,
-                       o.ent_w, o.grid, G2);
-    hipError_t e = launch_fft2d(o.grid, K, o.Gy, o.Gx, true, o.twx, o.twy, s);
+    hipError_t e = src ? tile_spread<KB_READ>(o, K, src + (size_t)c * o.M, (long)nc * o.M, c, 0, 0, nullptr, o.grid, s)
+                       : tile_spread<KB_NOISE>(o, K, nullptr, 0, c, seed, first, nullptr, o.grid, s);
     if (e != hipSuccess) return e;
+    if ((e = launch_fft2d(o.grid, K, o.Gy, o.Gx, true, o.twx, o.twy, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_kb_crop_combine, kb_grid(n, K), dim3(256), 0, s, o.grid, maps + (size_t)c * n,
                        o.dy, o.dx, out, o.ny, o.nx, o.Gy, o.Gx, scale, c > 0 ? 1 : 0);
   }
@@ -251,8 +361,123 @@ hipError_t kb_forward(const KbOp& o, const float2* maps, int nc, int K, const fl
                        o.grid, o.ny, o.nx, o.Gy, o.Gx, scale);
     hipError_t e = launch_fft2d(o.grid, K, o.Gy, o.Gx, false, o.twx, o.twy, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_kb_interp, kb_grid(o.M, K), dim3(256), 0, s, o.grid, o.ky0, o.kx0, o.wy, o.wx,
-                       out + (size_t)c * o.M, (long)nc * o.M, (int)o.M, o.W, o.Gy, o.Gx);
+    if ((e = interp(o, K, o.grid, out + (size_t)c * o.M, (long)nc * o.M, s)) != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gridding normal operator
+
+// double sum over a 256-thread block, fixed order
+__device__ double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o2 = 128; o2 > 0; o2 >>= 1) {
+    if ((int)threadIdx.x < o2) red[threadIdx.x] += red[threadIdx.x + o2];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// p of the CG step per image row (blockIdx.x = y, blockIdx.y = k), as the grid
+// path's first row kernel forms it, with |r|^2 of the row in part[k][y][0]
+template <int MODE>
+__global__ __launch_bounds__(256) void k_kbn_pro(Grid2dArgs a) {
+  __shared__ double red[256];
+  const int y = blockIdx.x, k = blockIdx.y;
+  const size_t row = ((size_t)k * a.ny + y) * a.nx;
+  float alpha = 0.f, beta = 0.f;
+  if constexpr (MODE == C1_ITER) {
+    alpha = (float)a.alpha[k];
+    beta = (float)a.beta[k];
+  }
+  double d0 = 0.0;
+  for (int x = threadIdx.x; x < a.nx; x += 256) {
+    const size_t i = row + x;
+    if constexpr (MODE == C1_FIRST_PROBE) {
+      const float2 v = draw_probe(arg_seed(a), arg_first(a) + k, (uint32_t)(y * a.nx + x), 0u, a.dist);
+      a.r[i] = v;
+      a.p[i] = v;
+      d0 += (double)v.x * v.x + (double)v.y * v.y;
+    } else if constexpr (MODE == C1_FIRST_BUF) {
+      const float2 v = a.r[i];
+      a.p[i] = v;
+      d0 += (double)v.x * v.x + (double)v.y * v.y;
+    } else if constexpr (MODE == C1_ITER) {
+      const float2 po = a.p[i], qo = a.q[i], ro = a.r[i];
+      const float2 xo = a.x_zero ? make_float2(0.f, 0.f) : a.x[i];
+      const float2 rn = cfma(ro, -alpha, qo);
+      a.x[i] = cfma(xo, alpha, po);
+      a.r[i] = rn;
+      a.p[i] = cfma(rn, beta, po);
+      d0 += (double)rn.x * rn.x + (double)rn.y * rn.y;
+    }
+  }
+  d0 = block_sum256(d0, red);
+  if (threadIdx.x == 0) a.part[((size_t)k * a.ny + y) * 4] = d0;
+}
+
+// q = (coil sum already in q) + lam p_in, and the partial dots Re p^H q, |q|^2,
+// Re r^H q of the row (r = p_in outside C1_ITER)
+template <int MODE>
+__global__ __launch_bounds__(256) void k_kbn_epi(Grid2dArgs a) {
+  __shared__ double red[256];
+  const int y = blockIdx.x, k = blockIdx.y;
+  const size_t row = ((size_t)k * a.ny + y) * a.nx;
+  double d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  for (int x = threadIdx.x; x < a.nx; x += 256) {
+    const size_t i = row + x;
+    const float2 pin = MODE == C1_APPLY ? cscale(a.src[i], a.scale) : a.p[i];
+    const float2 q = cfma(a.q[i], a.lam, pin);
+    a.q[i] = q;
+    const float2 rv = MODE == C1_ITER ? a.r[i] : pin;
+    d1 += (double)pin.x * q.x + (double)pin.y * q.y;
+    d2 += (double)q.x * q.x + (double)q.y * q.y;
+    d3 += (double)rv.x * q.x + (double)rv.y * q.y;
+  }
+  d1 = block_sum256(d1, red);
+  d2 = block_sum256(d2, red);
+  d3 = block_sum256(d3, red);
+  if (threadIdx.x == 0) {
+    double* pp = a.part + ((size_t)k * a.ny + y) * 4;
+    pp[1] = d1;
+    pp[2] = d2;
+    pp[3] = d3;
+  }
+}
+
+hipError_t launch_kb_normal(int mode, const Grid2dArgs& a, const KbOp& o, hipStream_t s) {
+  if (!o.grid2) return hipErrorInvalidValue;
+  const dim3 rows((unsigned)a.ny, a.K), block(256);
+  switch (mode) {
+    case C1_FIRST_PROBE: hipLaunchKernelGGL(k_kbn_pro<C1_FIRST_PROBE>, rows, block, 0, s, a); break;
+    case C1_FIRST_BUF: hipLaunchKernelGGL(k_kbn_pro<C1_FIRST_BUF>, rows, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL(k_kbn_pro<C1_ITER>, rows, block, 0, s, a); break;
+    case C1_APPLY: break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long G2 = (long)o.Gy * o.Gx, n = (long)o.ny * o.nx;
+  const float scale = (float)(1.0 / std::sqrt((double)n));
+  const float2* xin = mode == C1_APPLY ? a.src : a.p;
+  const float in_scale = mode == C1_APPLY ? scale * a.scale : scale;
+  for (int c = 0; c < a.nc; ++c) {
+    hipLaunchKernelGGL(k_kb_expand, kb_grid(G2, a.K), block, 0, s, xin, a.maps + (size_t)c * n, o.dy, o.dx, o.grid,
+                       o.ny, o.nx, o.Gy, o.Gx, in_scale);
+    if ((e = launch_fft2d(o.grid, a.K, o.Gy, o.Gx, false, o.twx, o.twy, s)) != hipSuccess) return e;
+    if ((e = tile_spread<KB_INTERP>(o, a.K, nullptr, 0, c, 0, 0, o.grid, o.grid2, s)) != hipSuccess) return e;
+    if ((e = launch_fft2d(o.grid2, a.K, o.Gy, o.Gx, true, o.twx, o.twy, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_kb_crop_combine, kb_grid(n, a.K), block, 0, s, o.grid2, a.maps + (size_t)c * n, o.dy, o.dx,
+                       a.q, o.ny, o.nx, o.Gy, o.Gx, scale, c > 0 ? 1 : 0);
+  }
+  switch (mode) {
+    case C1_FIRST_PROBE: hipLaunchKernelGGL(k_kbn_epi<C1_FIRST_PROBE>, rows, block, 0, s, a); break;
+    case C1_FIRST_BUF: hipLaunchKernelGGL(k_kbn_epi<C1_FIRST_BUF>, rows, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL(k_kbn_epi<C1_ITER>, rows, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_kbn_epi<C1_APPLY>, rows, block, 0, s, a); break;
   }
   return hipGetLastError();
 }

@@ -136,6 +136,7 @@ struct pico_op_s {
   uint8_t* mask_d = nullptr;    // [ny][nx] (Cartesian 2-D)
   // Kaiser-Bessel gridding data path (non-Cartesian, kb_width > 0)
   bool has_kb = false;
+  bool kb_normal = false;       // CG normal operator by gridding (A_grid^H A_grid) instead of Toeplitz
   pico::KbOp kb;
   // device memory: from the allocator in effect (pico_set_allocator, else
   // hipMalloc), or from a serving arena when one is set; bytes are counted in
@@ -360,6 +361,7 @@ hipError_t launch_normal(pico_op_t op, int K, int mode, const NormalCall& c, hip
   g.first = c.first;
   g.tp = c.tp;
   g.dist = c.dist;
+  if (op->kb_normal) return pico::launch_kb_normal(mode, g, op->kb, s);
   return pico::launch_grid_normal(mode, g, s);
 }
 
@@ -646,7 +648,7 @@ bool wants_gram16(const pico_op_desc_t* d) {
 }
 
 // Kaiser-Bessel tables of a non-Cartesian operator: device buffers in the
-// kb_layout order, tap weights and the spreading CSR built on the host
+// kb_layout order, samples sorted into grid-tile bins on the host
 hipError_t build_kb(pico_op_t op, const pico_op_desc_t* d, hipStream_t s) {
   int G[2];
   kb_grid_dims(d, G);
@@ -657,42 +659,43 @@ hipError_t build_kb(pico_op_t op, const pico_op_desc_t* d, hipStream_t s) {
   o.nx = op->nx;
   o.Gy = G[0];
   o.Gx = G[1];
-  const pico::KbLayout L = pico::kb_layout(o.M, o.W, o.ny, o.nx, o.Gy, o.Gx, op->K);
+  o.nby = o.Gy / pico::kKbTile;
+  o.nbx = o.Gx / pico::kKbTile;
+  const bool normal = d->noncart_normal == 1;
+  const pico::KbLayout L = pico::kb_layout(o.M, o.W, o.ny, o.nx, o.Gy, o.Gx, op->K, normal);
   hipError_t e;
-  char* part[pico::KbLayout::kParts];
+  char* part[pico::KbLayout::kParts] = {};
   for (int i = 0; i < pico::KbLayout::kParts; ++i)
-    if ((e = op->alloc(&part[i], L.bytes_of(i))) != hipSuccess) return e;
-  o.ky0 = (int*)part[0];
-  o.kx0 = (int*)part[1];
-  o.wy = (float*)part[2];
-  o.wx = (float*)part[3];
-  o.rowptr = (int*)part[4];
-  o.ent_m = (int*)part[5];
-  o.ent_w = (float*)part[6];
-  o.dy = (float*)part[7];
-  o.dx = (float*)part[8];
-  o.twx = (float2*)part[9];
-  o.twy = (float2*)part[10];
-  o.grid = (float2*)part[11];
-  o.samples = (float2*)part[12];
+    if (L.bytes_of(i) && (e = op->alloc(&part[i], L.bytes_of(i))) != hipSuccess) return e;
+  o.sky0 = (int*)part[0];
+  o.skx0 = (int*)part[1];
+  o.swy = (float*)part[2];
+  o.swx = (float*)part[3];
+  o.perm = (int*)part[4];
+  o.bin_ptr = (int*)part[5];
+  o.dy = (float*)part[6];
+  o.dx = (float*)part[7];
+  o.twx = (float2*)part[8];
+  o.twy = (float2*)part[9];
+  o.grid = (float2*)part[10];
+  o.grid2 = (float2*)part[11];
   std::vector<float> traj((size_t)2 * o.M);
   if ((e = hipMemcpyAsync(traj.data(), d->traj, traj.size() * sizeof(float), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  std::vector<int> ky0, kx0, rowptr, ent_m;
-  std::vector<float> wy, wx, ent_w, dy, dx;
-  pico::kb_build_host(traj.data(), o.M, o.W, d->oversamp, o.ny, o.nx, o.Gy, o.Gx, ky0, kx0, wy, wx, rowptr,
-                      ent_m, ent_w, dy, dx);
+  std::vector<int> sky0, skx0, perm, bin_ptr;
+  std::vector<float> swy, swx, dy, dx;
+  pico::kb_build_host(traj.data(), o.M, o.W, d->oversamp, o.ny, o.nx, o.Gy, o.Gx, sky0, skx0, swy, swx, perm,
+                      bin_ptr, dy, dx);
   const std::vector<float2> tx = twiddle_table(o.Gx), ty = twiddle_table(o.Gy);
   auto up = [&](void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
   };
-  if ((e = up(o.ky0, ky0.data(), ky0.size() * 4)) != hipSuccess || (e = up(o.kx0, kx0.data(), kx0.size() * 4)) != hipSuccess ||
-      (e = up(o.wy, wy.data(), wy.size() * 4)) != hipSuccess || (e = up(o.wx, wx.data(), wx.size() * 4)) != hipSuccess ||
-      (e = up(o.rowptr, rowptr.data(), rowptr.size() * 4)) != hipSuccess ||
-      (e = up(o.ent_m, ent_m.data(), ent_m.size() * 4)) != hipSuccess ||
-      (e = up(o.ent_w, ent_w.data(), ent_w.size() * 4)) != hipSuccess || (e = up(o.dy, dy.data(), dy.size() * 4)) != hipSuccess ||
-      (e = up(o.dx, dx.data(), dx.size() * 4)) != hipSuccess || (e = up(o.twx, tx.data(), tx.size() * 8)) != hipSuccess ||
-      (e = up(o.twy, ty.data(), ty.size() * 8)) != hipSuccess)
+  if ((e = up(o.sky0, sky0.data(), sky0.size() * 4)) != hipSuccess || (e = up(o.skx0, skx0.data(), skx0.size() * 4)) != hipSuccess ||
+      (e = up(o.swy, swy.data(), swy.size() * 4)) != hipSuccess || (e = up(o.swx, swx.data(), swx.size() * 4)) != hipSuccess ||
+      (e = up(o.perm, perm.data(), perm.size() * 4)) != hipSuccess ||
+      (e = up(o.bin_ptr, bin_ptr.data(), bin_ptr.size() * 4)) != hipSuccess ||
+      (e = up(o.dy, dy.data(), dy.size() * 4)) != hipSuccess || (e = up(o.dx, dx.data(), dx.size() * 4)) != hipSuccess ||
+      (e = up(o.twx, tx.data(), tx.size() * 8)) != hipSuccess || (e = up(o.twy, ty.data(), ty.size() * 8)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;   // host vectors go out of scope
   op->has_kb = true;
@@ -741,7 +744,7 @@ pico_status_t validate(const pico_op_desc_t* d) {
     if (!pico::cart1d_supported(d->ny))
       return fail(PICO_EINVAL, "ny=" + std::to_string(d->ny) +
                                    " has no built column FFT (64 96 128 160 192 256 288 320 384 512)");
-  } else {
+  } else if (!(d->sampling == PICO_NONCART && d->noncart_normal == 1)) {
     const int f = d->sampling == PICO_NONCART ? 2 : 1;
     if (!pico::grid_line_supported(f * d->ny) || !pico::grid_line_supported(f * d->nx))
       return fail(PICO_EINVAL, "grid " + std::to_string(f * d->ny) + "x" + std::to_string(f * d->nx) +
@@ -761,6 +764,9 @@ pico_status_t validate(const pico_op_desc_t* d) {
     return fail(PICO_EINVAL, "lambda > 0 needs power_iters >= 1 and power_margin > 0");
   if (d->normal_form < 0 || d->normal_form > 3) return fail(PICO_EINVAL, "normal_form must be 0, 1, 2 or 3");
   if (d->graph != 0 && d->graph != 1) return fail(PICO_EINVAL, "graph must be 0 or 1");
+  if (d->noncart_normal != 0 && d->noncart_normal != 1) return fail(PICO_EINVAL, "noncart_normal must be 0 or 1");
+  if (d->noncart_normal == 1 && (d->sampling != PICO_NONCART || d->kb_width == 0))
+    return fail(PICO_EINVAL, "the gridding normal operator needs PICO_NONCART and kb_width > 0");
   if (d->normal_form >= 2 && (d->sampling != PICO_CART_1D || !pico::gram_supported(d->ny)))
     return fail(PICO_EINVAL, "the dense normal form needs PICO_CART_1D and ny a multiple of 32 in 64..512");
   if (d->kb_width != 0) {
@@ -769,6 +775,8 @@ pico_status_t validate(const pico_op_desc_t* d) {
       return fail(PICO_EINVAL, "kb_width must be even in 2..8");
     int G[2];
     if (!kb_grid_dims(d, G)) return fail(PICO_EINVAL, "oversamp * ny and oversamp * nx must be integers > n");
+    if (G[0] % pico::kKbTile || G[1] % pico::kKbTile)
+      return fail(PICO_EINVAL, "the gridding grid must be a multiple of 16 points per axis");
     for (int g : G)
       if (!pico::grid_line_supported(g))
         return fail(PICO_EINVAL, "gridding length " + std::to_string(g) +
@@ -844,19 +852,25 @@ pico_status_t estimate_bytes(const pico_op_desc_t* d, size_t* resident, size_t* 
       add(pico::gram16_pexp_count(d->nx, K) * 4);
     }
   } else {
-    add(Gy * Gx * 4);
-    add(Gx * 8);
-    add(Gy * 8);
-    add(K * nc * ny * Gx * 8);
+    const bool kbn = d->noncart_normal == 1;
+    if (!kbn) {
+      add(Gy * Gx * 4);
+      add(Gx * 8);
+      add(Gy * 8);
+      add(K * nc * ny * Gx * 8);
+    }
     if (d->sampling == PICO_NONCART) {
-      const size_t sc = toeplitz_scratch_bytes(d->nsamples, d->ny, d->nx);
-      add(sc);
-      sub(sc);
+      if (!kbn) {
+        const size_t sc = toeplitz_scratch_bytes(d->nsamples, d->ny, d->nx);
+        add(sc);
+        sub(sc);
+      }
       if (d->kb_width > 0) {
         int G[2];
         kb_grid_dims(d, G);
-        const KbLayout L = kb_layout(d->nsamples, d->kb_width, d->ny, d->nx, G[0], G[1], d->probe_tile);
-        for (int i = 0; i < KbLayout::kParts; ++i) add(L.bytes_of(i));
+        const KbLayout L = kb_layout(d->nsamples, d->kb_width, d->ny, d->nx, G[0], G[1], d->probe_tile, kbn);
+        for (int i = 0; i < KbLayout::kParts; ++i)
+          if (L.bytes_of(i)) add(L.bytes_of(i));
       }
     }
   }
@@ -1014,13 +1028,18 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     }
   } else {
     const int Gy = op->Gy, Gx = op->Gx;
-    if ((e = op->alloc(&op->w, (size_t)Gy * Gx)) != hipSuccess) return bad(e, "weights");
-    if ((e = op->alloc(&op->twx, Gx)) != hipSuccess) return bad(e, "twiddles");
-    if ((e = op->alloc(&op->twy, Gy)) != hipSuccess) return bad(e, "twiddles");
-    if ((e = op->alloc(&op->T, (size_t)K * nc * ny * Gx)) != hipSuccess) return bad(e, "grid workspace");
+    // the gridding normal operator works on the Kaiser-Bessel grid alone: no
+    // Toeplitz weights, no row-transformed planes
+    op->kb_normal = d->noncart_normal == 1;
     std::vector<float2> tx = twiddle_table(Gx), ty = twiddle_table(Gy);
-    if ((e = hipMemcpyAsync(op->twx, tx.data(), Gx * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
-    if ((e = hipMemcpyAsync(op->twy, ty.data(), Gy * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+    if (!op->kb_normal) {
+      if ((e = op->alloc(&op->w, (size_t)Gy * Gx)) != hipSuccess) return bad(e, "weights");
+      if ((e = op->alloc(&op->twx, Gx)) != hipSuccess) return bad(e, "twiddles");
+      if ((e = op->alloc(&op->twy, Gy)) != hipSuccess) return bad(e, "twiddles");
+      if ((e = op->alloc(&op->T, (size_t)K * nc * ny * Gx)) != hipSuccess) return bad(e, "grid workspace");
+      if ((e = hipMemcpyAsync(op->twx, tx.data(), Gx * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+      if ((e = hipMemcpyAsync(op->twy, ty.data(), Gy * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) return bad(e, "upload");
+    }
     const int fold = d->sampling == PICO_CART_2D;
     if ((e = pico::launch_prep_maps_rowmajor((const float2*)d->maps, linv_d, op->maps, nc, ny, nx, fold, s)) != hipSuccess) return bad(e, "prep maps");
     // CG-SENSE: the rounded maps define the operator on every path (the FP32
@@ -1032,10 +1051,12 @@ pico_status_t pico::init_in_arena(const pico_op_desc_t* d, void* stream, pico::D
     if (d->sampling == PICO_CART_2D) {
       if ((e = pico::launch_mask_weights(d->mask, op->w, ny, nx, (float)(1.0 / ((double)ny * nx)), s)) != hipSuccess) return bad(e, "weights");
     } else {
-      char* scratch = nullptr;
-      if ((e = op->alloc(&scratch, pico::toeplitz_scratch_bytes(d->nsamples, ny, nx))) != hipSuccess) return bad(e, "Toeplitz scratch");
-      if ((e = pico::build_toeplitz_weights(d->traj, d->nsamples, ny, nx, op->w, scratch, s)) != hipSuccess) return bad(e, "Toeplitz weights");
-      op->release(scratch);
+      if (!op->kb_normal) {
+        char* tscratch = nullptr;
+        if ((e = op->alloc(&tscratch, pico::toeplitz_scratch_bytes(d->nsamples, ny, nx))) != hipSuccess) return bad(e, "Toeplitz scratch");
+        if ((e = pico::build_toeplitz_weights(d->traj, d->nsamples, ny, nx, op->w, tscratch, s)) != hipSuccess) return bad(e, "Toeplitz weights");
+        op->release(tscratch);
+      }
       if (d->kb_width > 0) {
         if ((e = build_kb(op, d, s)) != hipSuccess) return bad(e, "gridding tables");
       }

@@ -220,34 +220,45 @@ hipError_t tv_tangent_final(const float2* dz, const float2* dp, float2* xo, floa
                             float lam, float theta, hipStream_t s);
 
 // Kaiser-Bessel gridding NUFFT (non-Cartesian data path)
+// Kaiser-Bessel gridding tables: samples sorted into square bins of
+// kKbTile x kKbTile grid cells by the cell of their first tap, so that every
+// grid tile finds the samples whose footprint reaches it in its own bin and
+// the three bins below / left of it.
+constexpr int kKbTile = 16;
 struct KbLayout {
-  static constexpr int kParts = 13;   // ky0 kx0 wy wx rowptr ent_m ent_w dy dx twx twy grid samples
+  static constexpr int kParts = 12;   // sky0 skx0 swy swx perm bin_ptr dy dx twx twy grid grid2
   size_t sizes[kParts];
   size_t bytes_of(size_t i) const;
 };
-KbLayout kb_layout(long M, int W, int ny, int nx, int Gy, int Gx, int K);
+// normal: also the second grid of the gridding normal operator
+KbLayout kb_layout(long M, int W, int ny, int nx, int Gy, int Gx, int K, bool normal);
 struct KbOp {
   long M = 0;
   int W = 0, ny = 0, nx = 0, Gy = 0, Gx = 0;
-  int *ky0 = nullptr, *kx0 = nullptr;   // [M] first tap index per axis (mod G)
-  float *wy = nullptr, *wx = nullptr;   // [M][W] tap weights
-  int* rowptr = nullptr;                // [Gy Gx + 1] CSR of the spreading gather
-  int* ent_m = nullptr;                 // [M W W] sample of each entry
-  float* ent_w = nullptr;               // [M W W] weight of each entry
+  int nby = 0, nbx = 0;                 // bins per axis (G / kKbTile)
+  int *sky0 = nullptr, *skx0 = nullptr; // [M] first tap cell per axis (mod G), bin order
+  float *swy = nullptr, *swx = nullptr; // [M][W] tap weights, bin order
+  int* perm = nullptr;                  // [M] sample index of each position in bin order
+  int* bin_ptr = nullptr;               // [nby nbx + 1] first position of each bin
   float *dy = nullptr, *dx = nullptr;   // de-apodisation [ny], [nx]
   float2 *twx = nullptr, *twy = nullptr;
   float2* grid = nullptr;               // [K][Gy][Gx]
-  float2* samples = nullptr;            // [K][M] noise staging
+  float2* grid2 = nullptr;              // [K][Gy][Gx], gridding normal operator only
 };
 double kb_beta(double sigma, int W);
+// host tables in bin order (double precision, stored float32); traj_h [M][2]
 void kb_build_host(const float* traj_h, long M, int W, double sigma, int ny, int nx, int Gy, int Gx,
-                   std::vector<int>& ky0, std::vector<int>& kx0, std::vector<float>& wy,
-                   std::vector<float>& wx, std::vector<int>& rowptr, std::vector<int>& ent_m,
-                   std::vector<float>& ent_w, std::vector<float>& dy, std::vector<float>& dx);
+                   std::vector<int>& sky0, std::vector<int>& skx0, std::vector<float>& swy,
+                   std::vector<float>& swx, std::vector<int>& perm, std::vector<int>& bin_ptr,
+                   std::vector<float>& dy, std::vector<float>& dx);
 hipError_t kb_adjoint(const KbOp& o, const float2* maps, int nc, int K, const float2* src, uint64_t seed,
                       uint64_t first, float2* out, hipStream_t s);
 hipError_t kb_forward(const KbOp& o, const float2* maps, int nc, int K, const float2* x, float2* out,
                       hipStream_t s);
+// Gridding normal operator q = (sum_c S_c^H A_c^H A_c S_c + lam) p with the
+// Kaiser-Bessel A_c (interpolation and spread fused per grid tile), in the
+// CG modes and with the partial dots of launch_grid_normal
+hipError_t launch_kb_normal(int mode, const Grid2dArgs& a, const KbOp& o, hipStream_t s);
 hipError_t launch_cart1d(int mode, const Cart1dArgs& a, hipStream_t s);
 hipError_t launch_cart1d_bf16(int mode, const Cart1dArgs& a, hipStream_t s);   // a.maps_bf set
 // dense per-column normal operator (phase-encode masks, FP32 matrix cores)

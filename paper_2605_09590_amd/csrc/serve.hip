@@ -257,7 +257,7 @@ struct pico_server_s {
     uint64_t h = 0x5049434f;   // "PICO"
     const int32_t ints[] = {d.ny, d.nx, d.ncoils, d.sampling, d.cg_iters, d.power_iters, d.probe_tile, d.recon,
                             d.fista_iters, d.wavelet_levels, d.kb_width, d.normal_form, d.tv_inner_iters,
-                            d.storage, d.graph};
+                            d.storage, d.graph, d.noncart_normal};
     for (int32_t v : ints) h = mix_host(h, (uint64_t)(uint32_t)v);
     const double dbl[] = {d.lambda, d.cg_tol, d.power_margin, d.cs_lambda, d.oversamp};
     for (double v : dbl) {

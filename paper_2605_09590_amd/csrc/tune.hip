@@ -30,10 +30,11 @@ std::string tune_key(const pico_op_desc_t* d) {
   const bool cs = d->recon != PICO_CGSENSE;
   const long ns = d->sampling == PICO_NONCART ? (long)((d->nsamples + 4095) / 4096) : 0;
   char buf[256];
-  std::snprintf(buf, sizeof buf, "s%d_r%d_%dx%d_c%d_it%d_tikh%d_st%d_T%d_in%d_lv%d_m%ld", d->sampling, d->recon,
+  std::snprintf(buf, sizeof buf, "s%d_r%d_%dx%d_c%d_it%d_tikh%d_st%d_T%d_in%d_lv%d_m%ld_g%d", d->sampling, d->recon,
                 d->ny, d->nx, (d->ncoils + 7) / 8 * 8, cs ? 0 : d->cg_iters, (!cs && d->lambda > 0.0) ? 1 : 0,
                 d->storage, cs ? d->fista_iters : 0, d->recon == PICO_CS_FISTA_TV ? d->tv_inner_iters : 0,
-                d->recon == PICO_CS_FISTA_L1WAV ? d->wavelet_levels : 0, ns);
+                d->recon == PICO_CS_FISTA_L1WAV ? d->wavelet_levels : 0, ns,
+                d->sampling == PICO_NONCART ? d->noncart_normal : 0);
   return buf;
 }
 

@@ -48,6 +48,7 @@ class pico_op_desc_t(ctypes.Structure):
         ("tv_inner_iters", ctypes.c_int32),
         ("storage", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("noncart_normal", ctypes.c_int32),
     ]
 
 
@@ -236,7 +237,7 @@ def make_desc(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
               traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
               wavelet_levels=4, oversamp=2.0, kb_width=0, normal_form=0, ncoils=None,
-              tv_inner_iters=10, storage=0, graph=0):
+              tv_inner_iters=10, storage=0, graph=0, noncart_normal=0):
     """pico_op_desc_t for the arguments of pico_init; returns (desc, keep) where
     ``keep`` holds the host psi array the descriptor points to."""
     d = pico_op_desc_t()
@@ -268,6 +269,7 @@ def make_desc(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
     d.tv_inner_iters = tv_inner_iters
     d.storage = storage
     d.graph = graph
+    d.noncart_normal = noncart_normal
     return d, keep
 
 
@@ -275,14 +277,15 @@ def pico_init(ny, nx, maps, psi, mask, sampling=PICO_CART_1D, lam=0.0, cg_iters=
               power_iters=15, power_margin=1.01, probe_tile=256, recon=PICO_CGSENSE,
               traj=None, nsamples=0, kdata=None, fista_iters=100, cs_lambda=1e-3,
               wavelet_levels=4, oversamp=2.0, kb_width=0, normal_form=0, stream=None,
-              tv_inner_iters=10, storage=0, graph=0):
+              tv_inner_iters=10, storage=0, graph=0, noncart_normal=0):
     """pico_init: ``maps`` complex64 device tensor [nc][ny][nx]; ``psi`` numpy
     complex128 [nc][nc] or None; ``mask`` uint8 device tensor.  Returns the handle."""
     lib = load()
     d, keep = make_desc(ny, nx, maps, psi, mask, sampling, lam, cg_iters, cg_tol, power_iters,
                         power_margin, probe_tile, recon, traj, nsamples, kdata, fista_iters,
                         cs_lambda, wavelet_levels, oversamp, kb_width, normal_form,
-                        tv_inner_iters=tv_inner_iters, storage=storage, graph=graph)
+                        tv_inner_iters=tv_inner_iters, storage=storage, graph=graph,
+                        noncart_normal=noncart_normal)
     h = ctypes.c_void_p()
     _check(lib.pico_init(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
     del keep

@@ -65,3 +65,28 @@ def test_gridding_adjointness_and_taps():
     kappa = traj[:, 0] * g.Gy / (2 * math.pi)
     d = (kappa[:, None] - g.iy + g.Gy / 2) % g.Gy - g.Gy / 2
     assert np.all(np.abs(d) <= g.W / 2 + 1e-9)
+
+
+@pytest.mark.parametrize("sigma,W,bound", [(2.0, 6, 1e-5), (1.25, 4, 1e-2)])
+def test_gridding_normal_operator(sigma, W, bound):
+    # M_grid = sum_c S^H A_grid^H A_grid S against the exact (Toeplitz = NUDFT)
+    # normal operator: within the gridding error, which falls with the width;
+    # Hermitian and positive by construction (A_grid^H is the exact adjoint)
+    n = 32
+    rng = np.random.default_rng(7)
+    maps = workloads.coil_maps(n, n, 3, rng)
+    psi = workloads.noise_cov(3, rng)
+    traj = workloads.spiral_traj(n, 2, 12, 400)
+    exact = nufft.NonCartOp(maps, psi, traj)
+    grid = nufft.NonCartOp(maps, psi, traj, kb=(sigma, W), normal_mode="gridding")
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    y = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    mg, mt = grid.normal(x), exact.normal(x)
+    e = _rel(mg, mt)
+    assert 1e-12 < e < bound
+    np.testing.assert_allclose(mg, grid.normal_gridding(x), rtol=0, atol=0)
+    lhs, rhs = np.vdot(y, grid.normal(x)), np.vdot(grid.normal(y), x)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert np.vdot(x, mg).real > 0 and abs(np.vdot(x, mg).imag) <= 1e-12 * abs(np.vdot(x, mg))
+    with pytest.raises(ValueError):
+        nufft.NonCartOp(maps, psi, traj, normal_mode="gridding")
