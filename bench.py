@@ -205,6 +205,7 @@ def serve_leg(lib, workloads, torch, np, dev, n_req=24, rhos=(0.5, 0.9, 1.2), n_
                       "normal_form": t["normal_form"], "graph": t["graph"],
                       "probes_per_s": round(t["probes_per_s"], 1)})
     tune_s = time.perf_counter() - t0
+    progress(f"serving: tuned {len(pool)} operators in {tune_s:.1f} s")
     reqs = serve_requests(np, pool, n_req, probes)
     srv = lib.Server(budget, slots, depth)
     srv.set_tuning(tune_path)
@@ -216,7 +217,9 @@ def serve_leg(lib, workloads, torch, np, dev, n_req=24, rhos=(0.5, 0.9, 1.2), n_
     service = [d["t_done_ms"] - d["t_admit_ms"] for d in seq]
     capacity = 1e3 / float(np.mean(service))
     rates = []
+    progress(f"serving: warm capacity {capacity:.2f} requests/s")
     for rho in rhos:
+        progress(f"serving: rho {rho}")
         lam = rho * capacity
         arr = np.cumsum(np.random.default_rng(int(rho * 1000)).exponential(1.0 / lam, n_req))
         info, accs = serve_run(lib, torch, dev, srv, reqs, arrivals=arr)
@@ -560,74 +563,174 @@ def spiral_leg(lib, workloads, torch, np, dev, steps, storage):
     }
 
 
-def spiral_ttt_leg(lib, workloads, torch, np, dev, n_ref=16384, chunk=64, max_n=16384):
-    """Time to a 1 % std map on the spiral workload, the paper's non-Cartesian
-    comparison (Sec. 3.2.2; its appendix certifies a high-count reference):
-    no exact map exists at 256^2 (65536 solves), so the reference is a
-    separate PICO map of n_ref probes (seed 101).  Its own std-map error e_ref
-    (the standard-error proxy of its accumulator) adds in quadrature to the
-    measured NRMSE of an independent run, so a run counts as within 1 % when
-    sqrt(NRMSE^2 - e_ref^2) <= 1 %; the raw NRMSE at that point is reported.
-    PICO (seed 7) and PMR (seed 3) add samples in chunks; the clocks include
-    the monitor."""
+def spiral_subset_exact(lib, torch, h, n_side, voxels, K=256):
+    """Exact Sigma_jj (and the off-diagonal energies of column j) for the
+    voxels j of ``voxels`` (a multiple of K of them): unit-vector right-hand
+    sides e_j through pico_apply_cov, K per launch (Sigma e_j is column j of
+    Sigma).  Returns (diag, sum_{l != j} |Sigma_lj|^2, sum_{l != j} (Re Sigma_lj)^2)
+    as float64 tensors on the device."""
+    n = n_side * n_side
+    dev = voxels.device
+    ar = torch.arange(K, device=dev)
+    diag, off, off_re = [], [], []
+    v = torch.zeros((K, n), dtype=torch.complex64, device=dev)
+    u = torch.empty_like(v)
+    for c0 in range(0, voxels.numel(), K):
+        idx = voxels[c0:c0 + K]
+        v.zero_()
+        v[ar, idx] = 1.0
+        lib.pico_apply_cov(h, v, u, K)
+        ud = u[ar, idx]
+        uu = u.to(torch.complex128)
+        d = ud.real.to(torch.float64)
+        diag.append(d)
+        off.append((uu.abs() ** 2).sum(dim=1) - ud.to(torch.complex128).abs() ** 2)
+        off_re.append((uu.real ** 2).sum(dim=1) - d ** 2)
+    return torch.cat(diag), torch.cat(off), torch.cat(off_re)
+
+
+def spiral_exact_leg(lib, workloads, torch, np, dev, Rs=(2, 3, 4), n_vox=4096, chunk=128, max_n=32768,
+                     families=True):
+    """Time to a 1 % std map on the spiral workload at R = 2, 3, 4 (the
+    paper's non-Cartesian comparison, Sec. 3.2.2) against an exact
+    reference: Sigma_jj by unit-vector solves on a seeded random subset of
+    n_vox voxels, so the NRMSE of the std maps is taken over that subset (an
+    unbiased sample of the full-FOV sums).  PICO (seed 7) and PMR (noise
+    replicas through the gridding adjoint, seed 3) add samples in chunks;
+    the clocks include the monitor.  At R = 2 also the probe families
+    (Sec. 2.2, Eqs. (18)-(20)): probes to 1 %, and the per-voxel variance of
+    the probe terms Re(conj v_j (Sigma v)_j) against the closed forms of
+    App. B (random phase and QPSK: 1/2 sum_{l != j} |Sigma_jl|^2; complex
+    Gaussian: Sigma_jj^2 + 1/2 sum_{l != j} |Sigma_jl|^2; real Rademacher:
+    sum_{l != j} (Re Sigma_jl)^2)."""
+    out = {}
+    for R in Rs:
+        progress(f"spiral R = {R}")
+        sp = workloads.config(3, seed=0, R=R)
+        traj = torch.from_numpy(sp.traj.astype(np.float32)).to(dev)
+        smaps = torch.from_numpy(sp.maps.astype(np.complex64)).to(dev)
+        h = lib.pico_init(sp.ny, sp.nx, smaps, sp.psi, None, sampling=lib.PICO_NONCART, lam=sp.lam,
+                          cg_iters=sp.cg_iters, probe_tile=256, traj=traj, nsamples=traj.shape[0],
+                          oversamp=2.0, kb_width=6)
+        n = sp.ny * sp.nx
+        vox = torch.from_numpy(np.sort(np.random.default_rng(1000 + R).choice(n, n_vox, replace=False))).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref, off, off_re = spiral_subset_exact(lib, torch, h, sp.ny, vox)
+        torch.cuda.synchronize()
+        ref_s = time.perf_counter() - t0
+        s_ref = torch.sqrt(torch.clamp(ref, min=0.0))
+
+        def nrmse(var_sub):
+            return float(torch.linalg.norm(torch.sqrt(torch.clamp(var_sub, min=0.0)) - s_ref) /
+                         torch.linalg.norm(s_ref))
+
+        def run(kind, seed, dist=0):
+            at = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+            acc = lib.make_accum(*at)
+            var = torch.empty(n, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done, hit, e = 0, None, None
+            while done < max_n:
+                if kind == "pico":
+                    lib.pico_noise_map(h, seed, done, chunk, dist, acc)
+                    done += chunk
+                    e = nrmse(at[0][vox] / done)
+                else:
+                    lib.pico_pmr_baseline(h, seed, done, chunk, acc)
+                    done += chunk
+                    lib.pico_pmr_finalize(h, acc, var)
+                    e = nrmse(var[vox])
+                if e <= 0.01:
+                    hit = (time.perf_counter() - t0, done)
+                    break
+            return hit, e, at, done
+
+        (ph, pe, pat, pn) = run("pico", 7)
+        (mh, me, _, _) = run("pmr", 3)
+        res = {"samples": int(traj.shape[0]), "reference": f"exact Sigma_jj on {n_vox} seeded voxels "
+                                                        f"({n_vox // 256} launches of 256 unit vectors, {ref_s:.2f} s)",
+               "pico_time_to_1pct_s": round(ph[0], 4) if ph else None, "pico_n_at_1pct": ph[1] if ph else None,
+               "pico_nrmse_at_stop": round(pe, 5),
+               "pmr_time_to_1pct_s": round(mh[0], 4) if mh else None, "pmr_n_at_1pct": mh[1] if mh else None,
+               "pmr_nrmse_at_stop": round(me, 5),
+               "speedup_pico_vs_pmr": round(mh[0] / ph[0], 3) if (ph and mh) else None}
+        if families and R == Rs[0]:
+            pred = {"random_phase": 0.5 * off, "qpsk": 0.5 * off, "gaussian": ref ** 2 + 0.5 * off,
+                    "rademacher": off_re}
+            fam = {}
+            for name, dist in (("random_phase", 0), ("qpsk", 1), ("rademacher", 2), ("gaussian", 3)):
+                hit, e, at, N = run("pico", 41, dist)
+                m = at[0][vox] / N
+                s2 = (at[2][vox] - N * m * m) / (N - 1)
+                ratio = float((s2 / pred[name]).mean())
+                fam[name] = {"n_at_1pct": hit[1] if hit else None, "nrmse_at_stop": round(e, 5),
+                             "probe_term_var_over_closed_form": round(ratio, 4), "probes_for_ratio": N}
+            res["probe_families"] = fam
+        lib.pico_destroy(h)
+        out[f"R{R}"] = res
+    out["workload"] = ("spiral 256x256, 16 coils, 48x4096 interleaves subsampled by R, lambda 0.1, CG 30 per solve, "
+                       "K=256; Kaiser-Bessel gridding (2.0, W 6) for the PMR data path; samples in chunks of "
+                       f"{chunk}")
+    out["paper_context"] = ("paper, GE spiral phantom on its own hardware: 64.0 / 70.6 / 91.0 s (PICO) vs "
+                            "462.6 / 501.0 / 538.6 s (PMR) at R = 2 / 3 / 4")
+    return out
+
+
+def spiral_gridding_leg(lib, workloads, torch, np, dev, steps=1):
+    """The spiral workload (R=2, K=256) with the gridding normal operator
+    (Kaiser-Bessel sigma 2, W 6, binned tile interpolation/spread) instead of
+    the Toeplitz one: probe-solves/s, per-application time, and its HBM
+    roofline on the algorithmic bytes (per coil and probe: the grid written
+    by the expansion, read and written by each of the two grid FFTs and by the
+    fused interpolation/spread, the image part read by the crop; plus the
+    probe fields), and ||Sigma_grid v - Sigma_T v|| / ||Sigma_T v|| on 8 probes."""
     sp = workloads.config(3, seed=0)
     traj = torch.from_numpy(sp.traj.astype(np.float32)).to(dev)
     smaps = torch.from_numpy(sp.maps.astype(np.complex64)).to(dev)
-    h = lib.pico_init(sp.ny, sp.nx, smaps, sp.psi, None, sampling=lib.PICO_NONCART, lam=sp.lam,
-                      cg_iters=sp.cg_iters, probe_tile=256, traj=traj, nsamples=traj.shape[0],
-                      oversamp=2.0, kb_width=6)
+    K = 256
     n = sp.ny * sp.nx
-    ra = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
-    racc = lib.make_accum(*ra)
+    kw = dict(sampling=lib.PICO_NONCART, lam=sp.lam, cg_iters=sp.cg_iters, probe_tile=K, traj=traj,
+              nsamples=traj.shape[0], oversamp=2.0, kb_width=6)
+    h = lib.pico_init(sp.ny, sp.nx, smaps, sp.psi, None, noncart_normal=1, **kw)
+    at = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    acc = lib.make_accum(at[0], None, at[1])
+    lib.pico_noise_map(h, 3, 0, K, 0, acc)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lib.pico_noise_map(h, 101, 0, n_ref, 0, racc)
-    ref = torch.empty(n, dtype=torch.float64, device=dev)
-    lib.pico_finalize(h, racc, ref)
+    lib.pico_profile_start(h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        lib.pico_noise_map(h, 3, (i + 1) * K, K, 0, acc)
+    e1.record()
     torch.cuda.synchronize()
-    ref_s = time.perf_counter() - t0
-    e_ref = lib.pico_monitor_stderr(h, racc)
-    s_ref = torch.sqrt(torch.clamp(ref, min=0.0))
-
-    def within(e):
-        return e * e - e_ref * e_ref <= 1e-4
-    # PICO
-    acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
-    acc = lib.make_accum(acc_t[0], None, acc_t[1])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    done, hit, ep = 0, None, None
-    while done < max_n:
-        lib.pico_noise_map(h, 7, done, chunk, 0, acc)
-        done += chunk
-        ep = lib.pico_monitor_nrmse(h, acc, ref)
-        if within(ep):
-            hit = (time.perf_counter() - t0, done)
-            break
-    # PMR (noise replicas through the gridding adjoint and one CG solve each)
-    pa = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
-    pacc = lib.make_accum(*pa)
-    var = torch.empty(n, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pdone, phit, e = 0, None, None
-    while pdone < 4 * max_n:
-        lib.pico_pmr_baseline(h, 3, pdone, chunk, pacc)
-        pdone += chunk
-        lib.pico_pmr_finalize(h, pacc, var)
-        e = float(torch.linalg.norm(torch.sqrt(torch.clamp(var, min=0.0)) - s_ref) / torch.linalg.norm(s_ref))
-        if within(e):
-            phit = (time.perf_counter() - t0, pdone)
-            break
+    prof = lib.pico_profile_stop(h)
+    ms = e0.elapsed_time(e1) / steps
+    v = torch.from_numpy(np.exp(2j * np.pi * np.random.default_rng(4).random((8, n))).astype(np.complex64)).to(dev)
+    ug = torch.empty_like(v)
+    lib.pico_apply_cov(h, v, ug, 8)
     lib.pico_destroy(h)
-    return {"workload": "spiral 256x256, 16 coils, 48x4096 interleaves R=2, lambda 0.1, CG 30; Kaiser-Bessel "
-                        "gridding (2.0, W 6) for the PMR data path",
-            "reference": f"PICO map of {n_ref} probes ({ref_s:.2f} s), own std-map error {e_ref:.4f}",
-            "pico_time_to_1pct_s": round(hit[0], 4) if hit else None, "pico_n_at_1pct": hit[1] if hit else None,
-            "pico_raw_nrmse_at_stop": round(ep, 5) if ep is not None else None,
-            "pmr_time_to_1pct_s": round(phit[0], 4) if phit else None, "pmr_n_at_1pct": phit[1] if phit else None,
-            "pmr_raw_nrmse_at_stop": round(e, 5) if e is not None else None,
-            "paper_context": "paper, GE spiral phantom R=2 on its own hardware: 64 s (PICO) vs 462 s (PMR)"}
+    ht = lib.pico_init(sp.ny, sp.nx, smaps, sp.psi, None, noncart_normal=0, **kw)
+    ut = torch.empty_like(v)
+    lib.pico_apply_cov(ht, v, ut, 8)
+    torch.cuda.synchronize()
+    lib.pico_destroy(ht)
+    rel = float(torch.linalg.norm(ug - ut) / torch.linalg.norm(ut))
+    it_ms, it_n = prof["normal_iter"]
+    op_s = it_ms / it_n / 1e3
+    G = 2 * sp.ny
+    alg = K * sp.nc * (56 * G * G + 8 * n) + K * 4 * 8 * n
+    return {"workload": "spiral 256x256, 16 coils, 48x4096 R=2, lambda 0.1, CG 30, K=256; gridding normal "
+                        "operator (sigma 2, W 6, 16x16 tile bins)",
+            "probe_solves_per_s": round(K / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+            "sigma_rel_diff_vs_toeplitz_8_probes": rel,
+            "roofline": {"bound": "hbm", "achieved": round(alg / op_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(alg / op_s / 1e9 / PEAK_HBM_GBS, 4),
+                         "kernel": "gridding normal operator (expand, grid FFT, tile interp/spread, inverse "
+                                   "FFT, crop/combine), C1_ITER",
+                         "avg_application_us": round(op_s * 1e6, 1), "alg_bytes": alg},
+            "kernel_ms": {k: round(v2[0], 3) for k, v2 in prof.items()}}
 
 
 def std_map_nrmse(torch, a, ref):
@@ -790,6 +893,88 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     }
 
 
+def cs_converged_leg(lib, workloads, torch, np, dev, reg="l1wav", n_max=8192):
+    """Time to converged accuracy of the Jacobian probes on a CS workload,
+    measured with the reference protocol of the paper's appendix on reference
+    budgets: a gold map of n_max probes (seed 201, maps kept at every power of
+    two N >= K along the way); the reference is converged at the smallest N
+    whose doubling improves the std-map NRMSE against the gold by < 0.5 % and
+    changes the FOV-mean variance by < 0.2 %; converged accuracy is that
+    NRMSE.  An independent run (seed 7) then adds tiles of K probes with the
+    monitor against the gold until it reaches converged accuracy: the
+    measured seconds and N.  PMR (FP64 replicas) is reported as its measured
+    rate and the derived time for the same N."""
+    tv = reg == "tv"
+    pr = workloads.config(4, seed=0, reg="tv") if tv else workloads.config(4, seed=0)
+    K = pr.probes
+    n = pr.ny * pr.nx
+    kd = cs_kspace(torch, dev, pr)
+    maps = torch.from_numpy(pr.maps.astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(pr.mask).to(dev)
+    kw = dict(sampling=lib.PICO_CART_2D, kdata=kd, fista_iters=pr.extra["fista_iters"],
+              cs_lambda=pr.extra["cs_lambda"], probe_tile=K)
+    if tv:
+        kw.update(recon=lib.PICO_CS_FISTA_TV, tv_inner_iters=pr.extra["tv_inner"])
+    else:
+        kw.update(recon=lib.PICO_CS_FISTA_L1WAV, wavelet_levels=pr.extra["levels"])
+    h = lib.pico_init(pr.ny, pr.nx, maps, pr.psi, mask, **kw)
+    ga = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    gacc = lib.make_accum(*ga)
+    snaps = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < n_max:
+        lib.pico_noise_map(h, 201, done, K, 0, gacc)
+        done += K
+        if done & (done - 1) == 0:
+            snaps[done] = ga[0] / done
+    torch.cuda.synchronize()
+    gold_s = time.perf_counter() - t0
+    gold = snaps[n_max]
+    curve, n_conv, e_conv = [], None, None
+    for N in sorted(snaps):
+        if N == n_max:
+            break
+        e1, e2 = std_map_nrmse(torch, snaps[N], gold), std_map_nrmse(torch, snaps[2 * N], gold)
+        r1, r2 = float(snaps[N].mean()), float(snaps[2 * N].mean())
+        curve.append((N, round(e1, 5)))
+        if n_conv is None and e1 - e2 < 0.005 and abs(r2 - r1) / abs(r2) < 0.002:
+            n_conv, e_conv = N, e1
+    res = {"workload": f"{'TV' if tv else 'L1-db4'} CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2, "
+                       f"FISTA {pr.extra['fista_iters']}, K={K} per tile",
+           "gold": f"{n_max} probes ({gold_s:.2f} s)", "nrmse_vs_gold_by_n": curve,
+           "n_converged": n_conv, "converged_nrmse": round(e_conv, 5) if e_conv is not None else None}
+    if n_conv is not None:
+        at = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
+        acc = lib.make_accum(*at)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, hit, e = 0, None, None
+        while done < n_max:
+            lib.pico_noise_map(h, 7, done, K, 0, acc)
+            done += K
+            e = std_map_nrmse(torch, at[0] / done, gold)
+            if e <= e_conv:
+                hit = (time.perf_counter() - t0, done)
+                break
+        res.update({"pico_time_to_converged_s": round(hit[0], 4) if hit else None,
+                    "pico_n_at_converged": hit[1] if hit else None, "pico_nrmse_at_stop": round(e, 5)})
+        pa = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        pacc = lib.make_accum(*pa)
+        lib.pico_pmr_cs(h, 5, 0, 4, 1e-3, pacc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lib.pico_pmr_cs(h, 5, 4, 16, 1e-3, pacc)
+        torch.cuda.synchronize()
+        rate = 16 / (time.perf_counter() - t0)
+        res.update({"pmr_replicas_per_s": round(rate, 2),
+                    "pmr_s_at_same_n_derived": round((hit[1] if hit else n_conv) / rate, 2)})
+    lib.pico_destroy(h)
+    res["paper_context"] = "paper, fastMRI knee TV-CS on its own hardware: 52.3 s (PICO) vs 95.5 s (PMR) at N = 5000"
+    return res
+
+
 def cs_robustness(lib, workloads, torch, np, dev, N=128, reg="l1wav"):
     """Noise-level sweep of the CS workload (Sec. 3.2.3, robustness): data at
     input SNR 45 dB - 20 log10(scale); per level the Jacobian-probe std map
@@ -838,12 +1023,57 @@ def cs_robustness(lib, workloads, torch, np, dev, N=128, reg="l1wav"):
             "levels": rows}
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _cpu_init():
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+
+
+def _cpu_worker(first_probe, nprobes):
+    """One oracle process: nprobes probes of the headline workload (FP64 numpy,
+    one thread); returns the seconds it took."""
+    import workloads
+    from oracle import pico as opico
+    prob = workloads.config(2, seed=0)
+    cov = opico.Covariance(opico.cartesian(prob.maps, prob.psi, prob.mask), 0.0, prob.cg_iters)
+    t0 = time.perf_counter()
+    opico.noise_map(cov, 11, first_probe, nprobes)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(per_proc=2):
+    """The FP64 oracle on the host cores: one single-threaded process per core
+    (at most 16, the host share of one GPU), each on its own probes of the
+    headline workload; run before the GPU is touched (the pool starts fresh
+    interpreters)."""
+    import multiprocessing as mp
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    procs = max(1, min(16, ncpu))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs, initializer=_cpu_init) as pool:
+        pool.starmap(_cpu_worker, [(0, 1)] * procs)            # imports and problem set-up, untimed
+        t0 = time.perf_counter()
+        secs = pool.starmap(_cpu_worker, [(1000 + i * per_proc, per_proc) for i in range(procs)])
+        wall = time.perf_counter() - t0
+    total = procs * per_proc
+    return {"value": round(total / wall, 4), "unit": "probe-solves/s", "cores": procs, "kind": "oracle",
+            "sample": f"{total} probes of the same 320x320 15-coil workload ({per_proc} per process), CG 30, "
+                      f"FP64 numpy, {procs} single-threaded processes on {ncpu} host cores "
+                      f"({wall:.1f} s wall, {sum(secs):.1f} s CPU)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-probes", type=int, default=4, help="oracle sample size (probes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1%% leg")
     ap.add_argument("--no-ref", action="store_true", help="skip the exact reference map (implies --no-ttt)")
@@ -871,6 +1101,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # the CPU baseline first: its process pool starts before anything touches the GPU
+    progress("cpu baseline")
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+
     import numpy as np
     import torch
 
@@ -889,6 +1123,7 @@ def main():
     h = lib.pico_init(ny, nx, maps, prob.psi, mask, cg_iters=prob.cg_iters, probe_tile=K)
     init_s = time.perf_counter() - t0
 
+    progress("headline workload: exact reference, time to 1 %, PMR, plain FP32, reduced grid, families")
     # exact reference map (row-unit probing of the column-separable Sigma)
     ref = torch.empty(n, dtype=torch.float64, device=dev)
     ref_s = None
@@ -983,6 +1218,7 @@ def main():
         out["adaptive_1pct"] = {"seconds": round(t_ad, 5), "probes": used, "proxy": round(proxy, 5),
                                 "nrmse_vs_exact": round(lib.pico_monitor_nrmse(h, acc, ref), 5)}
 
+    progress("headline throughput")
     # --- steady-state throughput: K=256 probes per step
     acc_t = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
     acc = lib.make_accum(*acc_t)
@@ -1032,11 +1268,13 @@ def main():
         "hbm_GBs_alg": round(bytes_alg / avg_s / 1e9, 1),
     }
 
+    progress("stream ceiling, dense forms")
     # --- the same workload with the dense per-column operator on the matrix cores
     ceiling = stream_ceiling(torch, dev)
     dense = dense_leg(lib, torch, np, dev, prob, form=2) if args.dense else None
     dense16 = dense_leg(lib, torch, np, dev, prob, form=3, ref=None if args.no_ref else ref) if args.dense else None
 
+    progress("spiral")
     # --- second workload: spiral CG-SENSE, Toeplitz normal operator (HBM-bound path),
     # complex64 planes and the bfloat16-stream variant
     spiral = spiral_bf16 = None
@@ -1044,16 +1282,21 @@ def main():
         spiral = spiral_leg(lib, workloads, torch, np, dev, args.spiral_steps, lib.PICO_FP32)
         spiral_bf16 = spiral_leg(lib, workloads, torch, np, dev, args.spiral_steps, lib.PICO_BF16_STREAM)
 
-    spiral_ttt = None
+    progress("spiral R = 2, 3, 4 against exact subsets; gridding normal operator")
+    spiral_ttt = spiral_grid = None
     if args.spiral_steps > 0 and not args.no_ttt:
-        spiral_ttt = spiral_ttt_leg(lib, workloads, torch, np, dev)
+        spiral_ttt = spiral_exact_leg(lib, workloads, torch, np, dev)
+    if args.spiral_steps > 0:
+        spiral_grid = spiral_gridding_leg(lib, workloads, torch, np, dev)
 
+    progress("CS")
     # --- third workload: CS (FISTA L1-db4), batched Jacobian-vector probes
     cs_res = cs_bf16 = None
     if args.cs_steps > 0:
         cs_res = cs_leg(lib, workloads, torch, np, dev, args.cs_steps)
         cs_bf16 = cs_leg(lib, workloads, torch, np, dev, args.cs_steps, lib.PICO_BF16_STREAM)
 
+    progress("TV-CS")
     # --- the paper's CS model: TV-regularised FISTA, Jacobian probes vs FP64 PMR replicas
     cs_tv = cs_tv_bf16 = None
     if args.cs_tv_steps > 0:
@@ -1075,29 +1318,23 @@ def main():
             leg.pop("_map", None)
             leg.pop("probes_accumulated", None)
 
+    progress("CS time to converged accuracy")
+    cs_conv = None
+    if args.cs_steps > 0 and not args.no_ttt:
+        cs_conv = {"l1wav": cs_converged_leg(lib, workloads, torch, np, dev, "l1wav", 8192)}
+        if args.cs_tv_steps > 0:
+            cs_conv["tv"] = cs_converged_leg(lib, workloads, torch, np, dev, "tv", 4096)
+
     robust = (cs_robustness(lib, workloads, torch, np, dev, reg=args.cs_robustness)
               if args.cs_robustness != "off" else None)
 
+    progress("serving")
     # --- serving: mixed requests under Poisson arrivals, p50 / p99 latency
     serving = None
     if args.serve != "off":
         serving = serve_leg(lib, workloads, torch, np, dev, **({"n_req": 100, "rhos": (0.25, 0.5, 0.75, 0.9, 1.1, 1.3)}
                                                                  if args.serve == "full" else {}))
     graphs = graph_leg(lib, workloads, torch, np, dev)
-
-    # --- CPU baseline: the FP64 oracle on a bounded sample of the same workload
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import pico as opico
-        op = opico.cartesian(prob.maps, prob.psi, prob.mask)
-        cov = opico.Covariance(op, 0.0, prob.cg_iters)
-        t0 = time.perf_counter()
-        opico.noise_map(cov, 11, 0, args.cpu_probes)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": round(args.cpu_probes / cpu_s, 4), "unit": "probe-solves/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{args.cpu_probes} probes of the same 320x320 15-coil workload, "
-                         f"CG 30, FP64 numpy, one process ({cpu_s:.1f} s)"}
 
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "probe-solves/s", "n_gpus": 1,
@@ -1120,10 +1357,12 @@ def main():
         "spiral": spiral,
         "spiral_bf16": spiral_bf16,
         "spiral_time_to_1pct": spiral_ttt,
+        "spiral_gridding_normal": spiral_grid,
         "cs": cs_res,
         "cs_bf16": cs_bf16,
         "cs_tv": cs_tv,
         "cs_tv_bf16": cs_tv_bf16,
+        "cs_time_to_converged": cs_conv,
         "serving": serving,
         "graph_vs_direct": graphs,
     }

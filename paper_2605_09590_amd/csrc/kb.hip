@@ -8,23 +8,30 @@
 // kernel's Fourier transform at r / G, scale N^-1/2.  The adjoint is the
 // exact adjoint: spread with the same weights, inverse FFT, crop.
 //
-// Samples are sorted once per operator into bins of 16 x 16 grid cells by the
-// cell of their first tap.  A workgroup owns one 16 x 16 tile of the output
-// grid and gathers the contributions of the samples of its bin and of the
-// three bins below and left of it (the only ones whose W-wide footprints
-// reach the tile, W <= 8): their values (read, drawn, or interpolated from
-// the input grid staged in LDS with a W - 1 halo) are compacted into LDS in
-// bin order, and every thread sums, for its own grid point, the samples that
-// cover it in that order.  Each grid point is written once, by its own tile,
-// so the spread is deterministic and needs no atomics and no halo pass; the
-// fused form (interpolate, then spread back) applies P^H P of the
-// interpolation P per tile without storing the samples.
+// Spread (A^H): samples are sorted once per operator into bins of 8 x 8 grid
+// cells by the cell of their first tap.  A one-wave workgroup owns one 8 x 8
+// tile of the output grid and gathers the contributions of the samples of
+// its bin and of the three bins below and left of it (the only ones whose
+// W-wide footprints reach the tile, W <= 8): their values (read or drawn) are
+// compacted into LDS in bin order, and every lane sums, for its own grid
+// point, the samples that cover it in that order.  Each grid point is written
+// once, by its own tile, so the spread is deterministic and needs no atomics
+// and no halo pass.
+//
+// Normal operator (A^H A): interpolation followed by the spread is P^H P on
+// the grid, a real symmetric operator whose row for grid point g has
+// nonzeros only at offsets d in [-(W-1), W-1]^2: S[g][d] = sum_m w_m(g)
+// w_m(g + d).  It is built once per operator in FP64 (from the same tap
+// tables) and applied per 16 x 16 grid tile with the input window (tile plus
+// a W - 1 halo) in LDS and the tile's stencil in registers, for a run of
+// probes; tiles that no sample's footprint reaches are written as zeros.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
+#include "arena.h"
 #include "device_common.h"
 #include "runtime.h"
 
@@ -86,6 +93,9 @@ KbLayout kb_layout(long M, int W, int ny, int nx, int Gy, int Gx, int K, bool no
       (size_t)Gy * 8,                      // twiddles y
       (size_t)K * Gy * Gx * 8,             // grid [K][Gy][Gx]
       normal ? (size_t)K * Gy * Gx * 8 : 0,   // grid2 [K][Gy][Gx]
+      normal ? OffsetArena::round_up((size_t)(Gy / kKbStencilTile) * (Gx / kKbStencilTile) * 4) +  // tile list
+                   (size_t)Gy * Gx * (2 * W - 1) * (2 * W - 1) * 4                               // stencil
+             : 0,
   };
   for (int i = 0; i < KbLayout::kParts; ++i) L.sizes[i] = s[i];
   return L;
@@ -136,45 +146,75 @@ void kb_build_host(const float* traj_h, long M, int W, double sigma, int ny, int
   for (int x = 0; x < nx; ++x) dx[x] = (float)(1.0 / kb_phi_hat((double)(x - nx / 2) / Gx, W, beta));
 }
 
+void kb_build_stencil(const std::vector<int>& sky0, const std::vector<int>& skx0, const std::vector<float>& swy,
+                      const std::vector<float>& swx, long M, int W, int Gy, int Gx, std::vector<int>& tile_list,
+                      int& n_active, std::vector<float>& stencil) {
+  // S[g][d] = sum_m w_m(g) w_m(g + d): the weight of input grid point g + d
+  // in output point g of P^H P, d in [-(W-1), W-1]^2, w_m the sample's taps
+  constexpr int T = kKbStencilTile;
+  const int D = 2 * W - 1, nty = Gy / T, ntx = Gx / T, ntiles = nty * ntx;
+  std::vector<int> slot(ntiles, -1);
+  for (long m = 0; m < M; ++m)   // tiles any footprint reaches are active
+    for (int a = 0; a < W; ++a)
+      for (int b = 0; b < W; ++b) {
+        const int gy = (sky0[m] + a) % Gy, gx = (skx0[m] + b) % Gx;
+        slot[(gy / T) * ntx + gx / T] = 0;
+      }
+  tile_list.clear();
+  for (int t = 0; t < ntiles; ++t)
+    if (slot[t] == 0) {
+      slot[t] = (int)tile_list.size();
+      tile_list.push_back(t);
+    }
+  n_active = (int)tile_list.size();
+  for (int t = 0; t < ntiles; ++t)
+    if (slot[t] < 0) tile_list.push_back(t);
+  std::vector<double> acc((size_t)n_active * D * D * T * T, 0.0);
+  for (long m = 0; m < M; ++m) {
+    const float* wy = &swy[(size_t)m * W];
+    const float* wx = &swx[(size_t)m * W];
+    for (int a1 = 0; a1 < W; ++a1) {
+      const int gy = (sky0[m] + a1) % Gy;
+      for (int b1 = 0; b1 < W; ++b1) {
+        const int gx = (skx0[m] + b1) % Gx;
+        const int t = slot[(gy / T) * ntx + gx / T];
+        const size_t pt = (size_t)(gy % T) * T + gx % T;
+        const double w1 = (double)wy[a1] * wx[b1];
+        double* base = &acc[(size_t)t * D * D * T * T + pt];
+        for (int a2 = 0; a2 < W; ++a2) {
+          const double w12 = w1 * wy[a2];
+          const int dy = a2 - a1 + W - 1;
+          for (int b2 = 0; b2 < W; ++b2) base[((size_t)dy * D + (b2 - b1 + W - 1)) * T * T] += w12 * wx[b2];
+        }
+      }
+    }
+  }
+  stencil.resize(acc.size());
+  for (size_t i = 0; i < acc.size(); ++i) stencil[i] = (float)acc[i];
+}
+
 // ------------------------------------------------------------------ kernels
 
-enum KbSrc : int { KB_READ = 0, KB_NOISE = 1, KB_INTERP = 2 };
+enum KbSrc : int { KB_READ = 0, KB_NOISE = 1 };
 
-// One 16 x 16 tile of the output grid per workgroup (blockIdx.x), probe
-// blockIdx.y: gout[k][tile] = sum over the samples whose footprint covers each
-// point of weight x value, the samples taken from the tile's bin and the three
-// bins below / left of it in bin order.  Sample values:
+// One 8 x 8 tile of the output grid per one-wave workgroup (blockIdx.x),
+// probe blockIdx.y: gout[k][tile] = sum over the samples whose footprint
+// covers each point of weight x value, the samples taken from the tile's bin
+// and the three bins below / left of it, in bin order.  Sample values:
 //   KB_READ    src[k * bstride + m] (m the sample's index),
-//   KB_NOISE   CN(0, 1) Philox draw (stream 1, element c M + m, draw first + k),
-//   KB_INTERP  interpolation of gin[k] (the tile's window in LDS).
+//   KB_NOISE   CN(0, 1) Philox draw (stream 1, element c M + m, draw first + k).
 template <int W, int SRC>
-__global__ __launch_bounds__(256) void k_kb_tile_spread(KbOp o, const float2* __restrict__ src, long bstride, int c,
-                                                        uint64_t seed, uint64_t first, const float2* __restrict__ gin,
-                                                        float2* __restrict__ gout) {
-  constexpr int T = kKbTile, WIN = T + 2 * W - 2, CH = 256, REACH = T + W - 1;
-  static_assert(T * T == CH, "one output point per thread");
-  __shared__ float2 win[SRC == KB_INTERP ? WIN * WIN : 1];
+__global__ __launch_bounds__(64) void k_kb_tile_spread(KbOp o, const float2* __restrict__ src, long bstride, int c,
+                                                       uint64_t seed, uint64_t first, float2* __restrict__ gout) {
+  constexpr int T = kKbTile, CH = T * T, REACH = T + W - 1;
+  static_assert(CH == 64, "one output point per lane of one wave");
   __shared__ float2 sv[CH];
-  __shared__ int soff[CH];        // oy | ox << 16: first tap in window coordinates
+  __shared__ int soff[CH];        // oy | ox << 16: first tap relative to the tile origin - (W - 1)
   __shared__ float sw[CH][2 * W];
-  __shared__ int wcnt[4];
   const int ty = blockIdx.x / o.nbx, tx = blockIdx.x % o.nbx, k = blockIdx.y;
   const int y0 = ty * T, x0 = tx * T, wy0 = y0 - (W - 1), wx0 = x0 - (W - 1);
   const long G2 = (long)o.Gy * o.Gx;
-  if constexpr (SRC == KB_INTERP) {
-    const float2* gk = gin + (size_t)k * G2;
-    for (int i = threadIdx.x; i < WIN * WIN; i += CH) {
-      int gy = wy0 + i / WIN, gx = wx0 + i % WIN;   // the window spans less than one period
-      gy += gy < 0 ? o.Gy : 0;
-      gy -= gy >= o.Gy ? o.Gy : 0;
-      gx += gx < 0 ? o.Gx : 0;
-      gx -= gx >= o.Gx ? o.Gx : 0;
-      win[i] = gk[(size_t)gy * o.Gx + gx];
-    }
-    __syncthreads();
-  }
-  const int py = threadIdx.x / T, px = threadIdx.x % T;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x, py = lane / T, px = lane % T;
   float2 acc = make_float2(0.f, 0.f);
   for (int nb = 0; nb < 4; ++nb) {
     int by = ty - 1 + (nb >> 1), bx = tx - 1 + (nb & 1);
@@ -183,11 +223,9 @@ __global__ __launch_bounds__(256) void k_kb_tile_spread(KbOp o, const float2* __
     const int bin = by * o.nbx + bx;
     const int p0 = o.bin_ptr[bin], p1 = o.bin_ptr[bin + 1];
     for (int c0 = p0; c0 < p1; c0 += CH) {
-      const int j = c0 + threadIdx.x;
+      const int j = c0 + lane;
       bool take = false;
       int oy = 0, ox = 0;
-      float wyv[W], wxv[W];
-      float2 v = make_float2(0.f, 0.f);
       if (j < p1) {
         oy = o.sky0[j] - wy0;
         ox = o.skx0[j] - wx0;
@@ -197,42 +235,20 @@ __global__ __launch_bounds__(256) void k_kb_tile_spread(KbOp o, const float2* __
         ox -= ox >= o.Gx ? o.Gx : 0;
         take = oy < REACH && ox < REACH;   // the footprint meets the tile
       }
-      if (take) {
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          wyv[t] = o.swy[(size_t)j * W + t];
-          wxv[t] = o.swx[(size_t)j * W + t];
-        }
-        if constexpr (SRC == KB_READ) {
-          v = src[(size_t)k * bstride + o.perm[j]];
-        } else if constexpr (SRC == KB_NOISE) {
-          v = draw_probe(seed, first + k, (uint32_t)((size_t)c * o.M + o.perm[j]), 1u, 3);
-        } else {
-#pragma unroll
-          for (int a = 0; a < W; ++a) {
-            float2 r = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int t = 0; t < W; ++t) r = cfma(r, wxv[t], win[(oy + a) * WIN + ox + t]);
-            v = cfma(v, wyv[a], r);
-          }
-        }
-      }
-      // compaction that keeps bin order: wave ballots, wave offsets in LDS
+      // compaction that keeps bin order
       const uint64_t mask = __ballot(take);
-      const int before = __popcll(mask & ((1ull << lane) - 1ull));
-      if (lane == 0) wcnt[wave] = __popcll(mask);
-      __syncthreads();
-      int base = 0;
-      for (int w = 0; w < wave; ++w) base += wcnt[w];
-      const int total = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+      const int total = __popcll(mask);
       if (take) {
-        const int pos = base + before;
+        const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+        float2 v;
+        if constexpr (SRC == KB_READ) v = src[(size_t)k * bstride + o.perm[j]];
+        else v = draw_probe(seed, first + k, (uint32_t)((size_t)c * o.M + o.perm[j]), 1u, 3);
         sv[pos] = v;
         soff[pos] = oy | (ox << 16);
 #pragma unroll
         for (int t = 0; t < W; ++t) {
-          sw[pos][t] = wyv[t];
-          sw[pos][W + t] = wxv[t];
+          sw[pos][t] = o.swy[(size_t)j * W + t];
+          sw[pos][W + t] = o.swx[(size_t)j * W + t];
         }
       }
       __syncthreads();
@@ -246,6 +262,49 @@ __global__ __launch_bounds__(256) void k_kb_tile_spread(KbOp o, const float2* __
     }
   }
   gout[(size_t)k * G2 + (size_t)(y0 + py) * o.Gx + x0 + px] = acc;
+}
+
+// P^H P by its stencil, one 16 x 16 tile (slot blockIdx.x of the tile list)
+// and a run of kc probes (from blockIdx.y * kc) per workgroup
+template <int W>
+__global__ __launch_bounds__(256) void k_kb_stencil(KbOp o, const float2* __restrict__ gin, float2* __restrict__ gout,
+                                                    int K, int kc) {
+  constexpr int T = kKbStencilTile, D = 2 * W - 1, WIN = T + D - 1;
+  static_assert(T * T == 256, "one output point per thread");
+  __shared__ float2 win[WIN * WIN];
+  const int slot = blockIdx.x, tile = o.tile_list[slot], ntx = o.Gx / T;
+  const int y0 = (tile / ntx) * T, x0 = (tile % ntx) * T, wy0 = y0 - (W - 1), wx0 = x0 - (W - 1);
+  const int py = threadIdx.x / T, px = threadIdx.x % T;
+  const int k0 = blockIdx.y * kc, k1 = min(K, k0 + kc);
+  const long G2 = (long)o.Gy * o.Gx;
+  float2* outp = gout + (size_t)(y0 + py) * o.Gx + x0 + px;
+  if (slot >= o.n_active) {   // no sample reaches this tile
+    for (int k = k0; k < k1; ++k) outp[(size_t)k * G2] = make_float2(0.f, 0.f);
+    return;
+  }
+  float st[D * D];
+  const float* sp = o.stencil + (size_t)slot * D * D * T * T + threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) st[i] = sp[(size_t)i * T * T];
+  for (int k = k0; k < k1; ++k) {
+    const float2* gk = gin + (size_t)k * G2;
+    __syncthreads();   // every thread is done with the previous window
+    for (int i = threadIdx.x; i < WIN * WIN; i += 256) {
+      int gy = wy0 + i / WIN, gx = wx0 + i % WIN;   // the window spans less than one period
+      gy += gy < 0 ? o.Gy : 0;
+      gy -= gy >= o.Gy ? o.Gy : 0;
+      gx += gx < 0 ? o.Gx : 0;
+      gx -= gx >= o.Gx ? o.Gx : 0;
+      win[i] = gk[(size_t)gy * o.Gx + gx];
+    }
+    __syncthreads();
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < D; ++dx) acc = cfma(acc, st[dy * D + dx], win[(py + dy) * WIN + px + dx]);
+    outp[(size_t)k * G2] = acc;
+  }
 }
 
 // out[b * bstride + m] = sum_{a, t} wy[a] wx[t] grid[b][ky0 + a][kx0 + t], one
@@ -310,13 +369,27 @@ static dim3 kb_grid(long n, int K) { return dim3((unsigned)((n + 255) / 256), K)
 
 template <int SRC>
 static hipError_t tile_spread(const KbOp& o, int K, const float2* src, long bstride, int c, uint64_t seed,
-                              uint64_t first, const float2* gin, float2* gout, hipStream_t s) {
-  const dim3 grid((unsigned)(o.nby * o.nbx), K), block(256);
+                              uint64_t first, float2* gout, hipStream_t s) {
+  const dim3 grid((unsigned)(o.nby * o.nbx), K), block(64);
   switch (o.W) {
-    case 2: hipLaunchKernelGGL((k_kb_tile_spread<2, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
-    case 4: hipLaunchKernelGGL((k_kb_tile_spread<4, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
-    case 6: hipLaunchKernelGGL((k_kb_tile_spread<6, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
-    case 8: hipLaunchKernelGGL((k_kb_tile_spread<8, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gin, gout); break;
+    case 2: hipLaunchKernelGGL((k_kb_tile_spread<2, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gout); break;
+    case 4: hipLaunchKernelGGL((k_kb_tile_spread<4, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gout); break;
+    case 6: hipLaunchKernelGGL((k_kb_tile_spread<6, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gout); break;
+    case 8: hipLaunchKernelGGL((k_kb_tile_spread<8, SRC>), grid, block, 0, s, o, src, bstride, c, seed, first, gout); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static hipError_t stencil(const KbOp& o, int K, const float2* gin, float2* gout, hipStream_t s) {
+  constexpr int kc = 16;
+  const int slots = (o.Gy / kKbStencilTile) * (o.Gx / kKbStencilTile);
+  const dim3 grid((unsigned)slots, (unsigned)((K + kc - 1) / kc)), block(256);
+  switch (o.W) {
+    case 2: hipLaunchKernelGGL(k_kb_stencil<2>, grid, block, 0, s, o, gin, gout, K, kc); break;
+    case 4: hipLaunchKernelGGL(k_kb_stencil<4>, grid, block, 0, s, o, gin, gout, K, kc); break;
+    case 6: hipLaunchKernelGGL(k_kb_stencil<6>, grid, block, 0, s, o, gin, gout, K, kc); break;
+    case 8: hipLaunchKernelGGL(k_kb_stencil<8>, grid, block, 0, s, o, gin, gout, K, kc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -341,8 +414,8 @@ hipError_t kb_adjoint(const KbOp& o, const float2* maps, int nc, int K, const fl
   const long n = (long)o.ny * o.nx;
   const float scale = (float)(1.0 / std::sqrt((double)n));
   for (int c = 0; c < nc; ++c) {
-    hipError_t e = src ? tile_spread<KB_READ>(o, K, src + (size_t)c * o.M, (long)nc * o.M, c, 0, 0, nullptr, o.grid, s)
-                       : tile_spread<KB_NOISE>(o, K, nullptr, 0, c, seed, first, nullptr, o.grid, s);
+    hipError_t e = src ? tile_spread<KB_READ>(o, K, src + (size_t)c * o.M, (long)nc * o.M, c, 0, 0, o.grid, s)
+                       : tile_spread<KB_NOISE>(o, K, nullptr, 0, c, seed, first, o.grid, s);
     if (e != hipSuccess) return e;
     if ((e = launch_fft2d(o.grid, K, o.Gy, o.Gx, true, o.twx, o.twy, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_kb_crop_combine, kb_grid(n, K), dim3(256), 0, s, o.grid, maps + (size_t)c * n,
@@ -449,7 +522,7 @@ __global__ __launch_bounds__(256) void k_kbn_epi(Grid2dArgs a) {
 }
 
 hipError_t launch_kb_normal(int mode, const Grid2dArgs& a, const KbOp& o, hipStream_t s) {
-  if (!o.grid2) return hipErrorInvalidValue;
+  if (!o.grid2 || !o.stencil) return hipErrorInvalidValue;
   const dim3 rows((unsigned)a.ny, a.K), block(256);
   switch (mode) {
     case C1_FIRST_PROBE: hipLaunchKernelGGL(k_kbn_pro<C1_FIRST_PROBE>, rows, block, 0, s, a); break;
@@ -468,7 +541,7 @@ hipError_t launch_kb_normal(int mode, const Grid2dArgs& a, const KbOp& o, hipStr
     hipLaunchKernelGGL(k_kb_expand, kb_grid(G2, a.K), block, 0, s, xin, a.maps + (size_t)c * n, o.dy, o.dx, o.grid,
                        o.ny, o.nx, o.Gy, o.Gx, in_scale);
     if ((e = launch_fft2d(o.grid, a.K, o.Gy, o.Gx, false, o.twx, o.twy, s)) != hipSuccess) return e;
-    if ((e = tile_spread<KB_INTERP>(o, a.K, nullptr, 0, c, 0, 0, o.grid, o.grid2, s)) != hipSuccess) return e;
+    if ((e = stencil(o, a.K, o.grid, o.grid2, s)) != hipSuccess) return e;
     if ((e = launch_fft2d(o.grid2, a.K, o.Gy, o.Gx, true, o.twx, o.twy, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_kb_crop_combine, kb_grid(n, a.K), block, 0, s, o.grid2, a.maps + (size_t)c * n, o.dy, o.dx,
                        a.q, o.ny, o.nx, o.Gy, o.Gx, scale, c > 0 ? 1 : 0);

@@ -679,6 +679,9 @@ hipError_t build_kb(pico_op_t op, const pico_op_desc_t* d, hipStream_t s) {
   o.twy = (float2*)part[9];
   o.grid = (float2*)part[10];
   o.grid2 = (float2*)part[11];
+  const int nslots = (o.Gy / pico::kKbStencilTile) * (o.Gx / pico::kKbStencilTile);
+  o.tile_list = normal ? (int*)part[12] : nullptr;
+  o.stencil = normal ? (float*)(part[12] + pico::OffsetArena::round_up((size_t)nslots * 4)) : nullptr;
   std::vector<float> traj((size_t)2 * o.M);
   if ((e = hipMemcpyAsync(traj.data(), d->traj, traj.size() * sizeof(float), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
@@ -697,6 +700,14 @@ hipError_t build_kb(pico_op_t op, const pico_op_desc_t* d, hipStream_t s) {
       (e = up(o.dy, dy.data(), dy.size() * 4)) != hipSuccess || (e = up(o.dx, dx.data(), dx.size() * 4)) != hipSuccess ||
       (e = up(o.twx, tx.data(), tx.size() * 8)) != hipSuccess || (e = up(o.twy, ty.data(), ty.size() * 8)) != hipSuccess)
     return e;
+  std::vector<int> tile_list;
+  std::vector<float> stencil;
+  if (normal) {
+    pico::kb_build_stencil(sky0, skx0, swy, swx, o.M, o.W, o.Gy, o.Gx, tile_list, o.n_active, stencil);
+    if ((e = up(o.tile_list, tile_list.data(), tile_list.size() * 4)) != hipSuccess ||
+        (e = up(o.stencil, stencil.data(), stencil.size() * 4)) != hipSuccess)
+      return e;
+  }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;   // host vectors go out of scope
   op->has_kb = true;
   return hipSuccess;

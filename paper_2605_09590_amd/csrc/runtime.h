@@ -224,13 +224,20 @@ hipError_t tv_tangent_final(const float2* dz, const float2* dp, float2* xo, floa
 // kKbTile x kKbTile grid cells by the cell of their first tap, so that every
 // grid tile finds the samples whose footprint reaches it in its own bin and
 // the three bins below / left of it.
-constexpr int kKbTile = 16;
+constexpr int kKbTile = 8;
+// The gridding normal operator applies P^H P (P the interpolation from the
+// grid to the samples) as a precomputed real stencil over (2W - 1)^2 grid
+// offsets, stored for the kKbStencilTile^2-point tiles that any sample's
+// footprint reaches ("active" tiles); the others stay zero.
+constexpr int kKbStencilTile = 16;
 struct KbLayout {
-  static constexpr int kParts = 12;   // sky0 skx0 swy swx perm bin_ptr dy dx twx twy grid grid2
+  static constexpr int kParts = 13;   // sky0 skx0 swy swx perm bin_ptr dy dx twx twy grid grid2 stencil+list
   size_t sizes[kParts];
   size_t bytes_of(size_t i) const;
 };
-// normal: also the second grid of the gridding normal operator
+// normal: also the second grid and the stencil of the gridding normal
+// operator (room for every tile: which ones are active depends on the
+// trajectory, and the byte count must follow from the description alone)
 KbLayout kb_layout(long M, int W, int ny, int nx, int Gy, int Gx, int K, bool normal);
 struct KbOp {
   long M = 0;
@@ -244,6 +251,11 @@ struct KbOp {
   float2 *twx = nullptr, *twy = nullptr;
   float2* grid = nullptr;               // [K][Gy][Gx]
   float2* grid2 = nullptr;              // [K][Gy][Gx], gridding normal operator only
+  // gridding normal operator: stencil tiles, active ones first
+  int n_active = 0;
+  int* tile_list = nullptr;             // [(Gy / 16) (Gx / 16)] tile of each slot
+  float* stencil = nullptr;             // [n_active][(2W - 1)^2][256] P^H P per offset and point
+                                        // (room for every tile)
 };
 double kb_beta(double sigma, int W);
 // host tables in bin order (double precision, stored float32); traj_h [M][2]
@@ -251,6 +263,11 @@ void kb_build_host(const float* traj_h, long M, int W, double sigma, int ny, int
                    std::vector<int>& sky0, std::vector<int>& skx0, std::vector<float>& swy,
                    std::vector<float>& swx, std::vector<int>& perm, std::vector<int>& bin_ptr,
                    std::vector<float>& dy, std::vector<float>& dx);
+// stencil of P^H P in FP64 from the tap tables above (bin order), stored FP32
+// [n_active][(2W - 1)^2][256]; tile_list: active tiles first, in tile order
+void kb_build_stencil(const std::vector<int>& sky0, const std::vector<int>& skx0, const std::vector<float>& swy,
+                      const std::vector<float>& swx, long M, int W, int Gy, int Gx, std::vector<int>& tile_list,
+                      int& n_active, std::vector<float>& stencil);
 hipError_t kb_adjoint(const KbOp& o, const float2* maps, int nc, int K, const float2* src, uint64_t seed,
                       uint64_t first, float2* out, hipStream_t s);
 hipError_t kb_forward(const KbOp& o, const float2* maps, int nc, int K, const float2* x, float2* out,
