@@ -33,6 +33,19 @@ namespace {
 // column past the image, and tiles start inside it
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Work item of workgroup b when the launch has 8 * ceil(total / 8) of them:
+// workgroups go to the eight XCDs in turn, and XCD b mod 8 takes the
+// contiguous run of items starting at (b mod 8) * ceil(total / 8), in the
+// order (tangent block, tile) with tiles in row order, so the halo rows and
+// columns that neighbouring tiles read twice are fetched into one L2.
+// Returns -1 for the padding workgroups.
+__device__ __forceinline__ long xcd_item(long total) {
+  const long per = (total + 7) / 8;
+  const long v = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  return v < total ? v : -1;
+}
+static dim3 xcd_grid(long total) { return dim3((unsigned)(8 * ((total + 7) / 8))); }
+
 // out = z - lam D^H r over B images (blockIdx.y); out may alias z
 __global__ void k_tv_u64(const double2* z, const double2* __restrict__ r, double2* out, int ny, int nx,
                          double lam) {
@@ -153,8 +166,11 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
   __shared__ float2 sRx[kTY + 1][kTX + 2];   // dr_x rows y0 .. y0+TY, cols x0-1 .. x0+TX
   __shared__ float2 sU[kTY + 1][kTX + 1];    // du rows y0 .. y0+TY, cols x0 .. x0+TX
   const long n = (long)ny * nx;
-  const int tilesx = (nx + kTX - 1) / kTX;
-  const int y0 = (int)(blockIdx.x / tilesx) * kTY, x0 = (int)(blockIdx.x % tilesx) * kTX;
+  const int tilesx = (nx + kTX - 1) / kTX, tiles = tilesx * ((ny + kTY - 1) / kTY);
+  const long item = xcd_item((long)tiles * ((K + kper - 1) / kper));
+  if (item < 0) return;
+  const int tile = (int)(item % tiles), kblk = (int)(item / tiles);
+  const int y0 = (tile / tilesx) * kTY, x0 = (tile % tilesx) * kTX;
   const int t = threadIdx.x, ty = t / kTX, tx = t % kTX;
   const int y = y0 + ty, x = x0 + tx;
   const bool own = y < ny && x < nx;
@@ -166,7 +182,7 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
     wh = what[i];
     iv = invn[i];
   }
-  const int k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
+  const int k0 = kblk * kper, k1 = min(K, k0 + kper);
   TangentLoads cur;
   cur.py = cur.px = make_float2(0.f, 0.f);
   if (k0 < k1) tv_load(cur, dz, drA, dp, k0, n, ny, nx, y0, x0, t, own, i, fst);
@@ -274,8 +290,11 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
   __shared__ float4 sW[C::NPROJ];               // projection data of steps 0 .. S-2 on R_s (w^)
   __shared__ float sV[C::NPROJ];                // and 1/|w|
   const long n = (long)ny * nx;
-  const int tilesx = (nx + TX - 1) / TX;
-  const int y0 = (int)(blockIdx.x / tilesx) * TY, x0 = (int)(blockIdx.x % tilesx) * TX;
+  const int tilesx = (nx + TX - 1) / TX, tiles = tilesx * ((ny + TY - 1) / TY);
+  const long item = xcd_item((long)tiles * ((K + kper - 1) / kper));
+  if (item < 0) return;
+  const int tile = (int)(item % tiles), kblk = (int)(item / tiles);
+  const int y0 = (tile / tilesx) * TY, x0 = (tile % tilesx) * TX;
   const int t = threadIdx.x;
   const bool fst = first != 0;
   auto gidx = [&](int a, int b) { return (long)wrap(y0 - S + a, ny) * nx + wrap(x0 - S + b, nx); };
@@ -301,7 +320,7 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
     whl = what[(size_t)(S - 1) * n + i];
     ivl = invn[(size_t)(S - 1) * n + i];
   }
-  const int k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
+  const int k0 = kblk * kper, k1 = min(K, k0 + kper);
   struct BoxPt {
     float2 vy, vx, qy, qx, z;
   };
@@ -451,7 +470,7 @@ static void launch_tv_steps(const float2* dz, float2* drA, float2* drB, float2* 
   const int tiles = ((ny + TY - 1) / TY) * ((nx + TX - 1) / TX);
   int kper = 8;
   while (kper > 1 && (long)tiles * ((K + kper - 1) / kper) < 2048) kper >>= 1;
-  const dim3 grid((unsigned)tiles, (unsigned)((K + kper - 1) / kper));
+  const dim3 grid = xcd_grid((long)tiles * ((K + kper - 1) / kper));
   TvTheta tt{};
   for (int q = 0; q < S; ++q) tt.th[q] = th[q];
   hipLaunchKernelGGL((k_tv_steps<S, TY, TX>), grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what, invn, ny, nx, K,
@@ -466,7 +485,7 @@ hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* d
   const int tiles = ((ny + kTY - 1) / kTY) * ((nx + kTX - 1) / kTX);
   int kper = 8;
   while (kper > 1 && (long)tiles * ((K + kper - 1) / kper) < 2048) kper >>= 1;
-  const dim3 grid((unsigned)tiles, (unsigned)((K + kper - 1) / kper));
+  const dim3 grid = xcd_grid((long)tiles * ((K + kper - 1) / kper));
   const float c8 = 1.0f / (8.0f * lam);
   int it = 0;
   if (inner & 1) {   // an odd count starts with one single step (dp updated in place)
