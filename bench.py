@@ -1036,20 +1036,32 @@ def cs_robustness(lib, workloads, torch, np, dev, N=128, reg="l1wav"):
                           fista_iters=pr.extra["fista_iters"], cs_lambda=pr.extra["cs_lambda"],
                           wavelet_levels=pr.extra["levels"], tv_inner_iters=pr.extra["tv_inner"],
                           probe_tile=128)
-        a1 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(2)]
-        lib.pico_noise_map(h, 3, 0, N, 0, lib.make_accum(a1[0], None, a1[1]))
+        a1 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        acc1 = lib.make_accum(*a1)
+        t0 = time.perf_counter()
+        lib.pico_noise_map(h, 3, 0, N, 0, acc1)
+        e_pico = lib.pico_monitor_stderr(h, acc1)    # delta-method std-map error of the probe mean
+        t_pico = time.perf_counter() - t0
         a2 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
         acc2 = lib.make_accum(*a2)
-        lib.pico_pmr_cs(h, 5, 0, N, sigma, acc2)
+        t0 = time.perf_counter()
+        for r0 in range(0, N, 256):
+            lib.pico_pmr_cs(h, 5, r0, min(256, N - r0), sigma, acc2)
+            torch.cuda.synchronize()
+            progress(f"robustness {reg} {snr:.1f} dB: {min(N, r0 + 256)} / {N} replicas")
+        t_pmr = time.perf_counter() - t0
         var = torch.empty(n, dtype=torch.float64, device=dev)
         lib.pico_pmr_finalize(h, acc2, var)
         torch.cuda.synchronize()
         lib.pico_destroy(h)
         s_pico = torch.sqrt(torch.clamp(a1[0] / N, min=0.0))
         s_pmr = torch.sqrt(torch.clamp(var, min=0.0))
+        e_pmr = math.sqrt(1.0 / (2.0 * (N - 1)))      # std map of a Gaussian sample variance
         rows.append({"scale": scale, "snr_db": round(snr, 1), "sigma": sigma,
                      "nrmse_pmr_vs_pico": round(float(torch.linalg.norm(s_pmr - s_pico) / torch.linalg.norm(s_pico)), 4),
-                     "mean_std_pico": float(s_pico.mean()), "mean_std_pmr": float(s_pmr.mean())})
+                     "mc_spread_expected": round(math.sqrt(e_pico ** 2 + e_pmr ** 2), 4),
+                     "mean_std_pico": float(s_pico.mean()), "mean_std_pmr": float(s_pmr.mean()),
+                     "pico_s": round(t_pico, 2), "pmr_s": round(t_pmr, 2)})
     model = (f"TV (lambda_TV {pr.extra['cs_lambda']}, {pr.extra['tv_inner']} dual steps)" if tv
              else f"L1-db4 (lambda {pr.extra['cs_lambda']})")
     return {"workload": f"CS {pr.ny}x{pr.nx}, {pr.nc} coils, {model}, FISTA {pr.extra['fista_iters']}; "
@@ -1121,6 +1133,8 @@ def main():
                     help="serving leg: 24 requests at 3 rates (default), 100 at 6 rates, or off")
     ap.add_argument("--cs-robustness", choices=["off", "l1wav", "tv"], default="off",
                     help="also run the CS noise-level sweep (PICO vs PMR std maps) for that model")
+    ap.add_argument("--robust-n", type=int, default=3000,
+                    help="probes and replicas per noise level of the CS sweep (the paper's N = 3000)")
     ap.add_argument("--no-dense", dest="dense", action="store_false",
                     help="skip the dense (matrix-core) form of the main workload")
     ap.add_argument("--no-plain", dest="plain", action="store_false",
@@ -1362,7 +1376,7 @@ def main():
         if args.cs_tv_steps > 0:
             cs_conv["tv"] = cs_converged_leg(lib, workloads, torch, np, dev, "tv", 8192)
 
-    robust = (cs_robustness(lib, workloads, torch, np, dev, reg=args.cs_robustness)
+    robust = (cs_robustness(lib, workloads, torch, np, dev, N=args.robust_n, reg=args.cs_robustness)
               if args.cs_robustness != "off" else None)
 
     progress("serving")

@@ -293,3 +293,27 @@ def test_fista_tv_fixed_point_of_exact_prox_gradient_map():
         xk = cs.FistaTV(op, f.lam, k, inner=200).recon(b)
         gap = _tv_objective(op, f, b, xk) - fs
         assert -1e-9 <= gap <= bound0 / (k + 1) ** 2
+
+
+def test_noise_map_jvp_estimates_diag_JJH():
+    # the estimator's mean of |J w|^2 over random-phase k-space probes on the
+    # sampled locations approaches diag(J J^H), J taken column by column from
+    # whitened unit k-space vectors on the mask (Sec. 2.2, CS extension)
+    op, b, f = _cs_problem(n=16, lam=5e-3, iters=10)
+    f = cs.FistaL1Wavelet(op, 5e-3, 10, levels=1)
+    _, coeffs = f.recon(b, store=True)
+    exact = np.zeros((16, 16))
+    idx = np.argwhere(np.broadcast_to(op.P[None] > 0, (op.nc, 16, 16)))
+    for c, ky, kx in idx:
+        e = np.zeros((op.nc, 16, 16), np.complex128)
+        e[c, ky, kx] = 1.0
+        exact += np.abs(f.jvp(e, coeffs)) ** 2
+    N = 800       # Monte-Carlo error of each voxel's mean about 1 / sqrt(N) = 3.5 %
+    acc = cs.noise_map_jvp(f, coeffs, 17, 0, N)
+    est = acc["sum"] / acc["count"]
+    rel = np.abs(est - exact) / exact
+    assert acc["count"] == N
+    assert np.sqrt(np.mean(rel ** 2)) < 0.08 and rel.max() < 0.35
+    # a probe that also fills the unsampled locations changes nothing (A^H masks them)
+    w = cs.kspace_probe(op, 3, 0)
+    assert np.all(w[:, op.P == 0] == 0)

@@ -82,9 +82,18 @@ def test_estimate_grows_with_tile_and_kind(p):
                         sampling=p.PICO_NONCART, traj=0x4000, nsamples=50000, lam=0.1,
                         oversamp=2.0, kb_width=6)
     rk, _ = p.pico_estimate_bytes(kb)
-    # gridding tables: 2 tap starts + 2 x 6 weights per sample, CSR of 36 entries
-    # per sample (index + weight), the [K][256][256] grid and [K][M] staging
-    assert rk - rs >= 50000 * (8 + 48 + 36 * 8) + 16 * 256 * 256 * 8 + 16 * 50000 * 8
+    # gridding tables in bin order: 2 tap starts + 2 x 6 weights + the sample
+    # index per sample, and the [K][256][256] grid
+    assert rk - rs >= 50000 * (8 + 48 + 4) + 16 * 256 * 256 * 8
+    # the gridding normal operator: a second [K][256][256] grid and the stencil
+    # ((2W - 1)^2 weights per grid point) in place of the Toeplitz kernels
+    kbn, _ = p.make_desc(128, 128, 0x1000, None, None, ncoils=8, probe_tile=16,
+                         sampling=p.PICO_NONCART, traj=0x4000, nsamples=50000, lam=0.1,
+                         oversamp=2.0, kb_width=6, noncart_normal=1)
+    rn, pn = p.pico_estimate_bytes(kbn)
+    grid2_and_stencil = 16 * 256 * 256 * 8 + 256 * 256 * 121 * 4
+    assert rn >= 50000 * (8 + 48 + 4) + 16 * 256 * 256 * 8 + grid2_and_stencil
+    assert rn - rk < grid2_and_stencil           # no Toeplitz kernels held
     bad, _ = p.make_desc(128, 128, 0x1000, None, None, ncoils=8, probe_tile=16,
                          sampling=p.PICO_NONCART, traj=0x4000, nsamples=50000, oversamp=1.1,
                          kb_width=6)
