@@ -12,14 +12,21 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2605_09590_amd", "csrc")
 
 
-def test_arena_bookkeeping(tmp_path):
+# the second build runs the same checks under AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; any report fails the run)
+SANITIZE = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+@pytest.mark.parametrize("flags", [[], SANITIZE], ids=["plain", "asan_ubsan"])
+def test_arena_bookkeeping(tmp_path, flags):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path / "arena_check")
-    subprocess.run([gxx, "-std=c++17", "-O1", "-I", CSRC, os.path.join(ROOT, "tests", "cpp", "arena_check.cpp"),
-                    "-o", exe], check=True)
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    subprocess.run([gxx, "-std=c++17", "-O1", *flags, "-I", CSRC,
+                    os.path.join(ROOT, "tests", "cpp", "arena_check.cpp"), "-o", exe], check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120, env=env)
     assert r.returncode == 0, r.stderr
     assert "arena ok" in r.stdout
 
