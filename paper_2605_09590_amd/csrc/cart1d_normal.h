@@ -39,16 +39,39 @@ struct MapsBf16 {
 };
 
 
+// Mask weights mask[k] / ny of a lane's layout-B lines.  Two-step plans keep
+// them in registers (one multiply per value); the Stockham plans, whose
+// registers are full, keep one bit per line and select.
+template <class CF>
+struct MaskLines {
+  static constexpr bool kRegs = CF::kMaskInRegs;
+  float w[kRegs ? CF::VB : 1];
+  uint32_t bits = 0;
+  __device__ __forceinline__ void load(const float* __restrict__ maskw, int lane) {
+    const bool inB = CF::inB(lane);
+#pragma unroll
+    for (int r = 0; r < CF::VB; ++r) {
+      const float m = inB ? maskw[CF::posB(lane, r)] : 0.f;
+      if constexpr (kRegs) w[r] = m;
+      bits |= (m != 0.f ? 1u : 0u) << r;
+    }
+  }
+  __device__ __forceinline__ bool on(int r) const { return (bits >> r) & 1u; }
+  __device__ __forceinline__ float2 apply(float2 v, int r) const {
+    if constexpr (kRegs) return cscale(v, w[r]);
+    else return on(r) ? cscale(v, 1.0f / CF::N) : make_float2(0.f, 0.f);
+  }
+};
+
 // q = (M + lam) p for one probe column held in layout A by the lanes of one
 // group: per coil, S' p -> FFT (layout A -> B) -> weight mask[k]/ny -> inverse
 // FFT (B -> A) -> accumulate conj(S') times the result.
 template <class CF, class MS>
 __device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 (&qa)[CF::VMAX],
                                            float lam, MS mcol, int nc,
-                                           uint32_t mbits, float2* lds, int lane,
+                                           const MaskLines<CF>& mk, float2* lds, int lane,
                                            const typename CF::Tw& tw) {
   constexpr int N = CF::N;
-  constexpr float minv = 1.0f / N;
   const bool inA = CF::inA(lane);
 #pragma unroll
   for (int m = 0; m < CF::VA; ++m) qa[m] = cscale(pv[m], lam);
@@ -59,8 +82,7 @@ __device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 
     for (int m = 0; m < CF::VA; ++m) v[m] = inA ? cmul(s[CF::posA(lane, m)], pv[m]) : make_float2(0.f, 0.f);
     CF::template forward<false>(v, lds, lane, tw);
 #pragma unroll
-    for (int r = 0; r < CF::VB; ++r)
-      v[r] = ((mbits >> r) & 1u) ? cscale(v[r], minv) : make_float2(0.f, 0.f);
+    for (int r = 0; r < CF::VB; ++r) v[r] = mk.apply(v[r], r);
     CF::template inverse<true>(v, lds, lane, tw);
     if (inA) {
 #pragma unroll
@@ -101,11 +123,8 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
 
   typename CF::Tw tw;
   CF::load_tw(tw, a.twt, lane);
-  uint32_t mbits = 0;
-  if (inB) {
-#pragma unroll
-    for (int r = 0; r < VB; ++r) mbits |= (a.maskw[CF::posB(lane, r)] != 0.f ? 1u : 0u) << r;
-  }
+  MaskLines<CF> mk;
+  mk.load(a.maskw, lane);
 
   const size_t base = ((size_t)kk * a.nx + col) * N;
   using MS = std::conditional_t<BF, MapsBf16, MapsF32>;
@@ -125,7 +144,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
 #pragma unroll
       for (int r = 0; r < VB; ++r) {
         const int kc = CF::posB(lane, r);
-        if ((mbits >> r) & 1u) {
+        if (mk.on(r)) {
           const uint32_t elem = (uint32_t)(((size_t)c * N + kc) * a.nx + col);
           const float2 n = draw_probe(arg_seed(a), arg_first(a) + kk, elem, 1u, 3);
           v[r] = cscale(n, ((kc + N / 2) & 1) ? -rs : rs);
@@ -205,7 +224,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
     }
 
     float2 qa[CF::VMAX];
-    normal_col<CF, MS>(pv, qa, a.lam, mcol, a.nc, mbits, lds, lane, tw);
+    normal_col<CF, MS>(pv, qa, a.lam, mcol, a.nc, mk, lds, lane, tw);
 
     double d1 = 0.0, d2 = 0.0, d3 = 0.0;
     if (inA) {

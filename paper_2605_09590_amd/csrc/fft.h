@@ -83,9 +83,30 @@ __device__ __forceinline__ float2 ctwiddle(float2 a) {
   }
 }
 
-// R-point DFT in registers; composite R by decimation in time, R = F * Q:
-// X[k1 + Q k2] = sum_{n1<F} W_F^{n1 k2} W_R^{n1 k1} Y_{n1}[k1],
-// Y_{n1} = DFT_Q(x[n1 + F n2]).
+// Split of a composite R for the in-register DFT: R = F * Q with F the
+// largest power of two dividing R when R is neither a power of two nor odd
+// (then gcd(F, Q) = 1), else the first of 4, 2, 3, 5 that divides R.
+constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
+constexpr int pow2_part(int r) { return (r & (r - 1)) == 0 ? r : ((r & 1) ? 1 : 2 * pow2_part(r / 2)); }
+constexpr int dft_split(int R) {
+  return (pow2_part(R) > 1 && pow2_part(R) < R) ? pow2_part(R)
+         : (R % 4 == 0) ? 4 : (R % 2 == 0) ? 2 : (R % 3 == 0) ? 3 : 5;
+}
+// k < F Q with k = k1 (mod F), k = k2 (mod Q), for coprime F and Q
+constexpr int crt_index(int k1, int k2, int F, int Q) {
+  int k = k2;
+  while (k % F != k1) k += Q;
+  return k;
+}
+
+// R-point DFT in registers.  Composite R = F * Q:
+//  - coprime F, Q (Good-Thomas prime-factor split): with n = (Q n1 + F n2)
+//    mod R, W_R^{n k} = W_F^{n1 k1} W_Q^{n2 k2} for k1 = k mod F, k2 = k mod Q,
+//    so X[k] = DFT_F over n1 of DFT_Q over n2, with no twiddles between the two
+//    stages; both index maps are compile-time register renamings;
+//  - otherwise decimation in time:
+//    X[k1 + Q k2] = sum_{n1<F} W_F^{n1 k2} W_R^{n1 k1} Y_{n1}[k1],
+//    Y_{n1} = DFT_Q(x[n1 + F n2]).
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2 (&a)[R]) {
   if constexpr (R == 1) {
@@ -97,8 +118,21 @@ __device__ __forceinline__ void dft(float2 (&a)[R]) {
     dft4<INV>(a[0], a[1], a[2], a[3]);
   } else if constexpr (R == 5) {
     dft5<INV>(a[0], a[1], a[2], a[3], a[4]);
+  } else if constexpr (gcd_i(dft_split(R), R / dft_split(R)) == 1) {
+    constexpr int F = dft_split(R), Q = R / F;
+    float2 y[F][Q];
+    static_for<0, F>([&](auto n1) {
+      static_for<0, Q>([&](auto n2) { y[n1][n2] = a[(Q * n1 + F * n2) % R]; });
+      dft<Q, INV>(y[n1]);
+    });
+    static_for<0, Q>([&](auto k2) {
+      float2 z[F];
+      static_for<0, F>([&](auto n1) { z[n1] = y[n1][k2]; });
+      dft<F, INV>(z);
+      static_for<0, F>([&](auto k1) { a[crt_index(k1, k2, F, Q)] = z[k1]; });
+    });
   } else {
-    constexpr int F = (R % 4 == 0) ? 4 : (R % 2 == 0) ? 2 : (R % 3 == 0) ? 3 : 5;
+    constexpr int F = dft_split(R);
     constexpr int Q = R / F;
     static_assert(F * Q == R, "radix must factor into 2, 3, 4, 5");
     float2 y[F][Q];
@@ -248,6 +282,7 @@ struct TwoStep {
   static constexpr int VMAX = (VA > LA ? VA : LA);
   static constexpr int STRIDE = LA + 1;            // padded LDS row
   static constexpr int SPAN = VA * STRIDE;
+  static constexpr bool kMaskInRegs = N >= 256;    // room for LA mask weights per lane
   static_assert(64 % L == 0 || L <= 64, "group must fit a wavefront");
   struct Tw { float2 w[VA]; };
 
@@ -321,6 +356,7 @@ template <class PL>
 struct StockhamCol {
   static constexpr int N = PL::N, L = PL::T, VA = PL::P, VB = PL::P, VMAX = PL::P;
   static constexpr int SPAN = lds_span<PL::N>();
+  static constexpr bool kMaskInRegs = false;
   struct Tw { float2 w[PL::NTW]; };
   __device__ static __forceinline__ int posA(int lane, int m) { return lane + L * m; }
   __device__ static __forceinline__ int posB(int lane, int r) { return lane + L * r; }
