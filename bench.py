@@ -880,15 +880,18 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     # single step first when the count is odd, then passes of four dual steps
     # while four remain, then pairs.  The first pass starts from zero, reads dz
     # and writes dr, dp (40 B per tangent and pixel); each later pass reads dz,
-    # dr, dp and writes dr, dp (72 B); the last pass of several steps writes no
-    # dr (16 B less).  The projection data (20 B per pixel and step) is shared
-    # by the tangents of a workgroup and not counted.
+    # dr, dp and writes dr, dp (72 B); the last pass of several steps writes
+    # no dual field and ends with the FISTA step: x read and written, y
+    # written (40 + 24 B; 8 + 24 B if it is also the first).  The gradient
+    # point z = y - (q - g) / s^2 before the prox: 3 fields read, 1 written
+    # (32 B).  The projection data (20 B per pixel and step) is shared by the
+    # tangents of a workgroup and not counted.
     inner, T = pr.extra["tv_inner"], pr.extra["fista_iters"]
     passes, it = [], 0
     if inner % 2:
         passes.append(1)
         it = 1
-    while inner - it >= 4 and min(pr.ny, pr.nx) >= 24:
+    while inner - it >= 4 and min(pr.ny, pr.nx) >= 25:
         passes.append(4)
         it += 4
     while it < inner:
@@ -896,8 +899,10 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
         it += 2
     pass_bytes = [40 if j == 0 else 72 for j in range(len(passes))]
     if passes[-1] > 1:
-        pass_bytes[-1] -= 16
-    tv_bytes = T * K * n * sum(pass_bytes)
+        pass_bytes[-1] += 24 - 32
+    else:
+        pass_bytes.append(48)                     # a single step alone: separate FISTA step
+    tv_bytes = T * K * n * (sum(pass_bytes) + 32)
     tv_s = prof["other"][0] / 1e3 / steps
     return {
         "workload": f"TV-CS {pr.ny}x{pr.nx}, {pr.nc} coils, Poisson-disc R=2 (24x24 calib), "

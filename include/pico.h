@@ -147,7 +147,7 @@ typedef struct {
    * (Beck and Teboulle 2009), from a zero dual start each FISTA iteration,
    * 1..1000.  The tangents keep the projection data of every step of the
    * primal: fista_iters * tv_inner_iters * ny * nx * 20 bytes of device
-   * memory. */
+   * memory.  Needs ny >= 14 and nx >= 38. */
   int32_t tv_inner_iters;
   /* pico_storage_t: precision of stored maps and streamed intermediates
    * (mixed precision; bfloat16 results agree with FP32 storage to about

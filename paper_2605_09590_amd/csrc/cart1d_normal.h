@@ -63,30 +63,79 @@ struct MaskLines {
   }
 };
 
+// Coil map columns of one image column, staged through LDS: the wavefront's
+// probe groups all work on the same image column, so its 64 lanes load each
+// coil's column once (N / 64 values per lane) into one of two LDS buffers,
+// the next coil's while the current one is transformed.  Plans whose
+// registers are full read the maps from global memory directly.
+template <class CF, class MS>
+struct MapCols {
+  static constexpr int N = CF::N;
+  static constexpr bool kLds = CF::kMapsInLds;
+  static constexpr int NPL = kLds ? (N + 63) / 64 : 1;   // values per wave lane
+  static constexpr int LDS = kLds ? 2 * N : 1;           // float2, two buffers
+  MS mcol;
+  float2* buf;
+  float2 pre[NPL];
+  __device__ __forceinline__ void fetch(int c) {   // global loads of coil c (kept in flight)
+    if constexpr (kLds) {
+      const MS s = mcol + (size_t)c * N;
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        const int i = (int)threadIdx.x + 64 * j;
+        if (N % 64 == 0 || i < N) pre[j] = s[i];
+      }
+    }
+  }
+  __device__ __forceinline__ void stash(int c) {   // coil c's values into its buffer
+    if constexpr (kLds) {
+      float2* b = buf + (c & 1) * N;
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        const int i = (int)threadIdx.x + 64 * j;
+        if (N % 64 == 0 || i < N) b[i] = pre[j];
+      }
+    }
+  }
+  __device__ __forceinline__ float2 at(int c, int y) const {
+    if constexpr (kLds) return buf[(c & 1) * N + y];
+    else return (mcol + (size_t)c * N)[y];
+  }
+};
+
 // q = (M + lam) p for one probe column held in layout A by the lanes of one
 // group: per coil, S' p -> FFT (layout A -> B) -> weight mask[k]/ny -> inverse
-// FFT (B -> A) -> accumulate conj(S') times the result.
+// FFT (B -> A) -> accumulate conj(S') times the result.  With the maps in LDS,
+// coil c + 1's column is loaded during coil c's forward transform and stored
+// between the two transforms: its buffer was last read by coil c - 1 (before
+// the forward transform's barriers), and the inverse transform's barriers
+// publish it before coil c + 1 reads it.
 template <class CF, class MS>
 __device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 (&qa)[CF::VMAX],
-                                           float lam, MS mcol, int nc,
+                                           float lam, MapCols<CF, MS>& mc, int nc,
                                            const MaskLines<CF>& mk, float2* lds, int lane,
                                            const typename CF::Tw& tw) {
-  constexpr int N = CF::N;
   const bool inA = CF::inA(lane);
 #pragma unroll
   for (int m = 0; m < CF::VA; ++m) qa[m] = cscale(pv[m], lam);
+  if constexpr (MapCols<CF, MS>::kLds) {
+    mc.fetch(0);
+    mc.stash(0);
+    __syncthreads();
+  }
   for (int c = 0; c < nc; ++c) {
-    const MS s = mcol + (size_t)c * N;
+    if (c + 1 < nc) mc.fetch(c + 1);
     float2 v[CF::VMAX];
 #pragma unroll
-    for (int m = 0; m < CF::VA; ++m) v[m] = inA ? cmul(s[CF::posA(lane, m)], pv[m]) : make_float2(0.f, 0.f);
+    for (int m = 0; m < CF::VA; ++m) v[m] = inA ? cmul(mc.at(c, CF::posA(lane, m)), pv[m]) : make_float2(0.f, 0.f);
     CF::template forward<false>(v, lds, lane, tw);
 #pragma unroll
     for (int r = 0; r < CF::VB; ++r) v[r] = mk.apply(v[r], r);
+    if (c + 1 < nc) mc.stash(c + 1);
     CF::template inverse<true>(v, lds, lane, tw);
     if (inA) {
 #pragma unroll
-      for (int m = 0; m < CF::VA; ++m) qa[m] = cadd(qa[m], cmulc(s[CF::posA(lane, m)], v[m]));
+      for (int m = 0; m < CF::VA; ++m) qa[m] = cadd(qa[m], cmulc(mc.at(c, CF::posA(lane, m)), v[m]));
     }
   }
 }
@@ -110,7 +159,9 @@ template <class CF, int MODE, bool BF>
 __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
   constexpr int N = CF::N, L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
   constexpr int VA = CF::VA, VB = CF::VB;
+  using MS = std::conditional_t<BF, MapsBf16, MapsF32>;
   __shared__ float2 lds_all[NG * CF::SPAN];
+  __shared__ float2 lds_maps[MapCols<CF, MS>::LDS];
   __shared__ double red[64 + L];   // lane 0 of a partial last group reads L entries
   const int g = threadIdx.x / L;
   const int lane = threadIdx.x % L;
@@ -127,7 +178,6 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
   mk.load(a.maskw, lane);
 
   const size_t base = ((size_t)kk * a.nx + col) * N;
-  using MS = std::conditional_t<BF, MapsBf16, MapsF32>;
   const MS mcol = MS::of(a) + (size_t)col * a.nc * N;
   float2 pv[CF::VMAX];
   double d0 = 0.0;
@@ -224,7 +274,10 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
     }
 
     float2 qa[CF::VMAX];
-    normal_col<CF, MS>(pv, qa, a.lam, mcol, a.nc, mk, lds, lane, tw);
+    MapCols<CF, MS> mc;
+    mc.mcol = mcol;
+    mc.buf = lds_maps;
+    normal_col<CF, MS>(pv, qa, a.lam, mc, a.nc, mk, lds, lane, tw);
 
     double d1 = 0.0, d2 = 0.0, d3 = 0.0;
     if (inA) {

@@ -283,6 +283,7 @@ struct TwoStep {
   static constexpr int STRIDE = LA + 1;            // padded LDS row
   static constexpr int SPAN = VA * STRIDE;
   static constexpr bool kMaskInRegs = N >= 256;    // room for LA mask weights per lane
+  static constexpr bool kMapsInLds = N >= 256;     // and for N / 64 staged map values
   static_assert(64 % L == 0 || L <= 64, "group must fit a wavefront");
   struct Tw { float2 w[VA]; };
 
@@ -357,6 +358,7 @@ struct StockhamCol {
   static constexpr int N = PL::N, L = PL::T, VA = PL::P, VB = PL::P, VMAX = PL::P;
   static constexpr int SPAN = lds_span<PL::N>();
   static constexpr bool kMaskInRegs = false;
+  static constexpr bool kMapsInLds = false;
   struct Tw { float2 w[PL::NTW]; };
   __device__ static __forceinline__ int posA(int lane, int m) { return lane + L * m; }
   __device__ static __forceinline__ int posB(int lane, int r) { return lane + L * r; }

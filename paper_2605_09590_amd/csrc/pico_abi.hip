@@ -551,13 +551,9 @@ hipError_t fista_tangent(pico_op_t op, int K, hipStream_t s) {
         // TV prox tangent at the stored projection data of iteration k
         if (op->cs_lam == 0.0) return pico::launch_momentum(op->wA, op->x, op->p, K * n, op->theta[k - 1], s);
         const size_t off = (size_t)(k - 1) * op->tv_inner * n;
-        float2* dp = nullptr;
-        if ((e2 = pico::tv_tangent_prox(op->wA, op->tv_drA, op->tv_drB, op->tv_dp, op->tv_dpB, op->tv_what + off,
-                                        op->tv_invn + off, op->ny, op->nx, K, op->tv_inner, op->tv_th.data(),
-                                        (float)op->cs_lam, &dp, s)) != hipSuccess)
-          return e2;
-        return pico::tv_tangent_final(op->wA, dp, op->x, op->p, op->ny, op->nx, K, (float)op->cs_lam,
-                                      op->theta[k - 1], s);
+        return pico::tv_tangent_step(op->wA, op->tv_drA, op->tv_drB, op->tv_dp, op->tv_dpB, op->tv_what + off,
+                                     op->tv_invn + off, op->ny, op->nx, K, op->tv_inner, op->tv_th.data(),
+                                     (float)op->cs_lam, op->x, op->p, (float)op->theta[k - 1], s);
       }
       // xd = Psi^H D_k(Psi zd): zd formed inside the analysis, coefficients in wB
       // (wA scratch), the synthesis applying the momentum into (x, p) directly
@@ -741,6 +737,8 @@ pico_status_t validate(const pico_op_desc_t* d) {
       if (d->ny % m || d->nx % m) return fail(PICO_EINVAL, "ny and nx must be divisible by 2^wavelet_levels");
     } else if (d->tv_inner_iters < 1 || d->tv_inner_iters > 1000) {
       return fail(PICO_EINVAL, "tv_inner_iters must be in 1..1000");
+    } else if (d->ny < 14 || d->nx < 38) {
+      return fail(PICO_EINVAL, "TV needs ny >= 14 and nx >= 38 (the tangent's tile halos)");
     }
     if (d->power_iters < 1 || !(d->power_margin > 0.0)) return fail(PICO_EINVAL, "compressed sensing needs power_iters >= 1 and power_margin > 0");
   }

@@ -209,15 +209,14 @@ hipError_t launch_to_f32(const double2* a, float2* b, long n, hipStream_t s);
 // TV prox of B FP64 images in place (o.tv_* workspace); what / invn: the
 // projection data of its o.tv_inner steps ([tv_inner][ny][nx]) or NULL
 hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what, float* invn, hipStream_t s);
-// tangent of the TV prox for K FP32 images: inner fused steps on dz (kept)
-// with the ping-pong pairs drA / drB and dpA / dpB ([K][2][n] each); the
-// dual tangent of the last step is left in *dp_out (dpA or dpB)
-hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
+// tangent of one TV FISTA step for K FP32 images: the prox's inner steps on
+// dz (kept), fused several per pass, with the ping-pong pairs drA / drB and
+// dpA / dpB ([K][2][n] each), the last pass also forming the prox output
+// dx = dz - lam D^H dp and the FISTA momentum yo = dx + theta (dx - xo),
+// xo = dx.  Needs ny >= 13 and nx >= 37.
+hipError_t tv_tangent_step(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
                            const float4* what, const float* invn, int ny, int nx, int K, int inner,
-                           const float* th, float lam, float2** dp_out, hipStream_t s);
-// dx = dz - lam D^H dp, then the FISTA momentum: yo = dx + theta (dx - xo), xo = dx
-hipError_t tv_tangent_final(const float2* dz, const float2* dp, float2* xo, float2* yo, int ny, int nx, int K,
-                            float lam, float theta, hipStream_t s);
+                           const float* th, float lam, float2* xo, float2* yo, float theta, hipStream_t s);
 
 // Kaiser-Bessel gridding NUFFT (non-Cartesian data path)
 // Kaiser-Bessel gridding tables: samples sorted into square bins of

@@ -244,22 +244,29 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
 
 // S tangent inner steps i .. i+S-1 in one pass over a TY x TX tile T
 // (S = 2 on 8 x 32 tiles, S = 4 on 16 x 16).  The LDS box B is T grown by S on
-// every side, index [a][b] = pixel (y0 - S + a, x0 - S + b), periodic.  Step
-// s (from 0) updates r and p on R_s = rows [s+1, BY-2-s] x cols [s+1, BX-2-s]
-// from u_s = dz - lam D^H r_s on U_s = R_s grown by one towards +y / +x; u_s
-// reads r on R_{s-1} (the whole box for s = 0), so R_{S-1} = T:
+// every side (FIN: by S + 1 above and left), index [a][b] = pixel
+// (y0 - S - E + a, x0 - S - E + b), periodic, E = FIN.  Step s (from 0)
+// updates r and p on R_s = rows [s+1, BY-2-s] x cols [s+1, BX-2-s] from
+// u_s = dz - lam D^H r_s on U_s = R_s grown by one towards +y / +x; u_s reads
+// r on R_{s-1} (the whole box for s = 0), so R_{S-1} = T (FIN: T with the row
+// above and the column left of it):
 //   w = r_s + c8 D u_s,  p_{s+1} = dP_s(w),  r_{s+1} = p_{s+1} + th_s (p_{s+1} - p_s).
-// Inputs: r_i on B, p_i on R_0, dz on U_0; the projection data of steps
-// s < S-1 on R_s (LDS, shared by the block's tangents), of the last step at
-// the thread's own pixel.  r and p are read from (rA, pA) and the last step's
-// written to (rB, pB): neighbouring tiles read the halo of both.  first: r_i =
-// p_i = 0 (step 0 from the zero start).  Tangent k + 1's box is loaded into
-// registers while tangent k's steps run.  Needs ny >= TY + 2S and nx >= TX + 2S
-// (the halo wraps at most once).
-template <int S, int TY, int TX>
+// Inputs: r_i on B, p_i on R_0, dz on U_0; the projection data of the steps
+// on their regions in LDS (shared by the block's tangents; without FIN the
+// last step's only at the thread's own pixel).  r and p are read from
+// (rA, pA) and, without FIN, the last step's written to (rB, pB): neighbouring
+// tiles read the halo of both; last: the prox's last pass, only p is read
+// afterwards.  FIN (the prox's last pass, fused with the FISTA step): nothing
+// is written to the dual fields; each own pixel forms the prox output
+// dx = dz - lam D^H p from the box, then y = dx + theta (dx - xo), xo = dx.
+// first: r_i = p_i = 0 (step 0 from the zero start).  Tangent k + 1's box is
+// loaded into registers while tangent k's steps run.  Needs ny >= TY + 2S + E
+// and nx >= TX + 2S + E (the halo wraps at most once).
+template <int S, int TY, int TX, int E>
 struct TvSteps {
-  static constexpr int BY = TY + 2 * S, BX = TX + 2 * S, NB = BY * BX;
+  static constexpr int BY = TY + 2 * S + E, BX = TX + 2 * S + E, NB = BY * BX;
   static constexpr int NPT = (NB + 255) / 256;   // box points per thread
+  static constexpr int NPS = S - 1 + E;           // steps with projection data in LDS
   __host__ __device__ static constexpr int ry(int s) { return BY - 2 - 2 * s; }   // R_s rows
   __host__ __device__ static constexpr int rx(int s) { return BX - 2 - 2 * s; }   // R_s cols
   __host__ __device__ static constexpr int proj_off(int s) {
@@ -267,27 +274,29 @@ struct TvSteps {
     for (int q = 0; q < s; ++q) o += ry(q) * rx(q);
     return o;
   }
-  static constexpr int NPROJ = proj_off(S - 1) > 0 ? proj_off(S - 1) : 1;   // steps 0 .. S-2
+  static constexpr int NPROJ = proj_off(NPS) > 0 ? proj_off(NPS) : 1;
 };
 
 struct TvTheta {
   float th[4];
 };
 
-template <int S, int TY, int TX>
+template <int S, int TY, int TX, bool FIN>
 __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz, const float2* __restrict__ rA,
                                                   float2* __restrict__ rB, const float2* __restrict__ pA,
                                                   float2* __restrict__ pB, const float4* __restrict__ what,
                                                   const float* __restrict__ invn, int ny, int nx, int K, int kper,
-                                                  float lam, float c8, TvTheta th, int first, int last) {
-  using C = TvSteps<S, TY, TX>;
+                                                  float lam, float c8, TvTheta th, int first, int last,
+                                                  float2* __restrict__ xo, float2* __restrict__ yo, float theta) {
+  constexpr int E = FIN ? 1 : 0;
+  using C = TvSteps<S, TY, TX, E>;
   constexpr int BY = C::BY, BX = C::BX, NB = C::NB, NPT = C::NPT;
   static_assert(TY * TX == 256, "one output pixel per thread");
   __shared__ float2 sRy[BY][BX], sRx[BY][BX];   // r_s (in place)
   __shared__ float2 sPy[BY][BX], sPx[BY][BX];   // p_s (in place)
   __shared__ float2 sZ[BY][BX];                 // dz
   __shared__ float2 sU[BY][BX];                 // u_s
-  __shared__ float4 sW[C::NPROJ];               // projection data of steps 0 .. S-2 on R_s (w^)
+  __shared__ float4 sW[C::NPROJ];               // projection data of the steps in LDS on R_s (w^)
   __shared__ float sV[C::NPROJ];                // and 1/|w|
   const long n = (long)ny * nx;
   const int tilesx = (nx + TX - 1) / TX, tiles = tilesx * ((ny + TY - 1) / TY);
@@ -297,10 +306,9 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
   const int y0 = (tile / tilesx) * TY, x0 = (tile % tilesx) * TX;
   const int t = threadIdx.x;
   const bool fst = first != 0;
-  auto gidx = [&](int a, int b) { return (long)wrap(y0 - S + a, ny) * nx + wrap(x0 - S + b, nx); };
-  // projection data of steps 0 .. S-2 on their regions (step s at what + s n)
+  auto gidx = [&](int a, int b) { return (long)wrap(y0 - S - E + a, ny) * nx + wrap(x0 - S - E + b, nx); };
 #pragma unroll
-  for (int s = 0; s < S - 1; ++s) {
+  for (int s = 0; s < C::NPS; ++s) {
     const int RY = C::ry(s), RX = C::rx(s), off = C::proj_off(s);
     for (int e = t; e < RY * RX; e += 256) {
       const int a = s + 1 + e / RX, b = s + 1 + e % RX;
@@ -309,14 +317,15 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
       sV[off + e] = invn[(size_t)s * n + g];
     }
   }
-  // own pixel: the last step's projection data
+  // own pixel (box [S + E + ty][S + E + tx]); without FIN the last step's
+  // projection data
   const int ty = t / TX, tx = t % TX;
   const int y = y0 + ty, x = x0 + tx;
   const bool own = y < ny && x < nx;
   const long i = (long)y * nx + x;
   float4 whl = make_float4(0.f, 0.f, 0.f, 0.f);
   float ivl = 1.f;
-  if (own) {
+  if (!FIN && own) {
     whl = what[(size_t)(S - 1) * n + i];
     ivl = invn[(size_t)(S - 1) * n + i];
   }
@@ -390,16 +399,19 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
         }
       }
       __syncthreads();
-      if (s < S - 1) {   // step s on R_s; r and p replaced in place (each point reads only itself)
+      if (s < C::NPS) {   // step s on R_s; r and p replaced in place (each point reads only itself)
         const int RY = C::ry(s), RX = C::rx(s), off = C::proj_off(s);
         const float ths = th.th[s];
+        const bool need_r = s < S - 1;   // FIN's last step: only p is read afterwards
         for (int e = t; e < RY * RX; e += 256) {
           const int a = s + 1 + e / RX, b = s + 1 + e % RX;
           float2 qy, qx;
           proj_at(a, b, sW[off + e], sV[off + e], qy, qx);
-          const float2 oy = sPy[a][b], ox = sPx[a][b];
-          sRy[a][b] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
-          sRx[a][b] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
+          if (need_r) {
+            const float2 oy = sPy[a][b], ox = sPx[a][b];
+            sRy[a][b] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
+            sRx[a][b] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
+          }
           sPy[a][b] = qy;
           sPx[a][b] = qx;
         }
@@ -419,6 +431,19 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
         pb[n + i] = qx;
       }
       __syncthreads();
+    }
+    if constexpr (FIN) {
+      if (own) {   // prox output and FISTA step at the own pixel
+        const int a = S + E + ty, b = S + E + tx;
+        const float hx = sPy[a - 1][b].x - sPy[a][b].x + sPx[a][b - 1].x - sPx[a][b].x;
+        const float hy = sPy[a - 1][b].y - sPy[a][b].y + sPx[a][b - 1].y - sPx[a][b].y;
+        const float2 dxv = make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
+        const size_t o = (size_t)k * n + i;
+        const float2 xp = xo[o];
+        yo[o] = make_float2(fmaf(theta, dxv.x - xp.x, dxv.x), fmaf(theta, dxv.y - xp.y, dxv.y));
+        xo[o] = dxv;
+      }
+      __syncthreads();   // the next tangent's box overwrites sP and sZ
     }
   }
 }
@@ -463,24 +488,24 @@ hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what,
   return hipGetLastError();
 }
 
-template <int S, int TY, int TX>
+template <int S, int TY, int TX, bool FIN>
 static void launch_tv_steps(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB, const float4* what,
                             const float* invn, const float* th, int ny, int nx, int K, float lam, float c8, int first,
-                            int last, hipStream_t s) {
+                            int last, float2* xo, float2* yo, float theta, hipStream_t s) {
   const int tiles = ((ny + TY - 1) / TY) * ((nx + TX - 1) / TX);
   int kper = 8;
   while (kper > 1 && (long)tiles * ((K + kper - 1) / kper) < 2048) kper >>= 1;
   const dim3 grid = xcd_grid((long)tiles * ((K + kper - 1) / kper));
   TvTheta tt{};
   for (int q = 0; q < S; ++q) tt.th[q] = th[q];
-  hipLaunchKernelGGL((k_tv_steps<S, TY, TX>), grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what, invn, ny, nx, K,
-                     kper, lam, c8, tt, first, last);
+  hipLaunchKernelGGL((k_tv_steps<S, TY, TX, FIN>), grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what, invn, ny, nx,
+                     K, kper, lam, c8, tt, first, last, xo, yo, theta);
 }
 
-hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
+hipError_t tv_tangent_step(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
                            const float4* what, const float* invn, int ny, int nx, int K, int inner,
-                           const float* th, float lam, float2** dp_out, hipStream_t s) {
-  if (ny < kTY + 4 || nx < kTX + 4) return hipErrorInvalidValue;
+                           const float* th, float lam, float2* xo, float2* yo, float theta, hipStream_t s) {
+  if (ny < kTY + 5 || nx < kTX + 5) return hipErrorInvalidValue;
   const long n = (long)ny * nx;
   const int tiles = ((ny + kTY - 1) / kTY) * ((nx + kTX - 1) / kTX);
   int kper = 8;
@@ -494,27 +519,33 @@ hipError_t tv_tangent_prox(const float2* dz, float2* drA, float2* drB, float2* d
     std::swap(drA, drB);
     it = 1;
   }
-  // four steps per pass while four remain (16 x 16 tiles, halo 4), then pairs
-  const bool four = ny >= 16 + 8 && nx >= 16 + 8;
+  // four steps per pass while four remain (16 x 16 tiles, halo 4, the last
+  // pass 5 above and left), then pairs; the last pass ends with the FISTA step
+  const bool four = ny >= 16 + 9 && nx >= 16 + 9;
   for (; four && inner - it >= 4; it += 4) {
-    launch_tv_steps<4, 16, 16>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it, ny, nx,
-                               K, lam, c8, it == 0 ? 1 : 0, it + 4 == inner ? 1 : 0, s);
+    const int fst = it == 0 ? 1 : 0;
+    if (it + 4 == inner)
+      launch_tv_steps<4, 16, 16, true>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it,
+                                       ny, nx, K, lam, c8, fst, 1, xo, yo, theta, s);
+    else
+      launch_tv_steps<4, 16, 16, false>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n,
+                                        th + it, ny, nx, K, lam, c8, fst, 0, nullptr, nullptr, 0.f, s);
     std::swap(drA, drB);
     std::swap(dpA, dpB);
   }
   for (; it < inner; it += 2) {
-    launch_tv_steps<2, kTY, kTX>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it, ny,
-                                 nx, K, lam, c8, it == 0 ? 1 : 0, it + 2 >= inner ? 1 : 0, s);
+    const int fst = it == 0 ? 1 : 0;
+    if (it + 2 >= inner)
+      launch_tv_steps<2, kTY, kTX, true>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n,
+                                         th + it, ny, nx, K, lam, c8, fst, 1, xo, yo, theta, s);
+    else
+      launch_tv_steps<2, kTY, kTX, false>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n,
+                                          th + it, ny, nx, K, lam, c8, fst, 0, nullptr, nullptr, 0.f, s);
     std::swap(drA, drB);
     std::swap(dpA, dpB);
   }
-  *dp_out = dpA;
-  return hipGetLastError();
-}
-
-hipError_t tv_tangent_final(const float2* dz, const float2* dp, float2* xo, float2* yo, int ny, int nx, int K,
-                            float lam, float theta, hipStream_t s) {
-  hipLaunchKernelGGL(k_tv_final, grid_img((long)ny * nx, K), dim3(256), 0, s, dz, dp, xo, yo, ny, nx, lam, theta);
+  if (inner == 1)   // the single step alone: the FISTA step as its own pass
+    hipLaunchKernelGGL(k_tv_final, grid_img(n, K), dim3(256), 0, s, dz, dpA, xo, yo, ny, nx, lam, theta);
   return hipGetLastError();
 }
 

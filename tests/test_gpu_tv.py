@@ -69,10 +69,10 @@ def _init_tv(lib, maps, psi, mask, braw, lam, T, inner, tile):
                          cs_lambda=lam, tv_inner_iters=inner, probe_tile=tile)
 
 
-@pytest.mark.parametrize("inner", [10, 7])
+@pytest.mark.parametrize("inner", [10, 7, 8])
 def test_tv_recon_jvp_and_noise_map_parity(lib, inner):
     say(f"case: TV-CS 64x96, 4 coils, Poisson-disc R=2 (8x8 calib), lam 1e-2, "
-        f"FISTA 30, {inner} inner steps (two-step kernels{', one single step first' if inner % 2 else ''}); "
+        f"FISTA 30, {inner} inner steps (multi-step passes{', one single step first' if inner % 2 else ''}, the last fused with the FISTA step); "
         f"3 JVPs, noise map of 6 probes in tiles 4+2")
     maps, psi, mask, op, bw, braw = _setup(64, 96, 4, 2.0, 8, seed=3)
     lam, T = 1e-2, 30
