@@ -118,8 +118,7 @@ __device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 
   const bool inA = CF::inA(lane);
 #pragma unroll
   for (int m = 0; m < CF::VA; ++m) qa[m] = cscale(pv[m], lam);
-  if constexpr (MapCols<CF, MS>::kLds) {
-    mc.fetch(0);
+  if constexpr (MapCols<CF, MS>::kLds) {   // coil 0's loads were issued by the caller
     mc.stash(0);
     __syncthreads();
   }
@@ -140,16 +139,18 @@ __device__ __forceinline__ void normal_col(const float2 (&pv)[CF::VMAX], float2 
   }
 }
 
-// Sum of one double per lane over each lane group of L lanes, in lane order
-// (bitwise reproducible); the result is valid in the group's first lane.
-template <int L>
-__device__ __forceinline__ double group_reduce(double v, double* red, int lane) {
-  red[threadIdx.x] = v;
+// Sums of J doubles per lane over each lane group of L lanes, each in lane
+// order (bitwise reproducible): lane j < J of the group returns sum j.  red
+// holds (64 + L) J doubles (a partial last group reads past the wavefront).
+template <int L, int J>
+__device__ __forceinline__ double group_reduce(const double (&v)[J], double* red, int lane) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) red[threadIdx.x * J + j] = v[j];
   __syncthreads();
   double s = 0.0;
-  if (lane == 0) {
-    const int base = threadIdx.x;
-    for (int i = 0; i < L; ++i) s += red[base + i];
+  if (lane < J) {
+    const int base = (threadIdx.x - lane) * J + lane;
+    for (int i = 0; i < L; ++i) s += red[base + i * J];
   }
   __syncthreads();
   return s;
@@ -162,7 +163,9 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
   using MS = std::conditional_t<BF, MapsBf16, MapsF32>;
   __shared__ float2 lds_all[NG * CF::SPAN];
   __shared__ float2 lds_maps[MapCols<CF, MS>::LDS];
-  __shared__ double red[64 + L];   // lane 0 of a partial last group reads L entries
+  // the partial-dot reduction reuses the transform's LDS once it is done
+  static_assert(NG * CF::SPAN * sizeof(float2) >= (64 + L) * 4 * sizeof(double), "reduction space");
+  double* red = reinterpret_cast<double*>(lds_all);
   const int g = threadIdx.x / L;
   const int lane = threadIdx.x % L;
   const int col = blockIdx.y;
@@ -216,10 +219,16 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
         d0 += (double)pv[m].x * pv[m].x + (double)pv[m].y * pv[m].y;
       }
     }
-    d0 = group_reduce<L>(d0, red, lane);
+    const double dd[1] = {d0};
+    d0 = group_reduce<L, 1>(dd, red, lane);
     if (active && lane == 0) a.part[((size_t)k * a.nx + col) * 4] = d0;
     return;
   } else {
+    // coil 0's map column is loaded while the CG vectors are
+    MapCols<CF, MS> mc;
+    mc.mcol = mcol;
+    mc.buf = lds_maps;
+    mc.fetch(0);
     // rv keeps r_i for the d3 = Re(r^H q) partial; pv = p_i enters the normal operator
     float2 rv[CF::VMAX];
     if (inA) {
@@ -274,9 +283,6 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
     }
 
     float2 qa[CF::VMAX];
-    MapCols<CF, MS> mc;
-    mc.mcol = mcol;
-    mc.buf = lds_maps;
     normal_col<CF, MS>(pv, qa, a.lam, mc, a.nc, mk, lds, lane, tw);
 
     double d1 = 0.0, d2 = 0.0, d3 = 0.0;
@@ -290,17 +296,9 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
         d3 += (double)rv[m].x * qa[m].x + (double)rv[m].y * qa[m].y;
       }
     }
-    d0 = group_reduce<L>(d0, red, lane);
-    d1 = group_reduce<L>(d1, red, lane);
-    d2 = group_reduce<L>(d2, red, lane);
-    d3 = group_reduce<L>(d3, red, lane);
-    if (active && lane == 0) {
-      double* pp = a.part + ((size_t)k * a.nx + col) * 4;
-      pp[0] = d0;
-      pp[1] = d1;
-      pp[2] = d2;
-      pp[3] = d3;
-    }
+    const double dd[4] = {d0, d1, d2, d3};
+    const double sj = group_reduce<L, 4>(dd, red, lane);
+    if (active && lane < 4) a.part[((size_t)k * a.nx + col) * 4 + lane] = sj;
   }
 }
 
