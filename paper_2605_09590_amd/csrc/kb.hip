@@ -264,40 +264,69 @@ __global__ __launch_bounds__(64) void k_kb_tile_spread(KbOp o, const float2* __r
   gout[(size_t)k * G2 + (size_t)(y0 + py) * o.Gx + x0 + px] = acc;
 }
 
-// P^H P by its stencil, one 16 x 16 tile (slot blockIdx.x of the tile list)
-// and a run of kc probes (from blockIdx.y * kc) per workgroup
+// P^H P by its stencil, one 16 x 16 tile (a slot of the tile list) and a run
+// of kc probes per workgroup.  Work items (probe run, slot), slots fastest,
+// go to the eight XCDs in contiguous runs (workgroup b on XCD b mod 8 takes
+// item (b mod 8) * ceil(total / 8) + b / 8), so tiles that share window
+// halos meet in one L2; the padding workgroups return at once.
 template <int W>
 __global__ __launch_bounds__(256) void k_kb_stencil(KbOp o, const float2* __restrict__ gin, float2* __restrict__ gout,
-                                                    int K, int kc) {
+                                                    int K, int kc, int slots) {
   constexpr int T = kKbStencilTile, D = 2 * W - 1, WIN = T + D - 1;
   static_assert(T * T == 256, "one output point per thread");
   __shared__ float2 win[WIN * WIN];
-  const int slot = blockIdx.x, tile = o.tile_list[slot], ntx = o.Gx / T;
+  const long total = (long)slots * ((K + kc - 1) / kc), per = (total + 7) / 8;
+  const long item = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (item >= total) return;
+  const int slot = (int)(item % slots), tile = o.tile_list[slot], ntx = o.Gx / T;
   const int y0 = (tile / ntx) * T, x0 = (tile % ntx) * T, wy0 = y0 - (W - 1), wx0 = x0 - (W - 1);
   const int py = threadIdx.x / T, px = threadIdx.x % T;
-  const int k0 = blockIdx.y * kc, k1 = min(K, k0 + kc);
+  const int k0 = (int)(item / slots) * kc, k1 = min(K, k0 + kc);
   const long G2 = (long)o.Gy * o.Gx;
   float2* outp = gout + (size_t)(y0 + py) * o.Gx + x0 + px;
   if (slot >= o.n_active) {   // no sample reaches this tile
     for (int k = k0; k < k1; ++k) outp[(size_t)k * G2] = make_float2(0.f, 0.f);
     return;
   }
+  // window points of this thread (NW per thread), and the next probe's values
+  // loaded while the current probe is computed (W <= 6: at W = 8 the 225
+  // stencil weights leave no registers for them)
+  constexpr int NW = (WIN * WIN + 255) / 256;
+  constexpr bool PF = W <= 6;
+  auto goff = [&](int i) {
+    int gy = wy0 + i / WIN, gx = wx0 + i % WIN;   // the window spans less than one period
+    gy += gy < 0 ? o.Gy : 0;
+    gy -= gy >= o.Gy ? o.Gy : 0;
+    gx += gx < 0 ? o.Gx : 0;
+    gx -= gx >= o.Gx ? o.Gx : 0;
+    return (long)gy * o.Gx + gx;
+  };
+  float2 nxt[NW];
+  auto load_win = [&](int k) {
+    const float2* gk = gin + (size_t)k * G2;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      if (i < WIN * WIN) nxt[j] = gk[goff(i)];
+    }
+  };
+  if (PF && k0 < k1) load_win(k0);
   float st[D * D];
   const float* sp = o.stencil + (size_t)slot * D * D * T * T + threadIdx.x;
 #pragma unroll
   for (int i = 0; i < D * D; ++i) st[i] = sp[(size_t)i * T * T];
   for (int k = k0; k < k1; ++k) {
-    const float2* gk = gin + (size_t)k * G2;
     __syncthreads();   // every thread is done with the previous window
-    for (int i = threadIdx.x; i < WIN * WIN; i += 256) {
-      int gy = wy0 + i / WIN, gx = wx0 + i % WIN;   // the window spans less than one period
-      gy += gy < 0 ? o.Gy : 0;
-      gy -= gy >= o.Gy ? o.Gy : 0;
-      gx += gx < 0 ? o.Gx : 0;
-      gx -= gx >= o.Gx ? o.Gx : 0;
-      win[i] = gk[(size_t)gy * o.Gx + gx];
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 0; j < NW; ++j)
+        if (threadIdx.x + 256 * j < WIN * WIN) win[threadIdx.x + 256 * j] = nxt[j];
+    } else {
+      const float2* gk = gin + (size_t)k * G2;
+      for (int i = threadIdx.x; i < WIN * WIN; i += 256) win[i] = gk[goff(i)];
     }
     __syncthreads();
+    if (PF && k + 1 < k1) load_win(k + 1);
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int dy = 0; dy < D; ++dy)
@@ -381,15 +410,20 @@ static hipError_t tile_spread(const KbOp& o, int K, const float2* src, long bstr
   return hipGetLastError();
 }
 
+// Probes per workgroup: a workgroup loads its tile's (2W-1)^2 stencil weights
+// once (124 KB at W = 6) for its run of probes, so runs grow from 16 while
+// the active tiles still give at least 2048 workgroups.
 static hipError_t stencil(const KbOp& o, int K, const float2* gin, float2* gout, hipStream_t s) {
-  constexpr int kc = 16;
   const int slots = (o.Gy / kKbStencilTile) * (o.Gx / kKbStencilTile);
-  const dim3 grid((unsigned)slots, (unsigned)((K + kc - 1) / kc)), block(256);
+  int kc = 16;
+  while (kc < 128 && (long)std::max(o.n_active, 1) * ((K + 2 * kc - 1) / (2 * kc)) >= 2048) kc *= 2;
+  const long total = (long)slots * ((K + kc - 1) / kc);
+  const dim3 grid((unsigned)(8 * ((total + 7) / 8))), block(256);
   switch (o.W) {
-    case 2: hipLaunchKernelGGL(k_kb_stencil<2>, grid, block, 0, s, o, gin, gout, K, kc); break;
-    case 4: hipLaunchKernelGGL(k_kb_stencil<4>, grid, block, 0, s, o, gin, gout, K, kc); break;
-    case 6: hipLaunchKernelGGL(k_kb_stencil<6>, grid, block, 0, s, o, gin, gout, K, kc); break;
-    case 8: hipLaunchKernelGGL(k_kb_stencil<8>, grid, block, 0, s, o, gin, gout, K, kc); break;
+    case 2: hipLaunchKernelGGL(k_kb_stencil<2>, grid, block, 0, s, o, gin, gout, K, kc, slots); break;
+    case 4: hipLaunchKernelGGL(k_kb_stencil<4>, grid, block, 0, s, o, gin, gout, K, kc, slots); break;
+    case 6: hipLaunchKernelGGL(k_kb_stencil<6>, grid, block, 0, s, o, gin, gout, K, kc, slots); break;
+    case 8: hipLaunchKernelGGL(k_kb_stencil<8>, grid, block, 0, s, o, gin, gout, K, kc, slots); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
