@@ -185,7 +185,7 @@ def _lat_stats(np, info):
             "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2)}
 
 
-def serve_leg(lib, workloads, torch, np, dev, n_req=24, rhos=(0.5, 0.9, 1.2), n_ops=10):
+def serve_leg(lib, workloads, torch, np, dev, n_req=24, rhos=(0.5, 0.7, 0.9, 1.2), n_ops=10):
     """Serving mix over the stated ranges (matrix 128-384, coils 8-32, probes
     64-512; Cartesian / spiral / CS): a pool of distinct operators, tile shapes
     from the autotuner, graph replay, resident operators.  Cold pass (every
@@ -1135,7 +1135,7 @@ def main():
     ap.add_argument("--cs-tv-steps", type=int, default=1,
                     help="steps of the TV compressed-sensing JVP leg (0 to skip)")
     ap.add_argument("--serve", choices=["off", "short", "full"], default="short",
-                    help="serving leg: 24 requests at 3 rates (default), 100 at 6 rates, or off")
+                    help="serving leg: 24 requests at 4 rates (default), 100 at 6 rates, or off")
     ap.add_argument("--cs-robustness", choices=["off", "l1wav", "tv"], default="off",
                     help="also run the CS noise-level sweep (PICO vs PMR std maps) for that model")
     ap.add_argument("--robust-n", type=int, default=3000,
