@@ -152,10 +152,12 @@ def test_spiral_toeplitz_nonsquare_grid(lib):
         assert err < TOL
 
 
-def test_spiral_full_size_sampled_probes(lib):
-    say("case: spiral 256x256, 16 coils, 48x4096 R=2 (98304 samples), lambda 0.1, CG 30, "
-        "K=256 right-hand sides in one launch; probes 0, 137, 255 checked")
-    prob = workloads.config(3, seed=0)
+@pytest.mark.parametrize("R", [2, 3, 4])
+def test_spiral_full_size_sampled_probes(lib, R):
+    checked = (0, 137, 255) if R == 2 else (255,)
+    say(f"case: spiral 256x256, 16 coils, 48x4096 R={R} ({98304 * 2 // R} samples), lambda 0.1, CG 30, "
+        f"K=256 right-hand sides in one launch; probes {checked} checked, every probe by property")
+    prob = workloads.config(3, seed=0, R=R)
     traj = prob.traj.astype(np.float32)
     h = _init_noncart(lib, prob.maps, prob.psi, traj, prob.lam, prob.cg_iters, 256)
     v = np.stack([opico.probe_image(42, i, (256, 256)) for i in range(256)]).astype(np.complex64)
@@ -169,7 +171,7 @@ def test_spiral_full_size_sampled_probes(lib):
     op = onufft.NonCartOp(prob.maps, prob.psi, traj.astype(np.float64))
     cov = opico.Covariance(op, prob.lam, prob.cg_iters)
     say(f"  lambda_abs gpu {lam_abs:.8e} oracle {cov.lam:.8e}")
-    for k in (0, 137, 255):
+    for k in checked:
         ref = cov.apply(v[k].astype(np.complex128))
         err = _rel(u[k], ref)
         vox = float(np.max(np.abs(u[k] - ref)) / np.max(np.abs(ref)))

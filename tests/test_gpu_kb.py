@@ -93,12 +93,13 @@ def test_spiral_pmr_parity(lib):
         assert e < TOL
 
 
-def test_gridding_full_size(lib):
-    say("case: gridding at the spiral workload's size: 256x256, 16 coils, 48x4096 R=2 "
-        "(98304 samples), sigma 2, W 6, k=2")
+@pytest.mark.parametrize("sigma,W", [(2.0, 6), (1.25, 4)])
+def test_gridding_full_size(lib, sigma, W):
+    say(f"case: gridding at the spiral workload's size: 256x256, 16 coils, 48x4096 R=2 "
+        f"(98304 samples), sigma {sigma}, W {W}, k=2")
     rng, maps, psi, traj = _setup(256, 16, 2, 48, 4096, seed=0)
     M = traj.shape[0]
-    h = _init(lib, maps, psi, traj, 2.0, 6, 2, cg=30)
+    h = _init(lib, maps, psi, traj, sigma, W, 2, cg=30)
     x = (rng.standard_normal((2, 256, 256)) + 1j * rng.standard_normal((2, 256, 256))).astype(np.complex64)
     y = (rng.standard_normal((2, 16, M)) + 1j * rng.standard_normal((2, 16, M))).astype(np.complex64)
     fo = torch.empty((2, 16, M), dtype=torch.complex64, device="cuda:0")
@@ -107,7 +108,7 @@ def test_gridding_full_size(lib):
     lib.pico_apply_nufft(h, 1, _dev(y), ad, 2)
     torch.cuda.synchronize()
     lib.pico_destroy(h)
-    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64), kb=(2.0, 6))
+    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64), kb=(sigma, W))
     for k in range(2):
         ef = _rel(fo.cpu().numpy()[k], op.forward(x[k].astype(np.complex128)))
         ea = _rel(ad.cpu().numpy()[k], op.adjoint(y[k].astype(np.complex128)))
