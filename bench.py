@@ -1379,7 +1379,7 @@ def main():
     if args.cs_steps > 0 and not args.no_ttt:
         cs_conv = {"l1wav": cs_converged_leg(lib, workloads, torch, np, dev, "l1wav", 8192)}
         if args.cs_tv_steps > 0:
-            cs_conv["tv"] = cs_converged_leg(lib, workloads, torch, np, dev, "tv", 8192)
+            cs_conv["tv"] = cs_converged_leg(lib, workloads, torch, np, dev, "tv", 16384)
 
     robust = (cs_robustness(lib, workloads, torch, np, dev, N=args.robust_n, reg=args.cs_robustness)
               if args.cs_robustness != "off" else None)
