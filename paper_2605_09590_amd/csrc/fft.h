@@ -284,6 +284,7 @@ struct TwoStep {
   static constexpr int SPAN = VA * STRIDE;
   static constexpr bool kMaskInRegs = N >= 256;    // room for LA mask weights per lane
   static constexpr bool kMapsInLds = N >= 256;     // and for N / 64 staged map values
+  static constexpr bool kRowsDma = N >= 256;       // few groups: direct-to-LDS row loads
   static_assert(64 % L == 0 || L <= 64, "group must fit a wavefront");
   struct Tw { float2 w[VA]; };
 
@@ -359,6 +360,7 @@ struct StockhamCol {
   static constexpr int SPAN = lds_span<PL::N>();
   static constexpr bool kMaskInRegs = false;
   static constexpr bool kMapsInLds = false;
+  static constexpr bool kRowsDma = false;
   struct Tw { float2 w[PL::NTW]; };
   __device__ static __forceinline__ int posA(int lane, int m) { return lane + L * m; }
   __device__ static __forceinline__ int posB(int lane, int r) { return lane + L * r; }

@@ -48,6 +48,36 @@ template <int ST>
 __device__ __forceinline__ float2 map_at(const Grid2dArgs& a, size_t i) { return widen(map_raw<ST>(a, i)); }
 
 
+// Direct global -> LDS copy of one row of n elements of E per column group of
+// the wavefront: group gi's row, from src(gi), goes to the start of its
+// transform tile.  Each lane loads 16 bytes per instruction and the hardware
+// places them at tile + lane * 16 bytes, so the loads hold no registers.
+// The row kernels use it to fetch the next coil's row into the tile, which is
+// idle between two transforms; wait_lds_loads() precedes the first LDS read
+// of the row.  Rows are 16-byte aligned (n and the row pitch multiples of
+// 16 / E).
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima): the direct
+// LDS loads count as vector memory operations, and their data is in LDS once
+// the counter has drained.  Issued explicitly before the first read of a
+// fetched row: the compiler does not order LDS reads after these loads.
+__device__ __forceinline__ void wait_lds_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <class CF, class E, int GS, class F>
+__device__ __forceinline__ void dma_rows(E* dst, int n, F&& src) {
+  constexpr int G = 64 / CF::L, PER = 16 / (int)sizeof(E), CH = 64 * PER;
+  const int lo = (int)threadIdx.x * PER;   // this lane's first element of every chunk
+#pragma unroll
+  for (int gi = 0; gi < G; ++gi) {
+    const E* s = src(gi) + lo;
+    E* d = dst + gi * GS;
+#pragma unroll
+    for (int j = 0; j * CH < CF::N; ++j)   // rows are at most N elements
+      if (j * CH + lo < n)
+        __builtin_amdgcn_global_load_lds((const void*)(s + j * CH),
+                                         (__attribute__((address_space(3))) void*)(d + j * CH), 16, 0, 0);
+  }
+}
+
 template <int L>
 __device__ __forceinline__ double group_reduce2(double v, double* red, int lane) {
   red[threadIdx.x] = v;
@@ -76,6 +106,20 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   float2* lds = lds_all + g * CF::SPAN;
   typename CF::Tw tw;
   CF::load_tw(tw, a.twx, lane);
+  // two-step rows of 256 and 320 points: coil 0's map rows go into the
+  // transform tiles while the CG update runs (later coils': see the coil loop)
+  constexpr bool PF = CF::N >= 384, DMA = CF::kRowsDma;
+  using ME = MapElem<ST>;
+  auto map_rows = [&](int c) {
+    dma_rows<CF, ME, CF::SPAN * (int)(sizeof(float2) / sizeof(ME))>(reinterpret_cast<ME*>(lds_all), a.nx, [&](int gi) {
+      const long gq = (long)blockIdx.x * G + gi;
+      const long gr = gq < (long)a.K * a.ny ? gq : 0;
+      const size_t moff = ((size_t)c * a.ny + (int)(gr % a.ny)) * a.nx;
+      if constexpr (ST >= 1) return (const ME*)(a.maps_bf + moff);
+      else return (const ME*)(a.maps + moff);
+    });
+  };
+  if constexpr (DMA) map_rows(0);
 
   const size_t rowoff = ((size_t)k * a.ny + y) * a.nx;
   // the per-probe fields never alias one another: restrict lets every load of
@@ -104,13 +148,17 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
       if (active && ok) { R[i] = val; P[i] = val; }
       d0 += (double)val.x * val.x + (double)val.y * val.y;
     } else if constexpr (MODE == C1_FIRST_BUF) {
-      val = ok ? R[i] : make_float2(0.f, 0.f);
+      // loads go out on every lane (the address is in bounds) and lanes
+      // outside the row are zeroed by a factor: a load under a lane
+      // condition (or as an operand of a select) gets a branch and a wait
+      // of its own
+      val = cscale(R[i], ok ? 1.f : 0.f);
       if (active && ok) P[i] = val;
       d0 += (double)val.x * val.x + (double)val.y * val.y;
     } else if constexpr (MODE == C1_ITER) {
       val = make_float2(0.f, 0.f);   // the update runs below, all loads first
     } else {  // C1_APPLY
-      val = ok ? cscale(SRC[i], a.scale) : make_float2(0.f, 0.f);
+      val = cscale(SRC[i], ok ? a.scale : 0.f);
     }
     pv[m] = val;
   }
@@ -157,10 +205,13 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
 
   float2* __restrict__ T = a.T;
   uint32_t* __restrict__ Tb = a.Tb;
-  // Rows of 384 points and more: the map row of coil c + 1 is loaded while
-  // coil c is transformed (measured: 512-point spiral rows 6.63 -> 5.53 ms per
-  // application; for 320-point rows it only costs a wave per SIMD)
-  constexpr bool PF = CF::N >= 384;
+  // Rows of 384 points and more: the map row of coil c + 1 is loaded into
+  // registers while coil c is transformed (measured: 512-point spiral rows
+  // 6.63 -> 5.53 ms per application).  Shorter rows have no registers to
+  // spare (a wave per SIMD); the two-step 256- and 320-point rows get their
+  // map rows straight into the transform tiles, coil c + 1's once coil c's
+  // transform is done (the Stockham plans keep direct loads: their many
+  // groups per wavefront would need more address registers than they have).
   MapElem<ST> svn[CF::VMAX];
   auto load_maps = [&](int c) {
     const size_t moff = ((size_t)c * a.ny + y) * a.nx;
@@ -178,20 +229,31 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
       for (int m = 0; m < VA; ++m) {
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
-        v[m] = ok ? cmul(widen(svn[m]), pv[m]) : make_float2(0.f, 0.f);
+        v[m] = cmul(widen(svn[m]), pv[m]);   // pv is 0 outside the row
       }
       if (c + 1 < a.nc) load_maps(c + 1);
+    } else if constexpr (DMA) {
+      wait_lds_loads();
+      const ME* mrow = reinterpret_cast<const ME*>(lds);
+#pragma unroll
+      for (int m = 0; m < VA; ++m) {
+        const int xx = CF::posA(lane, m);
+        const bool ok = inA && xx < a.nx;
+        v[m] = cmul(widen(mrow[ok ? xx : 0]), pv[m]);   // pv is 0 outside the row
+      }
     } else {
       const size_t moff = ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
       for (int m = 0; m < VA; ++m) {
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
-        const float2 sv = map_at<ST>(a, moff + (ok ? xx : 0));
-        v[m] = ok ? cmul(sv, pv[m]) : make_float2(0.f, 0.f);
+        v[m] = cmul(map_at<ST>(a, moff + (ok ? xx : 0)), pv[m]);   // pv is 0 outside the row
       }
     }
     CF::template forward<false>(v, lds, lane, tw);
+    if constexpr (DMA) {
+      if (c + 1 < a.nc) map_rows(c + 1);
+    }
     if (active && inB) {
       const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
       if constexpr (ST == 2) {
@@ -325,6 +387,35 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   const float2* __restrict__ SRC = a.src;
   const float2* __restrict__ T = a.T;
   float2* __restrict__ Qo = a.q;
+  constexpr bool PF = CF::N >= 384, DMA = CF::kRowsDma;
+  using TE = std::conditional_t<ST == 2, uint32_t, float2>;
+  // two-step 256- and 320-point rows: coil c + 1's transformed rows go
+  // straight into the transform tiles once coil c's inverse transform is done
+  auto t_rows = [&](int c) {
+    dma_rows<CF, TE, CF::SPAN * (int)(sizeof(float2) / sizeof(TE))>(reinterpret_cast<TE*>(lds_all), a.Gx, [&](int gi) {
+      const long gq = (long)blockIdx.x * G + gi;
+      const long gr = gq < (long)a.K * a.ny ? gq : 0;
+      const size_t off = (((size_t)(gr / a.ny) * a.nc + c) * a.ny + (int)(gr % a.ny)) * a.Gx;
+      if constexpr (ST == 2) return (const TE*)(a.Tb + off);
+      else return (const TE*)(T + off);
+    });
+  };
+  if constexpr (DMA) t_rows(0);
+  // rows of 384 points and more: each coil's map rows come through LDS (a
+  // buffer of their own, fetched when the coil starts and read after its
+  // inverse transform); with the transformed row of the next coil already in
+  // registers, the combine's own loads would be serialised for want of them
+  using ME = MapElem<ST>;
+  __shared__ ME mapbuf[PF ? G * CF::N : 1];
+  auto map_rows = [&](int c) {
+    dma_rows<CF, ME, CF::N>(mapbuf, a.nx, [&](int gi) {
+      const long gq = (long)blockIdx.x * G + gi;
+      const long gr = gq < (long)a.K * a.ny ? gq : 0;
+      const size_t moff = ((size_t)c * a.ny + (int)(gr % a.ny)) * a.nx;
+      if constexpr (ST >= 1) return (const ME*)(a.maps_bf + moff);
+      else return (const ME*)(a.maps + moff);
+    });
+  };
   // p (or scale * src) of this row: lam p enters q first (when lam != 0); the
   // dots at the end load it again
   auto load_p = [&](float2* pa) {
@@ -333,8 +424,8 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
       const int xx = CF::posA(lane, m);
       const bool ok = inA && xx < a.nx;
       const size_t i = rowoff + (ok ? xx : 0);
-      const float2 pval = MODE == C1_APPLY ? cscale(SRC[i], a.scale) : P[i];
-      pa[m] = ok ? pval : make_float2(0.f, 0.f);
+      const float2 raw = MODE == C1_APPLY ? SRC[i] : P[i];
+      pa[m] = cscale(raw, ok ? (MODE == C1_APPLY ? a.scale : 1.f) : 0.f);
     }
   };
   float2 qa[CF::VMAX];
@@ -349,8 +440,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   // rows of 384 points and more: the transformed row of coil c + 1 is loaded
   // while coil c is inverted (raw storage form, unconditional loads from
   // in-row addresses; lanes outside layout B get zeros at use)
-  constexpr bool PF = CF::N >= 384;
-  std::conditional_t<ST == 2, uint32_t, float2> tn[CF::VMAX];
+  TE tn[CF::VMAX];
   auto load_row = [&](int c) {
     const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
 #pragma unroll
@@ -365,26 +455,47 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
     float2 v[CF::VMAX];
     if constexpr (PF) {
 #pragma unroll
-      for (int r = 0; r < VB; ++r) v[r] = inB ? widen(tn[r]) : make_float2(0.f, 0.f);
+      for (int r = 0; r < VB; ++r) v[r] = widen(tn[r]);   // unused outside layout B
+      map_rows(c);
       if (c + 1 < a.nc) load_row(c + 1);
+    } else if constexpr (DMA) {
+      wait_lds_loads();
+      const TE* trow = reinterpret_cast<const TE*>(lds);
+#pragma unroll   // lanes outside layout B read tile padding, unused by the transform
+      for (int r = 0; r < VB; ++r) v[r] = widen(trow[CF::posB(lane, r)]);
     } else {
       const size_t off = (((size_t)k * a.nc + c) * a.ny + y) * a.Gx;
       if constexpr (ST == 2) {
 #pragma unroll
-        for (int r = 0; r < VB; ++r) v[r] = inB ? unpack_bf16x2(a.Tb[off + CF::posB(lane, r)]) : make_float2(0.f, 0.f);
+        for (int r = 0; r < VB; ++r) v[r] = unpack_bf16x2(a.Tb[off + (inB ? CF::posB(lane, r) : 0)]);
       } else {
 #pragma unroll
-        for (int r = 0; r < VB; ++r) v[r] = inB ? T[off + CF::posB(lane, r)] : make_float2(0.f, 0.f);
+        for (int r = 0; r < VB; ++r) v[r] = T[off + (inB ? CF::posB(lane, r) : 0)];   // unused outside layout B
       }
     }
     CF::template inverse<true>(v, lds, lane, tw);
-    const size_t moff = ((size_t)c * a.ny + y) * a.nx;
+    if constexpr (DMA) {
+      if (c + 1 < a.nc) t_rows(c + 1);
+    }
+    // the combine is unconditional (lanes outside the row are never stored
+    // or summed)
+    if constexpr (PF) {
+      wait_lds_loads();
+      const ME* mrow = mapbuf + (g < G ? g : 0) * CF::N;
 #pragma unroll
-    for (int m = 0; m < VA; ++m) {
-      const int xx = CF::posA(lane, m);
-      const bool ok = inA && xx < a.nx;
-      const float2 sv = map_at<ST>(a, moff + (ok ? xx : 0));
-      if (ok) qa[m] = cadd(qa[m], cmulc(sv, v[m]));
+      for (int m = 0; m < VA; ++m) {
+        const int xx = CF::posA(lane, m);
+        const bool ok = inA && xx < a.nx;
+        qa[m] = cadd(qa[m], cmulc(widen(mrow[ok ? xx : 0]), v[m]));
+      }
+    } else {
+      const size_t moff = ((size_t)c * a.ny + y) * a.nx;
+#pragma unroll
+      for (int m = 0; m < VA; ++m) {
+        const int xx = CF::posA(lane, m);
+        const bool ok = inA && xx < a.nx;
+        qa[m] = cadd(qa[m], cmulc(map_at<ST>(a, moff + (ok ? xx : 0)), v[m]));
+      }
     }
   }
   float2 pa[CF::VMAX], ra[CF::VMAX];
