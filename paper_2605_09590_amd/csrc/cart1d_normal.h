@@ -51,7 +51,9 @@ struct MaskLines {
     const bool inB = CF::inB(lane);
 #pragma unroll
     for (int r = 0; r < CF::VB; ++r) {
-      const float m = inB ? maskw[CF::posB(lane, r)] : 0.f;
+      // one batch of loads from in-bounds indices, zeroed by a factor (a
+      // load under the lane condition gets a branch and a wait of its own)
+      const float m = maskw[inB ? CF::posB(lane, r) : 0] * (inB ? 1.f : 0.f);
       if constexpr (kRegs) w[r] = m;
       bits |= (m != 0.f ? 1u : 0u) << r;
     }
@@ -241,30 +243,55 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
           if (active) { a.r[base + y] = pv[m]; a.p[base + y] = pv[m]; }
         }
       } else if constexpr (MODE == C1_FIRST_BUF) {
+        const float2* __restrict__ R = a.r;   // all loads before the first store
+        float2* __restrict__ P = a.p;
 #pragma unroll
         for (int m = 0; m < VA; ++m) {
-          const int y = CF::posA(lane, m);
-          pv[m] = a.r[base + y];
+          pv[m] = R[base + CF::posA(lane, m)];
           rv[m] = pv[m];
-          if (active) a.p[base + y] = pv[m];
+        }
+        if (active) {
+#pragma unroll
+          for (int m = 0; m < VA; ++m) P[base + CF::posA(lane, m)] = pv[m];
         }
       } else if constexpr (MODE == C1_ITER) {
         // finish iteration i-1 and start iteration i:
         //   x += alpha p, r -= alpha q, p = r + beta p
+        // The fields never alias one another: restrict lets every load of a
+        // chunk of H elements go out before the chunk's first store (else
+        // each element's loads wait behind the previous element's stores).
+        float2* __restrict__ X = a.x;
+        float2* __restrict__ R = a.r;
+        float2* __restrict__ P = a.p;
+        const float2* __restrict__ Q = a.q;
         const float alpha = (float)a.alpha[kk];
         const float beta = (float)a.beta[kk];
+        const bool xz = a.x_zero != 0;
+        constexpr int H = VA > 8 ? 8 : VA;
 #pragma unroll
-        for (int m = 0; m < VA; ++m) {
-          const int y = CF::posA(lane, m);
-          const float2 po = a.p[base + y];
-          const float2 qo = a.q[base + y];
-          const float2 xo = a.x_zero ? make_float2(0.f, 0.f) : a.x[base + y];
-          rv[m] = cfma(a.r[base + y], -alpha, qo);
-          pv[m] = cfma(rv[m], beta, po);
-          if (active) {
-            a.x[base + y] = cfma(xo, alpha, po);
-            a.r[base + y] = rv[m];
-            a.p[base + y] = pv[m];
+        for (int m0 = 0; m0 < VA; m0 += H) {
+          float2 po[H], qo[H], ro[H], xo[H];
+#pragma unroll
+          for (int h = 0; h < H; ++h) {
+            if (m0 + h >= VA) break;
+            const size_t i = base + CF::posA(lane, m0 + h);
+            po[h] = P[i];
+            qo[h] = Q[i];
+            ro[h] = R[i];
+            xo[h] = X[i];
+          }
+#pragma unroll
+          for (int h = 0; h < H; ++h) {
+            const int m = m0 + h;
+            if (m >= VA) break;
+            const size_t i = base + CF::posA(lane, m);
+            rv[m] = cfma(ro[h], -alpha, qo[h]);
+            pv[m] = cfma(rv[m], beta, po[h]);
+            if (active) {
+              X[i] = cfma(xz ? make_float2(0.f, 0.f) : xo[h], alpha, po[h]);
+              R[i] = rv[m];
+              P[i] = pv[m];
+            }
           }
         }
       } else {  // C1_APPLY
