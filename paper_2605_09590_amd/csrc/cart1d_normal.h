@@ -347,16 +347,18 @@ static hipError_t launch_plan(int mode, const Cart1dArgs& a, hipStream_t s) {
 
 // Column-FFT layouts per line length.  Stockham plans keep N/T values on T
 // lanes through every pass; two-step plans split N = LA * VA over LA lanes
-// with a single LDS transpose per transform.
+// with a single LDS transpose per transform.  The 288- and 384-point columns
+// use two-step plans: their Stockham plans (16 lanes, 18 and 24 values per
+// lane) spilled at one wave per SIMD and ran 3.8x slower (K = 256, 16 coils).
 using Col64 = TwoStep<8, 8>;
 using Col96 = StockhamCol<FFTPlan<96, 8, 12, 4, 2>>;
 using Col128 = StockhamCol<FFTPlan<128, 16, 8, 4, 4>>;
 using Col160 = StockhamCol<FFTPlan<160, 8, 20, 4, 2>>;
 using Col192 = StockhamCol<FFTPlan<192, 16, 12, 4, 4>>;
 using Col256 = TwoStep<16, 16>;
-using Col288 = StockhamCol<FFTPlan<288, 16, 18, 2, 2, 2, 2>>;
+using Col288 = TwoStep<18, 16>;
 using Col320 = TwoStep<20, 16>;
-using Col384 = StockhamCol<FFTPlan<384, 16, 24, 4, 4>>;
+using Col384 = TwoStep<24, 16>;
 using Col512 = StockhamCol<FFTPlan<512, 32, 16, 16, 2>>;
 
 

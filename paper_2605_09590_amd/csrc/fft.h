@@ -282,7 +282,7 @@ struct TwoStep {
   static constexpr int VMAX = (VA > LA ? VA : LA);
   static constexpr int STRIDE = LA + 1;            // padded LDS row
   static constexpr int SPAN = VA * STRIDE;
-  static constexpr bool kMaskInRegs = N >= 256;    // room for LA mask weights per lane
+  static constexpr bool kMaskInRegs = N >= 256 && LA <= 20;   // room for LA mask weights per lane
   static constexpr bool kMapsInLds = N >= 256;     // and for N / 64 staged map values
   static constexpr bool kRowsDma = N >= 256;       // few groups: direct-to-LDS row loads
   static_assert(64 % L == 0 || L <= 64, "group must fit a wavefront");

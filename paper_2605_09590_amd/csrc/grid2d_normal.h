@@ -106,9 +106,9 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   float2* lds = lds_all + g * CF::SPAN;
   typename CF::Tw tw;
   CF::load_tw(tw, a.twx, lane);
-  // two-step rows of 256 and 320 points: coil 0's map rows go into the
+  // two-step rows (256 points and more): coil 0's map rows go into the
   // transform tiles while the CG update runs (later coils': see the coil loop)
-  constexpr bool PF = CF::N >= 384, DMA = CF::kRowsDma;
+  constexpr bool DMA = CF::kRowsDma, PF = !DMA && CF::N >= 384;
   using ME = MapElem<ST>;
   auto map_rows = [&](int c) {
     dma_rows<CF, ME, CF::SPAN * (int)(sizeof(float2) / sizeof(ME))>(reinterpret_cast<ME*>(lds_all), a.nx, [&](int gi) {
@@ -205,13 +205,13 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
 
   float2* __restrict__ T = a.T;
   uint32_t* __restrict__ Tb = a.Tb;
-  // Rows of 384 points and more: the map row of coil c + 1 is loaded into
-  // registers while coil c is transformed (measured: 512-point spiral rows
-  // 6.63 -> 5.53 ms per application).  Shorter rows have no registers to
-  // spare (a wave per SIMD); the two-step 256- and 320-point rows get their
-  // map rows straight into the transform tiles, coil c + 1's once coil c's
-  // transform is done (the Stockham plans keep direct loads: their many
-  // groups per wavefront would need more address registers than they have).
+  // Stockham rows of 512 and 768 points: the map row of coil c + 1 is loaded
+  // into registers while coil c is transformed (measured: 512-point spiral
+  // rows 6.63 -> 5.53 ms per application).  The two-step rows get their map
+  // rows straight into the transform tiles, coil c + 1's once coil c's
+  // transform is done; the short Stockham plans keep direct loads (their
+  // many groups per wavefront would need more address registers than they
+  // have).
   MapElem<ST> svn[CF::VMAX];
   auto load_maps = [&](int c) {
     const size_t moff = ((size_t)c * a.ny + y) * a.nx;
@@ -387,10 +387,10 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   const float2* __restrict__ SRC = a.src;
   const float2* __restrict__ T = a.T;
   float2* __restrict__ Qo = a.q;
-  constexpr bool PF = CF::N >= 384, DMA = CF::kRowsDma;
+  constexpr bool DMA = CF::kRowsDma, PF = !DMA && CF::N >= 384;
   using TE = std::conditional_t<ST == 2, uint32_t, float2>;
-  // two-step 256- and 320-point rows: coil c + 1's transformed rows go
-  // straight into the transform tiles once coil c's inverse transform is done
+  // two-step rows: coil c + 1's transformed rows go straight into the
+  // transform tiles once coil c's inverse transform is done
   auto t_rows = [&](int c) {
     dma_rows<CF, TE, CF::SPAN * (int)(sizeof(float2) / sizeof(TE))>(reinterpret_cast<TE*>(lds_all), a.Gx, [&](int gi) {
       const long gq = (long)blockIdx.x * G + gi;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
     });
   };
   if constexpr (DMA) t_rows(0);
-  // rows of 384 points and more: each coil's map rows come through LDS (a
+  // Stockham rows of 512 and 768 points: each coil's map rows come through LDS (a
   // buffer of their own, fetched when the coil starts and read after its
   // inverse transform); with the transformed row of the next coil already in
   // registers, the combine's own loads would be serialised for want of them
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
 #pragma unroll
     for (int m = 0; m < VA; ++m) qa[m] = make_float2(0.f, 0.f);
   }
-  // rows of 384 points and more: the transformed row of coil c + 1 is loaded
+  // Stockham rows of 512 and 768 points: the transformed row of coil c + 1 is loaded
   // while coil c is inverted (raw storage form, unconditional loads from
   // in-row addresses; lanes outside layout B get zeros at use)
   TE tn[CF::VMAX];
@@ -532,19 +532,29 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
 }
 
 // ---------------------------------------------------------------- plans
+// Every row and column kernel holds at most two waves per SIMD here, so the
+// plan per length is the one whose kernels fit 256 VGPRs without spilling:
+// two-step plans (one LDS transpose per transform) where LA + VA values per
+// lane fit, 32-lane groups for 576 and 640 points, and a 64-lane Stockham
+// plan for 768 points (12 values per lane; the 32-lane plans of 768 points
+// spill).  Measured per normal-operator application against the 16- and
+// 32-lane Stockham plans they replace: 288-point grid 6.87 -> 2.55 ms (30
+// coils, K = 128), 576 x 576 6.23 -> 3.54 ms and 640 x 640 4.82 -> 3.26 ms
+// (spiral, K = 64), 768 x 768 13.4 -> 6.6 ms (32 coils, K = 32).  The 64-lane
+// plan of 512 points (8 x 8 x 8) measured 2 % slower than the 32-lane one.
 using L64 = TwoStep<8, 8>;
 using L96 = StockhamCol<FFTPlan<96, 8, 12, 4, 2>>;
 using L128 = StockhamCol<FFTPlan<128, 16, 8, 4, 4>>;
 using L160 = StockhamCol<FFTPlan<160, 8, 20, 4, 2>>;
 using L192 = StockhamCol<FFTPlan<192, 16, 12, 4, 4>>;
 using L256 = TwoStep<16, 16>;
-using L288 = StockhamCol<FFTPlan<288, 16, 18, 2, 2, 2, 2>>;
+using L288 = TwoStep<18, 16>;
 using L320 = TwoStep<20, 16>;
-using L384 = StockhamCol<FFTPlan<384, 16, 24, 4, 4>>;
+using L384 = TwoStep<24, 16>;
 using L512 = StockhamCol<FFTPlan<512, 32, 16, 16, 2>>;
-using L576 = StockhamCol<FFTPlan<576, 16, 36, 4, 4>>;
-using L640 = StockhamCol<FFTPlan<640, 32, 20, 4, 4, 2>>;
-using L768 = StockhamCol<FFTPlan<768, 32, 24, 4, 4, 2>>;
+using L576 = TwoStep<32, 18>;
+using L640 = TwoStep<32, 20>;
+using L768 = StockhamCol<FFTPlan<768, 64, 12, 4, 4, 4>>;
 
 template <class F>
 static hipError_t with_line(int n, F&& f) {

@@ -235,6 +235,27 @@ def test_dense_form_parity(lib, ny, nx, nc, tile, nprobes, form):
     assert err < TOL and _rel(ss, ref["sumsq"].ravel()) < TOL
 
 
+# Column transforms of every plan family on the FFT path (normal form 0):
+# Stockham plans (96, 160, 192, 512) and two-step plans whose lane groups
+# leave part of the wavefront idle (18 lanes at 288, 24 at 384), with ragged
+# probe tiles.
+@pytest.mark.parametrize("ny,nx,nc,tile,nprobes", [(96, 40, 5, 4, 10), (160, 24, 8, 32, 45),
+                                                   (192, 20, 4, 7, 7), (288, 16, 3, 33, 33),
+                                                   (384, 12, 3, 17, 17), (512, 8, 2, 32, 32)])
+def test_fft_form_column_lengths(lib, ny, nx, nc, tile, nprobes):
+    say(f"case: FFT normal form {ny}x{nx} {nc} coils, {nprobes} probes in tiles of {tile}, CG 20")
+    prob = workloads.config(2, seed=ny + 1, ny=ny, nx=nx, nc=nc, acs=8, cg_iters=20)
+    h = _init(lib, prob, tile, form=0)
+    st = lib.pico_stats_t()
+    (s, si, ss), _ = _gpu_map(lib, h, ny * nx, 33, 1, nprobes, stats=st)
+    lib.pico_destroy(h)
+    cov = opico.Covariance(opico.cartesian(prob.maps, prob.psi, prob.mask), 0.0, 20)
+    ref = opico.noise_map(cov, 33, 1, nprobes)
+    err = _rel(s, ref["sum"].ravel())
+    say(f"  rel err sum {err:.2e}, sumsq {_rel(ss, ref['sumsq'].ravel()):.2e}, CG relres max {st.max_relres:.2e}")
+    assert err < TOL and _rel(ss, ref["sumsq"].ravel()) < TOL
+
+
 @pytest.mark.parametrize("form", [2, 3])
 def test_dense_form_apply_cov_tikhonov(lib, form):
     say(f"case: dense normal form {form}, apply_cov on 3 probes, lambda 0.1, 64x64, power method on the "

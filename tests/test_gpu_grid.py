@@ -13,6 +13,7 @@ import pytest
 import workloads
 from oracle import nufft as onufft
 from oracle import pico as opico
+from oracle import storage as ostore
 
 torch = pytest.importorskip("torch")
 
@@ -187,3 +188,54 @@ def test_spiral_full_size_sampled_probes(lib, R):
     assert np.max(np.abs(q.imag) / q.real) < 1e-4
     say(f"  all 256 probes: Re<v, u> / |v|^2 in [{(q.real / vv).min():.3e}, {(q.real / vv).max():.3e}] "
         f"(bound {1 / (4 * lam_abs):.3e}), max |Im| / Re {np.max(np.abs(q.imag) / q.real):.1e}")
+
+
+# Line lengths with two-step plans whose lane groups do not divide a
+# wavefront evenly (18 and 24 lanes) or fill it (32 lanes), and the 64-lane
+# Stockham plan of 768 points.  Row counts are chosen so that the last
+# workgroup of the row passes holds a partial set of row groups.
+@pytest.mark.parametrize("kind,ny,nx,storage", [
+    ("spiral", 128, 144, 0),   # rows 288 (three 18-lane groups; 2 x 128 rows: ragged), columns 256
+    ("spiral", 144, 96, 0),    # columns 288
+    ("spiral", 192, 160, 0),   # rows 320 x columns 384
+    ("spiral", 96, 192, 2),    # rows 384 (two 24-lane groups), bfloat16 maps and planes
+    ("spiral", 288, 320, 0),   # rows 640 x columns 576
+    ("spiral", 320, 288, 2),   # rows 576 x columns 640, bfloat16 maps and planes
+    ("cart2d", 160, 288, 0),   # Cartesian rows 288 (2 x 160 rows: ragged over groups of 3)
+    ("cart2d", 384, 384, 0),   # Cartesian rows and columns 384
+])
+def test_grid_line_lengths(lib, kind, ny, nx, storage):
+    K = 2
+    say(f"case: {kind} {ny}x{nx}, 2 coils, storage {storage}, apply_cov on {K} probes in one tile, CG 15")
+    rng = np.random.default_rng(ny * 1000 + nx)
+    maps = workloads.coil_maps(ny, nx, 2, rng)
+    psi = workloads.noise_cov(2, rng)
+    if kind == "spiral":
+        traj = workloads.spiral_traj(max(ny, nx), 1, 12, 1024).astype(np.float32)
+        h = lib.pico_init(ny, nx, _dev(maps.astype(np.complex64)), psi, None, sampling=lib.PICO_NONCART,
+                          lam=0.1, cg_iters=15, probe_tile=K, traj=_dev(traj), nsamples=traj.shape[0],
+                          storage=storage)
+        lam = 0.1
+        op_maps = ostore.bf16_whitened_maps(maps, psi) if storage else maps
+        op = onufft.NonCartOp(op_maps, None if storage else psi, traj.astype(np.float64))
+    else:
+        mask = workloads.poisson_disc_mask(ny, nx, 2.0, 16, seed=ny + nx)
+        h = lib.pico_init(ny, nx, _dev(maps.astype(np.complex64)), psi, _dev(mask),
+                          sampling=lib.PICO_CART_2D, lam=0.05, cg_iters=15, probe_tile=K, storage=storage)
+        lam = 0.05
+        op = opico.cartesian(maps, psi, mask)
+    v = np.stack([opico.probe_image(7, i, (ny, nx)) for i in range(K)])
+    vt = _dev(v.astype(np.complex64))
+    ut = torch.empty_like(vt)
+    lib.pico_apply_cov(h, vt, ut, K)
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    cov = opico.Covariance(op, lam, 15)
+    # storage 2 rounds every plane to bfloat16 as well: the rounded-map oracle
+    # bounds the map rounding only, so the bar is the bfloat16 one
+    tol = TOL if storage == 0 else 1e-2
+    u = ut.cpu().numpy()
+    for k in range(K):
+        err = _rel(u[k], cov.apply(v[k]))
+        say(f"  probe {k}: rel err {err:.2e}")
+        assert err < tol
