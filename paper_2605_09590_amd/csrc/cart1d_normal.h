@@ -347,19 +347,23 @@ static hipError_t launch_plan(int mode, const Cart1dArgs& a, hipStream_t s) {
 
 // Column-FFT layouts per line length.  Stockham plans keep N/T values on T
 // lanes through every pass; two-step plans split N = LA * VA over LA lanes
-// with a single LDS transpose per transform.  The 288- and 384-point columns
-// use two-step plans: their Stockham plans (16 lanes, 18 and 24 values per
-// lane) spilled at one wave per SIMD and ran 3.8x slower (K = 256, 16 coils).
+// with a single LDS transpose per transform.  Each length takes the faster
+// plan measured (K = 256, 16 coils, ms per application, replaced Stockham
+// plan first): 128 points 0.192 -> 0.152, 160 0.560 -> 0.225 (that plan
+// spilled), 192 0.398 -> 0.312, 288 2.93 -> 0.77 and 384 5.22 -> 1.42 (16
+// lanes with 18 and 24 values each: one wave per SIMD, spilled), 512 4.87 ->
+// 2.08 (32 lanes with 16 values -> 64 lanes with 8); at 96 points the
+// Stockham plan stays (0.132 against 0.201 for two-step 8 x 12).
 using Col64 = TwoStep<8, 8>;
 using Col96 = StockhamCol<FFTPlan<96, 8, 12, 4, 2>>;
-using Col128 = StockhamCol<FFTPlan<128, 16, 8, 4, 4>>;
-using Col160 = StockhamCol<FFTPlan<160, 8, 20, 4, 2>>;
-using Col192 = StockhamCol<FFTPlan<192, 16, 12, 4, 4>>;
+using Col128 = TwoStep<16, 8>;
+using Col160 = TwoStep<16, 10>;
+using Col192 = TwoStep<16, 12>;
 using Col256 = TwoStep<16, 16>;
 using Col288 = TwoStep<18, 16>;
 using Col320 = TwoStep<20, 16>;
 using Col384 = TwoStep<24, 16>;
-using Col512 = StockhamCol<FFTPlan<512, 32, 16, 16, 2>>;
+using Col512 = StockhamCol<FFTPlan<512, 64, 8, 8, 8>>;
 
 
 template <bool BF>

@@ -540,13 +540,16 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
 // spill).  Measured per normal-operator application against the 16- and
 // 32-lane Stockham plans they replace: 288-point grid 6.87 -> 2.55 ms (30
 // coils, K = 128), 576 x 576 6.23 -> 3.54 ms and 640 x 640 4.82 -> 3.26 ms
-// (spiral, K = 64), 768 x 768 13.4 -> 6.6 ms (32 coils, K = 32).  The 64-lane
-// plan of 512 points (8 x 8 x 8) measured 2 % slower than the 32-lane one.
+// (spiral, K = 64), 768 x 768 13.4 -> 6.6 ms (32 coils, K = 32); 160- and
+// 192-point grids (16 coils, K = 256) 1.03 -> 0.86 and 1.44 -> 1.15 ms.  The
+// 64-lane plan of 512 points (8 x 8 x 8) measured 2 % slower than the 32-lane
+// one, and the two-step plans of 96 and 128 points 5-15 % slower than the
+// Stockham ones kept there.
 using L64 = TwoStep<8, 8>;
 using L96 = StockhamCol<FFTPlan<96, 8, 12, 4, 2>>;
 using L128 = StockhamCol<FFTPlan<128, 16, 8, 4, 4>>;
-using L160 = StockhamCol<FFTPlan<160, 8, 20, 4, 2>>;
-using L192 = StockhamCol<FFTPlan<192, 16, 12, 4, 4>>;
+using L160 = TwoStep<16, 10>;
+using L192 = TwoStep<16, 12>;
 using L256 = TwoStep<16, 16>;
 using L288 = TwoStep<18, 16>;
 using L320 = TwoStep<20, 16>;

@@ -235,11 +235,12 @@ def test_dense_form_parity(lib, ny, nx, nc, tile, nprobes, form):
     assert err < TOL and _rel(ss, ref["sumsq"].ravel()) < TOL
 
 
-# Column transforms of every plan family on the FFT path (normal form 0):
-# Stockham plans (96, 160, 192, 512) and two-step plans whose lane groups
-# leave part of the wavefront idle (18 lanes at 288, 24 at 384), with ragged
-# probe tiles.
-@pytest.mark.parametrize("ny,nx,nc,tile,nprobes", [(96, 40, 5, 4, 10), (160, 24, 8, 32, 45),
+# Column transforms of every line length on the FFT path (normal form 0):
+# two-step plans whose lane groups leave part of the wavefront idle (12 lanes
+# at 96, 18 at 288, 24 at 384) or fill it, and the 64-lane Stockham plan of
+# 512 points, with ragged probe tiles.
+@pytest.mark.parametrize("ny,nx,nc,tile,nprobes", [(96, 40, 5, 4, 10), (128, 24, 6, 9, 9),
+                                                   (160, 24, 8, 32, 45),
                                                    (192, 20, 4, 7, 7), (288, 16, 3, 33, 33),
                                                    (384, 12, 3, 17, 17), (512, 8, 2, 32, 32)])
 def test_fft_form_column_lengths(lib, ny, nx, nc, tile, nprobes):

@@ -203,6 +203,9 @@ def test_spiral_full_size_sampled_probes(lib, R):
     ("spiral", 320, 288, 2),   # rows 576 x columns 640, bfloat16 maps and planes
     ("cart2d", 160, 288, 0),   # Cartesian rows 288 (2 x 160 rows: ragged over groups of 3)
     ("cart2d", 384, 384, 0),   # Cartesian rows and columns 384
+    ("spiral", 96, 64, 0),     # rows 128 x columns 192
+    ("cart2d", 192, 160, 0),   # Cartesian rows 160 x columns 192
+    ("cart2d", 96, 96, 2),     # Cartesian rows and columns 96 (five 12-lane groups), bfloat16
 ])
 def test_grid_line_lengths(lib, kind, ny, nx, storage):
     K = 2
