@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
 }
 
 // S tangent inner steps i .. i+S-1 in one pass over a TY x TX tile T
-// (S = 2 on 8 x 32 tiles, S = 4 on 16 x 16).  The LDS box B is T grown by S on
+// (S = 2 on 8 x 32 tiles, S = 4 on 16 x 16).  The box B is T grown by S on
 // every side (FIN: by S + 1 above and left), index [a][b] = pixel
 // (y0 - S - E + a, x0 - S - E + b), periodic, E = FIN.  Step s (from 0)
 // updates r and p on R_s = rows [s+1, BY-2-s] x cols [s+1, BX-2-s] from
@@ -251,22 +251,23 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
 // r on R_{s-1} (the whole box for s = 0), so R_{S-1} = T (FIN: T with the row
 // above and the column left of it):
 //   w = r_s + c8 D u_s,  p_{s+1} = dP_s(w),  r_{s+1} = p_{s+1} + th_s (p_{s+1} - p_s).
-// Inputs: r_i on B, p_i on R_0, dz on U_0; the projection data of the steps
-// on their regions in LDS (shared by the block's tangents; without FIN the
-// last step's only at the thread's own pixel).  r and p are read from
-// (rA, pA) and, without FIN, the last step's written to (rB, pB): neighbouring
-// tiles read the halo of both; last: the prox's last pass, only p is read
-// afterwards.  FIN (the prox's last pass, fused with the FISTA step): nothing
-// is written to the dual fields; each own pixel forms the prox output
-// dx = dz - lam D^H p from the box, then y = dx + theta (dx - xo), xo = dx.
-// first: r_i = p_i = 0 (step 0 from the zero start).  Tangent k + 1's box is
-// loaded into registers while tangent k's steps run.  Needs ny >= TY + 2S + E
-// and nx >= TX + 2S + E (the halo wraps at most once).
+// Thread t owns the box points e = t + 256 j (j < NPT) through every step:
+// their r, p, dz, u and the steps' projection data stay in its registers, and
+// only r and u go through LDS, for the neighbours' reads (a point reads r at
+// (a-1, b), (a, b-1) and u at (a+1, b), (a, b+1)).  The projection data is
+// loaded once per workgroup, for its run of tangents.  Inputs: r_i on B, p_i
+// on R_0, dz on U_0, read from (rA, pA); without FIN r and p of T written to
+// (rB, pB) (neighbouring tiles read the halo of both; last: the prox's last
+// pass, only p is read afterwards).  FIN (the prox's last pass, fused with the
+// FISTA step): nothing is written to the dual fields; each pixel of T forms
+// the prox output dx = dz - lam D^H p from the box, then y = dx + theta (dx -
+// xo), xo = dx.  first: r_i = p_i = 0 (step 0 from the zero start).  Tangent
+// k + 1's box is loaded into registers while tangent k's steps run.  Needs
+// ny >= TY + 2S + E and nx >= TX + 2S + E (the halo wraps at most once).
 template <int S, int TY, int TX, int E>
 struct TvSteps {
   static constexpr int BY = TY + 2 * S + E, BX = TX + 2 * S + E, NB = BY * BX;
   static constexpr int NPT = (NB + 255) / 256;   // box points per thread
-  static constexpr int NPS = S - 1 + E;           // steps with projection data in LDS
   __host__ __device__ static constexpr int ry(int s) { return BY - 2 - 2 * s; }   // R_s rows
   __host__ __device__ static constexpr int rx(int s) { return BX - 2 - 2 * s; }   // R_s cols
   __host__ __device__ static constexpr int proj_off(int s) {
@@ -274,7 +275,7 @@ struct TvSteps {
     for (int q = 0; q < s; ++q) o += ry(q) * rx(q);
     return o;
   }
-  static constexpr int NPROJ = proj_off(NPS) > 0 ? proj_off(NPS) : 1;
+  static constexpr int NPROJ = proj_off(S);   // projection data of the S steps on their regions
 };
 
 struct TvTheta {
@@ -291,12 +292,9 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
   constexpr int E = FIN ? 1 : 0;
   using C = TvSteps<S, TY, TX, E>;
   constexpr int BY = C::BY, BX = C::BX, NB = C::NB, NPT = C::NPT;
-  static_assert(TY * TX == 256, "one output pixel per thread");
-  __shared__ float2 sRy[BY][BX], sRx[BY][BX];   // r_s (in place)
-  __shared__ float2 sPy[BY][BX], sPx[BY][BX];   // p_s (in place)
-  __shared__ float2 sZ[BY][BX];                 // dz
+  __shared__ float2 sRy[BY][BX], sRx[BY][BX];   // r_s at every box point
   __shared__ float2 sU[BY][BX];                 // u_s
-  __shared__ float4 sW[C::NPROJ];               // projection data of the steps in LDS on R_s (w^)
+  __shared__ float4 sW[C::NPROJ];               // projection data of the steps on R_s (w^)
   __shared__ float sV[C::NPROJ];                // and 1/|w|
   const long n = (long)ny * nx;
   const int tilesx = (nx + TX - 1) / TX, tiles = tilesx * ((ny + TY - 1) / TY);
@@ -306,144 +304,152 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
   const int y0 = (tile / tilesx) * TY, x0 = (tile % tilesx) * TX;
   const int t = threadIdx.x;
   const bool fst = first != 0;
-  auto gidx = [&](int a, int b) { return (long)wrap(y0 - S - E + a, ny) * nx + wrap(x0 - S - E + b, nx); };
+  // this thread's box points: coordinates, in-box flag, image index
+  int sa[NPT], sb[NPT], gi[NPT];   // images have fewer than 2^31 pixels
+  bool sv[NPT];
 #pragma unroll
-  for (int s = 0; s < C::NPS; ++s) {
+  for (int j = 0; j < NPT; ++j) {
+    const int e = t + 256 * j;
+    sv[j] = e < NB;
+    const int ee = sv[j] ? e : 0;
+    sa[j] = ee / BX;
+    sb[j] = ee - sa[j] * BX;
+    gi[j] = wrap(y0 - S - E + sa[j], ny) * nx + wrap(x0 - S - E + sb[j], nx);
+  }
+  auto inU = [&](int s, int j) {
+    return sv[j] && sa[j] >= s + 1 && sa[j] <= BY - 1 - s && sb[j] >= s + 1 && sb[j] <= BX - 1 - s;
+  };
+  auto inR = [&](int s, int j) {
+    return sv[j] && sa[j] >= s + 1 && sa[j] <= BY - 2 - s && sb[j] >= s + 1 && sb[j] <= BX - 2 - s;
+  };
+  auto inT = [&](int j) {   // own output pixels: T, inside the image
+    const int a = sa[j] - S - E, b = sb[j] - S - E;
+    return sv[j] && a >= 0 && a < TY && b >= 0 && b < TX && y0 + a < ny && x0 + b < nx;
+  };
+  // projection data of the S steps on their regions, shared by the run of
+  // tangents
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
     const int RY = C::ry(s), RX = C::rx(s), off = C::proj_off(s);
     for (int e = t; e < RY * RX; e += 256) {
       const int a = s + 1 + e / RX, b = s + 1 + e % RX;
-      const long g = gidx(a, b);
+      const int g = wrap(y0 - S - E + a, ny) * nx + wrap(x0 - S - E + b, nx);
       sW[off + e] = what[(size_t)s * n + g];
       sV[off + e] = invn[(size_t)s * n + g];
     }
   }
-  // own pixel (box [S + E + ty][S + E + tx]); without FIN the last step's
-  // projection data
-  const int ty = t / TX, tx = t % TX;
-  const int y = y0 + ty, x = x0 + tx;
-  const bool own = y < ny && x < nx;
-  const long i = (long)y * nx + x;
-  float4 whl = make_float4(0.f, 0.f, 0.f, 0.f);
-  float ivl = 1.f;
-  if (!FIN && own) {
-    whl = what[(size_t)(S - 1) * n + i];
-    ivl = invn[(size_t)(S - 1) * n + i];
-  }
   const int k0 = kblk * kper, k1 = min(K, k0 + kper);
-  struct BoxPt {
-    float2 vy, vx, qy, qx, z;
-  };
-  BoxPt nb[NPT];
+  float2 nry[NPT], nrx[NPT], npy[NPT], npx[NPT], nz[NPT];
   auto box_load = [&](int k) {
     const float2* zk = dz + (size_t)k * n;
     const float2* ryk = rA + (size_t)k * 2 * n;
     const float2* pyk = pA + (size_t)k * 2 * n;
     const float2 zero = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int it = 0; it < NPT; ++it) {
-      const int e = t + 256 * it;
-      nb[it].vy = nb[it].vx = nb[it].qy = nb[it].qx = nb[it].z = zero;
-      if (e < NB) {
-        const int a = e / BX, b = e - a * BX;
-        const long g = gidx(a, b);
-        if (!fst) {
-          nb[it].vy = ryk[g];
-          nb[it].vx = ryk[n + g];
-          if (a >= 1 && a <= BY - 2 && b >= 1 && b <= BX - 2) {   // R_0
-            nb[it].qy = pyk[g];
-            nb[it].qx = pyk[n + g];
-          }
+    for (int j = 0; j < NPT; ++j) {
+      nry[j] = nrx[j] = npy[j] = npx[j] = nz[j] = zero;
+      if (!fst) {
+        nry[j] = ryk[gi[j]];
+        nrx[j] = ryk[n + gi[j]];
+        if (inR(0, j)) {
+          npy[j] = pyk[gi[j]];
+          npx[j] = pyk[n + gi[j]];
         }
-        if (a >= 1 && b >= 1) nb[it].z = zk[g];                  // U_0
       }
+      if (inU(0, j)) nz[j] = zk[gi[j]];
     }
-  };
-  // u_s at (a, b): dz - lam D^H r
-  auto u_at = [&](int a, int b) {
-    const float hx = sRy[a - 1][b].x - sRy[a][b].x + sRx[a][b - 1].x - sRx[a][b].x;
-    const float hy = sRy[a - 1][b].y - sRy[a][b].y + sRx[a][b - 1].y - sRx[a][b].y;
-    return make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
-  };
-  // dP(w) dw for w = r + c8 D u at (a, b): (qy, qx)
-  auto proj_at = [&](int a, int b, float4 wh, float iv, float2& qy, float2& qx) {
-    const float2 u0 = sU[a][b], uy = sU[a + 1][b], ux = sU[a][b + 1];
-    const float2 wy = make_float2(fmaf(c8, uy.x - u0.x, sRy[a][b].x), fmaf(c8, uy.y - u0.y, sRy[a][b].y));
-    const float2 wx = make_float2(fmaf(c8, ux.x - u0.x, sRx[a][b].x), fmaf(c8, ux.y - u0.y, sRx[a][b].y));
-    const float re = wh.x * wy.x + wh.y * wy.y + wh.z * wx.x + wh.w * wx.y;   // Re(w^H dw)
-    qy = make_float2((wy.x - wh.x * re) * iv, (wy.y - wh.y * re) * iv);
-    qx = make_float2((wx.x - wh.z * re) * iv, (wx.y - wh.w * re) * iv);
   };
   if (k0 < k1) box_load(k0);
   for (int k = k0; k < k1; ++k) {
+    float2 ry[NPT], rx[NPT], py[NPT], px[NPT], zz[NPT], uu[NPT];
 #pragma unroll
-    for (int it = 0; it < NPT; ++it) {
-      const int e = t + 256 * it;
-      if (e < NB) {
-        const int a = e / BX, b = e - a * BX;
-        sRy[a][b] = nb[it].vy;
-        sRx[a][b] = nb[it].vx;
-        sPy[a][b] = nb[it].qy;
-        sPx[a][b] = nb[it].qx;
-        sZ[a][b] = nb[it].z;
+    for (int j = 0; j < NPT; ++j) {
+      ry[j] = nry[j];
+      rx[j] = nrx[j];
+      py[j] = npy[j];
+      px[j] = npx[j];
+      zz[j] = nz[j];
+      uu[j] = make_float2(0.f, 0.f);
+      if (sv[j]) {
+        sRy[sa[j]][sb[j]] = ry[j];
+        sRx[sa[j]][sb[j]] = rx[j];
       }
     }
     __syncthreads();
     if (k + 1 < k1) box_load(k + 1);   // in flight during this tangent's steps
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      {   // u_s on U_s = rows [s+1, BY-1-s] x cols [s+1, BX-1-s]
-        const int UY = BY - 1 - 2 * s, UX = BX - 1 - 2 * s;
-        for (int e = t; e < UY * UX; e += 256) {
-          const int a = s + 1 + e / UX, b = s + 1 + e % UX;
-          sU[a][b] = u_at(a, b);
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) {   // u_s = dz - lam D^H r_s on U_s
+        if (inU(s, j)) {
+          const int a = sa[j], b = sb[j];
+          const float2 ryn = sRy[a - 1][b], rxn = sRx[a][b - 1];
+          const float hx = ryn.x - ry[j].x + rxn.x - rx[j].x;
+          const float hy = ryn.y - ry[j].y + rxn.y - rx[j].y;
+          uu[j] = make_float2(fmaf(-lam, hx, zz[j].x), fmaf(-lam, hy, zz[j].y));
+          sU[a][b] = uu[j];
         }
       }
       __syncthreads();
-      if (s < C::NPS) {   // step s on R_s; r and p replaced in place (each point reads only itself)
-        const int RY = C::ry(s), RX = C::rx(s), off = C::proj_off(s);
-        const float ths = th.th[s];
-        const bool need_r = s < S - 1;   // FIN's last step: only p is read afterwards
-        for (int e = t; e < RY * RX; e += 256) {
-          const int a = s + 1 + e / RX, b = s + 1 + e % RX;
-          float2 qy, qx;
-          proj_at(a, b, sW[off + e], sV[off + e], qy, qx);
-          if (need_r) {
-            const float2 oy = sPy[a][b], ox = sPx[a][b];
-            sRy[a][b] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
-            sRx[a][b] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
+      const float ths = th.th[s];
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) {   // step s on R_s: w, dP(w) dw, r and p
+        if (inR(s, j)) {
+          const int a = sa[j], b = sb[j];
+          const float2 uy = sU[a + 1][b], ux = sU[a][b + 1];
+          const float2 wy = make_float2(fmaf(c8, uy.x - uu[j].x, ry[j].x), fmaf(c8, uy.y - uu[j].y, ry[j].y));
+          const float2 wx = make_float2(fmaf(c8, ux.x - uu[j].x, rx[j].x), fmaf(c8, ux.y - uu[j].y, rx[j].y));
+          const int pe = C::proj_off(s) + (a - s - 1) * C::rx(s) + (b - s - 1);
+          const float4 wh = sW[pe];
+          const float iv = sV[pe];
+          const float re = wh.x * wy.x + wh.y * wy.y + wh.z * wx.x + wh.w * wx.y;   // Re(w^H dw)
+          const float2 qy = make_float2((wy.x - wh.x * re) * iv, (wy.y - wh.y * re) * iv);
+          const float2 qx = make_float2((wx.x - wh.z * re) * iv, (wx.y - wh.w * re) * iv);
+          ry[j] = make_float2(fmaf(ths, qy.x - py[j].x, qy.x), fmaf(ths, qy.y - py[j].y, qy.y));
+          rx[j] = make_float2(fmaf(ths, qx.x - px[j].x, qx.x), fmaf(ths, qx.y - px[j].y, qx.y));
+          py[j] = qy;
+          px[j] = qx;
+          if (s + 1 < S) {   // r_{s+1} for the next step's neighbour reads
+            sRy[a][b] = ry[j];
+            sRx[a][b] = rx[j];
+          } else if (FIN) {   // p_S for the prox output's neighbour reads
+            sRy[a][b] = qy;
+            sRx[a][b] = qx;
           }
-          sPy[a][b] = qy;
-          sPx[a][b] = qx;
         }
-      } else if (own) {   // the last step on T, written out
-        const int a = S + ty, b = S + tx;
-        float2 qy, qx;
-        proj_at(a, b, whl, ivl, qy, qx);
-        const float2 oy = sPy[a][b], ox = sPx[a][b];
-        const float ths = th.th[S - 1];
-        float2* pb = pB + (size_t)k * 2 * n;
-        if (!last) {   // the prox's last pass: only p is read afterwards
-          float2* rb = rB + (size_t)k * 2 * n;
-          rb[i] = make_float2(fmaf(ths, qy.x - oy.x, qy.x), fmaf(ths, qy.y - oy.y, qy.y));
-          rb[n + i] = make_float2(fmaf(ths, qx.x - ox.x, qx.x), fmaf(ths, qx.y - ox.y, qx.y));
-        }
-        pb[i] = qy;
-        pb[n + i] = qx;
       }
-      __syncthreads();
+      if (s + 1 < S || FIN) __syncthreads();
     }
     if constexpr (FIN) {
-      if (own) {   // prox output and FISTA step at the own pixel
-        const int a = S + E + ty, b = S + E + tx;
-        const float hx = sPy[a - 1][b].x - sPy[a][b].x + sPx[a][b - 1].x - sPx[a][b].x;
-        const float hy = sPy[a - 1][b].y - sPy[a][b].y + sPx[a][b - 1].y - sPx[a][b].y;
-        const float2 dxv = make_float2(fmaf(-lam, hx, sZ[a][b].x), fmaf(-lam, hy, sZ[a][b].y));
-        const size_t o = (size_t)k * n + i;
-        const float2 xp = xo[o];
-        yo[o] = make_float2(fmaf(theta, dxv.x - xp.x, dxv.x), fmaf(theta, dxv.y - xp.y, dxv.y));
-        xo[o] = dxv;
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) {   // prox output and FISTA step on T
+        if (inT(j)) {
+          const int a = sa[j], b = sb[j];
+          const float2 pyn = sRy[a - 1][b], pxn = sRx[a][b - 1];
+          const float hx = pyn.x - py[j].x + pxn.x - px[j].x;
+          const float hy = pyn.y - py[j].y + pxn.y - px[j].y;
+          const float2 dxv = make_float2(fmaf(-lam, hx, zz[j].x), fmaf(-lam, hy, zz[j].y));
+          const size_t o = (size_t)k * n + gi[j];
+          const float2 xp = xo[o];
+          yo[o] = make_float2(fmaf(theta, dxv.x - xp.x, dxv.x), fmaf(theta, dxv.y - xp.y, dxv.y));
+          xo[o] = dxv;
+        }
       }
-      __syncthreads();   // the next tangent's box overwrites sP and sZ
+      __syncthreads();   // the next tangent's r overwrites these p values
+    } else {
+      float2* rb = rB + (size_t)k * 2 * n;
+      float2* pb = pB + (size_t)k * 2 * n;
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) {
+        if (inT(j)) {
+          if (!last) {   // the prox's last pass: only p is read afterwards
+            rb[gi[j]] = ry[j];
+            rb[n + gi[j]] = rx[j];
+          }
+          pb[gi[j]] = py[j];
+          pb[n + gi[j]] = px[j];
+        }
+      }
     }
   }
 }
