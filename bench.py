@@ -891,7 +891,7 @@ def cs_tv_leg(lib, workloads, torch, np, dev, steps, n_conv=5000, storage=0, pmr
     if inner % 2:
         passes.append(1)
         it = 1
-    while inner - it >= 4 and min(pr.ny, pr.nx) >= 25:
+    while inner - it >= 4 and pr.ny >= 25 and pr.nx >= 41:
         passes.append(4)
         it += 4
     while it < inner:

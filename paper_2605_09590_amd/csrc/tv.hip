@@ -251,7 +251,8 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
 // r on R_{s-1} (the whole box for s = 0), so R_{S-1} = T (FIN: T with the row
 // above and the column left of it):
 //   w = r_s + c8 D u_s,  p_{s+1} = dP_s(w),  r_{s+1} = p_{s+1} + th_s (p_{s+1} - p_s).
-// Thread t owns the box points e = t + 256 j (j < NPT) through every step:
+// Thread t of the TY * TX owns the box points e = t + TY TX j (j < NPT)
+// through every step:
 // their r, p, dz, u and the steps' projection data stay in its registers, and
 // only r and u go through LDS, for the neighbours' reads (a point reads r at
 // (a-1, b), (a, b-1) and u at (a+1, b), (a, b+1)).  The projection data is
@@ -267,7 +268,8 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
 template <int S, int TY, int TX, int E>
 struct TvSteps {
   static constexpr int BY = TY + 2 * S + E, BX = TX + 2 * S + E, NB = BY * BX;
-  static constexpr int NPT = (NB + 255) / 256;   // box points per thread
+  static constexpr int NT = TY * TX;             // threads per workgroup
+  static constexpr int NPT = (NB + NT - 1) / NT; // box points per thread
   __host__ __device__ static constexpr int ry(int s) { return BY - 2 - 2 * s; }   // R_s rows
   __host__ __device__ static constexpr int rx(int s) { return BX - 2 - 2 * s; }   // R_s cols
   __host__ __device__ static constexpr int proj_off(int s) {
@@ -283,7 +285,7 @@ struct TvTheta {
 };
 
 template <int S, int TY, int TX, bool FIN>
-__global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz, const float2* __restrict__ rA,
+__global__ __launch_bounds__(TY * TX) void k_tv_steps(const float2* __restrict__ dz, const float2* __restrict__ rA,
                                                   float2* __restrict__ rB, const float2* __restrict__ pA,
                                                   float2* __restrict__ pB, const float4* __restrict__ what,
                                                   const float* __restrict__ invn, int ny, int nx, int K, int kper,
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
                                                   float2* __restrict__ xo, float2* __restrict__ yo, float theta) {
   constexpr int E = FIN ? 1 : 0;
   using C = TvSteps<S, TY, TX, E>;
-  constexpr int BY = C::BY, BX = C::BX, NB = C::NB, NPT = C::NPT;
+  constexpr int BY = C::BY, BX = C::BX, NB = C::NB, NT = C::NT, NPT = C::NPT;
   __shared__ float2 sRy[BY][BX], sRx[BY][BX];   // r_s at every box point
   __shared__ float2 sU[BY][BX];                 // u_s
   __shared__ float4 sW[C::NPROJ];               // projection data of the steps on R_s (w^)
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
   bool sv[NPT];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int e = t + 256 * j;
+    const int e = t + NT * j;
     sv[j] = e < NB;
     const int ee = sv[j] ? e : 0;
     sa[j] = ee / BX;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void k_tv_steps(const float2* __restrict__ dz,
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int RY = C::ry(s), RX = C::rx(s), off = C::proj_off(s);
-    for (int e = t; e < RY * RX; e += 256) {
+    for (int e = t; e < RY * RX; e += NT) {
       const int a = s + 1 + e / RX, b = s + 1 + e % RX;
       const int g = wrap(y0 - S - E + a, ny) * nx + wrap(x0 - S - E + b, nx);
       sW[off + e] = what[(size_t)s * n + g];
@@ -504,9 +506,11 @@ static void launch_tv_steps(const float2* dz, float2* drA, float2* drB, float2* 
   const dim3 grid = xcd_grid((long)tiles * ((K + kper - 1) / kper));
   TvTheta tt{};
   for (int q = 0; q < S; ++q) tt.th[q] = th[q];
-  hipLaunchKernelGGL((k_tv_steps<S, TY, TX, FIN>), grid, dim3(256), 0, s, dz, drA, drB, dpA, dpB, what, invn, ny, nx,
+  hipLaunchKernelGGL((k_tv_steps<S, TY, TX, FIN>), grid, dim3(TY * TX), 0, s, dz, drA, drB, dpA, dpB, what, invn, ny, nx,
                      K, kper, lam, c8, tt, first, last, xo, yo, theta);
 }
+
+constexpr int kFY = 16, kFX = 32;   // four-step tiles (512 threads)
 
 hipError_t tv_tangent_step(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
                            const float4* what, const float* invn, int ny, int nx, int K, int inner,
@@ -525,16 +529,18 @@ hipError_t tv_tangent_step(const float2* dz, float2* drA, float2* drB, float2* d
     std::swap(drA, drB);
     it = 1;
   }
-  // four steps per pass while four remain (16 x 16 tiles, halo 4, the last
-  // pass 5 above and left), then pairs; the last pass ends with the FISTA step
-  const bool four = ny >= 16 + 9 && nx >= 16 + 9;
+  // four steps per pass while four remain (kFY x kFX tiles, halo 4; a last
+  // pass of four, fused with the FISTA step, on 16 x 16 tiles, halo 5 above
+  // and left: its larger box would leave one workgroup per CU), then pairs;
+  // the last pass ends with the FISTA step
+  const bool four = ny >= kFY + 9 && nx >= kFX + 9;
   for (; four && inner - it >= 4; it += 4) {
     const int fst = it == 0 ? 1 : 0;
     if (it + 4 == inner)
       launch_tv_steps<4, 16, 16, true>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n, th + it,
                                        ny, nx, K, lam, c8, fst, 1, xo, yo, theta, s);
     else
-      launch_tv_steps<4, 16, 16, false>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n,
+      launch_tv_steps<4, kFY, kFX, false>(dz, drA, drB, dpA, dpB, what + (size_t)it * n, invn + (size_t)it * n,
                                         th + it, ny, nx, K, lam, c8, fst, 0, nullptr, nullptr, 0.f, s);
     std::swap(drA, drB);
     std::swap(dpA, dpB);
