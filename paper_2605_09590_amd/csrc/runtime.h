@@ -213,7 +213,8 @@ hipError_t tv64_prox(const Cs64& o, int B, double2* z, double lam, float4* what,
 // dz (kept), fused several per pass, with the ping-pong pairs drA / drB and
 // dpA / dpB ([K][2][n] each), the last pass also forming the prox output
 // dx = dz - lam D^H dp and the FISTA momentum yo = dx + theta (dx - xo),
-// xo = dx.  Needs ny >= 13 and nx >= 37.
+// xo = dx.  Needs ny >= 13 and nx >= 37; passes of four steps need ny >= 25
+// and nx >= 41 (smaller images take pairs only).
 hipError_t tv_tangent_step(const float2* dz, float2* drA, float2* drB, float2* dpA, float2* dpB,
                            const float4* what, const float* invn, int ny, int nx, int K, int inner,
                            const float* th, float lam, float2* xo, float2* yo, float theta, hipStream_t s);

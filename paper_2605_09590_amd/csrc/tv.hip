@@ -15,8 +15,8 @@
 // derivative data, w^ = w/|w| and 1/|w| where |w| > 1, else w^ = 0 and 1, so
 // the tangent map is dP(w) dw = (dw - w^ Re(w^H dw)) / |w| for all pixels,
 // with the inside / outside decision taken in FP64.  Tangent (FP32, K probes
-// at once): the same steps on (dz, dr, dp) with that stored dP, two inner
-// steps per fused kernel (u and w of a tile and its halo from LDS, the halo
+// at once): the same steps on (dz, dr, dp) with that stored dP, two or four
+// inner steps per fused kernel (u and w of a tile and its halo from LDS, the halo
 // recomputed), one single-step kernel first when the count is odd.
 //
 // Dual fields are [image][2][ny][nx] (y component, then x component).
@@ -243,7 +243,8 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
 }
 
 // S tangent inner steps i .. i+S-1 in one pass over a TY x TX tile T
-// (S = 2 on 8 x 32 tiles, S = 4 on 16 x 16).  The box B is T grown by S on
+// (S = 2 on 8 x 32 tiles; S = 4 on 16 x 32, or 16 x 16 when fused with the
+// FISTA step; one thread per pixel of T).  The box B is T grown by S on
 // every side (FIN: by S + 1 above and left), index [a][b] = pixel
 // (y0 - S - E + a, x0 - S - E + b), periodic, E = FIN.  Step s (from 0)
 // updates r and p on R_s = rows [s+1, BY-2-s] x cols [s+1, BX-2-s] from
