@@ -69,7 +69,7 @@ def _init_tv(lib, maps, psi, mask, braw, lam, T, inner, tile):
                          cs_lambda=lam, tv_inner_iters=inner, probe_tile=tile)
 
 
-@pytest.mark.parametrize("inner", [10, 7, 8])
+@pytest.mark.parametrize("inner", [10, 7, 8, 3])
 def test_tv_recon_jvp_and_noise_map_parity(lib, inner):
     say(f"case: TV-CS 64x96, 4 coils, Poisson-disc R=2 (8x8 calib), lam 1e-2, "
         f"FISTA 30, {inner} inner steps (multi-step passes{', one single step first' if inner % 2 else ''}, the last fused with the FISTA step); "
