@@ -252,12 +252,12 @@ __global__ __launch_bounds__(256) void k_tv_inner(const float2* __restrict__ dz,
 // r on R_{s-1} (the whole box for s = 0), so R_{S-1} = T (FIN: T with the row
 // above and the column left of it):
 //   w = r_s + c8 D u_s,  p_{s+1} = dP_s(w),  r_{s+1} = p_{s+1} + th_s (p_{s+1} - p_s).
-// Thread t of the TY * TX owns the box points e = t + TY TX j (j < NPT)
-// through every step:
-// their r, p, dz, u and the steps' projection data stay in its registers, and
-// only r and u go through LDS, for the neighbours' reads (a point reads r at
-// (a-1, b), (a, b-1) and u at (a+1, b), (a, b+1)).  The projection data is
-// loaded once per workgroup, for its run of tangents.  Inputs: r_i on B, p_i
+// Thread t (of TY * TX) owns the box points e = t + TY TX j (j < NPT)
+// through every step: their r, p, dz and u stay in its registers, and only r
+// and u go through LDS, for the neighbours' reads (a point reads r at (a-1,
+// b), (a, b-1) and u at (a+1, b), (a, b+1)).  The steps' projection data sits
+// in LDS region by region, loaded once per workgroup for its run of
+// tangents.  Inputs: r_i on B, p_i
 // on R_0, dz on U_0, read from (rA, pA); without FIN r and p of T written to
 // (rB, pB) (neighbouring tiles read the halo of both; last: the prox's last
 // pass, only p is read afterwards).  FIN (the prox's last pass, fused with the
