@@ -37,13 +37,14 @@ __device__ __forceinline__ float2 mul_mj(float2 a) {
 
 // ---------------------------------------------------------------- bfloat16 storage
 // A complex value as two bfloat16 halves of one 32-bit word (real in the low
-// half).  Packing rounds FP32 to nearest, ties to even; NaN stays a quiet NaN.
-__device__ __forceinline__ uint32_t bf16_rne(float f) {
-  const uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// half).  Packing rounds FP32 to nearest, ties to even, with gfx950's
+// v_cvt_pk_bf16_f32 (both halves in one instruction); NaN stays a NaN.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float2 v) {
+  const f32x2_t f = {v.x, v.y};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
-__device__ __forceinline__ uint32_t pack_bf16x2(float2 v) { return bf16_rne(v.x) | (bf16_rne(v.y) << 16); }
 __device__ __forceinline__ float2 unpack_bf16x2(uint32_t w) {
   return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
 }
