@@ -80,6 +80,25 @@ def test_bf16_maps_phase_encode(lib, form):
     assert eq < TOL and e < TOL_BF16
 
 
+# bfloat16 maps on the FFT path for the column plans of every family: two-step
+# plans with the mask weights in registers (160, 288) or selected from the
+# mask bits (384: 24-lane groups), and the 64-lane Stockham plan (512)
+@pytest.mark.parametrize("ny,nx,nc", [(160, 24, 4), (288, 16, 3), (384, 12, 3), (512, 8, 2)])
+def test_bf16_maps_fft_form_column_lengths(lib, ny, nx, nc):
+    say(f"case: phase-encode {ny}x{nx}, {nc} coils, R=2 + 8 ACS, 9 probes in tiles of 5, CG 20, "
+        f"bfloat16 maps, FFT form")
+    prob = workloads.config(2, seed=ny + 3, ny=ny, nx=nx, nc=nc, acs=8, cg_iters=20)
+    h = lib.pico_init(ny, nx, _dev(prob.maps.astype(np.complex64)), prob.psi, _dev(prob.mask),
+                      cg_iters=20, probe_tile=5, storage=lib.PICO_BF16_MAPS, normal_form=0)
+    s = _gpu_map(lib, h, ny * nx, 6, 0, 9)
+    lib.pico_destroy(h)
+    wq = ostore.bf16_whitened_maps(prob.maps, prob.psi)
+    ref_q = opico.noise_map(opico.Covariance(opico.cartesian(wq, None, prob.mask), 0.0, 20), 6, 0, 9)
+    eq = _rel(s, ref_q["sum"].ravel())
+    say(f"  vs rounded-map oracle {eq:.2e}")
+    assert eq < TOL
+
+
 @pytest.mark.parametrize("storage", [1, 2])
 def test_bf16_cart2d_apply_cov(lib, storage):
     say(f"case: Cartesian 2-D Poisson-disc 64x96, 5 coils, lambda 0.05, apply_cov on 3 probes, CG 20, "
