@@ -682,11 +682,15 @@ def spiral_gridding_leg(lib, workloads, torch, np, dev, steps=1):
     """The spiral workload (R=2, K=256) with the gridding normal operator
     (Kaiser-Bessel sigma 2, W 6, binned tile interpolation/spread) instead of
     the Toeplitz one: probe-solves/s, per-application time, and its HBM
-    roofline on the algorithmic bytes (per coil and probe: the grid written
-    by the expansion, read and written by each of the two grid FFTs and by the
-    fused interpolation/spread, the image part read by the crop; plus the
-    probe fields), and ||Sigma_grid v - Sigma_T v|| / ||Sigma_T v|| over one
-    tile of K random-phase probes (every launch of the leg is a K-probe one)."""
+    roofline on the algorithmic bytes (per coil and probe, G^2 complex64
+    points: the image rows' row transforms written (half the grid), read by the
+    column transforms, which write the full grid; the stencil reads and writes
+    it; the inverse column transforms read it and write the image rows, which
+    the inverse row transforms read: 6 half-or-full grids, 48 G^2 bytes; the
+    image row read and the combined q read and written, 24 B per pixel; plus
+    the probe fields), and ||Sigma_grid v - Sigma_T v|| / ||Sigma_T v|| over
+    one tile of K random-phase probes (every launch of the leg is a K-probe
+    one)."""
     sp = workloads.config(3, seed=0)
     traj = torch.from_numpy(sp.traj.astype(np.float32)).to(dev)
     smaps = torch.from_numpy(sp.maps.astype(np.complex64)).to(dev)
@@ -721,15 +725,15 @@ def spiral_gridding_leg(lib, workloads, torch, np, dev, steps=1):
     it_ms, it_n = prof["normal_iter"]
     op_s = it_ms / it_n / 1e3
     G = 2 * sp.ny
-    alg = K * sp.nc * (56 * G * G + 8 * n) + K * 4 * 8 * n
+    alg = K * sp.nc * (48 * G * G + 24 * n) + K * 4 * 8 * n
     return {"workload": "spiral 256x256, 16 coils, 48x4096 R=2, lambda 0.1, CG 30, K=256; gridding normal "
                         "operator (sigma 2, W 6, 16x16 tile bins)",
             "probe_solves_per_s": round(K / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
             "sigma_rel_diff_vs_toeplitz_256_probes": rel,
             "roofline": {"bound": "hbm", "achieved": round(alg / op_s / 1e9, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(alg / op_s / 1e9 / PEAK_HBM_GBS, 4),
-                         "kernel": "gridding normal operator (expand, grid FFT, tile interp/spread, inverse "
-                                   "FFT, crop/combine), C1_ITER",
+                         "kernel": "gridding normal operator (expand + row FFTs, column FFTs, stencil, "
+                                   "inverse column FFTs, inverse row FFTs + crop/combine), C1_ITER",
                          "avg_application_us": round(op_s * 1e6, 1), "alg_bytes": alg},
             "kernel_ms": {k: round(v2[0], 3) for k, v2 in prof.items()}}
 

@@ -118,6 +118,166 @@ hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse,
   });
 }
 
+// ---------------------------------------------------------------- gridding normal operator: image-row passes
+// The coil image (ny x nx, centred) sits on the oversampled grid (Gy x Gx)
+// at rows (y - ny/2) mod Gy and columns (x - nx/2) mod Gx; every other point
+// of the expanded image is zero, and only those rows and columns are read
+// back after the inverse transform.  So the row transforms run on the ny
+// image rows only, kept compactly ([K][ny][Gx], row y), and the column
+// transforms read (forward) or write (inverse) just those rows of the grid.
+
+// image index of grid index g (line of G points, image of n), -1 outside
+__device__ __forceinline__ int crop_index(int g, int n, int G) {
+  return g < n / 2 ? g + n / 2 : (g >= G - n / 2 ? g - (G - n / 2) : -1);
+}
+
+// forward: out[b][y] = FFT_Gx of the grid row of image row y, which holds
+// S_c x[b] dy dx scale at columns (x - nx/2) mod Gx.  inverse: the inverse
+// FFT_Gx of in[b][y] cropped to the image, de-apodised, times conj(S_c) and
+// written (or added, accumulate) to out[b][y][x].  One row per group of L
+// lanes; every load goes out from an in-bounds address.
+template <class CF, bool INV>
+__global__ __launch_bounds__(64) void k_kbn_rows(const float2* __restrict__ in, const float2* __restrict__ Sc,
+                                                 const float* __restrict__ dy, const float* __restrict__ dx,
+                                                 float2* __restrict__ out, long nlines, int ny, int nx, float scale,
+                                                 int accumulate, const float2* __restrict__ twx) {
+  constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
+  __shared__ float2 lds_all[NG * CF::SPAN];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const long line = (long)blockIdx.x * G + g;
+  const bool active = g < G && line < nlines;
+  const long ln = active ? line : 0;
+  const int y = (int)(ln % ny);
+  typename CF::Tw tw;
+  CF::load_tw(tw, twx, lane);
+  const float fy = dy[y] * scale;
+  const float2* sr = Sc + (size_t)y * nx;
+  float2 v[CF::VMAX];
+  if constexpr (!INV) {
+    const float2* xr = in + (size_t)ln * nx;   // image row y of probe ln / ny
+#pragma unroll
+    for (int m = 0; m < CF::VA; ++m) {
+      const int x = CF::inA(lane) ? crop_index(CF::posA(lane, m), nx, CF::N) : -1;
+      const int xs = x >= 0 ? x : 0;
+      v[m] = cscale(cmul(sr[xs], xr[xs]), x >= 0 ? fy * dx[xs] : 0.f);
+    }
+  } else {
+    const float2* ir = in + (size_t)ln * CF::N;
+#pragma unroll
+    for (int m = 0; m < CF::VA; ++m) {
+      const bool ok = CF::inA(lane);
+      v[m] = cscale(ir[ok ? CF::posA(lane, m) : 0], ok ? 1.f : 0.f);
+    }
+  }
+  CF::template forward<INV>(v, lds_all + g * CF::SPAN, lane, tw);
+  if (!active || !CF::inB(lane)) return;
+  if constexpr (!INV) {
+    float2* o = out + (size_t)ln * CF::N;
+#pragma unroll
+    for (int r = 0; r < CF::VB; ++r) o[CF::posB(lane, r)] = v[r];
+  } else {
+    float2* o = out + (size_t)ln * nx;
+    float2 prev[CF::VMAX];
+#pragma unroll
+    for (int r = 0; r < CF::VB; ++r) {
+      const int x = crop_index(CF::posB(lane, r), nx, CF::N);
+      prev[r] = accumulate ? o[x >= 0 ? x : 0] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < CF::VB; ++r) {
+      const int x = crop_index(CF::posB(lane, r), nx, CF::N);
+      const int xs = x >= 0 ? x : 0;
+      const float2 t = cmulc(sr[xs], cscale(v[r], fy * dx[xs]));
+      if (x >= 0) o[x] = cadd(prev[r], t);
+    }
+  }
+}
+
+// Column transforms of B planes between the compact image rows and the full
+// grid: forward reads in[b] = [ny][Gx] (image row y is grid row (y - ny/2)
+// mod Gy, zero elsewhere) and writes out[b] = [Gy][Gx]; inverse reads all Gy
+// rows of in[b] and writes only the image rows, out[b] = [ny][Gx].  The strip
+// tile doubles as the groups' exchange regions once every group holds its
+// column in registers.
+template <class CF, bool INV>
+__global__ __launch_bounds__(256) void k_fft_cols_crop(const float2* __restrict__ in, float2* __restrict__ out,
+                                                       int ny, int Gx, const float2* __restrict__ twt) {
+  constexpr int L = CF::L, NGRP = 256 / L, TS = NGRP + 1, GY = CF::N;
+  extern __shared__ float2 dyn[];
+  float2* tile = dyn;
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const int x0 = blockIdx.x * NGRP;
+  const size_t b = blockIdx.y;
+  const int ncol = min(NGRP, Gx - x0);
+  const int rows_in = INV ? GY : ny, rows_out = INV ? ny : GY;
+  strip_load(tile, in + b * rows_in * Gx + x0, rows_in, NGRP, TS, ncol, Gx);
+  __syncthreads();
+  const bool grp = g < NGRP && g < ncol;
+  typename CF::Tw tw;
+  CF::load_tw(tw, twt, lane);
+  float2 v[CF::VMAX];
+#pragma unroll
+  for (int m = 0; m < CF::VA; ++m) {
+    const int gy = CF::posA(lane, m);
+    const int row = INV ? gy : crop_index(gy, ny, GY);
+    v[m] = (grp && CF::inA(lane) && row >= 0) ? tile[row * TS + g] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();   // every group holds its column: the tile becomes the exchange regions
+  CF::template forward<INV>(v, dyn + g * CF::SPAN, lane, tw);
+  __syncthreads();   // every transform is done before outputs overwrite the exchange regions
+  if (grp && CF::inB(lane)) {
+#pragma unroll
+    for (int r = 0; r < CF::VB; ++r) {
+      const int gy = CF::posB(lane, r);
+      const int row = INV ? crop_index(gy, ny, GY) : gy;
+      if (row >= 0) tile[row * TS + g] = v[r];
+    }
+  }
+  __syncthreads();
+  strip_store(tile, out + b * rows_out * Gx + x0, rows_out, NGRP, TS, ncol, Gx);
+}
+
+hipError_t launch_kbn_rows(bool inverse, const float2* in, const float2* Sc, const float* dy, const float* dx,
+                           float2* out, int K, int ny, int nx, int Gx, float scale, int accumulate,
+                           const float2* twx, hipStream_t s) {
+  const long nlines = (long)K * ny;
+  return with_line(Gx, [&](auto cf) {
+    using CF = decltype(cf);
+    constexpr int G = 64 / CF::L;
+    const dim3 grid((unsigned)((nlines + G - 1) / G)), block(64);
+    if (inverse)
+      hipLaunchKernelGGL((k_kbn_rows<CF, true>), grid, block, 0, s, in, Sc, dy, dx, out, nlines, ny, nx, scale,
+                         accumulate, twx);
+    else
+      hipLaunchKernelGGL((k_kbn_rows<CF, false>), grid, block, 0, s, in, Sc, dy, dx, out, nlines, ny, nx, scale,
+                         accumulate, twx);
+    return hipGetLastError();
+  });
+}
+
+template <class CF, bool INV>
+static hipError_t cols_crop(const float2* in, float2* out, long planes, int ny, int Gx, const float2* twy,
+                            hipStream_t s) {
+  constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
+  const size_t lds = std::max((size_t)CF::N * (NGRP + 1), (size_t)NG * CF::SPAN) * sizeof(float2);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_fft_cols_crop<CF, INV>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) return attr;
+  const dim3 grid((unsigned)((Gx + NGRP - 1) / NGRP), (unsigned)planes), block(256);
+  hipLaunchKernelGGL((k_fft_cols_crop<CF, INV>), grid, block, lds, s, in, out, ny, Gx, twy);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_cols_crop(const float2* in, float2* out, long planes, int ny, int Gy, int Gx, bool inverse,
+                                const float2* twy, hipStream_t s) {
+  return with_line(Gy, [&](auto cf) {
+    using CF = decltype(cf);
+    return inverse ? cols_crop<CF, true>(in, out, planes, ny, Gx, twy, s)
+                   : cols_crop<CF, false>(in, out, planes, ny, Gx, twy, s);
+  });
+}
+
 // ---------------------------------------------------------------- k-space inputs
 // out[b][c][ky][kx] = f(b, c, ky, kx) * mask[ky][kx] * (-1)^(ky+kx) * scale, where f
 // is the measured data whitened here (src and linv given, b = 0:

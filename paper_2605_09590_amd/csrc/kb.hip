@@ -567,18 +567,25 @@ hipError_t launch_kb_normal(int mode, const Grid2dArgs& a, const KbOp& o, hipStr
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long G2 = (long)o.Gy * o.Gx, n = (long)o.ny * o.nx;
+  const long n = (long)o.ny * o.nx;
   const float scale = (float)(1.0 / std::sqrt((double)n));
   const float2* xin = mode == C1_APPLY ? a.src : a.p;
   const float in_scale = mode == C1_APPLY ? scale * a.scale : scale;
+  // per coil: image rows expanded and row-transformed ([K][ny][Gx] in
+  // grid2), column transforms to the full grid, stencil, inverse column
+  // transforms back to the image rows (in grid), inverse row transforms
+  // cropped and combined into q
   for (int c = 0; c < a.nc; ++c) {
-    hipLaunchKernelGGL(k_kb_expand, kb_grid(G2, a.K), block, 0, s, xin, a.maps + (size_t)c * n, o.dy, o.dx, o.grid,
-                       o.ny, o.nx, o.Gy, o.Gx, in_scale);
-    if ((e = launch_fft2d(o.grid, a.K, o.Gy, o.Gx, false, o.twx, o.twy, s)) != hipSuccess) return e;
+    const float2* Sc = a.maps + (size_t)c * n;
+    if ((e = launch_kbn_rows(false, xin, Sc, o.dy, o.dx, o.grid2, a.K, o.ny, o.nx, o.Gx, in_scale, 0, o.twx, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_fft_cols_crop(o.grid2, o.grid, a.K, o.ny, o.Gy, o.Gx, false, o.twy, s)) != hipSuccess) return e;
     if ((e = stencil(o, a.K, o.grid, o.grid2, s)) != hipSuccess) return e;
-    if ((e = launch_fft2d(o.grid2, a.K, o.Gy, o.Gx, true, o.twx, o.twy, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_kb_crop_combine, kb_grid(n, a.K), block, 0, s, o.grid2, a.maps + (size_t)c * n, o.dy, o.dx,
-                       a.q, o.ny, o.nx, o.Gy, o.Gx, scale, c > 0 ? 1 : 0);
+    if ((e = launch_fft_cols_crop(o.grid2, o.grid, a.K, o.ny, o.Gy, o.Gx, true, o.twy, s)) != hipSuccess) return e;
+    if ((e = launch_kbn_rows(true, o.grid, Sc, o.dy, o.dx, a.q, a.K, o.ny, o.nx, o.Gx, scale, c > 0 ? 1 : 0, o.twx,
+                             s)) != hipSuccess)
+      return e;
   }
   switch (mode) {
     case C1_FIRST_PROBE: hipLaunchKernelGGL(k_kbn_epi<C1_FIRST_PROBE>, rows, block, 0, s, a); break;

@@ -137,6 +137,18 @@ hipError_t launch_upsample_bilinear(const double* coarse, double* out, int cy, i
 hipError_t launch_power_start_rowmajor(float2* p, int n, hipStream_t s);
 hipError_t launch_fft2d(float2* data, long planes, int ny, int nx, bool inverse, const float2* twx,
                         const float2* twy, hipStream_t s);
+// gridding normal operator passes on the ny image rows of a Gy x Gx grid
+// (image row y at grid row (y - ny/2) mod Gy, column x at (x - nx/2) mod Gx):
+// forward rows: out [K][ny][Gx] = row FFTs of S_c x dy dx scale placed on the
+// grid rows; inverse rows: out [K][ny][nx] (= or +=, accumulate) conj(S_c)
+// dy dx scale times the inverse row FFTs of in [K][ny][Gx], cropped.
+// Column transforms: forward [planes][ny][Gx] (the image rows) -> the full
+// [planes][Gy][Gx]; inverse the full grid -> its image rows [planes][ny][Gx].
+hipError_t launch_kbn_rows(bool inverse, const float2* in, const float2* Sc, const float* dy, const float* dx,
+                           float2* out, int K, int ny, int nx, int Gx, float scale, int accumulate,
+                           const float2* twx, hipStream_t s);
+hipError_t launch_fft_cols_crop(const float2* in, float2* out, long planes, int ny, int Gy, int Gx, bool inverse,
+                                const float2* twy, hipStream_t s);
 hipError_t launch_kspace_in(const float2* src, const double* linv, const uint8_t* mask, float2* out,
                             int B, int nc, int ny, int nx, uint64_t seed, uint64_t first,
                             const uint64_t* tp, uint32_t stream, int dist, float scale, hipStream_t s);
