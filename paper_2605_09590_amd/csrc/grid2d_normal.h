@@ -308,8 +308,12 @@ __device__ __forceinline__ void strip_store(const float2* __restrict__ tile, E* 
 
 // ---------------------------------------------------------------- column pass
 // One workgroup of 256 lanes: NGRP = 256 / L column groups, one grid column
-// each, adjacent columns of one (k, c) plane.
-template <class CF, bool TB>
+// each, adjacent columns of one (k, c) plane.  HALF (the Toeplitz grids,
+// ny = Gy / 2): the input column is zero past its first half and only the
+// first half of the output is kept; both layouts place values m < VA / 2 and
+// r < VB / 2 in the first half, so the zeros and the unused outputs are
+// compile-time facts the compiler folds out of the first and last passes.
+template <class CF, bool TB, bool HALF>
 __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
   constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
   constexpr int VA = CF::VA, VB = CF::VB;
@@ -341,7 +345,8 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
     const int yy = CF::posA(lane, m);
-    v[m] = (grp && inA && yy < a.ny) ? tile[yy * TS + g] : make_float2(0.f, 0.f);
+    if (HALF && m >= VA / 2) v[m] = make_float2(0.f, 0.f);
+    else v[m] = (grp && inA && (HALF || yy < a.ny)) ? tile[yy * TS + g] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   float2* lds = xch + g * CF::SPAN;
@@ -354,9 +359,9 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
   CF::template inverse<true>(v, lds, lane, tw);
   if (grp && inA) {
 #pragma unroll
-    for (int m = 0; m < VA; ++m) {
+    for (int m = 0; m < (HALF ? VA / 2 : VA); ++m) {
       const int yy = CF::posA(lane, m);
-      if (yy < a.ny) tile[yy * TS + g] = v[m];
+      if (HALF || yy < a.ny) tile[yy * TS + g] = v[m];
     }
   }
   __syncthreads();
@@ -609,20 +614,29 @@ static hipError_t rows_inv(int mode, const Grid2dArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class CF, bool TB, bool HALF>
+static hipError_t cols_launch(const Grid2dArgs& a, size_t lds, hipStream_t s) {
+  constexpr int NGRP = 256 / CF::L;
+  // allow more than the default 64 KiB of dynamic LDS (once per process,
+  // thread-safe initialisation)
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_cols<CF, TB, HALF>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) return attr;
+  const long W = (long)((a.Gx + NGRP - 1) / NGRP) * a.K * a.nc;
+  dim3 grid((unsigned)(8 * ((W + 7) / 8))), block(256);
+  hipLaunchKernelGGL((k_cols<CF, TB, HALF>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
 template <class CF, bool TB>
 static hipError_t cols(const Grid2dArgs& a, hipStream_t s) {
   constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
   const size_t lds = std::max((size_t)a.ny * (NGRP + 1), (size_t)NG * CF::SPAN) * sizeof(float2);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  // allow more than the default 64 KiB of dynamic LDS (once per process,
-  // thread-safe initialisation)
-  static const hipError_t attr = hipFuncSetAttribute((const void*)k_cols<CF, TB>,
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (attr != hipSuccess) return attr;
-  const long W = (long)((a.Gx + NGRP - 1) / NGRP) * a.K * a.nc;
-  dim3 grid((unsigned)(8 * ((W + 7) / 8))), block(256);
-  hipLaunchKernelGGL((k_cols<CF, TB>), grid, block, lds, s, a);
-  return hipGetLastError();
+  if constexpr (CF::VA % 2 == 0 && CF::VB % 2 == 0) {
+    if (2 * a.ny == a.Gy) return cols_launch<CF, TB, true>(a, lds, s);
+  }
+  return cols_launch<CF, TB, false>(a, lds, s);
 }
 
 
