@@ -91,10 +91,13 @@ __device__ __forceinline__ double group_reduce2(double v, double* red, int lane)
 }
 
 // ---------------------------------------------------------------- row pass 1
-template <class CF, int MODE, int ST>
+template <class CF, int MODE, int ST, bool HALF>
 __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
   constexpr int VA = CF::VA, VB = CF::VB;
+  // HALF (the Toeplitz grids, nx = Gx / 2): values m >= VA / 2 lie past the
+  // image row, so they are compile-time zeros in the forward transform
+  constexpr int VAH = HALF ? VA / 2 : VA;
   __shared__ float2 lds_all[NG * CF::SPAN];
   __shared__ double red[64 + L];   // lane 0 of a partial last group reads L entries
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
@@ -138,6 +141,10 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   }
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
+    if (HALF && m >= VAH) {   // past the image row
+      pv[m] = make_float2(0.f, 0.f);
+      continue;
+    }
     const int xx = CF::posA(lane, m);
     const bool ok = inA && xx < a.nx;
     const size_t i = rowoff + (ok ? xx : 0);   // in-bounds address for every lane
@@ -165,14 +172,14 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
   if constexpr (MODE == C1_ITER) {
     // finish iteration i-1 and start i: x += alpha p, r -= alpha q, p = r + beta p.
     // In chunks of H elements, every load of a chunk is issued before its first store.
-    constexpr int H = VA > 8 ? 8 : VA;
+    constexpr int H = VAH > 8 ? 8 : VAH;
     const bool xz = a.x_zero != 0;
 #pragma unroll
-    for (int m0 = 0; m0 < VA; m0 += H) {
+    for (int m0 = 0; m0 < VAH; m0 += H) {
       float2 po[H], qo[H], ro[H], xo[H];
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        if (m0 + h >= VA) break;
+        if (m0 + h >= VAH) break;
         const int xx = CF::posA(lane, m0 + h);
         const size_t i = rowoff + ((inA && xx < a.nx) ? xx : 0);
         po[h] = P[i];
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int m = m0 + h;
-        if (m >= VA) break;
+        if (m >= VAH) break;
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
         const size_t i = rowoff + (ok ? xx : 0);
@@ -217,6 +224,7 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
     const size_t moff = ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
+      if (HALF && m >= VAH) continue;   // past the image row (zero)
       const int xx = CF::posA(lane, m);
       svn[m] = map_raw<ST>(a, moff + ((inA && xx < a.nx) ? xx : 0));
     }
@@ -227,6 +235,10 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
     if constexpr (PF) {
 #pragma unroll
       for (int m = 0; m < VA; ++m) {
+        if (HALF && m >= VAH) {   // past the image row
+          v[m] = make_float2(0.f, 0.f);
+          continue;
+        }
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
         v[m] = cmul(widen(svn[m]), pv[m]);   // pv is 0 outside the row
@@ -237,6 +249,10 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
       const ME* mrow = reinterpret_cast<const ME*>(lds);
 #pragma unroll
       for (int m = 0; m < VA; ++m) {
+        if (HALF && m >= VAH) {   // past the image row
+          v[m] = make_float2(0.f, 0.f);
+          continue;
+        }
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
         v[m] = cmul(widen(mrow[ok ? xx : 0]), pv[m]);   // pv is 0 outside the row
@@ -245,6 +261,10 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
       const size_t moff = ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
       for (int m = 0; m < VA; ++m) {
+        if (HALF && m >= VAH) {   // past the image row
+          v[m] = make_float2(0.f, 0.f);
+          continue;
+        }
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
         v[m] = cmul(map_at<ST>(a, moff + (ok ? xx : 0)), pv[m]);   // pv is 0 outside the row
@@ -370,10 +390,13 @@ __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
 }
 
 // ---------------------------------------------------------------- row pass 2
-template <class CF, int MODE, int ST>
+template <class CF, int MODE, int ST, bool HALF>
 __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   constexpr int L = CF::L, G = 64 / L, NG = (64 + L - 1) / L;
   constexpr int VA = CF::VA, VB = CF::VB;
+  // HALF (the Toeplitz grids, nx = Gx / 2): only values m < VA / 2 of the
+  // inverse transform lie in the image row
+  constexpr int VAH = HALF ? VA / 2 : VA;
   __shared__ float2 lds_all[NG * CF::SPAN];
   __shared__ double red[64 + L];   // lane 0 of a partial last group reads L entries
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
@@ -426,6 +449,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   auto load_p = [&](float2* pa) {
 #pragma unroll
     for (int m = 0; m < VA; ++m) {
+      if (HALF && m >= VAH) continue;   // past the image row (zero)
       const int xx = CF::posA(lane, m);
       const bool ok = inA && xx < a.nx;
       const size_t i = rowoff + (ok ? xx : 0);
@@ -437,10 +461,10 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   if (a.lam != 0.f) {
     load_p(qa);
 #pragma unroll
-    for (int m = 0; m < VA; ++m) qa[m] = cscale(qa[m], a.lam);
+    for (int m = 0; m < VAH; ++m) qa[m] = cscale(qa[m], a.lam);
   } else {
 #pragma unroll
-    for (int m = 0; m < VA; ++m) qa[m] = make_float2(0.f, 0.f);
+    for (int m = 0; m < VAH; ++m) qa[m] = make_float2(0.f, 0.f);
   }
   // Stockham rows of 512 and 768 points: the transformed row of coil c + 1 is loaded
   // while coil c is inverted (raw storage form, unconditional loads from
@@ -489,6 +513,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
       const ME* mrow = mapbuf + (g < G ? g : 0) * CF::N;
 #pragma unroll
       for (int m = 0; m < VA; ++m) {
+        if (HALF && m >= VAH) continue;   // past the image row (zero)
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
         qa[m] = cadd(qa[m], cmulc(widen(mrow[ok ? xx : 0]), v[m]));
@@ -497,6 +522,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
       const size_t moff = ((size_t)c * a.ny + y) * a.nx;
 #pragma unroll
       for (int m = 0; m < VA; ++m) {
+        if (HALF && m >= VAH) continue;   // past the image row (zero)
         const int xx = CF::posA(lane, m);
         const bool ok = inA && xx < a.nx;
         qa[m] = cadd(qa[m], cmulc(map_at<ST>(a, moff + (ok ? xx : 0)), v[m]));
@@ -507,6 +533,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   load_p(pa);
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
+    if (HALF && m >= VAH) continue;   // past the image row (zero)
     const int xx = CF::posA(lane, m);
     const size_t i = rowoff + ((inA && xx < a.nx) ? xx : 0);
     ra[m] = MODE == C1_ITER ? R[i] : pa[m];
@@ -514,6 +541,7 @@ __global__ __launch_bounds__(64) void k_rows_inv(Grid2dArgs a) {
   double d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
   for (int m = 0; m < VA; ++m) {
+    if (HALF && m >= VAH) continue;   // past the image row (zero)
     const int xx = CF::posA(lane, m);
     const bool ok = inA && xx < a.nx;
     const size_t i = rowoff + (ok ? xx : 0);
@@ -584,34 +612,52 @@ static hipError_t with_line(int n, F&& f) {
   }
 }
 
-template <class CF, int ST>
-static hipError_t rows_fwd(int mode, const Grid2dArgs& a, hipStream_t s) {
+template <class CF, int ST, bool HALF>
+static hipError_t rows_fwd_h(int mode, const Grid2dArgs& a, hipStream_t s) {
   constexpr int G = 64 / CF::L;
   const long rows = (long)a.K * a.ny;
   dim3 grid((unsigned)((rows + G - 1) / G)), block(64);
   switch (mode) {
-    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_rows_fwd<CF, C1_FIRST_PROBE, ST>), grid, block, 0, s, a); break;
-    case C1_FIRST_BUF: hipLaunchKernelGGL((k_rows_fwd<CF, C1_FIRST_BUF, ST>), grid, block, 0, s, a); break;
-    case C1_ITER: hipLaunchKernelGGL((k_rows_fwd<CF, C1_ITER, ST>), grid, block, 0, s, a); break;
-    case C1_APPLY: hipLaunchKernelGGL((k_rows_fwd<CF, C1_APPLY, ST>), grid, block, 0, s, a); break;
+    case C1_FIRST_PROBE: hipLaunchKernelGGL((k_rows_fwd<CF, C1_FIRST_PROBE, ST, HALF>), grid, block, 0, s, a); break;
+    case C1_FIRST_BUF: hipLaunchKernelGGL((k_rows_fwd<CF, C1_FIRST_BUF, ST, HALF>), grid, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL((k_rows_fwd<CF, C1_ITER, ST, HALF>), grid, block, 0, s, a); break;
+    case C1_APPLY: hipLaunchKernelGGL((k_rows_fwd<CF, C1_APPLY, ST, HALF>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <class CF, int ST>
-static hipError_t rows_inv(int mode, const Grid2dArgs& a, hipStream_t s) {
+template <class CF, int ST, bool HALF>
+static hipError_t rows_inv_h(int mode, const Grid2dArgs& a, hipStream_t s) {
   constexpr int G = 64 / CF::L;
   const long rows = (long)a.K * a.ny;
   dim3 grid((unsigned)((rows + G - 1) / G)), block(64);
   switch (mode) {
     case C1_FIRST_PROBE: case C1_FIRST_BUF:
-      hipLaunchKernelGGL((k_rows_inv<CF, C1_FIRST_BUF, ST>), grid, block, 0, s, a); break;
-    case C1_ITER: hipLaunchKernelGGL((k_rows_inv<CF, C1_ITER, ST>), grid, block, 0, s, a); break;
-    case C1_APPLY: hipLaunchKernelGGL((k_rows_inv<CF, C1_APPLY, ST>), grid, block, 0, s, a); break;
+      hipLaunchKernelGGL((k_rows_inv<CF, C1_FIRST_BUF, ST, HALF>), grid, block, 0, s, a); break;
+    case C1_ITER: hipLaunchKernelGGL((k_rows_inv<CF, C1_ITER, ST, HALF>), grid, block, 0, s, a); break;
+    case C1_APPLY: hipLaunchKernelGGL((k_rows_inv<CF, C1_APPLY, ST, HALF>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// the half-row variants when the image row is the first half of the grid row
+// (the Toeplitz grids, nx = Gx / 2)
+template <class CF, int ST>
+static hipError_t rows_fwd(int mode, const Grid2dArgs& a, hipStream_t s) {
+  if constexpr (CF::VA % 2 == 0) {
+    if (2 * a.nx == a.Gx) return rows_fwd_h<CF, ST, true>(mode, a, s);
+  }
+  return rows_fwd_h<CF, ST, false>(mode, a, s);
+}
+
+template <class CF, int ST>
+static hipError_t rows_inv(int mode, const Grid2dArgs& a, hipStream_t s) {
+  if constexpr (CF::VA % 2 == 0) {
+    if (2 * a.nx == a.Gx) return rows_inv_h<CF, ST, true>(mode, a, s);
+  }
+  return rows_inv_h<CF, ST, false>(mode, a, s);
 }
 
 template <class CF, bool TB, bool HALF>
