@@ -239,8 +239,6 @@ __global__ __launch_bounds__(64) void k_rows_fwd(Grid2dArgs a) {
           v[m] = make_float2(0.f, 0.f);
           continue;
         }
-        const int xx = CF::posA(lane, m);
-        const bool ok = inA && xx < a.nx;
         v[m] = cmul(widen(svn[m]), pv[m]);   // pv is 0 outside the row
       }
       if (c + 1 < a.nc) load_maps(c + 1);
@@ -335,7 +333,7 @@ __device__ __forceinline__ void strip_store(const float2* __restrict__ tile, E* 
 // compile-time facts the compiler folds out of the first and last passes.
 template <class CF, bool TB, bool HALF>
 __global__ __launch_bounds__(256) void k_cols(Grid2dArgs a) {
-  constexpr int L = CF::L, NGRP = 256 / L, NG = (256 + L - 1) / L;
+  constexpr int L = CF::L, NGRP = 256 / L;
   constexpr int VA = CF::VA, VB = CF::VB;
   constexpr int TS = NGRP + 1;  // padded tile row
   extern __shared__ float2 dyn[];
