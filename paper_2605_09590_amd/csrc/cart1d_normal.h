@@ -174,7 +174,7 @@ __global__ __launch_bounds__(64) void k_cart1d(Cart1dArgs a) {
   const int k = blockIdx.x * G + g;
   const bool active = g < G && k < a.K;
   const int kk = active ? k : 0;  // idle lanes work on probe 0 but never store
-  const bool inA = CF::inA(lane), inB = CF::inB(lane);
+  const bool inA = CF::inA(lane);
   float2* lds = lds_all + g * CF::SPAN;
 
   typename CF::Tw tw;
