@@ -150,6 +150,40 @@ def test_gridding_normal_operator_parity(lib, n, nc, sigma, W, samples):
         assert e < TOL
 
 
+# Non-square images: the image rows (ny) and columns (nx) sit on grids of
+# different lengths, so a swap of the two in the row and column passes of the
+# gridding normal operator shows here
+@pytest.mark.parametrize("ny,nx,W", [(64, 96, 6), (96, 64, 4)])
+def test_gridding_normal_operator_nonsquare(lib, ny, nx, W):
+    say(f"case: CG on the gridding normal operator, {ny}x{nx} (grid {2 * ny}x{2 * nx}), 3 coils, sigma 2, "
+        f"W {W}, 16 x 512 R=2, lambda 0.1, CG 20; apply_cov on 2 probes and a 4-probe map in tiles of 2")
+    rng = np.random.default_rng(ny + nx + W)
+    maps = workloads.coil_maps(ny, nx, 3, rng)
+    psi = workloads.noise_cov(3, rng)
+    traj = workloads.spiral_traj(max(ny, nx), 2, 16, 512).astype(np.float32)
+    h = lib.pico_init(ny, nx, _dev(maps.astype(np.complex64)), psi, None, sampling=lib.PICO_NONCART, lam=0.1,
+                      cg_iters=20, probe_tile=2, traj=_dev(traj), nsamples=traj.shape[0], oversamp=2.0,
+                      kb_width=W, noncart_normal=1)
+    v = np.stack([opico.probe_image(5, i, (ny, nx)) for i in range(2)]).astype(np.complex64)
+    ut = torch.empty((2, ny, nx), dtype=torch.complex64, device="cuda:0")
+    lib.pico_apply_cov(h, _dev(v), ut, 2)
+    acc_t = [torch.zeros(ny * nx, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    lib.pico_noise_map(h, 11, 0, 4, 0, lib.make_accum(*acc_t))
+    torch.cuda.synchronize()
+    lib.pico_destroy(h)
+    op = onufft.NonCartOp(maps, psi, traj.astype(np.float64), kb=(2.0, W), normal_mode="gridding")
+    cov = opico.Covariance(op, 0.1, 20)
+    u = ut.cpu().numpy()
+    for k in range(2):
+        e = _rel(u[k], cov.apply(v[k].astype(np.complex128)))
+        say(f"  probe {k}: rel err {e:.2e}")
+        assert e < TOL
+    ref = opico.noise_map(cov, 11, 0, 4)
+    e = _rel(acc_t[0].cpu().numpy(), ref["sum"].ravel())
+    say(f"  map sum: rel err {e:.2e}")
+    assert e < TOL
+
+
 def test_gridding_normal_full_size_vs_toeplitz(lib):
     say("case: spiral 256x256, 16 coils, 48x4096 R=2, lambda 0.1, CG 30, K=256 in one launch: "
         "Sigma v with the gridding normal operator (sigma 2, W 6) against the exact Toeplitz one")
