@@ -166,8 +166,11 @@ typedef struct {
    * form (point-spread function by the direct NUDFT).  1: the gridding form
    * M = sum_c S_c^H A_c^H A_c S_c with the Kaiser-Bessel A_c of oversamp /
    * kb_width (kb_width > 0, oversamp * n a multiple of 16): per coil and
-   * probe, grid FFT, interpolation and spread fused per 16 x 16 grid tile
-   * (samples sorted into tile bins once), inverse grid FFT; deterministic. */
+   * probe, the image rows expanded and row-transformed, column transforms to
+   * the full grid, interpolation followed by spread applied as one real
+   * stencil per 16 x 16 grid tile (P^H P, built once from the binned
+   * samples), and the inverse transforms back to the image rows, cropped
+   * and combined; deterministic. */
   int32_t noncart_normal;
 } pico_op_desc_t;
 
